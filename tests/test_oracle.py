@@ -1,0 +1,413 @@
+"""Pins for the FP64 oracle: checks against facts the paper and the mathematics fix.
+
+None of these re-types the oracle's own code path: they compare it with a
+library routine (numpy.fft), closed forms, invariants, statistics with known
+laws, brute force evaluated a different way, or finite differences.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+RNG = np.random.default_rng(12345)
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _cell(Q, lo=-math.pi, hi=math.pi, rng=RNG):
+    x = rng.uniform(lo, hi, Q)
+    y = rng.uniform(lo, hi, Q)
+    h = rng.normal(size=Q)
+    w = rng.uniform(0.5, 1.5, Q)
+    return x, y, h, w
+
+
+def _modes(N):
+    return np.arange(-(N // 2), -(N // 2) + N)
+
+
+# ----------------------------------------------------------------------------- type 1
+
+@pytest.mark.parametrize("N1,N2", [(4, 4), (5, 3), (1, 6)])
+def test_type1_brute_force_dense_matrix(N1, N2):
+    """Tiny inputs: f = C h with C_kq = w_q W_q exp(-i k.x_q) built as a dense complex
+    matrix from numpy's complex exponential (matrix form of the quadrature sum,
+    Appendix A5 eq. (enufft_matrix))."""
+    Q = 9
+    x, y, h, w = _cell(Q)
+    win = np.array([0.3, -0.2, 2.9])
+    f = oracle.type1([0, Q], x, y, h, w, win, (N1, N2), scale=0.37, kind=1)[0]
+    W = np.array([oracle.hann(a, b, *win)[0] for a, b in zip(x, y)])
+    KX, KY = np.meshgrid(_modes(N1), _modes(N2))
+    C = 0.37 * np.exp(-1j * (KX.reshape(-1, 1) * x[None, :] + KY.reshape(-1, 1) * y[None, :])) * (w * W)[None, :]
+    ref = (C @ h).reshape(N2, N1)
+    assert np.abs(f - ref).max() <= 1e-13 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("n", [8, 12, 16])
+def test_type1_regular_grid_reduces_to_fft(n):
+    """On an equispaced grid the quadrature sum is the 2D DFT (Section 2.1.1).  With
+    x_r = -pi + 2 pi r / n and w = (2 pi / n)^2, f_k = w (-1)^(kx+ky) FFT2(h)[k mod n]."""
+    r = np.arange(n)
+    xg = -math.pi + 2 * math.pi * r / n
+    X, Y = np.meshgrid(xg, xg)           # h[s, r] at (x_r, y_s)
+    H = RNG.normal(size=(n, n))
+    w = np.full(n * n, (2 * math.pi / n) ** 2)
+    N = n
+    f = oracle.type1([0, n * n], X.ravel(), Y.ravel(), H.ravel(), w, [0, 0, 0], (N, N), kind=0)[0]
+    F = np.fft.fft2(H)
+    k = _modes(N)
+    KX, KY = np.meshgrid(k, k)
+    ref = w[0] * ((-1.0) ** (KX + KY)) * F[KY % n, KX % n]
+    assert np.abs(f - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+def test_type1_single_point_closed_form():
+    """One point: f_k = scale c exp(-i k.x), so |f_k| = |scale c| for every k and
+    f_{k+e_x} / f_k = exp(-i x), f_{k+e_y} / f_k = exp(-i y)."""
+    x, y, h, w = np.array([1.234]), np.array([-2.5]), np.array([3.0]), np.array([0.7])
+    win = np.array([0.5, -0.5, 3.5])
+    f = oracle.type1([0, 1], x, y, h, w, win, (7, 6), scale=1.5, kind=1)[0]
+    W = 0.5 * (1 + math.cos(math.pi * math.hypot(1.234 - 0.5, -2.5 + 0.5) / 3.5))
+    c = 1.5 * 0.7 * W * 3.0
+    assert np.allclose(np.abs(f), abs(c), rtol=1e-14, atol=0)
+    assert np.allclose(f[:, 1:] / f[:, :-1], np.exp(-1j * 1.234), rtol=1e-13, atol=0)
+    assert np.allclose(f[1:, :] / f[:-1, :], np.exp(1j * 2.5), rtol=1e-13, atol=0)
+    assert np.isclose(f[3, 3], c, rtol=1e-14)     # k = 0 is the plain sum
+
+
+def test_type1_linearity_hermitian_shift_period():
+    Q = 300
+    x, y, h1, w = _cell(Q)
+    h2 = RNG.normal(size=Q)
+    win = np.array([0.1, 0.2, 2.8])
+    N = (9, 7)          # odd boxes are symmetric, so f_{-k} is always in the box
+    f1 = oracle.type1([0, Q], x, y, h1, w, win, N)[0]
+    f2 = oracle.type1([0, Q], x, y, h2, w, win, N)[0]
+    f12 = oracle.type1([0, Q], x, y, 2.5 * h1 - 0.75 * h2, w, win, N)[0]
+    assert np.abs(f12 - (2.5 * f1 - 0.75 * f2)).max() <= 1e-12 * np.abs(f12).max()
+    # realness of eq. (series): f_{-k} = conj(f_k)
+    assert np.abs(f1[::-1, ::-1] - np.conj(f1)).max() <= 1e-12 * np.abs(f1).max()
+    # shift theorem (no window): moving every point by (a, b) multiplies f_k by exp(-i k.(a,b))
+    g0 = oracle.type1([0, Q], x, y, h1, w, [0, 0, 0], N, kind=0)[0]
+    g1 = oracle.type1([0, Q], x + 0.3, y - 1.1, h1, w, [0, 0, 0], N, kind=0)[0]
+    KX, KY = np.meshgrid(_modes(N[0]), _modes(N[1]))
+    assert np.abs(g1 - g0 * np.exp(-1j * (KX * 0.3 - KY * 1.1))).max() <= 1e-12 * np.abs(g0).max()
+    # periodicity of the box: integer-mode sums do not see a 2 pi shift
+    g2 = oracle.type1([0, Q], x + 2 * math.pi, y - 4 * math.pi, h1, w, [0, 0, 0], N, kind=0)[0]
+    assert np.abs(g2 - g0).max() <= 1e-11 * np.abs(g0).max()
+
+
+def test_type1_batched_cells_are_independent():
+    counts = [5, 0, 17, 1]
+    off = np.concatenate([[0], np.cumsum(counts)])
+    x, y, h, w = _cell(int(off[-1]))
+    wins = RNG.uniform(0.5, 3.0, size=(4, 3))
+    f = oracle.type1(off, x, y, h, w, wins, (6, 4))
+    for c in range(4):
+        a, b = off[c], off[c + 1]
+        fc = oracle.type1([0, b - a], x[a:b], y[a:b], h[a:b], w[a:b], wins[c], (6, 4))[0]
+        assert np.array_equal(f[c], fc)
+    assert np.all(f[1] == 0)
+
+
+def test_type1_modes_agrees_with_full_box():
+    Q = 200
+    x, y, h, w = _cell(Q)
+    win = np.array([0.0, 0.0, 3.0])
+    f = oracle.type1([0, Q], x, y, h, w, win, (8, 6), scale=2.0)[0]
+    c = oracle.strength(x, y, h, w, win)
+    KX, KY = np.meshgrid(_modes(8), _modes(6))
+    g = oracle.type1_modes(x, y, c, KX.ravel(), KY.ravel(), scale=2.0).reshape(6, 8)
+    assert np.abs(f - g).max() <= 1e-12 * np.abs(f).max()
+
+
+def test_monte_carlo_error_law_and_leakage():
+    """Appendix A3.1: for h = A cos(k_s.x) sampled at Q uniform points with uniform weights,
+    the coefficient at k_s is A/2 plus an error with E|eps|^2 = A^2/(4Q).  Appendix A3.2:
+    for h = 1 the coefficient at any k != 0 has E|C|^2 = 1/Q."""
+    A, Q, S = 1000.0, 150, 300
+    ks = (3, -2)
+    area = (2 * math.pi) ** 2
+    rng = np.random.default_rng(777)
+    vals, leak = [], []
+    for s in range(S):
+        x = rng.uniform(0, 2 * math.pi, Q)
+        y = rng.uniform(0, 2 * math.pi, Q)
+        h = A * np.cos(ks[0] * x + ks[1] * y)
+        w = np.full(Q, area / Q)
+        f = oracle.type1([0, Q], x, y, h, w, [0, 0, 0], (9, 9), scale=1.0 / area, kind=0)[0]
+        vals.append(f[ks[1] + 4, ks[0] + 4])
+        g = oracle.type1([0, Q], x, y, np.ones(Q), w, [0, 0, 0], (9, 9), scale=1.0 / area, kind=0)[0]
+        leak.append(g[4 + 1, 4 + 2])
+    vals = np.array(vals)
+    eps = vals - A / 2
+    m2 = np.mean(np.abs(eps) ** 2)
+    sd = A / (2 * math.sqrt(Q))
+    assert abs(vals.real.mean() - A / 2) < 5 * sd / math.sqrt(S)
+    assert abs(vals.imag.mean()) < 5 * sd / math.sqrt(S)
+    # |eps|^2 / sd^2 is approximately exponential(1): the mean of S draws has rel. sd 1/sqrt(S)
+    assert abs(m2 / sd ** 2 - 1.0) < 5 / math.sqrt(S)
+    lm2 = np.mean(np.abs(np.array(leak)) ** 2)
+    assert abs(lm2 * Q - 1.0) < 5 / math.sqrt(S)
+
+
+# ----------------------------------------------------------------------------- window
+
+def test_hann_values_and_gradient():
+    cx, cy, R = 0.4, -0.3, 2.0
+    assert oracle.hann(cx, cy, cx, cy, R) == (1.0, 0.0, 0.0)
+    W, _, _ = oracle.hann(cx + 1.0, cy, cx, cy, R)
+    assert abs(W - 0.5) < 1e-15
+    assert oracle.hann(cx + 2.0, cy, cx, cy, R)[0] == 0.0
+    assert oracle.hann(cx + 1.5, cy + 1.5, cx, cy, R) == (0.0, 0.0, 0.0)
+    assert oracle.hann(5.0, 5.0, 0, 0, 1.0, kind=0) == (1.0, 0.0, 0.0)
+    for (x, y) in [(0.9, 0.1), (-1.0, -0.8), (cx + 1e-9, cy), (0.4, 1.5)]:
+        W, gx, gy = oracle.hann(x, y, cx, cy, R)
+        e = 1e-6
+        fx = (oracle.hann(x + e, y, cx, cy, R)[0] - oracle.hann(x - e, y, cx, cy, R)[0]) / (2 * e)
+        fy = (oracle.hann(x, y + e, cx, cy, R)[0] - oracle.hann(x, y - e, cx, cy, R)[0]) / (2 * e)
+        assert abs(fx - gx) < 1e-8 and abs(fy - gy) < 1e-8
+
+
+# ----------------------------------------------------------------------------- EMS
+
+def _ems_on_list(E, prm, perm_seed=None, real=False):
+    """Run the oracle's EMS on a 1 x J box whose signed modes are the units (no pairing,
+    DC kept), with |f_j|^2 = E_j placed in a shuffled order."""
+    E = np.asarray(E, dtype=np.float64)
+    J = len(E)
+    order = np.arange(J) if perm_seed is None else np.random.default_rng(perm_seed).permutation(J)
+    f = np.zeros((1, J), dtype=np.complex128)
+    phase = np.ones(J) if real else np.exp(1j * np.linspace(0, 5, J))
+    f[0, order] = np.sqrt(E) * phase
+    p = oracle.EmsParams(**{**prm.__dict__, "use_pairs": 0, "exclude_dc": 0})
+    r = oracle.ems(f, p)
+    return r, order
+
+
+def _closed_neff_geometric(r, J):
+    return (1 - r ** J) ** 2 * (1 + r) / ((1 - r) * (1 - r ** (2 * J)))
+
+
+def test_ems_fig2_families_closed_form():
+    g = json.load(open(os.path.join(GOLDEN, "ems_fig2_families.json")))
+    P = g["params"]
+    prm = oracle.EmsParams(k_min=P["k_min"], k_max=P["k_max"], alpha_min=P["alpha_min"],
+                           alpha_max=P["alpha_max"], delta=P["delta"], w1=P["w1"], w2=P["w2"])
+    J, K, d = P["J_star"], P["k_max"], P["delta"]
+    j = np.arange(1, J + 1)
+    fam = {
+        "uniform": np.full(J, 0.5),
+        "exponential": np.exp(1.0 - j),
+        "peak": np.where(j == 1, 1.0, 0.05),
+        "step": np.where(j <= 5, 0.7, 0.35),
+        "geometric": 0.9 * 0.85 ** (j - 1),
+        "cosine": 0.9 * np.cos(math.pi * (j - 1) / (2 * J)),
+    }
+    assert set(fam) == set(g["families"])
+    e1 = math.exp(-1.0)
+    # closed forms (N_eff, S_delta, K*) per family; geometric sums for the decaying ones
+    expect = {
+        "uniform": (20.0, 1.0, 12),
+        "exponential": (_closed_neff_geometric(e1, J), math.exp(-(math.e - 1) / d), 1),
+        "peak": (1.95 ** 2 / (1 + 19 * 0.05 ** 2), (math.exp(-19 / d) + 10) / 11, 1),
+        "step": (8.75 ** 2 / 4.2875, (10 + math.exp(-1 / d)) / 11, 12),
+        "geometric": (_closed_neff_geometric(0.85, J), math.exp(-(1 / 0.85 - 1) / d), 3),
+    }
+    for name, E in fam.items():
+        r, order = _ems_on_list(E, prm, perm_seed=len(name))
+        T, Pk, neff, sdel, C, aC, th, Js = r.stats
+        assert Js == J
+        assert np.isclose(T, E.sum(), rtol=1e-15)
+        if name in expect:
+            n_ref, s_ref, k_ref = expect[name]
+            assert np.isclose(neff, n_ref, rtol=1e-13), name
+            assert np.isclose(sdel, s_ref, rtol=1e-12, atol=1e-300), name
+            assert r.k_star == k_ref, name
+        # C and alpha_C follow eqs. (c_score), (alpha_c) from N_eff and S_delta
+        assert np.isclose(C, 0.5 * min(neff, K) / K + 0.5 * sdel, rtol=1e-15)
+        assert np.isclose(aC, 0.7 * C, rtol=1e-15)
+        # K* by brute force: scan the descending list for the first K with theta >= alpha_C
+        Es = np.sort(E)[::-1]
+        theta = np.cumsum(Es) / Es.sum()
+        kc = int(np.argmax(theta >= aC)) + 1 if (theta >= aC).any() else J
+        assert r.k_star == min(K, max(1, kc)), name
+        assert np.isclose(th, theta[r.k_star - 1], rtol=1e-14)
+        # the kept modes are exactly the top-K* energies
+        kept = np.nonzero(r.keep[0])[0]
+        assert len(kept) == r.k_star
+        assert np.isclose(Pk, Es[:r.k_star].sum(), rtol=1e-14)
+    # cosine family: N_eff and S_delta from their definitions on the (already sorted) list
+    E = fam["cosine"]
+    r, _ = _ems_on_list(E, prm, perm_seed=3)
+    assert np.isclose(r.stats[2], E.sum() ** 2 / (E ** 2).sum(), rtol=1e-13)
+    G = E[:K - 1] / E[1:K]
+    assert np.isclose(r.stats[3], np.mean(np.exp(-(G - 1) / d)), rtol=1e-12)
+    assert r.k_star == 7
+
+
+@pytest.mark.parametrize("eps", [0.97, 0.5, 0.01])
+def test_ems_flat_tail_closed_form(eps):
+    """Appendix A4.1: E = (1, eps, ..., eps) in R^Kmax with J* = Kmax gives
+    S_delta = [exp(-(1/eps - 1)/delta) + Kmax - 2]/(Kmax - 1) and
+    N_eff = [1 + (Kmax - 1) eps]^2 / [1 + (Kmax - 1) eps^2]."""
+    K, d = 12, 0.02
+    E = np.array([1.0] + [eps] * (K - 1))
+    prm = oracle.EmsParams(k_min=1, k_max=K, alpha_min=0.0, alpha_max=0.7, delta=d)
+    r, _ = _ems_on_list(E, prm, perm_seed=5)
+    s_ref = (math.exp(-(1 / eps - 1) / d) + K - 2) / (K - 1)
+    n_ref = (1 + (K - 1) * eps) ** 2 / (1 + (K - 1) * eps ** 2)
+    assert np.isclose(r.stats[3], s_ref, rtol=1e-13)
+    assert np.isclose(r.stats[2], n_ref, rtol=1e-13)
+
+
+@pytest.mark.parametrize("rho,p", [(0.8, 2), (0.9, 3), (0.95, 4)])
+def test_ems_moment_degeneracy_closed_form(rho, p):
+    """Appendix A4.2: the geometric spectrum rho^(j-1) and the two-level step (b x p, c x r)
+    built by eqs. (dformula), (bcformula) share (M1, M2), hence N_eff; their S_delta are
+    exp(-(1/rho - 1)/delta) and [(Kmax - 2) + exp(-(b/c - 1)/delta)] / (Kmax - 1)."""
+    K, d = 12, 0.02
+    A = rho ** np.arange(K)
+    M1, M2 = A.sum(), (A ** 2).sum()
+    r_ = K - p
+    dd = math.sqrt((K * M2 - M1 ** 2) / (p * r_))
+    b = M1 / K + r_ / K * dd
+    c = M1 / K - p / K * dd
+    assert c > 0
+    B = np.array([b] * p + [c] * r_)
+    prm = oracle.EmsParams(k_min=1, k_max=K, alpha_min=0.1, alpha_max=0.9, delta=d)
+    ra, _ = _ems_on_list(A, prm, perm_seed=9)
+    rb, _ = _ems_on_list(B, prm, perm_seed=10)
+    assert np.isclose(ra.stats[2], rb.stats[2], rtol=1e-12)
+    assert np.isclose(ra.stats[2], M1 ** 2 / M2, rtol=1e-13)
+    assert np.isclose(ra.stats[3], math.exp(-(1 / rho - 1) / d), rtol=1e-12)
+    assert np.isclose(rb.stats[3], (K - 2 + math.exp(-(b / c - 1) / d)) / (K - 1), rtol=1e-12)
+
+
+def test_ems_pairs_scale_invariance_and_threshold_bruteforce():
+    """Pair units on a real-data spectrum: K* depends only on ratios (scale invariance);
+    with alpha_min = alpha_max the selection is the plain cumulative threshold (brute
+    force over sorted pair energies); the kept set is closed under k -> -k."""
+    Q = 400
+    x, y, h, w = _cell(Q)
+    win = np.array([0.0, 0.0, 3.0])
+    N1 = N2 = 8
+    f = oracle.type1([0, Q], x, y, h, w, win, (N1, N2))[0]
+    prm = oracle.EmsParams(alpha_min=0.9, alpha_max=0.9)
+    r = oracle.ems(f, prm)
+    r2 = oracle.ems(f * 123.456, prm)
+    assert r.k_star == r2.k_star and np.array_equal(r.keep, r2.keep)
+    assert np.allclose(r.stats[2:5], r2.stats[2:5], rtol=1e-12)
+    # brute force pair energies
+    k = _modes(N1)
+    units = {}
+    for iy, ky in enumerate(k):
+        for ix, kx in enumerate(k):
+            if kx == 0 and ky == 0:
+                continue
+            e = abs(f[iy, ix]) ** 2
+            mx, my = -kx, -ky
+            key = frozenset({(kx, ky)})
+            if k[0] <= mx <= k[-1] and k[0] <= my <= k[-1]:
+                key = frozenset({(kx, ky), (mx, my)})
+            units[key] = units.get(key, 0.0) + e
+    # 8x8 box, k in [-4, 3]: 15 edge singletons (kx or ky = -4) and 48/2 interior pairs
+    assert len(units) == r.stats[7] == 15 + 24
+    Es = np.sort(np.array(list(units.values())))[::-1]
+    th = np.cumsum(Es) / Es.sum()
+    assert r.k_star == int(np.argmax(th >= 0.9)) + 1
+    assert np.isclose(r.stats[0], Es.sum(), rtol=1e-13)
+    kept = r.keep.astype(bool)
+    for iy, ky in enumerate(k):
+        for ix, kx in enumerate(k):
+            if kept[iy, ix] and k[0] <= -kx <= k[-1] and k[0] <= -ky <= k[-1]:
+                assert kept[list(k).index(-ky), list(k).index(-kx)]
+    assert not kept[N2 // 2, N1 // 2]        # DC excluded
+
+
+def test_ems_ties_break_by_unit_id_and_edge_cases():
+    prm = oracle.EmsParams(k_min=1, k_max=3, alpha_min=0.99, alpha_max=0.99)
+    r, order = _ems_on_list(np.ones(6), prm, perm_seed=4, real=True)   # exact ties
+    assert r.k_star == 3
+    assert list(np.nonzero(r.keep[0])[0]) == [0, 1, 2]
+    assert list(r.sorted_id) == list(range(6))
+    # zero total power: K* = min(K_min, J*)
+    r0, _ = _ems_on_list(np.zeros(5), oracle.EmsParams(k_min=2, k_max=4))
+    assert r0.k_star == 2 and r0.stats[0] == 0.0
+    # one unit: S_delta = 1 by convention
+    r1, _ = _ems_on_list(np.array([2.0]), oracle.EmsParams(k_min=1, k_max=4))
+    assert r1.k_star == 1 and r1.stats[3] == 1.0
+    # k_min above the threshold count
+    r2, _ = _ems_on_list(np.array([10.0, 1, 1, 1]), oracle.EmsParams(k_min=3, k_max=4, alpha_min=0.5, alpha_max=0.5))
+    assert r2.k_star == 3
+
+
+# ----------------------------------------------------------------------------- adjoint
+
+def test_vjp_adjoint_identity():
+    """<T1 c, g> = <c, Re T2 g> with the real inner product Re sum conj(a) b."""
+    Q = 120
+    x, y, c, _ = _cell(Q)
+    N = (7, 6)
+    g = RNG.normal(size=(1, N[1], N[0])) + 1j * RNG.normal(size=(1, N[1], N[0]))
+    f = oracle.type1([0, Q], x, y, c, np.ones(Q), [0, 0, 0], N, scale=0.8, kind=0)
+    u, _, _ = oracle.type1_vjp([0, Q], x, y, c, np.ones(Q), [0, 0, 0], N, g, scale=0.8, kind=0)
+    lhs = np.real(np.sum(np.conj(f) * g))
+    rhs = np.dot(c, u)
+    assert abs(lhs - rhs) <= 1e-12 * (abs(lhs) + np.abs(f).sum() * np.abs(g).max())
+
+
+def test_vjp_single_point_closed_form():
+    """One point, keep all K modes: P = K (s w W h)^2, dP/dh = 2K s^2 w^2 W^2 h,
+    dP/dx = 2K s^2 w^2 h^2 W dW/dx."""
+    x, y, h, w = np.array([0.8]), np.array([-0.4]), np.array([2.0]), np.array([0.3])
+    win = np.array([0.1, 0.2, 2.5])
+    N = (5, 4)
+    K = 20
+    s = 0.9
+    f = oracle.type1([0, 1], x, y, h, w, win, N, scale=s)
+    W, dWx, dWy = oracle.hann(0.8, -0.4, *win)
+    g = 2.0 * f
+    gh, gx, gy = oracle.type1_vjp([0, 1], x, y, h, w, win, N, g, scale=s)
+    assert np.isclose(np.sum(np.abs(f) ** 2), K * (s * 0.3 * W * 2.0) ** 2, rtol=1e-14)
+    assert np.isclose(gh[0], 2 * K * s ** 2 * 0.09 * W ** 2 * 2.0, rtol=1e-12)
+    assert np.isclose(gx[0], 2 * K * s ** 2 * 0.09 * 4.0 * W * dWx, rtol=1e-12)
+    assert np.isclose(gy[0], 2 * K * s ** 2 * 0.09 * 4.0 * W * dWy, rtol=1e-12)
+
+
+def test_vjp_finite_differences_on_retained_power():
+    """Central differences (step 1e-6, FP64) of P = sum_keep |f_k|^2 with the kept set frozen
+    match the analytic gradient from the direct type-2 sums."""
+    b = synth.config1(count_scale=0.004, n_cells=3)
+    inp = oracle.batch_inputs(b)
+    inp["n_modes"] = (16, 16)
+    prm = oracle.EmsParams(alpha_min=0.95, alpha_max=0.95)
+    res = oracle.retained_power_grad(prm=prm, **inp)
+    keep = res["keep"]
+    off = inp["offsets"]
+
+    def P(x, y, h):
+        f = oracle.type1(off, x, y, h, inp["w"], inp["windows"], inp["n_modes"])
+        return np.sum(np.abs(f) ** 2 * keep)
+
+    rng = np.random.default_rng(5)
+    idx = rng.choice(len(inp["x"]), size=6, replace=False)
+    P0 = P(inp["x"], inp["y"], inp["h"])
+    step = 1e-6
+    for j in idx:
+        for name, key in (("h", "grad_h"), ("x", "grad_x"), ("y", "grad_y")):
+            a = {k: inp[k].copy() for k in ("x", "y", "h")}
+            bb = {k: inp[k].copy() for k in ("x", "y", "h")}
+            sc = step * max(1.0, abs(inp[name][j]))
+            a[name][j] += sc
+            bb[name][j] -= sc
+            fd = (P(a["x"], a["y"], a["h"]) - P(bb["x"], bb["y"], bb["h"])) / (2 * sc)
+            an = res[key][j]
+            # rounding floor of a central difference of P in FP64
+            noise = 64 * np.finfo(float).eps * P0 / (2 * sc)
+            assert abs(fd - an) <= 1e-6 * abs(an) + noise, (name, j, fd, an, noise)

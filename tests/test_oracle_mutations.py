@@ -1,0 +1,54 @@
+"""Planted mistakes in the oracle must be caught by its pins.
+
+Each case copies oracle.c, applies one plausible mistake (a sign, a dropped
+term, a swapped index, a wrong convention), builds it on the CPU and runs the
+pin suite against it; the suite must fail.  This shows the pins constrain
+every part of the oracle, not just that the current build passes them.
+"""
+import os
+import subprocess
+import sys
+import tempfile
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "oracle", "oracle.c")
+
+MUTATIONS = [
+    ("type1 sign of the x phase", "ex[2 * i + 1] = -sin(k * x[j]);", "ex[2 * i + 1] = sin(k * x[j]);"),
+    ("type1 complex product", "row[2 * i + 1] += yr * xi + yi * xr;", "row[2 * i + 1] += yr * xi - yi * xr;"),
+    ("mode box offset", "static int mode_lo(int N) { return -(N / 2); }", "static int mode_lo(int N) { return -((N - 1) / 2); }"),
+    ("window dropped from the strength", "return w * W * h;", "return w * h;"),
+    ("Hann sign", "*W = 0.5 * (1.0 + cos(u));", "*W = 0.5 * (1.0 - cos(u));"),
+    ("Hann gradient transposed", "*dWdy = g * dy;", "*dWdy = g * dx;"),
+    ("scale dropped", "for (int64_t m = 0; m < 2 * M; ++m) out[m] *= scale;", ""),
+    ("EMS tie-break reversed", "return (a->id < b->id) ? -1 : (a->id > b->id);", "return (a->id > b->id) ? -1 : (a->id < b->id);"),
+    ("EMS participation ratio", "tot * tot / tot2", "tot / tot2"),
+    ("EMS gap ratio inverted", "term = exp(-(a / b - 1.0) / delta);", "term = exp(-(b / a - 1.0) / delta);"),
+    ("EMS S_delta normaliser", "sdel = acc / (double)(Jmax - 1);", "sdel = acc / (double)(Jmax);"),
+    ("EMS N_eff clip dropped", "w1 * nclip / (double)Jmax", "w1 * neff / (double)Jmax"),
+    ("EMS threshold off by one", "if (run / tot >= alphaC) { kc = j + 1; break; }", "if (run / tot >= alphaC) { kc = j + 2; break; }"),
+    ("EMS no pairing", "if (use_pairs && !(kx == 0 && ky == 0)) {", "if (0) {"),
+    ("EMS k_min ignored", "int k = (kc > k_min) ? kc : k_min;", "int k = kc;"),
+    ("adjoint x derivative sign", "sx += -kxv * im;", "sx += kxv * im;"),
+    ("adjoint phase sign", "ey[2 * i + 1] = sin(k * y[j]);", "ey[2 * i + 1] = -sin(k * y[j]);"),
+    ("adjoint grad_x uses y derivative", "(dWx * u + W * ux)", "(dWx * u + W * uy)"),
+    ("adjoint window derivative dropped", "(dWy * u + W * uy)", "(W * uy)"),
+]
+
+
+@pytest.mark.parametrize("name,old,new", MUTATIONS, ids=[m[0] for m in MUTATIONS])
+def test_pins_catch_mutation(name, old, new):
+    src = open(SRC).read()
+    assert src.count(old) == 1, "mutation site not unique: " + old
+    with tempfile.TemporaryDirectory() as td:
+        mut = os.path.join(td, "oracle_mut.c")
+        lib = os.path.join(td, "liboracle_mut.so")
+        open(mut, "w").write(src.replace(old, new))
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-o", lib, mut, "-lm"])
+        env = dict(os.environ, ENUFFT_ORACLE_LIB=lib, OMP_NUM_THREADS="2")
+        r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
+                            os.path.join(ROOT, "tests", "test_oracle.py")],
+                           cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
+        assert r.returncode != 0, "pins did not catch: " + name
