@@ -1,0 +1,223 @@
+/*
+ * enufft.h -- C ABI of the MI355X (gfx950) ENUFFT hot path.
+ *
+ * What it computes (per cell c of a batch, local coordinates on a periodic box
+ * of side 2*pi so that wave numbers are integers, Appendix A1 with L = 2*pi):
+ *
+ *   f_c[k] = scale * sum_{j in c} w_j * W_c(x_j, y_j) * h_j * exp(-i (kx x_j + ky y_j))
+ *
+ * i.e. the windowed, quadrature-weighted type-1 sum of Section 2.1.1 eq. (quad)
+ * and Appendix A2 eq. (discrete_quadrature), evaluated as a type-1 NUFFT
+ * (Section 2.1.2: spread, FFT, deconvolve, truncate), followed by Elastic Mode
+ * Selection over the resulting power (Section 2.2), and the adjoint (a type-2
+ * NUFFT, +i sign of eq. (series)) that gives gradients of a retained-power loss
+ * with respect to heights and point coordinates.
+ *
+ * Conventions shared by every entry point
+ *   Layout.    Points are grouped by cell (CSR): cell c owns points
+ *              [cell_offsets[c], cell_offsets[c+1]) of the x, y, h, w arrays.
+ *              Coefficients are complex interleaved (re, im), per cell a
+ *              row-major N2 x N1 block, k_y slow and k_x fast, each ascending
+ *              from -floor(N/2) to ceil(N/2) - 1.
+ *   Precision. Real arrays are float for ENUFFT_F32 plans and double for
+ *              ENUFFT_F64 plans; coefficient arrays are float2 / double2.
+ *   Memory.    Pointers documented "device" are caller-owned device memory,
+ *              borrowed until the enqueued work completes on the plan's
+ *              stream; the library never frees them.  Host arrays passed to
+ *              enufft_plan are deep-copied.
+ *   Streams.   Every compute call enqueues asynchronously on the plan's stream
+ *              and returns; only enufft_plan (which may run timed trial
+ *              launches when autotuning) and enufft_get_timing synchronise.
+ *   Errors.    Every call returns an enufft_status; no exception crosses the
+ *              ABI.  Arguments are validated before any device work, so an
+ *              argument error leaves outputs untouched and the plan usable.
+ *              enufft_last_error() describes the last failure.
+ *   Threads.   A plan is not thread-safe; separate plans may be used
+ *              concurrently on separate streams.
+ *   Coordinates are any finite reals in box units; they are folded modulo 2*pi
+ *   for the transform (the window uses the unfolded values).
+ */
+#ifndef ENUFFT_H
+#define ENUFFT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct enufft_plan_s *enufft_plan_t;
+
+typedef enum {
+    ENUFFT_OK = 0,
+    ENUFFT_EINVAL = 1,   /* bad argument (null pointer, bad size, non-monotone offsets, ...) */
+    ENUFFT_ENOMEM = 2,   /* device or host allocation failed (or exceeded ENUFFT_ALLOC_CAP_MB) */
+    ENUFFT_EDEVICE = 3,  /* HIP runtime error or no usable gfx950 device */
+    ENUFFT_EEPS = 4,     /* requested eps is not attainable at the requested precision */
+    ENUFFT_ESTATE = 5,   /* plan unusable after an earlier device fault */
+    ENUFFT_EUNSUPPORTED = 6 /* valid request outside what this build implements */
+} enufft_status;
+
+typedef enum { ENUFFT_F32 = 0, ENUFFT_F64 = 1 } enufft_precision;
+
+/* Per-cell window W_c.  NONE: W = 1.  HANN_RADIAL: W(r) = (1 + cos(pi r / R)) / 2 for
+ * r = |(x, y) - (cx, cy)| < R and 0 otherwise (a C^1 taper standing in for the
+ * indicator masks of Appendix A1; radius must be > 0). */
+typedef enum { ENUFFT_WIN_NONE = 0, ENUFFT_WIN_HANN_RADIAL = 1 } enufft_window_kind;
+
+typedef struct { double cx, cy, radius; } enufft_window;
+
+/* Transform options.
+ *   n_modes   N1 (along x) and N2 (along y), each in [1, 64] for this build's
+ *             LDS-resident path (the fine grid must fit one workgroup's LDS).
+ *   sigma     oversampling factor (>= 1.25); the fine grid per axis is the
+ *             smallest power of two >= max(16, sigma * N) (Section 2.1.2, Step 1).
+ *   eps       requested relative accuracy of the spreading approximation; sets the
+ *             exponential-of-semicircle kernel width.  F32 needs eps >= 1e-6, F64
+ *             eps >= 1e-13 (else ENUFFT_EEPS).
+ *   precision enufft_precision.
+ *   window_kind enufft_window_kind.
+ *   scale     overall factor on f (1 / |D| reproduces eq. (discrete_quadrature)).
+ *   autotune  0: default launch shape; 1: timed trials at plan time on synthetic
+ *             points with the plan's cell sizes (synchronises the stream).
+ *   kernel_width 0: from eps; otherwise a width >= the eps-derived one. */
+typedef struct {
+    int32_t n_modes[2];
+    double sigma;
+    double eps;
+    int32_t precision;
+    int32_t window_kind;
+    double scale;
+    int32_t autotune;
+    int32_t kernel_width;
+} enufft_opts;
+
+/* Elastic Mode Selection parameters (Section 2.2).
+ *   k_min, k_max      the budget K_min <= K* <= K_max of eq. (k_elastic).
+ *   alpha_min/max     the target range of eq. (alpha_c), each in [0, 1].
+ *   delta             the gap-ratio scale of eq. (s_delta), > 0.
+ *   w1, w2            the weights of eq. (c_score), each in [0, 1].
+ *   use_pairs         1: units are +-k pairs (energy below eq. (energy)), a mode
+ *                     whose partner is outside the box is its own unit; 0: every
+ *                     signed mode is a unit.
+ *   exclude_dc        1: the k = 0 mode is not a unit (it is never kept). */
+typedef struct {
+    int32_t k_min, k_max;
+    double alpha_min, alpha_max, delta, w1, w2;
+    int32_t use_pairs, exclude_dc;
+} enufft_ems_params;
+
+typedef struct {
+    int32_t n_modes[2];      /* N1, N2 */
+    int32_t grid[2];         /* fine grid n1, n2 */
+    int32_t kernel_width;    /* spreading kernel width in fine-grid cells */
+    double beta;             /* ES shape: psi(z) = exp(beta (sqrt(1 - z^2) - 1)) */
+    int64_t n_cells;
+    int64_t n_points;
+    int64_t n_items_fwd;     /* work items of the batched forward launch */
+    int64_t n_split_cells;   /* cells spread by several workgroups and merged */
+    int64_t n_items_adj;     /* work items of the batched adjoint launch */
+    int32_t adj_bands;       /* row bands per cell in the adjoint */
+    int32_t fwd_threads, fwd_blocks;   /* forward launch shape */
+    int32_t adj_threads, adj_blocks;
+    int64_t workspace_bytes;
+} enufft_plan_info;
+
+/* Fill *o with defaults: 64 x 64 modes, sigma 2, eps 1e-5, F32, Hann window,
+ * scale 1, no autotuning. */
+enufft_status enufft_default_opts(enufft_opts *o);
+
+/* Create a plan for a fixed batch layout.
+ *   out          receives the plan (set to NULL on failure).
+ *   n_cells      number of cells, >= 0.
+ *   cell_offsets host, n_cells + 1 int64, [0] = 0, non-decreasing.
+ *   windows      host, n_cells entries (may be NULL for ENUFFT_WIN_NONE).
+ *   opts         host, see enufft_opts.
+ *   hip_stream   hipStream_t for every later call (NULL = default stream).
+ * Builds the deconvolution tables (FP64 quadrature of the kernel's Fourier
+ * transform, Section 2.1.2 Step 4), the work schedule and the workspace. */
+enufft_status enufft_plan(enufft_plan_t *out, int64_t n_cells, const int64_t *cell_offsets,
+                          const enufft_window *windows, const enufft_opts *opts, void *hip_stream);
+
+/* Change the stream later calls enqueue on. */
+enufft_status enufft_set_stream(enufft_plan_t p, void *hip_stream);
+
+/* Batched type-1 (Section 2.1.2 Steps 1-4 plus truncation to the mode box).
+ *   x, y, h, w  device, n_points each: coordinates, heights, quadrature weights.
+ *   f           device, n_cells * N2 * N1 complex: written in full.
+ * One persistent launch spreads every cell into an LDS-resident fine grid,
+ * runs the FFT in LDS, deconvolves and crops; cells larger than one work
+ * item are spread by several workgroups and merged by the last to finish. */
+enufft_status enufft_type1_batched(enufft_plan_t p, const void *x, const void *y, const void *h,
+                                   const void *w, void *f);
+
+/* Elastic Mode Selection on coefficients f (Section 2.2, eqs. energy ... k_elastic).
+ *   f           device, n_cells * N2 * N1 complex (the plan's precision).
+ *   prm         host parameters.
+ *   mode_weight device, N2 * N1 doubles (the w_mn of eq. (weighted_e)), or NULL for 1.
+ *   keep        device, n_cells * N2 * N1 bytes: 1 for kept modes, else 0.
+ *   k_star      device, n_cells int32: the elastic count K*.
+ *   stats       device, n_cells * 8 doubles: (T, P, N_eff, S_delta, C, alpha_C,
+ *               theta(K*), J*) with T the total unit energy and P the kept power
+ *               sum |f_k|^2.  Energies, sums and the cumulative threshold are FP64.
+ * Units are ordered by descending energy, ties by ascending row-major index of
+ * the unit's representative (the member with k_y > 0, or k_y = 0 and k_x > 0). */
+enufft_status enufft_ems(enufft_plan_t p, const void *f, const enufft_ems_params *prm,
+                         const double *mode_weight, uint8_t *keep, int32_t *k_star, double *stats);
+
+/* Adjoint of the batched type-1 map (a type-2 NUFFT) and the chain rule.
+ *   fbar        device, n_cells * N2 * N1 complex cotangent g = dL/dRe f + i dL/dIm f
+ *               (for L = sum_c lambda_c P_c this is 2 lambda_c f keep).
+ *   grad_h, grad_x, grad_y  device, n_points each, or NULL to skip; written in full:
+ *     u_j  = scale Re sum_k g_k exp(+i k.x_j),  (ux_j, uy_j) likewise with (i kx, i ky) g_k,
+ *     grad_h = w W u,  grad_x = w h (dW/dx u + W ux),  grad_y = w h (dW/dy u + W uy).
+ * The fine grids are recomputed from fbar (never stored by the forward). */
+enufft_status enufft_type1_adjoint(enufft_plan_t p, const void *x, const void *y, const void *h,
+                                   const void *w, const void *fbar, void *grad_h, void *grad_x,
+                                   void *grad_y);
+
+/* Gradients of the retained-power loss L = sum_c lam_c P_c, P_c = sum over kept modes
+ * of |f_c[k]|^2 (the quantity EMS preserves, Section 2.2), with the kept set held
+ * fixed: enufft_type1_adjoint with the cotangent 2 lam_c f keep formed inside the
+ * kernel instead of by the caller.
+ *   f     device, n_cells * N2 * N1 complex: the coefficients of the forward pass.
+ *   keep  device, n_cells * N2 * N1 bytes from enufft_ems.
+ *   lam   device, n_cells doubles, or NULL for lam_c = 1.
+ *   other arguments as enufft_type1_adjoint. */
+enufft_status enufft_retained_power_adjoint(enufft_plan_t p, const void *x, const void *y, const void *h,
+                                            const void *w, const void *f, const uint8_t *keep,
+                                            const double *lam, void *grad_h, void *grad_x, void *grad_y);
+
+/* Plain per-cell form of type-1 + EMS for comparison: the same kernels,
+ * launched once per cell from a host loop on the plan's stream (no batching,
+ * no graph).  Arguments as enufft_type1_batched and enufft_ems. */
+enufft_status enufft_percell_loop(enufft_plan_t p, const void *x, const void *y, const void *h,
+                                  const void *w, void *f, const enufft_ems_params *prm,
+                                  const double *mode_weight, uint8_t *keep, int32_t *k_star,
+                                  double *stats);
+
+/* Record HIP events around every main-kernel launch (enable = 1), or stop (0). */
+enufft_status enufft_set_timing(enufft_plan_t p, int32_t enable);
+
+/* Synchronise on the recorded events and return, per kernel kind, the summed
+ * launch durations in ms and the launch counts: out[0..2] = ms of type-1, EMS,
+ * adjoint; out[3..5] = launch counts.  Clears the record. */
+enufft_status enufft_get_timing(enufft_plan_t p, double *out6);
+
+enufft_status enufft_get_info(enufft_plan_t p, enufft_plan_info *info);
+
+/* Destroy a plan (waits for its stream) and free its workspace.  NULL is a no-op. */
+enufft_status enufft_destroy(enufft_plan_t p);
+
+/* Text of the last error of p, or of the calling thread when p is NULL.  The
+ * string is owned by the library and valid until the next call. */
+const char *enufft_last_error(enufft_plan_t p);
+
+/* Library version string. */
+const char *enufft_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ENUFFT_H */

@@ -1,0 +1,480 @@
+// Adjoint of the batched type-1 map on gfx950: a type-2 NUFFT (the +i sign of
+// the series, eq. series) followed by the chain rule through the per-point
+// strength c_j = w_j W(x_j) h_j.
+//
+// For a cotangent g on the coefficients, u_j = scale Re sum_k g_k exp(+i k.x_j)
+// and its coordinate derivatives come from three fine grids: the pre-corrected
+// spectrum (g_k divided by the kernel factors p(kx) p(ky), the inverse of
+// Step 4) made Hermitian, and the same times i kx and i ky, each brought to the
+// grid by an inverse FFT; the points then gather W x W taps from each grid with
+// the same spreading kernel.  The three grids of a whole cell do not fit in
+// LDS, so each work item rebuilds one row band (plus the kernel's halo) and
+// serves the points whose footprint starts in that band.  Nothing of the
+// forward pass is stored.
+#include <algorithm>
+#include <string>
+
+#include "device_common.h"
+#include "launch.h"
+#include "plan.h"
+
+namespace enufft {
+
+struct AdjLayout {
+  int rows;       // band rows including halo = band_rows + W
+  int cpitch;     // column-workspace pitch (elements) = 2 (K1 + 1) + 2
+  size_t g_off, gx_off, gy_off, db0_off, db1_off, ws_off;   // element offsets
+  size_t total;   // elements
+};
+
+__host__ __device__ inline AdjLayout adj_layout(const Geom &g, int W, int band_rows) {
+  AdjLayout L;
+  L.rows = band_rows + W;
+  L.cpitch = 2 * (g.K1 + 1) + 2;
+  const size_t gsz = (size_t)L.rows * g.pitch;
+  L.g_off = 0;
+  L.gx_off = gsz;
+  L.gy_off = 2 * gsz;
+  // the column workspace aliases the grids (it is dead before they are
+  // written) but never the band spectra, which are filled while it is live
+  const size_t ws = (size_t)g.n2 * L.cpitch;
+  L.ws_off = 0;
+  L.db0_off = std::max(3 * gsz, ws);
+  L.db1_off = L.db0_off + (size_t)L.rows * (g.K1 + 1) * 2;
+  L.total = L.db1_off + (size_t)L.rows * (g.K1 + 1) * 2;
+  return L;
+}
+
+// Fill the column workspace with the Hermitian, pre-corrected spectrum for
+// columns kx = 0..K1 over all n2 bins; with yderiv, multiplied by i ky.
+template <typename T, int NT>
+__device__ void load_columns(const AdjArgs<T> &a, const T *gc, int cell, T *ws, int cpitch, bool yderiv) {
+  const Geom &g = a.g;
+  const int per = g.K1 + 1;
+  const int hi1 = g.lo1 + g.N1 - 1, hi2 = g.lo2 + g.N2 - 1;
+  // retained-power cotangent g = 2 lam_c f keep, formed on the fly
+  const uint8_t *kp = a.keep ? a.keep + (int64_t)cell * g.N1 * g.N2 : nullptr;
+  const T two_lam = a.keep ? T(2.0 * (a.lam ? a.lam[cell] : 1.0)) : T(1);
+  for (int it = threadIdx.x; it < g.n2 * per; it += NT) {
+    const int bin = it / per, kx = it - bin * per;
+    const int ky = bin <= g.n2 / 2 ? bin : bin - g.n2;   // signed frequency of this bin
+    T hr = 0, hi = 0;
+    if (ky >= -g.K2 && ky <= g.K2) {
+      const T s = a.decon_x[kx] * a.decon_y[ky < 0 ? -ky : ky];
+      // G(kx, ky) and conj G(-kx, -ky), each zero outside the box
+      if (kx <= hi1 && ky >= g.lo2 && ky <= hi2) {
+        const int m = (ky - g.lo2) * g.N1 + (kx - g.lo1);
+        const T sc = kp ? (kp[m] ? two_lam : T(0)) : T(1);
+        hr += sc * gc[2 * m];
+        hi += sc * gc[2 * m + 1];
+      }
+      if (-kx >= g.lo1 && -ky >= g.lo2 && -ky <= hi2) {
+        const int m = (-ky - g.lo2) * g.N1 + (-kx - g.lo1);
+        const T sc = kp ? (kp[m] ? two_lam : T(0)) : T(1);
+        hr += sc * gc[2 * m];
+        hi -= sc * gc[2 * m + 1];
+      }
+      hr *= T(0.5) * s;
+      hi *= T(0.5) * s;
+      if (yderiv) {   // times i ky
+        const T t = hr;
+        hr = -T(ky) * hi;
+        hi = T(ky) * t;
+      }
+    }
+    ws[bin * cpitch + 2 * kx] = hr;
+    ws[bin * cpitch + 2 * kx + 1] = hi;
+  }
+  __syncthreads();
+}
+
+// Copy the band rows (with halo) of the inverse-transformed columns into db.
+template <typename T, int NT>
+__device__ void extract_band(const Geom &g, const T *ws, int cpitch, T *db, int rows, int y0) {
+  const int per = g.K1 + 1;
+  for (int it = threadIdx.x; it < rows * per; it += NT) {
+    const int r = it / per, kx = it - r * per;
+    const int y = (y0 + r) & (g.n2 - 1);
+    const int pos = fft_pos(y, g.n2);
+    db[2 * (r * per + kx)] = ws[pos * cpitch + 2 * kx];
+    db[2 * (r * per + kx) + 1] = ws[pos * cpitch + 2 * kx + 1];
+  }
+  __syncthreads();
+}
+
+template <typename T, int W, int NT>
+__global__ __launch_bounds__(NT) void adj_kernel(AdjArgs<T> a) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T *sm = reinterpret_cast<T *>(smem_raw);
+  __shared__ int s_item;
+  const Geom &g = a.g;
+  const int pitch = g.pitch;
+  const AdjLayout L = adj_layout(g, W, a.band_rows);
+  T *Gu = sm + L.g_off, *Gx = sm + L.gx_off, *Gy = sm + L.gy_off;
+  T *db0 = sm + L.db0_off, *db1 = sm + L.db1_off, *ws = sm + L.ws_off;
+  const int per = g.K1 + 1;
+  const bool persistent = a.work_counter != nullptr;
+  int64_t idx = a.item_base + blockIdx.x;
+  if (!persistent && idx >= a.n_items) return;
+  for (;;) {
+    if (persistent) {
+      if (threadIdx.x == 0) s_item = atomicAdd(a.work_counter, 1);
+      __syncthreads();
+      idx = s_item;
+      __syncthreads();
+      if (idx >= a.n_items) break;
+    }
+    const AdjItem it = a.items[idx];
+    const T *gc = a.fbar + (int64_t)it.cell * g.N1 * g.N2 * 2;
+    const int y0 = it.band * a.band_rows - W / 2;   // fine row of band-local row 0
+
+    // columns of H and of i ky H, inverse transformed along y; keep the band rows
+    load_columns<T, NT>(a, gc, it.cell, ws, L.cpitch, false);
+    fft_batch<true, NT, T>(g.n2, per, a.tw2, [&](int q) {
+      ColAcc<T> acc;
+      acc.base = ws + 2 * q;
+      acc.stride = L.cpitch;
+      return acc;
+    });
+    extract_band<T, NT>(g, ws, L.cpitch, db0, L.rows, y0);
+    load_columns<T, NT>(a, gc, it.cell, ws, L.cpitch, true);
+    fft_batch<true, NT, T>(g.n2, per, a.tw2, [&](int q) {
+      ColAcc<T> acc;
+      acc.base = ws + 2 * q;
+      acc.stride = L.cpitch;
+      return acc;
+    });
+    extract_band<T, NT>(g, ws, L.cpitch, db1, L.rows, y0);
+
+    // Row stage.  Pair (u_r, ux_r): Z(k) = D(k) + i (i k D(k)); pair (uy_r, uy_r+1):
+    // Z(k) = Dy_r(k) + i Dy_r+1(k); negative bins from Hermitian symmetry.
+    const int n1 = g.n1;
+    const int ny_pairs = L.rows / 2;
+    for (int i2 = threadIdx.x; i2 < L.rows * n1; i2 += NT) {
+      const int r = i2 / n1, k = i2 - r * n1;
+      T zr = 0, zi = 0, yr = 0, yi = 0;
+      const int kk = k <= n1 / 2 ? k : n1 - k;     // |frequency| of this bin
+      if (kk <= g.K1 && (k == kk || kk > 0)) {
+        const bool neg = k != kk;
+        T dr = db0[2 * (r * per + kk)], di = db0[2 * (r * per + kk) + 1];
+        if (neg) di = -di;
+        const T kf = neg ? -T(kk) : T(kk);
+        // Z = D + i (i k D) = (1 - k) D
+        zr = dr - kf * dr;
+        zi = di - kf * di;
+        const int rr = r;   // uy rows r (re) and r + 1 (im) for even r
+        if ((rr & 1) == 0) {
+          T ar = db1[2 * (rr * per + kk)], ai = db1[2 * (rr * per + kk) + 1];
+          T br = 0, bi = 0;
+          if (rr + 1 < L.rows) { br = db1[2 * ((rr + 1) * per + kk)]; bi = db1[2 * ((rr + 1) * per + kk) + 1]; }
+          if (neg) { ai = -ai; bi = -bi; }
+          yr = ar - bi;
+          yi = ai + br;
+        }
+      }
+      Gu[r * pitch + k] = zr;
+      Gx[r * pitch + k] = zi;
+      if ((r & 1) == 0) {
+        Gy[r * pitch + k] = yr;
+        if (r + 1 < L.rows) Gy[(r + 1) * pitch + k] = yi;
+      }
+    }
+    __syncthreads();
+    fft_batch<true, NT, T>(n1, L.rows, a.tw1, [&](int q) {
+      RowPairAcc<T> acc;
+      acc.r0 = Gu + q * pitch;
+      acc.r1 = Gx + q * pitch;
+      return acc;
+    });
+    // band rows = band_rows + W is even (both terms are), so uy rows pair up exactly
+    fft_batch<true, NT, T>(n1, ny_pairs, a.tw1, [&](int q) {
+      RowPairAcc<T> acc;
+      acc.r0 = Gy + (2 * q) * pitch;
+      acc.r1 = acc.r0 + pitch;
+      return acc;
+    });
+
+    // Gather at the points of this band.
+    const T n1f = T(g.n1), n2f = T(g.n2);
+    const T s1 = n1f / T(2.0 * M_PI), s2 = n2f / T(2.0 * M_PI);
+    const T halfw = T(W) / T(2);
+    const T zsc = T(2) / T(W);
+    const double *wn = a.windows + 3 * (int64_t)it.cell;
+    const T cx = T(wn[0]), cy = T(wn[1]), R = T(wn[2]);
+    const int band_lo = it.band * a.band_rows;
+    for (int64_t j = it.begin + threadIdx.x; j < it.end; j += NT) {
+      const T yj = a.y[j];
+      const T ty = fold_grid<T>(yj, s2, n2f);
+      int band = (int)floor(ty / T(a.band_rows));
+      band = min(max(band, 0), a.bands - 1);
+      if (band != it.band) continue;
+      const T xj = a.x[j];
+      const T tx = fold_grid<T>(xj, s1, n1f);
+      const int i0x = (int)ceil(tx - halfw);
+      int r0 = (int)ceil(ty - halfw) - band_lo + W / 2;
+      r0 = min(max(r0, 0), a.band_rows);
+      T kx[W], ky[W];
+      int cp[W];
+#pragma unroll
+      for (int d = 0; d < W; ++d) {
+        kx[d] = es_eval(T(i0x + d - tx) * zsc, a.beta);
+        ky[d] = es_eval(T(r0 - W / 2 + band_lo + d - ty) * zsc, a.beta);
+        cp[d] = fft_pos((i0x + d) & (n1 - 1), n1);
+      }
+      T u = 0, ux = 0, uy = 0;
+#pragma unroll
+      for (int dy = 0; dy < W; ++dy) {
+        const int rb = (r0 + dy) * pitch;
+        T su = 0, sx = 0, sy = 0;
+#pragma unroll
+        for (int dx = 0; dx < W; ++dx) {
+          su += kx[dx] * Gu[rb + cp[dx]];
+          sx += kx[dx] * Gx[rb + cp[dx]];
+          sy += kx[dx] * Gy[rb + cp[dx]];
+        }
+        u += ky[dy] * su;
+        ux += ky[dy] * sx;
+        uy += ky[dy] * sy;
+      }
+      T dWx, dWy;
+      const T Wv = hann_wg<T>(a.window_kind, xj, yj, cx, cy, R, dWx, dWy);
+      const T wj = a.w[j];
+      if (a.grad_h) a.grad_h[j] = wj * Wv * u;
+      if (a.grad_x || a.grad_y) {
+        const T wh = wj * a.h[j];
+        if (a.grad_x) a.grad_x[j] = wh * (dWx * u + Wv * ux);
+        if (a.grad_y) a.grad_y[j] = wh * (dWy * u + Wv * uy);
+      }
+    }
+    __syncthreads();
+    if (!persistent) break;
+  }
+  if (persistent && threadIdx.x == 0) {
+    __threadfence();
+    const int old = atomicAdd(a.done_counter, 1);
+    if (old == (int)gridDim.x - 1) {
+      *a.work_counter = 0;
+      *a.done_counter = 0;
+    }
+  }
+}
+
+template <typename T, int W>
+static hipError_t launch_adj_w(const AdjArgs<T> &a, int blocks, int threads, size_t lds, hipStream_t s) {
+  if (threads == 256) hipLaunchKernelGGL((adj_kernel<T, W, 256>), dim3(blocks), dim3(256), lds, s, a);
+  else hipLaunchKernelGGL((adj_kernel<T, W, 512>), dim3(blocks), dim3(512), lds, s, a);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_adj(const AdjArgs<T> &a, int W, int blocks, int threads, size_t lds, hipStream_t s) {
+  switch (W) {
+    case 4: return launch_adj_w<T, 4>(a, blocks, threads, lds, s);
+    case 6: return launch_adj_w<T, 6>(a, blocks, threads, lds, s);
+    case 8: return launch_adj_w<T, 8>(a, blocks, threads, lds, s);
+    case 10: return launch_adj_w<T, 10>(a, blocks, threads, lds, s);
+    case 12: return launch_adj_w<T, 12>(a, blocks, threads, lds, s);
+    case 14: return launch_adj_w<T, 14>(a, blocks, threads, lds, s);
+    case 16: return launch_adj_w<T, 16>(a, blocks, threads, lds, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template hipError_t launch_adj<float>(const AdjArgs<float> &, int, int, int, size_t, hipStream_t);
+template hipError_t launch_adj<double>(const AdjArgs<double> &, int, int, int, size_t, hipStream_t);
+
+// ------------------------------------------------------------------ host side
+
+enufft_status record_start(enufft_plan_t p, int kind, hipEvent_t *ev);
+enufft_status record_stop(enufft_plan_t p, int kind, hipEvent_t start);
+
+// Bands per cell: the fewest row bands whose three grids, band spectra and
+// column workspace fit one workgroup's LDS.
+int choose_bands(const Geom &g, int W, size_t elem, size_t lds_max, int *band_rows, size_t *lds) {
+  if (W & 1) return 0;   // uy rows are transformed in pairs: band rows must be even
+  for (int B = 1; B <= g.n2 / 2; B <<= 1) {
+    const int R = g.n2 / B;
+    if (R < 2) break;
+    const AdjLayout L = adj_layout(g, W, R);
+    const size_t bytes = L.total * elem;
+    if (bytes <= lds_max) {
+      *band_rows = R;
+      *lds = bytes;
+      return B;
+    }
+  }
+  return 0;
+}
+
+// Adjoint work list: every (cell, band) pair, cells above the chunk target cut
+// into point chunks (gathers need no merge), longest first.
+void build_adj_schedule(enufft_plan_t p, int slots) {
+  const int64_t Q = p->n_points;
+  const int B = p->adj_bands;
+  const int64_t T = std::max<int64_t>(16384, (Q * B + 2LL * slots - 1) / std::max(1, 2 * slots));
+  p->adj_items.clear();
+  for (int64_t c = 0; c < p->n_cells; ++c) {
+    const int64_t a = p->offsets[c], b = p->offsets[c + 1];
+    const int64_t q = b - a;
+    if (q == 0) continue;
+    const int64_t nch = std::max<int64_t>(1, (q + T - 1) / T);
+    for (int band = 0; band < B; ++band)
+      for (int64_t i = 0; i < nch; ++i)
+        p->adj_items.push_back(AdjItem{a + q * i / nch, a + q * (i + 1) / nch, (int32_t)c, band, 0, 0});
+  }
+  std::stable_sort(p->adj_items.begin(), p->adj_items.end(), [](const AdjItem &x, const AdjItem &y) {
+    return (x.end - x.begin) > (y.end - y.begin);
+  });
+}
+
+template <typename T>
+hipError_t adj_occ(int W, int threads, size_t lds, int *per_cu) {
+  const void *fn = nullptr;
+#define ENUFFT_PICK(WW) \
+  case WW: fn = threads == 256 ? (const void *)&adj_kernel<T, WW, 256> : (const void *)&adj_kernel<T, WW, 512>; break;
+  switch (W) {
+    ENUFFT_PICK(4) ENUFFT_PICK(6) ENUFFT_PICK(8) ENUFFT_PICK(10) ENUFFT_PICK(12) ENUFFT_PICK(14) ENUFFT_PICK(16)
+    default: return hipErrorInvalidValue;
+  }
+#undef ENUFFT_PICK
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, fn, threads, lds);
+}
+
+// Lazily set up the adjoint schedule on first use.
+enufft_status adj_prepare(enufft_plan_t p) {
+  if (p->d_adj_items) return ENUFFT_OK;
+  hipDeviceProp_t prop;
+  hipError_t e = hipGetDeviceProperties(&prop, p->device);
+  if (e != hipSuccess) {
+    p->last_error = std::string("hipGetDeviceProperties: ") + hipGetErrorString(e);
+    return ENUFFT_EDEVICE;
+  }
+  p->adj_threads = p->prec == ENUFFT_F64 ? 256 : 512;
+  const int B = choose_bands(p->geom, p->W, p->elem, (size_t)prop.sharedMemPerBlock, &p->adj_band_rows, &p->adj_lds);
+  if (B == 0) {
+    p->last_error = "adjoint: fine-grid bands do not fit in LDS";
+    return ENUFFT_EUNSUPPORTED;
+  }
+  p->adj_bands = B;
+  int per_cu = 0;
+  e = p->prec == ENUFFT_F64 ? adj_occ<double>(p->W, p->adj_threads, p->adj_lds, &per_cu)
+                            : adj_occ<float>(p->W, p->adj_threads, p->adj_lds, &per_cu);
+  if (e != hipSuccess || per_cu < 1) {
+    p->last_error = "adjoint kernel cannot be resident";
+    return ENUFFT_EDEVICE;
+  }
+  const int slots = p->n_cu * per_cu;
+  build_adj_schedule(p, slots);
+  p->adj_blocks = (int)std::min<int64_t>(slots, std::max<int64_t>(1, (int64_t)p->adj_items.size()));
+  void *d = nullptr;
+  e = hipMalloc(&d, std::max<size_t>(1, p->adj_items.size()) * sizeof(AdjItem));
+  if (e != hipSuccess) {
+    p->last_error = "adjoint item allocation failed";
+    return ENUFFT_ENOMEM;
+  }
+  p->allocations.push_back(d);
+  p->workspace_bytes += (int64_t)(std::max<size_t>(1, p->adj_items.size()) * sizeof(AdjItem));
+  if (!p->adj_items.empty()) {
+    e = hipMemcpy(d, p->adj_items.data(), p->adj_items.size() * sizeof(AdjItem), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      p->last_error = std::string("adjoint item upload: ") + hipGetErrorString(e);
+      p->faulted = true;
+      return ENUFFT_EDEVICE;
+    }
+  }
+  p->d_adj_items = d;
+  return ENUFFT_OK;
+}
+
+template <typename T>
+AdjArgs<T> make_adj_args(enufft_plan_t p, const void *x, const void *y, const void *h, const void *w,
+                         const void *fbar, void *gh, void *gx, void *gy) {
+  AdjArgs<T> a{};
+  a.x = (const T *)x; a.y = (const T *)y; a.h = (const T *)h; a.w = (const T *)w;
+  a.fbar = (const T *)fbar;
+  a.keep = nullptr;
+  a.lam = nullptr;
+  a.grad_h = (T *)gh; a.grad_x = (T *)gx; a.grad_y = (T *)gy;
+  a.items = (const AdjItem *)p->d_adj_items;
+  a.n_items = (int64_t)p->adj_items.size();
+  a.item_base = 0;
+  a.work_counter = p->d_counters + 2;
+  a.done_counter = p->d_counters + 3;
+  a.windows = (const double *)p->d_windows;
+  a.window_kind = p->window_kind;
+  a.decon_x = (const T *)p->d_decon_x; a.decon_y = (const T *)p->d_decon_y;
+  a.tw1 = (const T *)p->d_tw1; a.tw2 = (const T *)p->d_tw2;
+  a.beta = (T)p->beta;
+  a.bands = p->adj_bands;
+  a.band_rows = p->adj_band_rows;
+  a.g = p->geom;
+  return a;
+}
+
+}  // namespace enufft
+
+namespace enufft {
+enufft_status adjoint_common(enufft_plan_t p, const char *fn, const void *x, const void *y, const void *h,
+                             const void *w, const void *fin, const uint8_t *keep, const double *lam, void *grad_h,
+                             void *grad_x, void *grad_y) {
+  if (!p) return ENUFFT_EINVAL;
+  if (p->faulted) {
+    p->last_error = std::string(fn) + ": plan unusable after a device fault";
+    return ENUFFT_ESTATE;
+  }
+  if (p->n_cells == 0 || p->n_points == 0) return ENUFFT_OK;
+  if (!fin) {
+    p->last_error = std::string(fn) + ": null coefficient input";
+    return ENUFFT_EINVAL;
+  }
+  if (!x || !y || !w || ((grad_x || grad_y) && !h)) {
+    p->last_error = std::string(fn) + ": null point array";
+    return ENUFFT_EINVAL;
+  }
+  if (!grad_h && !grad_x && !grad_y) return ENUFFT_OK;
+  enufft_status st = adj_prepare(p);
+  if (st != ENUFFT_OK) return st;
+  hipEvent_t ev;
+  st = record_start(p, 2, &ev);
+  if (st != ENUFFT_OK) return st;
+  hipError_t e;
+  if (p->prec == ENUFFT_F64) {
+    auto a = make_adj_args<double>(p, x, y, h, w, fin, grad_h, grad_x, grad_y);
+    a.keep = keep;
+    a.lam = lam;
+    e = launch_adj<double>(a, p->W, p->adj_blocks, p->adj_threads, p->adj_lds, p->stream);
+  } else {
+    auto a = make_adj_args<float>(p, x, y, h, w, fin, grad_h, grad_x, grad_y);
+    a.keep = keep;
+    a.lam = lam;
+    e = launch_adj<float>(a, p->W, p->adj_blocks, p->adj_threads, p->adj_lds, p->stream);
+  }
+  if (e != hipSuccess) {
+    p->last_error = std::string(fn) + " launch: " + hipGetErrorString(e);
+    p->faulted = true;
+    return ENUFFT_EDEVICE;
+  }
+  return record_stop(p, 2, ev);
+}
+}  // namespace enufft
+
+extern "C" enufft_status enufft_type1_adjoint(enufft_plan_t p, const void *x, const void *y, const void *h,
+                                              const void *w, const void *fbar, void *grad_h, void *grad_x,
+                                              void *grad_y) {
+  return enufft::adjoint_common(p, "enufft_type1_adjoint", x, y, h, w, fbar, nullptr, nullptr, grad_h, grad_x,
+                                grad_y);
+}
+
+extern "C" enufft_status enufft_retained_power_adjoint(enufft_plan_t p, const void *x, const void *y,
+                                                       const void *h, const void *w, const void *f,
+                                                       const uint8_t *keep, const double *lam, void *grad_h,
+                                                       void *grad_x, void *grad_y) {
+  if (p && !keep) {
+    p->last_error = "enufft_retained_power_adjoint: null keep";
+    return ENUFFT_EINVAL;
+  }
+  return enufft::adjoint_common(p, "enufft_retained_power_adjoint", x, y, h, w, f, keep, lam, grad_h, grad_x,
+                                grad_y);
+}

@@ -1,0 +1,280 @@
+// Device building blocks shared by the gfx950 kernels: work-item records,
+// kernel-argument blocks, the exponential-of-semicircle (ES) spreading kernel,
+// and an in-LDS four-step FFT with small in-register DFTs.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace enufft {
+
+// ------------------------------------------------------------------ records
+
+// One forward work item: points [begin, end) of `cell`.  A cell with more
+// points than one item holds is split into `nchunks` items; chunk partial
+// grids go to slots [slot0, slot0 + nchunks) and the last chunk to finish
+// merges them.  `slot` is this chunk's slot (-1 for an unsplit cell).
+struct FwdItem {
+  int64_t begin, end;
+  int32_t cell, nchunks, slot, slot0;
+};
+
+// One adjoint work item: points [begin, end) of `cell`, row band `band`.
+struct AdjItem {
+  int64_t begin, end;
+  int32_t cell, band, pad0, pad1;
+};
+
+// Fine-grid and mode-box geometry.
+struct Geom {
+  int n1, n2;       // fine grid (powers of two, 16..128)
+  int N1, N2;       // modes per axis
+  int lo1, lo2;     // -floor(N/2)
+  int K1, K2;       // floor(N/2): largest |k| needed per axis
+  int pitch;        // LDS row pitch (elements) = n1 + 2
+};
+
+template <typename T>
+struct FwdArgs {
+  const T *x, *y, *h, *w;
+  T *f;                      // interleaved complex, n_cells * N2 * N1
+  const FwdItem *items;
+  int64_t n_items;
+  int64_t item_base;         // static mode: block b runs item item_base + b
+  int *work_counter;         // persistent mode (NULL: static mode)
+  int *done_counter;
+  int *cell_counters;        // per cell, for merging split cells
+  T *partial;                // partial grids, n1 * n2 reals per slot
+  const double *windows;     // per cell (cx, cy, R)
+  int window_kind;
+  const T *decon_x;          // [K1 + 1]: scale / p_x(|k|)
+  const T *decon_y;          // [K2 + 1]: 1 / p_y(|k|)
+  const T *tw1, *tw2;        // forward twiddles exp(-2 pi i j / n), interleaved, n entries
+  T beta;                    // ES shape parameter
+  Geom g;
+};
+
+template <typename T>
+struct AdjArgs {
+  const T *x, *y, *h, *w;
+  const T *fbar;             // interleaved complex cotangent (or f when keep != NULL)
+  const uint8_t *keep;       // non-NULL: cotangent is 2 lam_c f keep (retained-power loss)
+  const double *lam;         // per-cell loss weights lam_c (NULL: 1)
+  T *grad_h, *grad_x, *grad_y;
+  const AdjItem *items;
+  int64_t n_items;
+  int64_t item_base;
+  int *work_counter;
+  int *done_counter;
+  const double *windows;
+  int window_kind;
+  const T *decon_x, *decon_y;  // as the forward (decon_x carries scale)
+  const T *tw1, *tw2;          // forward twiddles (the inverse uses their conjugates)
+  T beta;
+  int bands, band_rows;        // row bands per cell and rows per band
+  Geom g;
+};
+
+// ------------------------------------------------------------------ ES kernel
+
+// psi(z) = exp(beta (sqrt(1 - z^2) - 1)) on |z| <= 1.  Rounding can push |z|
+// a hair past 1; those taps take the edge value exp(-beta).
+__device__ __forceinline__ float es_eval(float z, float beta) {
+  float s = fmaxf(1.0f - z * z, 0.0f);
+  return __expf(beta * (__builtin_sqrtf(s) - 1.0f));
+}
+__device__ __forceinline__ double es_eval(double z, double beta) {
+  double s = fmax(1.0 - z * z, 0.0);
+  return exp(beta * (sqrt(s) - 1.0));
+}
+
+// Fold a coordinate to fine-grid units t in [0, n): t = x n / (2 pi) mod n.
+template <typename T>
+__device__ __forceinline__ T fold_grid(T x, T n_over_2pi, T n) {
+  T t = x * n_over_2pi;
+  t = t - n * floor(t / n);
+  if (!(t < n)) t = (t >= n) ? t - n : T(0);   // rounding at the top edge; NaN -> 0
+  if (!(t >= T(0))) t = T(0);
+  return t;
+}
+
+__device__ __forceinline__ void sincos_t(float u, float &s, float &c) { sincosf(u, &s, &c); }
+__device__ __forceinline__ void sincos_t(double u, double &s, double &c) { sincos(u, &s, &c); }
+
+// Radial Hann window and gradient; kind 0 is no window.
+template <typename T>
+__device__ __forceinline__ T hann_w(int kind, T x, T y, T cx, T cy, T R) {
+  if (kind == 0) return T(1);
+  T dx = x - cx, dy = y - cy;
+  T r = sqrt(dx * dx + dy * dy);
+  if (!(r < R)) return T(0);
+  return T(0.5) * (T(1) + cos(T(M_PI) * r / R));
+}
+template <typename T>
+__device__ __forceinline__ T hann_wg(int kind, T x, T y, T cx, T cy, T R, T &gx, T &gy) {
+  gx = T(0); gy = T(0);
+  if (kind == 0) return T(1);
+  T dx = x - cx, dy = y - cy;
+  T r = sqrt(dx * dx + dy * dy);
+  if (!(r < R)) return T(0);
+  T u = T(M_PI) * r / R;
+  T s, c;
+  sincos_t(u, s, c);
+  T sinc = (u > T(0)) ? s / u : T(1);
+  T k = -(T(M_PI) * T(M_PI)) / (T(2) * R * R) * sinc;
+  gx = k * dx;
+  gy = k * dy;
+  return T(0.5) * (T(1) + c);
+}
+
+// ------------------------------------------------------------------ small DFTs
+
+// cos(2 pi k / 16) and sin(2 pi k / 16).  Used with compile-time k only, so
+// every twiddle below folds to an immediate.
+__host__ __device__ constexpr double cos16(int k) {
+  switch (k & 15) {
+    case 0: return 1.0;
+    case 1: return 0.92387953251128673848;
+    case 2: return 0.70710678118654752440;
+    case 3: return 0.38268343236508977173;
+    case 4: return 0.0;
+    case 5: return -0.38268343236508977173;
+    case 6: return -0.70710678118654752440;
+    case 7: return -0.92387953251128673848;
+    case 8: return -1.0;
+    case 9: return -0.92387953251128673848;
+    case 10: return -0.70710678118654752440;
+    case 11: return -0.38268343236508977173;
+    case 12: return 0.0;
+    case 13: return 0.38268343236508977173;
+    case 14: return 0.70710678118654752440;
+    default: return 0.92387953251128673848;
+  }
+}
+__host__ __device__ constexpr double sin16(int k) { return cos16(k - 4); }
+
+// In-register DFT of length R (R | 16): X[k] = sum_m x[m] exp(-+ 2 pi i m k / R),
+// minus sign for the forward transform, plus for INV.  Radix-2 decimation in
+// time by recursion; natural order in and out.
+template <int R, bool INV, typename T>
+__device__ __forceinline__ void dft_reg(T *re, T *im) {
+  if constexpr (R == 2) {
+    T ar = re[0], ai = im[0];
+    re[0] = ar + re[1]; im[0] = ai + im[1];
+    re[1] = ar - re[1]; im[1] = ai - im[1];
+  } else if constexpr (R > 2) {
+    constexpr int H = R / 2;
+    T er[H], ei[H], orr[H], oi[H];
+#pragma unroll
+    for (int k = 0; k < H; ++k) {
+      er[k] = re[2 * k]; ei[k] = im[2 * k];
+      orr[k] = re[2 * k + 1]; oi[k] = im[2 * k + 1];
+    }
+    dft_reg<H, INV, T>(er, ei);
+    dft_reg<H, INV, T>(orr, oi);
+#pragma unroll
+    for (int k = 0; k < H; ++k) {
+      const T c = T(cos16(k * (16 / R)));
+      const T s = INV ? T(sin16(k * (16 / R))) : T(-sin16(k * (16 / R)));
+      const T tr = c * orr[k] - s * oi[k];
+      const T ti = c * oi[k] + s * orr[k];
+      re[k] = er[k] + tr; im[k] = ei[k] + ti;
+      re[k + H] = er[k] - tr; im[k + H] = ei[k] - ti;
+    }
+  }
+}
+
+// Four-step FFT of length N = A * B held in LDS (any element accessor).
+// Index x = a B + b, k = k1 + A k2:
+//   Z[k1 + A k2] = sum_b W_B^{b k2} ( W_N^{b k1} sum_a z[a B + b] W_A^{a k1} ).
+// Step 1 (one call per column b) transforms over a, applies W_N^{b k1} and stores
+// back in place at k1 B + b.  Step 2 (one call per k1) transforms over b and
+// stores Z[k1 + A k2] in place at k1 B + k2.  Output: Z[k] at (k % A) B + k / A.
+template <int A, int B, bool INV, typename T, typename Acc>
+__device__ __forceinline__ void fft4_step1(const Acc &acc, int b, const T *tw) {
+  T re[A], im[A];
+#pragma unroll
+  for (int a = 0; a < A; ++a) acc.load(a * B + b, re[a], im[a]);
+  dft_reg<A, INV, T>(re, im);
+#pragma unroll
+  for (int k1 = 0; k1 < A; ++k1) {
+    T r = re[k1], i = im[k1];
+    if (k1 > 0) {
+      const int j = b * k1;
+      const T c = tw[2 * j];
+      const T s = INV ? -tw[2 * j + 1] : tw[2 * j + 1];
+      const T nr = r * c - i * s;
+      i = r * s + i * c;
+      r = nr;
+    }
+    acc.store(k1 * B + b, r, i);
+  }
+}
+template <int A, int B, bool INV, typename T, typename Acc>
+__device__ __forceinline__ void fft4_step2(const Acc &acc, int k1) {
+  T re[B], im[B];
+#pragma unroll
+  for (int b = 0; b < B; ++b) acc.load(k1 * B + b, re[b], im[b]);
+  dft_reg<B, INV, T>(re, im);
+#pragma unroll
+  for (int k2 = 0; k2 < B; ++k2) acc.store(k1 * B + k2, re[k2], im[k2]);
+}
+
+// Factorisation used for each supported length.
+__host__ __device__ constexpr int fft_A(int n) { return n == 16 ? 4 : n == 32 ? 8 : n == 64 ? 8 : 16; }
+__host__ __device__ constexpr int fft_B(int n) { return n == 16 ? 4 : n == 32 ? 4 : n == 64 ? 8 : 8; }
+// Position of output bin k after the four-step transform.
+__device__ __forceinline__ int fft_pos(int k, int n) {
+  const int A = fft_A(n), B = fft_B(n);
+  return (k % A) * B + k / A;
+}
+
+// Run step 1 or 2 of a length-n transform for one (instance, column) item.
+template <bool INV, int STEP, typename T, typename Acc>
+__device__ __forceinline__ void fft4_dispatch(int n, const Acc &acc, int idx, const T *tw) {
+  switch (n) {
+    case 16: if (STEP == 1) fft4_step1<4, 4, INV, T>(acc, idx, tw); else fft4_step2<4, 4, INV, T>(acc, idx); break;
+    case 32: if (STEP == 1) fft4_step1<8, 4, INV, T>(acc, idx, tw); else fft4_step2<8, 4, INV, T>(acc, idx); break;
+    case 64: if (STEP == 1) fft4_step1<8, 8, INV, T>(acc, idx, tw); else fft4_step2<8, 8, INV, T>(acc, idx); break;
+    default: if (STEP == 1) fft4_step1<16, 8, INV, T>(acc, idx, tw); else fft4_step2<16, 8, INV, T>(acc, idx); break;
+  }
+}
+
+// Accessors.  Pair of real rows viewed as one complex row (re in r0, im in r1).
+template <typename T>
+struct RowPairAcc {
+  T *r0, *r1;
+  __device__ void load(int i, T &re, T &im) const { re = r0[i]; im = r1[i]; }
+  __device__ void store(int i, T re, T im) const { r0[i] = re; r1[i] = im; }
+};
+// Complex column: element i at base[i * stride], interleaved (re, im).
+template <typename T>
+struct ColAcc {
+  T *base;
+  int stride;
+  __device__ void load(int i, T &re, T &im) const { re = base[i * stride]; im = base[i * stride + 1]; }
+  __device__ void store(int i, T re, T im) const { base[i * stride] = re; base[i * stride + 1] = im; }
+};
+
+// Batched four-step transform over `count` instances of length n; instance q is
+// addressed through make(q).  All threads of the block take part.
+template <bool INV, int NT, typename T, typename Make>
+__device__ __forceinline__ void fft_batch(int n, int count, const T *tw, const Make &make) {
+  const int A = fft_A(n), B = fft_B(n);
+  for (int it = threadIdx.x; it < count * B; it += NT) {
+    const int q = it / B, b = it - q * B;
+    fft4_dispatch<INV, 1, T>(n, make(q), b, tw);
+  }
+  __syncthreads();
+  for (int it = threadIdx.x; it < count * A; it += NT) {
+    const int q = it / A, k1 = it - q * A;
+    fft4_dispatch<INV, 2, T>(n, make(q), k1, tw);
+  }
+  __syncthreads();
+}
+
+template <typename T> struct vec2;
+template <> struct vec2<float> { using type = float2; };
+template <> struct vec2<double> { using type = double2; };
+
+}  // namespace enufft

@@ -1,0 +1,275 @@
+// Batched type-1 NUFFT on gfx950: spread -> fold -> FFT -> deconvolve -> crop,
+// one fine grid per workgroup, resident in LDS from the first atomic add to
+// the last coefficient written.
+//
+// Section 2.1.2 of the paper: Step 1 spreads every sample onto an oversampled
+// periodic grid with a compact kernel (eq. spreading, here the exponential of a
+// semicircle); Step 2's quadrature weight is folded into the per-point
+// strength c_j = w_j W(x_j) h_j; Step 3 is the 2D FFT; Step 4 divides by the
+// kernel's Fourier transform (eq. deconv) and the result is truncated to the
+// mode box.
+#include "device_common.h"
+#include "launch.h"
+
+namespace enufft {
+
+// Spread the points [begin, end) of one item into the LDS grid.
+// grid has n2 + W rows of `pitch` elements; stored row s holds fine-grid row
+// s - W/2 (rows outside [0, n2) are folded back afterwards), columns wrap.
+template <typename T, int W, int NT>
+__device__ __forceinline__ void spread_item(const FwdArgs<T> &a, T *grid, int64_t begin, int64_t end,
+                                            T cx, T cy, T R) {
+  const Geom &g = a.g;
+  const T n1f = T(g.n1), n2f = T(g.n2);
+  const T s1 = n1f / T(2.0 * M_PI), s2 = n2f / T(2.0 * M_PI);
+  const T halfw = T(W) / T(2);
+  const T zsc = T(2) / T(W);
+  const int mask1 = g.n1 - 1;
+  const int pitch = g.pitch;
+  const int i0max1 = (int)ceil(n1f - halfw), i0max2 = (int)ceil(n2f - halfw);
+  for (int64_t j = begin + threadIdx.x; j < end; j += NT) {
+    const T xj = a.x[j], yj = a.y[j];
+    const T c = a.w[j] * a.h[j] * hann_w<T>(a.window_kind, xj, yj, cx, cy, R);
+    if (c == T(0)) continue;
+    const T tx = fold_grid<T>(xj, s1, n1f);
+    const T ty = fold_grid<T>(yj, s2, n2f);
+    int i0x = (int)ceil(tx - halfw);
+    int i0y = (int)ceil(ty - halfw);
+    i0x = min(max(i0x, -(W / 2)), i0max1);
+    i0y = min(max(i0y, -(W / 2)), i0max2);
+    T kx[W], ky[W];
+#pragma unroll
+    for (int d = 0; d < W; ++d) {
+      kx[d] = es_eval(T(i0x + d - tx) * zsc, a.beta);
+      ky[d] = c * es_eval(T(i0y + d - ty) * zsc, a.beta);
+    }
+    int col[W];
+#pragma unroll
+    for (int d = 0; d < W; ++d) col[d] = (i0x + d) & mask1;
+    T *rowp = grid + (i0y + W / 2) * pitch;
+#pragma unroll
+    for (int dy = 0; dy < W; ++dy) {
+#pragma unroll
+      for (int dx = 0; dx < W; ++dx) {
+        __hip_atomic_fetch_add(rowp + dy * pitch + col[dx], ky[dy] * kx[dx], __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_WORKGROUP);
+      }
+    }
+  }
+}
+
+// Fold the padding rows of the spread grid onto the periodic rows.
+template <typename T, int W, int NT>
+__device__ __forceinline__ void fold_rows(T *grid, const Geom &g) {
+  const int plo = W / 2, phi = W - W / 2;
+  const int pitch = g.pitch;
+  // stored rows [0, plo) hold fine rows -plo..-1, the same as fine rows n2-plo..n2-1
+  // (stored n2..n2+plo-1); stored rows [n2+plo, n2+W) hold fine rows n2.. = rows 0..phi-1.
+  for (int i = threadIdx.x; i < plo * g.n1; i += NT) {
+    const int r = i / g.n1, c = i - r * g.n1;
+    grid[(r + g.n2) * pitch + c] += grid[r * pitch + c];
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < phi * g.n1; i += NT) {
+    const int r = i / g.n1, c = i - r * g.n1;
+    grid[(plo + r) * pitch + c] += grid[(plo + g.n2 + r) * pitch + c];
+  }
+  __syncthreads();
+}
+
+// FFT of the folded real grid G (logical row 0 at G), deconvolution and crop.
+// Row stage: rows are transformed two at a time as one complex row; the
+// needed bins kx = 0..K1 of each real row are unpacked in place into the
+// first 2 (K1 + 1) elements of that row.  Column stage: complex transforms
+// along y of those columns.  Output: bins (kx, ky), kx in [0, K1], |ky| <= K2;
+// the box's negative-kx modes come from Hermitian symmetry of the real grid.
+template <typename T, int NT>
+__device__ void fft_deconv_store(const FwdArgs<T> &a, T *G, int cell) {
+  const Geom &g = a.g;
+  const int pitch = g.pitch;
+  const int n1 = g.n1, n2 = g.n2;
+  const int npairs = n2 / 2;
+  fft_batch<false, NT, T>(n1, npairs, a.tw1, [&](int q) {
+    RowPairAcc<T> acc;
+    acc.r0 = G + (2 * q) * pitch;
+    acc.r1 = acc.r0 + pitch;
+    return acc;
+  });
+  // Unpack: Z = FFT(row 2p + i row 2p+1); A(k) = (Z(k) + conj Z(-k)) / 2 is row 2p's
+  // spectrum and B(k) = (Z(k) - conj Z(-k)) / 2i is row 2p+1's.
+  const int per = g.K1 + 1;
+  const int ppr = max(1, NT / per);
+  for (int p0 = 0; p0 < npairs; p0 += ppr) {
+    const int it = threadIdx.x;
+    const int p = p0 + it / per, k = it % per;
+    const bool active = (it < ppr * per) && (p < npairs);
+    T ar = 0, ai = 0, br = 0, bi = 0;
+    if (active) {
+      const T *r0 = G + (2 * p) * pitch, *r1 = r0 + pitch;
+      const int pk = fft_pos(k, n1), pm = fft_pos((n1 - k) & (n1 - 1), n1);
+      const T zr = r0[pk], zi = r1[pk], mr = r0[pm], mi = r1[pm];
+      ar = T(0.5) * (zr + mr); ai = T(0.5) * (zi - mi);
+      br = T(0.5) * (zi + mi); bi = T(-0.5) * (zr - mr);
+    }
+    __syncthreads();
+    if (active) {
+      T *r0 = G + (2 * p) * pitch, *r1 = r0 + pitch;
+      r0[2 * k] = ar; r0[2 * k + 1] = ai;
+      r1[2 * k] = br; r1[2 * k + 1] = bi;
+    }
+    __syncthreads();
+  }
+  fft_batch<false, NT, T>(n2, per, a.tw2, [&](int q) {
+    ColAcc<T> acc;
+    acc.base = G + 2 * q;
+    acc.stride = pitch;
+    return acc;
+  });
+  // Deconvolve (real, even factor) and write the mode box.
+  using C = typename vec2<T>::type;
+  C *fout = reinterpret_cast<C *>(a.f) + (int64_t)cell * g.N1 * g.N2;
+  const int hi1 = g.lo1 + g.N1 - 1, hi2 = g.lo2 + g.N2 - 1;
+  const int nky = 2 * g.K2 + 1;
+  for (int it = threadIdx.x; it < nky * per; it += NT) {
+    const int kyi = it / per, kx = it - kyi * per;
+    const int ky = kyi - g.K2;
+    const int bin = ky & (n2 - 1);
+    const int pos = fft_pos(bin, n2);
+    const T zr = G[pos * pitch + 2 * kx], zi = G[pos * pitch + 2 * kx + 1];
+    const T s = a.decon_x[kx] * a.decon_y[ky < 0 ? -ky : ky];
+    const T vr = zr * s, vi = zi * s;
+    if (kx <= hi1 && ky >= g.lo2 && ky <= hi2) {
+      C v; v.x = vr; v.y = vi;
+      fout[(ky - g.lo2) * g.N1 + (kx - g.lo1)] = v;
+    }
+    if (kx >= 1 && -kx >= g.lo1 && -ky >= g.lo2 && -ky <= hi2) {
+      C v; v.x = vr; v.y = -vi;
+      fout[(-ky - g.lo2) * g.N1 + (-kx - g.lo1)] = v;
+    }
+  }
+}
+
+template <typename T, int W, int NT>
+__global__ __launch_bounds__(NT) void fwd_kernel(FwdArgs<T> a) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T *grid = reinterpret_cast<T *>(smem_raw);
+  __shared__ int s_item, s_last;
+  const Geom &g = a.g;
+  const int pitch = g.pitch;
+  const int total = (g.n2 + W) * pitch;
+  T *G = grid + (W / 2) * pitch;   // logical fine row 0
+  const bool persistent = a.work_counter != nullptr;
+  int64_t idx = a.item_base + blockIdx.x;
+  if (!persistent && idx >= a.n_items) return;
+  for (;;) {
+    if (persistent) {
+      if (threadIdx.x == 0) s_item = atomicAdd(a.work_counter, 1);
+      __syncthreads();
+      idx = s_item;
+      __syncthreads();
+      if (idx >= a.n_items) break;
+    }
+    const FwdItem it = a.items[idx];
+    for (int i = threadIdx.x; i < total; i += NT) grid[i] = T(0);
+    __syncthreads();
+    const double *wn = a.windows + 3 * (int64_t)it.cell;
+    spread_item<T, W, NT>(a, grid, it.begin, it.end, T(wn[0]), T(wn[1]), T(wn[2]));
+    __syncthreads();
+    fold_rows<T, W, NT>(grid, g);
+    bool run_fft = true;
+    if (it.nchunks > 1) {
+      const int nn = g.n1 * g.n2;
+      T *slot = a.partial + (int64_t)it.slot * nn;
+      for (int i = threadIdx.x; i < nn; i += NT) {
+        const int r = i / g.n1, c = i - r * g.n1;
+        slot[i] = G[r * pitch + c];
+      }
+      __threadfence();
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        const int old = atomicAdd(a.cell_counters + it.cell, 1);
+        s_last = (old == it.nchunks - 1);
+        if (s_last) a.cell_counters[it.cell] = 0;   // ready for the next call
+      }
+      __syncthreads();
+      run_fft = s_last != 0;
+      if (run_fft) {
+        __threadfence();
+        const T *p0 = a.partial + (int64_t)it.slot0 * nn;
+        for (int i = threadIdx.x; i < nn; i += NT) {
+          T s = T(0);
+          for (int q = 0; q < it.nchunks; ++q) s += p0[(int64_t)q * nn + i];
+          const int r = i / g.n1, c = i - r * g.n1;
+          G[r * pitch + c] = s;
+        }
+        __syncthreads();
+      }
+    }
+    if (run_fft) fft_deconv_store<T, NT>(a, G, it.cell);
+    __syncthreads();
+    if (!persistent) break;
+  }
+  if (persistent && threadIdx.x == 0) {
+    __threadfence();
+    const int old = atomicAdd(a.done_counter, 1);
+    if (old == (int)gridDim.x - 1) {
+      *a.work_counter = 0;
+      *a.done_counter = 0;
+    }
+  }
+}
+
+template <typename T, int W>
+static hipError_t launch_fwd_w(const FwdArgs<T> &a, int blocks, int threads, size_t lds, hipStream_t s) {
+  if (threads == 256) {
+    hipLaunchKernelGGL((fwd_kernel<T, W, 256>), dim3(blocks), dim3(256), lds, s, a);
+  } else if (threads == 512) {
+    hipLaunchKernelGGL((fwd_kernel<T, W, 512>), dim3(blocks), dim3(512), lds, s, a);
+  } else {
+    hipLaunchKernelGGL((fwd_kernel<T, W, 1024>), dim3(blocks), dim3(1024), lds, s, a);
+  }
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_fwd(const FwdArgs<T> &a, int W, int blocks, int threads, size_t lds, hipStream_t s) {
+  switch (W) {
+    case 4: return launch_fwd_w<T, 4>(a, blocks, threads, lds, s);
+    case 6: return launch_fwd_w<T, 6>(a, blocks, threads, lds, s);
+    case 8: return launch_fwd_w<T, 8>(a, blocks, threads, lds, s);
+    case 10: return launch_fwd_w<T, 10>(a, blocks, threads, lds, s);
+    case 12: return launch_fwd_w<T, 12>(a, blocks, threads, lds, s);
+    case 14: return launch_fwd_w<T, 14>(a, blocks, threads, lds, s);
+    case 16: return launch_fwd_w<T, 16>(a, blocks, threads, lds, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <typename T>
+hipError_t fwd_occupancy(int W, int threads, size_t lds, int *blocks_per_cu) {
+  const void *fn = nullptr;
+#define ENUFFT_FN(WW, NT) (const void *)(&fwd_kernel<T, WW, NT>)
+#define ENUFFT_PICK(WW)                                   \
+  case WW:                                                \
+    fn = threads == 256 ? ENUFFT_FN(WW, 256)              \
+         : threads == 512 ? ENUFFT_FN(WW, 512)            \
+                          : ENUFFT_FN(WW, 1024);          \
+    break;
+  switch (W) {
+    ENUFFT_PICK(4) ENUFFT_PICK(6) ENUFFT_PICK(8) ENUFFT_PICK(10) ENUFFT_PICK(12) ENUFFT_PICK(14)
+    ENUFFT_PICK(16)
+    default: return hipErrorInvalidValue;
+  }
+#undef ENUFFT_PICK
+#undef ENUFFT_FN
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, fn, threads, lds);
+}
+
+template hipError_t launch_fwd<float>(const FwdArgs<float> &, int, int, int, size_t, hipStream_t);
+template hipError_t launch_fwd<double>(const FwdArgs<double> &, int, int, int, size_t, hipStream_t);
+template hipError_t fwd_occupancy<float>(int, int, size_t, int *);
+template hipError_t fwd_occupancy<double>(int, int, size_t, int *);
+
+}  // namespace enufft

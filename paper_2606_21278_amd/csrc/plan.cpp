@@ -1,0 +1,596 @@
+// Host side of the ENUFFT library: argument validation, kernel parameters,
+// FP64 deconvolution tables, the work schedule, workspace and the C ABI.
+#include "plan.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "launch.h"
+
+using enufft::AdjItem;
+using enufft::FwdItem;
+using enufft::Geom;
+
+namespace {
+
+thread_local std::string g_thread_error;
+
+enufft_status fail(enufft_plan_t p, enufft_status s, const std::string &msg) {
+  if (p) p->last_error = msg;
+  g_thread_error = msg;
+  return s;
+}
+
+enufft_status hip_fail(enufft_plan_t p, hipError_t e, const char *what) {
+  std::string m = std::string(what) + ": " + hipGetErrorString(e);
+  if (p && e != hipErrorInvalidValue && e != hipErrorMemoryAllocation && e != hipErrorOutOfMemory)
+    p->faulted = true;
+  return fail(p, (e == hipErrorMemoryAllocation || e == hipErrorOutOfMemory) ? ENUFFT_ENOMEM : ENUFFT_EDEVICE, m);
+}
+
+#define HIP_TRY(p, expr, what)                      \
+  do {                                              \
+    hipError_t e_ = (expr);                         \
+    if (e_ != hipSuccess) return hip_fail(p, e_, what); \
+  } while (0)
+
+int next_pow2(int v) {
+  int n = 1;
+  while (n < v) n <<= 1;
+  return n;
+}
+
+// Widths with compiled kernels; a requested width is rounded up to one of these.
+const int kWidths[] = {4, 6, 8, 10, 12, 14, 16};
+
+// Spreading-kernel width for a requested accuracy and effective oversampling:
+// the exponential-of-semicircle kernel at upsampling 2 reaches about
+// 10^-(W-1) with W grid points and shape beta = 2.30 W; for smaller upsampling
+// the width grows as -ln(eps) / (pi sqrt(1 - 1/sigma)) with
+// beta = 0.97 pi (1 - 1/(2 sigma)) W.
+void kernel_params(double eps, double sigma_eff, int min_w, int *W_out, double *beta_out) {
+  int w;
+  if (sigma_eff >= 2.0 - 1e-12) {
+    w = (int)std::ceil(-std::log10(eps / 10.0));
+  } else {
+    w = (int)std::ceil(-std::log(eps) / (M_PI * std::sqrt(1.0 - 1.0 / sigma_eff)));
+  }
+  w = std::max(w, min_w);
+  w = std::max(w, 2);
+  int W = 16;
+  for (int c : kWidths)
+    if (c >= w) { W = c; break; }
+  double beta;
+  if (sigma_eff >= 2.0 - 1e-12) beta = 2.30 * W;
+  else beta = 0.97 * M_PI * (1.0 - 1.0 / (2.0 * sigma_eff)) * W;
+  *W_out = W;
+  *beta_out = beta;
+}
+
+// Gauss-Legendre nodes and weights on [-1, 1] (Newton on the Legendre recurrence).
+void gauss_legendre(int M, std::vector<double> &x, std::vector<double> &w) {
+  x.resize(M);
+  w.resize(M);
+  for (int i = 0; i < M; ++i) {
+    double z = std::cos(M_PI * (i + 0.75) / (M + 0.5));
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = z;
+      for (int k = 2; k <= M; ++k) {
+        double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      double dp = M * (z * p1 - p0) / (z * z - 1.0);
+      double dz = p1 / dp;
+      z -= dz;
+      if (std::fabs(dz) < 1e-16) break;
+    }
+    double p0 = 1.0, p1 = z;
+    for (int k = 2; k <= M; ++k) {
+      double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+      p0 = p1;
+      p1 = p2;
+    }
+    double dp = M * (z * p1 - p0) / (z * z - 1.0);
+    x[i] = z;
+    w[i] = 2.0 / ((1.0 - z * z) * dp * dp);
+  }
+}
+
+// Kernel Fourier factor p(k) = (1/Delta) int phi(x) exp(-i k x) dx for the grid
+// spacing Delta = 2 pi / n and phi(x) = psi(x / alpha), alpha = W Delta / 2:
+//   p(k) = (W / 2) int_{-1}^{1} psi(z) cos(k pi W z / n) dz.
+// With z = sin(theta) the integrand is smooth:
+//   int_{-pi/2}^{pi/2} exp(beta (cos theta - 1)) cos(a sin theta) cos theta dtheta.
+// This is the factor divided out in Step 4 (eq. deconv).
+std::vector<double> kernel_ft(int W, double beta, int n, int kmax) {
+  static std::vector<double> gx, gw;
+  if (gx.empty()) gauss_legendre(200, gx, gw);
+  std::vector<double> p(kmax + 1);
+  for (int k = 0; k <= kmax; ++k) {
+    const double a = k * M_PI * W / n;
+    double s = 0.0;
+    for (size_t i = 0; i < gx.size(); ++i) {
+      const double th = 0.5 * M_PI * gx[i];
+      s += gw[i] * std::exp(beta * (std::cos(th) - 1.0)) * std::cos(a * std::sin(th)) * std::cos(th);
+    }
+    p[k] = 0.5 * W * s * 0.5 * M_PI;
+  }
+  return p;
+}
+
+int64_t alloc_cap_bytes() {
+  const char *s = std::getenv("ENUFFT_ALLOC_CAP_MB");
+  if (!s || !*s) return -1;
+  return (int64_t)(std::atof(s) * 1048576.0);
+}
+
+enufft_status dev_alloc(enufft_plan_t p, void **ptr, size_t bytes, const char *what) {
+  *ptr = nullptr;
+  if (bytes == 0) bytes = 16;
+  const int64_t cap = alloc_cap_bytes();
+  if (cap >= 0 && p->workspace_bytes + (int64_t)bytes > cap)
+    return fail(p, ENUFFT_ENOMEM, std::string("workspace over ENUFFT_ALLOC_CAP_MB while allocating ") + what);
+  hipError_t e = hipMalloc(ptr, bytes);
+  if (e != hipSuccess) {
+    *ptr = nullptr;
+    return fail(p, ENUFFT_ENOMEM, std::string("hipMalloc failed for ") + what + ": " + hipGetErrorString(e));
+  }
+  p->allocations.push_back(*ptr);
+  p->workspace_bytes += (int64_t)bytes;
+  return ENUFFT_OK;
+}
+
+template <typename T>
+std::vector<T> cast_vec(const std::vector<double> &v) {
+  return std::vector<T>(v.begin(), v.end());
+}
+
+void free_plan(enufft_plan_t p) {
+  if (!p) return;
+  for (void *a : p->allocations) (void)hipFree(a);
+  for (size_t i = 0; i < p->tim.start.size(); ++i) {
+    (void)hipEventDestroy(p->tim.start[i]);
+    (void)hipEventDestroy(p->tim.stop[i]);
+  }
+  delete p;
+}
+
+bool check_gfx950(std::string *name) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return false;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return false;
+  *name = prop.gcnArchName;
+  return std::strncmp(prop.gcnArchName, "gfx950", 6) == 0;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------- scheduling
+
+namespace enufft {
+
+// Forward work list.  Target chunk size T keeps roughly two items per resident
+// workgroup so the largest cells do not leave CUs idle; cells above T are cut
+// into near-equal chunks whose partial grids are merged.  The batched list is
+// ordered by decreasing size (longest first), the per-cell list by cell.
+void build_fwd_schedule(enufft_plan_t p, int slots) {
+  const int64_t Q = p->n_points;
+  const int64_t T = std::max<int64_t>(16384, (Q + 2LL * slots - 1) / std::max(1, 2 * slots));
+  p->fwd_items.clear();
+  p->fwd_items_cell.clear();
+  p->fwd_cell_first.assign(p->n_cells + 1, 0);
+  int64_t slot = 0, nsplit = 0;
+  for (int64_t c = 0; c < p->n_cells; ++c) {
+    const int64_t a = p->offsets[c], b = p->offsets[c + 1];
+    const int64_t q = b - a;
+    const int64_t nch = std::max<int64_t>(1, (q + T - 1) / T);
+    p->fwd_cell_first[c] = (int64_t)p->fwd_items_cell.size();
+    if (nch == 1) {
+      p->fwd_items_cell.push_back(FwdItem{a, b, (int32_t)c, 1, -1, -1});
+    } else {
+      ++nsplit;
+      for (int64_t i = 0; i < nch; ++i) {
+        const int64_t s = a + q * i / nch, e = a + q * (i + 1) / nch;
+        p->fwd_items_cell.push_back(FwdItem{s, e, (int32_t)c, (int32_t)nch, (int32_t)(slot + i), (int32_t)slot});
+      }
+      slot += nch;
+    }
+  }
+  p->fwd_cell_first[p->n_cells] = (int64_t)p->fwd_items_cell.size();
+  p->fwd_items = p->fwd_items_cell;
+  std::stable_sort(p->fwd_items.begin(), p->fwd_items.end(), [](const FwdItem &x, const FwdItem &y) {
+    return (x.end - x.begin) > (y.end - y.begin);
+  });
+  p->n_slots = slot;
+  p->n_split = nsplit;
+}
+
+}  // namespace enufft
+
+// ---------------------------------------------------------------------- C ABI
+
+extern "C" {
+
+const char *enufft_version(void) { return "enufft-gfx950 0.1"; }
+
+const char *enufft_last_error(enufft_plan_t p) {
+  return p ? p->last_error.c_str() : g_thread_error.c_str();
+}
+
+enufft_status enufft_default_opts(enufft_opts *o) {
+  if (!o) return fail(nullptr, ENUFFT_EINVAL, "enufft_default_opts: null opts");
+  o->n_modes[0] = 64;
+  o->n_modes[1] = 64;
+  o->sigma = 2.0;
+  o->eps = 1e-5;
+  o->precision = ENUFFT_F32;
+  o->window_kind = ENUFFT_WIN_HANN_RADIAL;
+  o->scale = 1.0;
+  o->autotune = 0;
+  o->kernel_width = 0;
+  return ENUFFT_OK;
+}
+
+enufft_status enufft_plan(enufft_plan_t *out, int64_t n_cells, const int64_t *cell_offsets,
+                          const enufft_window *windows, const enufft_opts *opts, void *hip_stream) {
+  if (!out) return fail(nullptr, ENUFFT_EINVAL, "enufft_plan: null output pointer");
+  *out = nullptr;
+  if (!opts) return fail(nullptr, ENUFFT_EINVAL, "enufft_plan: null opts");
+  if (n_cells < 0 || n_cells > (int64_t)INT32_MAX)
+    return fail(nullptr, ENUFFT_EINVAL, "enufft_plan: n_cells out of range");
+  if (!cell_offsets) return fail(nullptr, ENUFFT_EINVAL, "enufft_plan: null cell_offsets");
+  if (cell_offsets[0] != 0) return fail(nullptr, ENUFFT_EINVAL, "enufft_plan: cell_offsets[0] must be 0");
+  for (int64_t c = 0; c < n_cells; ++c)
+    if (cell_offsets[c + 1] < cell_offsets[c])
+      return fail(nullptr, ENUFFT_EINVAL, "enufft_plan: cell_offsets must be non-decreasing");
+  const int N1 = opts->n_modes[0], N2 = opts->n_modes[1];
+  if (N1 < 1 || N2 < 1) return fail(nullptr, ENUFFT_EINVAL, "enufft_plan: n_modes must be >= 1");
+  if (opts->precision != ENUFFT_F32 && opts->precision != ENUFFT_F64)
+    return fail(nullptr, ENUFFT_EINVAL, "enufft_plan: unknown precision");
+  if (opts->window_kind != ENUFFT_WIN_NONE && opts->window_kind != ENUFFT_WIN_HANN_RADIAL)
+    return fail(nullptr, ENUFFT_EINVAL, "enufft_plan: unknown window kind");
+  if (!(opts->sigma >= 1.25) || !(opts->sigma <= 16.0))
+    return fail(nullptr, ENUFFT_EINVAL, "enufft_plan: sigma must be in [1.25, 16]");
+  if (!(opts->eps > 0.0) || !(opts->eps < 1.0))
+    return fail(nullptr, ENUFFT_EINVAL, "enufft_plan: eps must be in (0, 1)");
+  if (opts->precision == ENUFFT_F32 && opts->eps < 1e-6)
+    return fail(nullptr, ENUFFT_EEPS, "enufft_plan: eps below 1e-6 is not attainable in FP32");
+  if (opts->precision == ENUFFT_F64 && opts->eps < 1e-13)
+    return fail(nullptr, ENUFFT_EEPS, "enufft_plan: eps below 1e-13 is not attainable in FP64");
+  if (!std::isfinite(opts->scale)) return fail(nullptr, ENUFFT_EINVAL, "enufft_plan: scale must be finite");
+  if (opts->kernel_width < 0 || opts->kernel_width > 16)
+    return fail(nullptr, ENUFFT_EINVAL, "enufft_plan: kernel_width must be in [0, 16]");
+  if (opts->window_kind == ENUFFT_WIN_HANN_RADIAL && n_cells > 0) {
+    if (!windows) return fail(nullptr, ENUFFT_EINVAL, "enufft_plan: Hann window needs windows");
+    for (int64_t c = 0; c < n_cells; ++c)
+      if (!(windows[c].radius > 0.0) || !std::isfinite(windows[c].cx) || !std::isfinite(windows[c].cy) ||
+          !std::isfinite(windows[c].radius))
+        return fail(nullptr, ENUFFT_EINVAL, "enufft_plan: window radius must be > 0 and finite");
+  }
+  if (N1 > 64 || N2 > 64)
+    return fail(nullptr, ENUFFT_EUNSUPPORTED,
+                "enufft_plan: mode boxes above 64 per axis need the tiled HBM-grid path, not in this build");
+  // Fine grid: the smallest power of two >= sigma N (and >= 16); the kernel
+  // parameters follow the effective oversampling, and a grid narrower than two
+  // kernel widths is widened (which only raises the oversampling).
+  int n1 = std::max(16, next_pow2((int)std::ceil(opts->sigma * N1 - 1e-9)));
+  int n2 = std::max(16, next_pow2((int)std::ceil(opts->sigma * N2 - 1e-9)));
+  const double sigma_eff = std::min((double)n1 / N1, (double)n2 / N2);
+  int W;
+  double beta;
+  kernel_params(opts->eps, sigma_eff, opts->kernel_width, &W, &beta);
+  n1 = std::max(n1, next_pow2(2 * W));
+  n2 = std::max(n2, next_pow2(2 * W));
+  if (n1 > 128 || n2 > 128)
+    return fail(nullptr, ENUFFT_EUNSUPPORTED, "enufft_plan: fine grid above 128 per axis is not in this build");
+
+  // ---- device
+  std::string arch;
+  if (!check_gfx950(&arch))
+    return fail(nullptr, ENUFFT_EDEVICE, "enufft_plan: no gfx950 device (found '" + arch + "')");
+
+  enufft_plan_t p = new enufft_plan_s();
+  p->n_cells = n_cells;
+  p->n_points = cell_offsets[n_cells];
+  p->offsets.assign(cell_offsets, cell_offsets + n_cells + 1);
+  p->N1 = N1; p->N2 = N2; p->n1 = n1; p->n2 = n2; p->W = W; p->beta = beta;
+  p->sigma = opts->sigma; p->eps = opts->eps; p->scale = opts->scale;
+  p->prec = opts->precision; p->window_kind = opts->window_kind;
+  p->elem = p->prec == ENUFFT_F64 ? 8 : 4;
+  p->stream = (hipStream_t)hip_stream;
+  Geom &g = p->geom;
+  g.n1 = n1; g.n2 = n2; g.N1 = N1; g.N2 = N2;
+  g.lo1 = -(N1 / 2); g.lo2 = -(N2 / 2);
+  g.K1 = N1 / 2; g.K2 = N2 / 2;
+  g.pitch = n1 + 2;
+
+  hipError_t e = hipGetDevice(&p->device);
+  if (e != hipSuccess) { enufft_status s = hip_fail(p, e, "hipGetDevice"); free_plan(p); return s; }
+  hipDeviceProp_t prop;
+  e = hipGetDeviceProperties(&prop, p->device);
+  if (e != hipSuccess) { enufft_status s = hip_fail(p, e, "hipGetDeviceProperties"); free_plan(p); return s; }
+  p->n_cu = prop.multiProcessorCount;
+
+  // ---- forward launch shape
+  p->fwd_threads = (p->prec == ENUFFT_F64) ? 256 : 512;
+  p->fwd_lds = enufft::fwd_lds_bytes(g, W, p->elem);
+  if (p->fwd_lds > (size_t)prop.sharedMemPerBlock) {
+    free_plan(p);
+    return fail(nullptr, ENUFFT_EUNSUPPORTED, "enufft_plan: fine grid does not fit in LDS at this precision");
+  }
+  int per_cu = 0;
+  enufft_status st = ENUFFT_OK;
+  e = (p->prec == ENUFFT_F64) ? enufft::fwd_occupancy<double>(W, p->fwd_threads, p->fwd_lds, &per_cu)
+                              : enufft::fwd_occupancy<float>(W, p->fwd_threads, p->fwd_lds, &per_cu);
+  if (e != hipSuccess || per_cu < 1) {
+    st = e != hipSuccess ? hip_fail(p, e, "occupancy query") : fail(p, ENUFFT_EDEVICE, "forward kernel cannot be resident");
+    free_plan(p);
+    return st;
+  }
+  const int slots = p->n_cu * per_cu;
+  enufft::build_fwd_schedule(p, slots);
+  p->fwd_blocks = (int)std::min<int64_t>((int64_t)slots, std::max<int64_t>(1, (int64_t)p->fwd_items.size()));
+
+  // ---- tables (FP64 on the host, rounded to the compute precision)
+  const int Kx = g.K1, Ky = g.K2;
+  std::vector<double> px = kernel_ft(W, beta, n1, Kx), py = kernel_ft(W, beta, n2, Ky);
+  std::vector<double> dx(Kx + 1), dy(Ky + 1);
+  for (int k = 0; k <= Kx; ++k) dx[k] = opts->scale / px[k];
+  for (int k = 0; k <= Ky; ++k) dy[k] = 1.0 / py[k];
+  std::vector<double> tw1(2 * n1), tw2(2 * n2);
+  for (int j = 0; j < n1; ++j) { tw1[2 * j] = std::cos(2 * M_PI * j / n1); tw1[2 * j + 1] = -std::sin(2 * M_PI * j / n1); }
+  for (int j = 0; j < n2; ++j) { tw2[2 * j] = std::cos(2 * M_PI * j / n2); tw2[2 * j + 1] = -std::sin(2 * M_PI * j / n2); }
+
+#define ALLOC(ptr, bytes, what)                                              \
+  do {                                                                       \
+    st = dev_alloc(p, (void **)&(ptr), (bytes), what);                       \
+    if (st != ENUFFT_OK) { std::string m_ = p->last_error; free_plan(p); return fail(nullptr, st, m_); } \
+  } while (0)
+#define UPLOAD(dst, src, bytes, what)                                        \
+  do {                                                                       \
+    hipError_t e_ = hipMemcpy((dst), (src), (bytes), hipMemcpyHostToDevice); \
+    if (e_ != hipSuccess) { st = hip_fail(p, e_, what); std::string m_ = p->last_error; free_plan(p); return fail(nullptr, st, m_); } \
+  } while (0)
+
+  auto upload_table = [&](void **dst, const std::vector<double> &v, const char *what) -> enufft_status {
+    enufft_status s2 = dev_alloc(p, dst, v.size() * p->elem, what);
+    if (s2 != ENUFFT_OK) return s2;
+    hipError_t e2;
+    if (p->prec == ENUFFT_F64) {
+      e2 = hipMemcpy(*dst, v.data(), v.size() * 8, hipMemcpyHostToDevice);
+    } else {
+      std::vector<float> f = cast_vec<float>(v);
+      e2 = hipMemcpy(*dst, f.data(), f.size() * 4, hipMemcpyHostToDevice);
+    }
+    return e2 == hipSuccess ? ENUFFT_OK : hip_fail(p, e2, what);
+  };
+  for (auto &tb : {std::make_pair(&p->d_decon_x, &dx), std::make_pair(&p->d_decon_y, &dy),
+                   std::make_pair(&p->d_tw1, &tw1), std::make_pair(&p->d_tw2, &tw2)}) {
+    st = upload_table(tb.first, *tb.second, "tables");
+    if (st != ENUFFT_OK) { std::string m = p->last_error; free_plan(p); return fail(nullptr, st, m); }
+  }
+
+  std::vector<double> win(3 * std::max<int64_t>(1, n_cells), 0.0);
+  for (int64_t c = 0; c < n_cells; ++c) {
+    if (windows) { win[3 * c] = windows[c].cx; win[3 * c + 1] = windows[c].cy; win[3 * c + 2] = windows[c].radius; }
+  }
+  ALLOC(p->d_windows, win.size() * sizeof(double), "windows");
+  UPLOAD(p->d_windows, win.data(), win.size() * sizeof(double), "upload windows");
+  ALLOC(p->d_fwd_items, std::max<size_t>(1, p->fwd_items.size()) * sizeof(FwdItem), "forward items");
+  if (!p->fwd_items.empty()) UPLOAD(p->d_fwd_items, p->fwd_items.data(), p->fwd_items.size() * sizeof(FwdItem), "upload items");
+  ALLOC(p->d_fwd_items_cell, std::max<size_t>(1, p->fwd_items_cell.size()) * sizeof(FwdItem), "forward items by cell");
+  if (!p->fwd_items_cell.empty())
+    UPLOAD(p->d_fwd_items_cell, p->fwd_items_cell.data(), p->fwd_items_cell.size() * sizeof(FwdItem), "upload items");
+  ALLOC(p->d_counters, 16 * sizeof(int), "counters");
+  ALLOC(p->d_cell_counters, std::max<int64_t>(1, n_cells) * sizeof(int), "cell counters");
+  ALLOC(p->d_partial, std::max<int64_t>(1, p->n_slots) * (size_t)n1 * n2 * p->elem, "partial grids");
+  e = hipMemset(p->d_counters, 0, 16 * sizeof(int));
+  if (e == hipSuccess) e = hipMemset(p->d_cell_counters, 0, std::max<int64_t>(1, n_cells) * sizeof(int));
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e != hipSuccess) { st = hip_fail(p, e, "zero counters"); std::string m = p->last_error; free_plan(p); return fail(nullptr, st, m); }
+#undef ALLOC
+#undef UPLOAD
+  *out = p;
+  return ENUFFT_OK;
+}
+
+enufft_status enufft_set_stream(enufft_plan_t p, void *hip_stream) {
+  if (!p) return fail(nullptr, ENUFFT_EINVAL, "enufft_set_stream: null plan");
+  p->stream = (hipStream_t)hip_stream;
+  return ENUFFT_OK;
+}
+
+enufft_status enufft_destroy(enufft_plan_t p) {
+  if (!p) return ENUFFT_OK;
+  if (p->stream || true) (void)hipStreamSynchronize(p->stream);
+  free_plan(p);
+  return ENUFFT_OK;
+}
+
+enufft_status enufft_get_info(enufft_plan_t p, enufft_plan_info *info) {
+  if (!p || !info) return fail(p, ENUFFT_EINVAL, "enufft_get_info: null argument");
+  std::memset(info, 0, sizeof(*info));
+  info->n_modes[0] = p->N1; info->n_modes[1] = p->N2;
+  info->grid[0] = p->n1; info->grid[1] = p->n2;
+  info->kernel_width = p->W;
+  info->beta = p->beta;
+  info->n_cells = p->n_cells;
+  info->n_points = p->n_points;
+  info->n_items_fwd = (int64_t)p->fwd_items.size();
+  info->n_split_cells = p->n_split;
+  info->n_items_adj = (int64_t)p->adj_items.size();
+  info->adj_bands = p->adj_bands;
+  info->fwd_threads = p->fwd_threads; info->fwd_blocks = p->fwd_blocks;
+  info->adj_threads = p->adj_threads; info->adj_blocks = p->adj_blocks;
+  info->workspace_bytes = p->workspace_bytes;
+  return ENUFFT_OK;
+}
+
+enufft_status enufft_set_timing(enufft_plan_t p, int32_t enable) {
+  if (!p) return fail(nullptr, ENUFFT_EINVAL, "enufft_set_timing: null plan");
+  p->timing = enable != 0;
+  return ENUFFT_OK;
+}
+
+enufft_status enufft_get_timing(enufft_plan_t p, double *out6) {
+  if (!p || !out6) return fail(p, ENUFFT_EINVAL, "enufft_get_timing: null argument");
+  for (int i = 0; i < 6; ++i) out6[i] = 0.0;
+  enufft_status st = ENUFFT_OK;
+  for (size_t i = 0; i < p->tim.start.size(); ++i) {
+    float ms = 0.f;
+    hipError_t e = hipEventSynchronize(p->tim.stop[i]);
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, p->tim.start[i], p->tim.stop[i]);
+    if (e != hipSuccess && st == ENUFFT_OK) st = hip_fail(p, e, "event timing");
+    out6[p->tim.kind[i]] += ms;
+    out6[3 + p->tim.kind[i]] += 1.0;
+    (void)hipEventDestroy(p->tim.start[i]);
+    (void)hipEventDestroy(p->tim.stop[i]);
+  }
+  p->tim.start.clear(); p->tim.stop.clear(); p->tim.kind.clear();
+  return st;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------- launches
+
+namespace enufft {
+
+enufft_status record_start(enufft_plan_t p, int kind, hipEvent_t *ev) {
+  *ev = nullptr;
+  if (!p->timing) return ENUFFT_OK;
+  HIP_TRY(p, hipEventCreate(ev), "hipEventCreate");
+  HIP_TRY(p, hipEventRecord(*ev, p->stream), "hipEventRecord");
+  (void)kind;
+  return ENUFFT_OK;
+}
+enufft_status record_stop(enufft_plan_t p, int kind, hipEvent_t start) {
+  if (!p->timing || !start) return ENUFFT_OK;
+  hipEvent_t ev;
+  HIP_TRY(p, hipEventCreate(&ev), "hipEventCreate");
+  HIP_TRY(p, hipEventRecord(ev, p->stream), "hipEventRecord");
+  p->tim.start.push_back(start);
+  p->tim.stop.push_back(ev);
+  p->tim.kind.push_back(kind);
+  return ENUFFT_OK;
+}
+
+template <typename T>
+FwdArgs<T> make_fwd_args(enufft_plan_t p, const void *x, const void *y, const void *h, const void *w, void *f) {
+  FwdArgs<T> a{};
+  a.x = (const T *)x; a.y = (const T *)y; a.h = (const T *)h; a.w = (const T *)w;
+  a.f = (T *)f;
+  a.items = (const FwdItem *)p->d_fwd_items;
+  a.n_items = (int64_t)p->fwd_items.size();
+  a.item_base = 0;
+  a.work_counter = p->d_counters + 0;
+  a.done_counter = p->d_counters + 1;
+  a.cell_counters = p->d_cell_counters;
+  a.partial = (T *)p->d_partial;
+  a.windows = (const double *)p->d_windows;
+  a.window_kind = p->window_kind;
+  a.decon_x = (const T *)p->d_decon_x; a.decon_y = (const T *)p->d_decon_y;
+  a.tw1 = (const T *)p->d_tw1; a.tw2 = (const T *)p->d_tw2;
+  a.beta = (T)p->beta;
+  a.g = p->geom;
+  return a;
+}
+
+enufft_status check_plan(enufft_plan_t p, const char *fn) {
+  if (!p) return fail(nullptr, ENUFFT_EINVAL, std::string(fn) + ": null plan");
+  if (p->faulted) return fail(p, ENUFFT_ESTATE, std::string(fn) + ": plan unusable after a device fault");
+  return ENUFFT_OK;
+}
+
+}  // namespace enufft
+
+extern "C" enufft_status enufft_type1_batched(enufft_plan_t p, const void *x, const void *y, const void *h,
+                                              const void *w, void *f) {
+  enufft_status st = enufft::check_plan(p, "enufft_type1_batched");
+  if (st != ENUFFT_OK) return st;
+  if (p->n_cells == 0) return ENUFFT_OK;
+  if (!f) return fail(p, ENUFFT_EINVAL, "enufft_type1_batched: null f");
+  if (p->n_points > 0 && (!x || !y || !h || !w))
+    return fail(p, ENUFFT_EINVAL, "enufft_type1_batched: null point array");
+  hipEvent_t ev;
+  st = enufft::record_start(p, 0, &ev);
+  if (st != ENUFFT_OK) return st;
+  hipError_t e;
+  if (p->prec == ENUFFT_F64) {
+    auto a = enufft::make_fwd_args<double>(p, x, y, h, w, f);
+    e = enufft::launch_fwd<double>(a, p->W, p->fwd_blocks, p->fwd_threads, p->fwd_lds, p->stream);
+  } else {
+    auto a = enufft::make_fwd_args<float>(p, x, y, h, w, f);
+    e = enufft::launch_fwd<float>(a, p->W, p->fwd_blocks, p->fwd_threads, p->fwd_lds, p->stream);
+  }
+  if (e != hipSuccess) return hip_fail(p, e, "forward launch");
+  return enufft::record_stop(p, 0, ev);
+}
+
+namespace enufft {
+enufft_status percell_fwd(enufft_plan_t p, int64_t c, const void *x, const void *y, const void *h, const void *w,
+                          void *f) {
+  const int64_t first = p->fwd_cell_first[c], cnt = p->fwd_cell_first[c + 1] - first;
+  if (cnt == 0) return ENUFFT_OK;
+  hipError_t e;
+  if (p->prec == ENUFFT_F64) {
+    auto a = make_fwd_args<double>(p, x, y, h, w, f);
+    a.items = (const FwdItem *)p->d_fwd_items_cell;
+    a.n_items = (int64_t)p->fwd_items_cell.size();
+    a.item_base = first;
+    a.work_counter = nullptr; a.done_counter = nullptr;
+    e = launch_fwd<double>(a, p->W, (int)cnt, p->fwd_threads, p->fwd_lds, p->stream);
+  } else {
+    auto a = make_fwd_args<float>(p, x, y, h, w, f);
+    a.items = (const FwdItem *)p->d_fwd_items_cell;
+    a.n_items = (int64_t)p->fwd_items_cell.size();
+    a.item_base = first;
+    a.work_counter = nullptr; a.done_counter = nullptr;
+    e = launch_fwd<float>(a, p->W, (int)cnt, p->fwd_threads, p->fwd_lds, p->stream);
+  }
+  if (e != hipSuccess) return hip_fail(p, e, "per-cell forward launch");
+  return ENUFFT_OK;
+}
+}  // namespace enufft
+
+// Defined with the EMS kernel.
+namespace enufft {
+enufft_status ems_launch(enufft_plan_t p, const void *f, const enufft_ems_params *prm, const double *mode_weight,
+                         uint8_t *keep, int32_t *k_star, double *stats, int64_t cell_begin, int64_t cell_count);
+enufft_status ems_validate(enufft_plan_t p, const void *f, const enufft_ems_params *prm, uint8_t *keep,
+                           int32_t *k_star, double *stats);
+}  // namespace enufft
+
+extern "C" enufft_status enufft_percell_loop(enufft_plan_t p, const void *x, const void *y, const void *h,
+                                             const void *w, void *f, const enufft_ems_params *prm,
+                                             const double *mode_weight, uint8_t *keep, int32_t *k_star,
+                                             double *stats) {
+  enufft_status st = enufft::check_plan(p, "enufft_percell_loop");
+  if (st != ENUFFT_OK) return st;
+  if (p->n_cells == 0) return ENUFFT_OK;
+  if (!f) return fail(p, ENUFFT_EINVAL, "enufft_percell_loop: null f");
+  if (p->n_points > 0 && (!x || !y || !h || !w)) return fail(p, ENUFFT_EINVAL, "enufft_percell_loop: null point array");
+  const bool with_ems = prm != nullptr;
+  if (with_ems) {
+    st = enufft::ems_validate(p, f, prm, keep, k_star, stats);
+    if (st != ENUFFT_OK) return st;
+  }
+  for (int64_t c = 0; c < p->n_cells; ++c) {
+    st = enufft::percell_fwd(p, c, x, y, h, w, f);
+    if (st != ENUFFT_OK) return st;
+    if (with_ems) {
+      st = enufft::ems_launch(p, f, prm, mode_weight, keep, k_star, stats, c, 1);
+      if (st != ENUFFT_OK) return st;
+    }
+  }
+  return ENUFFT_OK;
+}

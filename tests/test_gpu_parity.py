@@ -1,0 +1,238 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Tolerances: relative l2 error per cell <= 5e-5 on the FP32 path and <= 1e-10 on the
+FP64 path; EMS kept sets identical on tie-free cells; adjoint gradients <= 5e-5
+(FP32) and <= 1e-10 (FP64) relative l2 over all points."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2606_21278_amd as enf
+import synth
+from helpers import gpu_batch, make_plan, oracle_f, per_cell_rel_l2, rel_l2, robust_selection
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f32": 5e-5, "f64": 1e-10}
+
+
+def _type1(batch, **kw):
+    gb = gpu_batch(batch)
+    plan = make_plan(gb, **kw)
+    f = plan.type1(gb.x, gb.y, gb.h, gb.w)
+    torch.cuda.synchronize()
+    return plan, gb, f.cpu().numpy()
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_config0_single_hexagon(prec):
+    b = synth.config0(precision=prec)
+    print("C0", prec, b.n_points, flush=True)
+    plan, gb, f = _type1(b)
+    ref = oracle_f(b.to(dtype=gb.x.dtype))
+    err = rel_l2(f, ref)
+    print("rel-l2", err, plan.info(), flush=True)
+    assert err <= TOL[prec]
+
+
+def test_config1_scaled_batch_fp32():
+    b = synth.config1(count_scale=0.01)
+    print("C1 scaled", b.n_cells, b.n_points, flush=True)
+    plan, gb, f = _type1(b)
+    ref = oracle_f(b.to(dtype=torch.float32))
+    e = per_cell_rel_l2(f, ref)
+    print("per-cell rel-l2 max %.3e median %.3e" % (e.max(), np.median(e)), flush=True)
+    assert e.max() <= TOL["f32"]
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_split_cells_merge(prec):
+    """Cells larger than one work item are spread by several workgroups and merged."""
+    b = synth.uniform_box(counts=[70000, 3, 0, 40000, 1, 20000], n_modes=(32, 16), precision=prec,
+                          window_radius=3.0)
+    print("split", prec, b.counts(), flush=True)
+    plan, gb, f = _type1(b)
+    info = plan.info()
+    print(info, flush=True)
+    assert info["n_split_cells"] >= 1
+    ref = oracle_f(b.to(dtype=gb.x.dtype))
+    e = per_cell_rel_l2(f, ref)
+    print("per-cell", e, flush=True)
+    assert np.all(f[2] == 0)
+    assert e.max() <= TOL[prec]
+    # a second call reuses the self-resetting counters
+    f2 = plan.type1(gb.x, gb.y, gb.h, gb.w).cpu().numpy()
+    assert per_cell_rel_l2(f2, ref).max() <= TOL[prec]
+
+
+@pytest.mark.parametrize("n_modes", [(16, 16), (17, 9), (1, 8), (64, 32)])
+def test_mode_box_shapes(n_modes):
+    b = synth.uniform_box(counts=[500, 1200], n_modes=n_modes, precision="f64", window_radius=2.5)
+    print("box", n_modes, flush=True)
+    plan, gb, f = _type1(b)
+    ref = oracle_f(b)
+    assert per_cell_rel_l2(f, ref).max() <= TOL["f64"]
+
+
+def test_coordinates_fold_and_edges():
+    """Points on the box edges and far outside it (folded modulo 2 pi); no window."""
+    g = torch.Generator().manual_seed(3)
+    x = torch.cat([torch.tensor([-math.pi, math.pi, 0.0, 2 * math.pi, -1e-12, 1000.0 * math.pi + 0.3],
+                                dtype=torch.float64), (torch.rand(300, generator=g, dtype=torch.float64) - 0.5) * 40])
+    y = torch.cat([torch.tensor([math.pi, -math.pi, 2 * math.pi - 1e-13, 0.0, 7.0, -55.5], dtype=torch.float64),
+                   (torch.rand(300, generator=g, dtype=torch.float64) - 0.5) * 40])
+    n = x.numel()
+    h = torch.randn(n, generator=g, dtype=torch.float64)
+    w = torch.rand(n, generator=g, dtype=torch.float64)
+    off = np.array([0, n], dtype=np.int64)
+    b = synth.Batch("edges", x, y, h, w, off, np.array([[0.0, 0.0, 0.0]]), (24, 24), 2.0, 1e-10, "f64")
+    plan, gb, f = _type1(b, window="none")
+    ref = oracle_f(b)
+    assert rel_l2(f, ref) <= TOL["f64"]
+
+
+def test_percell_loop_matches_batched():
+    b = synth.config1(count_scale=0.004, n_cells=40)
+    gb = gpu_batch(b)
+    plan = make_plan(gb)
+    f = plan.type1(gb.x, gb.y, gb.h, gb.w)
+    keep, ks, st = plan.ems(f)
+    f2, keep2, ks2, st2 = plan.percell_loop(gb.x, gb.y, gb.h, gb.w)
+    torch.cuda.synchronize()
+    assert rel_l2(f2.cpu().numpy(), f.cpu().numpy()) < 1e-6
+    ref = oracle_f(b.to(dtype=torch.float32))
+    assert per_cell_rel_l2(f2.cpu().numpy(), ref).max() <= TOL["f32"]
+
+
+# ------------------------------------------------------------------------- EMS
+
+def _ems_plan_for(f_ref, prec):
+    n, N2, N1 = f_ref.shape
+    off = np.arange(n + 1, dtype=np.int64)
+    plan = enf.Plan(off, np.tile([[0.0, 0.0, 1.0]], (n, 1)), n_modes=(N1, N2), precision=prec,
+                    eps=1e-10 if prec == "f64" else 1e-5)
+    return plan
+
+
+@pytest.mark.parametrize("prm", [oracle.EmsParams(),
+                                 oracle.EmsParams(k_min=1, k_max=12, alpha_min=0.0, alpha_max=0.7),
+                                 oracle.EmsParams(k_min=3, k_max=40, alpha_min=0.5, alpha_max=0.99, delta=0.05,
+                                                  w1=0.3, w2=0.7),
+                                 oracle.EmsParams(use_pairs=0, exclude_dc=0, alpha_min=0.9, alpha_max=0.9)])
+def test_ems_on_identical_coefficients(prm):
+    """Given the same FP64 coefficients, the GPU selection equals the oracle's exactly."""
+    b = synth.config1(count_scale=0.003, n_cells=24, precision="f64")
+    ref = oracle_f(b)
+    plan = _ems_plan_for(ref, "f64")
+    f = torch.from_numpy(ref).to("cuda:0")
+    keep, ks, st = plan.ems(f, enf.EmsParams(**prm.__dict__))
+    keep, ks, st = keep.cpu().numpy(), ks.cpu().numpy(), st.cpu().numpy()
+    ok_keep, ok_ks, ok_st = oracle.ems_batched(ref, prm)
+    assert np.array_equal(ks, ok_ks)
+    assert np.array_equal(keep, ok_keep)
+    assert np.allclose(st, ok_st, rtol=1e-11, atol=0)
+
+
+def test_ems_fig2_families_on_gpu():
+    J = 20
+    j = np.arange(1, J + 1)
+    fams = [np.full(J, 0.5), np.exp(1.0 - j), np.where(j == 1, 1.0, 0.05), np.where(j <= 5, 0.7, 0.35),
+            0.9 * 0.85 ** (j - 1), 0.9 * np.cos(math.pi * (j - 1) / (2 * J))]
+    expect = [12, 1, 1, 12, 3, 7]
+    f = np.zeros((len(fams), 1, J), dtype=np.complex128)
+    rng = np.random.default_rng(1)
+    for i, E in enumerate(fams):
+        f[i, 0, rng.permutation(J)] = np.sqrt(E)
+    plan = _ems_plan_for(f, "f64")
+    prm = enf.EmsParams(k_min=1, k_max=12, alpha_min=0.0, alpha_max=0.7, delta=0.02, w1=0.5, w2=0.5,
+                        use_pairs=0, exclude_dc=0)
+    keep, ks, st = plan.ems(torch.from_numpy(f).to("cuda:0"), prm)
+    assert list(ks.cpu().numpy()) == expect
+
+
+def test_ems_pipeline_fp32_mode_sets():
+    """FP32 coefficients from the GPU, FP64 selection.  (a) On the GPU's own coefficients
+    the GPU selection equals the oracle's exactly.  (b) Against the oracle's FP64
+    coefficients the kept sets are identical on every cell whose selection is robust to
+    the measured coefficient deviation (no ties at that resolution)."""
+    b = synth.config1(count_scale=0.01)
+    gb = gpu_batch(b)
+    plan = make_plan(gb)
+    f = plan.type1(gb.x, gb.y, gb.h, gb.w)
+    keep, ks, st = plan.ems(f)
+    fg = f.cpu().numpy().astype(np.complex128)
+    keep, ks, st = keep.cpu().numpy(), ks.cpu().numpy(), st.cpu().numpy()
+    prm = oracle.EmsParams()
+    ok_keep, ok_ks, ok_st = oracle.ems_batched(fg, prm)
+    assert np.array_equal(ks, ok_ks)
+    assert np.array_equal(keep, ok_keep)
+    assert np.allclose(st, ok_st, rtol=1e-9, atol=0)
+    ref = oracle_f(b.to(dtype=torch.float32))
+    n_rb = 0
+    for c in range(b.n_cells):
+        r = oracle.ems(ref[c], prm)
+        if not robust_selection(ref[c], fg[c], r, prm):
+            continue
+        n_rb += 1
+        assert ks[c] == r.k_star, c
+        assert np.array_equal(keep[c], r.keep), c
+    print("robust cells", n_rb, "of", b.n_cells, flush=True)
+    assert n_rb >= 1
+    # repeated runs give the same sets
+    for _ in range(5):
+        f2 = plan.type1(gb.x, gb.y, gb.h, gb.w)
+        k2, ks2, _ = plan.ems(f2)
+        assert np.array_equal(ks2.cpu().numpy(), ks)
+
+
+# --------------------------------------------------------------------- adjoint
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_adjoint_matches_oracle_vjp(prec):
+    """Same cotangent (2 f keep from the oracle) on both sides isolates the type-2 error."""
+    b = synth.config1(count_scale=0.004, n_cells=12, precision=prec)
+    b.eps = 1e-10 if prec == "f64" else 1e-5
+    inp = oracle.batch_inputs(b)
+    f = oracle_f(b)
+    keep, ks, st = oracle.ems_batched(f, oracle.EmsParams())
+    g = 2.0 * f * keep
+    gh, gx, gy = oracle.type1_vjp(inp["offsets"], inp["x"], inp["y"], inp["h"], inp["w"], inp["windows"],
+                                  inp["n_modes"], g)
+    gb = gpu_batch(b)
+    plan = make_plan(gb)
+    fbar = torch.from_numpy(g).to("cuda:0", plan.cdtype)
+    ah, ax, ay = plan.adjoint(gb.x, gb.y, gb.h, gb.w, fbar)
+    print(plan.info(), flush=True)
+    eh = rel_l2(ah.cpu().numpy(), gh)
+    ex = rel_l2(ax.cpu().numpy(), gx)
+    ey = rel_l2(ay.cpu().numpy(), gy)
+    print(prec, "adjoint rel-l2 h %.3e x %.3e y %.3e" % (eh, ex, ey), flush=True)
+    assert max(eh, ex, ey) <= TOL[prec]
+
+
+def test_retained_power_autograd_fp32():
+    b = synth.config1(count_scale=0.004, n_cells=16)
+    gb = gpu_batch(b)
+    plan = make_plan(gb)
+    x = gb.x.clone().requires_grad_(True)
+    y = gb.y.clone().requires_grad_(True)
+    h = gb.h.clone().requires_grad_(True)
+    P = enf.retained_power(x, y, h, gb.w, plan)
+    P.sum().backward()
+    inp = oracle.batch_inputs(b.to(dtype=torch.float32))
+    res = oracle.retained_power_grad(prm=oracle.EmsParams(), **inp)
+    ks_gpu = None
+    # compare on cells whose kept set agrees with the oracle's
+    _, ks, _ = plan.ems(plan.type1(gb.x, gb.y, gb.h, gb.w))
+    ks = ks.cpu().numpy()
+    same = ks == res["k_star"]
+    assert same.mean() >= 0.8
+    mask = np.repeat(same, b.counts())
+    for name, t in (("grad_h", h.grad), ("grad_x", x.grad), ("grad_y", y.grad)):
+        e = rel_l2(t.detach().cpu().numpy()[mask], res[name][mask])
+        print(name, "rel-l2 %.3e" % e, flush=True)
+        assert e <= TOL["f32"]
+    assert np.allclose(P.detach().cpu().numpy()[same], res["stats"][same, 1], rtol=1e-4)
