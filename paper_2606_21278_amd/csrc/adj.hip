@@ -29,7 +29,7 @@ struct AdjLayout {
 
 __host__ __device__ inline AdjLayout adj_layout(const Geom &g, int W, int band_rows) {
   AdjLayout L;
-  L.rows = band_rows + W;
+  L.rows = band_rows + W;   // R + W - 1 rows are used; one more keeps the uy rows paired
   L.cpitch = 2 * (g.K1 + 1) + 2;
   const size_t gsz = (size_t)L.rows * g.pitch;
   L.g_off = 0;
@@ -126,7 +126,7 @@ __global__ __launch_bounds__(NT) void adj_kernel(AdjArgs<T> a) {
     }
     const AdjItem it = a.items[idx];
     const T *gc = a.fbar + (int64_t)it.cell * g.N1 * g.N2 * 2;
-    const int y0 = it.band * a.band_rows - W / 2;   // fine row of band-local row 0
+    const int y0 = it.band * a.band_rows;   // fine row of band-local row 0
 
     // columns of H and of i ky H, inverse transformed along y; keep the band rows
     load_columns<T, NT>(a, gc, it.cell, ws, L.cpitch, false);
@@ -195,8 +195,6 @@ __global__ __launch_bounds__(NT) void adj_kernel(AdjArgs<T> a) {
     });
 
     // Gather at the points of this band.
-    const T n1f = T(g.n1), n2f = T(g.n2);
-    const T s1 = n1f / T(2.0 * M_PI), s2 = n2f / T(2.0 * M_PI);
     const T halfw = T(W) / T(2);
     const T zsc = T(2) / T(W);
     const double *wn = a.windows + 3 * (int64_t)it.cell;
@@ -204,22 +202,18 @@ __global__ __launch_bounds__(NT) void adj_kernel(AdjArgs<T> a) {
     const int band_lo = it.band * a.band_rows;
     for (int64_t j = it.begin + threadIdx.x; j < it.end; j += NT) {
       const T yj = a.y[j];
-      const T ty = fold_grid<T>(yj, s2, n2f);
-      int band = (int)floor(ty / T(a.band_rows));
-      band = min(max(band, 0), a.bands - 1);
-      if (band != it.band) continue;
+      const FineCoord<T> fy = fine_coord<T>(yj, a.s2_hi, a.s2_lo, halfw);
+      const int r0 = (fy.i0 & (g.n2 - 1)) - band_lo;    // first footprint row, band-local
+      if (r0 < 0 || r0 >= a.band_rows) continue;
       const T xj = a.x[j];
-      const T tx = fold_grid<T>(xj, s1, n1f);
-      const int i0x = (int)ceil(tx - halfw);
-      int r0 = (int)ceil(ty - halfw) - band_lo + W / 2;
-      r0 = min(max(r0, 0), a.band_rows);
+      const FineCoord<T> fx = fine_coord<T>(xj, a.s1_hi, a.s1_lo, halfw);
       T kx[W], ky[W];
       int cp[W];
 #pragma unroll
       for (int d = 0; d < W; ++d) {
-        kx[d] = es_eval(T(i0x + d - tx) * zsc, a.beta);
-        ky[d] = es_eval(T(r0 - W / 2 + band_lo + d - ty) * zsc, a.beta);
-        cp[d] = fft_pos((i0x + d) & (n1 - 1), n1);
+        kx[d] = es_eval(fx.offset(d) * zsc, a.beta);
+        ky[d] = es_eval(fy.offset(d) * zsc, a.beta);
+        cp[d] = fft_pos((fx.i0 + d) & (n1 - 1), n1);
       }
       T u = 0, ux = 0, uy = 0;
 #pragma unroll
@@ -287,6 +281,8 @@ template hipError_t launch_adj<double>(const AdjArgs<double> &, int, int, int, s
 
 enufft_status record_start(enufft_plan_t p, int kind, hipEvent_t *ev);
 enufft_status record_stop(enufft_plan_t p, int kind, hipEvent_t start);
+template <typename T>
+void split_scale(int n, T *hi, T *lo);
 
 // Bands per cell: the fewest row bands whose three grids, band spectra and
 // column workspace fit one workgroup's LDS.
@@ -407,6 +403,8 @@ AdjArgs<T> make_adj_args(enufft_plan_t p, const void *x, const void *y, const vo
   a.decon_x = (const T *)p->d_decon_x; a.decon_y = (const T *)p->d_decon_y;
   a.tw1 = (const T *)p->d_tw1; a.tw2 = (const T *)p->d_tw2;
   a.beta = (T)p->beta;
+  split_scale<T>(p->n1, &a.s1_hi, &a.s1_lo);
+  split_scale<T>(p->n2, &a.s2_hi, &a.s2_lo);
   a.bands = p->adj_bands;
   a.band_rows = p->adj_band_rows;
   a.g = p->geom;

@@ -51,6 +51,7 @@ struct FwdArgs {
   const T *decon_y;          // [K2 + 1]: 1 / p_y(|k|)
   const T *tw1, *tw2;        // forward twiddles exp(-2 pi i j / n), interleaved, n entries
   T beta;                    // ES shape parameter
+  T s1_hi, s1_lo, s2_hi, s2_lo;   // n1 / (2 pi) and n2 / (2 pi) as hi + lo
   Geom g;
 };
 
@@ -71,31 +72,48 @@ struct AdjArgs {
   const T *decon_x, *decon_y;  // as the forward (decon_x carries scale)
   const T *tw1, *tw2;          // forward twiddles (the inverse uses their conjugates)
   T beta;
+  T s1_hi, s1_lo, s2_hi, s2_lo;
   int bands, band_rows;        // row bands per cell and rows per band
   Geom g;
 };
 
 // ------------------------------------------------------------------ ES kernel
 
-// psi(z) = exp(beta (sqrt(1 - z^2) - 1)) on |z| <= 1.  Rounding can push |z|
-// a hair past 1; those taps take the edge value exp(-beta).
+// psi(z) = exp(beta (sqrt(1 - z^2) - 1)) on |z| <= 1, evaluated as
+// exp(-beta z^2 / (1 + sqrt(1 - z^2))) so the exponent has no cancellation.
+// Rounding can push |z| a hair past 1; those taps take the edge value.
 __device__ __forceinline__ float es_eval(float z, float beta) {
-  float s = fmaxf(1.0f - z * z, 0.0f);
-  return __expf(beta * (__builtin_sqrtf(s) - 1.0f));
+  const float z2 = z * z;
+  const float s = __builtin_sqrtf(fmaxf(1.0f - z2, 0.0f));
+  return __expf(-beta * z2 / (1.0f + s));
 }
 __device__ __forceinline__ double es_eval(double z, double beta) {
-  double s = fmax(1.0 - z * z, 0.0);
-  return exp(beta * (sqrt(s) - 1.0));
+  const double z2 = z * z;
+  const double s = sqrt(fmax(1.0 - z2, 0.0));
+  return exp(-beta * z2 / (1.0 + s));
 }
 
-// Fold a coordinate to fine-grid units t in [0, n): t = x n / (2 pi) mod n.
+// Fine-grid coordinate t = x n / (2 pi), kept as t_hi + t_lo with the scale
+// n / (2 pi) split the same way, so the tap offsets (i0 + d) - t are exact to a
+// few units in the last place whatever the size of t.  The footprint starts at
+// i0 = ceil(t - W/2); indices are wrapped with the grid mask by the caller, so
+// no folding rounds t.  Non-finite or huge coordinates (|t| >= 2^22) are
+// placed at t = 0 so every index stays in range.
 template <typename T>
-__device__ __forceinline__ T fold_grid(T x, T n_over_2pi, T n) {
-  T t = x * n_over_2pi;
-  t = t - n * floor(t / n);
-  if (!(t < n)) t = (t >= n) ? t - n : T(0);   // rounding at the top edge; NaN -> 0
-  if (!(t >= T(0))) t = T(0);
-  return t;
+struct FineCoord {
+  int i0;
+  T hi, lo;
+  __device__ __forceinline__ T offset(int d) const { return (T(i0 + d) - hi) - lo; }
+};
+template <typename T>
+__device__ __forceinline__ FineCoord<T> fine_coord(T x, T s_hi, T s_lo, T halfw) {
+  FineCoord<T> c;
+  c.hi = x * s_hi;
+  c.lo = fma(x, s_hi, -c.hi) + x * s_lo;
+  const T t = c.hi + c.lo;
+  if (!(fabs(t) < T(4194304))) { c.hi = T(0); c.lo = T(0); }
+  c.i0 = (int)ceil((c.hi + c.lo) - halfw);
+  return c;
 }
 
 __device__ __forceinline__ void sincos_t(float u, float &s, float &c) { sincosf(u, &s, &c); }

@@ -14,39 +14,34 @@
 namespace enufft {
 
 // Spread the points [begin, end) of one item into the LDS grid.
-// grid has n2 + W rows of `pitch` elements; stored row s holds fine-grid row
-// s - W/2 (rows outside [0, n2) are folded back afterwards), columns wrap.
+// The grid accumulates in FP64: on gfx950 the LDS adds FP64 values many times
+// faster than FP32 ones, and the wider sum costs no accuracy.  Stored row r
+// holds fine row r mod n2 (rows n2 .. n2 + W - 2 are folded back afterwards);
+// columns wrap with the grid mask.
 template <typename T, int W, int NT>
-__device__ __forceinline__ void spread_item(const FwdArgs<T> &a, T *grid, int64_t begin, int64_t end,
+__device__ __forceinline__ void spread_item(const FwdArgs<T> &a, double *grid, int64_t begin, int64_t end,
                                             T cx, T cy, T R) {
   const Geom &g = a.g;
-  const T n1f = T(g.n1), n2f = T(g.n2);
-  const T s1 = n1f / T(2.0 * M_PI), s2 = n2f / T(2.0 * M_PI);
   const T halfw = T(W) / T(2);
   const T zsc = T(2) / T(W);
-  const int mask1 = g.n1 - 1;
+  const int mask1 = g.n1 - 1, mask2 = g.n2 - 1;
   const int pitch = g.pitch;
-  const int i0max1 = (int)ceil(n1f - halfw), i0max2 = (int)ceil(n2f - halfw);
   for (int64_t j = begin + threadIdx.x; j < end; j += NT) {
     const T xj = a.x[j], yj = a.y[j];
     const T c = a.w[j] * a.h[j] * hann_w<T>(a.window_kind, xj, yj, cx, cy, R);
     if (c == T(0)) continue;
-    const T tx = fold_grid<T>(xj, s1, n1f);
-    const T ty = fold_grid<T>(yj, s2, n2f);
-    int i0x = (int)ceil(tx - halfw);
-    int i0y = (int)ceil(ty - halfw);
-    i0x = min(max(i0x, -(W / 2)), i0max1);
-    i0y = min(max(i0y, -(W / 2)), i0max2);
-    T kx[W], ky[W];
+    const FineCoord<T> fx = fine_coord<T>(xj, a.s1_hi, a.s1_lo, halfw);
+    const FineCoord<T> fy = fine_coord<T>(yj, a.s2_hi, a.s2_lo, halfw);
+    double kx[W], ky[W];
 #pragma unroll
     for (int d = 0; d < W; ++d) {
-      kx[d] = es_eval(T(i0x + d - tx) * zsc, a.beta);
-      ky[d] = c * es_eval(T(i0y + d - ty) * zsc, a.beta);
+      kx[d] = (double)es_eval(fx.offset(d) * zsc, a.beta);
+      ky[d] = (double)(c * es_eval(fy.offset(d) * zsc, a.beta));
     }
     int col[W];
 #pragma unroll
-    for (int d = 0; d < W; ++d) col[d] = (i0x + d) & mask1;
-    T *rowp = grid + (i0y + W / 2) * pitch;
+    for (int d = 0; d < W; ++d) col[d] = (fx.i0 + d) & mask1;
+    double *rowp = grid + (fy.i0 & mask2) * pitch;
 #pragma unroll
     for (int dy = 0; dy < W; ++dy) {
 #pragma unroll
@@ -58,23 +53,44 @@ __device__ __forceinline__ void spread_item(const FwdArgs<T> &a, T *grid, int64_
   }
 }
 
-// Fold the padding rows of the spread grid onto the periodic rows.
-template <typename T, int W, int NT>
-__device__ __forceinline__ void fold_rows(T *grid, const Geom &g) {
-  const int plo = W / 2, phi = W - W / 2;
+// Fold stored rows n2 .. n2 + W - 2 onto rows 0 .. W - 2.
+template <int W, int NT>
+__device__ __forceinline__ void fold_rows(double *grid, const Geom &g) {
   const int pitch = g.pitch;
-  // stored rows [0, plo) hold fine rows -plo..-1, the same as fine rows n2-plo..n2-1
-  // (stored n2..n2+plo-1); stored rows [n2+plo, n2+W) hold fine rows n2.. = rows 0..phi-1.
-  for (int i = threadIdx.x; i < plo * g.n1; i += NT) {
+  for (int i = threadIdx.x; i < (W - 1) * g.n1; i += NT) {
     const int r = i / g.n1, c = i - r * g.n1;
-    grid[(r + g.n2) * pitch + c] += grid[r * pitch + c];
+    grid[r * pitch + c] += grid[(r + g.n2) * pitch + c];
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < phi * g.n1; i += NT) {
-    const int r = i / g.n1, c = i - r * g.n1;
-    grid[(plo + r) * pitch + c] += grid[(plo + g.n2 + r) * pitch + c];
+}
+
+// Round the FP64 grid (n2 rows of `pitch`) to T in place: element i moves from
+// byte 8 i to byte sizeof(T) i.  Each round reads a block before any thread
+// writes it, and a write of round k lands on bytes read in rounds <= k.
+template <typename T, int NT>
+__device__ __forceinline__ void grid_to_t(double *grid, const Geom &g) {
+  if constexpr (sizeof(T) == sizeof(double)) {
+    return;
+  } else {
+    constexpr int PER = 8;
+    const int total = g.n2 * g.pitch;
+    T *out = reinterpret_cast<T *>(grid);
+    for (int base = 0; base < total; base += PER * NT) {
+      double v[PER];
+#pragma unroll
+      for (int q = 0; q < PER; ++q) {
+        const int i = base + q * NT + threadIdx.x;
+        v[q] = i < total ? grid[i] : 0.0;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < PER; ++q) {
+        const int i = base + q * NT + threadIdx.x;
+        if (i < total) out[i] = (T)v[q];
+      }
+      __syncthreads();
+    }
   }
-  __syncthreads();
 }
 
 // FFT of the folded real grid G (logical row 0 at G), deconvolution and crop.
@@ -152,12 +168,12 @@ __device__ void fft_deconv_store(const FwdArgs<T> &a, T *G, int cell) {
 template <typename T, int W, int NT>
 __global__ __launch_bounds__(NT) void fwd_kernel(FwdArgs<T> a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  T *grid = reinterpret_cast<T *>(smem_raw);
+  double *grid = reinterpret_cast<double *>(smem_raw);
+  T *G = reinterpret_cast<T *>(smem_raw);   // the same grid after rounding to T
   __shared__ int s_item, s_last;
   const Geom &g = a.g;
   const int pitch = g.pitch;
-  const int total = (g.n2 + W) * pitch;
-  T *G = grid + (W / 2) * pitch;   // logical fine row 0
+  const int total = (g.n2 + W - 1) * pitch;
   const bool persistent = a.work_counter != nullptr;
   int64_t idx = a.item_base + blockIdx.x;
   if (!persistent && idx >= a.n_items) return;
@@ -170,12 +186,13 @@ __global__ __launch_bounds__(NT) void fwd_kernel(FwdArgs<T> a) {
       if (idx >= a.n_items) break;
     }
     const FwdItem it = a.items[idx];
-    for (int i = threadIdx.x; i < total; i += NT) grid[i] = T(0);
+    for (int i = threadIdx.x; i < total; i += NT) grid[i] = 0.0;
     __syncthreads();
     const double *wn = a.windows + 3 * (int64_t)it.cell;
     spread_item<T, W, NT>(a, grid, it.begin, it.end, T(wn[0]), T(wn[1]), T(wn[2]));
     __syncthreads();
-    fold_rows<T, W, NT>(grid, g);
+    fold_rows<W, NT>(grid, g);
+    grid_to_t<T, NT>(grid, g);
     bool run_fft = true;
     if (it.nchunks > 1) {
       const int nn = g.n1 * g.n2;

@@ -18,9 +18,9 @@ hipError_t launch_adj(const AdjArgs<T> &a, int W, int blocks, int threads, size_
 template <typename T>
 hipError_t adj_occupancy(int W, int threads, size_t lds, int *blocks_per_cu);
 
-// LDS bytes of the forward kernel for a geometry and kernel width.
-inline size_t fwd_lds_bytes(const Geom &g, int W, size_t elem) {
-  return (size_t)(g.n2 + W) * g.pitch * elem;
+// LDS bytes of the forward kernel: the FP64 spread grid with W - 1 wrap rows.
+inline size_t fwd_lds_bytes(const Geom &g, int W) {
+  return (size_t)(g.n2 + W - 1) * g.pitch * sizeof(double);
 }
 
 }  // namespace enufft

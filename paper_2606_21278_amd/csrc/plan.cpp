@@ -321,8 +321,8 @@ enufft_status enufft_plan(enufft_plan_t *out, int64_t n_cells, const int64_t *ce
   p->n_cu = prop.multiProcessorCount;
 
   // ---- forward launch shape
-  p->fwd_threads = (p->prec == ENUFFT_F64) ? 256 : 512;
-  p->fwd_lds = enufft::fwd_lds_bytes(g, W, p->elem);
+  p->fwd_threads = (p->prec == ENUFFT_F64) ? 512 : 1024;
+  p->fwd_lds = enufft::fwd_lds_bytes(g, W);
   if (p->fwd_lds > (size_t)prop.sharedMemPerBlock) {
     free_plan(p);
     return fail(nullptr, ENUFFT_EUNSUPPORTED, "enufft_plan: fine grid does not fit in LDS at this precision");
@@ -484,6 +484,16 @@ enufft_status record_stop(enufft_plan_t p, int kind, hipEvent_t start) {
   return ENUFFT_OK;
 }
 
+// n / (2 pi) as hi + lo in T (from extended precision on the host).
+template <typename T>
+void split_scale(int n, T *hi, T *lo) {
+  const long double s = (long double)n / (2.0L * 3.141592653589793238462643383279502884L);
+  *hi = (T)s;
+  *lo = (T)(s - (long double)*hi);
+}
+template void split_scale<float>(int, float *, float *);
+template void split_scale<double>(int, double *, double *);
+
 template <typename T>
 FwdArgs<T> make_fwd_args(enufft_plan_t p, const void *x, const void *y, const void *h, const void *w, void *f) {
   FwdArgs<T> a{};
@@ -501,6 +511,8 @@ FwdArgs<T> make_fwd_args(enufft_plan_t p, const void *x, const void *y, const vo
   a.decon_x = (const T *)p->d_decon_x; a.decon_y = (const T *)p->d_decon_y;
   a.tw1 = (const T *)p->d_tw1; a.tw2 = (const T *)p->d_tw2;
   a.beta = (T)p->beta;
+  split_scale<T>(p->n1, &a.s1_hi, &a.s1_lo);
+  split_scale<T>(p->n2, &a.s2_hi, &a.s2_lo);
   a.g = p->geom;
   return a;
 }
