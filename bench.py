@@ -73,6 +73,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--shuffled", action="store_true", help="random point order within each cell")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MB",
+                    help="after timing, run one plain device copy of this size (for profiler byte counters)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -132,6 +134,16 @@ def main():
     tadj = tm["adjoint_ms"] / max(1, tm["adjoint_launches"])
     value = Q / ((t1 + tems) * 1e-3)
     log("per step: type1 %.3f ms, ems %.3f ms, adjoint %.3f ms, step %.3f ms" % (t1, tems, tadj, ms_step))
+
+    if args.calibrate_copy > 0:
+        n = args.calibrate_copy * 1024 * 1024 // 4
+        src = torch.ones(n, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copy calibration: %d MB read + %d MB written" % (args.calibrate_copy, args.calibrate_copy))
+        del src, dst
 
     percell = None
     if not args.no_percell:

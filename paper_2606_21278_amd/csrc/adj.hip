@@ -199,6 +199,7 @@ __global__ __launch_bounds__(NT) void adj_kernel(AdjArgs<T> a) {
     const T zsc = T(2) / T(W);
     const double *wn = a.windows + 3 * (int64_t)it.cell;
     const T cx = T(wn[0]), cy = T(wn[1]), R = T(wn[2]);
+    const T pr = R > T(0) ? T(M_PI) / R : T(0);
     const int band_lo = it.band * a.band_rows;
     for (int64_t j = it.begin + threadIdx.x; j < it.end; j += NT) {
       const T yj = a.y[j];
@@ -231,7 +232,7 @@ __global__ __launch_bounds__(NT) void adj_kernel(AdjArgs<T> a) {
         uy += ky[dy] * sy;
       }
       T dWx, dWy;
-      const T Wv = hann_wg<T>(a.window_kind, xj, yj, cx, cy, R, dWx, dWy);
+      const T Wv = hann_wg(a.window_kind, xj, yj, cx, cy, R, pr, dWx, dWy);
       const T wj = a.w[j];
       if (a.grad_h) a.grad_h[j] = wj * Wv * u;
       if (a.grad_x || a.grad_y) {

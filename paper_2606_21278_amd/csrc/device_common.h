@@ -52,6 +52,7 @@ struct FwdArgs {
   const T *tw1, *tw2;        // forward twiddles exp(-2 pi i j / n), interleaved, n entries
   T beta;                    // ES shape parameter
   T s1_hi, s1_lo, s2_hi, s2_lo;   // n1 / (2 pi) and n2 / (2 pi) as hi + lo
+  int vec4;                  // x, y, h, w are 16-byte aligned: load runs of 4 points
   Geom g;
 };
 
@@ -85,7 +86,7 @@ struct AdjArgs {
 __device__ __forceinline__ float es_eval(float z, float beta) {
   const float z2 = z * z;
   const float s = __builtin_sqrtf(fmaxf(1.0f - z2, 0.0f));
-  return __expf(-beta * z2 / (1.0f + s));
+  return __expf(-beta * z2 * __builtin_amdgcn_rcpf(1.0f + s));
 }
 __device__ __forceinline__ double es_eval(double z, double beta) {
   const double z2 = z * z;
@@ -116,33 +117,56 @@ __device__ __forceinline__ FineCoord<T> fine_coord(T x, T s_hi, T s_lo, T halfw)
   return c;
 }
 
-__device__ __forceinline__ void sincos_t(float u, float &s, float &c) { sincosf(u, &s, &c); }
-__device__ __forceinline__ void sincos_t(double u, double &s, double &c) { sincos(u, &s, &c); }
 
-// Radial Hann window and gradient; kind 0 is no window.
-template <typename T>
-__device__ __forceinline__ T hann_w(int kind, T x, T y, T cx, T cy, T R) {
-  if (kind == 0) return T(1);
-  T dx = x - cx, dy = y - cy;
-  T r = sqrt(dx * dx + dy * dy);
-  if (!(r < R)) return T(0);
-  return T(0.5) * (T(1) + cos(T(M_PI) * r / R));
+// Radial Hann window W = (1 + cos(pi r / R)) / 2 for r < R, else 0, and its
+// gradient -(pi^2 / (2 R^2)) sinc(pi r / R) (x - cx, y - cy).  kind 0 is no
+// window.  pr = pi / R is precomputed per cell.  FP32 uses the hardware
+// sqrt / reciprocal / sin / cos (errors ~1e-6 absolute on W, far inside the
+// FP32 tolerance); FP64 uses the accurate library functions.
+__device__ __forceinline__ float hann_w(int kind, float x, float y, float cx, float cy, float R, float pr) {
+  if (kind == 0) return 1.0f;
+  const float dx = x - cx, dy = y - cy;
+  const float r = __builtin_sqrtf(dx * dx + dy * dy);
+  if (!(r < R)) return 0.0f;
+  return 0.5f + 0.5f * __cosf(pr * r);
 }
-template <typename T>
-__device__ __forceinline__ T hann_wg(int kind, T x, T y, T cx, T cy, T R, T &gx, T &gy) {
-  gx = T(0); gy = T(0);
-  if (kind == 0) return T(1);
-  T dx = x - cx, dy = y - cy;
-  T r = sqrt(dx * dx + dy * dy);
-  if (!(r < R)) return T(0);
-  T u = T(M_PI) * r / R;
-  T s, c;
-  sincos_t(u, s, c);
-  T sinc = (u > T(0)) ? s / u : T(1);
-  T k = -(T(M_PI) * T(M_PI)) / (T(2) * R * R) * sinc;
+__device__ __forceinline__ double hann_w(int kind, double x, double y, double cx, double cy, double R, double pr) {
+  if (kind == 0) return 1.0;
+  const double dx = x - cx, dy = y - cy;
+  const double r = sqrt(dx * dx + dy * dy);
+  if (!(r < R)) return 0.0;
+  return 0.5 + 0.5 * cos(pr * r);
+}
+__device__ __forceinline__ float hann_wg(int kind, float x, float y, float cx, float cy, float R, float pr,
+                                         float &gx, float &gy) {
+  gx = 0.0f; gy = 0.0f;
+  if (kind == 0) return 1.0f;
+  const float dx = x - cx, dy = y - cy;
+  const float r = __builtin_sqrtf(dx * dx + dy * dy);
+  if (!(r < R)) return 0.0f;
+  const float u = pr * r;
+  const float s = __sinf(u), c = __cosf(u);
+  const float sinc = (u > 1e-4f) ? s * __builtin_amdgcn_rcpf(u) : 1.0f - u * u * (1.0f / 6.0f);
+  const float k = -0.5f * pr * pr * sinc;
   gx = k * dx;
   gy = k * dy;
-  return T(0.5) * (T(1) + c);
+  return 0.5f + 0.5f * c;
+}
+__device__ __forceinline__ double hann_wg(int kind, double x, double y, double cx, double cy, double R, double pr,
+                                          double &gx, double &gy) {
+  gx = 0.0; gy = 0.0;
+  if (kind == 0) return 1.0;
+  const double dx = x - cx, dy = y - cy;
+  const double r = sqrt(dx * dx + dy * dy);
+  if (!(r < R)) return 0.0;
+  const double u = pr * r;
+  double s, c;
+  sincos(u, &s, &c);
+  const double sinc = (u > 1e-8) ? s / u : 1.0 - u * u / 6.0;
+  const double k = -0.5 * pr * pr * sinc;
+  gx = k * dx;
+  gy = k * dy;
+  return 0.5 + 0.5 * c;
 }
 
 // ------------------------------------------------------------------ small DFTs
@@ -294,5 +318,8 @@ __device__ __forceinline__ void fft_batch(int n, int count, const T *tw, const M
 template <typename T> struct vec2;
 template <> struct vec2<float> { using type = float2; };
 template <> struct vec2<double> { using type = double2; };
+template <typename T> struct vec4;
+template <> struct vec4<float> { using type = float4; };
+template <> struct vec4<double> { using type = double4; };
 
 }  // namespace enufft

@@ -8,6 +8,8 @@
 // strength c_j = w_j W(x_j) h_j; Step 3 is the 2D FFT; Step 4 divides by the
 // kernel's Fourier transform (eq. deconv) and the result is truncated to the
 // mode box.
+#include <climits>
+
 #include "device_common.h"
 #include "launch.h"
 
@@ -18,46 +20,166 @@ namespace enufft {
 // faster than FP32 ones, and the wider sum costs no accuracy.  Stored row r
 // holds fine row r mod n2 (rows n2 .. n2 + W - 2 are folded back afterwards);
 // columns wrap with the grid mask.
-template <typename T, int W, int NT>
-__device__ __forceinline__ void spread_item(const FwdArgs<T> &a, double *grid, int64_t begin, int64_t end,
-                                            T cx, T cy, T R) {
+// Add one point's W x W contributions to the FP64 grid.
+template <typename T, int W>
+__device__ __forceinline__ void spread_point(const FwdArgs<T> &a, double *grid, T c, const FineCoord<T> &fx,
+                                             const FineCoord<T> &fy) {
   const Geom &g = a.g;
-  const T halfw = T(W) / T(2);
   const T zsc = T(2) / T(W);
-  const int mask1 = g.n1 - 1, mask2 = g.n2 - 1;
-  const int pitch = g.pitch;
-  for (int64_t j = begin + threadIdx.x; j < end; j += NT) {
-    const T xj = a.x[j], yj = a.y[j];
-    const T c = a.w[j] * a.h[j] * hann_w<T>(a.window_kind, xj, yj, cx, cy, R);
-    if (c == T(0)) continue;
-    const FineCoord<T> fx = fine_coord<T>(xj, a.s1_hi, a.s1_lo, halfw);
-    const FineCoord<T> fy = fine_coord<T>(yj, a.s2_hi, a.s2_lo, halfw);
-    double kx[W], ky[W];
+  double kx[W], ky[W];
 #pragma unroll
-    for (int d = 0; d < W; ++d) {
-      kx[d] = (double)es_eval(fx.offset(d) * zsc, a.beta);
-      ky[d] = (double)(c * es_eval(fy.offset(d) * zsc, a.beta));
-    }
-    int col[W];
+  for (int d = 0; d < W; ++d) {
+    kx[d] = (double)es_eval(fx.offset(d) * zsc, a.beta);
+    ky[d] = (double)(c * es_eval(fy.offset(d) * zsc, a.beta));
+  }
+  int col[W];
 #pragma unroll
-    for (int d = 0; d < W; ++d) col[d] = (fx.i0 + d) & mask1;
-    double *rowp = grid + (fy.i0 & mask2) * pitch;
+  for (int d = 0; d < W; ++d) col[d] = (fx.i0 + d) & (g.n1 - 1);
+  double *rowp = grid + (fy.i0 & (g.n2 - 1)) * g.pitch;
 #pragma unroll
-    for (int dy = 0; dy < W; ++dy) {
+  for (int dy = 0; dy < W; ++dy) {
 #pragma unroll
-      for (int dx = 0; dx < W; ++dx) {
-        __hip_atomic_fetch_add(rowp + dy * pitch + col[dx], ky[dy] * kx[dx], __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_WORKGROUP);
-      }
+    for (int dx = 0; dx < W; ++dx) {
+      __hip_atomic_fetch_add(rowp + dy * g.pitch + col[dx], ky[dy] * kx[dx], __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_WORKGROUP);
     }
   }
 }
 
-// Fold stored rows n2 .. n2 + W - 2 onto rows 0 .. W - 2.
+// Runs of consecutive points.  Each thread takes K = 4 consecutive points (one
+// 16-byte load per array).  When their footprints start within two rows and
+// three columns of each other -- the usual case for points stored in raster
+// order, several per fine-grid cell -- their contributions are summed in a
+// (W + 1) x (W + 2) register window and the window is added to the grid once,
+// which cuts the LDS atomics per point and spreads neighbouring lanes apart.
+// Other groups fall back to spreading point by point.
+constexpr int RUN_K = 4, RUN_SX = 2, RUN_SY = 1;
+
+template <typename T, int W>
+__device__ __forceinline__ void spread_run(const FwdArgs<T> &a, double *grid, const T (&xs)[RUN_K],
+                                           const T (&ys)[RUN_K], const T (&cs)[RUN_K]) {
+  const Geom &g = a.g;
+  const T halfw = T(W) / T(2);
+  const T zsc = T(2) / T(W);
+  FineCoord<T> fx[RUN_K], fy[RUN_K];
+  int cmin = INT_MAX, rmin = INT_MAX, cmax = INT_MIN, rmax = INT_MIN;
+#pragma unroll
+  for (int k = 0; k < RUN_K; ++k) {
+    fx[k] = fine_coord<T>(xs[k], a.s1_hi, a.s1_lo, halfw);
+    fy[k] = fine_coord<T>(ys[k], a.s2_hi, a.s2_lo, halfw);
+    if (cs[k] != T(0)) {
+      cmin = min(cmin, fx[k].i0); cmax = max(cmax, fx[k].i0);
+      rmin = min(rmin, fy[k].i0); rmax = max(rmax, fy[k].i0);
+    }
+  }
+  if (rmin == INT_MAX) return;   // every point outside the window
+  if (cmax - cmin <= RUN_SX && rmax - rmin <= RUN_SY) {
+    constexpr int WC = W + RUN_SX, WR = W + RUN_SY;
+    T acc[WR][WC];
+#pragma unroll
+    for (int r = 0; r < WR; ++r)
+#pragma unroll
+      for (int q = 0; q < WC; ++q) acc[r][q] = T(0);
+#pragma unroll
+    for (int k = 0; k < RUN_K; ++k) {
+      if (cs[k] == T(0)) continue;
+      T kx[W], ky[W];
+#pragma unroll
+      for (int d = 0; d < W; ++d) {
+        kx[d] = es_eval(fx[k].offset(d) * zsc, a.beta);
+        ky[d] = cs[k] * es_eval(fy[k].offset(d) * zsc, a.beta);
+      }
+      const int sx = fx[k].i0 - cmin, sy = fy[k].i0 - rmin;
+      T KX[WC], KY[WR];
+#pragma unroll
+      for (int q = 0; q < WC; ++q) {
+        T v = T(0);
+#pragma unroll
+        for (int s = 0; s <= RUN_SX; ++s)
+          if (q - s >= 0 && q - s < W) v = (sx == s) ? kx[q - s] : v;
+        KX[q] = v;
+      }
+#pragma unroll
+      for (int r = 0; r < WR; ++r) {
+        T v = T(0);
+#pragma unroll
+        for (int s = 0; s <= RUN_SY; ++s)
+          if (r - s >= 0 && r - s < W) v = (sy == s) ? ky[r - s] : v;
+        KY[r] = v;
+      }
+#pragma unroll
+      for (int r = 0; r < WR; ++r)
+#pragma unroll
+        for (int q = 0; q < WC; ++q) acc[r][q] += KY[r] * KX[q];
+    }
+    int col[WC];
+#pragma unroll
+    for (int q = 0; q < WC; ++q) col[q] = (cmin + q) & (g.n1 - 1);
+    double *rowp = grid + (rmin & (g.n2 - 1)) * g.pitch;
+    const int nr = W + (rmax - rmin), nc = W + (cmax - cmin);
+#pragma unroll
+    for (int r = 0; r < WR; ++r) {
+      if (r >= nr) break;
+#pragma unroll
+      for (int q = 0; q < WC; ++q) {
+        if (q < nc)
+          __hip_atomic_fetch_add(rowp + r * g.pitch + col[q], (double)acc[r][q], __ATOMIC_RELAXED,
+                                 __HIP_MEMORY_SCOPE_WORKGROUP);
+      }
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < RUN_K; ++k)
+      if (cs[k] != T(0)) spread_point<T, W>(a, grid, cs[k], fx[k], fy[k]);
+  }
+}
+
+// Spread the points [begin, end) of one item into the FP64 LDS grid.
+// The grid accumulates in FP64: on gfx950 the LDS adds FP64 values many times
+// faster than FP32 ones, and the wider sum costs no accuracy.  Stored row r
+// holds fine row r mod n2 (rows n2 .. n2 + W - 1 are folded back afterwards);
+// columns wrap with the grid mask.
+template <typename T, int W, int NT>
+__device__ __forceinline__ void spread_item(const FwdArgs<T> &a, double *grid, int64_t begin, int64_t end,
+                                            T cx, T cy, T R) {
+  const T halfw = T(W) / T(2);
+  const T pr = R > T(0) ? T(M_PI) / R : T(0);
+  int64_t body0 = end, body1 = end;
+  // runs need 16-byte aligned arrays; the register window is sized for FP32 and W <= 6
+  constexpr bool kRuns = sizeof(T) == 4 && W <= 6;
+  if (kRuns && a.vec4) {
+    body0 = min(end, (begin + RUN_K - 1) / RUN_K * RUN_K);
+    body1 = max(body0, end / RUN_K * RUN_K);
+  }
+  using V = typename vec4<T>::type;
+  const V *x4 = reinterpret_cast<const V *>(a.x), *y4 = reinterpret_cast<const V *>(a.y);
+  const V *h4 = reinterpret_cast<const V *>(a.h), *w4 = reinterpret_cast<const V *>(a.w);
+  if constexpr (kRuns) for (int64_t q = body0 / RUN_K + threadIdx.x; q < body1 / RUN_K; q += NT) {
+    const V xv = x4[q], yv = y4[q], hv = h4[q], wv = w4[q];
+    const T xs[RUN_K] = {xv.x, xv.y, xv.z, xv.w}, ys[RUN_K] = {yv.x, yv.y, yv.z, yv.w};
+    const T hs[RUN_K] = {hv.x, hv.y, hv.z, hv.w}, ws[RUN_K] = {wv.x, wv.y, wv.z, wv.w};
+    T cs[RUN_K];
+#pragma unroll
+    for (int k = 0; k < RUN_K; ++k) cs[k] = ws[k] * hs[k] * hann_w(a.window_kind, xs[k], ys[k], cx, cy, R, pr);
+    spread_run<T, W>(a, grid, xs, ys, cs);
+  }
+  // points outside the aligned body, one per thread
+  const int64_t nhead = body0 - begin, ntail = end - body1;
+  for (int64_t i = threadIdx.x; i < nhead + ntail; i += NT) {
+    const int64_t j = i < nhead ? begin + i : body1 + (i - nhead);
+    const T xj = a.x[j], yj = a.y[j];
+    const T c = a.w[j] * a.h[j] * hann_w(a.window_kind, xj, yj, cx, cy, R, pr);
+    if (c == T(0)) continue;
+    spread_point<T, W>(a, grid, c, fine_coord<T>(xj, a.s1_hi, a.s1_lo, halfw),
+                       fine_coord<T>(yj, a.s2_hi, a.s2_lo, halfw));
+  }
+}
+
+// Fold stored rows n2 .. n2 + W - 1 onto rows 0 .. W - 1.
 template <int W, int NT>
 __device__ __forceinline__ void fold_rows(double *grid, const Geom &g) {
   const int pitch = g.pitch;
-  for (int i = threadIdx.x; i < (W - 1) * g.n1; i += NT) {
+  for (int i = threadIdx.x; i < W * g.n1; i += NT) {
     const int r = i / g.n1, c = i - r * g.n1;
     grid[r * pitch + c] += grid[(r + g.n2) * pitch + c];
   }
@@ -173,7 +295,7 @@ __global__ __launch_bounds__(NT) void fwd_kernel(FwdArgs<T> a) {
   __shared__ int s_item, s_last;
   const Geom &g = a.g;
   const int pitch = g.pitch;
-  const int total = (g.n2 + W - 1) * pitch;
+  const int total = (g.n2 + W) * pitch;
   const bool persistent = a.work_counter != nullptr;
   int64_t idx = a.item_base + blockIdx.x;
   if (!persistent && idx >= a.n_items) return;

@@ -18,9 +18,10 @@ hipError_t launch_adj(const AdjArgs<T> &a, int W, int blocks, int threads, size_
 template <typename T>
 hipError_t adj_occupancy(int W, int threads, size_t lds, int *blocks_per_cu);
 
-// LDS bytes of the forward kernel: the FP64 spread grid with W - 1 wrap rows.
+// LDS bytes of the forward kernel: the FP64 spread grid with W wrap rows
+// (a merged run of points spans up to W + 1 rows).
 inline size_t fwd_lds_bytes(const Geom &g, int W) {
-  return (size_t)(g.n2 + W - 1) * g.pitch * sizeof(double);
+  return (size_t)(g.n2 + W) * g.pitch * sizeof(double);
 }
 
 }  // namespace enufft

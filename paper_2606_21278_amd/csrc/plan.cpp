@@ -321,7 +321,7 @@ enufft_status enufft_plan(enufft_plan_t *out, int64_t n_cells, const int64_t *ce
   p->n_cu = prop.multiProcessorCount;
 
   // ---- forward launch shape
-  p->fwd_threads = (p->prec == ENUFFT_F64) ? 512 : 1024;
+  p->fwd_threads = 512;
   p->fwd_lds = enufft::fwd_lds_bytes(g, W);
   if (p->fwd_lds > (size_t)prop.sharedMemPerBlock) {
     free_plan(p);
@@ -499,6 +499,11 @@ FwdArgs<T> make_fwd_args(enufft_plan_t p, const void *x, const void *y, const vo
   FwdArgs<T> a{};
   a.x = (const T *)x; a.y = (const T *)y; a.h = (const T *)h; a.w = (const T *)w;
   a.f = (T *)f;
+  {
+    const size_t al = 4 * sizeof(T);
+    a.vec4 = ((uintptr_t)x % al == 0 && (uintptr_t)y % al == 0 && (uintptr_t)h % al == 0 &&
+              (uintptr_t)w % al == 0) ? 1 : 0;
+  }
   a.items = (const FwdItem *)p->d_fwd_items;
   a.n_items = (int64_t)p->fwd_items.size();
   a.item_base = 0;

@@ -94,6 +94,34 @@ def test_coordinates_fold_and_edges():
     assert rel_l2(f, ref) <= TOL["f64"]
 
 
+@pytest.mark.parametrize("shuffled", [False, True])
+def test_config3_cells_raster_and_shuffled(shuffled):
+    """Icosahedral triangles with jittered-lattice points: raster order exercises the
+    merged runs of consecutive points, shuffled order the point-by-point fallback."""
+    b = synth.config3(n_cells=8, count_scale=1.0, shuffled=shuffled)
+    print("C3 subset", b.n_points, "shuffled", shuffled, flush=True)
+    plan, gb, f = _type1(b)
+    ref = oracle_f(b.to(dtype=torch.float32))
+    e = per_cell_rel_l2(f, ref)
+    print("per-cell rel-l2 max %.3e median %.3e" % (e.max(), np.median(e)), flush=True)
+    assert e.max() <= TOL["f32"]
+
+
+def test_unaligned_point_arrays():
+    """Arrays that are not 16-byte aligned take the point-by-point path; same result."""
+    b = synth.config3(n_cells=12, count_scale=0.05)
+    gb = gpu_batch(b)
+    plan = make_plan(gb)
+    f_al = plan.type1(gb.x, gb.y, gb.h, gb.w).cpu().numpy()
+    shift = lambda t: torch.cat([t.new_zeros(1), t])[1:]
+    xs, ys, hs, ws = shift(gb.x), shift(gb.y), shift(gb.h), shift(gb.w)
+    assert xs.data_ptr() % 16 != 0
+    f_un = plan.type1(xs, ys, hs, ws).cpu().numpy()
+    ref = oracle_f(b.to(dtype=torch.float32))
+    assert per_cell_rel_l2(f_al, ref).max() <= TOL["f32"]
+    assert per_cell_rel_l2(f_un, ref).max() <= TOL["f32"]
+
+
 def test_percell_loop_matches_batched():
     b = synth.config1(count_scale=0.004, n_cells=40)
     gb = gpu_batch(b)
