@@ -121,6 +121,7 @@ typedef struct {
     int32_t fwd_threads, fwd_blocks;   /* forward launch shape */
     int32_t adj_threads, adj_blocks;
     int64_t workspace_bytes;
+    double kernel_poly_err;  /* FP32: max |polynomial - psi| of the kernel fit, 0 if the exact kernel is used */
 } enufft_plan_info;
 
 /* Fill *o with defaults: 64 x 64 modes, sigma 2, eps 1e-5, F32, Hann window,

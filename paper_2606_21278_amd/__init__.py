@@ -54,7 +54,7 @@ class PlanInfo(ctypes.Structure):
                 ("n_items_adj", ctypes.c_int64), ("adj_bands", ctypes.c_int32),
                 ("fwd_threads", ctypes.c_int32), ("fwd_blocks", ctypes.c_int32),
                 ("adj_threads", ctypes.c_int32), ("adj_blocks", ctypes.c_int32),
-                ("workspace_bytes", ctypes.c_int64)]
+                ("workspace_bytes", ctypes.c_int64), ("kernel_poly_err", ctypes.c_double)]
 
 
 EXPORTS = ["enufft_default_opts", "enufft_plan", "enufft_set_stream", "enufft_type1_batched", "enufft_ems",

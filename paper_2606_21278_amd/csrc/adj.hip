@@ -210,12 +210,10 @@ __global__ __launch_bounds__(NT) void adj_kernel(AdjArgs<T> a) {
       const FineCoord<T> fx = fine_coord<T>(xj, a.s1_hi, a.s1_lo, halfw);
       T kx[W], ky[W];
       int cp[W];
+      es_taps<T, W>(fx, a.beta, a.es, kx);
+      es_taps<T, W>(fy, a.beta, a.es, ky);
 #pragma unroll
-      for (int d = 0; d < W; ++d) {
-        kx[d] = es_eval(fx.offset(d) * zsc, a.beta);
-        ky[d] = es_eval(fy.offset(d) * zsc, a.beta);
-        cp[d] = fft_pos((fx.i0 + d) & (n1 - 1), n1);
-      }
+      for (int d = 0; d < W; ++d) cp[d] = fft_pos((fx.i0 + d) & (n1 - 1), n1);
       T u = 0, ux = 0, uy = 0;
 #pragma unroll
       for (int dy = 0; dy < W; ++dy) {
@@ -406,6 +404,7 @@ AdjArgs<T> make_adj_args(enufft_plan_t p, const void *x, const void *y, const vo
   a.beta = (T)p->beta;
   split_scale<T>(p->n1, &a.s1_hi, &a.s1_lo);
   split_scale<T>(p->n2, &a.s2_hi, &a.s2_lo);
+  a.es = p->es;
   a.bands = p->adj_bands;
   a.band_rows = p->adj_band_rows;
   a.g = p->geom;

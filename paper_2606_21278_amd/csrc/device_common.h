@@ -25,6 +25,16 @@ struct AdjItem {
   int32_t cell, band, pad0, pad1;
 };
 
+// Degree of the per-tap kernel polynomials (FP32 plans) and the largest width
+// they are fitted for; the coefficients travel by value in the kernel arguments
+// so every lane reads them from scalar registers.
+constexpr int ES_DEG = 7;
+constexpr int ES_MAXW = 8;
+struct EsPoly {
+  int on;
+  float c[ES_MAXW * (ES_DEG + 1)];   // tap-major, ascending powers of u = 2 v - 1
+};
+
 // Fine-grid and mode-box geometry.
 struct Geom {
   int n1, n2;       // fine grid (powers of two, 16..128)
@@ -53,6 +63,7 @@ struct FwdArgs {
   T beta;                    // ES shape parameter
   T s1_hi, s1_lo, s2_hi, s2_lo;   // n1 / (2 pi) and n2 / (2 pi) as hi + lo
   int vec4;                  // x, y, h, w are 16-byte aligned: load runs of 4 points
+  EsPoly es;                 // FP32 plans: per-tap kernel polynomials (es.on = 0: exact kernel)
   Geom g;
 };
 
@@ -74,6 +85,7 @@ struct AdjArgs {
   const T *tw1, *tw2;          // forward twiddles (the inverse uses their conjugates)
   T beta;
   T s1_hi, s1_lo, s2_hi, s2_lo;
+  EsPoly es;                   // as in FwdArgs
   int bands, band_rows;        // row bands per cell and rows per band
   Geom g;
 };
@@ -106,6 +118,7 @@ struct FineCoord {
   T hi, lo;
   __device__ __forceinline__ T offset(int d) const { return (T(i0 + d) - hi) - lo; }
 };
+
 template <typename T>
 __device__ __forceinline__ FineCoord<T> fine_coord(T x, T s_hi, T s_lo, T halfw) {
   FineCoord<T> c;
@@ -116,7 +129,6 @@ __device__ __forceinline__ FineCoord<T> fine_coord(T x, T s_hi, T s_lo, T halfw)
   c.i0 = (int)ceil((c.hi + c.lo) - halfw);
   return c;
 }
-
 
 // Radial Hann window W = (1 + cos(pi r / R)) / 2 for r < R, else 0, and its
 // gradient -(pi^2 / (2 R^2)) sinc(pi r / R) (x - cx, y - cy).  kind 0 is no
@@ -167,6 +179,42 @@ __device__ __forceinline__ double hann_wg(int kind, double x, double y, double c
   gx = k * dx;
   gy = k * dy;
   return 0.5 + 0.5 * c;
+}
+
+// Polynomial form of the spreading kernel.  With v = i0 - t + W/2 in [0, 1),
+// tap d sits at z = (v + d - W/2) 2 / W, a smooth function of v on the whole
+// interval; psi there is fitted (plan time, FP64 Chebyshev interpolation) by a
+// degree-ES_DEG polynomial in u = 2 v - 1.  Horner on these coefficients
+// replaces the square root, reciprocal and exponential of every tap by ES_DEG
+// fused multiply-adds.
+template <int W>
+__device__ __forceinline__ void es_taps_poly(const FineCoord<float> &c, float halfw, const EsPoly &cf,
+                                             float (&out)[W]) {
+  float v = ((float(c.i0) - c.hi) - c.lo) + halfw;
+  v = fminf(fmaxf(v, 0.0f), 1.0f);
+  const float u = 2.0f * v - 1.0f;
+#pragma unroll
+  for (int d = 0; d < W; ++d) {
+    float acc = cf.c[d * (ES_DEG + 1) + ES_DEG];
+#pragma unroll
+    for (int k = ES_DEG - 1; k >= 0; --k) acc = fmaf(acc, u, cf.c[d * (ES_DEG + 1) + k]);
+    out[d] = acc;
+  }
+}
+
+// The W kernel values of one point along one axis: polynomial form when the
+// plan provides it (FP32, W <= ES_MAXW), else the exponential of the semicircle.
+template <typename T, int W>
+__device__ __forceinline__ void es_taps(const FineCoord<T> &c, T beta, const EsPoly &cf, T (&out)[W]) {
+  if constexpr (sizeof(T) == 4 && W <= ES_MAXW) {
+    if (cf.on) {
+      es_taps_poly<W>(c, float(W) * 0.5f, cf, out);
+      return;
+    }
+  }
+  const T zsc = T(2) / T(W);
+#pragma unroll
+  for (int d = 0; d < W; ++d) out[d] = es_eval(c.offset(d) * zsc, beta);
 }
 
 // ------------------------------------------------------------------ small DFTs

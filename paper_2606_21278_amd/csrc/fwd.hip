@@ -25,12 +25,14 @@ template <typename T, int W>
 __device__ __forceinline__ void spread_point(const FwdArgs<T> &a, double *grid, T c, const FineCoord<T> &fx,
                                              const FineCoord<T> &fy) {
   const Geom &g = a.g;
-  const T zsc = T(2) / T(W);
+  T tx[W], ty[W];
+  es_taps<T, W>(fx, a.beta, a.es, tx);
+  es_taps<T, W>(fy, a.beta, a.es, ty);
   double kx[W], ky[W];
 #pragma unroll
   for (int d = 0; d < W; ++d) {
-    kx[d] = (double)es_eval(fx.offset(d) * zsc, a.beta);
-    ky[d] = (double)(c * es_eval(fy.offset(d) * zsc, a.beta));
+    kx[d] = (double)tx[d];
+    ky[d] = (double)(c * ty[d]);
   }
   int col[W];
 #pragma unroll
@@ -84,11 +86,10 @@ __device__ __forceinline__ void spread_run(const FwdArgs<T> &a, double *grid, co
     for (int k = 0; k < RUN_K; ++k) {
       if (cs[k] == T(0)) continue;
       T kx[W], ky[W];
+      es_taps<T, W>(fx[k], a.beta, a.es, kx);
+      es_taps<T, W>(fy[k], a.beta, a.es, ky);
 #pragma unroll
-      for (int d = 0; d < W; ++d) {
-        kx[d] = es_eval(fx[k].offset(d) * zsc, a.beta);
-        ky[d] = cs[k] * es_eval(fy[k].offset(d) * zsc, a.beta);
-      }
+      for (int d = 0; d < W; ++d) ky[d] *= cs[k];
       const int sx = fx[k].i0 - cmin, sy = fy[k].i0 - rmin;
       T KX[WC], KY[WR];
 #pragma unroll
@@ -112,20 +113,18 @@ __device__ __forceinline__ void spread_run(const FwdArgs<T> &a, double *grid, co
 #pragma unroll
         for (int q = 0; q < WC; ++q) acc[r][q] += KY[r] * KX[q];
     }
+    // flush the whole window (cells outside every footprint add zero); no
+    // per-cell branches, so the adds issue back to back
     int col[WC];
 #pragma unroll
     for (int q = 0; q < WC; ++q) col[q] = (cmin + q) & (g.n1 - 1);
     double *rowp = grid + (rmin & (g.n2 - 1)) * g.pitch;
-    const int nr = W + (rmax - rmin), nc = W + (cmax - cmin);
 #pragma unroll
     for (int r = 0; r < WR; ++r) {
-      if (r >= nr) break;
 #pragma unroll
-      for (int q = 0; q < WC; ++q) {
-        if (q < nc)
-          __hip_atomic_fetch_add(rowp + r * g.pitch + col[q], (double)acc[r][q], __ATOMIC_RELAXED,
-                                 __HIP_MEMORY_SCOPE_WORKGROUP);
-      }
+      for (int q = 0; q < WC; ++q)
+        __hip_atomic_fetch_add(rowp + r * g.pitch + col[q], (double)acc[r][q], __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_WORKGROUP);
     }
   } else {
 #pragma unroll
@@ -154,14 +153,32 @@ __device__ __forceinline__ void spread_item(const FwdArgs<T> &a, double *grid, i
   using V = typename vec4<T>::type;
   const V *x4 = reinterpret_cast<const V *>(a.x), *y4 = reinterpret_cast<const V *>(a.y);
   const V *h4 = reinterpret_cast<const V *>(a.h), *w4 = reinterpret_cast<const V *>(a.w);
-  if constexpr (kRuns) for (int64_t q = body0 / RUN_K + threadIdx.x; q < body1 / RUN_K; q += NT) {
-    const V xv = x4[q], yv = y4[q], hv = h4[q], wv = w4[q];
+  if constexpr (kRuns) {
+    // Group-to-lane map: in each block of NT consecutive groups, wave w takes
+    // groups w, w + NW, w + 2 NW, ...  Lanes of one wave then hold groups NW
+    // runs (4 NW points) apart, so the windows they add in the same instruction
+    // start at different grid cells even when many points share a cell (LDS
+    // atomics on one address serialise); the NW waves together still consume
+    // every cache line of the block.  Software pipeline: the next block's loads
+    // are in flight while this one spreads.
+    constexpr int NW = NT / 64;
+    const int lane_off = (threadIdx.x & 63) * NW + (threadIdx.x >> 6);
+    const int64_t q1 = body1 / RUN_K;
+    int64_t q = body0 / RUN_K + lane_off;
+    V xn{}, yn{}, hn{}, wn{};
+    if (q < q1) { xn = x4[q]; yn = y4[q]; hn = h4[q]; wn = w4[q]; }
+    for (int64_t qb = body0 / RUN_K; qb < q1; qb += NT, q += NT) {
+    const bool live = q < q1;
+    const V xv = xn, yv = yn, hv = hn, wv = wn;
+    if (q + NT < q1) { xn = x4[q + NT]; yn = y4[q + NT]; hn = h4[q + NT]; wn = w4[q + NT]; }
+    if (!live) continue;
     const T xs[RUN_K] = {xv.x, xv.y, xv.z, xv.w}, ys[RUN_K] = {yv.x, yv.y, yv.z, yv.w};
     const T hs[RUN_K] = {hv.x, hv.y, hv.z, hv.w}, ws[RUN_K] = {wv.x, wv.y, wv.z, wv.w};
     T cs[RUN_K];
 #pragma unroll
     for (int k = 0; k < RUN_K; ++k) cs[k] = ws[k] * hs[k] * hann_w(a.window_kind, xs[k], ys[k], cx, cy, R, pr);
     spread_run<T, W>(a, grid, xs, ys, cs);
+    }
   }
   // points outside the aligned body, one per thread
   const int64_t nhead = body0 - begin, ntail = end - body1;

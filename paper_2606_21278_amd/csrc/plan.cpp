@@ -126,6 +126,52 @@ std::vector<double> kernel_ft(int W, double beta, int n, int kmax) {
   return p;
 }
 
+// psi(z) = exp(beta (sqrt(1 - z^2) - 1)), zero for |z| > 1.
+double es_host(double z, double beta) {
+  if (std::fabs(z) > 1.0) return 0.0;
+  return std::exp(-beta * z * z / (1.0 + std::sqrt(1.0 - z * z)));
+}
+
+// Per-tap polynomials of the kernel in u = 2 v - 1, v = i0 - t + W/2 in [0, 1):
+// Chebyshev interpolation at deg + 1 nodes, converted to monomial coefficients
+// (ascending).  Returns the largest deviation from psi on a fine sample.
+double fit_es_poly(int W, double beta, int deg, std::vector<double> &coef) {
+  coef.assign((size_t)W * (deg + 1), 0.0);
+  double maxerr = 0.0;
+  const int n = deg + 1;
+  for (int d = 0; d < W; ++d) {
+    std::vector<double> cheb(n, 0.0), yn(n), un(n);
+    for (int i = 0; i < n; ++i) {
+      un[i] = std::cos(M_PI * (i + 0.5) / n);
+      yn[i] = es_host(((0.5 * (un[i] + 1.0)) + d - 0.5 * W) * 2.0 / W, beta);
+    }
+    for (int j = 0; j < n; ++j) {
+      double s = 0.0;
+      for (int i = 0; i < n; ++i) s += yn[i] * std::cos(j * M_PI * (i + 0.5) / n);
+      cheb[j] = (j == 0 ? 1.0 : 2.0) * s / n;
+    }
+    // Chebyshev -> monomial: T_0 = 1, T_1 = u, T_{j+1} = 2 u T_j - T_{j-1}
+    std::vector<std::vector<double>> Tm(n, std::vector<double>(n, 0.0));
+    Tm[0][0] = 1.0;
+    if (n > 1) Tm[1][1] = 1.0;
+    for (int j = 1; j + 1 < n; ++j)
+      for (int k = 0; k < n; ++k) {
+        double v = -Tm[j - 1][k];
+        if (k > 0) v += 2.0 * Tm[j][k - 1];
+        Tm[j + 1][k] = v;
+      }
+    for (int j = 0; j < n; ++j)
+      for (int k = 0; k < n; ++k) coef[(size_t)d * n + k] += cheb[j] * Tm[j][k];
+    for (int i = 0; i <= 2000; ++i) {
+      const double v = i / 2000.0, u = 2.0 * v - 1.0;
+      double acc = coef[(size_t)d * n + deg];
+      for (int k = deg - 1; k >= 0; --k) acc = acc * u + coef[(size_t)d * n + k];
+      maxerr = std::max(maxerr, std::fabs(acc - es_host((v + d - 0.5 * W) * 2.0 / W, beta)));
+    }
+  }
+  return maxerr;
+}
+
 int64_t alloc_cap_bytes() {
   const char *s = std::getenv("ENUFFT_ALLOC_CAP_MB");
   if (!s || !*s) return -1;
@@ -379,6 +425,18 @@ enufft_status enufft_plan(enufft_plan_t *out, int64_t n_cells, const int64_t *ce
     if (st != ENUFFT_OK) { std::string m = p->last_error; free_plan(p); return fail(nullptr, st, m); }
   }
 
+  // FP32 plans evaluate the kernel as per-tap polynomials when the fit is far
+  // below the requested accuracy (it is for the compiled widths 4..8).
+  if (p->prec == ENUFFT_F32 && W <= enufft::ES_MAXW) {
+    std::vector<double> cf;
+    const double err = fit_es_poly(W, beta, enufft::ES_DEG, cf);
+    if (err <= std::max(0.1 * opts->eps, 1e-6)) {
+      p->es_poly_err = err;
+      p->es.on = 1;
+      for (size_t i = 0; i < cf.size(); ++i) p->es.c[i] = (float)cf[i];
+    }
+  }
+
   std::vector<double> win(3 * std::max<int64_t>(1, n_cells), 0.0);
   for (int64_t c = 0; c < n_cells; ++c) {
     if (windows) { win[3 * c] = windows[c].cx; win[3 * c + 1] = windows[c].cy; win[3 * c + 2] = windows[c].radius; }
@@ -432,6 +490,7 @@ enufft_status enufft_get_info(enufft_plan_t p, enufft_plan_info *info) {
   info->fwd_threads = p->fwd_threads; info->fwd_blocks = p->fwd_blocks;
   info->adj_threads = p->adj_threads; info->adj_blocks = p->adj_blocks;
   info->workspace_bytes = p->workspace_bytes;
+  info->kernel_poly_err = p->es_poly_err;
   return ENUFFT_OK;
 }
 
@@ -518,6 +577,7 @@ FwdArgs<T> make_fwd_args(enufft_plan_t p, const void *x, const void *y, const vo
   a.beta = (T)p->beta;
   split_scale<T>(p->n1, &a.s1_hi, &a.s1_lo);
   split_scale<T>(p->n2, &a.s2_hi, &a.s2_lo);
+  a.es = p->es;
   a.g = p->geom;
   return a;
 }

@@ -58,6 +58,8 @@ struct enufft_plan_s {
   int *d_cell_counters = nullptr;
   void *d_partial = nullptr;
   void *d_decon_x = nullptr, *d_decon_y = nullptr, *d_tw1 = nullptr, *d_tw2 = nullptr;
+  enufft::EsPoly es{};             // FP32 plans: kernel polynomial coefficients (es.on = 0: exact)
+  double es_poly_err = 0.0;        // max |poly - psi| over the fit interval
   enufft::UnitTable units[2][2];
   int64_t workspace_bytes = 0;
   std::vector<void *> allocations;
