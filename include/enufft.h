@@ -79,7 +79,12 @@ typedef struct { double cx, cy, radius; } enufft_window;
  *   window_kind enufft_window_kind.
  *   scale     overall factor on f (1 / |D| reproduces eq. (discrete_quadrature)).
  *   autotune  0: default launch shape; 1: timed trials at plan time on synthetic
- *             points with the plan's cell sizes (synchronises the stream).
+ *             points with the plan's cell sizes (synchronises the stream; allocates
+ *             trial buffers of up to 2^27 points, env ENUFFT_TUNE_MAX_POINTS,
+ *             using a prefix of the cells beyond that).  The choice is cached
+ *             in the file ENUFFT_TUNE_CACHE ("off" disables; default
+ *             $HOME/.cache/enufft/tune_cache.txt) keyed by device, shape and
+ *             the exact cell layout.
  *   kernel_width 0: from eps; otherwise a width >= the eps-derived one. */
 typedef struct {
     int32_t n_modes[2];
@@ -122,6 +127,13 @@ typedef struct {
     int32_t adj_threads, adj_blocks;
     int64_t workspace_bytes;
     double kernel_poly_err;  /* FP32: max |polynomial - psi| of the kernel fit, 0 if the exact kernel is used */
+    int32_t tuned;           /* 1 if the autotuner set the launch shape */
+    int32_t tune_cache_hit;  /* 1 if that choice came from the on-disk cache */
+    int64_t fwd_chunk_min;   /* smallest forward work item (points) */
+    int32_t fwd_items_per_slot, adj_items_per_slot;  /* work items per resident workgroup */
+    int32_t adj_band_mult;   /* adjoint row bands = this x the fewest that fit LDS */
+    int32_t reserved_;
+    double tune_fwd_ms, tune_adj_ms;   /* best trial times of the autotuner */
 } enufft_plan_info;
 
 /* Fill *o with defaults: 64 x 64 modes, sigma 2, eps 1e-5, F32, Hann window,
@@ -197,13 +209,22 @@ enufft_status enufft_percell_loop(enufft_plan_t p, const void *x, const void *y,
                                   const double *mode_weight, uint8_t *keep, int32_t *k_star,
                                   double *stats);
 
+/* Type-1 + EMS (enufft_type1_batched then enufft_ems) recorded once as a HIP
+ * graph and replayed on the plan's stream: one graph launch per call.  The
+ * graph is re-captured when any pointer or EMS parameter differs from the last
+ * call.  Arguments as enufft_type1_batched and enufft_ems. */
+enufft_status enufft_forward_graph(enufft_plan_t p, const void *x, const void *y, const void *h,
+                                   const void *w, void *f, const enufft_ems_params *prm,
+                                   const double *mode_weight, uint8_t *keep, int32_t *k_star,
+                                   double *stats);
+
 /* Record HIP events around every main-kernel launch (enable = 1), or stop (0). */
 enufft_status enufft_set_timing(enufft_plan_t p, int32_t enable);
 
-/* Synchronise on the recorded events and return, per kernel kind, the summed
- * launch durations in ms and the launch counts: out[0..2] = ms of type-1, EMS,
- * adjoint; out[3..5] = launch counts.  Clears the record. */
-enufft_status enufft_get_timing(enufft_plan_t p, double *out6);
+/* Synchronise on the recorded events and return, per kind, the summed
+ * durations in ms and the counts: out[0..3] = ms of type-1, EMS, adjoint and
+ * forward-graph launches; out[4..7] = their counts.  Clears the record. */
+enufft_status enufft_get_timing(enufft_plan_t p, double *out8);
 
 enufft_status enufft_get_info(enufft_plan_t p, enufft_plan_info *info);
 

@@ -54,11 +54,15 @@ class PlanInfo(ctypes.Structure):
                 ("n_items_adj", ctypes.c_int64), ("adj_bands", ctypes.c_int32),
                 ("fwd_threads", ctypes.c_int32), ("fwd_blocks", ctypes.c_int32),
                 ("adj_threads", ctypes.c_int32), ("adj_blocks", ctypes.c_int32),
-                ("workspace_bytes", ctypes.c_int64), ("kernel_poly_err", ctypes.c_double)]
+                ("workspace_bytes", ctypes.c_int64), ("kernel_poly_err", ctypes.c_double),
+                ("tuned", ctypes.c_int32), ("tune_cache_hit", ctypes.c_int32), ("fwd_chunk_min", ctypes.c_int64),
+                ("fwd_items_per_slot", ctypes.c_int32), ("adj_items_per_slot", ctypes.c_int32),
+                ("adj_band_mult", ctypes.c_int32), ("reserved_", ctypes.c_int32),
+                ("tune_fwd_ms", ctypes.c_double), ("tune_adj_ms", ctypes.c_double)]
 
 
 EXPORTS = ["enufft_default_opts", "enufft_plan", "enufft_set_stream", "enufft_type1_batched", "enufft_ems",
-           "enufft_type1_adjoint", "enufft_retained_power_adjoint", "enufft_percell_loop", "enufft_set_timing", "enufft_get_timing",
+           "enufft_type1_adjoint", "enufft_retained_power_adjoint", "enufft_percell_loop", "enufft_forward_graph", "enufft_set_timing", "enufft_get_timing",
            "enufft_get_info", "enufft_destroy", "enufft_last_error", "enufft_version"]
 
 _lib = None
@@ -83,6 +87,7 @@ def load_library(path: str = LIB_PATH):
     L.enufft_type1_adjoint.argtypes = [vp] * 9
     L.enufft_retained_power_adjoint.argtypes = [vp] * 11
     L.enufft_percell_loop.argtypes = [vp] * 6 + [ctypes.POINTER(EmsParamsC), vp, vp, vp, vp]
+    L.enufft_forward_graph.argtypes = [vp] * 6 + [ctypes.POINTER(EmsParamsC), vp, vp, vp, vp]
     L.enufft_set_timing.argtypes = [vp, i32]
     L.enufft_get_timing.argtypes = [vp, dp]
     L.enufft_get_info.argtypes = [vp, ctypes.POINTER(PlanInfo)]
@@ -256,14 +261,33 @@ class Plan:
                                              _ptr(keep), _ptr(ks), _ptr(st)), self._h)
         return f, keep, ks, st
 
+    def forward_graph(self, x, y, h, w, params: EmsParams = EmsParams(), out=None, mode_weight=None):
+        """Type-1 + EMS replayed as one captured HIP graph.  Reusing the same output
+        tensors (pass ``out=(f, keep, k_star, stats)``) replays without re-capture."""
+        self._pts(x, y, h, w)
+        if out is None:
+            f = self.empty_modes()
+            keep = torch.empty(f.shape, dtype=torch.uint8, device=self.device)
+            ks = torch.empty(self.n_cells, dtype=torch.int32, device=self.device)
+            st = torch.empty((self.n_cells, 8), dtype=torch.float64, device=self.device)
+        else:
+            f, keep, ks, st = out
+        mw = None if mode_weight is None else mode_weight.to(device=self.device, dtype=torch.float64).contiguous()
+        prm = params.c()
+        self._sync_stream()
+        _check(self._lib.enufft_forward_graph(self._h, _ptr(x), _ptr(y), _ptr(h), _ptr(w), _ptr(f), ctypes.byref(prm),
+                                              _ptr(mw), _ptr(keep), _ptr(ks), _ptr(st)), self._h)
+        return f, keep, ks, st
+
     def set_timing(self, enable: bool):
         _check(self._lib.enufft_set_timing(self._h, int(enable)), self._h)
 
     def get_timing(self) -> dict:
-        out = (ctypes.c_double * 6)()
+        out = (ctypes.c_double * 8)()
         _check(self._lib.enufft_get_timing(self._h, out), self._h)
-        return {"type1_ms": out[0], "ems_ms": out[1], "adjoint_ms": out[2],
-                "type1_launches": int(out[3]), "ems_launches": int(out[4]), "adjoint_launches": int(out[5])}
+        return {"type1_ms": out[0], "ems_ms": out[1], "adjoint_ms": out[2], "graph_ms": out[3],
+                "type1_launches": int(out[4]), "ems_launches": int(out[5]), "adjoint_launches": int(out[6]),
+                "graph_launches": int(out[7])}
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:

@@ -306,7 +306,8 @@ int choose_bands(const Geom &g, int W, size_t elem, size_t lds_max, int *band_ro
 void build_adj_schedule(enufft_plan_t p, int slots) {
   const int64_t Q = p->n_points;
   const int B = p->adj_bands;
-  const int64_t T = std::max<int64_t>(16384, (Q * B + 2LL * slots - 1) / std::max(1, 2 * slots));
+  const int64_t per = (int64_t)p->adj_items_per_slot * std::max(1, slots);
+  const int64_t T = std::max<int64_t>(16384, (Q * B + per - 1) / per);
   p->adj_items.clear();
   for (int64_t c = 0; c < p->n_cells; ++c) {
     const int64_t a = p->offsets[c], b = p->offsets[c + 1];
@@ -337,6 +338,13 @@ hipError_t adj_occ(int W, int threads, size_t lds, int *per_cu) {
   return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, fn, threads, lds);
 }
 
+// Release the adjoint schedule so the next call rebuilds it (autotuner).
+void adj_reset(enufft_plan_t p) {
+  if (!p->d_adj_items) return;
+  dev_release(p, &p->d_adj_items, std::max<size_t>(1, p->adj_items.size()) * sizeof(AdjItem));
+  p->adj_items.clear();
+}
+
 // Lazily set up the adjoint schedule on first use.
 enufft_status adj_prepare(enufft_plan_t p) {
   if (p->d_adj_items) return ENUFFT_OK;
@@ -347,10 +355,16 @@ enufft_status adj_prepare(enufft_plan_t p) {
     return ENUFFT_EDEVICE;
   }
   p->adj_threads = p->prec == ENUFFT_F64 ? 256 : 512;
-  const int B = choose_bands(p->geom, p->W, p->elem, (size_t)prop.sharedMemPerBlock, &p->adj_band_rows, &p->adj_lds);
+  int B = choose_bands(p->geom, p->W, p->elem, (size_t)prop.sharedMemPerBlock, &p->adj_band_rows, &p->adj_lds);
   if (B == 0) {
     p->last_error = "adjoint: fine-grid bands do not fit in LDS";
     return ENUFFT_EUNSUPPORTED;
+  }
+  // more bands than the minimum (autotuner choice): smaller LDS footprint per item
+  for (int m = p->adj_band_mult; m > 1 && p->geom.n2 / (B * 2) >= 2; m >>= 1) {
+    B *= 2;
+    p->adj_band_rows = p->geom.n2 / B;
+    p->adj_lds = adj_layout(p->geom, p->W, p->adj_band_rows).total * p->elem;
   }
   p->adj_bands = B;
   int per_cu = 0;

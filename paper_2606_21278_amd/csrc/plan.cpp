@@ -201,6 +201,9 @@ std::vector<T> cast_vec(const std::vector<double> &v) {
 
 void free_plan(enufft_plan_t p) {
   if (!p) return;
+  if (p->graph_exec) (void)hipGraphExecDestroy(p->graph_exec);
+  if (p->graph) (void)hipGraphDestroy(p->graph);
+  if (p->capture_stream) (void)hipStreamDestroy(p->capture_stream);
   for (void *a : p->allocations) (void)hipFree(a);
   for (size_t i = 0; i < p->tim.start.size(); ++i) {
     (void)hipEventDestroy(p->tim.start[i]);
@@ -224,13 +227,26 @@ bool check_gfx950(std::string *name) {
 
 namespace enufft {
 
+enufft_status autotune(enufft_plan_t p);
+
+// Free one workspace allocation made by dev_alloc (no-op for NULL).
+void dev_release(enufft_plan_t p, void **ptr, size_t bytes) {
+  if (!*ptr) return;
+  for (auto it = p->allocations.begin(); it != p->allocations.end(); ++it)
+    if (*it == *ptr) { p->allocations.erase(it); break; }
+  (void)hipFree(*ptr);
+  *ptr = nullptr;
+  p->workspace_bytes -= (int64_t)(bytes == 0 ? 16 : bytes);
+}
+
 // Forward work list.  Target chunk size T keeps roughly two items per resident
 // workgroup so the largest cells do not leave CUs idle; cells above T are cut
 // into near-equal chunks whose partial grids are merged.  The batched list is
 // ordered by decreasing size (longest first), the per-cell list by cell.
 void build_fwd_schedule(enufft_plan_t p, int slots) {
   const int64_t Q = p->n_points;
-  const int64_t T = std::max<int64_t>(16384, (Q + 2LL * slots - 1) / std::max(1, 2 * slots));
+  const int64_t per = (int64_t)p->fwd_items_per_slot * std::max(1, slots);
+  const int64_t T = std::max<int64_t>(p->fwd_chunk_min, (Q + per - 1) / per);
   p->fwd_items.clear();
   p->fwd_items_cell.clear();
   p->fwd_cell_first.assign(p->n_cells + 1, 0);
@@ -258,6 +274,32 @@ void build_fwd_schedule(enufft_plan_t p, int slots) {
   });
   p->n_slots = slot;
   p->n_split = nsplit;
+}
+
+// (Re)build the forward schedule for the plan's launch-shape parameters and
+// replace its device copies (item lists and the partial grids of split cells).
+enufft_status install_fwd_schedule(enufft_plan_t p) {
+  dev_release(p, &p->d_fwd_items, std::max<size_t>(1, p->fwd_items.size()) * sizeof(FwdItem));
+  dev_release(p, &p->d_fwd_items_cell, std::max<size_t>(1, p->fwd_items_cell.size()) * sizeof(FwdItem));
+  dev_release(p, &p->d_partial, std::max<int64_t>(1, p->n_slots) * (size_t)p->n1 * p->n2 * p->elem);
+  build_fwd_schedule(p, p->fwd_slots);
+  p->fwd_blocks = (int)std::min<int64_t>((int64_t)p->fwd_slots, std::max<int64_t>(1, (int64_t)p->fwd_items.size()));
+  enufft_status st = dev_alloc(p, &p->d_fwd_items, std::max<size_t>(1, p->fwd_items.size()) * sizeof(FwdItem),
+                               "forward items");
+  if (st == ENUFFT_OK)
+    st = dev_alloc(p, &p->d_fwd_items_cell, std::max<size_t>(1, p->fwd_items_cell.size()) * sizeof(FwdItem),
+                   "forward items by cell");
+  if (st == ENUFFT_OK)
+    st = dev_alloc(p, &p->d_partial, std::max<int64_t>(1, p->n_slots) * (size_t)p->n1 * p->n2 * p->elem,
+                   "partial grids");
+  if (st != ENUFFT_OK) return st;
+  hipError_t e = hipSuccess;
+  if (!p->fwd_items.empty())
+    e = hipMemcpy(p->d_fwd_items, p->fwd_items.data(), p->fwd_items.size() * sizeof(FwdItem), hipMemcpyHostToDevice);
+  if (e == hipSuccess && !p->fwd_items_cell.empty())
+    e = hipMemcpy(p->d_fwd_items_cell, p->fwd_items_cell.data(), p->fwd_items_cell.size() * sizeof(FwdItem),
+                  hipMemcpyHostToDevice);
+  return e == hipSuccess ? ENUFFT_OK : hip_fail(p, e, "upload forward items");
 }
 
 }  // namespace enufft
@@ -353,6 +395,8 @@ enufft_status enufft_plan(enufft_plan_t *out, int64_t n_cells, const int64_t *ce
   p->prec = opts->precision; p->window_kind = opts->window_kind;
   p->elem = p->prec == ENUFFT_F64 ? 8 : 4;
   p->stream = (hipStream_t)hip_stream;
+  p->opts = *opts;
+  if (windows) p->windows_host.assign(windows, windows + n_cells);
   Geom &g = p->geom;
   g.n1 = n1; g.n2 = n2; g.N1 = N1; g.N2 = N2;
   g.lo1 = -(N1 / 2); g.lo2 = -(N2 / 2);
@@ -382,9 +426,7 @@ enufft_status enufft_plan(enufft_plan_t *out, int64_t n_cells, const int64_t *ce
     free_plan(p);
     return st;
   }
-  const int slots = p->n_cu * per_cu;
-  enufft::build_fwd_schedule(p, slots);
-  p->fwd_blocks = (int)std::min<int64_t>((int64_t)slots, std::max<int64_t>(1, (int64_t)p->fwd_items.size()));
+  p->fwd_slots = p->n_cu * per_cu;
 
   // ---- tables (FP64 on the host, rounded to the compute precision)
   const int Kx = g.K1, Ky = g.K2;
@@ -443,20 +485,20 @@ enufft_status enufft_plan(enufft_plan_t *out, int64_t n_cells, const int64_t *ce
   }
   ALLOC(p->d_windows, win.size() * sizeof(double), "windows");
   UPLOAD(p->d_windows, win.data(), win.size() * sizeof(double), "upload windows");
-  ALLOC(p->d_fwd_items, std::max<size_t>(1, p->fwd_items.size()) * sizeof(FwdItem), "forward items");
-  if (!p->fwd_items.empty()) UPLOAD(p->d_fwd_items, p->fwd_items.data(), p->fwd_items.size() * sizeof(FwdItem), "upload items");
-  ALLOC(p->d_fwd_items_cell, std::max<size_t>(1, p->fwd_items_cell.size()) * sizeof(FwdItem), "forward items by cell");
-  if (!p->fwd_items_cell.empty())
-    UPLOAD(p->d_fwd_items_cell, p->fwd_items_cell.data(), p->fwd_items_cell.size() * sizeof(FwdItem), "upload items");
+  st = enufft::install_fwd_schedule(p);
+  if (st != ENUFFT_OK) { std::string m = p->last_error; free_plan(p); return fail(nullptr, st, m); }
   ALLOC(p->d_counters, 16 * sizeof(int), "counters");
   ALLOC(p->d_cell_counters, std::max<int64_t>(1, n_cells) * sizeof(int), "cell counters");
-  ALLOC(p->d_partial, std::max<int64_t>(1, p->n_slots) * (size_t)n1 * n2 * p->elem, "partial grids");
   e = hipMemset(p->d_counters, 0, 16 * sizeof(int));
   if (e == hipSuccess) e = hipMemset(p->d_cell_counters, 0, std::max<int64_t>(1, n_cells) * sizeof(int));
   if (e == hipSuccess) e = hipDeviceSynchronize();
   if (e != hipSuccess) { st = hip_fail(p, e, "zero counters"); std::string m = p->last_error; free_plan(p); return fail(nullptr, st, m); }
 #undef ALLOC
 #undef UPLOAD
+  if (opts->autotune) {
+    st = enufft::autotune(p);
+    if (st != ENUFFT_OK) { std::string m = p->last_error; free_plan(p); return fail(nullptr, st, m); }
+  }
   *out = p;
   return ENUFFT_OK;
 }
@@ -491,6 +533,14 @@ enufft_status enufft_get_info(enufft_plan_t p, enufft_plan_info *info) {
   info->adj_threads = p->adj_threads; info->adj_blocks = p->adj_blocks;
   info->workspace_bytes = p->workspace_bytes;
   info->kernel_poly_err = p->es_poly_err;
+  info->tuned = p->tuned;
+  info->tune_cache_hit = p->tune_cache_hit;
+  info->fwd_chunk_min = p->fwd_chunk_min;
+  info->fwd_items_per_slot = p->fwd_items_per_slot;
+  info->adj_items_per_slot = p->adj_items_per_slot;
+  info->adj_band_mult = p->adj_band_mult;
+  info->tune_fwd_ms = p->tune_fwd_ms;
+  info->tune_adj_ms = p->tune_adj_ms;
   return ENUFFT_OK;
 }
 
@@ -500,17 +550,18 @@ enufft_status enufft_set_timing(enufft_plan_t p, int32_t enable) {
   return ENUFFT_OK;
 }
 
-enufft_status enufft_get_timing(enufft_plan_t p, double *out6) {
-  if (!p || !out6) return fail(p, ENUFFT_EINVAL, "enufft_get_timing: null argument");
-  for (int i = 0; i < 6; ++i) out6[i] = 0.0;
+enufft_status enufft_get_timing(enufft_plan_t p, double *out8) {
+  if (!p || !out8) return fail(p, ENUFFT_EINVAL, "enufft_get_timing: null argument");
+  double *out6 = out8;
+  for (int i = 0; i < 8; ++i) out8[i] = 0.0;
   enufft_status st = ENUFFT_OK;
   for (size_t i = 0; i < p->tim.start.size(); ++i) {
     float ms = 0.f;
     hipError_t e = hipEventSynchronize(p->tim.stop[i]);
     if (e == hipSuccess) e = hipEventElapsedTime(&ms, p->tim.start[i], p->tim.stop[i]);
     if (e != hipSuccess && st == ENUFFT_OK) st = hip_fail(p, e, "event timing");
-    out6[p->tim.kind[i]] += ms;
-    out6[3 + p->tim.kind[i]] += 1.0;
+    out8[p->tim.kind[i]] += ms;
+    out8[4 + p->tim.kind[i]] += 1.0;
     (void)hipEventDestroy(p->tim.start[i]);
     (void)hipEventDestroy(p->tim.stop[i]);
   }
@@ -670,4 +721,64 @@ extern "C" enufft_status enufft_percell_loop(enufft_plan_t p, const void *x, con
     }
   }
   return ENUFFT_OK;
+}
+
+// ---------------------------------------------------------------------- graph
+
+namespace {
+void key_append(std::vector<uint8_t> &k, const void *ptr, size_t n) {
+  const uint8_t *b = (const uint8_t *)ptr;
+  k.insert(k.end(), b, b + n);
+}
+}  // namespace
+
+// Type-1 + EMS as one captured graph.  The two launches (the persistent
+// forward kernel and the per-cell EMS kernel) are recorded once on a private
+// stream and replayed on the plan's stream; nothing in them needs a memset
+// (the forward's work counters reset themselves), so replays are independent.
+// A call with different pointers or EMS parameters re-captures.
+extern "C" enufft_status enufft_forward_graph(enufft_plan_t p, const void *x, const void *y, const void *h,
+                                              const void *w, void *f, const enufft_ems_params *prm,
+                                              const double *mode_weight, uint8_t *keep, int32_t *k_star,
+                                              double *stats) {
+  enufft_status st = enufft::check_plan(p, "enufft_forward_graph");
+  if (st != ENUFFT_OK) return st;
+  if (p->n_cells == 0) return ENUFFT_OK;
+  if (!f) return fail(p, ENUFFT_EINVAL, "enufft_forward_graph: null f");
+  if (p->n_points > 0 && (!x || !y || !h || !w)) return fail(p, ENUFFT_EINVAL, "enufft_forward_graph: null point array");
+  st = enufft::ems_validate(p, f, prm, keep, k_star, stats);
+  if (st != ENUFFT_OK) return st;
+  std::vector<uint8_t> key;
+  const void *ptrs[] = {x, y, h, w, f, mode_weight, keep, k_star, stats};
+  key_append(key, ptrs, sizeof(ptrs));
+  key_append(key, prm, sizeof(*prm));
+  if (!p->graph_exec || key != p->graph_key) {
+    if (!p->capture_stream) HIP_TRY(p, hipStreamCreateWithFlags(&p->capture_stream, hipStreamNonBlocking), "capture stream");
+    if (p->graph_exec) { (void)hipGraphExecDestroy(p->graph_exec); p->graph_exec = nullptr; }
+    if (p->graph) { (void)hipGraphDestroy(p->graph); p->graph = nullptr; }
+    HIP_TRY(p, hipStreamBeginCapture(p->capture_stream, hipStreamCaptureModeThreadLocal), "begin capture");
+    hipStream_t user = p->stream;
+    const bool timing = p->timing;
+    p->stream = p->capture_stream;
+    p->timing = false;
+    enufft_status s1 = enufft_type1_batched(p, x, y, h, w, f);
+    enufft_status s2 = s1 == ENUFFT_OK ? enufft::ems_launch(p, f, prm, mode_weight, keep, k_star, stats, 0, p->n_cells)
+                                       : s1;
+    p->stream = user;
+    p->timing = timing;
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(p->capture_stream, &g);
+    if (s2 != ENUFFT_OK) { if (g) (void)hipGraphDestroy(g); return s2; }
+    if (e != hipSuccess) return hip_fail(p, e, "end capture");
+    p->graph = g;
+    HIP_TRY(p, hipGraphInstantiate(&p->graph_exec, g, nullptr, nullptr, 0), "graph instantiate");
+    p->graph_key = key;
+    ++p->graph_captures;
+  }
+  hipEvent_t ev;
+  st = enufft::record_start(p, 3, &ev);
+  if (st != ENUFFT_OK) return st;
+  HIP_TRY(p, hipGraphLaunch(p->graph_exec, p->stream), "graph launch");
+  ++p->graph_launches;
+  return enufft::record_stop(p, 3, ev);
 }

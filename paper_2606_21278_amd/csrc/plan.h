@@ -36,13 +36,23 @@ struct enufft_plan_s {
   int device = 0, n_cu = 0;
   enufft::Geom geom{};
   std::vector<int64_t> offsets;
+  enufft_opts opts{};              // as given to enufft_plan
+  std::vector<enufft_window> windows_host;
+
+  // launch-shape parameters (defaults, or chosen by the autotuner)
+  int64_t fwd_chunk_min = 16384;   // smallest forward work item (points)
+  int fwd_items_per_slot = 2;      // target forward items per resident workgroup
+  int adj_items_per_slot = 2;      // same for the adjoint
+  int adj_band_mult = 1;           // adjoint bands = mult x the fewest that fit LDS
+  bool tuned = false, tune_cache_hit = false;
+  double tune_fwd_ms = 0.0, tune_adj_ms = 0.0;   // best trial times (ms)
 
   // forward schedule
   std::vector<enufft::FwdItem> fwd_items;        // descending size (batched launch)
   std::vector<enufft::FwdItem> fwd_items_cell;   // grouped by cell (per-cell loop)
   std::vector<int64_t> fwd_cell_first;           // per cell: first index in fwd_items_cell (+ n_cells sentinel)
   int64_t n_slots = 0, n_split = 0;
-  int fwd_threads = 512, fwd_blocks = 0;
+  int fwd_threads = 512, fwd_blocks = 0, fwd_slots = 0;
   size_t fwd_lds = 0;
 
   // adjoint schedule
@@ -64,9 +74,24 @@ struct enufft_plan_s {
   int64_t workspace_bytes = 0;
   std::vector<void *> allocations;
 
+  // captured forward (type-1 + EMS) graph and the arguments it was captured with
+  hipStream_t capture_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  std::vector<uint8_t> graph_key;
+  int64_t graph_launches = 0, graph_captures = 0;
+
   // state
   bool faulted = false;
   std::string last_error;
   bool timing = false;
   enufft::Timing tim;
 };
+
+namespace enufft {
+// Workspace helpers shared by the translation units (defined with the plan).
+void dev_release(enufft_plan_t p, void **ptr, size_t bytes);
+enufft_status install_fwd_schedule(enufft_plan_t p);
+void adj_reset(enufft_plan_t p);
+enufft_status autotune(enufft_plan_t p);
+}  // namespace enufft

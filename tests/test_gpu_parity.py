@@ -264,3 +264,72 @@ def test_retained_power_autograd_fp32():
         print(name, "rel-l2 %.3e" % e, flush=True)
         assert e <= TOL["f32"]
     assert np.allclose(P.detach().cpu().numpy()[same], res["stats"][same, 1], rtol=1e-4)
+
+
+# ------------------------------------------------------------------------ graph
+
+@pytest.mark.parametrize("kind", ["raster", "split"])
+def test_forward_graph_replays_match_eager(kind):
+    """The captured type-1 + EMS graph, replayed several times with eager work and
+    synchronisations between replays, matches the eager launches every time (split
+    cells check that the merge counters reset themselves between replays)."""
+    if kind == "raster":
+        b = synth.config3(n_cells=16, count_scale=0.3)
+    else:
+        b = synth.uniform_box(counts=[90000, 5, 30000, 0, 45000], n_modes=(64, 64), precision="f32",
+                              window_radius=3.0)
+    gb = gpu_batch(b)
+    plan = make_plan(gb)
+    f0 = plan.type1(gb.x, gb.y, gb.h, gb.w)
+    k0, ks0, st0 = plan.ems(f0)
+    torch.cuda.synchronize()
+    f0, k0, ks0 = f0.cpu().numpy(), k0.cpu().numpy(), ks0.cpu().numpy()
+    out = (plan.empty_modes(), torch.empty(f0.shape, dtype=torch.uint8, device="cuda:0"),
+           torch.empty(b.n_cells, dtype=torch.int32, device="cuda:0"),
+           torch.empty((b.n_cells, 8), dtype=torch.float64, device="cuda:0"))
+    for rep in range(4):
+        plan.forward_graph(gb.x, gb.y, gb.h, gb.w, out=out)
+        torch.cuda.synchronize()
+        f, keep, ks, st = [t.cpu().numpy() for t in out]
+        assert rel_l2(f, f0) < 1e-6, rep
+        assert np.array_equal(ks, ks0) and np.array_equal(keep, k0), rep
+        # eager work between replays
+        g = plan.type1(gb.x, gb.y, gb.h, gb.w)
+        plan.ems(g)
+        torch.cuda.synchronize()
+    ref = oracle_f(b.to(dtype=torch.float32))
+    assert per_cell_rel_l2(f, ref).max() <= TOL["f32"]
+
+
+# ------------------------------------------------------------------------ autotuner
+
+def test_autotune_choice_cached_and_correct(tmp_path, monkeypatch):
+    """A tuned plan gives the default plan's coefficients and gradients (to FP32
+    rounding of a different split of the large cells), and a second plan over the
+    same layout takes the cached choice without new trials."""
+    monkeypatch.setenv("ENUFFT_TUNE_CACHE", str(tmp_path / "tune.txt"))
+    b = synth.uniform_box(counts=[250000, 40000, 7, 0, 120000, 3000], n_modes=(64, 64), precision="f32",
+                          window_radius=3.0)
+    gb = gpu_batch(b)
+    base = make_plan(gb)
+    tuned = make_plan(gb, autotune=True)
+    info = tuned.info()
+    print("tuned", {k: info[k] for k in ("tuned", "tune_cache_hit", "fwd_chunk_min", "fwd_items_per_slot",
+                                         "adj_items_per_slot", "adj_band_mult", "tune_fwd_ms", "tune_adj_ms")},
+          flush=True)
+    assert info["tuned"] == 1 and info["tune_cache_hit"] == 0
+    again = make_plan(gb, autotune=True).info()
+    assert again["tune_cache_hit"] == 1
+    for k in ("fwd_chunk_min", "fwd_items_per_slot", "adj_items_per_slot", "adj_band_mult"):
+        assert again[k] == info[k]
+    f0 = base.type1(gb.x, gb.y, gb.h, gb.w)
+    f1 = tuned.type1(gb.x, gb.y, gb.h, gb.w)
+    keep = torch.ones(f0.shape, dtype=torch.uint8, device="cuda:0")
+    g0 = base.retained_power_adjoint(gb.x, gb.y, gb.h, gb.w, f0, keep)
+    g1 = tuned.retained_power_adjoint(gb.x, gb.y, gb.h, gb.w, f0, keep)
+    torch.cuda.synchronize()
+    assert rel_l2(f1.cpu().numpy(), f0.cpu().numpy()) < 1e-6
+    for a, c in zip(g0, g1):
+        assert rel_l2(c.cpu().numpy(), a.cpu().numpy()) < 1e-6
+    ref = oracle_f(b.to(dtype=torch.float32))
+    assert per_cell_rel_l2(f1.cpu().numpy(), ref).max() <= TOL["f32"]
