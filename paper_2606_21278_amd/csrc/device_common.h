@@ -32,7 +32,7 @@ constexpr int ES_DEG = 7;
 constexpr int ES_MAXW = 8;
 struct EsPoly {
   int on;
-  float c[ES_MAXW * (ES_DEG + 1)];   // tap-major, ascending powers of u = 2 v - 1
+  float c[(ES_MAXW / 2) * (ES_DEG + 1)];   // taps 0 .. W/2 - 1, tap-major, ascending powers of u = 2 v - 1
 };
 
 // Fine-grid and mode-box geometry.
@@ -187,19 +187,48 @@ __device__ __forceinline__ double hann_wg(int kind, double x, double y, double c
 // degree-ES_DEG polynomial in u = 2 v - 1.  Horner on these coefficients
 // replaces the square root, reciprocal and exponential of every tap by ES_DEG
 // fused multiply-adds.
+//
+// psi is even, so tap W - 1 - d at u equals tap d at -u.  Splitting tap d's
+// polynomial into even and odd parts, P_d(u) = E(u^2) + u O(u^2), gives both
+// mirror taps from one pair of half-degree Horner chains: E + u O and E - u O.
+//
+// tap_v gives v = i0 - t + W/2 clamped to [0, 1]; es_taps_poly_v the W taps from it.
+__device__ __forceinline__ float tap_v(const FineCoord<float> &c, float halfw) {
+  const float v = ((float(c.i0) - c.hi) - c.lo) + halfw;
+  return fminf(fmaxf(v, 0.0f), 1.0f);
+}
+
+template <int W>
+__device__ __forceinline__ void es_taps_poly_v(float v, const EsPoly &cf, float (&out)[W]) {
+  static_assert(W % 2 == 0 && ES_DEG % 2 == 1, "mirror-pair evaluation needs even W and odd degree");
+  const float u = 2.0f * v - 1.0f;
+  const float s = u * u;
+#pragma unroll
+  for (int d = 0; d < W / 2; ++d) {
+    const float *cd = cf.c + d * (ES_DEG + 1);
+    float e = cd[ES_DEG - 1], o = cd[ES_DEG];
+#pragma unroll
+    for (int k = ES_DEG - 3; k >= 0; k -= 2) {
+      e = fmaf(e, s, cd[k]);
+      o = fmaf(o, s, cd[k + 1]);
+    }
+    out[d] = fmaf(u, o, e);
+    out[W - 1 - d] = fmaf(-u, o, e);
+  }
+}
+
 template <int W>
 __device__ __forceinline__ void es_taps_poly(const FineCoord<float> &c, float halfw, const EsPoly &cf,
                                              float (&out)[W]) {
-  float v = ((float(c.i0) - c.hi) - c.lo) + halfw;
-  v = fminf(fmaxf(v, 0.0f), 1.0f);
-  const float u = 2.0f * v - 1.0f;
+  es_taps_poly_v<W>(tap_v(c, halfw), cf, out);
+}
+
+// Exact FP32 taps from v (tap d at z = (v + d - W/2) 2 / W).
+template <int W>
+__device__ __forceinline__ void es_taps_exact_v(float v, float beta, float (&out)[W]) {
+  const float zsc = 2.0f / float(W);
 #pragma unroll
-  for (int d = 0; d < W; ++d) {
-    float acc = cf.c[d * (ES_DEG + 1) + ES_DEG];
-#pragma unroll
-    for (int k = ES_DEG - 1; k >= 0; --k) acc = fmaf(acc, u, cf.c[d * (ES_DEG + 1) + k]);
-    out[d] = acc;
-  }
+  for (int d = 0; d < W; ++d) out[d] = es_eval((v + float(d - W / 2)) * zsc, beta);
 }
 
 // The W kernel values of one point along one axis: polynomial form when the

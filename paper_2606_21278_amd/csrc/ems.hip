@@ -1,4 +1,5 @@
-// Elastic Mode Selection on gfx950: one workgroup per cell.
+// Elastic Mode Selection on gfx950: one workgroup per cell; the unit energies
+// are sorted in registers per wave and merged through LDS.
 //
 // Section 2.2 of the paper, in its order: unit energies (eq. energy, with the
 // optional weight of eq. weighted_e), the descending order of eq.
@@ -26,173 +27,401 @@ struct EmsArgs {
   int32_t *k_star;
   double *stats;
   const int2 *units;          // (rep, partner | -1), ascending unit id
-  int J, Jpad;
+  const int4 *mode_unit;      // [M]: (rep, partner | -1, unit id, 0) of each mode's unit; rep -1: no unit
+  int J;
   int M;                      // modes per cell = N1 * N2
-  int64_t cell_begin;
+  int64_t cell_begin, cell_end;
   int k_min, k_max;
   double alpha_min, alpha_max, delta, w1, w2;
 };
 
-template <int NT>
-__device__ double block_sum(double v, double *red) {
+// One wave per cell.  Wave-wide helpers: every lane returns the same value.
+__device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  __syncthreads();
-  if (lane == 0) red[wid] = v;
-  __syncthreads();
-  double s = 0.0;
-  if (threadIdx.x == 0) {
-    for (int i = 0; i < NT / 64; ++i) s += red[i];
-    red[NT / 64] = s;
+  return v;
+}
+__device__ __forceinline__ int wave_sum_i(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ __forceinline__ int wave_min_i(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
+  return v;
+}
+// Exclusive prefix over lanes (Hillis-Steele on the wave).
+template <typename V>
+__device__ __forceinline__ V wave_exclusive_scan(V v, int lane) {
+  V inc = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const V t = __shfl_up(inc, o, 64);
+    if (lane >= o) inc += t;
   }
-  __syncthreads();
-  s = red[NT / 64];
-  __syncthreads();
-  return s;
+  return inc - v;
 }
 
-// "a precedes b" in the order of eq. (sorted_energy): larger energy first, ties
-// by smaller unit id.
-__device__ __forceinline__ bool precedes(double ea, int ia, double eb, int ib) {
-  return ea > eb || (ea == eb && ia < ib);
+// max / min of two energies.  The values are finite and never signalling
+// NaNs, so the plain instructions do (the generic fmax would first quiet both
+// operands).
+__device__ __forceinline__ double dmax(double a, double b) {
+  double r;
+  asm("v_max_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+  return r;
+}
+__device__ __forceinline__ double dmin(double a, double b) {
+  double r;
+  asm("v_min_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+  return r;
 }
 
-template <typename T, int NT>
-__global__ __launch_bounds__(NT) void ems_kernel(EmsArgs a) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  double *E = reinterpret_cast<double *>(smem_raw);
-  int *id = reinterpret_cast<int *>(E + a.Jpad);
-  uint8_t *kp = reinterpret_cast<uint8_t *>(id + a.Jpad);
-  __shared__ double red[NT / 64 + 1];
-  __shared__ double scan_tot[NT];
-  __shared__ int s_kc;
+// Descending bitonic sort of the wave's JP = 64 R values held blocked (lane l
+// holds positions l R .. l R + R - 1), in the flip form: for each block size
+// k a flip comparator (i against i ^ (k - 1)) then half-cleaners j = k/4 .. 1;
+// the lower index of every pair takes the larger value, so no direction bits.
+// Pairs inside a lane are register compare-exchanges; pairs across lanes
+// exchange through cross-lane shuffles.  Stages are template-expanded so every
+// register index is a constant.
+template <int R, int K>
+__device__ __forceinline__ void flip_stage(double (&e)[R], int lane) {
+  if constexpr (K <= R) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int q = r ^ (K - 1);
+      if (r < q) {
+        const double hi = dmax(e[r], e[q]), lo = dmin(e[r], e[q]);
+        e[r] = hi; e[q] = lo;
+      }
+    }
+  } else {
+    constexpr int lm = K / R - 1;
+    const bool lower = (lane & (K / (2 * R))) == 0;
+#pragma unroll
+    for (int r = 0; r < (R + 1) / 2; ++r) {
+      const int q = R - 1 - r;
+      const double o1 = __shfl_xor(e[q], lm, 64);   // partner of my r is the partner lane's q
+      if (q != r) {
+        const double o2 = __shfl_xor(e[r], lm, 64);
+        const double h2 = dmax(e[q], o2), l2 = dmin(e[q], o2);
+        e[q] = lower ? h2 : l2;
+      }
+      const double h1 = dmax(e[r], o1), l1 = dmin(e[r], o1);
+      e[r] = lower ? h1 : l1;
+      if ((r & 7) == 7) __builtin_amdgcn_sched_barrier(0);   // bound the shuffles in flight
+    }
+  }
+}
 
+template <int R, int J>
+__device__ __forceinline__ void half_stages(double (&e)[R], int lane) {
+  if constexpr (J >= 1) {
+    if constexpr (J < R) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int q = r ^ J;
+        if (r < q) {
+          const double hi = dmax(e[r], e[q]), lo = dmin(e[r], e[q]);
+          e[r] = hi; e[q] = lo;
+        }
+      }
+    } else {
+      constexpr int lm = J / R;
+      const bool lower = (lane & lm) == 0;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const double o = __shfl_xor(e[r], lm, 64);
+        const double hi = dmax(e[r], o), lo = dmin(e[r], o);
+        e[r] = lower ? hi : lo;
+        if ((r & 15) == 15) __builtin_amdgcn_sched_barrier(0);
+      }
+    }
+    half_stages<R, J / 2>(e, lane);
+  }
+}
+
+template <int R, int K = 2>
+__device__ __forceinline__ void wave_sort_desc(double (&e)[R], int lane) {
+  if constexpr (K <= 64 * R) {
+    flip_stage<R, K>(e, lane);
+    half_stages<R, K / 4>(e, lane);
+    wave_sort_desc<R, 2 * K>(e, lane);
+  }
+}
+
+// Energy of unit u (FP64; products of FP32 values are exact in FP64).
+// The same arithmetic serves the sort (unit order) and the keep pass (mode
+// order), so a unit's energy is bit-identical in both.  Loads are
+// unconditional (a missing partner reads the representative and is masked).
+template <typename C>
+__device__ __forceinline__ double pair_energy(const EmsArgs &a, const C *f, int rep, int partner) {
+  const int pq = partner >= 0 ? partner : rep;
+  const C fr = f[rep], fp = f[pq];
+  double e = (double)fr.x * (double)fr.x + (double)fr.y * (double)fr.y;
+  double ep = (double)fp.x * (double)fp.x + (double)fp.y * (double)fp.y;
+  if (a.mode_weight) {
+    e *= a.mode_weight[rep];
+    ep *= a.mode_weight[pq];
+  }
+  return partner >= 0 ? e + ep : e;
+}
+
+// Workgroup-wide sum / integer sum / integer min / exclusive scan for NW
+// waves (NW = 1: the wave operations alone, no barrier).  Every thread gets
+// the result; the summation order is fixed.
+template <int NW>
+__device__ __forceinline__ double block_sum(double v, double *red, int wave) {
+  v = wave_sum(v);
+  if constexpr (NW == 1) {
+    return v;
+  } else {
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[wave] = v;
+    __syncthreads();
+    double s = 0.0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) s += red[w];
+    return s;
+  }
+}
+template <int NW>
+__device__ __forceinline__ int block_sum_i(int v, int *red, int wave) {
+  v = wave_sum_i(v);
+  if constexpr (NW == 1) {
+    return v;
+  } else {
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[wave] = v;
+    __syncthreads();
+    int s = 0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) s += red[w];
+    return s;
+  }
+}
+template <int NW>
+__device__ __forceinline__ int block_min_i(int v, int *red, int wave) {
+  v = wave_min_i(v);
+  if constexpr (NW == 1) {
+    return v;
+  } else {
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[wave] = v;
+    __syncthreads();
+    int s = INT_MAX;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) s = min(s, red[w]);
+    return s;
+  }
+}
+template <int NW, typename V>
+__device__ __forceinline__ V block_exclusive_scan(V v, V *red, int wave, int lane) {
+  V x = wave_exclusive_scan<V>(v, lane);
+  if constexpr (NW == 1) {
+    return x;
+  } else {
+    const V tot = __shfl(x + v, 63, 64);
+    __syncthreads();
+    if (lane == 0) red[wave] = tot;
+    __syncthreads();
+    V base = V(0);
+#pragma unroll
+    for (int w = 0; w < NW; ++w)
+      if (w < wave) base += red[w];
+    return base + x;
+  }
+}
+
+// One workgroup of NW waves per cell; thread t holds sort positions
+// t R .. t R + R - 1.  Each wave sorts its 64 R energies in registers, the
+// sorted runs are merged pairwise through LDS (merge path: every thread finds
+// where its R outputs start by binary search and merges them sequentially),
+// and the scores are read from the sorted array.
+//
+// The order of eq. (sorted_energy) is by energy, ties by ascending unit id.
+// Every quantity before the cut depends only on the sorted energy values, so
+// the sort carries values only; which of several units tied at the cut energy
+// are kept is settled afterwards by ascending id (a prefix count of the ties).
+template <typename T, int R, int NW>
+__global__ __launch_bounds__(64 * NW) void ems_kernel(EmsArgs a) {
+  constexpr int NT = 64 * NW, JW = 64 * R, JP = JW * NW;
+  __shared__ double sorted[JP];
+  __shared__ uint8_t tie_kept[JP];
+  __shared__ double redd[NW];
+  __shared__ int redi[NW];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, t = threadIdx.x;
   const int64_t cell = a.cell_begin + blockIdx.x;
   using C = typename vec2<T>::type;
   const C *f = reinterpret_cast<const C *>(a.f) + cell * a.M;
-  const int J = a.J, Jpad = a.Jpad;
+  const int J = a.J;
 
-  // unit energies in FP64 (products of FP32 values are exact in FP64)
+  // eq. (energy) / (weighted_e), unit u = position t R + r.  Padding is +0,
+  // which sorts among real zero energies; positions >= J are excluded from
+  // every sum below, and equal values are interchangeable.
+  double e[R];
   double t1 = 0.0, t2 = 0.0;
-  for (int u = threadIdx.x; u < Jpad; u += NT) {
-    if (u < J) {
-      const int2 un = a.units[u];
-      const C fr = f[un.x];
-      double e = (double)fr.x * (double)fr.x + (double)fr.y * (double)fr.y;
-      if (a.mode_weight) e *= a.mode_weight[un.x];
-      if (un.y >= 0) {
-        const C fp = f[un.y];
-        double ep = (double)fp.x * (double)fp.x + (double)fp.y * (double)fp.y;
-        if (a.mode_weight) ep *= a.mode_weight[un.y];
-        e += ep;
-      }
-      E[u] = e;
-      id[u] = u;
-      t1 += e;
-      t2 += e * e;
-    } else {
-      E[u] = -1.0;
-      id[u] = INT_MAX;
-    }
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int u = t * R + r;
+    const int2 un = a.units[u < J ? u : max(J - 1, 0)];
+    const double v = pair_energy<C>(a, f, un.x, un.y);
+    e[r] = u < J ? v : 0.0;
+    t1 += e[r];
+    t2 += e[r] * e[r];
   }
-  const double T1 = block_sum<NT>(t1, red);
-  const double T2 = block_sum<NT>(t2, red);
+  const double T1 = block_sum<NW>(t1, redd, wave);
+  const double T2 = block_sum<NW>(t2, redd, wave);
 
-  // bitonic sort of (E, id) into the order of eq. (sorted_energy)
-  for (int k = 2; k <= Jpad; k <<= 1) {
-    for (int j = k >> 1; j > 0; j >>= 1) {
-      for (int i = threadIdx.x; i < Jpad; i += NT) {
-        const int l = i ^ j;
-        if (l > i) {
-          const double ei = E[i], el = E[l];
-          const int ii = id[i], il = id[l];
-          const bool up = (i & k) == 0;
-          const bool sw = up ? precedes(el, il, ei, ii) : precedes(ei, ii, el, il);
-          if (sw) { E[i] = el; E[l] = ei; id[i] = il; id[l] = ii; }
-        }
-      }
-      __syncthreads();
+  // eq. (sorted_energy): runs of JW per wave, then merges
+  wave_sort_desc<R>(e, lane);
+#pragma unroll
+  for (int r = 0; r < R; ++r) sorted[t * R + r] = e[r];
+#pragma unroll
+  for (int width = JW; width < JP; width *= 2) {
+    __syncthreads();
+    const int o0 = t * R;                       // first output position
+    const int base = o0 / (2 * width) * (2 * width);
+    const double *A = sorted + base, *B = A + width;
+    const int d = o0 - base;                    // outputs before mine in this merged run
+    int lo = d > width ? d - width : 0, hi = d < width ? d : width;
+    while (lo < hi) {                           // first d outputs take lo from A
+      const int mid = (lo + hi) >> 1;
+      if (A[mid] >= B[d - 1 - mid]) lo = mid + 1;
+      else hi = mid;
     }
+    int ia = lo, ib = d - lo;
+    double out[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const double va = A[min(ia, width - 1)], vb = B[min(ib, width - 1)];   // in bounds; guarded below
+      const bool take_a = ib >= width || (ia < width && va >= vb);
+      out[r] = take_a ? va : vb;
+      ia += take_a;
+      ib += !take_a;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < R; ++r) sorted[o0 + r] = out[r];
   }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < R; ++r) e[r] = sorted[t * R + r];   // this thread's sorted positions
+  const double enext = (t * R + R < JP) ? sorted[t * R + R] : 0.0;
 
   const int Jmax = J < a.k_max ? J : a.k_max;
-  // eq. (n_eff) over all J* units, clipped by the budget
+  // eq. (n_eff) over all J units, clipped by the budget
   const double neff = T2 > 0.0 ? T1 * T1 / T2 : 0.0;
   const double nclip = neff < (double)Jmax ? neff : (double)Jmax;
   // eq. (s_delta) over the first J_max - 1 gaps
   double sd = 0.0;
-  for (int j = threadIdx.x; j < Jmax - 1; j += NT) {
-    const double ea = E[j], eb = E[j + 1];
-    double term;
-    if (eb == 0.0 && ea == 0.0) term = 1.0;
-    else if (eb == 0.0) term = 0.0;
-    else term = exp(-(ea / eb - 1.0) / a.delta);
-    sd += term;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int j = t * R + r;
+    if (j < Jmax - 1) {
+      const double ea = e[r], eb = (r + 1 < R) ? e[r + 1 < R ? r + 1 : r] : enext;
+      double term;
+      if (eb == 0.0 && ea == 0.0) term = 1.0;
+      else if (eb == 0.0) term = 0.0;
+      else term = exp(-(ea / eb - 1.0) / a.delta);
+      sd += term;
+    }
   }
-  const double sdsum = block_sum<NT>(sd, red);
+  const double sdsum = block_sum<NW>(sd, redd, wave);
   const double sdel = Jmax < 2 ? 1.0 : sdsum / (double)(Jmax - 1);
+  // eqs. (c_score), (alpha_c)
   const double Cs = (Jmax > 0 ? a.w1 * nclip / (double)Jmax : 0.0) + a.w2 * sdel;
   const double alphaC = a.alpha_min + (a.alpha_max - a.alpha_min) * Cs;
 
-  // running sum of the sorted energies (eq. f_cum): contiguous segments per
-  // thread, then a scan of the segment totals
-  const int seg = (J + NT - 1) / NT;
-  const int s0 = threadIdx.x * seg;
-  const int s1 = min(J, s0 + seg);
+  // eq. (f_cum): running sum in sorted order; the first K with theta(K) >= alpha_C
   double loc = 0.0;
-  for (int j = s0; j < s1; ++j) loc += E[j];
-  scan_tot[threadIdx.x] = loc;
-  if (threadIdx.x == 0) s_kc = INT_MAX;
-  __syncthreads();
-  for (int o = 1; o < NT; o <<= 1) {
-    const double v = threadIdx.x >= o ? scan_tot[threadIdx.x - o] : 0.0;
-    __syncthreads();
-    scan_tot[threadIdx.x] += v;
-    __syncthreads();
-  }
-  double run = threadIdx.x > 0 ? scan_tot[threadIdx.x - 1] : 0.0;
-  if (T1 > 0.0) {
-    for (int j = s0; j < s1; ++j) {
-      run += E[j];
-      if (run / T1 >= alphaC) { atomicMin(&s_kc, j + 1); break; }
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+    if (t * R + r < J) loc += e[r];
+  double run = block_exclusive_scan<NW, double>(loc, redd, wave, lane);
+  int kc = INT_MAX;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int j = t * R + r;
+    if (j < J) {
+      run += e[r];
+      if (T1 > 0.0 && kc == INT_MAX && run / T1 >= alphaC) kc = j + 1;
     }
   }
-  // zero the keep staging area
-  for (int m = threadIdx.x; m < a.M; m += NT) kp[m] = 0;
-  __syncthreads();
+  kc = block_min_i<NW>(kc, redi, wave);
+  // eq. (k_elastic)
   int kstar;
   if (!(T1 > 0.0)) {
     kstar = a.k_min < J ? a.k_min : J;
   } else {
-    const int kc = s_kc == INT_MAX ? J : s_kc;
-    const int k = kc > a.k_min ? kc : a.k_min;
+    const int kcc = kc == INT_MAX ? J : kc;
+    const int k = kcc > a.k_min ? kcc : a.k_min;
     kstar = k < Jmax ? k : Jmax;
   }
-  // eq. (k_elastic): keep every mode of the first K* units
-  for (int j = threadIdx.x; j < kstar; j += NT) {
-    const int2 un = a.units[id[j]];
-    kp[un.x] = 1;
-    if (un.y >= 0) kp[un.y] = 1;
+  // cut energy E_(K*), the retained sum of the first K* sorted energies, and
+  // how many units lie strictly above the cut or at it
+  const double eth = kstar > 0 ? sorted[kstar - 1] : 0.0;
+  double part = 0.0;
+  int cgt = 0, ceq = 0;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int j = t * R + r;
+    if (j < kstar) part += e[r];
+    if (j < J) {
+      cgt += e[r] > eth;
+      ceq += e[r] == eth;
+    }
   }
-  __syncthreads();
-  double pw = 0.0, th = 0.0;
-  for (int m = threadIdx.x; m < a.M; m += NT) {
-    const uint8_t v = kp[m];
-    a.keep[cell * a.M + m] = v;
+  const double th = block_sum<NW>(part, redd, wave);
+  const int ngt = block_sum_i<NW>(cgt, redi, wave);
+  const int neq = block_sum_i<NW>(ceq, redi, wave);
+  const int need = kstar - ngt;   // units kept at the cut energy, lowest ids first
+
+  // Ties straddling the cut (more units at the cut energy than kept there):
+  // rank the tied units by id.  Otherwise every unit at the cut is kept.
+  const bool split_ties = kstar > 0 && neq > need;
+  if (split_ties) {   // the same in every thread
+    int ties = 0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int u = t * R + r;
+      const int2 un = a.units[u < J ? u : max(J - 1, 0)];
+      ties += (u < J && pair_energy<C>(a, f, un.x, un.y) == eth);
+    }
+    int rank = block_exclusive_scan<NW, int>(ties, redi, wave, lane);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int u = t * R + r;
+      const int2 un = a.units[u < J ? u : max(J - 1, 0)];
+      const bool tie = u < J && pair_energy<C>(a, f, un.x, un.y) == eth;
+      tie_kept[u] = tie && rank < need;
+      rank += tie;
+    }
+    __syncthreads();
+  }
+
+  // modes (coalesced): keep flags and the retained power
+  double pw = 0.0;
+  uint8_t *kout = a.keep + cell * a.M;
+  for (int m = t; m < a.M; m += NT) {
+    const int4 mu = a.mode_unit[m];
+    uint8_t v = 0;
+    if (kstar > 0 && mu.x >= 0) {
+      const double eu = pair_energy<C>(a, f, mu.x, mu.y);
+      v = eu > eth || (eu == eth && (!split_ties || tie_kept[mu.z]));
+    }
+    kout[m] = v;
     if (v) {
       const C fr = f[m];
       pw += (double)fr.x * (double)fr.x + (double)fr.y * (double)fr.y;
     }
   }
-  for (int j = threadIdx.x; j < kstar; j += NT) th += E[j];
-  const double P = block_sum<NT>(pw, red);
-  const double TH = block_sum<NT>(th, red);
-  if (threadIdx.x == 0) {
+  const double P = block_sum<NW>(pw, redd, wave);
+  if (t == 0) {
     a.k_star[cell] = kstar;
     double *st = a.stats + cell * 8;
     st[0] = T1; st[1] = P; st[2] = neff; st[3] = sdel;
-    st[4] = Cs; st[5] = alphaC; st[6] = T1 > 0.0 ? TH / T1 : 0.0; st[7] = (double)J;
+    st[4] = Cs; st[5] = alphaC; st[6] = T1 > 0.0 ? th / T1 : 0.0; st[7] = (double)J;
   }
 }
 
@@ -217,34 +446,42 @@ static void build_units(int N1, int N2, bool pairs, bool exclude_dc, std::vector
   }
 }
 
-static int ems_threads() { return 512; }
-
-static size_t ems_lds(int Jpad, int M) { return (size_t)Jpad * (8 + 4) + (size_t)M + 16; }
 
 enufft_status ems_units(enufft_plan_t p, const enufft_ems_params *prm, UnitTable **ut) {
   UnitTable &u = p->units[prm->use_pairs ? 1 : 0][prm->exclude_dc ? 1 : 0];
   if (!u.built) {
     std::vector<int2> v;
     build_units(p->N1, p->N2, prm->use_pairs != 0, prm->exclude_dc != 0, v);
+    const int M = p->N1 * p->N2;
     u.J = (int)v.size();
-    u.Jpad = 1;
-    while (u.Jpad < std::max(1, u.J)) u.Jpad <<= 1;
-    void *d = nullptr;
+    // the kernel's branch-free loads read unit max(J - 1, 0): give an empty set
+    // one harmless entry (mode 0, no partner) that is never counted
+    if (v.empty()) v.push_back(make_int2(0, -1));
+    std::vector<int4> of_mode(M, make_int4(-1, -1, -1, 0));
+    for (int i = 0; i < u.J; ++i) {
+      of_mode[v[i].x] = make_int4(v[i].x, v[i].y, i, 0);
+      if (v[i].y >= 0) of_mode[v[i].y] = make_int4(v[i].x, v[i].y, i, 0);
+    }
+    u.Jpad = 64;
+    while (u.Jpad < u.J) u.Jpad <<= 1;
+    void *d = nullptr, *dm = nullptr;
     hipError_t e = hipMalloc(&d, std::max<size_t>(1, v.size()) * sizeof(int2));
+    if (e == hipSuccess) p->allocations.push_back(d);
+    if (e == hipSuccess) e = hipMalloc(&dm, (size_t)M * sizeof(int4));
+    if (e == hipSuccess) p->allocations.push_back(dm);
     if (e != hipSuccess) {
       p->last_error = "EMS unit table allocation failed";
       return ENUFFT_ENOMEM;
     }
-    p->allocations.push_back(d);
-    if (!v.empty()) {
-      e = hipMemcpy(d, v.data(), v.size() * sizeof(int2), hipMemcpyHostToDevice);
-      if (e != hipSuccess) {
-        p->last_error = std::string("EMS unit table upload: ") + hipGetErrorString(e);
-        p->faulted = true;
-        return ENUFFT_EDEVICE;
-      }
+    if (!v.empty()) e = hipMemcpy(d, v.data(), v.size() * sizeof(int2), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(dm, of_mode.data(), (size_t)M * sizeof(int4), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      p->last_error = std::string("EMS unit table upload: ") + hipGetErrorString(e);
+      p->faulted = true;
+      return ENUFFT_EDEVICE;
     }
     u.d_units = (int2 *)d;
+    u.d_mode_unit = (int4 *)dm;
     u.built = true;
   }
   *ut = &u;
@@ -270,8 +507,18 @@ enufft_status ems_validate(enufft_plan_t p, const void *f, const enufft_ems_para
 }
 
 template <typename T>
-hipError_t launch_ems_t(const EmsArgs &a, int blocks, size_t lds, hipStream_t s) {
-  hipLaunchKernelGGL((ems_kernel<T, 512>), dim3(blocks), dim3(512), lds, s, a);
+hipError_t launch_ems_t(const EmsArgs &a, int Jpad, int blocks, hipStream_t s) {
+  const dim3 g(blocks);
+  switch (Jpad) {
+    case 64: hipLaunchKernelGGL((ems_kernel<T, 1, 1>), g, dim3(64), 0, s, a); break;
+    case 128: hipLaunchKernelGGL((ems_kernel<T, 2, 1>), g, dim3(64), 0, s, a); break;
+    case 256: hipLaunchKernelGGL((ems_kernel<T, 4, 1>), g, dim3(64), 0, s, a); break;
+    case 512: hipLaunchKernelGGL((ems_kernel<T, 8, 1>), g, dim3(64), 0, s, a); break;
+    case 1024: hipLaunchKernelGGL((ems_kernel<T, 16, 1>), g, dim3(64), 0, s, a); break;
+    case 2048: hipLaunchKernelGGL((ems_kernel<T, 16, 2>), g, dim3(128), 0, s, a); break;
+    case 4096: hipLaunchKernelGGL((ems_kernel<T, 16, 4>), g, dim3(256), 0, s, a); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
@@ -285,14 +532,15 @@ enufft_status ems_launch(enufft_plan_t p, const void *f, const enufft_ems_params
   if (st != ENUFFT_OK) return st;
   EmsArgs a{};
   a.f = f; a.mode_weight = mode_weight; a.keep = keep; a.k_star = k_star; a.stats = stats;
-  a.units = ut->d_units; a.J = ut->J; a.Jpad = ut->Jpad; a.M = p->N1 * p->N2;
+  a.units = ut->d_units; a.mode_unit = ut->d_mode_unit; a.J = ut->J; a.M = p->N1 * p->N2;
   a.cell_begin = cell_begin;
+  a.cell_end = cell_begin + cell_count;
   a.k_min = prm->k_min; a.k_max = prm->k_max;
   a.alpha_min = prm->alpha_min; a.alpha_max = prm->alpha_max; a.delta = prm->delta;
   a.w1 = prm->w1; a.w2 = prm->w2;
-  const size_t lds = ems_lds(a.Jpad, a.M);
-  hipError_t e = p->prec == ENUFFT_F64 ? launch_ems_t<double>(a, (int)cell_count, lds, p->stream)
-                                       : launch_ems_t<float>(a, (int)cell_count, lds, p->stream);
+  const int blocks = (int)cell_count;
+  hipError_t e = p->prec == ENUFFT_F64 ? launch_ems_t<double>(a, ut->Jpad, blocks, p->stream)
+                                       : launch_ems_t<float>(a, ut->Jpad, blocks, p->stream);
   if (e != hipSuccess) {
     p->last_error = std::string("EMS launch: ") + hipGetErrorString(e);
     p->faulted = true;

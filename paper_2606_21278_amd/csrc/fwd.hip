@@ -15,19 +15,36 @@
 
 namespace enufft {
 
-// Spread the points [begin, end) of one item into the LDS grid.
+// Row pitch of the LDS grid: P > 0 is known at compile time (immediate LDS
+// offsets for the rows of a footprint), P = 0 reads it from the geometry.
+template <int P>
+__device__ __forceinline__ int grid_pitch(const Geom &g) {
+  return P > 0 ? P : g.pitch;
+}
+
+// Kernel values along one axis.  The constant-pitch builds are launched only
+// when the plan carries the kernel polynomial, so they evaluate it directly.
+template <typename T, int W, int P>
+__device__ __forceinline__ void taps(const FwdArgs<T> &a, const FineCoord<T> &c, T (&out)[W]) {
+  if constexpr (P > 0 && sizeof(T) == 4 && W <= ES_MAXW)
+    es_taps_poly<W>(c, float(W) * 0.5f, a.es, out);
+  else
+    es_taps<T, W>(c, a.beta, a.es, out);
+}
+
+// Add one point's W x W contributions to the FP64 grid.
 // The grid accumulates in FP64: on gfx950 the LDS adds FP64 values many times
 // faster than FP32 ones, and the wider sum costs no accuracy.  Stored row r
-// holds fine row r mod n2 (rows n2 .. n2 + W - 2 are folded back afterwards);
+// holds fine row r mod n2 (rows n2 .. n2 + W - 1 are folded back afterwards);
 // columns wrap with the grid mask.
-// Add one point's W x W contributions to the FP64 grid.
-template <typename T, int W>
+template <typename T, int W, int P>
 __device__ __forceinline__ void spread_point(const FwdArgs<T> &a, double *grid, T c, const FineCoord<T> &fx,
                                              const FineCoord<T> &fy) {
   const Geom &g = a.g;
+  const int pitch = grid_pitch<P>(g);
   T tx[W], ty[W];
-  es_taps<T, W>(fx, a.beta, a.es, tx);
-  es_taps<T, W>(fy, a.beta, a.es, ty);
+  taps<T, W, P>(a, fx, tx);
+  taps<T, W, P>(a, fy, ty);
   double kx[W], ky[W];
 #pragma unroll
   for (int d = 0; d < W; ++d) {
@@ -37,12 +54,12 @@ __device__ __forceinline__ void spread_point(const FwdArgs<T> &a, double *grid, 
   int col[W];
 #pragma unroll
   for (int d = 0; d < W; ++d) col[d] = (fx.i0 + d) & (g.n1 - 1);
-  double *rowp = grid + (fy.i0 & (g.n2 - 1)) * g.pitch;
+  double *rowp = grid + (fy.i0 & (g.n2 - 1)) * pitch;
 #pragma unroll
   for (int dy = 0; dy < W; ++dy) {
 #pragma unroll
     for (int dx = 0; dx < W; ++dx) {
-      __hip_atomic_fetch_add(rowp + dy * g.pitch + col[dx], ky[dy] * kx[dx], __ATOMIC_RELAXED,
+      __hip_atomic_fetch_add(rowp + dy * pitch + col[dx], ky[dy] * kx[dx], __ATOMIC_RELAXED,
                              __HIP_MEMORY_SCOPE_WORKGROUP);
     }
   }
@@ -54,93 +71,132 @@ __device__ __forceinline__ void spread_point(const FwdArgs<T> &a, double *grid, 
 // order, several per fine-grid cell -- their contributions are summed in a
 // (W + 1) x (W + 2) register window and the window is added to the grid once,
 // which cuts the LDS atomics per point and spreads neighbouring lanes apart.
-// Other groups fall back to spreading point by point.
+// Returns false, having added nothing, for a group that does not fit one
+// window; the caller defers it.
 constexpr int RUN_K = 4, RUN_SX = 2, RUN_SY = 1;
 
-template <typename T, int W>
-__device__ __forceinline__ void spread_run(const FwdArgs<T> &a, double *grid, const T (&xs)[RUN_K],
+template <typename T, int W, int P>
+__device__ __forceinline__ bool spread_run(const FwdArgs<T> &a, double *grid, const T (&xs)[RUN_K],
                                            const T (&ys)[RUN_K], const T (&cs)[RUN_K]) {
+  static_assert(sizeof(T) == 4, "runs are the FP32 path");
   const Geom &g = a.g;
-  const T halfw = T(W) / T(2);
-  const T zsc = T(2) / T(W);
-  FineCoord<T> fx[RUN_K], fy[RUN_K];
+  const int pitch = grid_pitch<P>(g);
+  const float halfw = float(W) / 2.0f;
+  // footprint origins and the in-cell offsets v = i0 - t + W/2 (all the taps need)
+  int ix[RUN_K], iy[RUN_K];
+  float vx[RUN_K], vy[RUN_K];
   int cmin = INT_MAX, rmin = INT_MAX, cmax = INT_MIN, rmax = INT_MIN;
 #pragma unroll
   for (int k = 0; k < RUN_K; ++k) {
-    fx[k] = fine_coord<T>(xs[k], a.s1_hi, a.s1_lo, halfw);
-    fy[k] = fine_coord<T>(ys[k], a.s2_hi, a.s2_lo, halfw);
-    if (cs[k] != T(0)) {
-      cmin = min(cmin, fx[k].i0); cmax = max(cmax, fx[k].i0);
-      rmin = min(rmin, fy[k].i0); rmax = max(rmax, fy[k].i0);
+    const FineCoord<float> fx = fine_coord<float>(xs[k], a.s1_hi, a.s1_lo, halfw);
+    const FineCoord<float> fy = fine_coord<float>(ys[k], a.s2_hi, a.s2_lo, halfw);
+    ix[k] = fx.i0; iy[k] = fy.i0;
+    vx[k] = tap_v(fx, halfw); vy[k] = tap_v(fy, halfw);
+    if (cs[k] != 0.0f) {
+      cmin = min(cmin, ix[k]); cmax = max(cmax, ix[k]);
+      rmin = min(rmin, iy[k]); rmax = max(rmax, iy[k]);
     }
   }
-  if (rmin == INT_MAX) return;   // every point outside the window
-  if (cmax - cmin <= RUN_SX && rmax - rmin <= RUN_SY) {
-    constexpr int WC = W + RUN_SX, WR = W + RUN_SY;
-    T acc[WR][WC];
+  if (rmin == INT_MAX) return true;   // every point outside the window
+  if (!(cmax - cmin <= RUN_SX && rmax - rmin <= RUN_SY)) return false;
+  // Every point enters the window, branch-free: one with c = 0 (outside the
+  // cell window) contributes exact zeros, and its taps stay finite because
+  // the tap offsets are clamped to the kernel's interval.
+  constexpr int WC = W + RUN_SX, WR = W + RUN_SY;
+  float acc[WR][WC];
+#pragma unroll
+  for (int k = 0; k < RUN_K; ++k) {
+    float kx[W], ky[W];
+    if constexpr (P > 0) {
+      es_taps_poly_v<W>(vx[k], a.es, kx);
+      es_taps_poly_v<W>(vy[k], a.es, ky);
+    } else if (a.es.on) {
+      es_taps_poly_v<W>(vx[k], a.es, kx);
+      es_taps_poly_v<W>(vy[k], a.es, ky);
+    } else {
+      es_taps_exact_v<W>(vx[k], a.beta, kx);
+      es_taps_exact_v<W>(vy[k], a.beta, ky);
+    }
+#pragma unroll
+    for (int d = 0; d < W; ++d) ky[d] *= cs[k];
+    const int sx = ix[k] - cmin, sy = iy[k] - rmin;
+    float KX[WC], KY[WR];
+#pragma unroll
+    for (int q = 0; q < WC; ++q) {
+      float v = 0.0f;
+#pragma unroll
+      for (int s = 0; s <= RUN_SX; ++s)
+        if (q - s >= 0 && q - s < W) v = (sx == s) ? kx[q - s] : v;
+      KX[q] = v;
+    }
+#pragma unroll
+    for (int r = 0; r < WR; ++r) {
+      float v = 0.0f;
+#pragma unroll
+      for (int s = 0; s <= RUN_SY; ++s)
+        if (r - s >= 0 && r - s < W) v = (sy == s) ? ky[r - s] : v;
+      KY[r] = v;
+    }
 #pragma unroll
     for (int r = 0; r < WR; ++r)
 #pragma unroll
-      for (int q = 0; q < WC; ++q) acc[r][q] = T(0);
+      for (int q = 0; q < WC; ++q) acc[r][q] = (k == 0) ? KY[r] * KX[q] : fmaf(KY[r], KX[q], acc[r][q]);
+    // one point at a time: interleaving the points' taps raises register
+    // pressure past the 128 registers of a 16-wave block
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  // flush the whole window (cells outside every footprint add zero); no
+  // per-cell branches, so the adds issue back to back
+  int col[WC];
 #pragma unroll
-    for (int k = 0; k < RUN_K; ++k) {
-      if (cs[k] == T(0)) continue;
-      T kx[W], ky[W];
-      es_taps<T, W>(fx[k], a.beta, a.es, kx);
-      es_taps<T, W>(fy[k], a.beta, a.es, ky);
+  for (int q = 0; q < WC; ++q) col[q] = (cmin + q) & (g.n1 - 1);
+  double *rowp = grid + (rmin & (g.n2 - 1)) * pitch;
 #pragma unroll
-      for (int d = 0; d < W; ++d) ky[d] *= cs[k];
-      const int sx = fx[k].i0 - cmin, sy = fy[k].i0 - rmin;
-      T KX[WC], KY[WR];
+  for (int q = 0; q < WC; ++q) {
+    double *cp = rowp + col[q];
 #pragma unroll
-      for (int q = 0; q < WC; ++q) {
-        T v = T(0);
+    for (int r = 0; r < WR; ++r)
+      __hip_atomic_fetch_add(cp + r * pitch, (double)acc[r][q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  }
+  return true;
+}
+
+// Orders this wave's LDS accesses around the deferred-group queue (LDS
+// operations of one wave complete in issue order; this keeps the compiler
+// from moving them).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Spread the deferred groups queue[0 .. n) of this wave, one group per lane,
+// point by point.  Entries are group offsets from g0 (groups of RUN_K points).
+template <typename T, int W, int P>
+__device__ __forceinline__ void drain_groups(const FwdArgs<T> &a, double *grid, const int *queue, int n,
+                                             int64_t g0, T cx, T cy, T R, T pr) {
+  using V = typename vec4<T>::type;
+  const int lane = threadIdx.x & 63;
+  if (lane >= n) return;
+  const int64_t q = g0 + queue[lane];
+  const V xv = reinterpret_cast<const V *>(a.x)[q], yv = reinterpret_cast<const V *>(a.y)[q];
+  const V hv = reinterpret_cast<const V *>(a.h)[q], wv = reinterpret_cast<const V *>(a.w)[q];
+  const T xs[RUN_K] = {xv.x, xv.y, xv.z, xv.w}, ys[RUN_K] = {yv.x, yv.y, yv.z, yv.w};
+  const T hs[RUN_K] = {hv.x, hv.y, hv.z, hv.w}, ws[RUN_K] = {wv.x, wv.y, wv.z, wv.w};
+  const T halfw = T(W) / T(2);
 #pragma unroll
-        for (int s = 0; s <= RUN_SX; ++s)
-          if (q - s >= 0 && q - s < W) v = (sx == s) ? kx[q - s] : v;
-        KX[q] = v;
-      }
-#pragma unroll
-      for (int r = 0; r < WR; ++r) {
-        T v = T(0);
-#pragma unroll
-        for (int s = 0; s <= RUN_SY; ++s)
-          if (r - s >= 0 && r - s < W) v = (sy == s) ? ky[r - s] : v;
-        KY[r] = v;
-      }
-#pragma unroll
-      for (int r = 0; r < WR; ++r)
-#pragma unroll
-        for (int q = 0; q < WC; ++q) acc[r][q] += KY[r] * KX[q];
-    }
-    // flush the whole window (cells outside every footprint add zero); no
-    // per-cell branches, so the adds issue back to back
-    int col[WC];
-#pragma unroll
-    for (int q = 0; q < WC; ++q) col[q] = (cmin + q) & (g.n1 - 1);
-    double *rowp = grid + (rmin & (g.n2 - 1)) * g.pitch;
-#pragma unroll
-    for (int r = 0; r < WR; ++r) {
-#pragma unroll
-      for (int q = 0; q < WC; ++q)
-        __hip_atomic_fetch_add(rowp + r * g.pitch + col[q], (double)acc[r][q], __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_WORKGROUP);
-    }
-  } else {
-#pragma unroll
-    for (int k = 0; k < RUN_K; ++k)
-      if (cs[k] != T(0)) spread_point<T, W>(a, grid, cs[k], fx[k], fy[k]);
+  for (int k = 0; k < RUN_K; ++k) {
+    const T c = ws[k] * hs[k] * hann_w(a.window_kind, xs[k], ys[k], cx, cy, R, pr);
+    if (c != T(0))
+      spread_point<T, W, P>(a, grid, c, fine_coord<T>(xs[k], a.s1_hi, a.s1_lo, halfw),
+                            fine_coord<T>(ys[k], a.s2_hi, a.s2_lo, halfw));
   }
 }
 
 // Spread the points [begin, end) of one item into the FP64 LDS grid.
-// The grid accumulates in FP64: on gfx950 the LDS adds FP64 values many times
-// faster than FP32 ones, and the wider sum costs no accuracy.  Stored row r
-// holds fine row r mod n2 (rows n2 .. n2 + W - 1 are folded back afterwards);
-// columns wrap with the grid mask.
-template <typename T, int W, int NT>
-__device__ __forceinline__ void spread_item(const FwdArgs<T> &a, double *grid, int64_t begin, int64_t end,
-                                            T cx, T cy, T R) {
+template <typename T, int W, int NT, int P>
+__device__ __forceinline__ void spread_item(const FwdArgs<T> &a, double *grid, int *queue, int64_t begin,
+                                            int64_t end, T cx, T cy, T R) {
   const T halfw = T(W) / T(2);
   const T pr = R > T(0) ? T(M_PI) / R : T(0);
   int64_t body0 = end, body1 = end;
@@ -161,23 +217,59 @@ __device__ __forceinline__ void spread_item(const FwdArgs<T> &a, double *grid, i
     // atomics on one address serialise); the NW waves together still consume
     // every cache line of the block.  Software pipeline: the next block's loads
     // are in flight while this one spreads.
+    //
+    // Groups that do not fit one window (a raster row ends inside the group,
+    // or the points are unordered) are queued per wave and spread point by
+    // point 64 at a time, so the rare misfit does not stall the other 63 lanes.
     constexpr int NW = NT / 64;
-    const int lane_off = (threadIdx.x & 63) * NW + (threadIdx.x >> 6);
-    const int64_t q1 = body1 / RUN_K;
-    int64_t q = body0 / RUN_K + lane_off;
+    const int lane = threadIdx.x & 63;
+    const int lane_off = lane * NW + (threadIdx.x >> 6);
+    const int64_t g0 = body0 / RUN_K, q1 = body1 / RUN_K;
+    int64_t q = g0 + lane_off;
+    int nq = 0;   // queued groups (the same in every lane)
+    // 16-wave blocks hide load latency by occupancy and need the registers
+    constexpr bool kPrefetch = NT < 1024;
     V xn{}, yn{}, hn{}, wn{};
-    if (q < q1) { xn = x4[q]; yn = y4[q]; hn = h4[q]; wn = w4[q]; }
-    for (int64_t qb = body0 / RUN_K; qb < q1; qb += NT, q += NT) {
-    const bool live = q < q1;
-    const V xv = xn, yv = yn, hv = hn, wv = wn;
-    if (q + NT < q1) { xn = x4[q + NT]; yn = y4[q + NT]; hn = h4[q + NT]; wn = w4[q + NT]; }
-    if (!live) continue;
-    const T xs[RUN_K] = {xv.x, xv.y, xv.z, xv.w}, ys[RUN_K] = {yv.x, yv.y, yv.z, yv.w};
-    const T hs[RUN_K] = {hv.x, hv.y, hv.z, hv.w}, ws[RUN_K] = {wv.x, wv.y, wv.z, wv.w};
-    T cs[RUN_K];
+    if (kPrefetch && q < q1) { xn = x4[q]; yn = y4[q]; hn = h4[q]; wn = w4[q]; }
+    for (int64_t qb = g0; qb < q1; qb += NT, q += NT) {
+      const bool live = q < q1;
+      V xv, yv, hv, wv;
+      if constexpr (kPrefetch) {
+        xv = xn; yv = yn; hv = hn; wv = wn;
+        if (q + NT < q1) { xn = x4[q + NT]; yn = y4[q + NT]; hn = h4[q + NT]; wn = w4[q + NT]; }
+      } else if (live) {
+        xv = x4[q]; yv = y4[q]; hv = h4[q]; wv = w4[q];
+      }
+      bool fits = true;
+      if (live) {
+        const T xs[RUN_K] = {xv.x, xv.y, xv.z, xv.w}, ys[RUN_K] = {yv.x, yv.y, yv.z, yv.w};
+        const T hs[RUN_K] = {hv.x, hv.y, hv.z, hv.w}, ws[RUN_K] = {wv.x, wv.y, wv.z, wv.w};
+        T cs[RUN_K];
 #pragma unroll
-    for (int k = 0; k < RUN_K; ++k) cs[k] = ws[k] * hs[k] * hann_w(a.window_kind, xs[k], ys[k], cx, cy, R, pr);
-    spread_run<T, W>(a, grid, xs, ys, cs);
+        for (int k = 0; k < RUN_K; ++k) cs[k] = ws[k] * hs[k] * hann_w(a.window_kind, xs[k], ys[k], cx, cy, R, pr);
+        fits = spread_run<T, W, P>(a, grid, xs, ys, cs);
+      }
+      const uint64_t m = __ballot(!fits);
+      if (m != 0) {
+        if (!fits) {
+          const int pos = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+          queue[nq + pos] = (int)(q - g0);   // nq < 64 here, so nq + pos < FWD_QCAP
+        }
+        nq += __popcll(m);
+        if (nq >= 64) {
+          wave_lds_sync();
+          drain_groups<T, W, P>(a, grid, queue, 64, g0, cx, cy, R, pr);
+          nq -= 64;
+          const int rest = lane < nq ? queue[64 + lane] : 0;
+          wave_lds_sync();
+          if (lane < nq) queue[lane] = rest;
+          wave_lds_sync();
+        }
+      }
+    }
+    if (nq > 0) {
+      wave_lds_sync();
+      drain_groups<T, W, P>(a, grid, queue, nq, g0, cx, cy, R, pr);
     }
   }
   // points outside the aligned body, one per thread
@@ -187,8 +279,8 @@ __device__ __forceinline__ void spread_item(const FwdArgs<T> &a, double *grid, i
     const T xj = a.x[j], yj = a.y[j];
     const T c = a.w[j] * a.h[j] * hann_w(a.window_kind, xj, yj, cx, cy, R, pr);
     if (c == T(0)) continue;
-    spread_point<T, W>(a, grid, c, fine_coord<T>(xj, a.s1_hi, a.s1_lo, halfw),
-                       fine_coord<T>(yj, a.s2_hi, a.s2_lo, halfw));
+    spread_point<T, W, P>(a, grid, c, fine_coord<T>(xj, a.s1_hi, a.s1_lo, halfw),
+                          fine_coord<T>(yj, a.s2_hi, a.s2_lo, halfw));
   }
 }
 
@@ -304,10 +396,11 @@ __device__ void fft_deconv_store(const FwdArgs<T> &a, T *G, int cell) {
   }
 }
 
-template <typename T, int W, int NT>
+template <typename T, int W, int NT, int P>
 __global__ __launch_bounds__(NT) void fwd_kernel(FwdArgs<T> a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   double *grid = reinterpret_cast<double *>(smem_raw);
+  int *queue = reinterpret_cast<int *>(smem_raw + fwd_grid_bytes(a.g, W)) + (threadIdx.x >> 6) * FWD_QCAP;
   T *G = reinterpret_cast<T *>(smem_raw);   // the same grid after rounding to T
   __shared__ int s_item, s_last;
   const Geom &g = a.g;
@@ -328,7 +421,7 @@ __global__ __launch_bounds__(NT) void fwd_kernel(FwdArgs<T> a) {
     for (int i = threadIdx.x; i < total; i += NT) grid[i] = 0.0;
     __syncthreads();
     const double *wn = a.windows + 3 * (int64_t)it.cell;
-    spread_item<T, W, NT>(a, grid, it.begin, it.end, T(wn[0]), T(wn[1]), T(wn[2]));
+    spread_item<T, W, NT, P>(a, grid, queue, it.begin, it.end, T(wn[0]), T(wn[1]), T(wn[2]));
     __syncthreads();
     fold_rows<W, NT>(grid, g);
     grid_to_t<T, NT>(grid, g);
@@ -375,49 +468,56 @@ __global__ __launch_bounds__(NT) void fwd_kernel(FwdArgs<T> a) {
   }
 }
 
+// The compiled variants: FP32 with the kernel polynomial (W <= 8) also has a
+// constant-pitch build for the 128-wide grid, used when the plan carries the
+// polynomial.
 template <typename T, int W>
-static hipError_t launch_fwd_w(const FwdArgs<T> &a, int blocks, int threads, size_t lds, hipStream_t s) {
-  if (threads == 256) {
-    hipLaunchKernelGGL((fwd_kernel<T, W, 256>), dim3(blocks), dim3(256), lds, s, a);
-  } else if (threads == 512) {
-    hipLaunchKernelGGL((fwd_kernel<T, W, 512>), dim3(blocks), dim3(512), lds, s, a);
-  } else {
-    hipLaunchKernelGGL((fwd_kernel<T, W, 1024>), dim3(blocks), dim3(1024), lds, s, a);
+constexpr bool has_pitch128() {
+  return sizeof(T) == 4 && W <= ES_MAXW;
+}
+
+template <typename T, int W>
+static const void *fwd_fn(int threads, int pitch) {
+  if constexpr (has_pitch128<T, W>()) {
+    if (pitch == FWD_PITCH128) {
+      if (threads == 256) return (const void *)&fwd_kernel<T, W, 256, FWD_PITCH128>;
+      if (threads == 512) return (const void *)&fwd_kernel<T, W, 512, FWD_PITCH128>;
+      return (const void *)&fwd_kernel<T, W, 1024, FWD_PITCH128>;
+    }
   }
-  return hipGetLastError();
+  if (threads == 256) return (const void *)&fwd_kernel<T, W, 256, 0>;
+  if (threads == 512) return (const void *)&fwd_kernel<T, W, 512, 0>;
+  return (const void *)&fwd_kernel<T, W, 1024, 0>;
+}
+
+template <typename T>
+static const void *fwd_fn_w(int W, int threads, int pitch) {
+  switch (W) {
+    case 4: return fwd_fn<T, 4>(threads, pitch);
+    case 6: return fwd_fn<T, 6>(threads, pitch);
+    case 8: return fwd_fn<T, 8>(threads, pitch);
+    case 10: return fwd_fn<T, 10>(threads, pitch);
+    case 12: return fwd_fn<T, 12>(threads, pitch);
+    case 14: return fwd_fn<T, 14>(threads, pitch);
+    case 16: return fwd_fn<T, 16>(threads, pitch);
+    default: return nullptr;
+  }
 }
 
 template <typename T>
 hipError_t launch_fwd(const FwdArgs<T> &a, int W, int blocks, int threads, size_t lds, hipStream_t s) {
-  switch (W) {
-    case 4: return launch_fwd_w<T, 4>(a, blocks, threads, lds, s);
-    case 6: return launch_fwd_w<T, 6>(a, blocks, threads, lds, s);
-    case 8: return launch_fwd_w<T, 8>(a, blocks, threads, lds, s);
-    case 10: return launch_fwd_w<T, 10>(a, blocks, threads, lds, s);
-    case 12: return launch_fwd_w<T, 12>(a, blocks, threads, lds, s);
-    case 14: return launch_fwd_w<T, 14>(a, blocks, threads, lds, s);
-    case 16: return launch_fwd_w<T, 16>(a, blocks, threads, lds, s);
-    default: return hipErrorInvalidValue;
-  }
+  if (threads != 256 && threads != 512 && threads != 1024) return hipErrorInvalidValue;
+  const void *fn = fwd_fn_w<T>(W, threads, fwd_variant_pitch(a.g, a.es));
+  if (!fn) return hipErrorInvalidValue;
+  void *args[] = {const_cast<FwdArgs<T> *>(&a)};
+  return hipLaunchKernel(fn, dim3(blocks), dim3(threads), args, lds, s);
 }
 
 template <typename T>
-hipError_t fwd_occupancy(int W, int threads, size_t lds, int *blocks_per_cu) {
-  const void *fn = nullptr;
-#define ENUFFT_FN(WW, NT) (const void *)(&fwd_kernel<T, WW, NT>)
-#define ENUFFT_PICK(WW)                                   \
-  case WW:                                                \
-    fn = threads == 256 ? ENUFFT_FN(WW, 256)              \
-         : threads == 512 ? ENUFFT_FN(WW, 512)            \
-                          : ENUFFT_FN(WW, 1024);          \
-    break;
-  switch (W) {
-    ENUFFT_PICK(4) ENUFFT_PICK(6) ENUFFT_PICK(8) ENUFFT_PICK(10) ENUFFT_PICK(12) ENUFFT_PICK(14)
-    ENUFFT_PICK(16)
-    default: return hipErrorInvalidValue;
-  }
-#undef ENUFFT_PICK
-#undef ENUFFT_FN
+hipError_t fwd_occupancy(int W, int threads, int pitch, size_t lds, int *blocks_per_cu) {
+  if (threads != 256 && threads != 512 && threads != 1024) return hipErrorInvalidValue;
+  const void *fn = fwd_fn_w<T>(W, threads, pitch);
+  if (!fn) return hipErrorInvalidValue;
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, fn, threads, lds);
@@ -425,7 +525,7 @@ hipError_t fwd_occupancy(int W, int threads, size_t lds, int *blocks_per_cu) {
 
 template hipError_t launch_fwd<float>(const FwdArgs<float> &, int, int, int, size_t, hipStream_t);
 template hipError_t launch_fwd<double>(const FwdArgs<double> &, int, int, int, size_t, hipStream_t);
-template hipError_t fwd_occupancy<float>(int, int, size_t, int *);
-template hipError_t fwd_occupancy<double>(int, int, size_t, int *);
+template hipError_t fwd_occupancy<float>(int, int, int, size_t, int *);
+template hipError_t fwd_occupancy<double>(int, int, int, size_t, int *);
 
 }  // namespace enufft

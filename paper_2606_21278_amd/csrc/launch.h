@@ -11,17 +11,33 @@ namespace enufft {
 template <typename T>
 hipError_t launch_fwd(const FwdArgs<T> &a, int W, int blocks, int threads, size_t lds, hipStream_t s);
 template <typename T>
-hipError_t fwd_occupancy(int W, int threads, size_t lds, int *blocks_per_cu);
+hipError_t fwd_occupancy(int W, int threads, int pitch, size_t lds, int *blocks_per_cu);
 
 template <typename T>
 hipError_t launch_adj(const AdjArgs<T> &a, int W, int blocks, int threads, size_t lds, hipStream_t s);
 template <typename T>
 hipError_t adj_occupancy(int W, int threads, size_t lds, int *blocks_per_cu);
 
+// Per-wave queue of deferred point groups in the forward kernel (entries).
+constexpr int FWD_QCAP = 128;
+// Row pitch of the 128-wide fine grid (64-mode boxes at sigma 2), for which
+// the FP32 forward kernel is compiled with the pitch as a constant.
+constexpr int FWD_PITCH128 = 130;
+
 // LDS bytes of the forward kernel: the FP64 spread grid with W wrap rows
-// (a merged run of points spans up to W + 1 rows).
-inline size_t fwd_lds_bytes(const Geom &g, int W) {
-  return (size_t)(g.n2 + W) * g.pitch * sizeof(double);
+// (a merged run of points spans up to W + 1 rows), then one deferred-group
+// queue per wave.
+// Pitch argument that selects the forward build: FWD_PITCH128 for the
+// constant-pitch polynomial build, 0 for the general one.
+inline int fwd_variant_pitch(const Geom &g, const EsPoly &es) {
+  return (g.pitch == FWD_PITCH128 && es.on) ? FWD_PITCH128 : 0;
+}
+
+__host__ __device__ inline size_t fwd_grid_bytes(const Geom &g, int W) {
+  return ((size_t)(g.n2 + W) * g.pitch * sizeof(double) + 15) / 16 * 16;
+}
+inline size_t fwd_lds_bytes(const Geom &g, int W, int threads) {
+  return fwd_grid_bytes(g, W) + (size_t)(threads / 64) * FWD_QCAP * sizeof(int);
 }
 
 }  // namespace enufft

@@ -276,6 +276,25 @@ void build_fwd_schedule(enufft_plan_t p, int slots) {
   p->n_split = nsplit;
 }
 
+// Forward workgroup size (256, 512 or 1024 threads): LDS footprint and the
+// resident workgroups per CU that size the schedule.
+enufft_status set_fwd_threads(enufft_plan_t p, int threads, size_t lds_limit) {
+  if (threads != 256 && threads != 512 && threads != 1024)
+    return fail(p, ENUFFT_EINVAL, "forward threads must be 256, 512 or 1024");
+  const size_t lds = fwd_lds_bytes(p->geom, p->W, threads);
+  if (lds > lds_limit) return fail(p, ENUFFT_EUNSUPPORTED, "enufft_plan: fine grid does not fit in LDS at this precision");
+  int per_cu = 0;
+  const int vp = fwd_variant_pitch(p->geom, p->es);
+  hipError_t e = (p->prec == ENUFFT_F64) ? fwd_occupancy<double>(p->W, threads, vp, lds, &per_cu)
+                                         : fwd_occupancy<float>(p->W, threads, vp, lds, &per_cu);
+  if (e != hipSuccess) return hip_fail(p, e, "occupancy query");
+  if (per_cu < 1) return fail(p, ENUFFT_EDEVICE, "forward kernel cannot be resident");
+  p->fwd_threads = threads;
+  p->fwd_lds = lds;
+  p->fwd_slots = p->n_cu * per_cu;
+  return ENUFFT_OK;
+}
+
 // (Re)build the forward schedule for the plan's launch-shape parameters and
 // replace its device copies (item lists and the partial grids of split cells).
 enufft_status install_fwd_schedule(enufft_plan_t p) {
@@ -410,23 +429,24 @@ enufft_status enufft_plan(enufft_plan_t *out, int64_t n_cells, const int64_t *ce
   if (e != hipSuccess) { enufft_status s = hip_fail(p, e, "hipGetDeviceProperties"); free_plan(p); return s; }
   p->n_cu = prop.multiProcessorCount;
 
-  // ---- forward launch shape
-  p->fwd_threads = 512;
-  p->fwd_lds = enufft::fwd_lds_bytes(g, W);
-  if (p->fwd_lds > (size_t)prop.sharedMemPerBlock) {
-    free_plan(p);
-    return fail(nullptr, ENUFFT_EUNSUPPORTED, "enufft_plan: fine grid does not fit in LDS at this precision");
+  // FP32 plans evaluate the kernel as per-tap polynomials when the fit is far
+  // below the requested accuracy (it is for the compiled widths 4..8).
+  if (p->prec == ENUFFT_F32 && W <= enufft::ES_MAXW) {
+    std::vector<double> cf;
+    const double err = fit_es_poly(W, beta, enufft::ES_DEG, cf);
+    if (err <= std::max(0.1 * opts->eps, 1e-6)) {
+      p->es_poly_err = err;
+      p->es.on = 1;
+      // the mirror taps W/2 .. W - 1 are evaluated from these (psi is even)
+      for (size_t i = 0; i < (size_t)(W / 2) * (enufft::ES_DEG + 1); ++i) p->es.c[i] = (float)cf[i];
+    }
   }
-  int per_cu = 0;
-  enufft_status st = ENUFFT_OK;
-  e = (p->prec == ENUFFT_F64) ? enufft::fwd_occupancy<double>(W, p->fwd_threads, p->fwd_lds, &per_cu)
-                              : enufft::fwd_occupancy<float>(W, p->fwd_threads, p->fwd_lds, &per_cu);
-  if (e != hipSuccess || per_cu < 1) {
-    st = e != hipSuccess ? hip_fail(p, e, "occupancy query") : fail(p, ENUFFT_EDEVICE, "forward kernel cannot be resident");
-    free_plan(p);
-    return st;
-  }
-  p->fwd_slots = p->n_cu * per_cu;
+
+  // ---- forward launch shape (threads per workgroup: ENUFFT_FWD_THREADS, or the autotuner)
+  int threads = 512;
+  if (const char *ev = std::getenv("ENUFFT_FWD_THREADS")) threads = std::atoi(ev);
+  enufft_status st = enufft::set_fwd_threads(p, threads, (size_t)prop.sharedMemPerBlock);
+  if (st != ENUFFT_OK) { std::string m = p->last_error; free_plan(p); return fail(nullptr, st, m); }
 
   // ---- tables (FP64 on the host, rounded to the compute precision)
   const int Kx = g.K1, Ky = g.K2;
@@ -465,18 +485,6 @@ enufft_status enufft_plan(enufft_plan_t *out, int64_t n_cells, const int64_t *ce
                    std::make_pair(&p->d_tw1, &tw1), std::make_pair(&p->d_tw2, &tw2)}) {
     st = upload_table(tb.first, *tb.second, "tables");
     if (st != ENUFFT_OK) { std::string m = p->last_error; free_plan(p); return fail(nullptr, st, m); }
-  }
-
-  // FP32 plans evaluate the kernel as per-tap polynomials when the fit is far
-  // below the requested accuracy (it is for the compiled widths 4..8).
-  if (p->prec == ENUFFT_F32 && W <= enufft::ES_MAXW) {
-    std::vector<double> cf;
-    const double err = fit_es_poly(W, beta, enufft::ES_DEG, cf);
-    if (err <= std::max(0.1 * opts->eps, 1e-6)) {
-      p->es_poly_err = err;
-      p->es.on = 1;
-      for (size_t i = 0; i < cf.size(); ++i) p->es.c[i] = (float)cf[i];
-    }
   }
 
   std::vector<double> win(3 * std::max<int64_t>(1, n_cells), 0.0);

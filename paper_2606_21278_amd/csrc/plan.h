@@ -19,8 +19,9 @@ struct Timing {
 struct UnitTable {                 // EMS units for one (use_pairs, exclude_dc) choice
   bool built = false;
   int32_t J = 0;                   // number of units
-  int32_t Jpad = 0;                // power of two >= J used by the in-LDS sort
+  int32_t Jpad = 0;                // power of two >= max(J, 64): the in-register sort size
   int2 *d_units = nullptr;         // (rep, partner or -1), ascending unit id
+  int4 *d_mode_unit = nullptr;     // [M]: (rep, partner, unit id, 0) of each mode's unit, rep -1: none
 };
 
 }  // namespace enufft
@@ -92,6 +93,7 @@ namespace enufft {
 // Workspace helpers shared by the translation units (defined with the plan).
 void dev_release(enufft_plan_t p, void **ptr, size_t bytes);
 enufft_status install_fwd_schedule(enufft_plan_t p);
+enufft_status set_fwd_threads(enufft_plan_t p, int threads, size_t lds_limit);
 void adj_reset(enufft_plan_t p);
 enufft_status autotune(enufft_plan_t p);
 }  // namespace enufft

@@ -2,11 +2,11 @@
 // synthetic points with the plan's own cell sizes, and an on-disk cache of the
 // choice keyed by device, transform shape and batch layout.
 //
-// Tuned: the smallest forward work item and the number of work items per
-// resident workgroup (how finely large cells are cut, Section 3's batched
-// single-launch schedule), and the adjoint's items per workgroup and row-band
-// count.  The kernel width is not tuned: it is the narrowest that meets eps,
-// and a wider one only adds work.
+// Tuned: the forward workgroup size, the smallest forward work item and the
+// number of work items per resident workgroup (how finely the batched launch
+// cuts large cells), and the adjoint's items per workgroup and row-band count.
+// The kernel width is not tuned: it is the narrowest that meets eps, and a
+// wider one only adds work.
 #include <hip/hip_runtime.h>
 
 #include <sys/stat.h>
@@ -64,7 +64,7 @@ __global__ void tune_points_kernel(const int64_t *off, const double *win, int us
 
 struct Choice {
   int64_t chunk_min = 16384;
-  int fwd_ips = 2, adj_ips = 2, band_mult = 1;
+  int fwd_ips = 2, adj_ips = 2, band_mult = 1, fwd_threads = 512;
   double fwd_ms = 0.0, adj_ms = 0.0;
 };
 
@@ -102,7 +102,8 @@ std::string cache_path() {
 
 bool valid(const Choice &c) {
   const bool pow2 = c.fwd_ips > 0 && c.adj_ips > 0 && c.band_mult > 0;
-  return pow2 && c.chunk_min >= 1024 && c.chunk_min <= (1LL << 24) && c.fwd_ips <= 64 && c.adj_ips <= 64 &&
+  const bool thr = c.fwd_threads == 256 || c.fwd_threads == 512 || c.fwd_threads == 1024;
+  return pow2 && thr && c.chunk_min >= 1024 && c.chunk_min <= (1LL << 24) && c.fwd_ips <= 64 && c.adj_ips <= 64 &&
          c.band_mult <= 8;
 }
 
@@ -116,8 +117,8 @@ bool cache_lookup(const std::string &path, const std::string &key, Choice *out) 
     char k[400];
     long long cm = 0;
     Choice c;
-    if (std::sscanf(line, "%399s %lld %d %d %d %lf %lf", k, &cm, &c.fwd_ips, &c.adj_ips, &c.band_mult, &c.fwd_ms,
-                    &c.adj_ms) == 7 &&
+    if (std::sscanf(line, "%399s %lld %d %d %d %d %lf %lf", k, &cm, &c.fwd_ips, &c.adj_ips, &c.band_mult,
+                    &c.fwd_threads, &c.fwd_ms, &c.adj_ms) == 8 &&
         key == k) {
       c.chunk_min = cm;
       if (valid(c)) { *out = c; found = true; }   // the last valid entry wins
@@ -131,8 +132,8 @@ void cache_store(const std::string &path, const std::string &key, const Choice &
   if (path.empty()) return;
   FILE *f = std::fopen(path.c_str(), "a");
   if (!f) return;
-  std::fprintf(f, "%s %lld %d %d %d %.6f %.6f\n", key.c_str(), (long long)c.chunk_min, c.fwd_ips, c.adj_ips,
-               c.band_mult, c.fwd_ms, c.adj_ms);
+  std::fprintf(f, "%s %lld %d %d %d %d %.6f %.6f\n", key.c_str(), (long long)c.chunk_min, c.fwd_ips, c.adj_ips,
+               c.band_mult, c.fwd_threads, c.fwd_ms, c.adj_ms);
   std::fclose(f);
 }
 
@@ -170,7 +171,7 @@ enufft_status time_calls(enufft_plan_t t, F fn, int reps, hipEvent_t e0, hipEven
 }
 
 // Timed trials on plan t (the plan itself or a plan over a prefix of its cells).
-enufft_status run_trials(enufft_plan_t t, Choice *best) {
+enufft_status run_trials(enufft_plan_t t, size_t lds_limit, Choice *best) {
   const int64_t Q = t->n_points;
   const size_t el = t->elem;
   const int64_t M = (int64_t)t->N1 * t->N2;
@@ -212,25 +213,31 @@ enufft_status run_trials(enufft_plan_t t, Choice *best) {
   enufft_status st = ENUFFT_OK;
   const int reps = 3;
 
-  // forward: chunk floor x items per resident workgroup
+  // forward: workgroup size x chunk floor x items per resident workgroup
   double fbest = 1e300;
   Choice c = *best;
-  for (int64_t cm : {4096LL, 16384LL, 65536LL}) {
-    for (int ips : {1, 2, 4, 8}) {
-      t->fwd_chunk_min = cm;
-      t->fwd_items_per_slot = ips;
-      st = install_fwd_schedule(t);
+  for (int thr : {512, 1024}) {
+    if (set_fwd_threads(t, thr, lds_limit) != ENUFFT_OK) continue;   // does not fit: not a candidate
+    for (int64_t cm : {4096LL, 16384LL, 65536LL}) {
+      for (int ips : {1, 2, 4}) {
+        t->fwd_chunk_min = cm;
+        t->fwd_items_per_slot = ips;
+        st = install_fwd_schedule(t);
+        if (st != ENUFFT_OK) break;
+        double ms = 0.0;
+        st = time_calls(t, [&] { return enufft_type1_batched(t, x, y, h, w, f); }, reps, e0, e1, &ms);
+        if (st != ENUFFT_OK) break;
+        if (ms < fbest) { fbest = ms; c.chunk_min = cm; c.fwd_ips = ips; c.fwd_threads = thr; }
+      }
       if (st != ENUFFT_OK) break;
-      double ms = 0.0;
-      st = time_calls(t, [&] { return enufft_type1_batched(t, x, y, h, w, f); }, reps, e0, e1, &ms);
-      if (st != ENUFFT_OK) break;
-      if (ms < fbest) { fbest = ms; c.chunk_min = cm; c.fwd_ips = ips; }
     }
     if (st != ENUFFT_OK) break;
   }
+  if (fbest == 1e300 && st == ENUFFT_OK) st = tune_err(t, ENUFFT_EDEVICE, "no forward launch shape fits");
   // adjoint: items per resident workgroup x row bands (the forward output above
   // stands in for the cotangent source; keep is all ones)
   double abest = 1e300;
+  if (st == ENUFFT_OK) st = set_fwd_threads(t, c.fwd_threads, lds_limit);
   if (st == ENUFFT_OK) {
     t->fwd_chunk_min = c.chunk_min;
     t->fwd_items_per_slot = c.fwd_ips;
@@ -279,7 +286,7 @@ enufft_status autotune(enufft_plan_t p) {
     if (const char *s = std::getenv("ENUFFT_TUNE_MAX_POINTS")) cap = std::max<int64_t>(1 << 16, std::atoll(s));
     enufft_status st;
     if (p->n_points <= cap) {
-      st = run_trials(p, &c);
+      st = run_trials(p, (size_t)prop.sharedMemPerBlock, &c);
     } else {
       int64_t nc = 0;
       while (nc < p->n_cells && p->offsets[nc + 1] <= cap) ++nc;
@@ -290,13 +297,15 @@ enufft_status autotune(enufft_plan_t p) {
       st = enufft_plan(&sub, nc, p->offsets.data(), p->windows_host.empty() ? nullptr : p->windows_host.data(), &o,
                        p->stream);
       if (st != ENUFFT_OK) return tune_err(p, st, std::string("prefix plan: ") + enufft_last_error(nullptr));
-      st = run_trials(sub, &c);
+      st = run_trials(sub, (size_t)prop.sharedMemPerBlock, &c);
       if (st != ENUFFT_OK) p->last_error = sub->last_error;
       (void)enufft_destroy(sub);
     }
     if (st != ENUFFT_OK) return st;
     cache_store(path, key, c);
   }
+  enufft_status st = set_fwd_threads(p, c.fwd_threads, (size_t)prop.sharedMemPerBlock);
+  if (st != ENUFFT_OK) return st;
   p->fwd_chunk_min = c.chunk_min;
   p->fwd_items_per_slot = c.fwd_ips;
   p->adj_items_per_slot = c.adj_ips;
