@@ -12,12 +12,19 @@ A step is one pass of the whole hot path: batched type-1 (spread, FFT,
 deconvolve, crop), EMS, and the type-2 adjoint giving d(sum retained power) /
 d(h, x, y).  The JSON line reports NU points/s of type-1 + EMS (kernel time
 from HIP events on the plan's stream), the fwd+bwd step time, the per-cell
-launch loop on the same GPU, the spreading kernel against the HBM roofline and
+launch loop on the same GPU, the forward kernel against the HBM roofline and
 the FP64 CPU oracle timed on a bounded sample of cells.  Parity of this exact
 launch configuration against the oracle is checked by the GPU test suite
 (full-size sampled cells), not here.
+
+Profiles: ``--summarize DIR`` turns rocprofv3 output collected from this script
+(kernel-trace stats CSV and FETCH_SIZE / WRITE_SIZE counter CSVs) into the
+text summaries and the traffic record kept under profiles/.
 """
 import argparse
+import csv
+import glob
+import hashlib
 import json
 import math
 import os
@@ -26,9 +33,38 @@ import time
 
 import numpy as np
 
+HERE = os.path.dirname(os.path.abspath(__file__))
+TRAFFIC_FILE = os.path.join(HERE, "profiles", "fwd_kernel_c3_traffic.json")
+# sources whose text fixes the forward kernel's code (traffic is void once they change)
+FWD_SOURCES = ["paper_2606_21278_amd/csrc/fwd.hip", "paper_2606_21278_amd/csrc/device_common.h",
+               "paper_2606_21278_amd/csrc/launch.h"]
+FWD_KERNEL = "fwd_kernel"
+COPY_KERNEL = "bitwise_not"
+
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def fwd_source_hash():
+    h = hashlib.sha256()
+    for rel in FWD_SOURCES:
+        with open(os.path.join(HERE, rel), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per forward launch from the committed counter record, if it was
+    taken with the current kernel source; else None."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_hash") != fwd_source_hash():
+        return None
+    return rec.get("bytes_per_launch")
 
 
 def cpu_baseline(batch, seconds, seed=1):
@@ -63,6 +99,88 @@ def cpu_baseline(batch, seconds, seed=1):
             "sample": "%d seeded cells, %d points, type-1 direct sums + EMS, %.1f s" % (len(cells), pts, dt)}
 
 
+# ------------------------------------------------------------------ profile summaries
+
+def _rows(path):
+    with open(path, newline="") as fh:
+        return list(csv.DictReader(fh))
+
+
+def _short(name):
+    name = name.split("(")[0]
+    return name if len(name) < 90 else name[:87] + "..."
+
+
+def summarize(d, command_trace, command_fetch, command_write, copy_mb):
+    """Write profiles/ summaries from rocprofv3 CSVs in directory d:
+    *kernel_stats.csv (kernel trace), fetch*counter_collection.csv, write*counter_collection.csv."""
+    out_dir = os.path.join(HERE, "profiles")
+    os.makedirs(out_dir, exist_ok=True)
+    stats = sorted(glob.glob(os.path.join(d, "**", "*kernel_stats.csv"), recursive=True))
+    lines = ["# Forward kernel, C3 workload: kernel-trace statistics", "",
+             "Command (repo root, one MI355X):", "", "    " + command_trace, "",
+             "Source hash of the forward kernel: `%s`" % fwd_source_hash(), "",
+             "| kernel | calls | total ms | average us | min us | max us | % |", "|---|---|---|---|---|---|---|"]
+    fwd_avg_us = None
+    if stats:
+        rows = _rows(stats[0])
+        for r in rows[:12]:
+            avg = float(r["AverageNs"]) / 1e3
+            lines.append("| %s | %s | %.3f | %.2f | %.2f | %.2f | %.2f |" % (
+                _short(r["Name"]), r["Calls"], float(r["TotalDurationNs"]) / 1e6, avg,
+                float(r["MinNs"]) / 1e3, float(r["MaxNs"]) / 1e3, float(r["Percentage"])))
+            if FWD_KERNEL in r["Name"] and fwd_avg_us is None:
+                fwd_avg_us = avg
+    with open(os.path.join(out_dir, "fwd_kernel_c3_kernel_trace.md"), "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+
+    def per_dispatch(pattern, counter):
+        files = sorted(glob.glob(os.path.join(d, "**", pattern), recursive=True))
+        vals = {}
+        for fpath in files:
+            for r in _rows(fpath):
+                if r["Counter_Name"] != counter:
+                    continue
+                name = r["Kernel_Name"]
+                key = FWD_KERNEL if FWD_KERNEL in name else (COPY_KERNEL if COPY_KERNEL in name else None)
+                if key:
+                    vals.setdefault(key, []).append(float(r["Counter_Value"]))
+        return vals
+
+    fetch = per_dispatch("fetch*counter_collection.csv", "FETCH_SIZE")
+    write = per_dispatch("write*counter_collection.csv", "WRITE_SIZE")
+    copy_bytes = copy_mb * 1024.0 * 1024.0
+    res = {"command_fetch": command_fetch, "command_write": command_write, "copy_mb": copy_mb,
+           "source_hash": fwd_source_hash()}
+    if fetch.get(COPY_KERNEL) and write.get(COPY_KERNEL) and fetch.get(FWD_KERNEL) and write.get(FWD_KERNEL):
+        # counters are KiB per dispatch; scale by what they read for a copy of known size
+        f_copy = max(fetch[COPY_KERNEL]) * 1024.0
+        w_copy = max(write[COPY_KERNEL]) * 1024.0
+        sf, sw = copy_bytes / f_copy, copy_bytes / w_copy
+        fb = float(np.median(fetch[FWD_KERNEL])) * 1024.0 * sf
+        wb = float(np.median(write[FWD_KERNEL])) * 1024.0 * sw
+        res.update({"fetch_scale": sf, "write_scale": sw, "fetch_bytes": fb, "write_bytes": wb,
+                    "bytes_per_launch": fb + wb, "dispatches": len(fetch[FWD_KERNEL])})
+    with open(TRAFFIC_FILE, "w") as fh:
+        json.dump(res, fh, indent=1)
+    lines = ["# Forward kernel, C3 workload: HBM traffic counters", "",
+             "FETCH_SIZE and WRITE_SIZE (KiB per dispatch) from two separate rocprofv3 passes:", "",
+             "    " + command_fetch, "    " + command_write, "",
+             "Each counter is scaled by what it reads for a plain streaming kernel (bitwise_not of %d MiB "
+             "int32, read once and written once) in the same run." % copy_mb,
+             ""]
+    for k in ("fetch_scale", "write_scale", "fetch_bytes", "write_bytes", "bytes_per_launch", "dispatches"):
+        if k in res:
+            lines.append("- %s: %s" % (k, ("%.4g" % res[k]) if isinstance(res[k], float) else res[k]))
+    if fwd_avg_us:
+        lines.append("- forward kernel average duration (kernel trace): %.1f us" % fwd_avg_us)
+    with open(os.path.join(out_dir, "fwd_kernel_c3_hbm_traffic.md"), "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print(json.dumps(res))
+
+
+# ------------------------------------------------------------------ benchmark
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -73,9 +191,17 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--shuffled", action="store_true", help="random point order within each cell")
+    ap.add_argument("--autotune", action="store_true", help="plan with the autotuner")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MB",
                     help="after timing, run one plain device copy of this size (for profiler byte counters)")
+    ap.add_argument("--summarize", metavar="DIR", help="write profiles/ summaries from rocprofv3 CSVs in DIR")
+    ap.add_argument("--cmd-trace", default="")
+    ap.add_argument("--cmd-fetch", default="")
+    ap.add_argument("--cmd-write", default="")
     args = ap.parse_args()
+    if args.summarize:
+        summarize(args.summarize, args.cmd_trace, args.cmd_fetch, args.cmd_write, args.calibrate_copy or 1024)
+        return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU: every box here has a single MI355X and this build has no "
@@ -84,22 +210,23 @@ def main():
         sys.exit(2)
 
     import torch
-    here = os.path.dirname(os.path.abspath(__file__))
-    sys.path.insert(0, here)
+    sys.path.insert(0, HERE)
     import paper_2606_21278_amd as enf
     import synth
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     t0 = time.perf_counter()
-    batch = synth.config3(device=dev, n_cells=args.cells, shuffled=args.shuffled)
+    batch = synth.config3(device=dev, n_cells=args.cells, shuffled=args.shuffled,
+                          progress=lambda s: log("generating: %s (%.0f s)" % (s, time.perf_counter() - t0)))
     torch.cuda.synchronize()
     log("generated %s: %d cells, %d points in %.1f s" % (batch.name, batch.n_cells, batch.n_points,
                                                          time.perf_counter() - t0))
     gb = batch.to(device=dev, dtype=torch.float32)
     del batch.x, batch.y, batch.h, batch.w
     batch.x, batch.y, batch.h, batch.w = gb.x, gb.y, gb.h, gb.w
-    plan = enf.Plan(gb.cell_offsets, gb.windows, n_modes=gb.n_modes, sigma=gb.sigma, eps=gb.eps, precision="f32")
+    plan = enf.Plan(gb.cell_offsets, gb.windows, n_modes=gb.n_modes, sigma=gb.sigma, eps=gb.eps, precision="f32",
+                    autotune=args.autotune)
     info = plan.info()
     log("plan", info)
     prm = enf.EmsParams()
@@ -112,9 +239,10 @@ def main():
         grads = plan.retained_power_adjoint(gb.x, gb.y, gb.h, gb.w, f, keep)
         return f, keep, ks, st, grads
 
-    for _ in range(args.warmup):
+    for i in range(args.warmup):
         step()
-    torch.cuda.synchronize()
+        torch.cuda.synchronize()
+        log("warm-up step %d done" % (i + 1))
     plan.get_timing()          # discard warm-up records
     plan.set_timing(True)
     stream = torch.cuda.current_stream()
@@ -136,13 +264,14 @@ def main():
     log("per step: type1 %.3f ms, ems %.3f ms, adjoint %.3f ms, step %.3f ms" % (t1, tems, tadj, ms_step))
 
     if args.calibrate_copy > 0:
+        # one streaming kernel of known traffic whose name no other kernel of this run shares
         n = args.calibrate_copy * 1024 * 1024 // 4
-        src = torch.ones(n, dtype=torch.float32, device=dev)
+        src = torch.ones(n, dtype=torch.int32, device=dev)
         dst = torch.empty_like(src)
         torch.cuda.synchronize()
-        dst.copy_(src)
+        torch.bitwise_not(src, out=dst)
         torch.cuda.synchronize()
-        log("copy calibration: %d MB read + %d MB written" % (args.calibrate_copy, args.calibrate_copy))
+        log("copy calibration: %d MiB read + %d MiB written" % (args.calibrate_copy, args.calibrate_copy))
         del src, dst
 
     percell = None
@@ -160,11 +289,13 @@ def main():
                    "launches": 2 * batch.n_cells}
         log("per-cell loop %.1f ms" % pc_ms)
 
-    fwd_bytes = 16.0 * Q + 8.0 * M * batch.n_cells        # read x, y, h, w; write f
+    # algorithmic bytes of one forward launch: read x, y, h, w (16 B per point), write f (8 B per mode)
+    fwd_bytes = 16.0 * Q + 8.0 * M * batch.n_cells
     achieved = fwd_bytes / (t1 * 1e-3) / 1e9
+    traffic = measured_traffic() if args.cells is None else None
     roofline = {"bound": "hbm", "achieved": achieved, "peak": 8000.0, "unit": "GB/s",
-                "frac": achieved / 8000.0, "traffic": None, "kernel": "fwd_kernel (spread+FFT+deconv+crop)",
-                "bytes_per_launch": fwd_bytes}
+                "frac": achieved / 8000.0, "traffic": traffic, "kernel": "fwd_kernel (spread+FFT+deconv+crop)",
+                "bytes_per_launch": fwd_bytes, "avg_launch_ms": t1}
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(batch, args.cpu_seconds)
@@ -178,7 +309,8 @@ def main():
                                "Hann window, EMS 95% power, fwd+bwd" if args.cells is None else
                                "first %d icosahedral triangles" % batch.n_cells,
                    "n_cells": batch.n_cells, "n_points": Q, "modes": list(gb.n_modes), "sigma": 2.0, "eps": 1e-5,
-                   "kernel_width": info["kernel_width"], "grid": info["grid"]},
+                   "kernel_width": info["kernel_width"], "grid": info["grid"],
+                   "fwd_threads": info["fwd_threads"], "autotuned": bool(info["tuned"])},
         "type1_ms": t1, "ems_ms": tems, "adjoint_ms": tadj, "fwd_bwd_ms": ms_step,
         "per_cell_loop": percell, "roofline": roofline, "cpu_baseline": cpu,
     }

@@ -71,94 +71,106 @@ __device__ __forceinline__ void spread_point(const FwdArgs<T> &a, double *grid, 
 // order, several per fine-grid cell -- their contributions are summed in a
 // (W + 1) x (W + 2) register window and the window is added to the grid once,
 // which cuts the LDS atomics per point and spreads neighbouring lanes apart.
-// Returns false, having added nothing, for a group that does not fit one
-// window; the caller defers it.
+// Groups that do not fit one window are deferred by the caller.
 constexpr int RUN_K = 4, RUN_SX = 2, RUN_SY = 1;
 
-template <typename T, int W, int P>
-__device__ __forceinline__ bool spread_run(const FwdArgs<T> &a, double *grid, const T (&xs)[RUN_K],
-                                           const T (&ys)[RUN_K], const T (&cs)[RUN_K]) {
-  static_assert(sizeof(T) == 4, "runs are the FP32 path");
-  const Geom &g = a.g;
-  const int pitch = grid_pitch<P>(g);
-  const float halfw = float(W) / 2.0f;
-  // footprint origins and the in-cell offsets v = i0 - t + W/2 (all the taps need)
+// Geometry of one group: footprint origins, the in-cell offsets v = i0 - t + W/2
+// (all the taps need) and the window origin.
+struct RunGeom {
   int ix[RUN_K], iy[RUN_K];
   float vx[RUN_K], vy[RUN_K];
-  int cmin = INT_MAX, rmin = INT_MAX, cmax = INT_MIN, rmax = INT_MIN;
+  int cmin, rmin;
+  bool fits, any;
+};
+
+template <typename T, int W>
+__device__ __forceinline__ RunGeom run_geom(const FwdArgs<T> &a, const float (&xs)[RUN_K], const float (&ys)[RUN_K],
+                                            const float (&cs)[RUN_K]) {
+  const float halfw = float(W) / 2.0f;
+  RunGeom rg;
+  int cmax = INT_MIN, rmax = INT_MIN;
+  rg.cmin = INT_MAX; rg.rmin = INT_MAX;
 #pragma unroll
   for (int k = 0; k < RUN_K; ++k) {
     const FineCoord<float> fx = fine_coord<float>(xs[k], a.s1_hi, a.s1_lo, halfw);
     const FineCoord<float> fy = fine_coord<float>(ys[k], a.s2_hi, a.s2_lo, halfw);
-    ix[k] = fx.i0; iy[k] = fy.i0;
-    vx[k] = tap_v(fx, halfw); vy[k] = tap_v(fy, halfw);
+    rg.ix[k] = fx.i0; rg.iy[k] = fy.i0;
+    rg.vx[k] = tap_v(fx, halfw); rg.vy[k] = tap_v(fy, halfw);
     if (cs[k] != 0.0f) {
-      cmin = min(cmin, ix[k]); cmax = max(cmax, ix[k]);
-      rmin = min(rmin, iy[k]); rmax = max(rmax, iy[k]);
+      rg.cmin = min(rg.cmin, rg.ix[k]); cmax = max(cmax, rg.ix[k]);
+      rg.rmin = min(rg.rmin, rg.iy[k]); rmax = max(rmax, rg.iy[k]);
     }
   }
-  if (rmin == INT_MAX) return true;   // every point outside the window
-  if (!(cmax - cmin <= RUN_SX && rmax - rmin <= RUN_SY)) return false;
-  // Every point enters the window, branch-free: one with c = 0 (outside the
-  // cell window) contributes exact zeros, and its taps stay finite because
-  // the tap offsets are clamped to the kernel's interval.
+  rg.any = rg.rmin != INT_MAX;   // some point inside the cell window
+  rg.fits = !rg.any || (cmax - rg.cmin <= RUN_SX && rmax - rg.rmin <= RUN_SY);
+  return rg;
+}
+
+// Add point k of a fitting group to the window.  Every point enters,
+// branch-free: one with c = 0 (outside the cell window) contributes exact
+// zeros, and its taps stay finite because the tap offsets are clamped to the
+// kernel's interval.  Point 0 initialises the window.
+template <typename T, int W, int P>
+__device__ __forceinline__ void run_add_point(const FwdArgs<T> &a, const RunGeom &rg, int k, float c,
+                                              float (&acc)[W + RUN_SY][W + RUN_SX]) {
   constexpr int WC = W + RUN_SX, WR = W + RUN_SY;
-  float acc[WR][WC];
-#pragma unroll
-  for (int k = 0; k < RUN_K; ++k) {
-    float kx[W], ky[W];
-    if constexpr (P > 0) {
-      es_taps_poly_v<W>(vx[k], a.es, kx);
-      es_taps_poly_v<W>(vy[k], a.es, ky);
-    } else if (a.es.on) {
-      es_taps_poly_v<W>(vx[k], a.es, kx);
-      es_taps_poly_v<W>(vy[k], a.es, ky);
-    } else {
-      es_taps_exact_v<W>(vx[k], a.beta, kx);
-      es_taps_exact_v<W>(vy[k], a.beta, ky);
-    }
-#pragma unroll
-    for (int d = 0; d < W; ++d) ky[d] *= cs[k];
-    const int sx = ix[k] - cmin, sy = iy[k] - rmin;
-    float KX[WC], KY[WR];
-#pragma unroll
-    for (int q = 0; q < WC; ++q) {
-      float v = 0.0f;
-#pragma unroll
-      for (int s = 0; s <= RUN_SX; ++s)
-        if (q - s >= 0 && q - s < W) v = (sx == s) ? kx[q - s] : v;
-      KX[q] = v;
-    }
-#pragma unroll
-    for (int r = 0; r < WR; ++r) {
-      float v = 0.0f;
-#pragma unroll
-      for (int s = 0; s <= RUN_SY; ++s)
-        if (r - s >= 0 && r - s < W) v = (sy == s) ? ky[r - s] : v;
-      KY[r] = v;
-    }
-#pragma unroll
-    for (int r = 0; r < WR; ++r)
-#pragma unroll
-      for (int q = 0; q < WC; ++q) acc[r][q] = (k == 0) ? KY[r] * KX[q] : fmaf(KY[r], KX[q], acc[r][q]);
-    // one point at a time: interleaving the points' taps raises register
-    // pressure past the 128 registers of a 16-wave block
-    __builtin_amdgcn_sched_barrier(0);
+  float kx[W], ky[W];
+  if constexpr (P > 0) {
+    es_taps_poly_v<W>(rg.vx[k], a.es, kx);
+    es_taps_poly_v<W>(rg.vy[k], a.es, ky);
+  } else if (a.es.on) {
+    es_taps_poly_v<W>(rg.vx[k], a.es, kx);
+    es_taps_poly_v<W>(rg.vy[k], a.es, ky);
+  } else {
+    es_taps_exact_v<W>(rg.vx[k], a.beta, kx);
+    es_taps_exact_v<W>(rg.vy[k], a.beta, ky);
   }
-  // flush the whole window (cells outside every footprint add zero); no
-  // per-cell branches, so the adds issue back to back
-  int col[WC];
 #pragma unroll
-  for (int q = 0; q < WC; ++q) col[q] = (cmin + q) & (g.n1 - 1);
-  double *rowp = grid + (rmin & (g.n2 - 1)) * pitch;
+  for (int d = 0; d < W; ++d) ky[d] *= c;
+  const int sx = rg.ix[k] - rg.cmin, sy = rg.iy[k] - rg.rmin;
+  float KX[WC], KY[WR];
 #pragma unroll
   for (int q = 0; q < WC; ++q) {
-    double *cp = rowp + col[q];
+    float v = 0.0f;
 #pragma unroll
-    for (int r = 0; r < WR; ++r)
-      __hip_atomic_fetch_add(cp + r * pitch, (double)acc[r][q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    for (int s = 0; s <= RUN_SX; ++s)
+      if (q - s >= 0 && q - s < W) v = (sx == s) ? kx[q - s] : v;
+    KX[q] = v;
   }
-  return true;
+#pragma unroll
+  for (int r = 0; r < WR; ++r) {
+    float v = 0.0f;
+#pragma unroll
+    for (int s = 0; s <= RUN_SY; ++s)
+      if (r - s >= 0 && r - s < W) v = (sy == s) ? ky[r - s] : v;
+    KY[r] = v;
+  }
+#pragma unroll
+  for (int r = 0; r < WR; ++r)
+#pragma unroll
+    for (int q = 0; q < WC; ++q) acc[r][q] = (k == 0) ? KY[r] * KX[q] : fmaf(KY[r], KX[q], acc[r][q]);
+}
+
+// Add window columns [q0, q1) to the grid (cells outside every footprint add
+// zero; no per-cell branches).  With rev the columns go out mirrored, so two
+// lanes whose windows start at the same cell never add to one address in the
+// same instruction.
+template <int W, int P>
+__device__ __forceinline__ void run_flush_cols(const Geom &g, double *grid, const float (&acc)[W + RUN_SY][W + RUN_SX],
+                                               int cmin, int rmin, bool rev, int q0, int q1) {
+  constexpr int WC = W + RUN_SX, WR = W + RUN_SY;
+  const int pitch = grid_pitch<P>(g);
+  double *rowp = grid + (rmin & (g.n2 - 1)) * pitch;
+#pragma unroll
+  for (int q = q0; q < q1; ++q) {
+    const int qs = rev ? WC - 1 - q : q;
+    double *cp = rowp + ((cmin + qs) & (g.n1 - 1));
+#pragma unroll
+    for (int r = 0; r < WR; ++r) {
+      const float v = rev ? acc[r][WC - 1 - q] : acc[r][q];
+      __hip_atomic_fetch_add(cp + r * pitch, (double)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    }
+  }
 }
 
 // Orders this wave's LDS accesses around the deferred-group queue (LDS
@@ -184,12 +196,17 @@ __device__ __forceinline__ void drain_groups(const FwdArgs<T> &a, double *grid, 
   const T xs[RUN_K] = {xv.x, xv.y, xv.z, xv.w}, ys[RUN_K] = {yv.x, yv.y, yv.z, yv.w};
   const T hs[RUN_K] = {hv.x, hv.y, hv.z, hv.w}, ws[RUN_K] = {wv.x, wv.y, wv.z, wv.w};
   const T halfw = T(W) / T(2);
-#pragma unroll
+  // one copy of the per-point code (instruction-cache footprint of the loop)
+#pragma unroll 1
   for (int k = 0; k < RUN_K; ++k) {
-    const T c = ws[k] * hs[k] * hann_w(a.window_kind, xs[k], ys[k], cx, cy, R, pr);
+    const T xk = k == 0 ? xs[0] : k == 1 ? xs[1] : k == 2 ? xs[2] : xs[3];
+    const T yk = k == 0 ? ys[0] : k == 1 ? ys[1] : k == 2 ? ys[2] : ys[3];
+    const T hk = k == 0 ? hs[0] : k == 1 ? hs[1] : k == 2 ? hs[2] : hs[3];
+    const T wk = k == 0 ? ws[0] : k == 1 ? ws[1] : k == 2 ? ws[2] : ws[3];
+    const T c = wk * hk * hann_w(a.window_kind, xk, yk, cx, cy, R, pr);
     if (c != T(0))
-      spread_point<T, W, P>(a, grid, c, fine_coord<T>(xs[k], a.s1_hi, a.s1_lo, halfw),
-                            fine_coord<T>(ys[k], a.s2_hi, a.s2_lo, halfw));
+      spread_point<T, W, P>(a, grid, c, fine_coord<T>(xk, a.s1_hi, a.s1_lo, halfw),
+                            fine_coord<T>(yk, a.s2_hi, a.s2_lo, halfw));
   }
 }
 
@@ -211,49 +228,53 @@ __device__ __forceinline__ void spread_item(const FwdArgs<T> &a, double *grid, i
   const V *h4 = reinterpret_cast<const V *>(a.h), *w4 = reinterpret_cast<const V *>(a.w);
   if constexpr (kRuns) {
     // Group-to-lane map: in each block of NT consecutive groups, wave w takes
-    // groups w, w + NW, w + 2 NW, ...  Lanes of one wave then hold groups NW
-    // runs (4 NW points) apart, so the windows they add in the same instruction
-    // start at different grid cells even when many points share a cell (LDS
-    // atomics on one address serialise); the NW waves together still consume
-    // every cache line of the block.  Software pipeline: the next block's loads
-    // are in flight while this one spreads.
+    // the 64 groups w 64 .. w 64 + 63 and lane l the group 8 (l mod 8) + l / 8.
+    // Each wave load reads 1 KiB contiguous (whole cache lines, no re-fetch),
+    // lanes l and l + 1 hold groups 8 runs apart, so the windows they add in
+    // the same instruction start at different grid cells even when many
+    // points share a cell (LDS atomics on one address serialise), and the
+    // neighbouring groups of lanes l and l + 8 flush in opposite orders.
     //
     // Groups that do not fit one window (a raster row ends inside the group,
     // or the points are unordered) are queued per wave and spread point by
     // point 64 at a time, so the rare misfit does not stall the other 63 lanes.
-    constexpr int NW = NT / 64;
     const int lane = threadIdx.x & 63;
-    const int lane_off = lane * NW + (threadIdx.x >> 6);
+    const int lane_off = (threadIdx.x >> 6) * 64 + ((lane & 7) << 3) + (lane >> 3);
+    const bool rev = (lane >> 3) & 1;
     const int64_t g0 = body0 / RUN_K, q1 = body1 / RUN_K;
     int64_t q = g0 + lane_off;
     int nq = 0;   // queued groups (the same in every lane)
-    // 16-wave blocks hide load latency by occupancy and need the registers
-    constexpr bool kPrefetch = NT < 1024;
-    V xn{}, yn{}, hn{}, wn{};
-    if (kPrefetch && q < q1) { xn = x4[q]; yn = y4[q]; hn = h4[q]; wn = w4[q]; }
-    for (int64_t qb = g0; qb < q1; qb += NT, q += NT) {
-      const bool live = q < q1;
-      V xv, yv, hv, wv;
-      if constexpr (kPrefetch) {
-        xv = xn; yv = yn; hv = hn; wv = wn;
-        if (q + NT < q1) { xn = x4[q + NT]; yn = y4[q + NT]; hn = h4[q + NT]; wn = w4[q + NT]; }
-      } else if (live) {
-        xv = x4[q]; yv = y4[q]; hv = h4[q]; wv = w4[q];
-      }
-      bool fits = true;
-      if (live) {
-        const T xs[RUN_K] = {xv.x, xv.y, xv.z, xv.w}, ys[RUN_K] = {yv.x, yv.y, yv.z, yv.w};
-        const T hs[RUN_K] = {hv.x, hv.y, hv.z, hv.w}, ws[RUN_K] = {wv.x, wv.y, wv.z, wv.w};
-        T cs[RUN_K];
+    constexpr int WC = W + RUN_SX, WR = W + RUN_SY;
+    // Loads run two blocks ahead in three register buffers (the loop is
+    // unrolled by three so no buffer is copied and the compiler waits only
+    // for the block about to be used): with one workgroup per CU, this is what
+    // keeps enough HBM requests in flight.
+    // Loads are unconditional (control flow around them makes the compiler
+    // wait for every load in flight); past the end they re-read the last group.
+    auto load = [&](V &xb, V &yb, V &hb, V &wb, int64_t qq) {
+      const int64_t qc = qq < q1 ? qq : q1 - 1;
+      xb = x4[qc]; yb = y4[qc]; hb = h4[qc]; wb = w4[qc];
+    };
+    auto step = [&](const V &xv, const V &yv, const V &hv, const V &wv, int64_t qq) {
+      const bool live = qq < q1;
+      const float xs[RUN_K] = {xv.x, xv.y, xv.z, xv.w}, ys[RUN_K] = {yv.x, yv.y, yv.z, yv.w};
+      float cs[RUN_K];
 #pragma unroll
-        for (int k = 0; k < RUN_K; ++k) cs[k] = ws[k] * hs[k] * hann_w(a.window_kind, xs[k], ys[k], cx, cy, R, pr);
-        fits = spread_run<T, W, P>(a, grid, xs, ys, cs);
+      for (int k = 0; k < RUN_K; ++k)
+        cs[k] = live ? (&wv.x)[k] * (&hv.x)[k] * hann_w(a.window_kind, xs[k], ys[k], cx, cy, R, pr) : 0.0f;
+      const RunGeom rg = run_geom<T, W>(a, xs, ys, cs);
+      const bool defer = live && !rg.fits;
+      if (live && rg.any && rg.fits) {
+        float acc[WR][WC];
+#pragma unroll
+        for (int k = 0; k < RUN_K; ++k) run_add_point<T, W, P>(a, rg, k, cs[k], acc);
+        run_flush_cols<W, P>(a.g, grid, acc, rg.cmin, rg.rmin, rev, 0, WC);
       }
-      const uint64_t m = __ballot(!fits);
+      const uint64_t m = __ballot(defer);
       if (m != 0) {
-        if (!fits) {
+        if (defer) {
           const int pos = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-          queue[nq + pos] = (int)(q - g0);   // nq < 64 here, so nq + pos < FWD_QCAP
+          queue[nq + pos] = (int)(qq - g0);   // nq < 64 here, so nq + pos < FWD_QCAP
         }
         nq += __popcll(m);
         if (nq >= 64) {
@@ -266,6 +287,19 @@ __device__ __forceinline__ void spread_item(const FwdArgs<T> &a, double *grid, i
           wave_lds_sync();
         }
       }
+    };
+    V x0{}, y0{}, h0{}, w0{}, x1{}, y1{}, h1{}, w1{}, x2{}, y2{}, h2{}, w2{};
+    if (q1 > g0) {
+      load(x0, y0, h0, w0, q);
+      load(x1, y1, h1, w1, q + NT);
+    }
+    for (int64_t qb = g0; qb < q1; qb += 3 * NT, q += 3 * NT) {
+      load(x2, y2, h2, w2, q + 2 * NT);
+      step(x0, y0, h0, w0, q);
+      load(x0, y0, h0, w0, q + 3 * NT);
+      step(x1, y1, h1, w1, q + NT);
+      load(x1, y1, h1, w1, q + 4 * NT);
+      step(x2, y2, h2, w2, q + 2 * NT);
     }
     if (nq > 0) {
       wave_lds_sync();

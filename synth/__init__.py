@@ -191,7 +191,7 @@ def _draw_terrain(rng: np.random.Generator, S: int, kmax: float, slope: float):
 
 
 def _eval_terrain(x: torch.Tensor, y: torch.Tensor, cell_of: torch.Tensor, terr: Terrain,
-                  offsets: np.ndarray, gen: torch.Generator, chunk: int = 1 << 20) -> torch.Tensor:
+                  offsets: np.ndarray, gen: torch.Generator, chunk: int = 1 << 20, progress=None) -> torch.Tensor:
     """Evaluate the sinusoid sums (float64), rescale per cell to the target std, add noise."""
     dev = x.device
     kx = torch.as_tensor(terr.kx, device=dev)
@@ -207,15 +207,33 @@ def _eval_terrain(x: torch.Tensor, y: torch.Tensor, cell_of: torch.Tensor, terr:
         yy = y[s:e].to(torch.float64)[:, None]
         arg = xx * kx[c] + yy * ky[c] + ph[c]
         raw[s:e] = (torch.cos(arg) * am[c]).sum(dim=1)
-    n_cells = len(offsets) - 1
+        if progress and (s // chunk) % 128 == 127:
+            progress("heights: %d of %d points" % (e, n))
     cnt = torch.as_tensor(np.diff(offsets), device=dev, dtype=torch.float64)
-    mean = torch.zeros(n_cells, dtype=torch.float64, device=dev).index_add_(0, cell_of, raw) / cnt.clamp(min=1)
+    mean = _segment_sum(raw, offsets) / cnt.clamp(min=1)
     dev2 = (raw - mean[cell_of]) ** 2
-    var = torch.zeros(n_cells, dtype=torch.float64, device=dev).index_add_(0, cell_of, dev2) / cnt.clamp(min=1)
+    var = _segment_sum(dev2, offsets) / cnt.clamp(min=1)
     scale = torch.as_tensor(terr.std, device=dev) / var.sqrt().clamp(min=1e-300)
     h = raw * scale[cell_of]
     h += terr.noise * torch.randn(n, dtype=torch.float64, device=dev, generator=gen)
     return h
+
+
+def _segment_sum(v: torch.Tensor, offsets: np.ndarray, chunk: int = 1 << 24) -> torch.Tensor:
+    """Per-cell sums of a cell-contiguous array (chunked prefix sums; no atomics)."""
+    dev = v.device
+    n_cells = len(offsets) - 1
+    off = torch.as_tensor(offsets, device=dev)
+    out = torch.zeros(n_cells, dtype=torch.float64, device=dev)
+    for s in range(0, v.numel(), chunk):
+        e = min(v.numel(), s + chunk)
+        ps = torch.zeros(e - s + 1, dtype=torch.float64, device=dev)
+        ps[1:] = torch.cumsum(v[s:e].to(torch.float64), 0)
+        # the part of every cell inside [s, e)
+        a = off[:-1].clamp(s, e) - s
+        b = off[1:].clamp(s, e) - s
+        out += ps[b] - ps[a]
+    return out
 
 
 def _cell_index(offsets: np.ndarray, device) -> torch.Tensor:
@@ -322,14 +340,16 @@ def fd_sample(batch: Batch, n_cells: int = 8, n_points: int = 64, seed: int = 20
 # --------------------------------------------------------------------------- icosahedral cells
 
 def config3(device="cpu", n_cells: int | None = None, count_scale: float = 1.0, seed_config: int = 3,
-            precision: str = "f32", shuffled: bool = False, chunk_candidates: int = 1 << 27) -> Batch:
+            precision: str = "f32", shuffled: bool = False, chunk_candidates: int = 1 << 27,
+            progress=None) -> Batch:
     """20,480 triangles of a 5x subdivided icosahedron in local tangent-plane frames (longest
     edge 2*pi), lognormal counts (median 2e4, sigma 1.2, clipped 500..5e5), jittered square
     lattice (spacing sqrt(0.7 area / Q_c), jitter +-0.25 spacing, 30 % dropout, raster order),
     heights as config 1, weights area/N_c, Hann centred on the centroid with R = max
     centroid-vertex distance, 64 x 64 modes.
 
-    ``n_cells`` keeps the first n cells (same per-cell data as the full set)."""
+    ``n_cells`` keeps the first n cells (same per-cell data as the full set).  ``progress``,
+    if given, is called with a short text after each generation chunk."""
     tris = local_triangles(5)
     F = len(tris)
     rng0 = np.random.Generator(np.random.PCG64(1000 * seed_config))
@@ -393,6 +413,8 @@ def config3(device="cpu", n_cells: int | None = None, count_scale: float = 1.0, 
         cnts[c0:c1] = torch.bincount(cell_of[keep] - c0, minlength=c1 - c0).cpu().numpy()
         del T, px, py, jx, jy, local, cell_of
         c0 = c1
+        if progress:
+            progress("positions: %d of %d cells" % (c1, n_cells))
     x = torch.cat(xs); y = torch.cat(ys)
     off = np.concatenate([[0], np.cumsum(cnts)]).astype(np.int64)
     if shuffled:
@@ -400,7 +422,7 @@ def config3(device="cpu", n_cells: int | None = None, count_scale: float = 1.0, 
         key = ci.to(torch.float64) + torch.rand(x.numel(), dtype=torch.float64, device=device, generator=gen) * 0.5
         perm = torch.argsort(key)
         x, y = x[perm], y[perm]
-    h = _eval_terrain(x, y, _cell_index(off, device), terr, off, gen)
+    h = _eval_terrain(x, y, _cell_index(off, device), terr, off, gen, progress=progress)
     cen = tris.mean(axis=1)
     Rw = np.linalg.norm(tris - cen[:, None, :], axis=-1).max(axis=1)
     win = np.concatenate([cen, Rw[:, None]], axis=1)
