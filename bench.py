@@ -99,6 +99,105 @@ def cpu_baseline(batch, seconds, seed=1):
             "sample": "%d seeded cells, %d points, type-1 direct sums + EMS, %.1f s" % (len(cells), pts, dt)}
 
 
+def cpu_baseline_points(batch, seconds, seed=1):
+    """The FP64 oracle's type-1 direct sums + EMS on a seeded sample of one cell's
+    points (all modes), scaled to points per second."""
+    import oracle
+    rng = np.random.default_rng(seed)
+    N1, N2 = batch.n_modes
+    win = batch.windows[:1]
+
+    def run(n):
+        idx = np.sort(rng.choice(batch.n_points, size=n, replace=False))
+        it = __import__("torch").as_tensor(idx, device=batch.x.device)
+        g = lambda t: t[it].cpu().double().numpy()
+        x, y, h, w = g(batch.x), g(batch.y), g(batch.h), g(batch.w)
+        off = np.array([0, n], dtype=np.int64)
+        t0 = time.perf_counter()
+        f = oracle.type1(off, x, y, h, w, win, (N1, N2), kind=1)
+        oracle.ems_batched(f, oracle.EmsParams())
+        return time.perf_counter() - t0
+
+    n = 2000
+    dt = run(n)
+    n = int(min(batch.n_points, max(n, n * seconds / max(dt, 1e-6))))
+    dt = run(n)
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": n / dt, "unit": "NU points/s", "cores": threads, "kind": "oracle",
+            "sample": "%d seeded points of the cell, type-1 direct sums over all %dx%d modes + EMS, %.1f s"
+                      % (n, N1, N2, dt)}
+
+
+def bench_c4(args, torch, enf, synth, dev):
+    """The single high-resolution cell: 1e8 clustered points, 512 x 512 modes on a
+    1024^2 grid (tile sort, tiled spreading into HBM, row/column FFT passes, EMS over
+    131,583 units with the device sort, tiled adjoint)."""
+    t0 = time.perf_counter()
+    b = synth.config4(device=dev, Q=args.points, precision=args.precision,
+                      progress=lambda s: log("generating: %s (%.0f s)" % (s, time.perf_counter() - t0)))
+    torch.cuda.synchronize()
+    log("generated %s in %.1f s" % (b.name, time.perf_counter() - t0))
+    plan = enf.Plan(b.cell_offsets, b.windows, n_modes=b.n_modes, sigma=b.sigma, eps=b.eps,
+                    precision=args.precision)
+    info = plan.info()
+    log("plan", info)
+    prm = enf.EmsParams()
+    Q = b.n_points
+    N1, N2 = b.n_modes
+
+    def step():
+        f = plan.type1(b.x, b.y, b.h, b.w)
+        keep, ks, st = plan.ems(f, prm)
+        grads = plan.retained_power_adjoint(b.x, b.y, b.h, b.w, f, keep)
+        return f, keep, ks, st, grads
+
+    for i in range(args.warmup):
+        step()
+        torch.cuda.synchronize()
+        log("warm-up step %d done" % (i + 1))
+    plan.get_timing()
+    plan.set_timing(True)
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(args.steps):
+        step()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    plan.set_timing(False)
+    ms_step = e0.elapsed_time(e1) / args.steps
+    tm = plan.get_timing()
+    t1 = tm["type1_ms"] / max(1, tm["type1_launches"])
+    tems = tm["ems_ms"] / max(1, tm["ems_launches"])
+    tadj = tm["adjoint_ms"] / max(1, tm["adjoint_launches"])
+    log("per step: type1 %.3f ms, ems %.3f ms, adjoint %.3f ms, step %.3f ms" % (t1, tems, tadj, ms_step))
+    el = 8 if args.precision == "f64" else 4
+    # algorithmic bytes of the type-1 pass: read x, y, h, w; write f
+    t1_bytes = 4.0 * el * Q + 2.0 * el * N1 * N2
+    achieved = t1_bytes / (t1 * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": achieved, "peak": 8000.0, "unit": "GB/s", "frac": achieved / 8000.0,
+                "traffic": None, "kernel": "type-1 pass (tile sort + tiled spreading + row/column FFT passes)",
+                "bytes_per_launch": t1_bytes, "avg_launch_ms": t1}
+    cpu = None if args.no_cpu_baseline else cpu_baseline_points(b, args.cpu_seconds)
+    if cpu:
+        log("cpu baseline", cpu)
+    out = {
+        "metric": "NU points/s batched type-1+EMS at rel-l2 5e-5 vs per-cell loop; fwd+bwd ms",
+        "value": Q / ((t1 + tems) * 1e-3), "unit": "NU points/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": args.precision, "data": "synthetic (seeded clustered hexagon terrain)",
+        "config": {"workload": "one hexagon, %d clustered points, %dx%d modes, sigma 2, eps %g, Hann window, "
+                               "EMS 95%% power, fwd+bwd" % (Q, N1, N2, b.eps),
+                   "n_cells": 1, "n_points": Q, "modes": [N1, N2], "sigma": 2.0, "eps": b.eps,
+                   "kernel_width": info["kernel_width"], "grid": info["grid"]},
+        "type1_ms": t1, "ems_ms": tems, "adjoint_ms": tadj, "fwd_bwd_ms": ms_step,
+        "per_cell_loop": None, "roofline": roofline, "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
 # ------------------------------------------------------------------ profile summaries
 
 def _rows(path):
@@ -198,6 +297,10 @@ def main():
     ap.add_argument("--cmd-trace", default="")
     ap.add_argument("--cmd-fetch", default="")
     ap.add_argument("--cmd-write", default="")
+    ap.add_argument("--workload", choices=["c3", "c4"], default="c3",
+                    help="c3: the 20,480-cell batch (default); c4: the single high-resolution cell")
+    ap.add_argument("--precision", choices=["f32", "f64"], default="f32", help="c4 only")
+    ap.add_argument("--points", type=int, default=100_000_000, help="c4 only: points in the cell")
     args = ap.parse_args()
     if args.summarize:
         summarize(args.summarize, args.cmd_trace, args.cmd_fetch, args.cmd_write, args.calibrate_copy or 1024)
@@ -216,6 +319,9 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.workload == "c4":
+        bench_c4(args, torch, enf, synth, dev)
+        return
     t0 = time.perf_counter()
     batch = synth.config3(device=dev, n_cells=args.cells, shuffled=args.shuffled,
                           progress=lambda s: log("generating: %s (%.0f s)" % (s, time.perf_counter() - t0)))

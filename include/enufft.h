@@ -68,8 +68,12 @@ typedef enum { ENUFFT_WIN_NONE = 0, ENUFFT_WIN_HANN_RADIAL = 1 } enufft_window_k
 typedef struct { double cx, cy, radius; } enufft_window;
 
 /* Transform options.
- *   n_modes   N1 (along x) and N2 (along y), each in [1, 64] for this build's
- *             LDS-resident path (the fine grid must fit one workgroup's LDS).
+ *   n_modes   N1 (along x) and N2 (along y), each >= 1.  Boxes up to 64 per axis
+ *             whose fine grid is at most 128 per axis keep the whole grid in one
+ *             workgroup's LDS; larger ones take the large-cell path (grid in HBM,
+ *             points sorted by 32 x 32 grid tiles, each axis widened to >= 64).
+ *             A fine grid above 4096 per axis or above 2^23 cells in total is
+ *             ENUFFT_EUNSUPPORTED.
  *   sigma     oversampling factor (>= 1.25); the fine grid per axis is the
  *             smallest power of two >= max(16, sigma * N) (Section 2.1.2, Step 1).
  *   eps       requested relative accuracy of the spreading approximation; sets the
@@ -160,7 +164,10 @@ enufft_status enufft_set_stream(enufft_plan_t p, void *hip_stream);
  *   f           device, n_cells * N2 * N1 complex: written in full.
  * One persistent launch spreads every cell into an LDS-resident fine grid,
  * runs the FFT in LDS, deconvolves and crops; cells larger than one work
- * item are spread by several workgroups and merged by the last to finish. */
+ * item are spread by several workgroups and merged by the last to finish.
+ * Large-cell plans instead run, per cell, a device sort of the points by grid
+ * tile, tiled spreading into an FP64 grid in HBM, and row and column FFT
+ * passes with the deconvolution and crop fused into the column pass. */
 enufft_status enufft_type1_batched(enufft_plan_t p, const void *x, const void *y, const void *h,
                                    const void *w, void *f);
 
@@ -174,7 +181,9 @@ enufft_status enufft_type1_batched(enufft_plan_t p, const void *x, const void *y
  *               theta(K*), J*) with T the total unit energy and P the kept power
  *               sum |f_k|^2.  Energies, sums and the cumulative threshold are FP64.
  * Units are ordered by descending energy, ties by ascending row-major index of
- * the unit's representative (the member with k_y > 0, or k_y = 0 and k_x > 0). */
+ * the unit's representative (the member with k_y > 0, or k_y = 0 and k_x > 0).
+ * Up to 4096 units per cell are sorted in registers by one workgroup per cell;
+ * more take a device bitonic sort per cell. */
 enufft_status enufft_ems(enufft_plan_t p, const void *f, const enufft_ems_params *prm,
                          const double *mode_weight, uint8_t *keep, int32_t *k_star, double *stats);
 

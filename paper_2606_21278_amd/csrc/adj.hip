@@ -102,6 +102,105 @@ __device__ void extract_band(const Geom &g, const T *ws, int cpitch, T *db, int 
   __syncthreads();
 }
 
+// Gradients at one point from the band's three grids (W x W taps each), if the
+// point's footprint starts in this band; the chain rule through the strength
+// c_j = w_j W(x_j) h_j turns the interpolated u, du/dx, du/dy into dL/dh,
+// dL/dx, dL/dy.
+template <typename T, int W>
+__device__ __forceinline__ void gather_point(const AdjArgs<T> &a, const T *Gu, const T *Gx, const T *Gy, int band_lo,
+                                             int64_t j, T xj, T yj, T hj, T wj, T cx, T cy, T R, T pr) {
+  const Geom &g = a.g;
+  const T halfw = T(W) / T(2);
+  const FineCoord<T> fy = fine_coord<T>(yj, a.s2_hi, a.s2_lo, halfw);
+  const int r0 = (fy.i0 & (g.n2 - 1)) - band_lo;    // first footprint row, band-local
+  if (r0 < 0 || r0 >= a.band_rows) return;
+  const FineCoord<T> fx = fine_coord<T>(xj, a.s1_hi, a.s1_lo, halfw);
+  const int n1 = g.n1, pitch = g.pitch;
+  T kx[W], ky[W];
+  int cp[W];
+  es_taps<T, W>(fx, a.beta, a.es, kx);
+  es_taps<T, W>(fy, a.beta, a.es, ky);
+#pragma unroll
+  for (int d = 0; d < W; ++d) cp[d] = fft_pos((fx.i0 + d) & (n1 - 1), n1);
+  T u = 0, ux = 0, uy = 0;
+#pragma unroll
+  for (int dy = 0; dy < W; ++dy) {
+    const int rb = (r0 + dy) * pitch;
+    T su = 0, sx = 0, sy = 0;
+#pragma unroll
+    for (int dx = 0; dx < W; ++dx) {
+      su += kx[dx] * Gu[rb + cp[dx]];
+      sx += kx[dx] * Gx[rb + cp[dx]];
+      sy += kx[dx] * Gy[rb + cp[dx]];
+    }
+    u += ky[dy] * su;
+    ux += ky[dy] * sx;
+    uy += ky[dy] * sy;
+  }
+  T dWx, dWy;
+  const T Wv = hann_wg(a.window_kind, xj, yj, cx, cy, R, pr, dWx, dWy);
+  if (a.grad_h) a.grad_h[j] = wj * Wv * u;
+  if (a.grad_x || a.grad_y) {
+    const T wh = wj * hj;
+    if (a.grad_x) a.grad_x[j] = wh * (dWx * u + Wv * ux);
+    if (a.grad_y) a.grad_y[j] = wh * (dWy * u + Wv * uy);
+  }
+}
+
+// All points of one item.  With 16-byte aligned arrays each lane takes runs of
+// 4 consecutive points (one 16-byte load per array); wave w reads 64 runs
+// contiguous (1 KiB per array) and the loads run two blocks ahead in three
+// register buffers, so the gather is not serialised behind point loads.
+// Every point of the item is read (its band decides whether it is served).
+template <typename T, int W, int NT>
+__device__ __forceinline__ void gather_item(const AdjArgs<T> &a, const T *Gu, const T *Gx, const T *Gy, int band_lo,
+                                            int64_t begin, int64_t end, T cx, T cy, T R) {
+  const T pr = R > T(0) ? T(M_PI) / R : T(0);
+  int64_t body0 = end, body1 = end;
+  // runs of 4 points for FP32 and the narrow kernels (register budget)
+  constexpr bool kRuns = sizeof(T) == 4 && W <= 6;
+  if (kRuns && a.vec4) {
+    body0 = min(end, (begin + 3) / 4 * 4);
+    body1 = max(body0, end / 4 * 4);
+  }
+  using V = typename vec4<T>::type;
+  const V *x4 = reinterpret_cast<const V *>(a.x), *y4 = reinterpret_cast<const V *>(a.y);
+  const V *h4 = reinterpret_cast<const V *>(a.h), *w4 = reinterpret_cast<const V *>(a.w);
+  const int64_t g0 = body0 / 4, q1 = body1 / 4;
+  if constexpr (kRuns) if (q1 > g0) {
+    const int lane = threadIdx.x & 63;
+    int64_t q = g0 + (threadIdx.x >> 6) * 64 + lane;
+    auto load = [&](V &xb, V &yb, V &hb, V &wb, int64_t qq) {
+      const int64_t qc = qq < q1 ? qq : q1 - 1;   // past the end: re-read the last run (unused)
+      xb = x4[qc]; yb = y4[qc]; hb = h4[qc]; wb = w4[qc];
+    };
+    auto step = [&](const V &xv, const V &yv, const V &hv, const V &wv, int64_t qq) {
+      if (qq >= q1) return;
+      gather_point<T, W>(a, Gu, Gx, Gy, band_lo, qq * 4 + 0, xv.x, yv.x, hv.x, wv.x, cx, cy, R, pr);
+      gather_point<T, W>(a, Gu, Gx, Gy, band_lo, qq * 4 + 1, xv.y, yv.y, hv.y, wv.y, cx, cy, R, pr);
+      gather_point<T, W>(a, Gu, Gx, Gy, band_lo, qq * 4 + 2, xv.z, yv.z, hv.z, wv.z, cx, cy, R, pr);
+      gather_point<T, W>(a, Gu, Gx, Gy, band_lo, qq * 4 + 3, xv.w, yv.w, hv.w, wv.w, cx, cy, R, pr);
+    };
+    V x0{}, y0{}, h0{}, w0{}, x1{}, y1{}, h1{}, w1{}, x2{}, y2{}, h2{}, w2{};
+    load(x0, y0, h0, w0, q);
+    load(x1, y1, h1, w1, q + NT);
+    for (int64_t qb = g0; qb < q1; qb += 3 * NT, q += 3 * NT) {
+      load(x2, y2, h2, w2, q + 2 * NT);
+      step(x0, y0, h0, w0, q);
+      load(x0, y0, h0, w0, q + 3 * NT);
+      step(x1, y1, h1, w1, q + NT);
+      load(x1, y1, h1, w1, q + 4 * NT);
+      step(x2, y2, h2, w2, q + 2 * NT);
+    }
+  }
+  // points outside the aligned body (all of them when unaligned), one per thread
+  const int64_t nhead = body0 - begin, ntail = end - body1;
+  for (int64_t i = threadIdx.x; i < nhead + ntail; i += NT) {
+    const int64_t j = i < nhead ? begin + i : body1 + (i - nhead);
+    gather_point<T, W>(a, Gu, Gx, Gy, band_lo, j, a.x[j], a.y[j], a.h[j], a.w[j], cx, cy, R, pr);
+  }
+}
+
 template <typename T, int W, int NT>
 __global__ __launch_bounds__(NT) void adj_kernel(AdjArgs<T> a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -195,50 +294,8 @@ __global__ __launch_bounds__(NT) void adj_kernel(AdjArgs<T> a) {
     });
 
     // Gather at the points of this band.
-    const T halfw = T(W) / T(2);
-    const T zsc = T(2) / T(W);
     const double *wn = a.windows + 3 * (int64_t)it.cell;
-    const T cx = T(wn[0]), cy = T(wn[1]), R = T(wn[2]);
-    const T pr = R > T(0) ? T(M_PI) / R : T(0);
-    const int band_lo = it.band * a.band_rows;
-    for (int64_t j = it.begin + threadIdx.x; j < it.end; j += NT) {
-      const T yj = a.y[j];
-      const FineCoord<T> fy = fine_coord<T>(yj, a.s2_hi, a.s2_lo, halfw);
-      const int r0 = (fy.i0 & (g.n2 - 1)) - band_lo;    // first footprint row, band-local
-      if (r0 < 0 || r0 >= a.band_rows) continue;
-      const T xj = a.x[j];
-      const FineCoord<T> fx = fine_coord<T>(xj, a.s1_hi, a.s1_lo, halfw);
-      T kx[W], ky[W];
-      int cp[W];
-      es_taps<T, W>(fx, a.beta, a.es, kx);
-      es_taps<T, W>(fy, a.beta, a.es, ky);
-#pragma unroll
-      for (int d = 0; d < W; ++d) cp[d] = fft_pos((fx.i0 + d) & (n1 - 1), n1);
-      T u = 0, ux = 0, uy = 0;
-#pragma unroll
-      for (int dy = 0; dy < W; ++dy) {
-        const int rb = (r0 + dy) * pitch;
-        T su = 0, sx = 0, sy = 0;
-#pragma unroll
-        for (int dx = 0; dx < W; ++dx) {
-          su += kx[dx] * Gu[rb + cp[dx]];
-          sx += kx[dx] * Gx[rb + cp[dx]];
-          sy += kx[dx] * Gy[rb + cp[dx]];
-        }
-        u += ky[dy] * su;
-        ux += ky[dy] * sx;
-        uy += ky[dy] * sy;
-      }
-      T dWx, dWy;
-      const T Wv = hann_wg(a.window_kind, xj, yj, cx, cy, R, pr, dWx, dWy);
-      const T wj = a.w[j];
-      if (a.grad_h) a.grad_h[j] = wj * Wv * u;
-      if (a.grad_x || a.grad_y) {
-        const T wh = wj * a.h[j];
-        if (a.grad_x) a.grad_x[j] = wh * (dWx * u + Wv * ux);
-        if (a.grad_y) a.grad_y[j] = wh * (dWy * u + Wv * uy);
-      }
-    }
+    gather_item<T, W, NT>(a, Gu, Gx, Gy, it.band * a.band_rows, it.begin, it.end, T(wn[0]), T(wn[1]), T(wn[2]));
     __syncthreads();
     if (!persistent) break;
   }
@@ -402,6 +459,11 @@ AdjArgs<T> make_adj_args(enufft_plan_t p, const void *x, const void *y, const vo
                          const void *fbar, void *gh, void *gx, void *gy) {
   AdjArgs<T> a{};
   a.x = (const T *)x; a.y = (const T *)y; a.h = (const T *)h; a.w = (const T *)w;
+  {
+    const size_t al = 4 * sizeof(T);
+    a.vec4 = ((uintptr_t)x % al == 0 && (uintptr_t)y % al == 0 && (uintptr_t)h % al == 0 &&
+              (uintptr_t)w % al == 0) ? 1 : 0;
+  }
   a.fbar = (const T *)fbar;
   a.keep = nullptr;
   a.lam = nullptr;
@@ -446,9 +508,16 @@ enufft_status adjoint_common(enufft_plan_t p, const char *fn, const void *x, con
     return ENUFFT_EINVAL;
   }
   if (!grad_h && !grad_x && !grad_y) return ENUFFT_OK;
+  hipEvent_t ev;
+  if (p->big) {
+    enufft_status st = record_start(p, 2, &ev);
+    if (st != ENUFFT_OK) return st;
+    st = big_adjoint(p, x, y, h, w, fin, keep, lam, grad_h, grad_x, grad_y);
+    if (st != ENUFFT_OK) return st;
+    return record_stop(p, 2, ev);
+  }
   enufft_status st = adj_prepare(p);
   if (st != ENUFFT_OK) return st;
-  hipEvent_t ev;
   st = record_start(p, 2, &ev);
   if (st != ENUFFT_OK) return st;
   hipError_t e;

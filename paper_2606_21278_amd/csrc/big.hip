@@ -1,0 +1,1240 @@
+// Cells whose fine grid does not fit one workgroup's LDS (mode boxes above 64
+// per axis, e.g. 512 x 512 modes on a 1024^2 grid): the same type-1, EMS and
+// adjoint, with the grid in HBM and the work tiled.
+//
+// Type-1 (Section 2.1.2):
+//   1. a device counting sort of the cell's points by the fine-grid tile of
+//      their footprint origin (BIG_TS x BIG_TS cells per tile): per-chunk LDS
+//      histograms, a scan, and a scatter that copies the points into tile order
+//      together with their original index;
+//   2. spreading (Step 1) by persistent workgroups over fixed-size chunks of the
+//      sorted points: each run of one tile accumulates in an FP64 LDS sub-grid
+//      (the tile, the kernel's reach and a one-cell margin) that is then added
+//      to the FP64 grid in HBM, so a crowded tile is shared by several
+//      workgroups and no work unit is heavier than one chunk;
+//   3. the FFT (Step 3): length-n1 transforms of row pairs (two real rows as one
+//      complex row, split into the kept kx >= 0 bins) into a column buffer,
+//      then the column transforms, each radix-2 Stockham in LDS;
+//   4. deconvolution and crop (Step 4, eq. deconv) fused into the column pass,
+//      the kx < 0 half of the box from Hermitian symmetry.
+// EMS (Section 2.2): unit energies, a bitonic sort of the values (LDS-resident
+// blocks plus global passes), the scores from one workgroup, the keep mask;
+// units tied at the cut energy are ranked by unit id.
+// Adjoint: the grids u, du/dx and du/dy built in HBM by the inverse column and
+// row passes, then a tiled gather over the sorted points (each run stages its
+// tile of the three grids in LDS) that writes the gradients at the original
+// point indices.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <climits>
+#include <cmath>
+#include <string>
+#include <vector>
+
+#include "device_common.h"
+#include "launch.h"
+#include "plan.h"
+
+namespace enufft {
+
+constexpr int BIG_TS = 32;            // tile side in fine-grid cells
+constexpr int BIG_CHUNK = 16384;      // sorted points per spreading / gather work unit
+constexpr int BIG_BIN_CHUNK = 65536;  // points per workgroup in the sort passes
+constexpr int BIG_SORT_BLOCK = 4096;  // elements of one LDS-resident sort block
+constexpr int BIG_SPREAD_THREADS = 256;
+
+template <typename T>
+void split_scale(int n, T *hi, T *lo);
+
+// ------------------------------------------------------------------ helpers
+
+template <typename T>
+__global__ void fill_kernel(T *p, int64_t n, T v) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+template <typename T>
+static hipError_t fill(T *p, int64_t n, T v, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const int blocks = (int)std::min<int64_t>(4096, (n + 255) / 256);
+  hipLaunchKernelGGL((fill_kernel<T>), dim3(blocks), dim3(256), 0, s, p, n, v);
+  return hipGetLastError();
+}
+
+// Footprint origin of a point on the (wrapped) fine grid.
+template <typename T>
+__device__ __forceinline__ int big_origin(T x, T s_hi, T s_lo, int W, int n) {
+  return fine_coord<T>(x, s_hi, s_lo, T(W) / T(2)).i0 & (n - 1);
+}
+
+// Local footprint origin inside the staged sub-grid of a tile whose cells start
+// at t0: one cell of margin before the tile, so an origin that lands one cell
+// off the tile the sort gave it still has its whole footprint inside the
+// sub-grid; anything further off is clamped (it cannot occur: both sides
+// compute the origin with the same code).
+__device__ __forceinline__ int big_local(int i0, int t0, int n) {
+  const int l = ((i0 - t0 + 1) & (n - 1));
+  return l < BIG_TS + 1 ? l : BIG_TS + 1;
+}
+
+// The W kernel values of one point along one axis: the plan's per-tap
+// polynomials (FP32, W <= ES_MAXW) when POLY, else psi itself.
+template <typename T, int W, bool POLY>
+__device__ __forceinline__ void big_taps(const FineCoord<T> &c, T beta, const EsPoly &cf, T (&out)[W]) {
+  if constexpr (POLY) {
+    es_taps_poly<W>(c, float(W) * 0.5f, cf, out);
+  } else {
+    const T zsc = T(2) / T(W);
+#pragma unroll
+    for (int d = 0; d < W; ++d) out[d] = es_eval(c.offset(d) * zsc, beta);
+  }
+}
+
+// Radix-2 Stockham transform of length n (a power of two) in LDS: a holds the
+// input, b is the ping-pong buffer, natural order in and out.  Forward uses
+// tw[j] = exp(-2 pi i j / n), INV the conjugates; unnormalised.  Returns the
+// buffer holding the result.  Every thread of the block must call it.
+template <bool INV, typename T>
+__device__ T *stockham(T *a, T *b, int n, const T *tw) {
+  T *x = a, *y = b;
+  for (int ns = 1; ns < n; ns <<= 1) {
+    for (int j = threadIdx.x; j < n / 2; j += blockDim.x) {
+      const int k = j & (ns - 1);
+      const T v0r = x[2 * j], v0i = x[2 * j + 1];
+      const T ur = x[2 * (j + n / 2)], ui = x[2 * (j + n / 2) + 1];
+      const int t = k * (n / (2 * ns));
+      const T c = tw[2 * t], s = INV ? -tw[2 * t + 1] : tw[2 * t + 1];
+      const T v1r = ur * c - ui * s, v1i = ur * s + ui * c;
+      const int d = (j - k) * 2 + k;   // (j / ns) * 2 ns + k
+      y[2 * d] = v0r + v1r;
+      y[2 * d + 1] = v0i + v1i;
+      y[2 * (d + ns)] = v0r - v1r;
+      y[2 * (d + ns) + 1] = v0i - v1i;
+    }
+    __syncthreads();
+    T *tmp = x;
+    x = y;
+    y = tmp;
+  }
+  return x;
+}
+
+// ------------------------------------------------------------------ device sort by tile
+
+template <typename T>
+struct BigSortArgs {
+  const T *x, *y, *h, *w;   // the cell's points (h may be NULL: copied as 0)
+  int64_t n;
+  T s1h, s1l, s2h, s2l;
+  int W, n1, n2, ntx, ntiles;
+  int *counts;              // [ntiles]
+  int64_t *cursor;          // [ntiles]
+  int *perm;                // [n] original index of each sorted position
+  T *xs, *ys, *hs, *ws;     // [n] points in tile order
+};
+
+template <typename T>
+__device__ __forceinline__ int big_tile(const BigSortArgs<T> &a, T x, T y) {
+  const int ix = big_origin<T>(x, a.s1h, a.s1l, a.W, a.n1);
+  const int iy = big_origin<T>(y, a.s2h, a.s2l, a.W, a.n2);
+  return (iy / BIG_TS) * a.ntx + ix / BIG_TS;
+}
+
+// Per-chunk tile histograms, added to the global counts.
+template <typename T>
+__global__ __launch_bounds__(512) void big_count_kernel(BigSortArgs<T> a) {
+  extern __shared__ int hist[];
+  for (int i = threadIdx.x; i < a.ntiles; i += blockDim.x) hist[i] = 0;
+  __syncthreads();
+  const int64_t s = (int64_t)blockIdx.x * BIG_BIN_CHUNK, e = min(a.n, s + BIG_BIN_CHUNK);
+  for (int64_t j = s + threadIdx.x; j < e; j += blockDim.x) atomicAdd(&hist[big_tile<T>(a, a.x[j], a.y[j])], 1);
+  __syncthreads();
+  for (int i = threadIdx.x; i < a.ntiles; i += blockDim.x)
+    if (hist[i]) atomicAdd(&a.counts[i], hist[i]);
+}
+
+// Exclusive scan of the tile counts in one workgroup: offsets[0..ntiles] and
+// the scatter cursors.
+__global__ __launch_bounds__(1024) void big_scan_kernel(const int *counts, int ntiles, int64_t *offsets,
+                                                        int64_t *cursor) {
+  __shared__ int64_t part[1024];
+  const int per = (ntiles + 1023) / 1024;
+  const int t0 = min(ntiles, (int)threadIdx.x * per), t1 = min(ntiles, t0 + per);
+  int64_t s = 0;
+  for (int t = t0; t < t1; ++t) s += counts[t];
+  part[threadIdx.x] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int64_t run = 0;
+    for (int i = 0; i < 1024; ++i) {
+      const int64_t v = part[i];
+      part[i] = run;
+      run += v;
+    }
+    offsets[ntiles] = run;
+  }
+  __syncthreads();
+  int64_t run = part[threadIdx.x];
+  for (int t = t0; t < t1; ++t) {
+    offsets[t] = run;
+    cursor[t] = run;
+    run += counts[t];
+  }
+}
+
+// Scatter: each chunk reserves its range in every tile with one global atomic
+// per (chunk, tile) and places its points by LDS ranks.
+template <typename T>
+__global__ __launch_bounds__(512) void big_scatter_kernel(BigSortArgs<T> a) {
+  extern __shared__ int smem[];
+  int *hist = smem;                                                          // [ntiles]
+  int64_t *base = reinterpret_cast<int64_t *>(smem + ((a.ntiles + 1) & ~1));   // [ntiles], 8-byte aligned
+  for (int i = threadIdx.x; i < a.ntiles; i += blockDim.x) hist[i] = 0;
+  __syncthreads();
+  const int64_t s = (int64_t)blockIdx.x * BIG_BIN_CHUNK, e = min(a.n, s + BIG_BIN_CHUNK);
+  for (int64_t j = s + threadIdx.x; j < e; j += blockDim.x) atomicAdd(&hist[big_tile<T>(a, a.x[j], a.y[j])], 1);
+  __syncthreads();
+  for (int i = threadIdx.x; i < a.ntiles; i += blockDim.x) {
+    const int c = hist[i];
+    base[i] = c ? (int64_t)atomicAdd((unsigned long long *)&a.cursor[i], (unsigned long long)c) : 0;
+    hist[i] = 0;
+  }
+  __syncthreads();
+  for (int64_t j = s + threadIdx.x; j < e; j += blockDim.x) {
+    const T xj = a.x[j], yj = a.y[j];
+    const int t = big_tile<T>(a, xj, yj);
+    const int64_t pos = base[t] + atomicAdd(&hist[t], 1);
+    if (pos >= a.n) continue;   // only if the two passes disagreed on a tile; never out of bounds
+    a.perm[pos] = (int)j;
+    a.xs[pos] = xj;
+    a.ys[pos] = yj;
+    a.hs[pos] = a.h ? a.h[j] : T(0);
+    a.ws[pos] = a.w[j];
+  }
+}
+
+// Tile holding sorted position k: the largest t with offsets[t] <= k.
+__device__ __forceinline__ int big_tile_of(const int64_t *offsets, int ntiles, int64_t k) {
+  int lo = 0, hi = ntiles - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (offsets[mid] <= k) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Common arguments of the tiled spreading and gather passes.
+template <typename T>
+struct BigTileArgs {
+  const T *xs, *ys, *hs, *ws;
+  const int *perm;
+  const int64_t *offsets;
+  int ntiles, ntx;
+  int64_t n;
+  int *work_counter, *done_counter;
+  const double *windows;    // per cell (cx, cy, R)
+  int64_t cell;
+  int window_kind;
+  Geom g;
+  T s1h, s1l, s2h, s2l, beta;
+  EsPoly es;
+  double *grid;             // spreading: n2 x n1 FP64 accumulator
+  const T *Gu, *Gx, *Gy;    // gather: n2 x n1 grids u, du/dx, du/dy
+  T *grad_h, *grad_x, *grad_y;   // gather: indexed by the cell-local original point index
+};
+
+// Persistent loop over chunks of the sorted points; body(t, lo, hi) runs every
+// tile run [lo, hi) of tile t inside the chunk.  The last workgroup to finish
+// resets the counters for the next launch.
+template <typename T, typename Body>
+__device__ __forceinline__ void big_chunks(const BigTileArgs<T> &a, int *s_chunk, const Body &body) {
+  const int64_t nchunks = (a.n + BIG_CHUNK - 1) / BIG_CHUNK;
+  for (;;) {
+    if (threadIdx.x == 0) *s_chunk = atomicAdd(a.work_counter, 1);
+    __syncthreads();
+    const int64_t c = *s_chunk;
+    __syncthreads();
+    if (c >= nchunks) break;
+    const int64_t k0 = c * BIG_CHUNK, k1 = min(a.n, k0 + BIG_CHUNK);
+    for (int t = big_tile_of(a.offsets, a.ntiles, k0); t < a.ntiles && a.offsets[t] < k1; ++t) {
+      const int64_t lo = max(k0, a.offsets[t]), hi = min(k1, a.offsets[t + 1]);
+      if (lo < hi) body(t, lo, hi);
+    }
+  }
+  if (threadIdx.x == 0) {
+    __threadfence();
+    if (atomicAdd(a.done_counter, 1) == (int)gridDim.x - 1) {
+      *a.work_counter = 0;
+      *a.done_counter = 0;
+    }
+  }
+}
+
+// ------------------------------------------------------------------ spreading into the HBM grid
+
+template <typename T, int W, bool POLY>
+__global__ __launch_bounds__(BIG_SPREAD_THREADS) void big_spread_kernel(BigTileArgs<T> a) {
+  constexpr int S = BIG_TS + W + 1;   // margin cell, tile, reach of the last origin
+  __shared__ double sub[S * S];
+  __shared__ int s_chunk;
+  const Geom &g = a.g;
+  const T halfw = T(W) / T(2);
+  const double *wn = a.windows + 3 * a.cell;
+  const T cx = T(wn[0]), cy = T(wn[1]), R = T(wn[2]);
+  const T pr = R > T(0) ? T(M_PI) / R : T(0);
+  big_chunks<T>(a, &s_chunk, [&](int t, int64_t lo, int64_t hi) {
+    for (int i = threadIdx.x; i < S * S; i += blockDim.x) sub[i] = 0.0;
+    __syncthreads();
+    const int tx0 = (t % a.ntx) * BIG_TS, ty0 = (t / a.ntx) * BIG_TS;
+    for (int64_t k = lo + threadIdx.x; k < hi; k += blockDim.x) {
+      const T xj = a.xs[k], yj = a.ys[k];
+      const T cj = a.ws[k] * a.hs[k] * hann_w(a.window_kind, xj, yj, cx, cy, R, pr);
+      const FineCoord<T> fx = fine_coord<T>(xj, a.s1h, a.s1l, halfw);
+      const FineCoord<T> fy = fine_coord<T>(yj, a.s2h, a.s2l, halfw);
+      const int lx = big_local(fx.i0 & (g.n1 - 1), tx0, g.n1);
+      const int ly = big_local(fy.i0 & (g.n2 - 1), ty0, g.n2);
+      T kx[W], ky[W];
+      big_taps<T, W, POLY>(fx, a.beta, a.es, kx);
+      big_taps<T, W, POLY>(fy, a.beta, a.es, ky);
+#pragma unroll
+      for (int dy = 0; dy < W; ++dy) {
+        const double vy = (double)(cj * ky[dy]);
+        double *row = sub + (ly + dy) * S + lx;
+#pragma unroll
+        for (int dx = 0; dx < W; ++dx)
+          __hip_atomic_fetch_add(row + dx, vy * (double)kx[dx], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < S * S; i += blockDim.x) {
+      const double v = sub[i];
+      if (v != 0.0) {
+        const int r = i / S, q = i - r * S;
+        const int gy = (ty0 - 1 + r) & (g.n2 - 1), gx = (tx0 - 1 + q) & (g.n1 - 1);
+        unsafeAtomicAdd(&a.grid[(int64_t)gy * g.n1 + gx], v);
+      }
+    }
+    __syncthreads();
+  });
+}
+
+// ------------------------------------------------------------------ FFT passes
+
+// Row pass: rows 2p and 2p + 1 of the FP64 grid as one complex row, forward
+// transform, then the bins kx = 0..K1 of each real row into the column buffer
+// cb[kx][row] (complex, n2 rows per column).
+template <typename T>
+__global__ __launch_bounds__(512) void big_rows_kernel(const double *grid, Geom g, const T *tw1, T *cb) {
+  extern __shared__ __align__(16) unsigned char sm_raw[];
+  const int n1 = g.n1;
+  T *A = reinterpret_cast<T *>(sm_raw), *B = A + 2 * n1;
+  const int p = blockIdx.x;
+  const double *r0 = grid + (int64_t)(2 * p) * n1, *r1 = r0 + n1;
+  for (int i = threadIdx.x; i < n1; i += blockDim.x) {
+    A[2 * i] = (T)r0[i];
+    A[2 * i + 1] = (T)r1[i];
+  }
+  __syncthreads();
+  const T *Z = stockham<false, T>(A, B, n1, tw1);
+  for (int k = threadIdx.x; k <= g.K1; k += blockDim.x) {
+    const int m = (n1 - k) & (n1 - 1);
+    const T zr = Z[2 * k], zi = Z[2 * k + 1], mr = Z[2 * m], mi = Z[2 * m + 1];
+    // row 2p: (Z(k) + conj Z(-k)) / 2; row 2p + 1: (Z(k) - conj Z(-k)) / 2i
+    T *c = cb + (int64_t)k * g.n2 * 2 + 4 * p;
+    c[0] = T(0.5) * (zr + mr);
+    c[1] = T(0.5) * (zi - mi);
+    c[2] = T(0.5) * (zi + mi);
+    c[3] = T(-0.5) * (zr - mr);
+  }
+}
+
+// Column pass: transform of column kx over the n2 rows, deconvolution and crop
+// into the mode box, the (-kx, -ky) entry as the conjugate.
+template <typename T>
+__global__ __launch_bounds__(512) void big_cols_kernel(const T *cb, Geom g, const T *tw2, const T *decon_x,
+                                                       const T *decon_y, T *f) {
+  extern __shared__ __align__(16) unsigned char sm_raw[];
+  const int n2 = g.n2;
+  T *A = reinterpret_cast<T *>(sm_raw), *B = A + 2 * n2;
+  const int kx = blockIdx.x;
+  const T *c = cb + (int64_t)kx * n2 * 2;
+  for (int i = threadIdx.x; i < 2 * n2; i += blockDim.x) A[i] = c[i];
+  __syncthreads();
+  const T *Z = stockham<false, T>(A, B, n2, tw2);
+  const int hi1 = g.lo1 + g.N1 - 1, hi2 = g.lo2 + g.N2 - 1;
+  for (int ky = -g.K2 + (int)threadIdx.x; ky <= g.K2; ky += blockDim.x) {
+    const int bin = ky & (n2 - 1);
+    const T s = decon_x[kx] * decon_y[ky < 0 ? -ky : ky];
+    const T vr = Z[2 * bin] * s, vi = Z[2 * bin + 1] * s;
+    if (kx <= hi1 && ky >= g.lo2 && ky <= hi2) {
+      T *o = f + 2 * ((int64_t)(ky - g.lo2) * g.N1 + (kx - g.lo1));
+      o[0] = vr;
+      o[1] = vi;
+    }
+    if (kx >= 1 && -kx >= g.lo1 && -ky >= g.lo2 && -ky <= hi2) {
+      T *o = f + 2 * ((int64_t)(-ky - g.lo2) * g.N1 + (-kx - g.lo1));
+      o[0] = vr;
+      o[1] = -vi;
+    }
+  }
+}
+
+// ------------------------------------------------------------------ EMS for one large cell
+
+struct BigCut {   // written by the scores pass
+  double T1, T2, neff, sdel, Cs, alphaC, th, eth;
+  int kstar, need, split, J;
+};
+
+template <typename C>
+__device__ __forceinline__ double big_pair_energy(const C *f, const double *mw, int rep, int partner) {
+  const int pq = partner >= 0 ? partner : rep;
+  const C fr = f[rep], fp = f[pq];
+  double e = (double)fr.x * (double)fr.x + (double)fr.y * (double)fr.y;
+  double ep = (double)fp.x * (double)fp.x + (double)fp.y * (double)fp.y;
+  if (mw) {
+    e *= mw[rep];
+    ep *= mw[pq];
+  }
+  return partner >= 0 ? e + ep : e;
+}
+
+// eq. (energy) / (weighted_e) of every unit into the sort buffer (padding +0
+// sorts last), with per-workgroup partial sums of E and E^2.
+template <typename T>
+__global__ __launch_bounds__(256) void big_ems_energy_kernel(const T *f, const double *mw, const int2 *units, int J,
+                                                             int Jpad, double *S, double *partial) {
+  using C = typename vec2<T>::type;
+  const C *fc = reinterpret_cast<const C *>(f);
+  __shared__ double r1[256], r2[256];
+  double s1 = 0.0, s2 = 0.0;
+  const int u = blockIdx.x * 256 + threadIdx.x;
+  if (u < Jpad) {
+    double e = 0.0;
+    if (u < J) {
+      const int2 un = units[u];
+      e = big_pair_energy<C>(fc, mw, un.x, un.y);
+      s1 = e;
+      s2 = e * e;
+    }
+    S[u] = e;
+  }
+  r1[threadIdx.x] = s1;
+  r2[threadIdx.x] = s2;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) {
+      r1[threadIdx.x] += r1[threadIdx.x + o];
+      r2[threadIdx.x] += r2[threadIdx.x + o];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    partial[2 * blockIdx.x] = r1[0];
+    partial[2 * blockIdx.x + 1] = r2[0];
+  }
+}
+
+// Bitonic network, descending overall (eq. sorted_energy): the pair (i, i ^ j)
+// with i < i ^ j keeps the larger value at i when (i & k) == 0, at i ^ j
+// otherwise.  Equal values are interchangeable, so only values are sorted.
+__device__ __forceinline__ void bitonic_ce(double &lo_v, double &hi_v, bool desc) {
+  const double a = lo_v, b = hi_v;
+  if (desc ? (a < b) : (a > b)) {
+    lo_v = b;
+    hi_v = a;
+  }
+}
+
+// The stages j <= jmax of block sizes k = kfirst, 2 kfirst, .., klast inside
+// one LDS-resident block of BIG_SORT_BLOCK values.
+__global__ __launch_bounds__(512) void big_sort_block_kernel(double *S, int kfirst, int klast, int jmax) {
+  __shared__ double b[BIG_SORT_BLOCK];
+  const int64_t base = (int64_t)blockIdx.x * BIG_SORT_BLOCK;
+  for (int i = threadIdx.x; i < BIG_SORT_BLOCK; i += blockDim.x) b[i] = S[base + i];
+  __syncthreads();
+  for (int k = kfirst; k <= klast; k <<= 1) {
+    for (int j = min(k >> 1, jmax); j > 0; j >>= 1) {
+      for (int i = threadIdx.x; i < BIG_SORT_BLOCK; i += blockDim.x) {
+        const int l = i ^ j;
+        if (l > i) bitonic_ce(b[i], b[l], ((base + i) & k) == 0);
+      }
+      __syncthreads();
+    }
+  }
+  for (int i = threadIdx.x; i < BIG_SORT_BLOCK; i += blockDim.x) S[base + i] = b[i];
+}
+
+// One stage (k, j) with j >= BIG_SORT_BLOCK over the whole buffer.
+__global__ __launch_bounds__(256) void big_sort_global_kernel(double *S, int64_t n, int64_t k, int64_t j) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t l = i ^ j;
+    if (l > i) {
+      double a = S[i], b = S[l];
+      bitonic_ce(a, b, (i & k) == 0);
+      S[i] = a;
+      S[l] = b;
+    }
+  }
+}
+
+// Workgroup sums in a fixed order (thread 0 adds the per-thread values).
+__device__ double big_block_sum(double v, double *red, double *out) {
+  __syncthreads();
+  red[threadIdx.x] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int i = 0; i < (int)blockDim.x; ++i) s += red[i];
+    *out = s;
+  }
+  __syncthreads();
+  return *out;
+}
+__device__ int big_block_sum_i(int v, int *red, int *out) {
+  __syncthreads();
+  red[threadIdx.x] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int s = 0;
+    for (int i = 0; i < (int)blockDim.x; ++i) s += red[i];
+    *out = s;
+  }
+  __syncthreads();
+  return *out;
+}
+
+// Scores over the sorted energies (one workgroup of 1024 threads, each owning
+// a contiguous run of sorted positions): eqs. (n_eff), (s_delta), (c_score),
+// (alpha_c), (f_cum) and (k_elastic), as in the per-cell kernel.
+__global__ __launch_bounds__(1024) void big_ems_scores_kernel(const double *S, const double *partial, int nparts,
+                                                              int J, enufft_ems_params prm, BigCut *cut) {
+  __shared__ double red[1024];
+  __shared__ int redi[1024];
+  __shared__ double s_out;
+  __shared__ int s_outi;
+  __shared__ double sT1, sT2;
+  __shared__ int s_kc;
+  const int t = threadIdx.x;
+  if (t == 0) {
+    double a = 0.0, b = 0.0;
+    for (int i = 0; i < nparts; ++i) {
+      a += partial[2 * i];
+      b += partial[2 * i + 1];
+    }
+    sT1 = a;
+    sT2 = b;
+    s_kc = INT_MAX;
+  }
+  __syncthreads();
+  const double T1 = sT1, T2 = sT2;
+  const int Jmax = J < prm.k_max ? J : prm.k_max;
+  const double neff = T2 > 0.0 ? T1 * T1 / T2 : 0.0;
+  const double nclip = neff < (double)Jmax ? neff : (double)Jmax;
+  const int per = (J + 1023) / 1024;
+  const int j0 = min(J, t * per), j1 = min(J, j0 + per);
+  double sd = 0.0;
+  for (int j = j0; j < j1 && j < Jmax - 1; ++j) {
+    const double ea = S[j], eb = S[j + 1];
+    double term;
+    if (eb == 0.0 && ea == 0.0) term = 1.0;
+    else if (eb == 0.0) term = 0.0;
+    else term = exp(-(ea / eb - 1.0) / prm.delta);
+    sd += term;
+  }
+  const double sdsum = big_block_sum(sd, red, &s_out);
+  const double sdel = Jmax < 2 ? 1.0 : sdsum / (double)(Jmax - 1);
+  const double Cs = (Jmax > 0 ? prm.w1 * nclip / (double)Jmax : 0.0) + prm.w2 * sdel;
+  const double alphaC = prm.alpha_min + (prm.alpha_max - prm.alpha_min) * Cs;
+  // running sum: per-thread totals, an exclusive scan in thread order, then the threshold
+  double loc = 0.0;
+  for (int j = j0; j < j1; ++j) loc += S[j];
+  __syncthreads();
+  red[t] = loc;
+  __syncthreads();
+  if (t == 0) {
+    double run = 0.0;
+    for (int i = 0; i < 1024; ++i) {
+      const double v = red[i];
+      red[i] = run;
+      run += v;
+    }
+  }
+  __syncthreads();
+  double run = red[t];
+  if (T1 > 0.0) {
+    for (int j = j0; j < j1; ++j) {
+      run += S[j];
+      if (run / T1 >= alphaC) {
+        atomicMin(&s_kc, j + 1);
+        break;
+      }
+    }
+  }
+  __syncthreads();
+  int kstar;
+  if (!(T1 > 0.0)) {
+    kstar = prm.k_min < J ? prm.k_min : J;
+  } else {
+    const int kc = s_kc == INT_MAX ? J : s_kc;
+    const int k = kc > prm.k_min ? kc : prm.k_min;
+    kstar = k < Jmax ? k : Jmax;
+  }
+  const double eth = kstar > 0 ? S[kstar - 1] : 0.0;
+  double part = 0.0;
+  int cgt = 0, ceq = 0;
+  for (int j = j0; j < j1; ++j) {
+    const double v = S[j];
+    if (j < kstar) part += v;
+    cgt += v > eth;
+    ceq += v == eth;
+  }
+  const double th = big_block_sum(part, red, &s_out);
+  const int ngt = big_block_sum_i(cgt, redi, &s_outi);
+  const int neq = big_block_sum_i(ceq, redi, &s_outi);
+  if (t == 0) {
+    cut->T1 = T1; cut->T2 = T2; cut->neff = neff; cut->sdel = sdel; cut->Cs = Cs; cut->alphaC = alphaC;
+    cut->th = th; cut->eth = eth; cut->kstar = kstar; cut->need = kstar - ngt;
+    cut->split = kstar > 0 && neq > kstar - ngt;
+    cut->J = J;
+  }
+}
+
+// Units tied at the cut energy when not all of them are kept: the `need` tied
+// units of lowest id are kept (one workgroup, units in id order).
+template <typename T>
+__global__ __launch_bounds__(1024) void big_ems_ties_kernel(const T *f, const double *mw, const int2 *units, int J,
+                                                            const BigCut *cut, uint8_t *tie_kept) {
+  if (!cut->split) return;
+  using C = typename vec2<T>::type;
+  const C *fc = reinterpret_cast<const C *>(f);
+  __shared__ int cnt[1024];
+  const double eth = cut->eth;
+  const int need = cut->need;
+  const int per = (J + 1023) / 1024;
+  const int u0 = min(J, (int)threadIdx.x * per), u1 = min(J, u0 + per);
+  int c = 0;
+  for (int u = u0; u < u1; ++u) {
+    const int2 un = units[u];
+    c += big_pair_energy<C>(fc, mw, un.x, un.y) == eth;
+  }
+  cnt[threadIdx.x] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int run = 0;
+    for (int i = 0; i < 1024; ++i) {
+      const int v = cnt[i];
+      cnt[i] = run;
+      run += v;
+    }
+  }
+  __syncthreads();
+  int rank = cnt[threadIdx.x];
+  for (int u = u0; u < u1; ++u) {
+    const int2 un = units[u];
+    const bool tie = big_pair_energy<C>(fc, mw, un.x, un.y) == eth;
+    tie_kept[u] = tie && rank < need;
+    rank += tie;
+  }
+}
+
+// Keep mask over the modes and per-workgroup partials of the retained power.
+template <typename T>
+__global__ __launch_bounds__(256) void big_ems_keep_kernel(const T *f, const double *mw, const int4 *mode_unit, int M,
+                                                           const BigCut *cut, const uint8_t *tie_kept, uint8_t *keep,
+                                                           double *partial) {
+  using C = typename vec2<T>::type;
+  const C *fc = reinterpret_cast<const C *>(f);
+  __shared__ double red[256];
+  const int m = blockIdx.x * 256 + threadIdx.x;
+  double pw = 0.0;
+  if (m < M) {
+    const int4 mu = mode_unit[m];
+    uint8_t v = 0;
+    if (cut->kstar > 0 && mu.x >= 0) {
+      const double eu = big_pair_energy<C>(fc, mw, mu.x, mu.y);
+      v = eu > cut->eth || (eu == cut->eth && (!cut->split || tie_kept[mu.z]));
+    }
+    keep[m] = v;
+    if (v) {
+      const C fr = fc[m];
+      pw = (double)fr.x * (double)fr.x + (double)fr.y * (double)fr.y;
+    }
+  }
+  red[threadIdx.x] = pw;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+__global__ void big_ems_finish_kernel(const BigCut *cut, const double *partial, int nparts, int32_t *k_star,
+                                      double *stats) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double P = 0.0;
+  for (int i = 0; i < nparts; ++i) P += partial[i];
+  *k_star = cut->kstar;
+  stats[0] = cut->T1;
+  stats[1] = P;
+  stats[2] = cut->neff;
+  stats[3] = cut->sdel;
+  stats[4] = cut->Cs;
+  stats[5] = cut->alphaC;
+  stats[6] = cut->T1 > 0.0 ? cut->th / cut->T1 : 0.0;
+  stats[7] = (double)cut->J;
+}
+
+// ------------------------------------------------------------------ adjoint for one large cell
+
+// Column pass of the adjoint.  The cotangent gbar (2 lam_c f keep for the
+// retained-power loss) times the deconvolution factors, made Hermitian
+// (H(k) = (G(k) + conj G(-k)) / 2, so the grids are real), and the same times
+// i ky, each inverse transformed along y into cb / cby (columns kx = 0..K1).
+template <typename T>
+__global__ __launch_bounds__(512) void big_adj_cols_kernel(const T *fin, const uint8_t *keep, const double *lam,
+                                                           int64_t cell, Geom g, const T *tw2, const T *decon_x,
+                                                           const T *decon_y, T *cb, T *cby) {
+  extern __shared__ __align__(16) unsigned char sm_raw[];
+  const int n2 = g.n2;
+  T *A = reinterpret_cast<T *>(sm_raw), *B = A + 2 * n2;
+  const int kx = blockIdx.x;
+  const int hi1 = g.lo1 + g.N1 - 1, hi2 = g.lo2 + g.N2 - 1;
+  const T sc_keep = keep ? T(2.0 * (lam ? lam[cell] : 1.0)) : T(1);
+  for (int pass = 0; pass < 2; ++pass) {
+    for (int bin = threadIdx.x; bin < n2; bin += blockDim.x) {
+      const int ky = bin <= n2 / 2 ? bin : bin - n2;
+      T hr = 0, hi = 0;
+      if (ky >= -g.K2 && ky <= g.K2) {
+        if (kx <= hi1 && ky >= g.lo2 && ky <= hi2) {
+          const int64_t m = (int64_t)(ky - g.lo2) * g.N1 + (kx - g.lo1);
+          const T sc = keep ? (keep[m] ? sc_keep : T(0)) : T(1);
+          hr += sc * fin[2 * m];
+          hi += sc * fin[2 * m + 1];
+        }
+        if (-kx >= g.lo1 && -ky >= g.lo2 && -ky <= hi2) {
+          const int64_t m = (int64_t)(-ky - g.lo2) * g.N1 + (-kx - g.lo1);
+          const T sc = keep ? (keep[m] ? sc_keep : T(0)) : T(1);
+          hr += sc * fin[2 * m];
+          hi -= sc * fin[2 * m + 1];
+        }
+        const T s = T(0.5) * decon_x[kx] * decon_y[ky < 0 ? -ky : ky];
+        hr *= s;
+        hi *= s;
+      }
+      if (pass == 0) {
+        A[2 * bin] = hr;
+        A[2 * bin + 1] = hi;
+      } else {   // times i ky
+        A[2 * bin] = -T(ky) * hi;
+        A[2 * bin + 1] = T(ky) * hr;
+      }
+    }
+    __syncthreads();
+    const T *Z = stockham<true, T>(A, B, n2, tw2);
+    T *c = (pass == 0 ? cb : cby) + (int64_t)kx * n2 * 2;
+    for (int i = threadIdx.x; i < 2 * n2; i += blockDim.x) c[i] = Z[i];
+    __syncthreads();
+  }
+}
+
+// Row pass of the adjoint for rows 2p and 2p + 1, three inverse transforms of
+// length n1: u + i du/dx of row 2p (spectrum D + i (i kx D) = (1 - kx) D), the
+// same for row 2p + 1, and du/dy of row 2p + i du/dy of row 2p + 1.  Bins
+// kx < 0 are the conjugates of column -kx (the grids are real).
+template <typename T>
+__global__ __launch_bounds__(512) void big_adj_rows_kernel(const T *cb, const T *cby, Geom g, const T *tw1, T *Gu,
+                                                           T *Gx, T *Gy) {
+  extern __shared__ __align__(16) unsigned char sm_raw[];
+  const int n1 = g.n1, n2 = g.n2;
+  T *A = reinterpret_cast<T *>(sm_raw), *B = A + 2 * n1;
+  const int p = blockIdx.x;
+  const int64_t r0 = (int64_t)(2 * p) * n1, r1 = r0 + n1;
+  for (int pass = 0; pass < 3; ++pass) {
+    for (int k = threadIdx.x; k < n1; k += blockDim.x) {
+      const int kk = k <= n1 / 2 ? k : n1 - k;
+      const bool neg = k != kk;
+      T zr = 0, zi = 0;
+      if (kk <= g.K1) {
+        const T *src = (pass == 2 ? cby : cb) + (int64_t)kk * n2 * 2 + 4 * p;
+        T a0r = src[0], a0i = src[1], a1r = src[2], a1i = src[3];
+        if (neg) {
+          a0i = -a0i;
+          a1i = -a1i;
+        }
+        if (pass < 2) {
+          const T kf = neg ? -T(kk) : T(kk);
+          const T dr = pass == 0 ? a0r : a1r, di = pass == 0 ? a0i : a1i;
+          zr = dr - kf * dr;
+          zi = di - kf * di;
+        } else {
+          zr = a0r - a1i;
+          zi = a0i + a1r;
+        }
+      }
+      A[2 * k] = zr;
+      A[2 * k + 1] = zi;
+    }
+    __syncthreads();
+    const T *Z = stockham<true, T>(A, B, n1, tw1);
+    for (int i = threadIdx.x; i < n1; i += blockDim.x) {
+      if (pass == 0) {
+        Gu[r0 + i] = Z[2 * i];
+        Gx[r0 + i] = Z[2 * i + 1];
+      } else if (pass == 1) {
+        Gu[r1 + i] = Z[2 * i];
+        Gx[r1 + i] = Z[2 * i + 1];
+      } else {
+        Gy[r0 + i] = Z[2 * i];
+        Gy[r1 + i] = Z[2 * i + 1];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Gather (the type-2 interpolation back to the points) from the three grids,
+// each tile run staging its sub-grid of u, du/dx and du/dy in LDS.
+template <typename T, int W, bool POLY>
+__global__ __launch_bounds__(256) void big_gather_kernel(BigTileArgs<T> a) {
+  constexpr int S = BIG_TS + W + 1;
+  __shared__ T su[S * S], sx[S * S], sy[S * S];
+  __shared__ int s_chunk;
+  const Geom &g = a.g;
+  const T halfw = T(W) / T(2);
+  const double *wn = a.windows + 3 * a.cell;
+  const T cx = T(wn[0]), cy = T(wn[1]), R = T(wn[2]);
+  const T pr = R > T(0) ? T(M_PI) / R : T(0);
+  big_chunks<T>(a, &s_chunk, [&](int t, int64_t lo, int64_t hi) {
+    const int tx0 = (t % a.ntx) * BIG_TS, ty0 = (t / a.ntx) * BIG_TS;
+    for (int i = threadIdx.x; i < S * S; i += blockDim.x) {
+      const int r = i / S, q = i - r * S;
+      const int64_t gi = (int64_t)((ty0 - 1 + r) & (g.n2 - 1)) * g.n1 + ((tx0 - 1 + q) & (g.n1 - 1));
+      su[i] = a.Gu[gi];
+      sx[i] = a.Gx[gi];
+      sy[i] = a.Gy[gi];
+    }
+    __syncthreads();
+    for (int64_t k = lo + threadIdx.x; k < hi; k += blockDim.x) {
+      const T xj = a.xs[k], yj = a.ys[k];
+      const FineCoord<T> fx = fine_coord<T>(xj, a.s1h, a.s1l, halfw);
+      const FineCoord<T> fy = fine_coord<T>(yj, a.s2h, a.s2l, halfw);
+      const int lx = big_local(fx.i0 & (g.n1 - 1), tx0, g.n1);
+      const int ly = big_local(fy.i0 & (g.n2 - 1), ty0, g.n2);
+      T kx[W];
+      big_taps<T, W, POLY>(fx, a.beta, a.es, kx);
+      T u = 0, ux = 0, uy = 0;
+      auto row = [&](int dy, T kyv) {
+        const int rb = (ly + dy) * S + lx;
+        T au = 0, ax = 0, ay = 0;
+#pragma unroll
+        for (int dx = 0; dx < W; ++dx) {
+          au += kx[dx] * su[rb + dx];
+          ax += kx[dx] * sx[rb + dx];
+          ay += kx[dx] * sy[rb + dx];
+        }
+        u += kyv * au;
+        ux += kyv * ax;
+        uy += kyv * ay;
+      };
+      if constexpr (POLY) {
+        T ky[W];
+        big_taps<T, W, POLY>(fy, a.beta, a.es, ky);
+#pragma unroll
+        for (int dy = 0; dy < W; ++dy) row(dy, ky[dy]);
+      } else {   // one row at a time keeps the loads of W rows from being hoisted together
+        const T zsc = T(2) / T(W);
+#pragma unroll 1
+        for (int dy = 0; dy < W; ++dy) row(dy, es_eval(fy.offset(dy) * zsc, a.beta));
+      }
+      T dWx, dWy;
+      const T Wv = hann_wg(a.window_kind, xj, yj, cx, cy, R, pr, dWx, dWy);
+      const int j = a.perm[k];
+      if ((unsigned)j >= (unsigned)a.n) continue;   // defensive: every sorted slot holds a cell index
+      const T wj = a.ws[k];
+      if (a.grad_h) a.grad_h[j] = wj * Wv * u;
+      if (a.grad_x || a.grad_y) {
+        const T wh = wj * a.hs[k];
+        if (a.grad_x) a.grad_x[j] = wh * (dWx * u + Wv * ux);
+        if (a.grad_y) a.grad_y[j] = wh * (dWy * u + Wv * uy);
+      }
+    }
+    __syncthreads();
+  });
+}
+
+// ------------------------------------------------------------------ host side
+
+namespace {
+
+enufft_status big_fail(enufft_plan_t p, hipError_t e, const char *what) {
+  if (e == hipSuccess) return ENUFFT_OK;
+  p->last_error = std::string(what) + ": " + hipGetErrorString(e);
+  if (e == hipErrorMemoryAllocation || e == hipErrorOutOfMemory) return ENUFFT_ENOMEM;
+  if (e != hipErrorInvalidValue) p->faulted = true;
+  return ENUFFT_EDEVICE;
+}
+
+int stock_threads(int n) { return std::min(512, std::max(64, n / 2)); }
+
+size_t sort_lds(int ntiles) { return (size_t)((ntiles + 1) & ~1) * sizeof(int) + (size_t)ntiles * sizeof(int64_t); }
+
+template <typename T>
+hipError_t set_attrs_t(int n1, int n2, int ntiles) {
+  const size_t el = sizeof(T);
+  auto set = [](const void *fn, size_t bytes) {
+    return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  };
+  hipError_t e = set((const void *)&big_count_kernel<T>, (size_t)ntiles * sizeof(int));
+  if (e == hipSuccess) e = set((const void *)&big_scatter_kernel<T>, sort_lds(ntiles));
+  if (e == hipSuccess) e = set((const void *)&big_rows_kernel<T>, 4 * (size_t)n1 * el);
+  if (e == hipSuccess) e = set((const void *)&big_cols_kernel<T>, 4 * (size_t)n2 * el);
+  if (e == hipSuccess) e = set((const void *)&big_adj_cols_kernel<T>, 4 * (size_t)n2 * el);
+  if (e == hipSuccess) e = set((const void *)&big_adj_rows_kernel<T>, 4 * (size_t)n1 * el);
+  return e;
+}
+
+template <typename T>
+BigSortArgs<T> sort_args(enufft_plan_t p, int64_t c, const T *x, const T *y, const T *h, const T *w) {
+  const int64_t a0 = p->offsets[c];
+  BigSortArgs<T> a{};
+  a.x = x + a0; a.y = y + a0; a.h = h ? h + a0 : nullptr; a.w = w + a0;
+  a.n = p->offsets[c + 1] - a0;
+  split_scale<T>(p->n1, &a.s1h, &a.s1l);
+  split_scale<T>(p->n2, &a.s2h, &a.s2l);
+  a.W = p->W; a.n1 = p->n1; a.n2 = p->n2;
+  a.ntx = p->big_ntx; a.ntiles = p->big_ntx * p->big_nty;
+  a.counts = p->big_counts; a.cursor = p->big_cursor; a.perm = p->big_perm;
+  a.xs = (T *)p->big_xs; a.ys = (T *)p->big_ys; a.hs = (T *)p->big_hs; a.ws = (T *)p->big_ws;
+  return a;
+}
+
+// Sort the points of cell c by tile into the plan's buffers.
+template <typename T>
+hipError_t sort_cell(enufft_plan_t p, int64_t c, const T *x, const T *y, const T *h, const T *w) {
+  const BigSortArgs<T> a = sort_args<T>(p, c, x, y, h, w);
+  hipError_t e = fill<int>(p->big_counts, a.ntiles, 0, p->stream);
+  const int blocks = (int)((a.n + BIG_BIN_CHUNK - 1) / BIG_BIN_CHUNK);
+  if (e == hipSuccess && a.n > 0) {
+    hipLaunchKernelGGL((big_count_kernel<T>), dim3(blocks), dim3(512), (size_t)a.ntiles * sizeof(int), p->stream, a);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(big_scan_kernel, dim3(1), dim3(1024), 0, p->stream, (const int *)p->big_counts, a.ntiles,
+                       p->big_offsets, p->big_cursor);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess && a.n > 0) {
+    hipLaunchKernelGGL((big_scatter_kernel<T>), dim3(blocks), dim3(512), sort_lds(a.ntiles), p->stream, a);
+    e = hipGetLastError();
+  }
+  return e;
+}
+
+template <typename T>
+BigTileArgs<T> tile_args(enufft_plan_t p, int64_t c) {
+  BigTileArgs<T> a{};
+  a.xs = (const T *)p->big_xs; a.ys = (const T *)p->big_ys; a.hs = (const T *)p->big_hs; a.ws = (const T *)p->big_ws;
+  a.perm = p->big_perm;
+  a.offsets = p->big_offsets;
+  a.ntiles = p->big_ntx * p->big_nty;
+  a.ntx = p->big_ntx;
+  a.n = p->offsets[c + 1] - p->offsets[c];
+  a.windows = (const double *)p->d_windows;
+  a.cell = c;
+  a.window_kind = p->window_kind;
+  a.g = p->geom;
+  split_scale<T>(p->n1, &a.s1h, &a.s1l);
+  split_scale<T>(p->n2, &a.s2h, &a.s2l);
+  a.beta = (T)p->beta;
+  a.es = p->es;
+  return a;
+}
+
+int tile_blocks(enufft_plan_t p, int64_t n) {
+  return (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)p->n_cu * 8, (n + BIG_CHUNK - 1) / BIG_CHUNK));
+}
+
+template <typename T, int W, bool POLY>
+struct SpreadW {
+  static hipError_t run(const BigTileArgs<T> &a, int blocks, hipStream_t s) {
+    hipLaunchKernelGGL((big_spread_kernel<T, W, POLY>), dim3(blocks), dim3(BIG_SPREAD_THREADS), 0, s, a);
+    return hipGetLastError();
+  }
+};
+template <typename T, int W, bool POLY>
+struct GatherW {
+  static hipError_t run(const BigTileArgs<T> &a, int blocks, hipStream_t s) {
+    hipLaunchKernelGGL((big_gather_kernel<T, W, POLY>), dim3(blocks), dim3(256), 0, s, a);
+    return hipGetLastError();
+  }
+};
+
+// Width dispatch; the polynomial taps exist for FP32 plans with W <= ES_MAXW.
+template <typename T, template <typename, int, bool> class Fn>
+hipError_t by_width(int W, const BigTileArgs<T> &a, int blocks, hipStream_t s) {
+  if constexpr (sizeof(T) == 4) {
+    if (a.es.on) {
+      switch (W) {
+        case 4: return Fn<T, 4, true>::run(a, blocks, s);
+        case 6: return Fn<T, 6, true>::run(a, blocks, s);
+        case 8: return Fn<T, 8, true>::run(a, blocks, s);
+        default: return hipErrorInvalidValue;
+      }
+    }
+  }
+  switch (W) {
+    case 4: return Fn<T, 4, false>::run(a, blocks, s);
+    case 6: return Fn<T, 6, false>::run(a, blocks, s);
+    case 8: return Fn<T, 8, false>::run(a, blocks, s);
+    case 10: return Fn<T, 10, false>::run(a, blocks, s);
+    case 12: return Fn<T, 12, false>::run(a, blocks, s);
+    case 14: return Fn<T, 14, false>::run(a, blocks, s);
+    case 16: return Fn<T, 16, false>::run(a, blocks, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <typename T>
+enufft_status type1_t(enufft_plan_t p, const T *x, const T *y, const T *h, const T *w, T *f, int64_t c0,
+                      int64_t c1) {
+  const Geom &g = p->geom;
+  const size_t el = sizeof(T);
+  for (int64_t c = c0; c < c1; ++c) {
+    const int64_t n = p->offsets[c + 1] - p->offsets[c];
+    hipError_t e = fill<double>(p->big_grid, (int64_t)g.n1 * g.n2, 0.0, p->stream);
+    if (e == hipSuccess && n > 0) e = sort_cell<T>(p, c, x, y, h, w);
+    if (e == hipSuccess && n > 0) {
+      BigTileArgs<T> a = tile_args<T>(p, c);
+      a.grid = p->big_grid;
+      a.work_counter = p->big_work;
+      a.done_counter = p->big_work + 1;
+      e = by_width<T, SpreadW>(p->W, a, tile_blocks(p, n), p->stream);
+    }
+    if (e == hipSuccess) {
+      hipLaunchKernelGGL((big_rows_kernel<T>), dim3(g.n2 / 2), dim3(stock_threads(g.n1)), 4 * (size_t)g.n1 * el,
+                         p->stream, (const double *)p->big_grid, g, (const T *)p->d_tw1, (T *)p->big_cb);
+      e = hipGetLastError();
+    }
+    if (e == hipSuccess) {
+      hipLaunchKernelGGL((big_cols_kernel<T>), dim3(g.K1 + 1), dim3(stock_threads(g.n2)), 4 * (size_t)g.n2 * el,
+                         p->stream, (const T *)p->big_cb, g, (const T *)p->d_tw2, (const T *)p->d_decon_x,
+                         (const T *)p->d_decon_y, f + c * (int64_t)g.N1 * g.N2 * 2);
+      e = hipGetLastError();
+    }
+    if (e != hipSuccess) return big_fail(p, e, "large-cell type-1");
+  }
+  return ENUFFT_OK;
+}
+
+template <typename T>
+enufft_status adjoint_t(enufft_plan_t p, const T *x, const T *y, const T *h, const T *w, const T *fin,
+                        const uint8_t *keep, const double *lam, T *gh, T *gx, T *gy) {
+  const Geom &g = p->geom;
+  const int64_t M = (int64_t)g.N1 * g.N2;
+  const size_t el = sizeof(T);
+  for (int64_t c = 0; c < p->n_cells; ++c) {
+    const int64_t a0 = p->offsets[c], n = p->offsets[c + 1] - a0;
+    if (n == 0) continue;
+    hipError_t e = sort_cell<T>(p, c, x, y, h, w);
+    if (e == hipSuccess) {
+      hipLaunchKernelGGL((big_adj_cols_kernel<T>), dim3(g.K1 + 1), dim3(stock_threads(g.n2)), 4 * (size_t)g.n2 * el,
+                         p->stream, fin + c * M * 2, keep ? keep + c * M : nullptr, lam, c, g, (const T *)p->d_tw2,
+                         (const T *)p->d_decon_x, (const T *)p->d_decon_y, (T *)p->big_cb, (T *)p->big_cby);
+      e = hipGetLastError();
+    }
+    if (e == hipSuccess) {
+      hipLaunchKernelGGL((big_adj_rows_kernel<T>), dim3(g.n2 / 2), dim3(stock_threads(g.n1)), 4 * (size_t)g.n1 * el,
+                         p->stream, (const T *)p->big_cb, (const T *)p->big_cby, g, (const T *)p->d_tw1,
+                         (T *)p->big_gu, (T *)p->big_gx, (T *)p->big_gy);
+      e = hipGetLastError();
+    }
+    if (e == hipSuccess) {
+      BigTileArgs<T> a = tile_args<T>(p, c);
+      a.Gu = (const T *)p->big_gu; a.Gx = (const T *)p->big_gx; a.Gy = (const T *)p->big_gy;
+      a.grad_h = gh ? gh + a0 : nullptr;
+      a.grad_x = gx ? gx + a0 : nullptr;
+      a.grad_y = gy ? gy + a0 : nullptr;
+      a.work_counter = p->big_work + 2;
+      a.done_counter = p->big_work + 3;
+      e = by_width<T, GatherW>(p->W, a, tile_blocks(p, n), p->stream);
+    }
+    if (e != hipSuccess) return big_fail(p, e, "large-cell adjoint");
+  }
+  return ENUFFT_OK;
+}
+
+}  // namespace
+
+// Workspace of a large-cell plan: tile sort buffers sized for the largest cell,
+// the FP64 spreading grid, the column buffers, the three adjoint grids, the EMS
+// sort buffer (when a unit table can exceed the per-cell kernel's 4096) and
+// the work counters.
+enufft_status big_prepare(enufft_plan_t p) {
+  const Geom &g = p->geom;
+  p->big_ntx = g.n1 / BIG_TS;
+  p->big_nty = g.n2 / BIG_TS;
+  const int ntiles = p->big_ntx * p->big_nty;
+  int64_t qmax = 0;
+  for (int64_t c = 0; c < p->n_cells; ++c) qmax = std::max(qmax, p->offsets[c + 1] - p->offsets[c]);
+  if (qmax > (int64_t)INT32_MAX) {
+    p->last_error = "enufft_plan: a large cell holds more than 2^31 - 1 points";
+    return ENUFFT_EUNSUPPORTED;
+  }
+  const size_t el = p->elem;
+  const int64_t M = (int64_t)g.N1 * g.N2;
+  int64_t jpad = 64;
+  while (jpad < M) jpad <<= 1;
+  p->big_sort_jpad = jpad > BIG_SORT_BLOCK ? jpad : 0;
+  p->big_ems_parts = std::max<int64_t>(2 * ((jpad + 255) / 256), (M + 255) / 256);
+  const size_t n12 = (size_t)g.n1 * g.n2;
+  const size_t cols = (size_t)(g.K1 + 1) * g.n2 * 2 * el;
+  // sort buffer, partial sums, cut record (256 bytes reserved), tie flags
+  const size_t ems_bytes =
+      p->big_sort_jpad ? (size_t)p->big_sort_jpad * 8 + (size_t)p->big_ems_parts * 8 + 256 + (size_t)p->big_sort_jpad
+                       : 0;
+  struct A {
+    void **ptr;
+    size_t bytes;
+    const char *what;
+  };
+  const A list[] = {
+      {(void **)&p->big_counts, (size_t)ntiles * sizeof(int), "tile counts"},
+      {(void **)&p->big_offsets, (size_t)(ntiles + 1) * sizeof(int64_t), "tile offsets"},
+      {(void **)&p->big_cursor, (size_t)ntiles * sizeof(int64_t), "tile cursors"},
+      {(void **)&p->big_perm, (size_t)std::max<int64_t>(qmax, 1) * sizeof(int), "point permutation"},
+      {&p->big_xs, (size_t)std::max<int64_t>(qmax, 1) * el, "sorted x"},
+      {&p->big_ys, (size_t)std::max<int64_t>(qmax, 1) * el, "sorted y"},
+      {&p->big_hs, (size_t)std::max<int64_t>(qmax, 1) * el, "sorted h"},
+      {&p->big_ws, (size_t)std::max<int64_t>(qmax, 1) * el, "sorted w"},
+      {(void **)&p->big_grid, n12 * sizeof(double), "fine grid"},
+      {&p->big_cb, cols, "column buffer"},
+      {&p->big_cby, cols, "column buffer (y)"},
+      {&p->big_gu, n12 * el, "adjoint grid u"},
+      {&p->big_gx, n12 * el, "adjoint grid du/dx"},
+      {&p->big_gy, n12 * el, "adjoint grid du/dy"},
+      {(void **)&p->big_work, 4 * sizeof(int), "work counters"},
+      {(void **)&p->big_sort, ems_bytes, "EMS sort buffer"},
+  };
+  for (const A &it : list) {
+    if (it.bytes == 0) continue;
+    hipError_t e = hipMalloc(it.ptr, it.bytes);
+    if (e != hipSuccess) {
+      *it.ptr = nullptr;
+      p->last_error = std::string("hipMalloc failed for ") + it.what + ": " + hipGetErrorString(e);
+      return ENUFFT_ENOMEM;
+    }
+    p->allocations.push_back(*it.ptr);
+    p->workspace_bytes += (int64_t)it.bytes;
+  }
+  hipError_t e = hipMemset(p->big_work, 0, 4 * sizeof(int));
+  if (e == hipSuccess)
+    e = p->prec == ENUFFT_F64 ? set_attrs_t<double>(g.n1, g.n2, ntiles) : set_attrs_t<float>(g.n1, g.n2, ntiles);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  return big_fail(p, e, "large-cell workspace");
+}
+
+enufft_status big_type1(enufft_plan_t p, const void *x, const void *y, const void *h, const void *w, void *f,
+                        int64_t c0, int64_t c1) {
+  if (p->prec == ENUFFT_F64)
+    return type1_t<double>(p, (const double *)x, (const double *)y, (const double *)h, (const double *)w,
+                           (double *)f, c0, c1);
+  return type1_t<float>(p, (const float *)x, (const float *)y, (const float *)h, (const float *)w, (float *)f, c0,
+                        c1);
+}
+
+enufft_status big_adjoint(enufft_plan_t p, const void *x, const void *y, const void *h, const void *w,
+                          const void *fin, const uint8_t *keep, const double *lam, void *gh, void *gx, void *gy) {
+  if (p->prec == ENUFFT_F64)
+    return adjoint_t<double>(p, (const double *)x, (const double *)y, (const double *)h, (const double *)w,
+                             (const double *)fin, keep, lam, (double *)gh, (double *)gx, (double *)gy);
+  return adjoint_t<float>(p, (const float *)x, (const float *)y, (const float *)h, (const float *)w,
+                          (const float *)fin, keep, lam, (float *)gh, (float *)gx, (float *)gy);
+}
+
+// EMS of cells [cell_begin, cell_begin + cell_count) when the unit table is
+// larger than the per-cell kernel's register sort: energies, device sort,
+// scores, ties, keep, finish; one cell after the other.
+enufft_status big_ems(enufft_plan_t p, const void *f, const enufft_ems_params *prm, const double *mode_weight,
+                      uint8_t *keep, int32_t *k_star, double *stats, const UnitTable *ut, int64_t cell_begin,
+                      int64_t cell_count) {
+  const int J = ut->J, M = p->N1 * p->N2;
+  const int64_t Jpad = ut->Jpad;
+  if (!p->big_sort || Jpad > p->big_sort_jpad || Jpad < 2 * BIG_SORT_BLOCK) {
+    p->last_error = "EMS: unit table size not supported by the large-cell sort";
+    return ENUFFT_EUNSUPPORTED;
+  }
+  const int nb = (int)((Jpad + 255) / 256), mb = (M + 255) / 256;
+  double *S = p->big_sort;
+  double *partial = S + p->big_sort_jpad;
+  BigCut *cut = reinterpret_cast<BigCut *>(partial + p->big_ems_parts);
+  uint8_t *tie = reinterpret_cast<uint8_t *>(cut) + 256;
+  static_assert(sizeof(BigCut) <= 256, "cut record must fit its reserved bytes");
+  const size_t el = p->elem;
+  const int nblk = (int)(Jpad / BIG_SORT_BLOCK);
+  hipError_t e = hipSuccess;
+  for (int64_t c = cell_begin; c < cell_begin + cell_count && e == hipSuccess; ++c) {
+    const void *fc = (const char *)f + (size_t)c * M * 2 * el;
+    if (p->prec == ENUFFT_F64)
+      hipLaunchKernelGGL((big_ems_energy_kernel<double>), dim3(nb), dim3(256), 0, p->stream, (const double *)fc,
+                         mode_weight, ut->d_units, J, (int)Jpad, S, partial);
+    else
+      hipLaunchKernelGGL((big_ems_energy_kernel<float>), dim3(nb), dim3(256), 0, p->stream, (const float *)fc,
+                         mode_weight, ut->d_units, J, (int)Jpad, S, partial);
+    e = hipGetLastError();
+    if (e == hipSuccess) {
+      hipLaunchKernelGGL(big_sort_block_kernel, dim3(nblk), dim3(512), 0, p->stream, S, 2, BIG_SORT_BLOCK,
+                         BIG_SORT_BLOCK / 2);
+      e = hipGetLastError();
+    }
+    for (int64_t k = 2 * BIG_SORT_BLOCK; k <= Jpad && e == hipSuccess; k <<= 1) {
+      for (int64_t j = k >> 1; j >= BIG_SORT_BLOCK && e == hipSuccess; j >>= 1) {
+        hipLaunchKernelGGL(big_sort_global_kernel, dim3((int)std::min<int64_t>(4096, Jpad / 256)), dim3(256), 0,
+                           p->stream, S, Jpad, k, j);
+        e = hipGetLastError();
+      }
+      if (e == hipSuccess) {
+        hipLaunchKernelGGL(big_sort_block_kernel, dim3(nblk), dim3(512), 0, p->stream, S, (int)k, (int)k,
+                           BIG_SORT_BLOCK / 2);
+        e = hipGetLastError();
+      }
+    }
+    if (e == hipSuccess) {
+      hipLaunchKernelGGL(big_ems_scores_kernel, dim3(1), dim3(1024), 0, p->stream, (const double *)S,
+                         (const double *)partial, nb, J, *prm, cut);
+      e = hipGetLastError();
+    }
+    if (e == hipSuccess) {
+      if (p->prec == ENUFFT_F64)
+        hipLaunchKernelGGL((big_ems_ties_kernel<double>), dim3(1), dim3(1024), 0, p->stream, (const double *)fc,
+                           mode_weight, ut->d_units, J, (const BigCut *)cut, tie);
+      else
+        hipLaunchKernelGGL((big_ems_ties_kernel<float>), dim3(1), dim3(1024), 0, p->stream, (const float *)fc,
+                           mode_weight, ut->d_units, J, (const BigCut *)cut, tie);
+      e = hipGetLastError();
+    }
+    if (e == hipSuccess) {
+      if (p->prec == ENUFFT_F64)
+        hipLaunchKernelGGL((big_ems_keep_kernel<double>), dim3(mb), dim3(256), 0, p->stream, (const double *)fc,
+                           mode_weight, ut->d_mode_unit, M, (const BigCut *)cut, (const uint8_t *)tie, keep + c * M,
+                           partial);
+      else
+        hipLaunchKernelGGL((big_ems_keep_kernel<float>), dim3(mb), dim3(256), 0, p->stream, (const float *)fc,
+                           mode_weight, ut->d_mode_unit, M, (const BigCut *)cut, (const uint8_t *)tie, keep + c * M,
+                           partial);
+      e = hipGetLastError();
+    }
+    if (e == hipSuccess) {
+      hipLaunchKernelGGL(big_ems_finish_kernel, dim3(1), dim3(64), 0, p->stream, (const BigCut *)cut,
+                         (const double *)partial, mb, k_star + c, stats + c * 8);
+      e = hipGetLastError();
+    }
+  }
+  return big_fail(p, e, "large-cell EMS");
+}
+
+}  // namespace enufft

@@ -37,7 +37,7 @@ struct EsPoly {
 
 // Fine-grid and mode-box geometry.
 struct Geom {
-  int n1, n2;       // fine grid (powers of two, 16..128)
+  int n1, n2;       // fine grid (powers of two: 16..128 in LDS, 64..4096 for large cells)
   int N1, N2;       // modes per axis
   int lo1, lo2;     // -floor(N/2)
   int K1, K2;       // floor(N/2): largest |k| needed per axis
@@ -86,6 +86,7 @@ struct AdjArgs {
   T beta;
   T s1_hi, s1_lo, s2_hi, s2_lo;
   EsPoly es;                   // as in FwdArgs
+  int vec4;                    // x, y, h, w are 16-byte aligned: load runs of 4 points
   int bands, band_rows;        // row bands per cell and rows per band
   Geom g;
 };

@@ -530,6 +530,8 @@ enufft_status ems_launch(enufft_plan_t p, const void *f, const enufft_ems_params
   UnitTable *ut = nullptr;
   enufft_status st = ems_units(p, prm, &ut);
   if (st != ENUFFT_OK) return st;
+  if (ut->Jpad > 4096)   // beyond the per-cell register sort: device sort per cell
+    return big_ems(p, f, prm, mode_weight, keep, k_star, stats, ut, cell_begin, cell_count);
   EmsArgs a{};
   a.f = f; a.mode_weight = mode_weight; a.keep = keep; a.k_star = k_star; a.stats = stats;
   a.units = ut->d_units; a.mode_unit = ut->d_mode_unit; a.J = ut->J; a.M = p->N1 * p->N2;

@@ -383,9 +383,6 @@ enufft_status enufft_plan(enufft_plan_t *out, int64_t n_cells, const int64_t *ce
           !std::isfinite(windows[c].radius))
         return fail(nullptr, ENUFFT_EINVAL, "enufft_plan: window radius must be > 0 and finite");
   }
-  if (N1 > 64 || N2 > 64)
-    return fail(nullptr, ENUFFT_EUNSUPPORTED,
-                "enufft_plan: mode boxes above 64 per axis need the tiled HBM-grid path, not in this build");
   // Fine grid: the smallest power of two >= sigma N (and >= 16); the kernel
   // parameters follow the effective oversampling, and a grid narrower than two
   // kernel widths is widened (which only raises the oversampling).
@@ -397,8 +394,16 @@ enufft_status enufft_plan(enufft_plan_t *out, int64_t n_cells, const int64_t *ce
   kernel_params(opts->eps, sigma_eff, opts->kernel_width, &W, &beta);
   n1 = std::max(n1, next_pow2(2 * W));
   n2 = std::max(n2, next_pow2(2 * W));
-  if (n1 > 128 || n2 > 128)
-    return fail(nullptr, ENUFFT_EUNSUPPORTED, "enufft_plan: fine grid above 128 per axis is not in this build");
+  // Mode boxes above 64 per axis (or grids above 128) take the large-cell path:
+  // the grid lives in HBM and is tiled, each axis at least two tiles wide.
+  const bool big = N1 > 64 || N2 > 64 || n1 > 128 || n2 > 128;
+  if (big) {
+    n1 = std::max(n1, 64);
+    n2 = std::max(n2, 64);
+    if (n1 > 4096 || n2 > 4096 || (int64_t)n1 * n2 > (int64_t)1 << 23)
+      return fail(nullptr, ENUFFT_EUNSUPPORTED,
+                  "enufft_plan: fine grid above 4096 per axis or 2^23 cells is not supported");
+  }
 
   // ---- device
   std::string arch;
@@ -415,6 +420,7 @@ enufft_status enufft_plan(enufft_plan_t *out, int64_t n_cells, const int64_t *ce
   p->elem = p->prec == ENUFFT_F64 ? 8 : 4;
   p->stream = (hipStream_t)hip_stream;
   p->opts = *opts;
+  p->big = big;
   if (windows) p->windows_host.assign(windows, windows + n_cells);
   Geom &g = p->geom;
   g.n1 = n1; g.n2 = n2; g.N1 = N1; g.N2 = N2;
@@ -443,10 +449,13 @@ enufft_status enufft_plan(enufft_plan_t *out, int64_t n_cells, const int64_t *ce
   }
 
   // ---- forward launch shape (threads per workgroup: ENUFFT_FWD_THREADS, or the autotuner)
-  int threads = 512;
-  if (const char *ev = std::getenv("ENUFFT_FWD_THREADS")) threads = std::atoi(ev);
-  enufft_status st = enufft::set_fwd_threads(p, threads, (size_t)prop.sharedMemPerBlock);
-  if (st != ENUFFT_OK) { std::string m = p->last_error; free_plan(p); return fail(nullptr, st, m); }
+  enufft_status st = ENUFFT_OK;
+  if (!big) {
+    int threads = 512;
+    if (const char *ev = std::getenv("ENUFFT_FWD_THREADS")) threads = std::atoi(ev);
+    st = enufft::set_fwd_threads(p, threads, (size_t)prop.sharedMemPerBlock);
+    if (st != ENUFFT_OK) { std::string m = p->last_error; free_plan(p); return fail(nullptr, st, m); }
+  }
 
   // ---- tables (FP64 on the host, rounded to the compute precision)
   const int Kx = g.K1, Ky = g.K2;
@@ -493,7 +502,7 @@ enufft_status enufft_plan(enufft_plan_t *out, int64_t n_cells, const int64_t *ce
   }
   ALLOC(p->d_windows, win.size() * sizeof(double), "windows");
   UPLOAD(p->d_windows, win.data(), win.size() * sizeof(double), "upload windows");
-  st = enufft::install_fwd_schedule(p);
+  st = big ? enufft::big_prepare(p) : enufft::install_fwd_schedule(p);
   if (st != ENUFFT_OK) { std::string m = p->last_error; free_plan(p); return fail(nullptr, st, m); }
   ALLOC(p->d_counters, 16 * sizeof(int), "counters");
   ALLOC(p->d_cell_counters, std::max<int64_t>(1, n_cells) * sizeof(int), "cell counters");
@@ -503,7 +512,7 @@ enufft_status enufft_plan(enufft_plan_t *out, int64_t n_cells, const int64_t *ce
   if (e != hipSuccess) { st = hip_fail(p, e, "zero counters"); std::string m = p->last_error; free_plan(p); return fail(nullptr, st, m); }
 #undef ALLOC
 #undef UPLOAD
-  if (opts->autotune) {
+  if (opts->autotune && !big) {
     st = enufft::autotune(p);
     if (st != ENUFFT_OK) { std::string m = p->last_error; free_plan(p); return fail(nullptr, st, m); }
   }
@@ -660,6 +669,11 @@ extern "C" enufft_status enufft_type1_batched(enufft_plan_t p, const void *x, co
   hipEvent_t ev;
   st = enufft::record_start(p, 0, &ev);
   if (st != ENUFFT_OK) return st;
+  if (p->big) {
+    st = enufft::big_type1(p, x, y, h, w, f, 0, p->n_cells);
+    if (st != ENUFFT_OK) return st;
+    return enufft::record_stop(p, 0, ev);
+  }
   hipError_t e;
   if (p->prec == ENUFFT_F64) {
     auto a = enufft::make_fwd_args<double>(p, x, y, h, w, f);
@@ -675,6 +689,7 @@ extern "C" enufft_status enufft_type1_batched(enufft_plan_t p, const void *x, co
 namespace enufft {
 enufft_status percell_fwd(enufft_plan_t p, int64_t c, const void *x, const void *y, const void *h, const void *w,
                           void *f) {
+  if (p->big) return big_type1(p, x, y, h, w, f, c, c + 1);
   const int64_t first = p->fwd_cell_first[c], cnt = p->fwd_cell_first[c + 1] - first;
   if (cnt == 0) return ENUFFT_OK;
   hipError_t e;
@@ -756,6 +771,11 @@ extern "C" enufft_status enufft_forward_graph(enufft_plan_t p, const void *x, co
   if (p->n_points > 0 && (!x || !y || !h || !w)) return fail(p, ENUFFT_EINVAL, "enufft_forward_graph: null point array");
   st = enufft::ems_validate(p, f, prm, keep, k_star, stats);
   if (st != ENUFFT_OK) return st;
+  {   // unit tables are built (allocated, uploaded) outside the capture
+    enufft::UnitTable *ut = nullptr;
+    st = enufft::ems_units(p, prm, &ut);
+    if (st != ENUFFT_OK) return st;
+  }
   std::vector<uint8_t> key;
   const void *ptrs[] = {x, y, h, w, f, mode_weight, keep, k_star, stats};
   key_append(key, ptrs, sizeof(ptrs));

@@ -75,6 +75,21 @@ struct enufft_plan_s {
   int64_t workspace_bytes = 0;
   std::vector<void *> allocations;
 
+  // large-cell path: fine grid in HBM, points sorted by tile (mode boxes above 64 per axis)
+  bool big = false;
+  int big_ntx = 0, big_nty = 0;              // tiles per axis
+  int *big_counts = nullptr;                 // [tiles]
+  int64_t *big_offsets = nullptr;            // [tiles + 1]
+  int64_t *big_cursor = nullptr;             // [tiles]
+  int *big_perm = nullptr;                   // [largest cell] original index per sorted position
+  void *big_xs = nullptr, *big_ys = nullptr, *big_hs = nullptr, *big_ws = nullptr;
+  double *big_grid = nullptr;                // n2 x n1 FP64 spreading grid
+  void *big_cb = nullptr, *big_cby = nullptr;   // column buffers [K1 + 1][n2] complex
+  void *big_gu = nullptr, *big_gx = nullptr, *big_gy = nullptr;   // adjoint grids
+  int *big_work = nullptr;                   // persistent-loop counters
+  double *big_sort = nullptr;                // EMS sort buffer, partials, cut record, tie flags
+  int64_t big_sort_jpad = 0, big_ems_parts = 0;
+
   // captured forward (type-1 + EMS) graph and the arguments it was captured with
   hipStream_t capture_stream = nullptr;
   hipGraph_t graph = nullptr;
@@ -96,4 +111,14 @@ enufft_status install_fwd_schedule(enufft_plan_t p);
 enufft_status set_fwd_threads(enufft_plan_t p, int threads, size_t lds_limit);
 void adj_reset(enufft_plan_t p);
 enufft_status autotune(enufft_plan_t p);
+enufft_status ems_units(enufft_plan_t p, const enufft_ems_params *prm, UnitTable **ut);
+// Large-cell path (fine grid in HBM).
+enufft_status big_prepare(enufft_plan_t p);
+enufft_status big_type1(enufft_plan_t p, const void *x, const void *y, const void *h, const void *w, void *f,
+                        int64_t c0, int64_t c1);
+enufft_status big_adjoint(enufft_plan_t p, const void *x, const void *y, const void *h, const void *w,
+                          const void *fin, const uint8_t *keep, const double *lam, void *gh, void *gx, void *gy);
+enufft_status big_ems(enufft_plan_t p, const void *f, const enufft_ems_params *prm, const double *mode_weight,
+                      uint8_t *keep, int32_t *k_star, double *stats, const UnitTable *ut, int64_t cell_begin,
+                      int64_t cell_count);
 }  // namespace enufft

@@ -429,6 +429,61 @@ def config3(device="cpu", n_cells: int | None = None, count_scale: float = 1.0, 
     return _finish("C3 %d icosahedral triangles" % n_cells, x, y, h, off, area, win, (64, 64), 2.0, 1e-5, precision)
 
 
+def config4(device="cpu", Q: int = 100_000_000, precision: str = "f32", n_modes=(512, 512),
+            seed_config: int = 4, chunk: int = 1 << 24, progress=None) -> Batch:
+    """One hexagon (circumradius pi) with Q points: 30 % uniform background, 70 % from a
+    4-component isotropic Gaussian mixture (means area-uniform within radius 0.6 pi, sd
+    U(0.1, 0.4), weights Dirichlet(1)), draws outside the hexagon redrawn; heights from 400
+    sinusoids with |k| area-uniform in [1, 400] and amplitude |k|^-1.5, std 1,000 m, no
+    noise; weights = bin area / points in the bin of a 256 x 256 histogram over
+    [-pi, pi]^2 (inverse local density); radial Hann over the circumradius; 512 x 512
+    modes, sigma 2, eps 1e-5 (FP32) or 1e-10 (FP64).  Positions are drawn in chunks of
+    ``chunk`` candidates so memory stays bounded at Q = 1e8."""
+    R = math.pi
+    rng = np.random.Generator(np.random.PCG64(1000 * seed_config + 0))
+    kx, ky, am, ph = _draw_terrain(rng, 400, 400.0, 1.5)
+    terr = Terrain(kx[None], ky[None], am[None], ph[None], np.array([1000.0]), 0.0)
+    rm = 0.6 * R * np.sqrt(rng.uniform(0.0, 1.0, size=4))
+    tm = rng.uniform(0.0, TWO_PI, size=4)
+    means = np.stack([rm * np.cos(tm), rm * np.sin(tm)], axis=1)
+    sds = rng.uniform(0.1, 0.4, size=4)
+    wts = rng.dirichlet(np.ones(4))
+    n_bg = int(round(0.3 * Q))
+    n_comp = rng.multinomial(Q - n_bg, wts)
+    gen = torch.Generator(device=device).manual_seed(1000 * seed_config + 7)
+    xs, ys = [], []
+    if n_bg > 0:
+        bx, by = _uniform_in_hexagon(np.array([n_bg], dtype=np.int64), R, gen, device)
+        xs.append(bx); ys.append(by)
+    for m in range(4):
+        need = int(n_comp[m])
+        while need > 0:
+            nc = min(chunk, int(need * 1.3) + 1024)
+            px = torch.randn(nc, dtype=torch.float64, device=device, generator=gen) * sds[m] + means[m, 0]
+            py = torch.randn(nc, dtype=torch.float64, device=device, generator=gen) * sds[m] + means[m, 1]
+            ok = torch.nonzero(_inside_hexagon(px, py, R)).flatten()[:need]
+            xs.append(px[ok]); ys.append(py[ok])
+            need -= ok.numel()
+        if progress:
+            progress("positions: component %d of 4" % (m + 1))
+    x = torch.cat(xs); y = torch.cat(ys)
+    del xs, ys
+    off = np.array([0, Q], dtype=np.int64)
+    h = _eval_terrain(x, y, torch.zeros(Q, dtype=torch.long, device=device), terr, off, gen, progress=progress)
+    nb = 256
+    bw = TWO_PI / nb
+    ix = torch.clamp(torch.floor((x + R) / bw).to(torch.long), 0, nb - 1)
+    iy = torch.clamp(torch.floor((y + R) / bw).to(torch.long), 0, nb - 1)
+    b = iy * nb + ix
+    cnt = torch.bincount(b, minlength=nb * nb).to(torch.float64)
+    w = (bw * bw) / cnt[b]
+    dt = torch.float64 if precision == "f64" else torch.float32
+    return Batch("C4 one hexagon Q=%d clustered" % Q, x.to(dt).contiguous(), y.to(dt).contiguous(),
+                 h.to(dt).contiguous(), w.to(dt).contiguous(), off, np.array([[0.0, 0.0, R]]),
+                 tuple(n_modes), 2.0, 1e-10 if precision == "f64" else 1e-5, precision,
+                 np.array([hexagon_area(R)]))
+
+
 def uniform_box(device="cpu", counts=(1000,), n_modes=(16, 16), seed: int = 11, precision: str = "f64",
                 lo: float = -math.pi, hi: float = math.pi, window_radius: float = 0.0) -> Batch:
     """Plain uniform points on a square, heights N(0,1), weights box-area/Q.  With

@@ -76,7 +76,7 @@ def test_default_opts():
     (dict(window_kind=5), enf.EINVAL),
     (dict(windows=False), enf.EINVAL),                     # Hann needs windows
     (dict(kernel_width=40), enf.EINVAL),
-    (dict(n_modes=(128, 128)), enf.EUNSUPPORTED),
+    (dict(n_modes=(2100, 64)), enf.EUNSUPPORTED),           # fine grid above 4096
 ])
 def test_plan_argument_errors(kw, code):
     st, h, L = _plan(**kw)
