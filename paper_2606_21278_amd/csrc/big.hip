@@ -184,29 +184,82 @@ __global__ __launch_bounds__(1024) void big_scan_kernel(const int *counts, int n
   }
 }
 
-// Scatter: each chunk reserves its range in every tile with one global atomic
-// per (chunk, tile) and places its points by LDS ranks.
+// Scatter, one chunk of BIG_SCATTER_CHUNK points per workgroup, as a local
+// counting sort: the chunk's tile histogram in LDS, its exclusive scan, one
+// global atomic per non-empty tile to reserve the chunk's range in that tile,
+// then the chunk's points ranked into tile order in LDS (a 16-bit index per
+// point) and copied out with consecutive threads writing consecutive positions
+// of each tile's range, so the stores of a tile's segment coalesce.  (Ranks
+// straight from the atomics would send the 64 lanes of a store to 64 different
+// tiles' ranges: one partial cache line per 4-byte store.)
+constexpr int BIG_SCATTER_CHUNK = 16384;
+constexpr int BIG_SCATTER_THREADS = 512;
+
+__device__ __forceinline__ int big_wave_incl_scan(int v) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int t = __shfl_up(v, o, 64);
+    if (lane >= o) v += t;
+  }
+  return v;
+}
+
+// Exclusive scan of cnt[0 .. n) into out[0 .. n) by the whole workgroup
+// (BIG_SCATTER_THREADS threads, each owning a contiguous run of entries).
+__device__ void big_block_scan(const int *cnt, int *out, int n, int *wsum) {
+  constexpr int NW = BIG_SCATTER_THREADS / 64;
+  const int per = (n + BIG_SCATTER_THREADS - 1) / BIG_SCATTER_THREADS;
+  const int t0 = min(n, (int)threadIdx.x * per), t1 = min(n, t0 + per);
+  int v = 0;
+  for (int t = t0; t < t1; ++t) v += cnt[t];
+  const int inc = big_wave_incl_scan(v);
+  const int wave = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 63) wsum[wave] = inc;
+  __syncthreads();
+  int run = inc - v;
+  for (int w = 0; w < NW; ++w)
+    if (w < wave) run += wsum[w];
+  for (int t = t0; t < t1; ++t) {
+    out[t] = run;
+    run += cnt[t];
+  }
+  __syncthreads();
+}
+
 template <typename T>
-__global__ __launch_bounds__(512) void big_scatter_kernel(BigSortArgs<T> a) {
+__global__ __launch_bounds__(BIG_SCATTER_THREADS) void big_scatter_kernel(BigSortArgs<T> a) {
   extern __shared__ int smem[];
-  int *hist = smem;                                                          // [ntiles]
-  int64_t *base = reinterpret_cast<int64_t *>(smem + ((a.ntiles + 1) & ~1));   // [ntiles], 8-byte aligned
+  int *hist = smem;                    // [ntiles] counts, then the fill cursors
+  int *lstart = hist + a.ntiles;       // [ntiles] chunk-local start of each tile
+  int *gbase = lstart + a.ntiles;      // [ntiles] global start of the chunk's range in each tile
+  uint16_t *stage = reinterpret_cast<uint16_t *>(gbase + a.ntiles);   // [chunk] point index by slot
+  __shared__ int wsum[BIG_SCATTER_THREADS / 64];
+  const int64_t s = (int64_t)blockIdx.x * BIG_SCATTER_CHUNK;
+  const int cnt = (int)(min(a.n, s + BIG_SCATTER_CHUNK) - s);
   for (int i = threadIdx.x; i < a.ntiles; i += blockDim.x) hist[i] = 0;
   __syncthreads();
-  const int64_t s = (int64_t)blockIdx.x * BIG_BIN_CHUNK, e = min(a.n, s + BIG_BIN_CHUNK);
-  for (int64_t j = s + threadIdx.x; j < e; j += blockDim.x) atomicAdd(&hist[big_tile<T>(a, a.x[j], a.y[j])], 1);
+  for (int li = threadIdx.x; li < cnt; li += blockDim.x) atomicAdd(&hist[big_tile<T>(a, a.x[s + li], a.y[s + li])], 1);
   __syncthreads();
+  big_block_scan(hist, lstart, a.ntiles, wsum);
   for (int i = threadIdx.x; i < a.ntiles; i += blockDim.x) {
     const int c = hist[i];
-    base[i] = c ? (int64_t)atomicAdd((unsigned long long *)&a.cursor[i], (unsigned long long)c) : 0;
+    gbase[i] = c ? (int)atomicAdd((unsigned long long *)&a.cursor[i], (unsigned long long)c) : 0;
     hist[i] = 0;
   }
   __syncthreads();
-  for (int64_t j = s + threadIdx.x; j < e; j += blockDim.x) {
+  for (int li = threadIdx.x; li < cnt; li += blockDim.x) {
+    const int t = big_tile<T>(a, a.x[s + li], a.y[s + li]);
+    const int slot = lstart[t] + atomicAdd(&hist[t], 1);
+    if (slot < cnt) stage[slot] = (uint16_t)li;   // always true when both passes agree on the tile
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < cnt; i += blockDim.x) {
+    const int64_t j = s + min((int)stage[i], cnt - 1);   // clamp: stays inside the chunk whatever LDS held
     const T xj = a.x[j], yj = a.y[j];
     const int t = big_tile<T>(a, xj, yj);
-    const int64_t pos = base[t] + atomicAdd(&hist[t], 1);
-    if (pos >= a.n) continue;   // only if the two passes disagreed on a tile; never out of bounds
+    const int64_t pos = (int64_t)gbase[t] + (i - lstart[t]);
+    if (pos < 0 || pos >= a.n) continue;   // only if the passes disagreed on a tile; never out of bounds
     a.perm[pos] = (int)j;
     a.xs[pos] = xj;
     a.ys[pos] = yj;
@@ -242,7 +295,7 @@ struct BigTileArgs {
   T s1h, s1l, s2h, s2l, beta;
   EsPoly es;
   double *grid;             // spreading: n2 x n1 FP64 accumulator
-  const T *Gu, *Gx, *Gy;    // gather: n2 x n1 grids u, du/dx, du/dy
+  const typename vec4<T>::type *G4;   // gather: n2 x n1 cells of (u, du/dx, du/dy, 0)
   T *grad_h, *grad_x, *grad_y;   // gather: indexed by the cell-local original point index
 };
 
@@ -747,8 +800,8 @@ __global__ __launch_bounds__(512) void big_adj_cols_kernel(const T *fin, const u
 // same for row 2p + 1, and du/dy of row 2p + i du/dy of row 2p + 1.  Bins
 // kx < 0 are the conjugates of column -kx (the grids are real).
 template <typename T>
-__global__ __launch_bounds__(512) void big_adj_rows_kernel(const T *cb, const T *cby, Geom g, const T *tw1, T *Gu,
-                                                           T *Gx, T *Gy) {
+__global__ __launch_bounds__(512) void big_adj_rows_kernel(const T *cb, const T *cby, Geom g, const T *tw1,
+                                                           typename vec4<T>::type *G4) {
   extern __shared__ __align__(16) unsigned char sm_raw[];
   const int n1 = g.n1, n2 = g.n2;
   T *A = reinterpret_cast<T *>(sm_raw), *B = A + 2 * n1;
@@ -783,14 +836,16 @@ __global__ __launch_bounds__(512) void big_adj_rows_kernel(const T *cb, const T 
     const T *Z = stockham<true, T>(A, B, n1, tw1);
     for (int i = threadIdx.x; i < n1; i += blockDim.x) {
       if (pass == 0) {
-        Gu[r0 + i] = Z[2 * i];
-        Gx[r0 + i] = Z[2 * i + 1];
+        G4[r0 + i].x = Z[2 * i];
+        G4[r0 + i].y = Z[2 * i + 1];
       } else if (pass == 1) {
-        Gu[r1 + i] = Z[2 * i];
-        Gx[r1 + i] = Z[2 * i + 1];
+        G4[r1 + i].x = Z[2 * i];
+        G4[r1 + i].y = Z[2 * i + 1];
       } else {
-        Gy[r0 + i] = Z[2 * i];
-        Gy[r1 + i] = Z[2 * i + 1];
+        G4[r0 + i].z = Z[2 * i];
+        G4[r0 + i].w = T(0);
+        G4[r1 + i].z = Z[2 * i + 1];
+        G4[r1 + i].w = T(0);
       }
     }
     __syncthreads();
@@ -799,10 +854,17 @@ __global__ __launch_bounds__(512) void big_adj_rows_kernel(const T *cb, const T 
 
 // Gather (the type-2 interpolation back to the points) from the three grids,
 // each tile run staging its sub-grid of u, du/dx and du/dy in LDS.
+template <typename T, int W>
+constexpr size_t big_gather_lds() {
+  return (size_t)(BIG_TS + W + 1) * (BIG_TS + W + 1) * sizeof(typename vec4<T>::type);
+}
+
 template <typename T, int W, bool POLY>
 __global__ __launch_bounds__(256) void big_gather_kernel(BigTileArgs<T> a) {
   constexpr int S = BIG_TS + W + 1;
-  __shared__ T su[S * S], sx[S * S], sy[S * S];
+  using V4 = typename vec4<T>::type;
+  extern __shared__ __align__(16) unsigned char sm_raw[];
+  V4 *sg = reinterpret_cast<V4 *>(sm_raw);   // [S * S] staged (u, du/dx, du/dy, 0)
   __shared__ int s_chunk;
   const Geom &g = a.g;
   const T halfw = T(W) / T(2);
@@ -813,10 +875,7 @@ __global__ __launch_bounds__(256) void big_gather_kernel(BigTileArgs<T> a) {
     const int tx0 = (t % a.ntx) * BIG_TS, ty0 = (t / a.ntx) * BIG_TS;
     for (int i = threadIdx.x; i < S * S; i += blockDim.x) {
       const int r = i / S, q = i - r * S;
-      const int64_t gi = (int64_t)((ty0 - 1 + r) & (g.n2 - 1)) * g.n1 + ((tx0 - 1 + q) & (g.n1 - 1));
-      su[i] = a.Gu[gi];
-      sx[i] = a.Gx[gi];
-      sy[i] = a.Gy[gi];
+      sg[i] = a.G4[(int64_t)((ty0 - 1 + r) & (g.n2 - 1)) * g.n1 + ((tx0 - 1 + q) & (g.n1 - 1))];
     }
     __syncthreads();
     for (int64_t k = lo + threadIdx.x; k < hi; k += blockDim.x) {
@@ -833,20 +892,27 @@ __global__ __launch_bounds__(256) void big_gather_kernel(BigTileArgs<T> a) {
         T au = 0, ax = 0, ay = 0;
 #pragma unroll
         for (int dx = 0; dx < W; ++dx) {
-          au += kx[dx] * su[rb + dx];
-          ax += kx[dx] * sx[rb + dx];
-          ay += kx[dx] * sy[rb + dx];
+          const V4 v = sg[rb + dx];
+          au += kx[dx] * v.x;
+          ax += kx[dx] * v.y;
+          ay += kx[dx] * v.z;
         }
         u += kyv * au;
         ux += kyv * ax;
         uy += kyv * ay;
       };
+      // one row at a time keeps the loads of W rows from being hoisted together
       if constexpr (POLY) {
         T ky[W];
         big_taps<T, W, POLY>(fy, a.beta, a.es, ky);
+#pragma unroll 1
+        for (int dy = 0; dy < W; ++dy) {
+          T kyv = ky[0];
 #pragma unroll
-        for (int dy = 0; dy < W; ++dy) row(dy, ky[dy]);
-      } else {   // one row at a time keeps the loads of W rows from being hoisted together
+          for (int q = 1; q < W; ++q) kyv = dy == q ? ky[q] : kyv;   // register select, no indexed access
+          row(dy, kyv);
+        }
+      } else {
         const T zsc = T(2) / T(W);
 #pragma unroll 1
         for (int dy = 0; dy < W; ++dy) row(dy, es_eval(fy.offset(dy) * zsc, a.beta));
@@ -881,7 +947,7 @@ enufft_status big_fail(enufft_plan_t p, hipError_t e, const char *what) {
 
 int stock_threads(int n) { return std::min(512, std::max(64, n / 2)); }
 
-size_t sort_lds(int ntiles) { return (size_t)((ntiles + 1) & ~1) * sizeof(int) + (size_t)ntiles * sizeof(int64_t); }
+size_t sort_lds(int ntiles) { return (size_t)3 * ntiles * sizeof(int) + (size_t)BIG_SCATTER_CHUNK * sizeof(uint16_t); }
 
 template <typename T>
 hipError_t set_attrs_t(int n1, int n2, int ntiles) {
@@ -929,7 +995,9 @@ hipError_t sort_cell(enufft_plan_t p, int64_t c, const T *x, const T *y, const T
     e = hipGetLastError();
   }
   if (e == hipSuccess && a.n > 0) {
-    hipLaunchKernelGGL((big_scatter_kernel<T>), dim3(blocks), dim3(512), sort_lds(a.ntiles), p->stream, a);
+    const int sblocks = (int)((a.n + BIG_SCATTER_CHUNK - 1) / BIG_SCATTER_CHUNK);
+    hipLaunchKernelGGL((big_scatter_kernel<T>), dim3(sblocks), dim3(BIG_SCATTER_THREADS), sort_lds(a.ntiles),
+                       p->stream, a);
     e = hipGetLastError();
   }
   return e;
@@ -969,8 +1037,13 @@ struct SpreadW {
 template <typename T, int W, bool POLY>
 struct GatherW {
   static hipError_t run(const BigTileArgs<T> &a, int blocks, hipStream_t s) {
-    hipLaunchKernelGGL((big_gather_kernel<T, W, POLY>), dim3(blocks), dim3(256), 0, s, a);
+    const size_t lds = big_gather_lds<T, W>();
+    hipLaunchKernelGGL((big_gather_kernel<T, W, POLY>), dim3(blocks), dim3(256), lds, s, a);
     return hipGetLastError();
+  }
+  static hipError_t attr() {
+    return hipFuncSetAttribute((const void *)&big_gather_kernel<T, W, POLY>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)big_gather_lds<T, W>());
   }
 };
 
@@ -997,6 +1070,25 @@ hipError_t by_width(int W, const BigTileArgs<T> &a, int blocks, hipStream_t s) {
     case 16: return Fn<T, 16, false>::run(a, blocks, s);
     default: return hipErrorInvalidValue;
   }
+}
+
+// Dynamic LDS limits of every gather variant (the FP64 wide ones exceed 64 KB).
+template <typename T>
+hipError_t gather_attrs() {
+  hipError_t e = hipSuccess;
+  if constexpr (sizeof(T) == 4) {
+    if (e == hipSuccess) e = GatherW<T, 4, true>::attr();
+    if (e == hipSuccess) e = GatherW<T, 6, true>::attr();
+    if (e == hipSuccess) e = GatherW<T, 8, true>::attr();
+  }
+  if (e == hipSuccess) e = GatherW<T, 4, false>::attr();
+  if (e == hipSuccess) e = GatherW<T, 6, false>::attr();
+  if (e == hipSuccess) e = GatherW<T, 8, false>::attr();
+  if (e == hipSuccess) e = GatherW<T, 10, false>::attr();
+  if (e == hipSuccess) e = GatherW<T, 12, false>::attr();
+  if (e == hipSuccess) e = GatherW<T, 14, false>::attr();
+  if (e == hipSuccess) e = GatherW<T, 16, false>::attr();
+  return e;
 }
 
 template <typename T>
@@ -1050,12 +1142,12 @@ enufft_status adjoint_t(enufft_plan_t p, const T *x, const T *y, const T *h, con
     if (e == hipSuccess) {
       hipLaunchKernelGGL((big_adj_rows_kernel<T>), dim3(g.n2 / 2), dim3(stock_threads(g.n1)), 4 * (size_t)g.n1 * el,
                          p->stream, (const T *)p->big_cb, (const T *)p->big_cby, g, (const T *)p->d_tw1,
-                         (T *)p->big_gu, (T *)p->big_gx, (T *)p->big_gy);
+                         (typename vec4<T>::type *)p->big_gu);
       e = hipGetLastError();
     }
     if (e == hipSuccess) {
       BigTileArgs<T> a = tile_args<T>(p, c);
-      a.Gu = (const T *)p->big_gu; a.Gx = (const T *)p->big_gx; a.Gy = (const T *)p->big_gy;
+      a.G4 = (const typename vec4<T>::type *)p->big_gu;
       a.grad_h = gh ? gh + a0 : nullptr;
       a.grad_x = gx ? gx + a0 : nullptr;
       a.grad_y = gy ? gy + a0 : nullptr;
@@ -1114,9 +1206,7 @@ enufft_status big_prepare(enufft_plan_t p) {
       {(void **)&p->big_grid, n12 * sizeof(double), "fine grid"},
       {&p->big_cb, cols, "column buffer"},
       {&p->big_cby, cols, "column buffer (y)"},
-      {&p->big_gu, n12 * el, "adjoint grid u"},
-      {&p->big_gx, n12 * el, "adjoint grid du/dx"},
-      {&p->big_gy, n12 * el, "adjoint grid du/dy"},
+      {&p->big_gu, 4 * n12 * el, "adjoint grids (u, du/dx, du/dy) interleaved"},
       {(void **)&p->big_work, 4 * sizeof(int), "work counters"},
       {(void **)&p->big_sort, ems_bytes, "EMS sort buffer"},
   };
@@ -1134,6 +1224,7 @@ enufft_status big_prepare(enufft_plan_t p) {
   hipError_t e = hipMemset(p->big_work, 0, 4 * sizeof(int));
   if (e == hipSuccess)
     e = p->prec == ENUFFT_F64 ? set_attrs_t<double>(g.n1, g.n2, ntiles) : set_attrs_t<float>(g.n1, g.n2, ntiles);
+  if (e == hipSuccess) e = p->prec == ENUFFT_F64 ? gather_attrs<double>() : gather_attrs<float>();
   if (e == hipSuccess) e = hipDeviceSynchronize();
   return big_fail(p, e, "large-cell workspace");
 }

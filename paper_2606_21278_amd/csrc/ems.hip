@@ -282,23 +282,31 @@ __global__ __launch_bounds__(64 * NW) void ems_kernel(EmsArgs a) {
     __syncthreads();
     const int o0 = t * R;                       // first output position
     const int base = o0 / (2 * width) * (2 * width);
+    // runs A = [base, base + width) and B = the rest of the pair (shorter, or
+    // empty, at the end when NW is not a power of two)
+    const int lb = min(width, max(0, JP - base - width));
     const double *A = sorted + base, *B = A + width;
     const int d = o0 - base;                    // outputs before mine in this merged run
-    int lo = d > width ? d - width : 0, hi = d < width ? d : width;
-    while (lo < hi) {                           // first d outputs take lo from A
-      const int mid = (lo + hi) >> 1;
-      if (A[mid] >= B[d - 1 - mid]) lo = mid + 1;
-      else hi = mid;
-    }
-    int ia = lo, ib = d - lo;
     double out[R];
+    if (lb > 0) {
+      int lo = d > lb ? d - lb : 0, hi = d < width ? d : width;
+      while (lo < hi) {                         // first d outputs take lo from A
+        const int mid = (lo + hi) >> 1;
+        if (A[mid] >= B[d - 1 - mid]) lo = mid + 1;
+        else hi = mid;
+      }
+      int ia = lo, ib = d - lo;
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const double va = A[min(ia, width - 1)], vb = B[min(ib, width - 1)];   // in bounds; guarded below
-      const bool take_a = ib >= width || (ia < width && va >= vb);
-      out[r] = take_a ? va : vb;
-      ia += take_a;
-      ib += !take_a;
+      for (int r = 0; r < R; ++r) {
+        const double va = A[min(ia, width - 1)], vb = B[min(ib, lb - 1)];   // in bounds; guarded below
+        const bool take_a = ib >= lb || (ia < width && va >= vb);
+        out[r] = take_a ? va : vb;
+        ia += take_a;
+        ib += !take_a;
+      }
+    } else {                                    // unpaired run: already in place
+#pragma unroll
+      for (int r = 0; r < R; ++r) out[r] = sorted[o0 + r];
     }
     __syncthreads();
 #pragma unroll
@@ -506,19 +514,20 @@ enufft_status ems_validate(enufft_plan_t p, const void *f, const enufft_ems_para
   return ENUFFT_OK;
 }
 
+// Sort size per cell: the smallest 64 R NW >= J (R a power of two up to 16,
+// then 1 to 4 waves of 1,024).
 template <typename T>
-hipError_t launch_ems_t(const EmsArgs &a, int Jpad, int blocks, hipStream_t s) {
+hipError_t launch_ems_t(const EmsArgs &a, int J, int blocks, hipStream_t s) {
   const dim3 g(blocks);
-  switch (Jpad) {
-    case 64: hipLaunchKernelGGL((ems_kernel<T, 1, 1>), g, dim3(64), 0, s, a); break;
-    case 128: hipLaunchKernelGGL((ems_kernel<T, 2, 1>), g, dim3(64), 0, s, a); break;
-    case 256: hipLaunchKernelGGL((ems_kernel<T, 4, 1>), g, dim3(64), 0, s, a); break;
-    case 512: hipLaunchKernelGGL((ems_kernel<T, 8, 1>), g, dim3(64), 0, s, a); break;
-    case 1024: hipLaunchKernelGGL((ems_kernel<T, 16, 1>), g, dim3(64), 0, s, a); break;
-    case 2048: hipLaunchKernelGGL((ems_kernel<T, 16, 2>), g, dim3(128), 0, s, a); break;
-    case 4096: hipLaunchKernelGGL((ems_kernel<T, 16, 4>), g, dim3(256), 0, s, a); break;
-    default: return hipErrorInvalidValue;
-  }
+  if (J <= 64) hipLaunchKernelGGL((ems_kernel<T, 1, 1>), g, dim3(64), 0, s, a);
+  else if (J <= 128) hipLaunchKernelGGL((ems_kernel<T, 2, 1>), g, dim3(64), 0, s, a);
+  else if (J <= 256) hipLaunchKernelGGL((ems_kernel<T, 4, 1>), g, dim3(64), 0, s, a);
+  else if (J <= 512) hipLaunchKernelGGL((ems_kernel<T, 8, 1>), g, dim3(64), 0, s, a);
+  else if (J <= 1024) hipLaunchKernelGGL((ems_kernel<T, 16, 1>), g, dim3(64), 0, s, a);
+  else if (J <= 2048) hipLaunchKernelGGL((ems_kernel<T, 16, 2>), g, dim3(128), 0, s, a);
+  else if (J <= 3072) hipLaunchKernelGGL((ems_kernel<T, 16, 3>), g, dim3(192), 0, s, a);
+  else if (J <= 4096) hipLaunchKernelGGL((ems_kernel<T, 16, 4>), g, dim3(256), 0, s, a);
+  else return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
@@ -541,8 +550,8 @@ enufft_status ems_launch(enufft_plan_t p, const void *f, const enufft_ems_params
   a.alpha_min = prm->alpha_min; a.alpha_max = prm->alpha_max; a.delta = prm->delta;
   a.w1 = prm->w1; a.w2 = prm->w2;
   const int blocks = (int)cell_count;
-  hipError_t e = p->prec == ENUFFT_F64 ? launch_ems_t<double>(a, ut->Jpad, blocks, p->stream)
-                                       : launch_ems_t<float>(a, ut->Jpad, blocks, p->stream);
+  hipError_t e = p->prec == ENUFFT_F64 ? launch_ems_t<double>(a, ut->J, blocks, p->stream)
+                                       : launch_ems_t<float>(a, ut->J, blocks, p->stream);
   if (e != hipSuccess) {
     p->last_error = std::string("EMS launch: ") + hipGetErrorString(e);
     p->faulted = true;

@@ -85,7 +85,7 @@ struct enufft_plan_s {
   void *big_xs = nullptr, *big_ys = nullptr, *big_hs = nullptr, *big_ws = nullptr;
   double *big_grid = nullptr;                // n2 x n1 FP64 spreading grid
   void *big_cb = nullptr, *big_cby = nullptr;   // column buffers [K1 + 1][n2] complex
-  void *big_gu = nullptr, *big_gx = nullptr, *big_gy = nullptr;   // adjoint grids
+  void *big_gu = nullptr;                    // adjoint grids: n2 x n1 cells of (u, du/dx, du/dy, 0)
   int *big_work = nullptr;                   // persistent-loop counters
   double *big_sort = nullptr;                // EMS sort buffer, partials, cut record, tie flags
   int64_t big_sort_jpad = 0, big_ems_parts = 0;

@@ -158,6 +158,33 @@ def test_big_retained_power_pipeline_fp32():
     assert max(errs) <= TOL["f32"]
 
 
+def test_big_forward_graph_replays_match_eager():
+    """The captured type-1 + EMS graph of a large-cell plan (sort, spreading, FFT
+    passes, device-sort EMS; every buffer cleared by kernels, not memsets) replayed
+    several times, with eager work between replays, matches the eager launches."""
+    b = synth.uniform_box(counts=[40000, 0, 25000], n_modes=(128, 128), precision="f32", window_radius=3.0)
+    gb = gpu_batch(b)
+    plan = make_plan(gb)
+    f0 = plan.type1(gb.x, gb.y, gb.h, gb.w)
+    k0, ks0, st0 = plan.ems(f0)
+    torch.cuda.synchronize()
+    f0, k0, ks0 = f0.cpu().numpy(), k0.cpu().numpy(), ks0.cpu().numpy()
+    out = (plan.empty_modes(), torch.empty(f0.shape, dtype=torch.uint8, device="cuda:0"),
+           torch.empty(b.n_cells, dtype=torch.int32, device="cuda:0"),
+           torch.empty((b.n_cells, 8), dtype=torch.float64, device="cuda:0"))
+    for rep in range(4):
+        plan.forward_graph(gb.x, gb.y, gb.h, gb.w, out=out)
+        torch.cuda.synchronize()
+        f, keep, ks, st = [t.cpu().numpy() for t in out]
+        assert rel_l2(f, f0) < 1e-6, rep
+        assert np.array_equal(ks, ks0) and np.array_equal(keep, k0), rep
+        g = plan.type1(gb.x, gb.y, gb.h, gb.w)
+        plan.ems(g)
+        torch.cuda.synchronize()
+    ref = oracle_f(b.to(dtype=torch.float32))
+    assert per_cell_rel_l2(f, ref).max() <= TOL["f32"]
+
+
 # ----------------------------------------------------------- the full high-resolution cell
 
 def _sample_modes(N1, N2, n_rand, seed):
