@@ -72,7 +72,7 @@ typedef struct { double cx, cy, radius; } enufft_window;
  *             whose fine grid is at most 128 per axis keep the whole grid in one
  *             workgroup's LDS; larger ones take the large-cell path (grid in HBM,
  *             points sorted by 32 x 32 grid tiles, each axis widened to >= 64).
- *             A fine grid above 4096 per axis or above 2^23 cells in total is
+ *             A fine grid above 4096 per axis or above 2^22 cells in total is
  *             ENUFFT_EUNSUPPORTED.
  *   sigma     oversampling factor (>= 1.25); the fine grid per axis is the
  *             smallest power of two >= max(16, sigma * N) (Section 2.1.2, Step 1).

@@ -22,6 +22,8 @@ namespace enufft {
 
 struct AdjLayout {
   int rows;       // band rows including halo = band_rows + W
+  int apitch;     // grid row pitch (elements) = n1 + W - 1, rounded up to even: the first W - 1
+                  // columns are repeated after the last, so a footprint's W columns are contiguous
   int cpitch;     // column-workspace pitch (elements) = 2 (K1 + 1) + 2
   size_t g_off, gx_off, gy_off, db0_off, db1_off, ws_off;   // element offsets
   size_t total;   // elements
@@ -30,8 +32,9 @@ struct AdjLayout {
 __host__ __device__ inline AdjLayout adj_layout(const Geom &g, int W, int band_rows) {
   AdjLayout L;
   L.rows = band_rows + W;   // R + W - 1 rows are used; one more keeps the uy rows paired
+  L.apitch = (g.n1 + W - 1 + 1) & ~1;
   L.cpitch = 2 * (g.K1 + 1) + 2;
-  const size_t gsz = (size_t)L.rows * g.pitch;
+  const size_t gsz = (size_t)L.rows * L.apitch;
   L.g_off = 0;
   L.gx_off = gsz;
   L.gy_off = 2 * gsz;
@@ -102,40 +105,95 @@ __device__ void extract_band(const Geom &g, const T *ws, int cpitch, T *db, int 
   __syncthreads();
 }
 
+// The three grids' rows from the transform's output order into natural column
+// order (1,024 elements of each grid per round: read, barrier, write), then
+// columns 0 .. W - 2 repeated at n1 .. n1 + W - 2.
+template <typename T, int W, int NT>
+__device__ void rows_to_natural(T *Gu, T *Gx, T *Gy, int rows, int n1, int apitch) {
+  constexpr int PER = 3 * 1024 / NT;
+  const int ln1 = 31 - __builtin_clz(n1);
+  const int rb = 1024 >> ln1;   // rows per round
+  for (int r0 = 0; r0 < rows; r0 += rb) {
+    T v[PER];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int e = threadIdx.x + q * NT;
+      const int gi = e >> 10, w = e & 1023;
+      const int r = r0 + (w >> ln1), c = w & (n1 - 1);
+      const T *G = gi == 0 ? Gu : gi == 1 ? Gx : Gy;
+      v[q] = r < rows ? G[r * apitch + fft_pos(c, n1)] : T(0);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int e = threadIdx.x + q * NT;
+      const int gi = e >> 10, w = e & 1023;
+      const int r = r0 + (w >> ln1), c = w & (n1 - 1);
+      T *G = gi == 0 ? Gu : gi == 1 ? Gx : Gy;
+      if (r < rows) G[r * apitch + c] = v[q];
+    }
+    __syncthreads();
+  }
+  for (int e = threadIdx.x; e < 3 * rows * (W - 1); e += NT) {
+    const int gi = e / (rows * (W - 1)), rem = e - gi * rows * (W - 1);
+    const int r = rem / (W - 1), c = rem - r * (W - 1);
+    T *G = gi == 0 ? Gu : gi == 1 ? Gx : Gy;
+    G[r * apitch + n1 + c] = G[r * apitch + c];
+  }
+  __syncthreads();
+}
+
 // Gradients at one point from the band's three grids (W x W taps each), if the
 // point's footprint starts in this band; the chain rule through the strength
 // c_j = w_j W(x_j) h_j turns the interpolated u, du/dx, du/dy into dL/dh,
 // dL/dx, dL/dy.
-template <typename T, int W>
-__device__ __forceinline__ void gather_point(const AdjArgs<T> &a, const T *Gu, const T *Gx, const T *Gy, int band_lo,
-                                             int64_t j, T xj, T yj, T hj, T wj, T cx, T cy, T R, T pr) {
+template <typename T, int W, bool POLY>
+__device__ __forceinline__ void gather_point(const AdjArgs<T> &a, const T *Gu, const T *Gx, const T *Gy, int apitch,
+                                             int band_lo, int64_t j, T xj, T yj, T hj, T wj, T cx, T cy, T R,
+                                             T pr) {
   const Geom &g = a.g;
   const T halfw = T(W) / T(2);
   const FineCoord<T> fy = fine_coord<T>(yj, a.s2_hi, a.s2_lo, halfw);
   const int r0 = (fy.i0 & (g.n2 - 1)) - band_lo;    // first footprint row, band-local
   if (r0 < 0 || r0 >= a.band_rows) return;
   const FineCoord<T> fx = fine_coord<T>(xj, a.s1_hi, a.s1_lo, halfw);
-  const int n1 = g.n1, pitch = g.pitch;
-  T kx[W], ky[W];
-  int cp[W];
-  es_taps<T, W>(fx, a.beta, a.es, kx);
-  es_taps<T, W>(fy, a.beta, a.es, ky);
-#pragma unroll
-  for (int d = 0; d < W; ++d) cp[d] = fft_pos((fx.i0 + d) & (n1 - 1), n1);
+  T kx[W];
   T u = 0, ux = 0, uy = 0;
-#pragma unroll
-  for (int dy = 0; dy < W; ++dy) {
-    const int rb = (r0 + dy) * pitch;
+  // rows in natural column order with the wrap-around columns repeated: the
+  // W taps of a row are W consecutive elements from one base address
+  const T *pu = Gu + r0 * apitch + (fx.i0 & (g.n1 - 1));
+  const T *px = Gx + (pu - Gu), *py = Gy + (pu - Gu);
+  auto row = [&](T kyv) {
     T su = 0, sx = 0, sy = 0;
 #pragma unroll
     for (int dx = 0; dx < W; ++dx) {
-      su += kx[dx] * Gu[rb + cp[dx]];
-      sx += kx[dx] * Gx[rb + cp[dx]];
-      sy += kx[dx] * Gy[rb + cp[dx]];
+      su += kx[dx] * pu[dx];
+      sx += kx[dx] * px[dx];
+      sy += kx[dx] * py[dx];
     }
-    u += ky[dy] * su;
-    ux += ky[dy] * sx;
-    uy += ky[dy] * sy;
+    u += kyv * su;
+    ux += kyv * sx;
+    uy += kyv * sy;
+    pu += apitch;
+    px += apitch;
+    py += apitch;
+  };
+  // kernel values: the plan's per-tap polynomials (FP32, W <= ES_MAXW) or psi
+  // itself, chosen at compile time (a run-time choice makes the compiler keep
+  // the taps in scratch); the exact kernel goes one row at a time, so the
+  // loads of all W rows are not hoisted into registers together
+  if constexpr (POLY) {
+    T ky[W];
+    es_taps_poly<W>(fx, float(W) * 0.5f, a.es, kx);
+    es_taps_poly<W>(fy, float(W) * 0.5f, a.es, ky);
+#pragma unroll
+    for (int dy = 0; dy < W; ++dy) row(ky[dy]);
+  } else {
+    const T zsc = T(2) / T(W);
+#pragma unroll
+    for (int d = 0; d < W; ++d) kx[d] = es_eval(fx.offset(d) * zsc, a.beta);
+#pragma unroll 1
+    for (int dy = 0; dy < W; ++dy) row(es_eval(fy.offset(dy) * zsc, a.beta));
   }
   T dWx, dWy;
   const T Wv = hann_wg(a.window_kind, xj, yj, cx, cy, R, pr, dWx, dWy);
@@ -152,9 +210,9 @@ __device__ __forceinline__ void gather_point(const AdjArgs<T> &a, const T *Gu, c
 // contiguous (1 KiB per array) and the loads run two blocks ahead in three
 // register buffers, so the gather is not serialised behind point loads.
 // Every point of the item is read (its band decides whether it is served).
-template <typename T, int W, int NT>
-__device__ __forceinline__ void gather_item(const AdjArgs<T> &a, const T *Gu, const T *Gx, const T *Gy, int band_lo,
-                                            int64_t begin, int64_t end, T cx, T cy, T R) {
+template <typename T, int W, int NT, bool POLY>
+__device__ __forceinline__ void gather_item(const AdjArgs<T> &a, const T *Gu, const T *Gx, const T *Gy, int apitch,
+                                            int band_lo, int64_t begin, int64_t end, T cx, T cy, T R) {
   const T pr = R > T(0) ? T(M_PI) / R : T(0);
   int64_t body0 = end, body1 = end;
   // runs of 4 points for FP32 and the narrow kernels (register budget)
@@ -176,10 +234,10 @@ __device__ __forceinline__ void gather_item(const AdjArgs<T> &a, const T *Gu, co
     };
     auto step = [&](const V &xv, const V &yv, const V &hv, const V &wv, int64_t qq) {
       if (qq >= q1) return;
-      gather_point<T, W>(a, Gu, Gx, Gy, band_lo, qq * 4 + 0, xv.x, yv.x, hv.x, wv.x, cx, cy, R, pr);
-      gather_point<T, W>(a, Gu, Gx, Gy, band_lo, qq * 4 + 1, xv.y, yv.y, hv.y, wv.y, cx, cy, R, pr);
-      gather_point<T, W>(a, Gu, Gx, Gy, band_lo, qq * 4 + 2, xv.z, yv.z, hv.z, wv.z, cx, cy, R, pr);
-      gather_point<T, W>(a, Gu, Gx, Gy, band_lo, qq * 4 + 3, xv.w, yv.w, hv.w, wv.w, cx, cy, R, pr);
+      gather_point<T, W, POLY>(a, Gu, Gx, Gy, apitch, band_lo, qq * 4 + 0, xv.x, yv.x, hv.x, wv.x, cx, cy, R, pr);
+      gather_point<T, W, POLY>(a, Gu, Gx, Gy, apitch, band_lo, qq * 4 + 1, xv.y, yv.y, hv.y, wv.y, cx, cy, R, pr);
+      gather_point<T, W, POLY>(a, Gu, Gx, Gy, apitch, band_lo, qq * 4 + 2, xv.z, yv.z, hv.z, wv.z, cx, cy, R, pr);
+      gather_point<T, W, POLY>(a, Gu, Gx, Gy, apitch, band_lo, qq * 4 + 3, xv.w, yv.w, hv.w, wv.w, cx, cy, R, pr);
     };
     V x0{}, y0{}, h0{}, w0{}, x1{}, y1{}, h1{}, w1{}, x2{}, y2{}, h2{}, w2{};
     load(x0, y0, h0, w0, q);
@@ -197,18 +255,18 @@ __device__ __forceinline__ void gather_item(const AdjArgs<T> &a, const T *Gu, co
   const int64_t nhead = body0 - begin, ntail = end - body1;
   for (int64_t i = threadIdx.x; i < nhead + ntail; i += NT) {
     const int64_t j = i < nhead ? begin + i : body1 + (i - nhead);
-    gather_point<T, W>(a, Gu, Gx, Gy, band_lo, j, a.x[j], a.y[j], a.h[j], a.w[j], cx, cy, R, pr);
+    gather_point<T, W, POLY>(a, Gu, Gx, Gy, apitch, band_lo, j, a.x[j], a.y[j], a.h[j], a.w[j], cx, cy, R, pr);
   }
 }
 
-template <typename T, int W, int NT>
+template <typename T, int W, int NT, bool POLY>
 __global__ __launch_bounds__(NT) void adj_kernel(AdjArgs<T> a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T *sm = reinterpret_cast<T *>(smem_raw);
   __shared__ int s_item;
   const Geom &g = a.g;
-  const int pitch = g.pitch;
   const AdjLayout L = adj_layout(g, W, a.band_rows);
+  const int pitch = L.apitch;
   T *Gu = sm + L.g_off, *Gx = sm + L.gx_off, *Gy = sm + L.gy_off;
   T *db0 = sm + L.db0_off, *db1 = sm + L.db1_off, *ws = sm + L.ws_off;
   const int per = g.K1 + 1;
@@ -292,10 +350,12 @@ __global__ __launch_bounds__(NT) void adj_kernel(AdjArgs<T> a) {
       acc.r1 = acc.r0 + pitch;
       return acc;
     });
+    rows_to_natural<T, W, NT>(Gu, Gx, Gy, L.rows, n1, pitch);
 
     // Gather at the points of this band.
     const double *wn = a.windows + 3 * (int64_t)it.cell;
-    gather_item<T, W, NT>(a, Gu, Gx, Gy, it.band * a.band_rows, it.begin, it.end, T(wn[0]), T(wn[1]), T(wn[2]));
+    gather_item<T, W, NT, POLY>(a, Gu, Gx, Gy, L.apitch, it.band * a.band_rows, it.begin, it.end, T(wn[0]), T(wn[1]),
+                          T(wn[2]));
     __syncthreads();
     if (!persistent) break;
   }
@@ -309,10 +369,30 @@ __global__ __launch_bounds__(NT) void adj_kernel(AdjArgs<T> a) {
   }
 }
 
+// Compiled with the polynomial taps for FP32 plans that carry them (W <= ES_MAXW).
+template <typename T, int W>
+constexpr bool adj_has_poly() { return sizeof(T) == 4 && W <= ES_MAXW; }
+
+template <typename T, int W>
+static const void *adj_fn(int threads, bool poly) {
+  if constexpr (adj_has_poly<T, W>()) {
+    if (poly)
+      return threads == 256 ? (const void *)&adj_kernel<T, W, 256, true> : (const void *)&adj_kernel<T, W, 512, true>;
+  }
+  return threads == 256 ? (const void *)&adj_kernel<T, W, 256, false> : (const void *)&adj_kernel<T, W, 512, false>;
+}
+
 template <typename T, int W>
 static hipError_t launch_adj_w(const AdjArgs<T> &a, int blocks, int threads, size_t lds, hipStream_t s) {
-  if (threads == 256) hipLaunchKernelGGL((adj_kernel<T, W, 256>), dim3(blocks), dim3(256), lds, s, a);
-  else hipLaunchKernelGGL((adj_kernel<T, W, 512>), dim3(blocks), dim3(512), lds, s, a);
+  if constexpr (adj_has_poly<T, W>()) {
+    if (a.es.on) {
+      if (threads == 256) hipLaunchKernelGGL((adj_kernel<T, W, 256, true>), dim3(blocks), dim3(256), lds, s, a);
+      else hipLaunchKernelGGL((adj_kernel<T, W, 512, true>), dim3(blocks), dim3(512), lds, s, a);
+      return hipGetLastError();
+    }
+  }
+  if (threads == 256) hipLaunchKernelGGL((adj_kernel<T, W, 256, false>), dim3(blocks), dim3(256), lds, s, a);
+  else hipLaunchKernelGGL((adj_kernel<T, W, 512, false>), dim3(blocks), dim3(512), lds, s, a);
   return hipGetLastError();
 }
 
@@ -381,10 +461,10 @@ void build_adj_schedule(enufft_plan_t p, int slots) {
 }
 
 template <typename T>
-hipError_t adj_occ(int W, int threads, size_t lds, int *per_cu) {
+hipError_t adj_occ(int W, int threads, bool poly, size_t lds, int *per_cu) {
   const void *fn = nullptr;
 #define ENUFFT_PICK(WW) \
-  case WW: fn = threads == 256 ? (const void *)&adj_kernel<T, WW, 256> : (const void *)&adj_kernel<T, WW, 512>; break;
+  case WW: fn = adj_fn<T, WW>(threads, poly); break;
   switch (W) {
     ENUFFT_PICK(4) ENUFFT_PICK(6) ENUFFT_PICK(8) ENUFFT_PICK(10) ENUFFT_PICK(12) ENUFFT_PICK(14) ENUFFT_PICK(16)
     default: return hipErrorInvalidValue;
@@ -425,8 +505,8 @@ enufft_status adj_prepare(enufft_plan_t p) {
   }
   p->adj_bands = B;
   int per_cu = 0;
-  e = p->prec == ENUFFT_F64 ? adj_occ<double>(p->W, p->adj_threads, p->adj_lds, &per_cu)
-                            : adj_occ<float>(p->W, p->adj_threads, p->adj_lds, &per_cu);
+  e = p->prec == ENUFFT_F64 ? adj_occ<double>(p->W, p->adj_threads, p->es.on != 0, p->adj_lds, &per_cu)
+                            : adj_occ<float>(p->W, p->adj_threads, p->es.on != 0, p->adj_lds, &per_cu);
   if (e != hipSuccess || per_cu < 1) {
     p->last_error = "adjoint kernel cannot be resident";
     return ENUFFT_EDEVICE;

@@ -39,9 +39,7 @@
 namespace enufft {
 
 constexpr int BIG_TS = 32;            // tile side in fine-grid cells
-constexpr int BIG_CHUNK = 16384;      // sorted points per spreading / gather work unit
-constexpr int BIG_BIN_CHUNK = 65536;  // points per workgroup in the sort passes
-constexpr int BIG_SORT_BLOCK = 4096;  // elements of one LDS-resident sort block
+constexpr int BIG_SORT_BLOCK = 4096;  // elements of one LDS-resident EMS sort block
 constexpr int BIG_SPREAD_THREADS = 256;
 
 template <typename T>
@@ -123,15 +121,29 @@ __device__ T *stockham(T *a, T *b, int n, const T *tw) {
 
 // ------------------------------------------------------------------ device sort by tile
 
+// The cell's input points are taken in chunks of BIG_SORT_CHUNK.  Each chunk's
+// tile histogram goes to memory; scans over chunks and tiles give every chunk
+// its start in every tile's range, so no pass uses atomics in global memory.
+// (Device-scope atomics that many workgroups aim at the same few addresses
+// serialise far from the CUs; a thousand tile cursors hit by every chunk cost
+// milliseconds.)
+constexpr int BIG_SORT_CHUNK = 16384;
+constexpr int BIG_SORT_THREADS = 512;
+constexpr int BIG_SCAN_GROUP = 64;     // chunks per group in the chunk scans
+constexpr int BIG_UNIT_CHUNK = 16384;  // sorted points per spreading / gather work unit
+
 template <typename T>
 struct BigSortArgs {
   const T *x, *y, *h, *w;   // the cell's points (h may be NULL: copied as 0)
   int64_t n;
   T s1h, s1l, s2h, s2l;
   int W, n1, n2, ntx, ntiles;
-  int *counts;              // [ntiles]
-  int64_t *cursor;          // [ntiles]
-  int *perm;                // [n] original index of each sorted position
+  int nchunks, ngroups;
+  int *chunk_hist;          // [nchunks][ntiles]: counts, then each chunk's start in each tile
+  int *group_sum;           // [ngroups][ntiles]
+  int64_t *offsets;         // [ntiles + 1] tile ranges of the sorted order
+  int *unit_base;           // [ntiles + 1] first work unit of each tile; [ntiles] = units in all
+  int *inv;                 // [n] sorted position of each input point
   T *xs, *ys, *hs, *ws;     // [n] points in tile order
 };
 
@@ -141,59 +153,6 @@ __device__ __forceinline__ int big_tile(const BigSortArgs<T> &a, T x, T y) {
   const int iy = big_origin<T>(y, a.s2h, a.s2l, a.W, a.n2);
   return (iy / BIG_TS) * a.ntx + ix / BIG_TS;
 }
-
-// Per-chunk tile histograms, added to the global counts.
-template <typename T>
-__global__ __launch_bounds__(512) void big_count_kernel(BigSortArgs<T> a) {
-  extern __shared__ int hist[];
-  for (int i = threadIdx.x; i < a.ntiles; i += blockDim.x) hist[i] = 0;
-  __syncthreads();
-  const int64_t s = (int64_t)blockIdx.x * BIG_BIN_CHUNK, e = min(a.n, s + BIG_BIN_CHUNK);
-  for (int64_t j = s + threadIdx.x; j < e; j += blockDim.x) atomicAdd(&hist[big_tile<T>(a, a.x[j], a.y[j])], 1);
-  __syncthreads();
-  for (int i = threadIdx.x; i < a.ntiles; i += blockDim.x)
-    if (hist[i]) atomicAdd(&a.counts[i], hist[i]);
-}
-
-// Exclusive scan of the tile counts in one workgroup: offsets[0..ntiles] and
-// the scatter cursors.
-__global__ __launch_bounds__(1024) void big_scan_kernel(const int *counts, int ntiles, int64_t *offsets,
-                                                        int64_t *cursor) {
-  __shared__ int64_t part[1024];
-  const int per = (ntiles + 1023) / 1024;
-  const int t0 = min(ntiles, (int)threadIdx.x * per), t1 = min(ntiles, t0 + per);
-  int64_t s = 0;
-  for (int t = t0; t < t1; ++t) s += counts[t];
-  part[threadIdx.x] = s;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    int64_t run = 0;
-    for (int i = 0; i < 1024; ++i) {
-      const int64_t v = part[i];
-      part[i] = run;
-      run += v;
-    }
-    offsets[ntiles] = run;
-  }
-  __syncthreads();
-  int64_t run = part[threadIdx.x];
-  for (int t = t0; t < t1; ++t) {
-    offsets[t] = run;
-    cursor[t] = run;
-    run += counts[t];
-  }
-}
-
-// Scatter, one chunk of BIG_SCATTER_CHUNK points per workgroup, as a local
-// counting sort: the chunk's tile histogram in LDS, its exclusive scan, one
-// global atomic per non-empty tile to reserve the chunk's range in that tile,
-// then the chunk's points ranked into tile order in LDS (a 16-bit index per
-// point) and copied out with consecutive threads writing consecutive positions
-// of each tile's range, so the stores of a tile's segment coalesce.  (Ranks
-// straight from the atomics would send the 64 lanes of a store to 64 different
-// tiles' ranges: one partial cache line per 4-byte store.)
-constexpr int BIG_SCATTER_CHUNK = 16384;
-constexpr int BIG_SCATTER_THREADS = 512;
 
 __device__ __forceinline__ int big_wave_incl_scan(int v) {
   const int lane = threadIdx.x & 63;
@@ -205,117 +164,219 @@ __device__ __forceinline__ int big_wave_incl_scan(int v) {
   return v;
 }
 
-// Exclusive scan of cnt[0 .. n) into out[0 .. n) by the whole workgroup
-// (BIG_SCATTER_THREADS threads, each owning a contiguous run of entries).
-__device__ void big_block_scan(const int *cnt, int *out, int n, int *wsum) {
-  constexpr int NW = BIG_SCATTER_THREADS / 64;
-  const int per = (n + BIG_SCATTER_THREADS - 1) / BIG_SCATTER_THREADS;
+// Exclusive scan of cnt[0 .. n) into out[0 .. n) by a workgroup of NT threads,
+// each owning a contiguous run of entries; returns the total.  cnt and out may
+// be the same array.
+template <int NT, typename O>
+__device__ int big_block_scan(const int *cnt, O *out, int n, int *wsum) {
+  constexpr int NW = NT / 64;
+  const int per = (n + NT - 1) / NT;
   const int t0 = min(n, (int)threadIdx.x * per), t1 = min(n, t0 + per);
   int v = 0;
   for (int t = t0; t < t1; ++t) v += cnt[t];
   const int inc = big_wave_incl_scan(v);
   const int wave = threadIdx.x >> 6;
+  __syncthreads();
   if ((threadIdx.x & 63) == 63) wsum[wave] = inc;
   __syncthreads();
-  int run = inc - v;
-  for (int w = 0; w < NW; ++w)
+  int run = inc - v, total = 0;
+  for (int w = 0; w < NW; ++w) {
     if (w < wave) run += wsum[w];
+    total += wsum[w];
+  }
   for (int t = t0; t < t1; ++t) {
-    out[t] = run;
-    run += cnt[t];
+    const int c = cnt[t];
+    out[t] = (O)run;
+    run += c;
   }
   __syncthreads();
+  return total;
 }
 
+// Tile histogram of each chunk, written in full.
 template <typename T>
-__global__ __launch_bounds__(BIG_SCATTER_THREADS) void big_scatter_kernel(BigSortArgs<T> a) {
-  extern __shared__ int smem[];
-  int *hist = smem;                    // [ntiles] counts, then the fill cursors
-  int *lstart = hist + a.ntiles;       // [ntiles] chunk-local start of each tile
-  int *gbase = lstart + a.ntiles;      // [ntiles] global start of the chunk's range in each tile
-  uint16_t *stage = reinterpret_cast<uint16_t *>(gbase + a.ntiles);   // [chunk] point index by slot
-  __shared__ int wsum[BIG_SCATTER_THREADS / 64];
-  const int64_t s = (int64_t)blockIdx.x * BIG_SCATTER_CHUNK;
-  const int cnt = (int)(min(a.n, s + BIG_SCATTER_CHUNK) - s);
+__global__ __launch_bounds__(BIG_SORT_THREADS) void big_count_kernel(BigSortArgs<T> a) {
+  extern __shared__ int hist[];
   for (int i = threadIdx.x; i < a.ntiles; i += blockDim.x) hist[i] = 0;
   __syncthreads();
-  for (int li = threadIdx.x; li < cnt; li += blockDim.x) atomicAdd(&hist[big_tile<T>(a, a.x[s + li], a.y[s + li])], 1);
+  const int64_t s = (int64_t)blockIdx.x * BIG_SORT_CHUNK, e = min(a.n, s + BIG_SORT_CHUNK);
+  for (int64_t j = s + threadIdx.x; j < e; j += blockDim.x) atomicAdd(&hist[big_tile<T>(a, a.x[j], a.y[j])], 1);
   __syncthreads();
-  big_block_scan(hist, lstart, a.ntiles, wsum);
-  for (int i = threadIdx.x; i < a.ntiles; i += blockDim.x) {
-    const int c = hist[i];
-    gbase[i] = c ? (int)atomicAdd((unsigned long long *)&a.cursor[i], (unsigned long long)c) : 0;
-    hist[i] = 0;
+  int *row = a.chunk_hist + (int64_t)blockIdx.x * a.ntiles;
+  for (int i = threadIdx.x; i < a.ntiles; i += blockDim.x) row[i] = hist[i];
+}
+
+// Per tile, the sum over each group of BIG_SCAN_GROUP chunks.
+__global__ __launch_bounds__(256) void big_group_sum_kernel(const int *chunk_hist, int nchunks, int ntiles,
+                                                            int *group_sum) {
+  const int t = blockIdx.x * 256 + threadIdx.x, g = blockIdx.y;
+  if (t >= ntiles) return;
+  const int b0 = g * BIG_SCAN_GROUP, b1 = min(nchunks, b0 + BIG_SCAN_GROUP);
+  int s = 0;
+  for (int b = b0; b < b1; ++b) s += chunk_hist[(int64_t)b * ntiles + t];
+  group_sum[(int64_t)g * ntiles + t] = s;
+}
+
+// One workgroup: per tile, the exclusive scan of its group sums (in place) and
+// its total; the tile offsets (exclusive scan of the totals); the number of
+// work units of each tile (the unit chunks its range touches) and their scan.
+__global__ __launch_bounds__(1024) void big_tile_scan_kernel(int *group_sum, int ngroups, int ntiles,
+                                                             int64_t *offsets, int *unit_base) {
+  extern __shared__ int tot[];   // [ntiles]
+  __shared__ int wsum[16];
+  for (int t = threadIdx.x; t < ntiles; t += blockDim.x) {
+    int run = 0;
+    for (int g = 0; g < ngroups; ++g) {
+      int *p = group_sum + (int64_t)g * ntiles + t;
+      const int v = *p;
+      *p = run;
+      run += v;
+    }
+    tot[t] = run;
   }
   __syncthreads();
-  for (int li = threadIdx.x; li < cnt; li += blockDim.x) {
-    const int t = big_tile<T>(a, a.x[s + li], a.y[s + li]);
-    const int slot = lstart[t] + atomicAdd(&hist[t], 1);
-    if (slot < cnt) stage[slot] = (uint16_t)li;   // always true when both passes agree on the tile
+  const int n = big_block_scan<1024, int64_t>(tot, offsets, ntiles, wsum);
+  if (threadIdx.x == 0) offsets[ntiles] = n;
+  __syncthreads();
+  for (int t = threadIdx.x; t < ntiles; t += blockDim.x) {
+    const int64_t t0 = offsets[t], t1 = t0 + tot[t];
+    tot[t] = t1 > t0 ? (int)((t1 - 1) / BIG_UNIT_CHUNK - t0 / BIG_UNIT_CHUNK + 1) : 0;
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < cnt; i += blockDim.x) {
-    const int64_t j = s + min((int)stage[i], cnt - 1);   // clamp: stays inside the chunk whatever LDS held
-    const T xj = a.x[j], yj = a.y[j];
-    const int t = big_tile<T>(a, xj, yj);
-    const int64_t pos = (int64_t)gbase[t] + (i - lstart[t]);
-    if (pos < 0 || pos >= a.n) continue;   // only if the passes disagreed on a tile; never out of bounds
-    a.perm[pos] = (int)j;
-    a.xs[pos] = xj;
-    a.ys[pos] = yj;
-    a.hs[pos] = a.h ? a.h[j] : T(0);
-    a.ws[pos] = a.w[j];
+  const int units = big_block_scan<1024, int>(tot, unit_base, ntiles, wsum);
+  if (threadIdx.x == 0) unit_base[ntiles] = units;
+}
+
+// Each chunk's start in each tile: the tile offset, the chunk group's prefix
+// and the counts of the earlier chunks of the group.
+__global__ __launch_bounds__(256) void big_chunk_base_kernel(int *chunk_hist, const int *group_sum,
+                                                             const int64_t *offsets, int nchunks, int ntiles) {
+  const int t = blockIdx.x * 256 + threadIdx.x, g = blockIdx.y;
+  if (t >= ntiles) return;
+  const int b0 = g * BIG_SCAN_GROUP, b1 = min(nchunks, b0 + BIG_SCAN_GROUP);
+  int run = (int)offsets[t] + group_sum[(int64_t)g * ntiles + t];
+  for (int b = b0; b < b1; ++b) {
+    int *p = chunk_hist + (int64_t)b * ntiles + t;
+    const int v = *p;
+    *p = run;
+    run += v;
   }
 }
 
-// Tile holding sorted position k: the largest t with offsets[t] <= k.
-__device__ __forceinline__ int big_tile_of(const int64_t *offsets, int ntiles, int64_t k) {
-  int lo = 0, hi = ntiles - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (offsets[mid] <= k) lo = mid;
-    else hi = mid - 1;
+// Scatter, one chunk per workgroup, in sub-chunks that fit LDS: each
+// sub-chunk's tile histogram and its scan, then its points loaded once
+// (coalesced) and staged in LDS in tile order, then copied out with
+// consecutive threads on consecutive positions of each tile's segment, so the
+// stores coalesce.  The chunk's start in every tile advances by each
+// sub-chunk's count.  The inverse permutation is written in input order.
+// (Ranking in LDS but reading the points back from memory in tile order would
+// fetch a whole cache line for every 4-byte value.)
+template <typename T>
+constexpr int big_scatter_sub() { return sizeof(T) == 4 ? 4096 : 2048; }
+
+template <typename T>
+__global__ __launch_bounds__(BIG_SORT_THREADS) void big_scatter_kernel(BigSortArgs<T> a) {
+  using V4 = typename vec4<T>::type;
+  constexpr int SUB = big_scatter_sub<T>();
+  extern __shared__ __align__(32) unsigned char sm_raw[];
+  V4 *staged = reinterpret_cast<V4 *>(sm_raw);              // [SUB] (x, y, h, w) in tile order
+  int *hist = reinterpret_cast<int *>(staged + SUB);        // [ntiles] counts, then the fill cursors
+  int *lstart = hist + a.ntiles;                            // [ntiles] sub-chunk start of each tile
+  int *gbase = lstart + a.ntiles;                           // [ntiles] global start of the next points of each tile
+  __shared__ int wsum[BIG_SORT_THREADS / 64];
+  const int64_t s0 = (int64_t)blockIdx.x * BIG_SORT_CHUNK;
+  const int64_t e0 = min(a.n, s0 + BIG_SORT_CHUNK);
+  const int *base_row = a.chunk_hist + (int64_t)blockIdx.x * a.ntiles;
+  for (int i = threadIdx.x; i < a.ntiles; i += blockDim.x) gbase[i] = base_row[i];
+  for (int64_t s = s0; s < e0; s += SUB) {
+    const int cnt = (int)(min(e0, s + SUB) - s);
+    for (int i = threadIdx.x; i < a.ntiles; i += blockDim.x) hist[i] = 0;
+    __syncthreads();
+    for (int li = threadIdx.x; li < cnt; li += blockDim.x)
+      atomicAdd(&hist[big_tile<T>(a, a.x[s + li], a.y[s + li])], 1);
+    __syncthreads();
+    big_block_scan<BIG_SORT_THREADS, int>(hist, lstart, a.ntiles, wsum);
+    for (int li = threadIdx.x; li < cnt; li += blockDim.x) {
+      const int64_t j = s + li;
+      V4 v;
+      v.x = a.x[j];
+      v.y = a.y[j];
+      v.z = a.h ? a.h[j] : T(0);
+      v.w = a.w[j];
+      const int t = big_tile<T>(a, v.x, v.y);
+      // the histogram pass counted this point in tile t: hist[t] - 1 - (rank so far) is free
+      const int slot = lstart[t] + atomicSub(&hist[t], 1) - 1;
+      const int64_t pos = (int64_t)gbase[t] + (slot - lstart[t]);
+      if (slot >= 0 && slot < cnt) staged[slot] = v;   // always true when both passes agree on the tile
+      a.inv[j] = (pos >= 0 && pos < a.n) ? (int)pos : -1;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < cnt; i += blockDim.x) {
+      const V4 v = staged[i];
+      const int t = big_tile<T>(a, v.x, v.y);
+      const int64_t pos = (int64_t)gbase[t] + (i - lstart[t]);
+      if (pos < 0 || pos >= a.n) continue;   // only if the passes disagreed on a tile; never out of bounds
+      a.xs[pos] = v.x;
+      a.ys[pos] = v.y;
+      a.hs[pos] = v.z;
+      a.ws[pos] = v.w;
+    }
+    __syncthreads();
+    // advance each tile's start by this sub-chunk's count (the slots of tile t
+    // are [lstart[t], lstart[t + 1]))
+    for (int i = threadIdx.x; i < a.ntiles; i += blockDim.x) {
+      const int end = i + 1 < a.ntiles ? lstart[i + 1] : cnt;
+      gbase[i] += end - lstart[i];
+    }
+    __syncthreads();
   }
-  return lo;
 }
 
-// Common arguments of the tiled spreading and gather passes.
+// Common arguments of the tiled spreading and gather passes.  Their work units
+// are the pieces of each tile's range that fall in one BIG_UNIT_CHUNK of the
+// sorted order, so no unit holds more than one chunk of points.
 template <typename T>
 struct BigTileArgs {
   const T *xs, *ys, *hs, *ws;
-  const int *perm;
-  const int64_t *offsets;
+  const int64_t *offsets;    // [ntiles + 1]
+  const int *unit_base;      // [ntiles + 1]; [ntiles] = number of units
   int ntiles, ntx;
   int64_t n;
   int *work_counter, *done_counter;
-  const double *windows;    // per cell (cx, cy, R)
+  const double *windows;     // per cell (cx, cy, R)
   int64_t cell;
   int window_kind;
   Geom g;
   T s1h, s1l, s2h, s2l, beta;
   EsPoly es;
-  double *grid;             // spreading: n2 x n1 FP64 accumulator
+  double *partial;           // spreading: [units][S * S] FP64 sub-grids
   const typename vec4<T>::type *G4;   // gather: n2 x n1 cells of (u, du/dx, du/dy, 0)
-  T *grad_h, *grad_x, *grad_y;   // gather: indexed by the cell-local original point index
+  typename vec4<T>::type *gout;       // gather: [n] (dL/dh, dL/dx, dL/dy, 0) in sorted order
 };
 
-// Persistent loop over chunks of the sorted points; body(t, lo, hi) runs every
-// tile run [lo, hi) of tile t inside the chunk.  The last workgroup to finish
-// resets the counters for the next launch.
+// Persistent loop over the work units; body(t, lo, hi, u) runs unit u, the
+// sorted positions [lo, hi) of tile t.  The last workgroup to finish resets the
+// counters for the next launch.
 template <typename T, typename Body>
-__device__ __forceinline__ void big_chunks(const BigTileArgs<T> &a, int *s_chunk, const Body &body) {
-  const int64_t nchunks = (a.n + BIG_CHUNK - 1) / BIG_CHUNK;
+__device__ __forceinline__ void big_units(const BigTileArgs<T> &a, int *s_unit, const Body &body) {
+  const int nunits = a.unit_base[a.ntiles];
   for (;;) {
-    if (threadIdx.x == 0) *s_chunk = atomicAdd(a.work_counter, 1);
+    if (threadIdx.x == 0) *s_unit = atomicAdd(a.work_counter, 1);
     __syncthreads();
-    const int64_t c = *s_chunk;
+    const int u = *s_unit;
     __syncthreads();
-    if (c >= nchunks) break;
-    const int64_t k0 = c * BIG_CHUNK, k1 = min(a.n, k0 + BIG_CHUNK);
-    for (int t = big_tile_of(a.offsets, a.ntiles, k0); t < a.ntiles && a.offsets[t] < k1; ++t) {
-      const int64_t lo = max(k0, a.offsets[t]), hi = min(k1, a.offsets[t + 1]);
-      if (lo < hi) body(t, lo, hi);
+    if (u >= nunits) break;
+    int lo = 0, hi = a.ntiles - 1;   // the tile of unit u: the largest t with unit_base[t] <= u
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (a.unit_base[mid] <= u) lo = mid;
+      else hi = mid - 1;
     }
+    const int t = lo;
+    const int64_t t0 = a.offsets[t], t1 = a.offsets[t + 1];
+    const int64_t c = t0 / BIG_UNIT_CHUNK + (u - a.unit_base[t]);
+    const int64_t k0 = max(t0, c * BIG_UNIT_CHUNK), k1 = min(t1, (c + 1) * BIG_UNIT_CHUNK);
+    if (k0 < k1) body(t, k0, k1, u);
   }
   if (threadIdx.x == 0) {
     __threadfence();
@@ -328,17 +389,19 @@ __device__ __forceinline__ void big_chunks(const BigTileArgs<T> &a, int *s_chunk
 
 // ------------------------------------------------------------------ spreading into the HBM grid
 
+// Each unit accumulates in an FP64 LDS sub-grid and writes it out whole; the
+// assemble pass adds the sub-grids up.
 template <typename T, int W, bool POLY>
 __global__ __launch_bounds__(BIG_SPREAD_THREADS) void big_spread_kernel(BigTileArgs<T> a) {
   constexpr int S = BIG_TS + W + 1;   // margin cell, tile, reach of the last origin
   __shared__ double sub[S * S];
-  __shared__ int s_chunk;
+  __shared__ int s_unit;
   const Geom &g = a.g;
   const T halfw = T(W) / T(2);
   const double *wn = a.windows + 3 * a.cell;
   const T cx = T(wn[0]), cy = T(wn[1]), R = T(wn[2]);
   const T pr = R > T(0) ? T(M_PI) / R : T(0);
-  big_chunks<T>(a, &s_chunk, [&](int t, int64_t lo, int64_t hi) {
+  big_units<T>(a, &s_unit, [&](int t, int64_t lo, int64_t hi, int u) {
     for (int i = threadIdx.x; i < S * S; i += blockDim.x) sub[i] = 0.0;
     __syncthreads();
     const int tx0 = (t % a.ntx) * BIG_TS, ty0 = (t / a.ntx) * BIG_TS;
@@ -362,16 +425,47 @@ __global__ __launch_bounds__(BIG_SPREAD_THREADS) void big_spread_kernel(BigTileA
       }
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < S * S; i += blockDim.x) {
-      const double v = sub[i];
-      if (v != 0.0) {
-        const int r = i / S, q = i - r * S;
-        const int gy = (ty0 - 1 + r) & (g.n2 - 1), gx = (tx0 - 1 + q) & (g.n1 - 1);
-        unsafeAtomicAdd(&a.grid[(int64_t)gy * g.n1 + gx], v);
-      }
-    }
+    double *dst = a.partial + (int64_t)u * (S * S);
+    for (int i = threadIdx.x; i < S * S; i += blockDim.x) dst[i] = sub[i];
     __syncthreads();
   });
+}
+
+// Every fine-grid cell: the sum of the sub-grids that cover it, over all units
+// of its own tile and of the neighbouring tiles whose sub-grids reach it (the
+// tile above / left through their kernel reach, the tile below / right through
+// their margin cell).  Replaces clearing the grid and adding with atomics.
+__global__ __launch_bounds__(256) void big_assemble_kernel(const double *partial, const int *unit_base, Geom g,
+                                                           int ntx, int nty, int S, double *grid) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= (int64_t)g.n1 * g.n2) return;
+  const int gy = (int)(i / g.n1), gx = (int)(i - (int64_t)gy * g.n1);
+  const int tx = gx / BIG_TS, ty = gy / BIG_TS;
+  const int px = gx - tx * BIG_TS, py = gy - ty * BIG_TS;
+  double s = 0.0;
+  for (int dyt = -1; dyt <= 1; ++dyt) {
+    const int ly = py + 1 - dyt * BIG_TS;
+    if (ly < 0 || ly >= S) continue;
+    const int tyy = (ty + dyt + nty) % nty;
+    for (int dxt = -1; dxt <= 1; ++dxt) {
+      const int lx = px + 1 - dxt * BIG_TS;
+      if (lx < 0 || lx >= S) continue;
+      const int t = tyy * ntx + (tx + dxt + ntx) % ntx;
+      const int64_t off = (int64_t)ly * S + lx, stride = (int64_t)S * S;
+      const int u0 = unit_base[t], u1 = unit_base[t + 1];
+      int u = u0;
+      // crowded tiles have hundreds of units: keep eight loads in flight
+      for (; u + 8 <= u1; u += 8) {
+        double v[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) v[q] = partial[(int64_t)(u + q) * stride + off];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) s += v[q];
+      }
+      for (; u < u1; ++u) s += partial[(int64_t)u * stride + off];
+    }
+  }
+  grid[i] = s;
 }
 
 // ------------------------------------------------------------------ FFT passes
@@ -534,30 +628,35 @@ __global__ __launch_bounds__(256) void big_sort_global_kernel(double *S, int64_t
   }
 }
 
-// Workgroup sums in a fixed order (thread 0 adds the per-thread values).
-__device__ double big_block_sum(double v, double *red, double *out) {
+// Workgroup reductions and scans in a fixed order: within each wave by
+// shuffles, then over the waves' totals (wred holds one value per wave).
+template <typename V>
+__device__ V big_block_sum(V v, V *wred) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
   __syncthreads();
-  red[threadIdx.x] = v;
+  if ((threadIdx.x & 63) == 0) wred[threadIdx.x >> 6] = v;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    double s = 0.0;
-    for (int i = 0; i < (int)blockDim.x; ++i) s += red[i];
-    *out = s;
-  }
-  __syncthreads();
-  return *out;
+  V s = V(0);
+  for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += wred[w];
+  return s;
 }
-__device__ int big_block_sum_i(int v, int *red, int *out) {
-  __syncthreads();
-  red[threadIdx.x] = v;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    int s = 0;
-    for (int i = 0; i < (int)blockDim.x; ++i) s += red[i];
-    *out = s;
+
+template <typename V>
+__device__ V big_block_excl_scan(V v, V *wred) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  V inc = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const V t = __shfl_up(inc, o, 64);
+    if (lane >= o) inc += t;
   }
   __syncthreads();
-  return *out;
+  if (lane == 63) wred[wave] = inc;
+  __syncthreads();
+  V base = V(0);
+  for (int w = 0; w < wave; ++w) base += wred[w];
+  return base + inc - v;
 }
 
 // Scores over the sorted energies (one workgroup of 1024 threads, each owning
@@ -565,25 +664,18 @@ __device__ int big_block_sum_i(int v, int *red, int *out) {
 // (alpha_c), (f_cum) and (k_elastic), as in the per-cell kernel.
 __global__ __launch_bounds__(1024) void big_ems_scores_kernel(const double *S, const double *partial, int nparts,
                                                               int J, enufft_ems_params prm, BigCut *cut) {
-  __shared__ double red[1024];
-  __shared__ int redi[1024];
-  __shared__ double s_out;
-  __shared__ int s_outi;
-  __shared__ double sT1, sT2;
+  __shared__ double wred[16];
+  __shared__ int wredi[16];
   __shared__ int s_kc;
   const int t = threadIdx.x;
-  if (t == 0) {
-    double a = 0.0, b = 0.0;
-    for (int i = 0; i < nparts; ++i) {
-      a += partial[2 * i];
-      b += partial[2 * i + 1];
-    }
-    sT1 = a;
-    sT2 = b;
-    s_kc = INT_MAX;
+  if (t == 0) s_kc = INT_MAX;
+  double pa = 0.0, pb = 0.0;
+  for (int i = t; i < nparts; i += blockDim.x) {
+    pa += partial[2 * i];
+    pb += partial[2 * i + 1];
   }
-  __syncthreads();
-  const double T1 = sT1, T2 = sT2;
+  const double T1 = big_block_sum(pa, wred);
+  const double T2 = big_block_sum(pb, wred);
   const int Jmax = J < prm.k_max ? J : prm.k_max;
   const double neff = T2 > 0.0 ? T1 * T1 / T2 : 0.0;
   const double nclip = neff < (double)Jmax ? neff : (double)Jmax;
@@ -598,26 +690,14 @@ __global__ __launch_bounds__(1024) void big_ems_scores_kernel(const double *S, c
     else term = exp(-(ea / eb - 1.0) / prm.delta);
     sd += term;
   }
-  const double sdsum = big_block_sum(sd, red, &s_out);
+  const double sdsum = big_block_sum(sd, wred);
   const double sdel = Jmax < 2 ? 1.0 : sdsum / (double)(Jmax - 1);
   const double Cs = (Jmax > 0 ? prm.w1 * nclip / (double)Jmax : 0.0) + prm.w2 * sdel;
   const double alphaC = prm.alpha_min + (prm.alpha_max - prm.alpha_min) * Cs;
   // running sum: per-thread totals, an exclusive scan in thread order, then the threshold
   double loc = 0.0;
   for (int j = j0; j < j1; ++j) loc += S[j];
-  __syncthreads();
-  red[t] = loc;
-  __syncthreads();
-  if (t == 0) {
-    double run = 0.0;
-    for (int i = 0; i < 1024; ++i) {
-      const double v = red[i];
-      red[i] = run;
-      run += v;
-    }
-  }
-  __syncthreads();
-  double run = red[t];
+  double run = big_block_excl_scan(loc, wred);
   if (T1 > 0.0) {
     for (int j = j0; j < j1; ++j) {
       run += S[j];
@@ -645,9 +725,9 @@ __global__ __launch_bounds__(1024) void big_ems_scores_kernel(const double *S, c
     cgt += v > eth;
     ceq += v == eth;
   }
-  const double th = big_block_sum(part, red, &s_out);
-  const int ngt = big_block_sum_i(cgt, redi, &s_outi);
-  const int neq = big_block_sum_i(ceq, redi, &s_outi);
+  const double th = big_block_sum(part, wred);
+  const int ngt = big_block_sum(cgt, wredi);
+  const int neq = big_block_sum(ceq, wredi);
   if (t == 0) {
     cut->T1 = T1; cut->T2 = T2; cut->neff = neff; cut->sdel = sdel; cut->Cs = Cs; cut->alphaC = alphaC;
     cut->th = th; cut->eth = eth; cut->kstar = kstar; cut->need = kstar - ngt;
@@ -726,11 +806,13 @@ __global__ __launch_bounds__(256) void big_ems_keep_kernel(const T *f, const dou
   if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
 }
 
-__global__ void big_ems_finish_kernel(const BigCut *cut, const double *partial, int nparts, int32_t *k_star,
-                                      double *stats) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  double P = 0.0;
-  for (int i = 0; i < nparts; ++i) P += partial[i];
+__global__ __launch_bounds__(256) void big_ems_finish_kernel(const BigCut *cut, const double *partial, int nparts,
+                                                             int32_t *k_star, double *stats) {
+  __shared__ double wred[4];
+  double v = 0.0;
+  for (int i = threadIdx.x; i < nparts; i += blockDim.x) v += partial[i];
+  const double P = big_block_sum(v, wred);
+  if (threadIdx.x != 0) return;
   *k_star = cut->kstar;
   stats[0] = cut->T1;
   stats[1] = P;
@@ -863,15 +945,15 @@ template <typename T, int W, bool POLY>
 __global__ __launch_bounds__(256) void big_gather_kernel(BigTileArgs<T> a) {
   constexpr int S = BIG_TS + W + 1;
   using V4 = typename vec4<T>::type;
-  extern __shared__ __align__(16) unsigned char sm_raw[];
+  extern __shared__ __align__(32) unsigned char sm_raw[];
   V4 *sg = reinterpret_cast<V4 *>(sm_raw);   // [S * S] staged (u, du/dx, du/dy, 0)
-  __shared__ int s_chunk;
+  __shared__ int s_unit;
   const Geom &g = a.g;
   const T halfw = T(W) / T(2);
   const double *wn = a.windows + 3 * a.cell;
   const T cx = T(wn[0]), cy = T(wn[1]), R = T(wn[2]);
   const T pr = R > T(0) ? T(M_PI) / R : T(0);
-  big_chunks<T>(a, &s_chunk, [&](int t, int64_t lo, int64_t hi) {
+  big_units<T>(a, &s_unit, [&](int t, int64_t lo, int64_t hi, int) {
     const int tx0 = (t % a.ntx) * BIG_TS, ty0 = (t / a.ntx) * BIG_TS;
     for (int i = threadIdx.x; i < S * S; i += blockDim.x) {
       const int r = i / S, q = i - r * S;
@@ -919,18 +1001,31 @@ __global__ __launch_bounds__(256) void big_gather_kernel(BigTileArgs<T> a) {
       }
       T dWx, dWy;
       const T Wv = hann_wg(a.window_kind, xj, yj, cx, cy, R, pr, dWx, dWy);
-      const int j = a.perm[k];
-      if ((unsigned)j >= (unsigned)a.n) continue;   // defensive: every sorted slot holds a cell index
-      const T wj = a.ws[k];
-      if (a.grad_h) a.grad_h[j] = wj * Wv * u;
-      if (a.grad_x || a.grad_y) {
-        const T wh = wj * a.hs[k];
-        if (a.grad_x) a.grad_x[j] = wh * (dWx * u + Wv * ux);
-        if (a.grad_y) a.grad_y[j] = wh * (dWy * u + Wv * uy);
-      }
+      const T wj = a.ws[k], wh = wj * a.hs[k];
+      V4 o;
+      o.x = wj * Wv * u;
+      o.y = wh * (dWx * u + Wv * ux);
+      o.z = wh * (dWy * u + Wv * uy);
+      o.w = T(0);
+      a.gout[k] = o;   // sorted order, coalesced; the unpermute pass puts it at the input index
     }
     __syncthreads();
   });
+}
+
+// Gradients back to input order: one read of the sorted-order record per point
+// (at its sorted position) and coalesced writes of the three outputs.
+template <typename T>
+__global__ __launch_bounds__(256) void big_unpermute_kernel(const typename vec4<T>::type *gout, const int *inv,
+                                                            int64_t n, T *gh, T *gx, T *gy) {
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x) {
+    const int k = inv[j];
+    if (k < 0 || k >= n) continue;   // only if the sort's passes disagreed; never out of bounds
+    const typename vec4<T>::type v = gout[k];
+    if (gh) gh[j] = v.x;
+    if (gx) gx[j] = v.y;
+    if (gy) gy[j] = v.z;
+  }
 }
 
 // ------------------------------------------------------------------ host side
@@ -947,7 +1042,10 @@ enufft_status big_fail(enufft_plan_t p, hipError_t e, const char *what) {
 
 int stock_threads(int n) { return std::min(512, std::max(64, n / 2)); }
 
-size_t sort_lds(int ntiles) { return (size_t)3 * ntiles * sizeof(int) + (size_t)BIG_SCATTER_CHUNK * sizeof(uint16_t); }
+template <typename T>
+size_t sort_lds(int ntiles) {
+  return (size_t)big_scatter_sub<T>() * sizeof(typename vec4<T>::type) + (size_t)3 * ntiles * sizeof(int);
+}
 
 template <typename T>
 hipError_t set_attrs_t(int n1, int n2, int ntiles) {
@@ -956,7 +1054,8 @@ hipError_t set_attrs_t(int n1, int n2, int ntiles) {
     return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
   };
   hipError_t e = set((const void *)&big_count_kernel<T>, (size_t)ntiles * sizeof(int));
-  if (e == hipSuccess) e = set((const void *)&big_scatter_kernel<T>, sort_lds(ntiles));
+  if (e == hipSuccess) e = set((const void *)&big_scatter_kernel<T>, sort_lds<T>(ntiles));
+  if (e == hipSuccess) e = set((const void *)&big_tile_scan_kernel, (size_t)ntiles * sizeof(int));
   if (e == hipSuccess) e = set((const void *)&big_rows_kernel<T>, 4 * (size_t)n1 * el);
   if (e == hipSuccess) e = set((const void *)&big_cols_kernel<T>, 4 * (size_t)n2 * el);
   if (e == hipSuccess) e = set((const void *)&big_adj_cols_kernel<T>, 4 * (size_t)n2 * el);
@@ -974,29 +1073,40 @@ BigSortArgs<T> sort_args(enufft_plan_t p, int64_t c, const T *x, const T *y, con
   split_scale<T>(p->n2, &a.s2h, &a.s2l);
   a.W = p->W; a.n1 = p->n1; a.n2 = p->n2;
   a.ntx = p->big_ntx; a.ntiles = p->big_ntx * p->big_nty;
-  a.counts = p->big_counts; a.cursor = p->big_cursor; a.perm = p->big_perm;
+  a.nchunks = (int)((a.n + BIG_SORT_CHUNK - 1) / BIG_SORT_CHUNK);
+  a.ngroups = (a.nchunks + BIG_SCAN_GROUP - 1) / BIG_SCAN_GROUP;
+  a.chunk_hist = p->big_chunk_hist; a.group_sum = p->big_group_sum;
+  a.offsets = p->big_offsets; a.unit_base = p->big_unit_base; a.inv = p->big_inv;
   a.xs = (T *)p->big_xs; a.ys = (T *)p->big_ys; a.hs = (T *)p->big_hs; a.ws = (T *)p->big_ws;
   return a;
 }
 
-// Sort the points of cell c by tile into the plan's buffers.
+// Sort the points of cell c (n > 0) by tile into the plan's buffers: chunk
+// histograms, group sums, the tile scan, chunk starts, scatter.
 template <typename T>
 hipError_t sort_cell(enufft_plan_t p, int64_t c, const T *x, const T *y, const T *h, const T *w) {
   const BigSortArgs<T> a = sort_args<T>(p, c, x, y, h, w);
-  hipError_t e = fill<int>(p->big_counts, a.ntiles, 0, p->stream);
-  const int blocks = (int)((a.n + BIG_BIN_CHUNK - 1) / BIG_BIN_CHUNK);
-  if (e == hipSuccess && a.n > 0) {
-    hipLaunchKernelGGL((big_count_kernel<T>), dim3(blocks), dim3(512), (size_t)a.ntiles * sizeof(int), p->stream, a);
+  const dim3 tg((a.ntiles + 255) / 256, a.ngroups);
+  hipLaunchKernelGGL((big_count_kernel<T>), dim3(a.nchunks), dim3(BIG_SORT_THREADS), (size_t)a.ntiles * sizeof(int),
+                     p->stream, a);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(big_group_sum_kernel, tg, dim3(256), 0, p->stream, (const int *)a.chunk_hist, a.nchunks,
+                       a.ntiles, a.group_sum);
     e = hipGetLastError();
   }
   if (e == hipSuccess) {
-    hipLaunchKernelGGL(big_scan_kernel, dim3(1), dim3(1024), 0, p->stream, (const int *)p->big_counts, a.ntiles,
-                       p->big_offsets, p->big_cursor);
+    hipLaunchKernelGGL(big_tile_scan_kernel, dim3(1), dim3(1024), (size_t)a.ntiles * sizeof(int), p->stream,
+                       a.group_sum, a.ngroups, a.ntiles, a.offsets, a.unit_base);
     e = hipGetLastError();
   }
-  if (e == hipSuccess && a.n > 0) {
-    const int sblocks = (int)((a.n + BIG_SCATTER_CHUNK - 1) / BIG_SCATTER_CHUNK);
-    hipLaunchKernelGGL((big_scatter_kernel<T>), dim3(sblocks), dim3(BIG_SCATTER_THREADS), sort_lds(a.ntiles),
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(big_chunk_base_kernel, tg, dim3(256), 0, p->stream, a.chunk_hist,
+                       (const int *)a.group_sum, (const int64_t *)a.offsets, a.nchunks, a.ntiles);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL((big_scatter_kernel<T>), dim3(a.nchunks), dim3(BIG_SORT_THREADS), sort_lds<T>(a.ntiles),
                        p->stream, a);
     e = hipGetLastError();
   }
@@ -1007,8 +1117,8 @@ template <typename T>
 BigTileArgs<T> tile_args(enufft_plan_t p, int64_t c) {
   BigTileArgs<T> a{};
   a.xs = (const T *)p->big_xs; a.ys = (const T *)p->big_ys; a.hs = (const T *)p->big_hs; a.ws = (const T *)p->big_ws;
-  a.perm = p->big_perm;
   a.offsets = p->big_offsets;
+  a.unit_base = p->big_unit_base;
   a.ntiles = p->big_ntx * p->big_nty;
   a.ntx = p->big_ntx;
   a.n = p->offsets[c + 1] - p->offsets[c];
@@ -1023,8 +1133,10 @@ BigTileArgs<T> tile_args(enufft_plan_t p, int64_t c) {
   return a;
 }
 
+// Persistent workgroups for the unit passes (the unit count is known only on
+// the device; idle workgroups exit at once).
 int tile_blocks(enufft_plan_t p, int64_t n) {
-  return (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)p->n_cu * 8, (n + BIG_CHUNK - 1) / BIG_CHUNK));
+  return (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)p->n_cu * 8, p->big_units_max));
 }
 
 template <typename T, int W, bool POLY>
@@ -1096,16 +1208,27 @@ enufft_status type1_t(enufft_plan_t p, const T *x, const T *y, const T *h, const
                       int64_t c1) {
   const Geom &g = p->geom;
   const size_t el = sizeof(T);
+  const int64_t n12 = (int64_t)g.n1 * g.n2;
   for (int64_t c = c0; c < c1; ++c) {
     const int64_t n = p->offsets[c + 1] - p->offsets[c];
-    hipError_t e = fill<double>(p->big_grid, (int64_t)g.n1 * g.n2, 0.0, p->stream);
-    if (e == hipSuccess && n > 0) e = sort_cell<T>(p, c, x, y, h, w);
-    if (e == hipSuccess && n > 0) {
-      BigTileArgs<T> a = tile_args<T>(p, c);
-      a.grid = p->big_grid;
-      a.work_counter = p->big_work;
-      a.done_counter = p->big_work + 1;
-      e = by_width<T, SpreadW>(p->W, a, tile_blocks(p, n), p->stream);
+    hipError_t e = hipSuccess;
+    if (n == 0) {
+      e = fill<double>(p->big_grid, n12, 0.0, p->stream);
+    } else {
+      e = sort_cell<T>(p, c, x, y, h, w);
+      if (e == hipSuccess) {
+        BigTileArgs<T> a = tile_args<T>(p, c);
+        a.partial = p->big_partial;
+        a.work_counter = p->big_work;
+        a.done_counter = p->big_work + 1;
+        e = by_width<T, SpreadW>(p->W, a, tile_blocks(p, n), p->stream);
+      }
+      if (e == hipSuccess) {
+        hipLaunchKernelGGL(big_assemble_kernel, dim3((unsigned)((n12 + 255) / 256)), dim3(256), 0, p->stream,
+                           (const double *)p->big_partial, (const int *)p->big_unit_base, g, p->big_ntx, p->big_nty,
+                           BIG_TS + p->W + 1, p->big_grid);
+        e = hipGetLastError();
+      }
     }
     if (e == hipSuccess) {
       hipLaunchKernelGGL((big_rows_kernel<T>), dim3(g.n2 / 2), dim3(stock_threads(g.n1)), 4 * (size_t)g.n1 * el,
@@ -1129,6 +1252,7 @@ enufft_status adjoint_t(enufft_plan_t p, const T *x, const T *y, const T *h, con
   const Geom &g = p->geom;
   const int64_t M = (int64_t)g.N1 * g.N2;
   const size_t el = sizeof(T);
+  using V4 = typename vec4<T>::type;
   for (int64_t c = 0; c < p->n_cells; ++c) {
     const int64_t a0 = p->offsets[c], n = p->offsets[c + 1] - a0;
     if (n == 0) continue;
@@ -1142,18 +1266,23 @@ enufft_status adjoint_t(enufft_plan_t p, const T *x, const T *y, const T *h, con
     if (e == hipSuccess) {
       hipLaunchKernelGGL((big_adj_rows_kernel<T>), dim3(g.n2 / 2), dim3(stock_threads(g.n1)), 4 * (size_t)g.n1 * el,
                          p->stream, (const T *)p->big_cb, (const T *)p->big_cby, g, (const T *)p->d_tw1,
-                         (typename vec4<T>::type *)p->big_gu);
+                         (V4 *)p->big_gu);
       e = hipGetLastError();
     }
     if (e == hipSuccess) {
       BigTileArgs<T> a = tile_args<T>(p, c);
-      a.G4 = (const typename vec4<T>::type *)p->big_gu;
-      a.grad_h = gh ? gh + a0 : nullptr;
-      a.grad_x = gx ? gx + a0 : nullptr;
-      a.grad_y = gy ? gy + a0 : nullptr;
+      a.G4 = (const V4 *)p->big_gu;
+      a.gout = (V4 *)p->big_gout;
       a.work_counter = p->big_work + 2;
       a.done_counter = p->big_work + 3;
       e = by_width<T, GatherW>(p->W, a, tile_blocks(p, n), p->stream);
+    }
+    if (e == hipSuccess) {
+      const int blocks = (int)std::min<int64_t>(8192, (n + 255) / 256);
+      hipLaunchKernelGGL((big_unpermute_kernel<T>), dim3(blocks), dim3(256), 0, p->stream, (const V4 *)p->big_gout,
+                         (const int *)p->big_inv, n, gh ? gh + a0 : nullptr, gx ? gx + a0 : nullptr,
+                         gy ? gy + a0 : nullptr);
+      e = hipGetLastError();
     }
     if (e != hipSuccess) return big_fail(p, e, "large-cell adjoint");
   }
@@ -1162,9 +1291,11 @@ enufft_status adjoint_t(enufft_plan_t p, const T *x, const T *y, const T *h, con
 
 }  // namespace
 
-// Workspace of a large-cell plan: tile sort buffers sized for the largest cell,
-// the FP64 spreading grid, the column buffers, the three adjoint grids, the EMS
-// sort buffer (when a unit table can exceed the per-cell kernel's 4096) and
+// Workspace of a large-cell plan, sized for the largest cell: the sort's chunk
+// histograms, tile and unit offsets, the inverse permutation and the points in
+// tile order; the unit sub-grids and the FP64 spreading grid; the column
+// buffers and the interleaved adjoint grids; the sorted-order gradients; the
+// EMS sort buffer (when a unit table can exceed the per-cell kernel's 4096) and
 // the work counters.
 enufft_status big_prepare(enufft_plan_t p) {
   const Geom &g = p->geom;
@@ -1194,15 +1325,24 @@ enufft_status big_prepare(enufft_plan_t p) {
     size_t bytes;
     const char *what;
   };
+  const int64_t q1 = std::max<int64_t>(qmax, 1);
+  const int64_t nchunks = (q1 + BIG_SORT_CHUNK - 1) / BIG_SORT_CHUNK;
+  const int64_t ngroups = (nchunks + BIG_SCAN_GROUP - 1) / BIG_SCAN_GROUP;
+  // a tile's range touches at most (its length / chunk) + 2 unit chunks
+  p->big_units_max = (q1 + BIG_UNIT_CHUNK - 1) / BIG_UNIT_CHUNK + 2 * (int64_t)ntiles;
+  const int64_t S = BIG_TS + p->W + 1;
   const A list[] = {
-      {(void **)&p->big_counts, (size_t)ntiles * sizeof(int), "tile counts"},
+      {(void **)&p->big_chunk_hist, (size_t)(nchunks * ntiles) * sizeof(int), "chunk tile histograms"},
+      {(void **)&p->big_group_sum, (size_t)(ngroups * ntiles) * sizeof(int), "chunk group sums"},
       {(void **)&p->big_offsets, (size_t)(ntiles + 1) * sizeof(int64_t), "tile offsets"},
-      {(void **)&p->big_cursor, (size_t)ntiles * sizeof(int64_t), "tile cursors"},
-      {(void **)&p->big_perm, (size_t)std::max<int64_t>(qmax, 1) * sizeof(int), "point permutation"},
-      {&p->big_xs, (size_t)std::max<int64_t>(qmax, 1) * el, "sorted x"},
-      {&p->big_ys, (size_t)std::max<int64_t>(qmax, 1) * el, "sorted y"},
-      {&p->big_hs, (size_t)std::max<int64_t>(qmax, 1) * el, "sorted h"},
-      {&p->big_ws, (size_t)std::max<int64_t>(qmax, 1) * el, "sorted w"},
+      {(void **)&p->big_unit_base, (size_t)(ntiles + 1) * sizeof(int), "tile unit offsets"},
+      {(void **)&p->big_inv, (size_t)q1 * sizeof(int), "inverse permutation"},
+      {(void **)&p->big_partial, (size_t)(p->big_units_max * S * S) * sizeof(double), "unit sub-grids"},
+      {&p->big_gout, (size_t)q1 * 4 * el, "sorted-order gradients"},
+      {&p->big_xs, (size_t)q1 * el, "sorted x"},
+      {&p->big_ys, (size_t)q1 * el, "sorted y"},
+      {&p->big_hs, (size_t)q1 * el, "sorted h"},
+      {&p->big_ws, (size_t)q1 * el, "sorted w"},
       {(void **)&p->big_grid, n12 * sizeof(double), "fine grid"},
       {&p->big_cb, cols, "column buffer"},
       {&p->big_cby, cols, "column buffer (y)"},
@@ -1320,7 +1460,7 @@ enufft_status big_ems(enufft_plan_t p, const void *f, const enufft_ems_params *p
       e = hipGetLastError();
     }
     if (e == hipSuccess) {
-      hipLaunchKernelGGL(big_ems_finish_kernel, dim3(1), dim3(64), 0, p->stream, (const BigCut *)cut,
+      hipLaunchKernelGGL(big_ems_finish_kernel, dim3(1), dim3(256), 0, p->stream, (const BigCut *)cut,
                          (const double *)partial, mb, k_star + c, stats + c * 8);
       e = hipGetLastError();
     }

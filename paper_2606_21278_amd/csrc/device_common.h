@@ -340,13 +340,17 @@ __device__ __forceinline__ void fft4_step2(const Acc &acc, int k1) {
   for (int k2 = 0; k2 < B; ++k2) acc.store(k1 * B + k2, re[k2], im[k2]);
 }
 
-// Factorisation used for each supported length.
+// Factorisation used for each supported length (both factors powers of two;
+// the index arithmetic below uses their logarithms, since a division by a
+// factor known only at run time would compile to a full integer division).
 __host__ __device__ constexpr int fft_A(int n) { return n == 16 ? 4 : n == 32 ? 8 : n == 64 ? 8 : 16; }
 __host__ __device__ constexpr int fft_B(int n) { return n == 16 ? 4 : n == 32 ? 4 : n == 64 ? 8 : 8; }
-// Position of output bin k after the four-step transform.
+__host__ __device__ constexpr int fft_logA(int n) { return n == 16 ? 2 : n == 32 ? 3 : n == 64 ? 3 : 4; }
+__host__ __device__ constexpr int fft_logB(int n) { return n == 16 ? 2 : n == 32 ? 2 : n == 64 ? 3 : 3; }
+// Position of output bin k (>= 0) after the four-step transform: (k mod A) B + k / A.
 __device__ __forceinline__ int fft_pos(int k, int n) {
-  const int A = fft_A(n), B = fft_B(n);
-  return (k % A) * B + k / A;
+  const int la = fft_logA(n), lb = fft_logB(n);
+  return ((k & ((1 << la) - 1)) << lb) + (k >> la);
 }
 
 // Run step 1 or 2 of a length-n transform for one (instance, column) item.
@@ -380,14 +384,14 @@ struct ColAcc {
 // addressed through make(q).  All threads of the block take part.
 template <bool INV, int NT, typename T, typename Make>
 __device__ __forceinline__ void fft_batch(int n, int count, const T *tw, const Make &make) {
-  const int A = fft_A(n), B = fft_B(n);
+  const int A = fft_A(n), B = fft_B(n), la = fft_logA(n), lb = fft_logB(n);
   for (int it = threadIdx.x; it < count * B; it += NT) {
-    const int q = it / B, b = it - q * B;
+    const int q = it >> lb, b = it & (B - 1);
     fft4_dispatch<INV, 1, T>(n, make(q), b, tw);
   }
   __syncthreads();
   for (int it = threadIdx.x; it < count * A; it += NT) {
-    const int q = it / A, k1 = it - q * A;
+    const int q = it >> la, k1 = it & (A - 1);
     fft4_dispatch<INV, 2, T>(n, make(q), k1, tw);
   }
   __syncthreads();

@@ -400,9 +400,9 @@ enufft_status enufft_plan(enufft_plan_t *out, int64_t n_cells, const int64_t *ce
   if (big) {
     n1 = std::max(n1, 64);
     n2 = std::max(n2, 64);
-    if (n1 > 4096 || n2 > 4096 || (int64_t)n1 * n2 > (int64_t)1 << 23)
+    if (n1 > 4096 || n2 > 4096 || (int64_t)n1 * n2 > (int64_t)1 << 22)
       return fail(nullptr, ENUFFT_EUNSUPPORTED,
-                  "enufft_plan: fine grid above 4096 per axis or 2^23 cells is not supported");
+                  "enufft_plan: fine grid above 4096 per axis or 2^22 cells is not supported");
   }
 
   // ---- device

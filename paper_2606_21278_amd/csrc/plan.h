@@ -78,11 +78,15 @@ struct enufft_plan_s {
   // large-cell path: fine grid in HBM, points sorted by tile (mode boxes above 64 per axis)
   bool big = false;
   int big_ntx = 0, big_nty = 0;              // tiles per axis
-  int *big_counts = nullptr;                 // [tiles]
-  int64_t *big_offsets = nullptr;            // [tiles + 1]
-  int64_t *big_cursor = nullptr;             // [tiles]
-  int *big_perm = nullptr;                   // [largest cell] original index per sorted position
+  int *big_chunk_hist = nullptr;             // [chunks][tiles] counts, then chunk starts in each tile
+  int *big_group_sum = nullptr;              // [chunk groups][tiles]
+  int64_t *big_offsets = nullptr;            // [tiles + 1] tile ranges of the sorted order
+  int *big_unit_base = nullptr;              // [tiles + 1] first work unit of each tile
+  int *big_inv = nullptr;                    // [largest cell] sorted position of each input point
   void *big_xs = nullptr, *big_ys = nullptr, *big_hs = nullptr, *big_ws = nullptr;
+  double *big_partial = nullptr;             // [units][S x S] FP64 sub-grids of the spreading units
+  int64_t big_units_max = 0;
+  void *big_gout = nullptr;                  // [largest cell] gradients in sorted order (4-vectors)
   double *big_grid = nullptr;                // n2 x n1 FP64 spreading grid
   void *big_cb = nullptr, *big_cby = nullptr;   // column buffers [K1 + 1][n2] complex
   void *big_gu = nullptr;                    // adjoint grids: n2 x n1 cells of (u, du/dx, du/dy, 0)
