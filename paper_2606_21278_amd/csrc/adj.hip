@@ -38,8 +38,8 @@ __host__ __device__ inline AdjLayout adj_layout(const Geom &g, int W, int band_r
   L.g_off = 0;
   L.gx_off = gsz;
   L.gy_off = 2 * gsz;
-  // the column workspace aliases the grids (it is dead before they are
-  // written) but never the band spectra, which are filled while it is live
+  // the two column workspaces alias the grids (they are dead before the grids
+  // are written) but never the band spectra, which are filled while they are live
   const size_t ws = (size_t)g.n2 * L.cpitch;
   L.ws_off = 0;
   L.db0_off = std::max(3 * gsz, ws);
@@ -54,28 +54,31 @@ template <typename T, int NT>
 __device__ void load_columns(const AdjArgs<T> &a, const T *gc, int cell, T *ws, int cpitch, bool yderiv) {
   const Geom &g = a.g;
   const int per = g.K1 + 1;
+  const int M = g.N1 * g.N2;
   const int hi1 = g.lo1 + g.N1 - 1, hi2 = g.lo2 + g.N2 - 1;
+  const T *sf = gc;
+  const uint8_t *kp = a.keep ? a.keep + (int64_t)cell * M : nullptr;
+  const T *sdx = a.decon_x, *sdy = a.decon_y;
   // retained-power cotangent g = 2 lam_c f keep, formed on the fly
-  const uint8_t *kp = a.keep ? a.keep + (int64_t)cell * g.N1 * g.N2 : nullptr;
   const T two_lam = a.keep ? T(2.0 * (a.lam ? a.lam[cell] : 1.0)) : T(1);
   for (int it = threadIdx.x; it < g.n2 * per; it += NT) {
     const int bin = it / per, kx = it - bin * per;
     const int ky = bin <= g.n2 / 2 ? bin : bin - g.n2;   // signed frequency of this bin
     T hr = 0, hi = 0;
     if (ky >= -g.K2 && ky <= g.K2) {
-      const T s = a.decon_x[kx] * a.decon_y[ky < 0 ? -ky : ky];
+      const T s = sdx[kx] * sdy[ky < 0 ? -ky : ky];
       // G(kx, ky) and conj G(-kx, -ky), each zero outside the box
       if (kx <= hi1 && ky >= g.lo2 && ky <= hi2) {
         const int m = (ky - g.lo2) * g.N1 + (kx - g.lo1);
         const T sc = kp ? (kp[m] ? two_lam : T(0)) : T(1);
-        hr += sc * gc[2 * m];
-        hi += sc * gc[2 * m + 1];
+        hr += sc * sf[2 * m];
+        hi += sc * sf[2 * m + 1];
       }
       if (-kx >= g.lo1 && -ky >= g.lo2 && -ky <= hi2) {
         const int m = (-ky - g.lo2) * g.N1 + (-kx - g.lo1);
         const T sc = kp ? (kp[m] ? two_lam : T(0)) : T(1);
-        hr += sc * gc[2 * m];
-        hi -= sc * gc[2 * m + 1];
+        hr += sc * sf[2 * m];
+        hi -= sc * sf[2 * m + 1];
       }
       hr *= T(0.5) * s;
       hi *= T(0.5) * s;
@@ -105,11 +108,17 @@ __device__ void extract_band(const Geom &g, const T *ws, int cpitch, T *db, int 
   __syncthreads();
 }
 
-// The three grids' rows from the transform's output order into natural column
-// order (1,024 elements of each grid per round: read, barrier, write), then
-// columns 0 .. W - 2 repeated at n1 .. n1 + W - 2.
+// The grids' rows from the transform's output order into natural column order
+// (1,024 elements of each of the three fields per round: read, barrier,
+// write), then columns 0 .. W - 2 repeated at n1 .. n1 + W - 2.  Field 0 and 1
+// are the interleaved (u, du/dx) pairs of Guv, field 2 is Gy.
+template <typename T>
+__device__ __forceinline__ T *adj_field(T *Guv, T *Gy, int f, int e) {
+  return f == 2 ? Gy + e : Guv + 2 * e + f;
+}
+
 template <typename T, int W, int NT>
-__device__ void rows_to_natural(T *Gu, T *Gx, T *Gy, int rows, int n1, int apitch) {
+__device__ void rows_to_natural(T *Guv, T *Gy, int rows, int n1, int apitch) {
   constexpr int PER = 3 * 1024 / NT;
   const int ln1 = 31 - __builtin_clz(n1);
   const int rb = 1024 >> ln1;   // rows per round
@@ -118,27 +127,24 @@ __device__ void rows_to_natural(T *Gu, T *Gx, T *Gy, int rows, int n1, int apitc
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
       const int e = threadIdx.x + q * NT;
-      const int gi = e >> 10, w = e & 1023;
+      const int f = e >> 10, w = e & 1023;
       const int r = r0 + (w >> ln1), c = w & (n1 - 1);
-      const T *G = gi == 0 ? Gu : gi == 1 ? Gx : Gy;
-      v[q] = r < rows ? G[r * apitch + fft_pos(c, n1)] : T(0);
+      v[q] = r < rows ? *adj_field(Guv, Gy, f, r * apitch + fft_pos(c, n1)) : T(0);
     }
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
       const int e = threadIdx.x + q * NT;
-      const int gi = e >> 10, w = e & 1023;
+      const int f = e >> 10, w = e & 1023;
       const int r = r0 + (w >> ln1), c = w & (n1 - 1);
-      T *G = gi == 0 ? Gu : gi == 1 ? Gx : Gy;
-      if (r < rows) G[r * apitch + c] = v[q];
+      if (r < rows) *adj_field(Guv, Gy, f, r * apitch + c) = v[q];
     }
     __syncthreads();
   }
   for (int e = threadIdx.x; e < 3 * rows * (W - 1); e += NT) {
-    const int gi = e / (rows * (W - 1)), rem = e - gi * rows * (W - 1);
+    const int f = e / (rows * (W - 1)), rem = e - f * rows * (W - 1);
     const int r = rem / (W - 1), c = rem - r * (W - 1);
-    T *G = gi == 0 ? Gu : gi == 1 ? Gx : Gy;
-    G[r * apitch + n1 + c] = G[r * apitch + c];
+    *adj_field(Guv, Gy, f, r * apitch + n1 + c) = *adj_field(Guv, Gy, f, r * apitch + c);
   }
   __syncthreads();
 }
@@ -148,7 +154,7 @@ __device__ void rows_to_natural(T *Gu, T *Gx, T *Gy, int rows, int n1, int apitc
 // c_j = w_j W(x_j) h_j turns the interpolated u, du/dx, du/dy into dL/dh,
 // dL/dx, dL/dy.
 template <typename T, int W, bool POLY>
-__device__ __forceinline__ void gather_point(const AdjArgs<T> &a, const T *Gu, const T *Gx, const T *Gy, int apitch,
+__device__ __forceinline__ void gather_point(const AdjArgs<T> &a, const T *Guv, const T *Gy, int apitch,
                                              int band_lo, int64_t j, T xj, T yj, T hj, T wj, T cx, T cy, T R,
                                              T pr) {
   const Geom &g = a.g;
@@ -161,21 +167,23 @@ __device__ __forceinline__ void gather_point(const AdjArgs<T> &a, const T *Gu, c
   T u = 0, ux = 0, uy = 0;
   // rows in natural column order with the wrap-around columns repeated: the
   // W taps of a row are W consecutive elements from one base address
-  const T *pu = Gu + r0 * apitch + (fx.i0 & (g.n1 - 1));
-  const T *px = Gx + (pu - Gu), *py = Gy + (pu - Gu);
+  using V2 = typename vec2<T>::type;
+  const int e0 = r0 * apitch + (fx.i0 & (g.n1 - 1));
+  const V2 *puv = reinterpret_cast<const V2 *>(Guv) + e0;
+  const T *py = Gy + e0;
   auto row = [&](T kyv) {
     T su = 0, sx = 0, sy = 0;
 #pragma unroll
     for (int dx = 0; dx < W; ++dx) {
-      su += kx[dx] * pu[dx];
-      sx += kx[dx] * px[dx];
+      const V2 v = puv[dx];
+      su += kx[dx] * v.x;
+      sx += kx[dx] * v.y;
       sy += kx[dx] * py[dx];
     }
     u += kyv * su;
     ux += kyv * sx;
     uy += kyv * sy;
-    pu += apitch;
-    px += apitch;
+    puv += apitch;
     py += apitch;
   };
   // kernel values: the plan's per-tap polynomials (FP32, W <= ES_MAXW) or psi
@@ -211,7 +219,7 @@ __device__ __forceinline__ void gather_point(const AdjArgs<T> &a, const T *Gu, c
 // register buffers, so the gather is not serialised behind point loads.
 // Every point of the item is read (its band decides whether it is served).
 template <typename T, int W, int NT, bool POLY>
-__device__ __forceinline__ void gather_item(const AdjArgs<T> &a, const T *Gu, const T *Gx, const T *Gy, int apitch,
+__device__ __forceinline__ void gather_item(const AdjArgs<T> &a, const T *Guv, const T *Gy, int apitch,
                                             int band_lo, int64_t begin, int64_t end, T cx, T cy, T R) {
   const T pr = R > T(0) ? T(M_PI) / R : T(0);
   int64_t body0 = end, body1 = end;
@@ -234,10 +242,10 @@ __device__ __forceinline__ void gather_item(const AdjArgs<T> &a, const T *Gu, co
     };
     auto step = [&](const V &xv, const V &yv, const V &hv, const V &wv, int64_t qq) {
       if (qq >= q1) return;
-      gather_point<T, W, POLY>(a, Gu, Gx, Gy, apitch, band_lo, qq * 4 + 0, xv.x, yv.x, hv.x, wv.x, cx, cy, R, pr);
-      gather_point<T, W, POLY>(a, Gu, Gx, Gy, apitch, band_lo, qq * 4 + 1, xv.y, yv.y, hv.y, wv.y, cx, cy, R, pr);
-      gather_point<T, W, POLY>(a, Gu, Gx, Gy, apitch, band_lo, qq * 4 + 2, xv.z, yv.z, hv.z, wv.z, cx, cy, R, pr);
-      gather_point<T, W, POLY>(a, Gu, Gx, Gy, apitch, band_lo, qq * 4 + 3, xv.w, yv.w, hv.w, wv.w, cx, cy, R, pr);
+      gather_point<T, W, POLY>(a, Guv, Gy, apitch, band_lo, qq * 4 + 0, xv.x, yv.x, hv.x, wv.x, cx, cy, R, pr);
+      gather_point<T, W, POLY>(a, Guv, Gy, apitch, band_lo, qq * 4 + 1, xv.y, yv.y, hv.y, wv.y, cx, cy, R, pr);
+      gather_point<T, W, POLY>(a, Guv, Gy, apitch, band_lo, qq * 4 + 2, xv.z, yv.z, hv.z, wv.z, cx, cy, R, pr);
+      gather_point<T, W, POLY>(a, Guv, Gy, apitch, band_lo, qq * 4 + 3, xv.w, yv.w, hv.w, wv.w, cx, cy, R, pr);
     };
     V x0{}, y0{}, h0{}, w0{}, x1{}, y1{}, h1{}, w1{}, x2{}, y2{}, h2{}, w2{};
     load(x0, y0, h0, w0, q);
@@ -255,7 +263,7 @@ __device__ __forceinline__ void gather_item(const AdjArgs<T> &a, const T *Gu, co
   const int64_t nhead = body0 - begin, ntail = end - body1;
   for (int64_t i = threadIdx.x; i < nhead + ntail; i += NT) {
     const int64_t j = i < nhead ? begin + i : body1 + (i - nhead);
-    gather_point<T, W, POLY>(a, Gu, Gx, Gy, apitch, band_lo, j, a.x[j], a.y[j], a.h[j], a.w[j], cx, cy, R, pr);
+    gather_point<T, W, POLY>(a, Guv, Gy, apitch, band_lo, j, a.x[j], a.y[j], a.h[j], a.w[j], cx, cy, R, pr);
   }
 }
 
@@ -267,7 +275,9 @@ __global__ __launch_bounds__(NT) void adj_kernel(AdjArgs<T> a) {
   const Geom &g = a.g;
   const AdjLayout L = adj_layout(g, W, a.band_rows);
   const int pitch = L.apitch;
-  T *Gu = sm + L.g_off, *Gx = sm + L.gx_off, *Gy = sm + L.gy_off;
+  // Guv: rows of (u, du/dx) pairs (the real and imaginary parts of one complex
+  // row transform, kept interleaved); Gy: rows of du/dy
+  T *Guv = sm + L.g_off, *Gy = sm + L.gy_off;
   T *db0 = sm + L.db0_off, *db1 = sm + L.db1_off, *ws = sm + L.ws_off;
   const int per = g.K1 + 1;
   const bool persistent = a.work_counter != nullptr;
@@ -286,29 +296,24 @@ __global__ __launch_bounds__(NT) void adj_kernel(AdjArgs<T> a) {
     const int y0 = it.band * a.band_rows;   // fine row of band-local row 0
 
     // columns of H and of i ky H, inverse transformed along y; keep the band rows
-    load_columns<T, NT>(a, gc, it.cell, ws, L.cpitch, false);
-    fft_batch<true, NT, T>(g.n2, per, a.tw2, [&](int q) {
-      ColAcc<T> acc;
-      acc.base = ws + 2 * q;
-      acc.stride = L.cpitch;
-      return acc;
-    });
-    extract_band<T, NT>(g, ws, L.cpitch, db0, L.rows, y0);
-    load_columns<T, NT>(a, gc, it.cell, ws, L.cpitch, true);
-    fft_batch<true, NT, T>(g.n2, per, a.tw2, [&](int q) {
-      ColAcc<T> acc;
-      acc.base = ws + 2 * q;
-      acc.stride = L.cpitch;
-      return acc;
-    });
-    extract_band<T, NT>(g, ws, L.cpitch, db1, L.rows, y0);
+    for (int pass = 0; pass < 2; ++pass) {
+      load_columns<T, NT>(a, gc, it.cell, ws, L.cpitch, pass == 1);
+      fft_batch<true, NT, T>(g.n2, per, a.tw2, [&](int q) {
+        ColAcc<T> acc;
+        acc.base = ws + 2 * q;
+        acc.stride = L.cpitch;
+        return acc;
+      });
+      extract_band<T, NT>(g, ws, L.cpitch, pass == 0 ? db0 : db1, L.rows, y0);
+    }
 
     // Row stage.  Pair (u_r, ux_r): Z(k) = D(k) + i (i k D(k)); pair (uy_r, uy_r+1):
     // Z(k) = Dy_r(k) + i Dy_r+1(k); negative bins from Hermitian symmetry.
     const int n1 = g.n1;
     const int ny_pairs = L.rows / 2;
+    const int ln1 = 31 - __builtin_clz(n1);
     for (int i2 = threadIdx.x; i2 < L.rows * n1; i2 += NT) {
-      const int r = i2 / n1, k = i2 - r * n1;
+      const int r = i2 >> ln1, k = i2 & (n1 - 1);
       T zr = 0, zi = 0, yr = 0, yi = 0;
       const int kk = k <= n1 / 2 ? k : n1 - k;     // |frequency| of this bin
       if (kk <= g.K1 && (k == kk || kk > 0)) {
@@ -329,32 +334,34 @@ __global__ __launch_bounds__(NT) void adj_kernel(AdjArgs<T> a) {
           yi = ai + br;
         }
       }
-      Gu[r * pitch + k] = zr;
-      Gx[r * pitch + k] = zi;
+      Guv[2 * (r * pitch + k)] = zr;
+      Guv[2 * (r * pitch + k) + 1] = zi;
       if ((r & 1) == 0) {
         Gy[r * pitch + k] = yr;
         if (r + 1 < L.rows) Gy[(r + 1) * pitch + k] = yi;
       }
     }
     __syncthreads();
-    fft_batch<true, NT, T>(n1, L.rows, a.tw1, [&](int q) {
-      RowPairAcc<T> acc;
-      acc.r0 = Gu + q * pitch;
-      acc.r1 = Gx + q * pitch;
+    // one batch: the interleaved (u, du/dx) rows, then the du/dy row pairs (band
+    // rows = band_rows + W is even, both terms are, so uy rows pair up exactly)
+    fft_batch<true, NT, T>(n1, L.rows + ny_pairs, a.tw1, [&](int q) {
+      StridedPairAcc<T> acc;
+      if (q < L.rows) {
+        acc.r0 = Guv + 2 * q * pitch;
+        acc.r1 = acc.r0 + 1;
+        acc.stride = 2;
+      } else {
+        acc.r0 = Gy + 2 * (q - L.rows) * pitch;
+        acc.r1 = acc.r0 + pitch;
+        acc.stride = 1;
+      }
       return acc;
     });
-    // band rows = band_rows + W is even (both terms are), so uy rows pair up exactly
-    fft_batch<true, NT, T>(n1, ny_pairs, a.tw1, [&](int q) {
-      RowPairAcc<T> acc;
-      acc.r0 = Gy + (2 * q) * pitch;
-      acc.r1 = acc.r0 + pitch;
-      return acc;
-    });
-    rows_to_natural<T, W, NT>(Gu, Gx, Gy, L.rows, n1, pitch);
+    rows_to_natural<T, W, NT>(Guv, Gy, L.rows, n1, pitch);
 
     // Gather at the points of this band.
     const double *wn = a.windows + 3 * (int64_t)it.cell;
-    gather_item<T, W, NT, POLY>(a, Gu, Gx, Gy, L.apitch, it.band * a.band_rows, it.begin, it.end, T(wn[0]), T(wn[1]),
+    gather_item<T, W, NT, POLY>(a, Guv, Gy, L.apitch, it.band * a.band_rows, it.begin, it.end, T(wn[0]), T(wn[1]),
                           T(wn[2]));
     __syncthreads();
     if (!persistent) break;

@@ -371,6 +371,16 @@ struct RowPairAcc {
   __device__ void load(int i, T &re, T &im) const { re = r0[i]; im = r1[i]; }
   __device__ void store(int i, T re, T im) const { r0[i] = re; r1[i] = im; }
 };
+// Complex sequence with re and im in two strided arrays: element i is
+// (r0[i * stride], r1[i * stride]) -- a pair of real rows (r1 = r0 + pitch,
+// stride 1) or an interleaved complex row (r1 = r0 + 1, stride 2).
+template <typename T>
+struct StridedPairAcc {
+  T *r0, *r1;
+  int stride;
+  __device__ void load(int i, T &re, T &im) const { re = r0[i * stride]; im = r1[i * stride]; }
+  __device__ void store(int i, T re, T im) const { r0[i * stride] = re; r1[i * stride] = im; }
+};
 // Complex column: element i at base[i * stride], interleaved (re, im).
 template <typename T>
 struct ColAcc {
