@@ -108,10 +108,13 @@ __device__ void extract_band(const Geom &g, const T *ws, int cpitch, T *db, int 
   __syncthreads();
 }
 
-// The grids' rows from the transform's output order into natural column order
-// (1,024 elements of each of the three fields per round: read, barrier,
-// write), then columns 0 .. W - 2 repeated at n1 .. n1 + W - 2.  Field 0 and 1
-// are the interleaved (u, du/dx) pairs of Guv, field 2 is Gy.
+// The grids' rows from the transform's output order into natural column order,
+// with columns 0 .. W - 2 repeated at n1 .. n1 + W - 2.  Each wave permutes
+// whole rows of the three fields (the interleaved (u, du/dx) pairs of Guv and
+// du/dy in Gy) on its own: it reads a row's elements into registers, then
+// writes them back in natural order (one wave's LDS accesses complete in
+// order, and the writes depend on the reads), so no workgroup barrier is
+// needed until the end.
 template <typename T>
 __device__ __forceinline__ T *adj_field(T *Guv, T *Gy, int f, int e) {
   return f == 2 ? Gy + e : Guv + 2 * e + f;
@@ -119,35 +122,70 @@ __device__ __forceinline__ T *adj_field(T *Guv, T *Gy, int f, int e) {
 
 template <typename T, int W, int NT>
 __device__ void rows_to_natural(T *Guv, T *Gy, int rows, int n1, int apitch) {
-  constexpr int PER = 3 * 1024 / NT;
+  constexpr int NW = NT / 64;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  // 3 n1 elements per row, up to 3 * 128 / 64 = 6 per lane
+  const int per_lane = (3 * n1 + 63) / 64;
   const int ln1 = 31 - __builtin_clz(n1);
-  const int rb = 1024 >> ln1;   // rows per round
-  for (int r0 = 0; r0 < rows; r0 += rb) {
-    T v[PER];
+  for (int r = wave; r < rows; r += NW) {
+    T v[6];
 #pragma unroll
-    for (int q = 0; q < PER; ++q) {
-      const int e = threadIdx.x + q * NT;
-      const int f = e >> 10, w = e & 1023;
-      const int r = r0 + (w >> ln1), c = w & (n1 - 1);
-      v[q] = r < rows ? *adj_field(Guv, Gy, f, r * apitch + fft_pos(c, n1)) : T(0);
+    for (int q = 0; q < 6; ++q) {
+      const int e = lane + 64 * q;
+      if (q < per_lane && e < 3 * n1) {
+        const int f = e >> ln1, c = e & (n1 - 1);
+        v[q] = *adj_field(Guv, Gy, f, r * apitch + fft_pos(c, n1));
+      }
     }
-    __syncthreads();
 #pragma unroll
-    for (int q = 0; q < PER; ++q) {
-      const int e = threadIdx.x + q * NT;
-      const int f = e >> 10, w = e & 1023;
-      const int r = r0 + (w >> ln1), c = w & (n1 - 1);
-      if (r < rows) *adj_field(Guv, Gy, f, r * apitch + c) = v[q];
+    for (int q = 0; q < 6; ++q) {
+      const int e = lane + 64 * q;
+      if (q < per_lane && e < 3 * n1) {
+        const int f = e >> ln1, c = e & (n1 - 1);
+        *adj_field(Guv, Gy, f, r * apitch + c) = v[q];
+        if (c < W - 1) *adj_field(Guv, Gy, f, r * apitch + n1 + c) = v[q];
+      }
     }
-    __syncthreads();
-  }
-  for (int e = threadIdx.x; e < 3 * rows * (W - 1); e += NT) {
-    const int f = e / (rows * (W - 1)), rem = e - f * rows * (W - 1);
-    const int r = rem / (W - 1), c = rem - r * (W - 1);
-    *adj_field(Guv, Gy, f, r * apitch + n1 + c) = *adj_field(Guv, Gy, f, r * apitch + c);
   }
   __syncthreads();
 }
+
+// First-step accessor of the row transforms: load(k) forms bin k of the row's
+// spectrum from the band's column data db ([row][kx] complex, kx = 0..K1):
+// for a (u, du/dx) row, (1 - k) D(k); for a du/dy pair (rows row, row + 1),
+// D_row(k) + i D_row+1(k); D(-k) = conj D(k), zero beyond K1.  store() writes
+// the grid row like StridedPairAcc.
+template <typename T>
+struct RowSpecAcc {
+  const T *db;
+  T *r0, *r1;
+  int stride, row, per, n1, K1;
+  bool pair;
+  __device__ void load(int k, T &re, T &im) const {
+    const int kk = k <= n1 / 2 ? k : n1 - k;
+    re = T(0);
+    im = T(0);
+    if (kk > K1) return;
+    const bool neg = k != kk;
+    const T *d = db + 2 * (row * per + kk);
+    T dr = d[0], di = d[1];
+    if (neg) di = -di;
+    if (!pair) {
+      const T kf = neg ? -T(kk) : T(kk);
+      re = dr - kf * dr;
+      im = di - kf * di;
+    } else {
+      T br = d[2 * per], bi = d[2 * per + 1];
+      if (neg) bi = -bi;
+      re = dr - bi;
+      im = di + br;
+    }
+  }
+  __device__ void store(int i, T re, T im) const {
+    r0[i * stride] = re;
+    r1[i * stride] = im;
+  }
+};
 
 // Gradients at one point from the band's three grids (W x W taps each), if the
 // point's footprint starts in this band; the chain rule through the strength
@@ -307,56 +345,50 @@ __global__ __launch_bounds__(NT) void adj_kernel(AdjArgs<T> a) {
       extract_band<T, NT>(g, ws, L.cpitch, pass == 0 ? db0 : db1, L.rows, y0);
     }
 
-    // Row stage.  Pair (u_r, ux_r): Z(k) = D(k) + i (i k D(k)); pair (uy_r, uy_r+1):
-    // Z(k) = Dy_r(k) + i Dy_r+1(k); negative bins from Hermitian symmetry.
+    // Row stage, one batch of inverse transforms: the (u, du/dx) rows, spectrum
+    // Z(k) = D(k) + i (i k D(k)) = (1 - k) D(k), stored interleaved in Guv, and
+    // the du/dy row pairs, Z(k) = Dy_r(k) + i Dy_r+1(k), in Gy; the bins k < 0
+    // are the conjugates of column -k.  The first step of the transform reads
+    // the spectra straight from the band's column data (no separate pass
+    // writing them into the grids); band rows = band_rows + W is even, so the
+    // du/dy rows pair up exactly.
     const int n1 = g.n1;
     const int ny_pairs = L.rows / 2;
-    const int ln1 = 31 - __builtin_clz(n1);
-    for (int i2 = threadIdx.x; i2 < L.rows * n1; i2 += NT) {
-      const int r = i2 >> ln1, k = i2 & (n1 - 1);
-      T zr = 0, zi = 0, yr = 0, yi = 0;
-      const int kk = k <= n1 / 2 ? k : n1 - k;     // |frequency| of this bin
-      if (kk <= g.K1 && (k == kk || kk > 0)) {
-        const bool neg = k != kk;
-        T dr = db0[2 * (r * per + kk)], di = db0[2 * (r * per + kk) + 1];
-        if (neg) di = -di;
-        const T kf = neg ? -T(kk) : T(kk);
-        // Z = D + i (i k D) = (1 - k) D
-        zr = dr - kf * dr;
-        zi = di - kf * di;
-        const int rr = r;   // uy rows r (re) and r + 1 (im) for even r
-        if ((rr & 1) == 0) {
-          T ar = db1[2 * (rr * per + kk)], ai = db1[2 * (rr * per + kk) + 1];
-          T br = 0, bi = 0;
-          if (rr + 1 < L.rows) { br = db1[2 * ((rr + 1) * per + kk)]; bi = db1[2 * ((rr + 1) * per + kk) + 1]; }
-          if (neg) { ai = -ai; bi = -bi; }
-          yr = ar - bi;
-          yi = ai + br;
-        }
-      }
-      Guv[2 * (r * pitch + k)] = zr;
-      Guv[2 * (r * pitch + k) + 1] = zi;
-      if ((r & 1) == 0) {
-        Gy[r * pitch + k] = yr;
-        if (r + 1 < L.rows) Gy[(r + 1) * pitch + k] = yi;
-      }
-    }
-    __syncthreads();
-    // one batch: the interleaved (u, du/dx) rows, then the du/dy row pairs (band
-    // rows = band_rows + W is even, both terms are, so uy rows pair up exactly)
-    fft_batch<true, NT, T>(n1, L.rows + ny_pairs, a.tw1, [&](int q) {
-      StridedPairAcc<T> acc;
-      if (q < L.rows) {
-        acc.r0 = Guv + 2 * q * pitch;
-        acc.r1 = acc.r0 + 1;
-        acc.stride = 2;
-      } else {
-        acc.r0 = Gy + 2 * (q - L.rows) * pitch;
-        acc.r1 = acc.r0 + pitch;
-        acc.stride = 1;
-      }
-      return acc;
-    });
+    const int K1 = g.K1;
+    fft_batch2<true, NT, T>(
+        n1, L.rows + ny_pairs, a.tw1,
+        [&](int q) {
+          RowSpecAcc<T> acc;
+          acc.db = q < L.rows ? db0 : db1;
+          acc.row = q < L.rows ? q : 2 * (q - L.rows);
+          acc.pair = q >= L.rows;
+          acc.per = per;
+          acc.n1 = n1;
+          acc.K1 = K1;
+          if (q < L.rows) {
+            acc.r0 = Guv + 2 * q * pitch;
+            acc.r1 = acc.r0 + 1;
+            acc.stride = 2;
+          } else {
+            acc.r0 = Gy + 2 * (q - L.rows) * pitch;
+            acc.r1 = acc.r0 + pitch;
+            acc.stride = 1;
+          }
+          return acc;
+        },
+        [&](int q) {
+          StridedPairAcc<T> acc;
+          if (q < L.rows) {
+            acc.r0 = Guv + 2 * q * pitch;
+            acc.r1 = acc.r0 + 1;
+            acc.stride = 2;
+          } else {
+            acc.r0 = Gy + 2 * (q - L.rows) * pitch;
+            acc.r1 = acc.r0 + pitch;
+            acc.stride = 1;
+          }
+          return acc;
+        });
     rows_to_natural<T, W, NT>(Guv, Gy, L.rows, n1, pitch);
 
     // Gather at the points of this band.

@@ -390,6 +390,25 @@ struct ColAcc {
   __device__ void store(int i, T re, T im) const { base[i * stride] = re; base[i * stride + 1] = im; }
 };
 
+// As fft_batch, with separate accessors for the two steps: step 1 reads
+// instance q through make1(q) and stores through it, step 2 reads and writes
+// through make2(q).  make1 may read its inputs from elsewhere (the first step
+// then runs out of place), as long as its stores land where make2 reads.
+template <bool INV, int NT, typename T, typename Make1, typename Make2>
+__device__ __forceinline__ void fft_batch2(int n, int count, const T *tw, const Make1 &make1, const Make2 &make2) {
+  const int A = fft_A(n), B = fft_B(n), la = fft_logA(n), lb = fft_logB(n);
+  for (int it = threadIdx.x; it < count * B; it += NT) {
+    const int q = it >> lb, b = it & (B - 1);
+    fft4_dispatch<INV, 1, T>(n, make1(q), b, tw);
+  }
+  __syncthreads();
+  for (int it = threadIdx.x; it < count * A; it += NT) {
+    const int q = it >> la, k1 = it & (A - 1);
+    fft4_dispatch<INV, 2, T>(n, make2(q), k1, tw);
+  }
+  __syncthreads();
+}
+
 // Batched four-step transform over `count` instances of length n; instance q is
 // addressed through make(q).  All threads of the block take part.
 template <bool INV, int NT, typename T, typename Make>
