@@ -26,10 +26,18 @@ struct AdjLayout {
                   // columns are repeated after the last, so a footprint's W columns are contiguous
   int cpitch;     // column-workspace pitch (elements) = 2 (K1 + 1) + 2
   size_t g_off, gx_off, gy_off, db0_off, db1_off, ws_off;   // element offsets
+  size_t st_off;  // staged cell spectrum, deconvolution factors and keep bytes
   size_t total;   // elements
 };
 
-__host__ __device__ inline AdjLayout adj_layout(const Geom &g, int W, int band_rows) {
+// Elements of the staging area: the cell's N1 N2 complex coefficients, the
+// K1 + 1 and K2 + 1 deconvolution factors, then N1 N2 keep bytes.
+__host__ __device__ inline size_t adj_stage_elems(const Geom &g, size_t elem) {
+  const size_t M = (size_t)g.N1 * g.N2;
+  return 2 * M + (g.K1 + 1) + (g.K2 + 1) + (M + elem - 1) / elem;
+}
+
+__host__ __device__ inline AdjLayout adj_layout(const Geom &g, int W, int band_rows, size_t elem) {
   AdjLayout L;
   L.rows = band_rows + W;   // R + W - 1 rows are used; one more keeps the uy rows paired
   L.apitch = (g.n1 + W - 1 + 1) & ~1;
@@ -38,29 +46,72 @@ __host__ __device__ inline AdjLayout adj_layout(const Geom &g, int W, int band_r
   L.g_off = 0;
   L.gx_off = gsz;
   L.gy_off = 2 * gsz;
-  // the two column workspaces alias the grids (they are dead before the grids
-  // are written) but never the band spectra, which are filled while they are live
+  // the column workspace and the staging area behind it alias the grids (they
+  // are dead before the grids are written) but never the band spectra, which
+  // are filled while they are live
   const size_t ws = (size_t)g.n2 * L.cpitch;
   L.ws_off = 0;
-  L.db0_off = std::max(3 * gsz, ws);
+  L.st_off = ws;
+  L.db0_off = std::max(3 * gsz, ws + adj_stage_elems(g, elem));
   L.db1_off = L.db0_off + (size_t)L.rows * (g.K1 + 1) * 2;
   L.total = L.db1_off + (size_t)L.rows * (g.K1 + 1) * 2;
   return L;
 }
 
-// Fill the column workspace with the Hermitian, pre-corrected spectrum for
-// columns kx = 0..K1 over all n2 bins; with yderiv, multiplied by i ky.
+// Copy the cell's cotangent spectrum, its keep bytes and the deconvolution
+// factors into the staging area.  Every thread issues all of its global loads
+// before it stores any (the loads are unconditional, clamped to the last
+// element), so the copy costs about one memory latency instead of one per
+// element.
 template <typename T, int NT>
-__device__ void load_columns(const AdjArgs<T> &a, const T *gc, int cell, T *ws, int cpitch, bool yderiv) {
+__device__ void stage_spectrum(const AdjArgs<T> &a, const T *gc, int cell, T *st) {
+  const Geom &g = a.g;
+  const int M = g.N1 * g.N2, n = 2 * M;
+  constexpr int U = 16;
+  for (int base = 0; base < n; base += U * NT) {
+    T v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) v[u] = gc[min(base + u * NT + (int)threadIdx.x, n - 1)];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int i = base + u * NT + threadIdx.x;
+      if (i < n) st[i] = v[u];
+    }
+  }
+  T *sdx = st + n, *sdy = sdx + g.K1 + 1;
+  for (int i = threadIdx.x; i <= g.K1; i += NT) sdx[i] = a.decon_x[i];
+  for (int i = threadIdx.x; i <= g.K2; i += NT) sdy[i] = a.decon_y[i];
+  if (a.keep) {
+    const uint8_t *kp = a.keep + (int64_t)cell * M;
+    uint8_t *sk = reinterpret_cast<uint8_t *>(sdy + g.K2 + 1);
+    for (int base = 0; base < M; base += U * NT) {
+      uint8_t v[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) v[u] = kp[min(base + u * NT + (int)threadIdx.x, M - 1)];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int i = base + u * NT + threadIdx.x;
+        if (i < M) sk[i] = v[u];
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// Fill the column workspace with the Hermitian, pre-corrected spectrum for
+// columns kx = 0..K1 over all n2 bins (from the staged copy; two_lam is the
+// retained-power factor 2 lam_c, or 1 without a keep mask); with yderiv,
+// multiplied by i ky.
+template <typename T, int NT>
+__device__ void load_columns(const AdjArgs<T> &a, const T *st, T two_lam, T *ws, int cpitch, bool yderiv) {
   const Geom &g = a.g;
   const int per = g.K1 + 1;
   const int M = g.N1 * g.N2;
   const int hi1 = g.lo1 + g.N1 - 1, hi2 = g.lo2 + g.N2 - 1;
-  const T *sf = gc;
-  const uint8_t *kp = a.keep ? a.keep + (int64_t)cell * M : nullptr;
-  const T *sdx = a.decon_x, *sdy = a.decon_y;
+  const T *sf = st;
+  const T *sdx = st + 2 * M, *sdy = sdx + per;
+  const uint8_t *kp = a.keep ? reinterpret_cast<const uint8_t *>(sdy + g.K2 + 1) : nullptr;
   // retained-power cotangent g = 2 lam_c f keep, formed on the fly
-  const T two_lam = a.keep ? T(2.0 * (a.lam ? a.lam[cell] : 1.0)) : T(1);
   for (int it = threadIdx.x; it < g.n2 * per; it += NT) {
     const int bin = it / per, kx = it - bin * per;
     const int ky = bin <= g.n2 / 2 ? bin : bin - g.n2;   // signed frequency of this bin
@@ -311,7 +362,7 @@ __global__ __launch_bounds__(NT) void adj_kernel(AdjArgs<T> a) {
   T *sm = reinterpret_cast<T *>(smem_raw);
   __shared__ int s_item;
   const Geom &g = a.g;
-  const AdjLayout L = adj_layout(g, W, a.band_rows);
+  const AdjLayout L = adj_layout(g, W, a.band_rows, sizeof(T));
   const int pitch = L.apitch;
   // Guv: rows of (u, du/dx) pairs (the real and imaginary parts of one complex
   // row transform, kept interleaved); Gy: rows of du/dy
@@ -334,8 +385,11 @@ __global__ __launch_bounds__(NT) void adj_kernel(AdjArgs<T> a) {
     const int y0 = it.band * a.band_rows;   // fine row of band-local row 0
 
     // columns of H and of i ky H, inverse transformed along y; keep the band rows
+    T *st = sm + L.st_off;
+    const T two_lam = a.keep ? T(2.0 * (a.lam ? a.lam[it.cell] : 1.0)) : T(1);
+    stage_spectrum<T, NT>(a, gc, it.cell, st);
     for (int pass = 0; pass < 2; ++pass) {
-      load_columns<T, NT>(a, gc, it.cell, ws, L.cpitch, pass == 1);
+      load_columns<T, NT>(a, st, two_lam, ws, L.cpitch, pass == 1);
       fft_batch<true, NT, T>(g.n2, per, a.tw2, [&](int q) {
         ColAcc<T> acc;
         acc.base = ws + 2 * q;
@@ -466,7 +520,7 @@ int choose_bands(const Geom &g, int W, size_t elem, size_t lds_max, int *band_ro
   for (int B = 1; B <= g.n2 / 2; B <<= 1) {
     const int R = g.n2 / B;
     if (R < 2) break;
-    const AdjLayout L = adj_layout(g, W, R);
+    const AdjLayout L = adj_layout(g, W, R, elem);
     const size_t bytes = L.total * elem;
     if (bytes <= lds_max) {
       *band_rows = R;
@@ -540,7 +594,7 @@ enufft_status adj_prepare(enufft_plan_t p) {
   for (int m = p->adj_band_mult; m > 1 && p->geom.n2 / (B * 2) >= 2; m >>= 1) {
     B *= 2;
     p->adj_band_rows = p->geom.n2 / B;
-    p->adj_lds = adj_layout(p->geom, p->W, p->adj_band_rows).total * p->elem;
+    p->adj_lds = adj_layout(p->geom, p->W, p->adj_band_rows, p->elem).total * p->elem;
   }
   p->adj_bands = B;
   int per_cu = 0;

@@ -68,16 +68,22 @@ __device__ __forceinline__ void spread_point(const FwdArgs<T> &a, double *grid, 
 // Runs of consecutive points.  Each thread takes K = 4 consecutive points (one
 // 16-byte load per array).  When their footprints start within two rows and
 // three columns of each other -- the usual case for points stored in raster
-// order, several per fine-grid cell -- their contributions are summed in a
-// (W + 1) x (W + 2) register window and the window is added to the grid once,
-// which cuts the LDS atomics per point and spreads neighbouring lanes apart.
+// order, several per fine-grid cell -- their contributions are summed over a
+// (W + 1) x (W + 2) window in registers and each window cell is added to the
+// grid once, which cuts the LDS atomics per point and spreads neighbouring
+// lanes apart.
 // Groups that do not fit one window are deferred by the caller.
 constexpr int RUN_K = 4, RUN_SX = 2, RUN_SY = 1;
 
-// Geometry of one group: footprint origins, the in-cell offsets v = i0 - t + W/2
-// (all the taps need) and the window origin.
+// Geometry of one group: the in-cell offsets v = i0 - t + W/2 (all the taps
+// need), each point's shift against the window origin and the window origin.
+//
+// A lane with rev set walks its window's columns from the last to the first
+// (see spread_item).  It takes the x taps mirrored, which for the even kernel
+// is the same as evaluating them at 1 - v, and counts its column shifts from
+// the window's far edge, so the column loop below is the same for every lane.
 struct RunGeom {
-  int ix[RUN_K], iy[RUN_K];
+  int sx[RUN_K], sy[RUN_K];
   float vx[RUN_K], vy[RUN_K];
   int cmin, rmin;
   bool fits, any;
@@ -85,91 +91,94 @@ struct RunGeom {
 
 template <typename T, int W>
 __device__ __forceinline__ RunGeom run_geom(const FwdArgs<T> &a, const float (&xs)[RUN_K], const float (&ys)[RUN_K],
-                                            const float (&cs)[RUN_K]) {
+                                            const float (&cs)[RUN_K], bool rev) {
   const float halfw = float(W) / 2.0f;
   RunGeom rg;
+  int ix[RUN_K], iy[RUN_K];
   int cmax = INT_MIN, rmax = INT_MIN;
   rg.cmin = INT_MAX; rg.rmin = INT_MAX;
 #pragma unroll
   for (int k = 0; k < RUN_K; ++k) {
     const FineCoord<float> fx = fine_coord<float>(xs[k], a.s1_hi, a.s1_lo, halfw);
     const FineCoord<float> fy = fine_coord<float>(ys[k], a.s2_hi, a.s2_lo, halfw);
-    rg.ix[k] = fx.i0; rg.iy[k] = fy.i0;
-    rg.vx[k] = tap_v(fx, halfw); rg.vy[k] = tap_v(fy, halfw);
+    ix[k] = fx.i0; iy[k] = fy.i0;
+    const float vx = tap_v(fx, halfw);
+    rg.vx[k] = rev ? 1.0f - vx : vx;
+    rg.vy[k] = tap_v(fy, halfw);
     if (cs[k] != 0.0f) {
-      rg.cmin = min(rg.cmin, rg.ix[k]); cmax = max(cmax, rg.ix[k]);
-      rg.rmin = min(rg.rmin, rg.iy[k]); rmax = max(rmax, rg.iy[k]);
+      rg.cmin = min(rg.cmin, ix[k]); cmax = max(cmax, ix[k]);
+      rg.rmin = min(rg.rmin, iy[k]); rmax = max(rmax, iy[k]);
     }
   }
   rg.any = rg.rmin != INT_MAX;   // some point inside the cell window
   rg.fits = !rg.any || (cmax - rg.cmin <= RUN_SX && rmax - rg.rmin <= RUN_SY);
+#pragma unroll
+  for (int k = 0; k < RUN_K; ++k) {
+    // points with c = 0 may lie anywhere: their shifts then match no column
+    // and they add nothing
+    const int d = ix[k] - rg.cmin;
+    rg.sx[k] = rev ? RUN_SX - d : d;
+    rg.sy[k] = iy[k] - rg.rmin;
+  }
   return rg;
 }
 
-// Add point k of a fitting group to the window.  Every point enters,
-// branch-free: one with c = 0 (outside the cell window) contributes exact
-// zeros, and its taps stay finite because the tap offsets are clamped to the
-// kernel's interval.  Point 0 initialises the window.
-template <typename T, int W, int P>
-__device__ __forceinline__ void run_add_point(const FwdArgs<T> &a, const RunGeom &rg, int k, float c,
-                                              float (&acc)[W + RUN_SY][W + RUN_SX]) {
-  constexpr int WC = W + RUN_SX, WR = W + RUN_SY;
-  float kx[W], ky[W];
-  if constexpr (P > 0) {
-    es_taps_poly_v<W>(rg.vx[k], a.es, kx);
-    es_taps_poly_v<W>(rg.vy[k], a.es, ky);
-  } else if (a.es.on) {
-    es_taps_poly_v<W>(rg.vx[k], a.es, kx);
-    es_taps_poly_v<W>(rg.vy[k], a.es, ky);
-  } else {
-    es_taps_exact_v<W>(rg.vx[k], a.beta, kx);
-    es_taps_exact_v<W>(rg.vy[k], a.beta, ky);
-  }
-#pragma unroll
-  for (int d = 0; d < W; ++d) ky[d] *= c;
-  const int sx = rg.ix[k] - rg.cmin, sy = rg.iy[k] - rg.rmin;
-  float KX[WC], KY[WR];
-#pragma unroll
-  for (int q = 0; q < WC; ++q) {
-    float v = 0.0f;
-#pragma unroll
-    for (int s = 0; s <= RUN_SX; ++s)
-      if (q - s >= 0 && q - s < W) v = (sx == s) ? kx[q - s] : v;
-    KX[q] = v;
-  }
-#pragma unroll
-  for (int r = 0; r < WR; ++r) {
-    float v = 0.0f;
-#pragma unroll
-    for (int s = 0; s <= RUN_SY; ++s)
-      if (r - s >= 0 && r - s < W) v = (sy == s) ? ky[r - s] : v;
-    KY[r] = v;
-  }
-#pragma unroll
-  for (int r = 0; r < WR; ++r)
-#pragma unroll
-    for (int q = 0; q < WC; ++q) acc[r][q] = (k == 0) ? KY[r] * KX[q] : fmaf(KY[r], KX[q], acc[r][q]);
-}
-
-// Add window columns [q0, q1) to the grid (cells outside every footprint add
-// zero; no per-cell branches).  With rev the columns go out mirrored, so two
+// Spread one fitting group: the (W + RUN_SY) x (W + RUN_SX) window of the
+// summed footprints goes to the grid one column at a time.  Each column is
+// formed in registers from the four points' taps (every point enters,
+// branch-free: one with c = 0 contributes exact zeros, and its taps stay finite
+// because the offsets are clamped to the kernel's interval) and added with
+// one LDS atomic per row, so the adds of a column overlap the arithmetic of
+// the next.  With rev the columns go out from the last to the first, so two
 // lanes whose windows start at the same cell never add to one address in the
 // same instruction.
-template <int W, int P>
-__device__ __forceinline__ void run_flush_cols(const Geom &g, double *grid, const float (&acc)[W + RUN_SY][W + RUN_SX],
-                                               int cmin, int rmin, bool rev, int q0, int q1) {
+template <typename T, int W, int P>
+__device__ __forceinline__ void run_spread(const FwdArgs<T> &a, double *grid, const RunGeom &rg,
+                                           const float (&cs)[RUN_K], bool rev) {
   constexpr int WC = W + RUN_SX, WR = W + RUN_SY;
-  const int pitch = grid_pitch<P>(g);
-  double *rowp = grid + (rmin & (g.n2 - 1)) * pitch;
+  const Geom &g = a.g;
+  float kx[RUN_K][W], KY[RUN_K][WR];
 #pragma unroll
-  for (int q = q0; q < q1; ++q) {
-    const int qs = rev ? WC - 1 - q : q;
-    double *cp = rowp + ((cmin + qs) & (g.n1 - 1));
+  for (int k = 0; k < RUN_K; ++k) {
+    float ky[W];
+    if constexpr (P > 0) {
+      es_taps_poly_v<W>(rg.vx[k], a.es, kx[k]);
+      es_taps_poly_v<W>(rg.vy[k], a.es, ky);
+    } else if (a.es.on) {
+      es_taps_poly_v<W>(rg.vx[k], a.es, kx[k]);
+      es_taps_poly_v<W>(rg.vy[k], a.es, ky);
+    } else {
+      es_taps_exact_v<W>(rg.vx[k], a.beta, kx[k]);
+      es_taps_exact_v<W>(rg.vy[k], a.beta, ky);
+    }
 #pragma unroll
     for (int r = 0; r < WR; ++r) {
-      const float v = rev ? acc[r][WC - 1 - q] : acc[r][q];
-      __hip_atomic_fetch_add(cp + r * pitch, (double)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      float v = 0.0f;
+#pragma unroll
+      for (int s = 0; s <= RUN_SY; ++s)
+        if (r - s >= 0 && r - s < W) v = (rg.sy[k] == s) ? ky[r - s] : v;
+      KY[k][r] = v * cs[k];
     }
+  }
+  const int pitch = grid_pitch<P>(g);
+  double *rowp = grid + (rg.rmin & (g.n2 - 1)) * pitch;
+  const int c0 = rev ? rg.cmin + WC - 1 : rg.cmin, dc = rev ? -1 : 1;
+#pragma unroll
+  for (int j = 0; j < WC; ++j) {
+    float col[WR];
+#pragma unroll
+    for (int k = 0; k < RUN_K; ++k) {
+      float xv = 0.0f;
+#pragma unroll
+      for (int s = 0; s <= RUN_SX; ++s)
+        if (j - s >= 0 && j - s < W) xv = (rg.sx[k] == s) ? kx[k][j - s] : xv;
+#pragma unroll
+      for (int r = 0; r < WR; ++r) col[r] = (k == 0) ? KY[k][r] * xv : fmaf(KY[k][r], xv, col[r]);
+    }
+    double *cp = rowp + ((c0 + dc * j) & (g.n1 - 1));
+#pragma unroll
+    for (int r = 0; r < WR; ++r)
+      __hip_atomic_fetch_add(cp + r * pitch, (double)col[r], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
   }
 }
 
@@ -244,11 +253,10 @@ __device__ __forceinline__ void spread_item(const FwdArgs<T> &a, double *grid, i
     const int64_t g0 = body0 / RUN_K, q1 = body1 / RUN_K;
     int64_t q = g0 + lane_off;
     int nq = 0;   // queued groups (the same in every lane)
-    constexpr int WC = W + RUN_SX, WR = W + RUN_SY;
-    // Loads run two blocks ahead in three register buffers (the loop is
-    // unrolled by three so no buffer is copied and the compiler waits only
-    // for the block about to be used): with one workgroup per CU, this is what
-    // keeps enough HBM requests in flight.
+    // With 512 threads, loads run two blocks ahead in three register buffers
+    // (the loop is unrolled by three so no buffer is copied and the compiler
+    // waits only for the block about to be used): with one workgroup per CU,
+    // this is what keeps enough HBM requests in flight.
     // Loads are unconditional (control flow around them makes the compiler
     // wait for every load in flight); past the end they re-read the last group.
     auto load = [&](V &xb, V &yb, V &hb, V &wb, int64_t qq) {
@@ -262,14 +270,9 @@ __device__ __forceinline__ void spread_item(const FwdArgs<T> &a, double *grid, i
 #pragma unroll
       for (int k = 0; k < RUN_K; ++k)
         cs[k] = live ? (&wv.x)[k] * (&hv.x)[k] * hann_w(a.window_kind, xs[k], ys[k], cx, cy, R, pr) : 0.0f;
-      const RunGeom rg = run_geom<T, W>(a, xs, ys, cs);
+      const RunGeom rg = run_geom<T, W>(a, xs, ys, cs, rev);
       const bool defer = live && !rg.fits;
-      if (live && rg.any && rg.fits) {
-        float acc[WR][WC];
-#pragma unroll
-        for (int k = 0; k < RUN_K; ++k) run_add_point<T, W, P>(a, rg, k, cs[k], acc);
-        run_flush_cols<W, P>(a.g, grid, acc, rg.cmin, rg.rmin, rev, 0, WC);
-      }
+      if (live && rg.any && rg.fits) run_spread<T, W, P>(a, grid, rg, cs, rev);
       const uint64_t m = __ballot(defer);
       if (m != 0) {
         if (defer) {
@@ -288,18 +291,30 @@ __device__ __forceinline__ void spread_item(const FwdArgs<T> &a, double *grid, i
         }
       }
     };
-    V x0{}, y0{}, h0{}, w0{}, x1{}, y1{}, h1{}, w1{}, x2{}, y2{}, h2{}, w2{};
-    if (q1 > g0) {
-      load(x0, y0, h0, w0, q);
-      load(x1, y1, h1, w1, q + NT);
-    }
-    for (int64_t qb = g0; qb < q1; qb += 3 * NT, q += 3 * NT) {
-      load(x2, y2, h2, w2, q + 2 * NT);
-      step(x0, y0, h0, w0, q);
-      load(x0, y0, h0, w0, q + 3 * NT);
-      step(x1, y1, h1, w1, q + NT);
-      load(x1, y1, h1, w1, q + 4 * NT);
-      step(x2, y2, h2, w2, q + 2 * NT);
+    V x0{}, y0{}, h0{}, w0{}, x1{}, y1{}, h1{}, w1{};
+    if constexpr (NT >= 1024) {
+      // four waves per SIMD hide the load latency with one block in flight
+      if (q1 > g0) load(x0, y0, h0, w0, q);
+      for (int64_t qb = g0; qb < q1; qb += 2 * NT, q += 2 * NT) {
+        load(x1, y1, h1, w1, q + NT);
+        step(x0, y0, h0, w0, q);
+        load(x0, y0, h0, w0, q + 2 * NT);
+        step(x1, y1, h1, w1, q + NT);
+      }
+    } else {
+      V x2{}, y2{}, h2{}, w2{};
+      if (q1 > g0) {
+        load(x0, y0, h0, w0, q);
+        load(x1, y1, h1, w1, q + NT);
+      }
+      for (int64_t qb = g0; qb < q1; qb += 3 * NT, q += 3 * NT) {
+        load(x2, y2, h2, w2, q + 2 * NT);
+        step(x0, y0, h0, w0, q);
+        load(x0, y0, h0, w0, q + 3 * NT);
+        step(x1, y1, h1, w1, q + NT);
+        load(x1, y1, h1, w1, q + 4 * NT);
+        step(x2, y2, h2, w2, q + 2 * NT);
+      }
     }
     if (nq > 0) {
       wave_lds_sync();
