@@ -150,21 +150,56 @@ __device__ __forceinline__ void wave_sort_desc(double (&e)[R], int lane) {
   }
 }
 
-// Energy of unit u (FP64; products of FP32 values are exact in FP64).
-// The same arithmetic serves the sort (unit order) and the keep pass (mode
-// order), so a unit's energy is bit-identical in both.  Loads are
-// unconditional (a missing partner reads the representative and is masked).
+// Energy of unit u (FP64; products of FP32 values are exact in FP64) from its
+// loaded coefficients and mode weights (1 without weights: the product by 1
+// is exact).  The same arithmetic serves the sort (unit order), the tie
+// ranking and the keep pass (mode order), so a unit's energy is bit-identical
+// in all three.  Loads are unconditional (a missing partner reads the
+// representative and is masked).
+template <typename C>
+__device__ __forceinline__ double pair_energy_v(const C fr, const C fp, double wr, double wp, bool partner) {
+  const double e = ((double)fr.x * (double)fr.x + (double)fr.y * (double)fr.y) * wr;
+  const double ep = ((double)fp.x * (double)fp.x + (double)fp.y * (double)fp.y) * wp;
+  return partner ? e + ep : e;
+}
+
 template <typename C>
 __device__ __forceinline__ double pair_energy(const EmsArgs &a, const C *f, int rep, int partner) {
   const int pq = partner >= 0 ? partner : rep;
-  const C fr = f[rep], fp = f[pq];
-  double e = (double)fr.x * (double)fr.x + (double)fr.y * (double)fr.y;
-  double ep = (double)fp.x * (double)fp.x + (double)fp.y * (double)fp.y;
-  if (a.mode_weight) {
-    e *= a.mode_weight[rep];
-    ep *= a.mode_weight[pq];
+  const double wr = a.mode_weight ? a.mode_weight[rep] : 1.0, wp = a.mode_weight ? a.mode_weight[pq] : 1.0;
+  return pair_energy_v<C>(f[rep], f[pq], wr, wp, partner >= 0);
+}
+
+// The energies of n units (or of the units of n modes) with all loads of the
+// batch issued before any is used: member indices first, then coefficients,
+// then (with mode weights) the weights.  reps[i] < 0 marks an entry with no
+// unit (its energy is returned as 0).
+template <typename C, int N>
+__device__ __forceinline__ void batch_energy(const EmsArgs &a, const C *f, const int (&reps)[N],
+                                             const int (&partners)[N], double (&e)[N]) {
+  C fr[N], fp[N];
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    const int rep = reps[i] >= 0 ? reps[i] : 0;
+    fr[i] = f[rep];
+    fp[i] = f[partners[i] >= 0 ? partners[i] : rep];
   }
-  return partner >= 0 ? e + ep : e;
+  if (a.mode_weight) {
+    double wr[N], wp[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      const int rep = reps[i] >= 0 ? reps[i] : 0;
+      wr[i] = a.mode_weight[rep];
+      wp[i] = a.mode_weight[partners[i] >= 0 ? partners[i] : rep];
+    }
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+      e[i] = reps[i] >= 0 ? pair_energy_v<C>(fr[i], fp[i], wr[i], wp[i], partners[i] >= 0) : 0.0;
+  } else {
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+      e[i] = reps[i] >= 0 ? pair_energy_v<C>(fr[i], fp[i], 1.0, 1.0, partners[i] >= 0) : 0.0;
+  }
 }
 
 // Workgroup-wide sum / integer sum / integer min / exclusive scan for NW
@@ -261,12 +296,27 @@ __global__ __launch_bounds__(64 * NW) void ems_kernel(EmsArgs a) {
   // every sum below, and equal values are interchangeable.
   double e[R];
   double t1 = 0.0, t2 = 0.0;
+  // batches of EB units: few memory latencies per thread, few live registers
+  // (the kernel's register peak sets how many workgroups share a CU)
+  constexpr int EB = R < 4 ? R : 4;
+  static_assert(R % EB == 0, "energy batches must divide R");
+#pragma unroll
+  for (int r0 = 0; r0 < R; r0 += EB) {
+    int reps[EB], partners[EB];
+#pragma unroll
+    for (int i = 0; i < EB; ++i) {
+      const int u = t * R + r0 + i;
+      const int2 un = a.units[u < J ? u : max(J - 1, 0)];
+      reps[i] = u < J ? un.x : -1;
+      partners[i] = un.y;
+    }
+    double eb[EB];
+    batch_energy<C, EB>(a, f, reps, partners, eb);
+#pragma unroll
+    for (int i = 0; i < EB; ++i) e[r0 + i] = eb[i];
+  }
 #pragma unroll
   for (int r = 0; r < R; ++r) {
-    const int u = t * R + r;
-    const int2 un = a.units[u < J ? u : max(J - 1, 0)];
-    const double v = pair_energy<C>(a, f, un.x, un.y);
-    e[r] = u < J ? v : 0.0;
     t1 += e[r];
     t2 += e[r] * e[r];
   }
@@ -408,20 +458,44 @@ __global__ __launch_bounds__(64 * NW) void ems_kernel(EmsArgs a) {
     __syncthreads();
   }
 
-  // modes (coalesced): keep flags and the retained power
+  // modes (coalesced): keep flags and the retained power.  Batches of UK modes
+  // per thread: all loads of a batch come before its stores (the byte stores
+  // may alias the coefficients as far as the compiler knows, so a store
+  // between loads would serialise them), so a batch costs about two memory
+  // latencies instead of two per mode.
   double pw = 0.0;
   uint8_t *kout = a.keep + cell * a.M;
-  for (int m = t; m < a.M; m += NT) {
-    const int4 mu = a.mode_unit[m];
-    uint8_t v = 0;
-    if (kstar > 0 && mu.x >= 0) {
-      const double eu = pair_energy<C>(a, f, mu.x, mu.y);
-      v = eu > eth || (eu == eth && (!split_ties || tie_kept[mu.z]));
+  constexpr int UK = 4;
+  for (int m0 = t; m0 < a.M; m0 += UK * NT) {
+    uint8_t v[UK];
+    int4 mu[UK];
+    int reps[UK], partners[UK];
+#pragma unroll
+    for (int u = 0; u < UK; ++u) {
+      const int m = m0 + u * NT;
+      mu[u] = a.mode_unit[m < a.M ? m : a.M - 1];
+      reps[u] = m < a.M ? mu[u].x : -1;
+      partners[u] = mu[u].y;
     }
-    kout[m] = v;
-    if (v) {
-      const C fr = f[m];
-      pw += (double)fr.x * (double)fr.x + (double)fr.y * (double)fr.y;
+    double eu[UK];
+    batch_energy<C, UK>(a, f, reps, partners, eu);
+    C fm[UK];
+#pragma unroll
+    for (int u = 0; u < UK; ++u) {
+      const int m = m0 + u * NT;
+      fm[u] = f[m < a.M ? m : a.M - 1];
+    }
+#pragma unroll
+    for (int u = 0; u < UK; ++u) {
+      const bool keep = reps[u] >= 0 && kstar > 0 &&
+                        (eu[u] > eth || (eu[u] == eth && (!split_ties || tie_kept[mu[u].z])));
+      v[u] = keep;
+      if (keep) pw += (double)fm[u].x * (double)fm[u].x + (double)fm[u].y * (double)fm[u].y;
+    }
+#pragma unroll
+    for (int u = 0; u < UK; ++u) {
+      const int m = m0 + u * NT;
+      if (m < a.M) kout[m] = v[u];
     }
   }
   const double P = block_sum<NW>(pw, redd, wave);
