@@ -290,7 +290,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--shuffled", action="store_true", help="random point order within each cell")
-    ap.add_argument("--autotune", action="store_true", help="plan with the autotuner")
+    ap.add_argument("--no-autotune", dest="autotune", action="store_false",
+                    help="plan with the default launch shape instead of the autotuner's choice (c3)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MB",
                     help="after timing, run one plain device copy of this size (for profiler byte counters)")
     ap.add_argument("--summarize", metavar="DIR", help="write profiles/ summaries from rocprofv3 CSVs in DIR")
