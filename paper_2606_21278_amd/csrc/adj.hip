@@ -159,43 +159,48 @@ __device__ void extract_band(const Geom &g, const T *ws, int cpitch, T *db, int 
   __syncthreads();
 }
 
-// The grids' rows from the transform's output order into natural column order,
-// with columns 0 .. W - 2 repeated at n1 .. n1 + W - 2.  Each wave permutes
-// whole rows of the three fields (the interleaved (u, du/dx) pairs of Guv and
-// du/dy in Gy) on its own: it reads a row's elements into registers, then
-// writes them back in natural order (one wave's LDS accesses complete in
-// order, and the writes depend on the reads), so no workgroup barrier is
-// needed until the end.
-template <typename T>
-__device__ __forceinline__ T *adj_field(T *Guv, T *Gy, int f, int e) {
-  return f == 2 ? Gy + e : Guv + 2 * e + f;
+// Second step of the row transforms, writing natural column order.  Item k1
+// of a row computes bins k1 + A k2 (k2 = 0 .. B - 1) from positions k1 B + b
+// and stores bin k at column k, and again at n1 + k for k < W - 1 (the first
+// W - 1 columns repeated after the last, so a footprint's W taps in a row are
+// W consecutive elements).  The store lands on positions other items of the
+// same row still read, so the A items of a row must be one wave's lanes: a
+// wave's LDS accesses complete in issue order and every item loads before it
+// stores.  With A | 64 and 64 | NT, the items q A .. q A + A - 1 of the
+// batched loop below always share a wave.
+template <int A, int B, typename T, typename Acc>
+__device__ __forceinline__ void row_step2_natural(const Acc &acc, int k1, int n, int wrap) {
+  T re[B], im[B];
+#pragma unroll
+  for (int b = 0; b < B; ++b) acc.load(k1 * B + b, re[b], im[b]);
+  dft_reg<B, true, T>(re, im);
+#pragma unroll
+  for (int k2 = 0; k2 < B; ++k2) {
+    const int k = k1 + A * k2;
+    acc.store(k, re[k2], im[k2]);
+    if (k < wrap) acc.store(n + k, re[k2], im[k2]);
+  }
 }
 
-template <typename T, int W, int NT>
-__device__ void rows_to_natural(T *Guv, T *Gy, int rows, int n1, int apitch) {
-  constexpr int NW = NT / 64;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  // 3 n1 elements per row, up to 3 * 128 / 64 = 6 per lane
-  const int per_lane = (3 * n1 + 63) / 64;
-  const int ln1 = 31 - __builtin_clz(n1);
-  for (int r = wave; r < rows; r += NW) {
-    T v[6];
-#pragma unroll
-    for (int q = 0; q < 6; ++q) {
-      const int e = lane + 64 * q;
-      if (q < per_lane && e < 3 * n1) {
-        const int f = e >> ln1, c = e & (n1 - 1);
-        v[q] = *adj_field(Guv, Gy, f, r * apitch + fft_pos(c, n1));
-      }
-    }
-#pragma unroll
-    for (int q = 0; q < 6; ++q) {
-      const int e = lane + 64 * q;
-      if (q < per_lane && e < 3 * n1) {
-        const int f = e >> ln1, c = e & (n1 - 1);
-        *adj_field(Guv, Gy, f, r * apitch + c) = v[q];
-        if (c < W - 1) *adj_field(Guv, Gy, f, r * apitch + n1 + c) = v[q];
-      }
+// The batched inverse row transforms: step 1 through make1(q) (forming the
+// spectra), step 2 in place through make2(q) into natural column order.
+template <int NT, typename T, typename Make1, typename Make2>
+__device__ __forceinline__ void row_ifft_natural(int n, int count, const T *tw, int wrap, const Make1 &make1,
+                                                 const Make2 &make2) {
+  static_assert(NT % 64 == 0, "whole waves");
+  const int A = fft_A(n), B = fft_B(n), la = fft_logA(n), lb = fft_logB(n);
+  for (int it = threadIdx.x; it < count * B; it += NT) {
+    const int q = it >> lb, b = it & (B - 1);
+    fft4_dispatch<true, 1, T>(n, make1(q), b, tw);
+  }
+  __syncthreads();
+  for (int it = threadIdx.x; it < count * A; it += NT) {
+    const int q = it >> la, k1 = it & (A - 1);
+    switch (n) {
+      case 16: row_step2_natural<4, 4, T>(make2(q), k1, n, wrap); break;
+      case 32: row_step2_natural<8, 4, T>(make2(q), k1, n, wrap); break;
+      case 64: row_step2_natural<8, 8, T>(make2(q), k1, n, wrap); break;
+      default: row_step2_natural<16, 8, T>(make2(q), k1, n, wrap); break;
     }
   }
   __syncthreads();
@@ -404,13 +409,14 @@ __global__ __launch_bounds__(NT) void adj_kernel(AdjArgs<T> a) {
     // the du/dy row pairs, Z(k) = Dy_r(k) + i Dy_r+1(k), in Gy; the bins k < 0
     // are the conjugates of column -k.  The first step of the transform reads
     // the spectra straight from the band's column data (no separate pass
-    // writing them into the grids); band rows = band_rows + W is even, so the
-    // du/dy rows pair up exactly.
+    // writing them into the grids), the second writes natural column order with
+    // the wrap-around columns; band rows = band_rows + W is even, so the du/dy
+    // rows pair up exactly.
     const int n1 = g.n1;
     const int ny_pairs = L.rows / 2;
     const int K1 = g.K1;
-    fft_batch2<true, NT, T>(
-        n1, L.rows + ny_pairs, a.tw1,
+    row_ifft_natural<NT, T>(
+        n1, L.rows + ny_pairs, a.tw1, W - 1,
         [&](int q) {
           RowSpecAcc<T> acc;
           acc.db = q < L.rows ? db0 : db1;
@@ -443,7 +449,6 @@ __global__ __launch_bounds__(NT) void adj_kernel(AdjArgs<T> a) {
           }
           return acc;
         });
-    rows_to_natural<T, W, NT>(Guv, Gy, L.rows, n1, pitch);
 
     // Gather at the points of this band.
     const double *wn = a.windows + 3 * (int64_t)it.cell;
