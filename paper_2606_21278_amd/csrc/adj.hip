@@ -98,63 +98,120 @@ __device__ void stage_spectrum(const AdjArgs<T> &a, const T *gc, int cell, T *st
   __syncthreads();
 }
 
-// Fill the column workspace with the Hermitian, pre-corrected spectrum for
-// columns kx = 0..K1 over all n2 bins (from the staged copy; two_lam is the
-// retained-power factor 2 lam_c, or 1 without a keep mask); with yderiv,
-// multiplied by i ky.
-template <typename T, int NT>
-__device__ void load_columns(const AdjArgs<T> &a, const T *st, T two_lam, T *ws, int cpitch, bool yderiv) {
-  const Geom &g = a.g;
-  const int per = g.K1 + 1;
-  const int M = g.N1 * g.N2;
-  const int hi1 = g.lo1 + g.N1 - 1, hi2 = g.lo2 + g.N2 - 1;
-  const T *sf = st;
-  const T *sdx = st + 2 * M, *sdy = sdx + per;
-  const uint8_t *kp = a.keep ? reinterpret_cast<const uint8_t *>(sdy + g.K2 + 1) : nullptr;
-  // retained-power cotangent g = 2 lam_c f keep, formed on the fly
-  for (int it = threadIdx.x; it < g.n2 * per; it += NT) {
-    const int bin = it / per, kx = it - bin * per;
-    const int ky = bin <= g.n2 / 2 ? bin : bin - g.n2;   // signed frequency of this bin
+// First-step accessor of the column transforms: load(i) forms bin i (fine
+// row, natural order) of column kx of the Hermitian, pre-corrected spectrum
+// from the staged copy: (G(kx, ky) + conj G(-kx, -ky)) / 2 divided by the
+// kernel transform, each term zero outside the mode box, with the
+// retained-power factor two_lam on kept modes (1 without a keep mask); with
+// yderiv, times i ky.  store() writes the column workspace.
+template <typename T>
+struct ColSpecAcc {
+  const T *sf, *sdx, *sdy;
+  const uint8_t *kp;
+  T two_lam;
+  T *col;   // column kx of the workspace (interleaved complex, row pitch cpitch)
+  int cpitch, kx, n2, K2, N1, lo1, lo2, hi1, hi2;
+  bool yderiv;
+  __device__ void load(int bin, T &re, T &im) const {
+    const int ky = bin <= n2 / 2 ? bin : bin - n2;   // signed frequency of this bin
     T hr = 0, hi = 0;
-    if (ky >= -g.K2 && ky <= g.K2) {
+    if (ky >= -K2 && ky <= K2) {
       const T s = sdx[kx] * sdy[ky < 0 ? -ky : ky];
-      // G(kx, ky) and conj G(-kx, -ky), each zero outside the box
-      if (kx <= hi1 && ky >= g.lo2 && ky <= hi2) {
-        const int m = (ky - g.lo2) * g.N1 + (kx - g.lo1);
+      if (kx <= hi1 && ky >= lo2 && ky <= hi2) {
+        const int m = (ky - lo2) * N1 + (kx - lo1);
         const T sc = kp ? (kp[m] ? two_lam : T(0)) : T(1);
         hr += sc * sf[2 * m];
         hi += sc * sf[2 * m + 1];
       }
-      if (-kx >= g.lo1 && -ky >= g.lo2 && -ky <= hi2) {
-        const int m = (-ky - g.lo2) * g.N1 + (-kx - g.lo1);
+      if (-kx >= lo1 && -ky >= lo2 && -ky <= hi2) {
+        const int m = (-ky - lo2) * N1 + (-kx - lo1);
         const T sc = kp ? (kp[m] ? two_lam : T(0)) : T(1);
         hr += sc * sf[2 * m];
         hi -= sc * sf[2 * m + 1];
       }
       hr *= T(0.5) * s;
       hi *= T(0.5) * s;
-      if (yderiv) {   // times i ky
+      if (yderiv) {
         const T t = hr;
         hr = -T(ky) * hi;
         hi = T(ky) * t;
       }
     }
-    ws[bin * cpitch + 2 * kx] = hr;
-    ws[bin * cpitch + 2 * kx + 1] = hi;
+    re = hr;
+    im = hi;
   }
-  __syncthreads();
+  __device__ void store(int i, T re, T im) const {
+    col[i * cpitch] = re;
+    col[i * cpitch + 1] = im;
+  }
+};
+
+// Second step of the column transforms, out of place: item k1 of column kx
+// computes fine rows y = k1 + A k2 and writes those of the band (band row r
+// holds fine row (y0 + r) mod n2, r < rows) to the band spectra db
+// ([row][kx] complex).
+template <int A, int B, typename T>
+__device__ __forceinline__ void col_step2_band(const T *col, int cpitch, int k1, int n2, T *db, int per, int kx,
+                                               int rows, int y0) {
+  T re[B], im[B];
+#pragma unroll
+  for (int b = 0; b < B; ++b) {
+    re[b] = col[(k1 * B + b) * cpitch];
+    im[b] = col[(k1 * B + b) * cpitch + 1];
+  }
+  dft_reg<B, true, T>(re, im);
+#pragma unroll
+  for (int k2 = 0; k2 < B; ++k2) {
+    // band row r, and r + n2 too when the band's halo wraps onto its own
+    // first rows (one band per cell: rows = n2 + W)
+    const int r = (k1 + A * k2 - y0) & (n2 - 1);
+    if (r < rows) {
+      db[2 * (r * per + kx)] = re[k2];
+      db[2 * (r * per + kx) + 1] = im[k2];
+    }
+    if (r + n2 < rows) {
+      db[2 * ((r + n2) * per + kx)] = re[k2];
+      db[2 * ((r + n2) * per + kx) + 1] = im[k2];
+    }
+  }
 }
 
-// Copy the band rows (with halo) of the inverse-transformed columns into db.
+// One column pass: the inverse transforms along y of columns kx = 0..K1 of the
+// spectrum (times i ky with yderiv), formed from the staged copy in the first
+// step and written to the band spectra db by the second.
 template <typename T, int NT>
-__device__ void extract_band(const Geom &g, const T *ws, int cpitch, T *db, int rows, int y0) {
-  const int per = g.K1 + 1;
-  for (int it = threadIdx.x; it < rows * per; it += NT) {
-    const int r = it / per, kx = it - r * per;
-    const int y = (y0 + r) & (g.n2 - 1);
-    const int pos = fft_pos(y, g.n2);
-    db[2 * (r * per + kx)] = ws[pos * cpitch + 2 * kx];
-    db[2 * (r * per + kx) + 1] = ws[pos * cpitch + 2 * kx + 1];
+__device__ void column_pass(const AdjArgs<T> &a, const T *st, T two_lam, T *ws, int cpitch, bool yderiv, T *db,
+                            int rows, int y0) {
+  const Geom &g = a.g;
+  const int per = g.K1 + 1, n2 = g.n2, M = g.N1 * g.N2;
+  const int A = fft_A(n2), B = fft_B(n2), la = fft_logA(n2), lb = fft_logB(n2);
+  ColSpecAcc<T> acc;
+  acc.sf = st;
+  acc.sdx = st + 2 * M;
+  acc.sdy = acc.sdx + per;
+  acc.kp = a.keep ? reinterpret_cast<const uint8_t *>(acc.sdy + g.K2 + 1) : nullptr;
+  acc.two_lam = two_lam;
+  acc.cpitch = cpitch;
+  acc.n2 = n2; acc.K2 = g.K2; acc.N1 = g.N1; acc.lo1 = g.lo1; acc.lo2 = g.lo2;
+  acc.hi1 = g.lo1 + g.N1 - 1; acc.hi2 = g.lo2 + g.N2 - 1;
+  acc.yderiv = yderiv;
+  for (int it = threadIdx.x; it < per * B; it += NT) {
+    const int q = it >> lb, b = it & (B - 1);
+    ColSpecAcc<T> c = acc;
+    c.kx = q;
+    c.col = ws + 2 * q;
+    fft4_dispatch<true, 1, T>(n2, c, b, a.tw2);
+  }
+  __syncthreads();
+  for (int it = threadIdx.x; it < per * A; it += NT) {
+    const int q = it >> la, k1 = it & (A - 1);
+    const T *col = ws + 2 * q;
+    switch (n2) {
+      case 16: col_step2_band<4, 4, T>(col, cpitch, k1, n2, db, per, q, rows, y0); break;
+      case 32: col_step2_band<8, 4, T>(col, cpitch, k1, n2, db, per, q, rows, y0); break;
+      case 64: col_step2_band<8, 8, T>(col, cpitch, k1, n2, db, per, q, rows, y0); break;
+      default: col_step2_band<16, 8, T>(col, cpitch, k1, n2, db, per, q, rows, y0); break;
+    }
   }
   __syncthreads();
 }
@@ -393,16 +450,8 @@ __global__ __launch_bounds__(NT) void adj_kernel(AdjArgs<T> a) {
     T *st = sm + L.st_off;
     const T two_lam = a.keep ? T(2.0 * (a.lam ? a.lam[it.cell] : 1.0)) : T(1);
     stage_spectrum<T, NT>(a, gc, it.cell, st);
-    for (int pass = 0; pass < 2; ++pass) {
-      load_columns<T, NT>(a, st, two_lam, ws, L.cpitch, pass == 1);
-      fft_batch<true, NT, T>(g.n2, per, a.tw2, [&](int q) {
-        ColAcc<T> acc;
-        acc.base = ws + 2 * q;
-        acc.stride = L.cpitch;
-        return acc;
-      });
-      extract_band<T, NT>(g, ws, L.cpitch, pass == 0 ? db0 : db1, L.rows, y0);
-    }
+    for (int pass = 0; pass < 2; ++pass)
+      column_pass<T, NT>(a, st, two_lam, ws, L.cpitch, pass == 1, pass == 0 ? db0 : db1, L.rows, y0);
 
     // Row stage, one batch of inverse transforms: the (u, du/dx) rows, spectrum
     // Z(k) = D(k) + i (i k D(k)) = (1 - k) D(k), stored interleaved in Guv, and

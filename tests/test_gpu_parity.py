@@ -241,6 +241,28 @@ def test_adjoint_matches_oracle_vjp(prec):
     assert max(eh, ex, ey) <= TOL[prec]
 
 
+@pytest.mark.parametrize("prec,n_modes", [("f32", (16, 16)), ("f32", (32, 32)), ("f64", (17, 9)),
+                                          ("f64", (32, 32))])
+def test_adjoint_small_mode_boxes(prec, n_modes):
+    """Small and odd mode boxes: the whole fine grid (with its wrapped halo rows) is
+    one row band, or a few; checked against the oracle's analytic VJP."""
+    b = synth.uniform_box(counts=[3000, 1, 0, 800], n_modes=n_modes, precision=prec, window_radius=2.5, seed=5)
+    b.eps = 1e-10 if prec == "f64" else 1e-5
+    inp = oracle.batch_inputs(b)
+    g = np.random.default_rng(11).standard_normal((b.n_cells, n_modes[1], n_modes[0], 2)) @ np.array([1.0, 1j])
+    gh, gx, gy = oracle.type1_vjp(inp["offsets"], inp["x"], inp["y"], inp["h"], inp["w"], inp["windows"],
+                                  inp["n_modes"], g)
+    gb = gpu_batch(b)
+    plan = make_plan(gb)
+    fbar = torch.from_numpy(g).to("cuda:0", plan.cdtype)
+    ah, ax, ay = plan.adjoint(gb.x, gb.y, gb.h, gb.w, fbar)
+    info = plan.info()
+    print(prec, n_modes, "bands", info["adj_bands"], flush=True)
+    errs = [rel_l2(ah.cpu().numpy(), gh), rel_l2(ax.cpu().numpy(), gx), rel_l2(ay.cpu().numpy(), gy)]
+    print("adjoint rel-l2 h %.3e x %.3e y %.3e" % tuple(errs), flush=True)
+    assert max(errs) <= TOL[prec]
+
+
 def test_retained_power_autograd_fp32():
     b = synth.config1(count_scale=0.004, n_cells=16)
     gb = gpu_batch(b)
