@@ -27,6 +27,7 @@ struct AdjLayout {
   int cpitch;     // column-workspace pitch (elements) = 2 (K1 + 1) + 2
   size_t g_off, gx_off, gy_off, db0_off, db1_off, ws_off;   // element offsets
   size_t st_off;  // staged cell spectrum, deconvolution factors and keep bytes
+  size_t tw_off;  // twiddles of the row (n1) and column (n2) transforms, interleaved complex
   size_t total;   // elements
 };
 
@@ -54,7 +55,8 @@ __host__ __device__ inline AdjLayout adj_layout(const Geom &g, int W, int band_r
   L.st_off = ws;
   L.db0_off = std::max(3 * gsz, ws + adj_stage_elems(g, elem));
   L.db1_off = L.db0_off + (size_t)L.rows * (g.K1 + 1) * 2;
-  L.total = L.db1_off + (size_t)L.rows * (g.K1 + 1) * 2;
+  L.tw_off = L.db1_off + (size_t)L.rows * (g.K1 + 1) * 2;
+  L.total = L.tw_off + 2 * (size_t)(g.n1 + g.n2);
   return L;
 }
 
@@ -180,8 +182,8 @@ __device__ __forceinline__ void col_step2_band(const T *col, int cpitch, int k1,
 // spectrum (times i ky with yderiv), formed from the staged copy in the first
 // step and written to the band spectra db by the second.
 template <typename T, int NT>
-__device__ void column_pass(const AdjArgs<T> &a, const T *st, T two_lam, T *ws, int cpitch, bool yderiv, T *db,
-                            int rows, int y0) {
+__device__ void column_pass(const AdjArgs<T> &a, const T *st, const T *tw2, T two_lam, T *ws, int cpitch,
+                            bool yderiv, T *db, int rows, int y0) {
   const Geom &g = a.g;
   const int per = g.K1 + 1, n2 = g.n2, M = g.N1 * g.N2;
   const int A = fft_A(n2), B = fft_B(n2), la = fft_logA(n2), lb = fft_logB(n2);
@@ -200,7 +202,7 @@ __device__ void column_pass(const AdjArgs<T> &a, const T *st, T two_lam, T *ws, 
     ColSpecAcc<T> c = acc;
     c.kx = q;
     c.col = ws + 2 * q;
-    fft4_dispatch<true, 1, T>(n2, c, b, a.tw2);
+    fft4_dispatch<true, 1, T>(n2, c, b, tw2);
   }
   __syncthreads();
   for (int it = threadIdx.x; it < per * A; it += NT) {
@@ -434,6 +436,12 @@ __global__ __launch_bounds__(NT) void adj_kernel(AdjArgs<T> a) {
   const bool persistent = a.work_counter != nullptr;
   int64_t idx = a.item_base + blockIdx.x;
   if (!persistent && idx >= a.n_items) return;
+  // the transforms' twiddles stay in LDS for all items of this workgroup (the
+  // barrier at the top of the item loop orders them before first use)
+  T *tw1 = sm + L.tw_off, *tw2 = tw1 + 2 * g.n1;
+  for (int i = threadIdx.x; i < 2 * g.n1; i += NT) tw1[i] = a.tw1[i];
+  for (int i = threadIdx.x; i < 2 * g.n2; i += NT) tw2[i] = a.tw2[i];
+  if (!persistent) __syncthreads();
   for (;;) {
     if (persistent) {
       if (threadIdx.x == 0) s_item = atomicAdd(a.work_counter, 1);
@@ -451,7 +459,7 @@ __global__ __launch_bounds__(NT) void adj_kernel(AdjArgs<T> a) {
     const T two_lam = a.keep ? T(2.0 * (a.lam ? a.lam[it.cell] : 1.0)) : T(1);
     stage_spectrum<T, NT>(a, gc, it.cell, st);
     for (int pass = 0; pass < 2; ++pass)
-      column_pass<T, NT>(a, st, two_lam, ws, L.cpitch, pass == 1, pass == 0 ? db0 : db1, L.rows, y0);
+      column_pass<T, NT>(a, st, tw2, two_lam, ws, L.cpitch, pass == 1, pass == 0 ? db0 : db1, L.rows, y0);
 
     // Row stage, one batch of inverse transforms: the (u, du/dx) rows, spectrum
     // Z(k) = D(k) + i (i k D(k)) = (1 - k) D(k), stored interleaved in Guv, and
@@ -465,7 +473,7 @@ __global__ __launch_bounds__(NT) void adj_kernel(AdjArgs<T> a) {
     const int ny_pairs = L.rows / 2;
     const int K1 = g.K1;
     row_ifft_natural<NT, T>(
-        n1, L.rows + ny_pairs, a.tw1, W - 1,
+        n1, L.rows + ny_pairs, tw1, W - 1,
         [&](int q) {
           RowSpecAcc<T> acc;
           acc.db = q < L.rows ? db0 : db1;
