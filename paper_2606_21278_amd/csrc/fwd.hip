@@ -373,6 +373,67 @@ __device__ __forceinline__ void grid_to_t(double *grid, const Geom &g) {
   }
 }
 
+// Second step of the row-pair transforms with the unpacking of the two real
+// rows' spectra fused in.  Z = FFT(row 2p + i row 2p+1); A(k) = (Z(k) + conj
+// Z(-k)) / 2 is row 2p's spectrum and B(k) = (Z(k) - conj Z(-k)) / 2i is row
+// 2p+1's.  Item k1 computes Z(k1 + A k2) and (1) stores it in transform order,
+// (2) reads the partners Z(-k) of its bins k <= K1, (3) writes A(k) and B(k)
+// to elements 2k, 2k+1 of the two rows.  Steps (2) and (3) touch positions of
+// other items of the same row pair, so those items must be one wave's lanes:
+// a wave's LDS accesses complete in issue order, and every lane finishes each
+// step before any lane starts the next.  With A | 64 and 64 | NT, the items
+// q A .. q A + A - 1 of the loop below always share a wave.
+template <int A, int B, typename T>
+__device__ __forceinline__ void row_step2_unpack(const RowPairAcc<T> &acc, int k1, int n, int K1) {
+  T re[B], im[B];
+#pragma unroll
+  for (int b = 0; b < B; ++b) acc.load(k1 * B + b, re[b], im[b]);
+  dft_reg<B, false, T>(re, im);
+#pragma unroll
+  for (int k2 = 0; k2 < B; ++k2) acc.store(k1 * B + k2, re[k2], im[k2]);
+  T mr[B], mi[B];
+#pragma unroll
+  for (int k2 = 0; k2 < B; ++k2) {
+    const int k = k1 + A * k2;
+    mr[k2] = T(0);
+    mi[k2] = T(0);
+    if (k <= K1) acc.load(fft_pos((n - k) & (n - 1), n), mr[k2], mi[k2]);
+  }
+#pragma unroll
+  for (int k2 = 0; k2 < B; ++k2) {
+    const int k = k1 + A * k2;
+    if (k <= K1) {
+      acc.r0[2 * k] = T(0.5) * (re[k2] + mr[k2]);
+      acc.r0[2 * k + 1] = T(0.5) * (im[k2] - mi[k2]);
+      acc.r1[2 * k] = T(0.5) * (im[k2] + mi[k2]);
+      acc.r1[2 * k + 1] = T(-0.5) * (re[k2] - mr[k2]);
+    }
+  }
+}
+
+// The row stage: forward transforms of the row pairs, unpacked in their
+// second step (see above).
+template <int NT, typename T, typename Make>
+__device__ __forceinline__ void row_fft_unpack(int n, int count, const T *tw, int K1, const Make &make) {
+  static_assert(NT % 64 == 0, "whole waves");
+  const int A = fft_A(n), B = fft_B(n), la = fft_logA(n), lb = fft_logB(n);
+  for (int it = threadIdx.x; it < count * B; it += NT) {
+    const int q = it >> lb, b = it & (B - 1);
+    fft4_dispatch<false, 1, T>(n, make(q), b, tw);
+  }
+  __syncthreads();
+  for (int it = threadIdx.x; it < count * A; it += NT) {
+    const int q = it >> la, k1 = it & (A - 1);
+    switch (n) {
+      case 16: row_step2_unpack<4, 4, T>(make(q), k1, n, K1); break;
+      case 32: row_step2_unpack<8, 4, T>(make(q), k1, n, K1); break;
+      case 64: row_step2_unpack<8, 8, T>(make(q), k1, n, K1); break;
+      default: row_step2_unpack<16, 8, T>(make(q), k1, n, K1); break;
+    }
+  }
+  __syncthreads();
+}
+
 // FFT of the folded real grid G (logical row 0 at G), deconvolution and crop.
 // Row stage: rows are transformed two at a time as one complex row; the
 // needed bins kx = 0..K1 of each real row are unpacked in place into the
@@ -385,36 +446,13 @@ __device__ void fft_deconv_store(const FwdArgs<T> &a, T *G, int cell) {
   const int pitch = g.pitch;
   const int n1 = g.n1, n2 = g.n2;
   const int npairs = n2 / 2;
-  fft_batch<false, NT, T>(n1, npairs, a.tw1, [&](int q) {
+  row_fft_unpack<NT, T>(n1, npairs, a.tw1, g.K1, [&](int q) {
     RowPairAcc<T> acc;
     acc.r0 = G + (2 * q) * pitch;
     acc.r1 = acc.r0 + pitch;
     return acc;
   });
-  // Unpack: Z = FFT(row 2p + i row 2p+1); A(k) = (Z(k) + conj Z(-k)) / 2 is row 2p's
-  // spectrum and B(k) = (Z(k) - conj Z(-k)) / 2i is row 2p+1's.
   const int per = g.K1 + 1;
-  const int ppr = max(1, NT / per);
-  for (int p0 = 0; p0 < npairs; p0 += ppr) {
-    const int it = threadIdx.x;
-    const int p = p0 + it / per, k = it % per;
-    const bool active = (it < ppr * per) && (p < npairs);
-    T ar = 0, ai = 0, br = 0, bi = 0;
-    if (active) {
-      const T *r0 = G + (2 * p) * pitch, *r1 = r0 + pitch;
-      const int pk = fft_pos(k, n1), pm = fft_pos((n1 - k) & (n1 - 1), n1);
-      const T zr = r0[pk], zi = r1[pk], mr = r0[pm], mi = r1[pm];
-      ar = T(0.5) * (zr + mr); ai = T(0.5) * (zi - mi);
-      br = T(0.5) * (zi + mi); bi = T(-0.5) * (zr - mr);
-    }
-    __syncthreads();
-    if (active) {
-      T *r0 = G + (2 * p) * pitch, *r1 = r0 + pitch;
-      r0[2 * k] = ar; r0[2 * k + 1] = ai;
-      r1[2 * k] = br; r1[2 * k + 1] = bi;
-    }
-    __syncthreads();
-  }
   fft_batch<false, NT, T>(n2, per, a.tw2, [&](int q) {
     ColAcc<T> acc;
     acc.base = G + 2 * q;
