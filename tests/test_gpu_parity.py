@@ -107,6 +107,22 @@ def test_config3_cells_raster_and_shuffled(shuffled):
     assert e.max() <= TOL["f32"]
 
 
+@pytest.mark.parametrize("threads", [256, 1024])
+@pytest.mark.parametrize("shuffled", [False, True])
+def test_forward_workgroup_sizes(threads, shuffled, monkeypatch):
+    """The other forward workgroup sizes the autotuner can pick (1024 threads keeps
+    one block of loads in flight instead of two), on C3 cells in both orders."""
+    monkeypatch.setenv("ENUFFT_FWD_THREADS", str(threads))
+    b = synth.config3(n_cells=6, count_scale=0.5, shuffled=shuffled)
+    gb = gpu_batch(b)
+    plan = make_plan(gb)
+    assert plan.info()["fwd_threads"] == threads
+    f = plan.type1(gb.x, gb.y, gb.h, gb.w).cpu().numpy()
+    e = per_cell_rel_l2(f, oracle_f(b.to(dtype=torch.float32)))
+    print("threads", threads, "shuffled", shuffled, "per-cell rel-l2 max %.3e" % e.max(), flush=True)
+    assert e.max() <= TOL["f32"]
+
+
 def test_unaligned_point_arrays():
     """Arrays that are not 16-byte aligned take the point-by-point path; same result."""
     b = synth.config3(n_cells=12, count_scale=0.05)
