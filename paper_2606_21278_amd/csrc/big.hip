@@ -264,8 +264,9 @@ __global__ __launch_bounds__(256) void big_chunk_base_kernel(int *chunk_hist, co
 }
 
 // Scatter, one chunk per workgroup, in sub-chunks that fit LDS: each
-// sub-chunk's tile histogram and its scan, then its points loaded once
-// (coalesced) and staged in LDS in tile order, then copied out with
+// sub-chunk's points loaded once (coalesced, into registers, every load of a
+// thread issued before the first is used), its tile histogram and scan, the
+// points ranked and staged in LDS in tile order, then copied out with
 // consecutive threads on consecutive positions of each tile's segment, so the
 // stores coalesce.  The chunk's start in every tile advances by each
 // sub-chunk's count.  The inverse permutation is written in input order.
@@ -288,27 +289,41 @@ __global__ __launch_bounds__(BIG_SORT_THREADS) void big_scatter_kernel(BigSortAr
   const int64_t e0 = min(a.n, s0 + BIG_SORT_CHUNK);
   const int *base_row = a.chunk_hist + (int64_t)blockIdx.x * a.ntiles;
   for (int i = threadIdx.x; i < a.ntiles; i += blockDim.x) gbase[i] = base_row[i];
+  // each thread holds PER points of a sub-chunk in registers (all loads issued
+  // before the first is used), counts them and then ranks them
+  constexpr int PER = SUB / BIG_SORT_THREADS;
+  static_assert(SUB % BIG_SORT_THREADS == 0, "sub-chunks are whole rounds of the workgroup");
   for (int64_t s = s0; s < e0; s += SUB) {
     const int cnt = (int)(min(e0, s + SUB) - s);
+    V4 v[PER];
+    int tile[PER];
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      const int64_t j = s + min(k * BIG_SORT_THREADS + (int)threadIdx.x, cnt - 1);
+      v[k].x = a.x[j];
+      v[k].y = a.y[j];
+      v[k].z = a.h ? a.h[j] : T(0);
+      v[k].w = a.w[j];
+    }
     for (int i = threadIdx.x; i < a.ntiles; i += blockDim.x) hist[i] = 0;
     __syncthreads();
-    for (int li = threadIdx.x; li < cnt; li += blockDim.x)
-      atomicAdd(&hist[big_tile<T>(a, a.x[s + li], a.y[s + li])], 1);
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      tile[k] = big_tile<T>(a, v[k].x, v[k].y);
+      if (k * BIG_SORT_THREADS + (int)threadIdx.x < cnt) atomicAdd(&hist[tile[k]], 1);
+    }
     __syncthreads();
     big_block_scan<BIG_SORT_THREADS, int>(hist, lstart, a.ntiles, wsum);
-    for (int li = threadIdx.x; li < cnt; li += blockDim.x) {
-      const int64_t j = s + li;
-      V4 v;
-      v.x = a.x[j];
-      v.y = a.y[j];
-      v.z = a.h ? a.h[j] : T(0);
-      v.w = a.w[j];
-      const int t = big_tile<T>(a, v.x, v.y);
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      const int li = k * BIG_SORT_THREADS + threadIdx.x;
+      if (li >= cnt) continue;
+      const int t = tile[k];
       // the histogram pass counted this point in tile t: hist[t] - 1 - (rank so far) is free
       const int slot = lstart[t] + atomicSub(&hist[t], 1) - 1;
       const int64_t pos = (int64_t)gbase[t] + (slot - lstart[t]);
-      if (slot >= 0 && slot < cnt) staged[slot] = v;   // always true when both passes agree on the tile
-      a.inv[j] = (pos >= 0 && pos < a.n) ? (int)pos : -1;
+      if (slot >= 0 && slot < cnt) staged[slot] = v[k];   // always true: both passes use tile[k]
+      a.inv[s + li] = (pos >= 0 && pos < a.n) ? (int)pos : -1;
     }
     __syncthreads();
     for (int i = threadIdx.x; i < cnt; i += blockDim.x) {
@@ -405,9 +420,18 @@ __global__ __launch_bounds__(BIG_SPREAD_THREADS) void big_spread_kernel(BigTileA
     for (int i = threadIdx.x; i < S * S; i += blockDim.x) sub[i] = 0.0;
     __syncthreads();
     const int tx0 = (t % a.ntx) * BIG_TS, ty0 = (t / a.ntx) * BIG_TS;
-    for (int64_t k = lo + threadIdx.x; k < hi; k += blockDim.x) {
-      const T xj = a.xs[k], yj = a.ys[k];
-      const T cj = a.ws[k] * a.hs[k] * hann_w(a.window_kind, xj, yj, cx, cy, R, pr);
+    // the next point's loads are issued before this point's arithmetic
+    int64_t k = lo + threadIdx.x;
+    T xn = T(0), yn = T(0), wn_ = T(0), hn = T(0);
+    if (lo < hi) {
+      const int64_t kc = k < hi ? k : hi - 1;
+      xn = a.xs[kc]; yn = a.ys[kc]; wn_ = a.ws[kc]; hn = a.hs[kc];
+    }
+    for (; k < hi; k += blockDim.x) {
+      const T xj = xn, yj = yn, wj = wn_, hj = hn;
+      const int64_t kn = k + blockDim.x < hi ? k + blockDim.x : k;
+      xn = a.xs[kn]; yn = a.ys[kn]; wn_ = a.ws[kn]; hn = a.hs[kn];
+      const T cj = wj * hj * hann_w(a.window_kind, xj, yj, cx, cy, R, pr);
       const FineCoord<T> fx = fine_coord<T>(xj, a.s1h, a.s1l, halfw);
       const FineCoord<T> fy = fine_coord<T>(yj, a.s2h, a.s2l, halfw);
       const int lx = big_local(fx.i0 & (g.n1 - 1), tx0, g.n1);
@@ -960,8 +984,17 @@ __global__ __launch_bounds__(256) void big_gather_kernel(BigTileArgs<T> a) {
       sg[i] = a.G4[(int64_t)((ty0 - 1 + r) & (g.n2 - 1)) * g.n1 + ((tx0 - 1 + q) & (g.n1 - 1))];
     }
     __syncthreads();
-    for (int64_t k = lo + threadIdx.x; k < hi; k += blockDim.x) {
-      const T xj = a.xs[k], yj = a.ys[k];
+    // the next point's loads are issued before this point's arithmetic and store
+    int64_t k = lo + threadIdx.x;
+    T xn = T(0), yn = T(0), wn_ = T(0), hn = T(0);
+    if (lo < hi) {
+      const int64_t kc = k < hi ? k : hi - 1;
+      xn = a.xs[kc]; yn = a.ys[kc]; wn_ = a.ws[kc]; hn = a.hs[kc];
+    }
+    for (; k < hi; k += blockDim.x) {
+      const T xj = xn, yj = yn, wj = wn_, hj = hn;
+      const int64_t kn = k + blockDim.x < hi ? k + blockDim.x : k;
+      xn = a.xs[kn]; yn = a.ys[kn]; wn_ = a.ws[kn]; hn = a.hs[kn];
       const FineCoord<T> fx = fine_coord<T>(xj, a.s1h, a.s1l, halfw);
       const FineCoord<T> fy = fine_coord<T>(yj, a.s2h, a.s2l, halfw);
       const int lx = big_local(fx.i0 & (g.n1 - 1), tx0, g.n1);
@@ -1001,7 +1034,7 @@ __global__ __launch_bounds__(256) void big_gather_kernel(BigTileArgs<T> a) {
       }
       T dWx, dWy;
       const T Wv = hann_wg(a.window_kind, xj, yj, cx, cy, R, pr, dWx, dWy);
-      const T wj = a.ws[k], wh = wj * a.hs[k];
+      const T wh = wj * hj;
       V4 o;
       o.x = wj * Wv * u;
       o.y = wh * (dWx * u + Wv * ux);
@@ -1018,13 +1051,33 @@ __global__ __launch_bounds__(256) void big_gather_kernel(BigTileArgs<T> a) {
 template <typename T>
 __global__ __launch_bounds__(256) void big_unpermute_kernel(const typename vec4<T>::type *gout, const int *inv,
                                                             int64_t n, T *gh, T *gx, T *gy) {
-  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x) {
-    const int k = inv[j];
-    if (k < 0 || k >= n) continue;   // only if the sort's passes disagreed; never out of bounds
-    const typename vec4<T>::type v = gout[k];
-    if (gh) gh[j] = v.x;
-    if (gx) gx[j] = v.y;
-    if (gy) gy[j] = v.z;
+  // U points per thread and round, all loads of a round before its stores (the
+  // stores could alias the records as far as the compiler knows, so a store
+  // between loads would serialise them)
+  constexpr int U = 4;
+  using V4 = typename vec4<T>::type;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t j0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j0 < n; j0 += U * stride) {
+    int k[U];
+    V4 v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t j = j0 + u * stride;
+      k[u] = j < n ? inv[j] : -1;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const bool ok = k[u] >= 0 && k[u] < n;   // false only past the end (or if the sort's passes disagreed)
+      v[u] = gout[ok ? k[u] : 0];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t j = j0 + u * stride;
+      if (j >= n || k[u] < 0 || k[u] >= n) continue;
+      if (gh) gh[j] = v[u].x;
+      if (gx) gx[j] = v[u].y;
+      if (gy) gy[j] = v[u].z;
+    }
   }
 }
 
