@@ -420,18 +420,9 @@ __global__ __launch_bounds__(BIG_SPREAD_THREADS) void big_spread_kernel(BigTileA
     for (int i = threadIdx.x; i < S * S; i += blockDim.x) sub[i] = 0.0;
     __syncthreads();
     const int tx0 = (t % a.ntx) * BIG_TS, ty0 = (t / a.ntx) * BIG_TS;
-    // the next point's loads are issued before this point's arithmetic
-    int64_t k = lo + threadIdx.x;
-    T xn = T(0), yn = T(0), wn_ = T(0), hn = T(0);
-    if (lo < hi) {
-      const int64_t kc = k < hi ? k : hi - 1;
-      xn = a.xs[kc]; yn = a.ys[kc]; wn_ = a.ws[kc]; hn = a.hs[kc];
-    }
-    for (; k < hi; k += blockDim.x) {
-      const T xj = xn, yj = yn, wj = wn_, hj = hn;
-      const int64_t kn = k + blockDim.x < hi ? k + blockDim.x : k;
-      xn = a.xs[kn]; yn = a.ys[kn]; wn_ = a.ws[kn]; hn = a.hs[kn];
-      const T cj = wj * hj * hann_w(a.window_kind, xj, yj, cx, cy, R, pr);
+    for (int64_t k = lo + threadIdx.x; k < hi; k += blockDim.x) {
+      const T xj = a.xs[k], yj = a.ys[k];
+      const T cj = a.ws[k] * a.hs[k] * hann_w(a.window_kind, xj, yj, cx, cy, R, pr);
       const FineCoord<T> fx = fine_coord<T>(xj, a.s1h, a.s1l, halfw);
       const FineCoord<T> fy = fine_coord<T>(yj, a.s2h, a.s2l, halfw);
       const int lx = big_local(fx.i0 & (g.n1 - 1), tx0, g.n1);
@@ -984,17 +975,8 @@ __global__ __launch_bounds__(256) void big_gather_kernel(BigTileArgs<T> a) {
       sg[i] = a.G4[(int64_t)((ty0 - 1 + r) & (g.n2 - 1)) * g.n1 + ((tx0 - 1 + q) & (g.n1 - 1))];
     }
     __syncthreads();
-    // the next point's loads are issued before this point's arithmetic and store
-    int64_t k = lo + threadIdx.x;
-    T xn = T(0), yn = T(0), wn_ = T(0), hn = T(0);
-    if (lo < hi) {
-      const int64_t kc = k < hi ? k : hi - 1;
-      xn = a.xs[kc]; yn = a.ys[kc]; wn_ = a.ws[kc]; hn = a.hs[kc];
-    }
-    for (; k < hi; k += blockDim.x) {
-      const T xj = xn, yj = yn, wj = wn_, hj = hn;
-      const int64_t kn = k + blockDim.x < hi ? k + blockDim.x : k;
-      xn = a.xs[kn]; yn = a.ys[kn]; wn_ = a.ws[kn]; hn = a.hs[kn];
+    for (int64_t k = lo + threadIdx.x; k < hi; k += blockDim.x) {
+      const T xj = a.xs[k], yj = a.ys[k];
       const FineCoord<T> fx = fine_coord<T>(xj, a.s1h, a.s1l, halfw);
       const FineCoord<T> fy = fine_coord<T>(yj, a.s2h, a.s2l, halfw);
       const int lx = big_local(fx.i0 & (g.n1 - 1), tx0, g.n1);
@@ -1034,7 +1016,7 @@ __global__ __launch_bounds__(256) void big_gather_kernel(BigTileArgs<T> a) {
       }
       T dWx, dWy;
       const T Wv = hann_wg(a.window_kind, xj, yj, cx, cy, R, pr, dWx, dWy);
-      const T wh = wj * hj;
+      const T wj = a.ws[k], wh = wj * a.hs[k];
       V4 o;
       o.x = wj * Wv * u;
       o.y = wh * (dWx * u + Wv * ux);
