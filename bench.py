@@ -298,8 +298,9 @@ def main():
     ap.add_argument("--cmd-trace", default="")
     ap.add_argument("--cmd-fetch", default="")
     ap.add_argument("--cmd-write", default="")
-    ap.add_argument("--workload", choices=["c3", "c4"], default="c3",
-                    help="c3: the 20,480-cell batch (default); c4: the single high-resolution cell")
+    ap.add_argument("--workload", choices=["c1", "c3", "c4"], default="c3",
+                    help="c3: the 20,480-cell batch (default); c1: the 256-hexagon batch; "
+                         "c4: the single high-resolution cell")
     ap.add_argument("--precision", choices=["f32", "f64"], default="f32", help="c4 only")
     ap.add_argument("--points", type=int, default=100_000_000, help="c4 only: points in the cell")
     args = ap.parse_args()
@@ -324,8 +325,12 @@ def main():
         bench_c4(args, torch, enf, synth, dev)
         return
     t0 = time.perf_counter()
-    batch = synth.config3(device=dev, n_cells=args.cells, shuffled=args.shuffled,
-                          progress=lambda s: log("generating: %s (%.0f s)" % (s, time.perf_counter() - t0)))
+    c1 = args.workload == "c1"
+    if c1:
+        batch = synth.config1(device=dev, **({"n_cells": args.cells} if args.cells else {}))
+    else:
+        batch = synth.config3(device=dev, n_cells=args.cells, shuffled=args.shuffled,
+                              progress=lambda s: log("generating: %s (%.0f s)" % (s, time.perf_counter() - t0)))
     torch.cuda.synchronize()
     log("generated %s: %d cells, %d points in %.1f s" % (batch.name, batch.n_cells, batch.n_points,
                                                          time.perf_counter() - t0))
@@ -399,7 +404,7 @@ def main():
     # algorithmic bytes of one forward launch: read x, y, h, w (16 B per point), write f (8 B per mode)
     fwd_bytes = 16.0 * Q + 8.0 * M * batch.n_cells
     achieved = fwd_bytes / (t1 * 1e-3) / 1e9
-    traffic = measured_traffic() if args.cells is None else None
+    traffic = measured_traffic() if (args.cells is None and not c1) else None   # counters taken on C3
     roofline = {"bound": "hbm", "achieved": achieved, "peak": 8000.0, "unit": "GB/s",
                 "frac": achieved / 8000.0, "traffic": traffic, "kernel": "fwd_kernel (spread+FFT+deconv+crop)",
                 "bytes_per_launch": fwd_bytes, "avg_launch_ms": t1}
@@ -411,10 +416,13 @@ def main():
         "metric": "NU points/s batched type-1+EMS at rel-l2 5e-5 vs per-cell loop; fwd+bwd ms",
         "value": value, "unit": "NU points/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32", "data": "synthetic (seeded icosahedral-cell terrain)",
-        "config": {"workload": "20,480 icosahedral triangles, ~8e8 points, 64x64 modes, sigma 2, eps 1e-5, "
-                               "Hann window, EMS 95% power, fwd+bwd" if args.cells is None else
-                               "first %d icosahedral triangles" % batch.n_cells,
+        "dtype": "f32",
+        "data": "synthetic (seeded %s terrain)" % ("hexagon" if c1 else "icosahedral-cell"),
+        "config": {"workload": ("256 hexagons, lognormal counts (median 2e4, sigma 1.0), 64x64 modes, sigma 2, "
+                                "eps 1e-5, Hann window, EMS 95% power, fwd+bwd" if c1 else
+                                "20,480 icosahedral triangles, ~8e8 points, 64x64 modes, sigma 2, eps 1e-5, "
+                                "Hann window, EMS 95% power, fwd+bwd") if args.cells is None else
+                               "first %d %s" % (batch.n_cells, "hexagons" if c1 else "icosahedral triangles"),
                    "n_cells": batch.n_cells, "n_points": Q, "modes": list(gb.n_modes), "sigma": 2.0, "eps": 1e-5,
                    "kernel_width": info["kernel_width"], "grid": info["grid"],
                    "fwd_threads": info["fwd_threads"], "autotuned": bool(info["tuned"])},
