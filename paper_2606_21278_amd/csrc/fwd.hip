@@ -463,22 +463,35 @@ __device__ void fft_deconv_store(const FwdArgs<T> &a, T *G, int cell) {
   using C = typename vec2<T>::type;
   C *fout = reinterpret_cast<C *>(a.f) + (int64_t)cell * g.N1 * g.N2;
   const int hi1 = g.lo1 + g.N1 - 1, hi2 = g.lo2 + g.N2 - 1;
-  const int nky = 2 * g.K2 + 1;
-  for (int it = threadIdx.x; it < nky * per; it += NT) {
-    const int kyi = it / per, kx = it - kyi * per;
-    const int ky = kyi - g.K2;
-    const int bin = ky & (n2 - 1);
-    const int pos = fft_pos(bin, n2);
-    const T zr = G[pos * pitch + 2 * kx], zi = G[pos * pitch + 2 * kx + 1];
-    const T s = a.decon_x[kx] * a.decon_y[ky < 0 ? -ky : ky];
-    const T vr = zr * s, vi = zi * s;
-    if (kx <= hi1 && ky >= g.lo2 && ky <= hi2) {
-      C v; v.x = vr; v.y = vi;
-      fout[(ky - g.lo2) * g.N1 + (kx - g.lo1)] = v;
+  // Items in rounds of U per thread, with the factors' loads of a round issued
+  // before its stores (the stores could alias the factor tables as far as the
+  // compiler knows, so a store between loads would serialise them).
+  const int nky = 2 * g.K2 + 1, nit = nky * per;
+  constexpr int U = 4;
+  for (int it0 = threadIdx.x; it0 < nit; it0 += U * NT) {
+    int kx[U], ky[U];
+    T s[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int it = min(it0 + u * NT, nit - 1);
+      const int kyi = it / per;
+      kx[u] = it - kyi * per;
+      ky[u] = kyi - g.K2;
+      s[u] = a.decon_x[kx[u]] * a.decon_y[ky[u] < 0 ? -ky[u] : ky[u]];
     }
-    if (kx >= 1 && -kx >= g.lo1 && -ky >= g.lo2 && -ky <= hi2) {
-      C v; v.x = vr; v.y = -vi;
-      fout[(-ky - g.lo2) * g.N1 + (-kx - g.lo1)] = v;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (it0 + u * NT >= nit) break;
+      const int pos = fft_pos(ky[u] & (n2 - 1), n2);
+      const T vr = G[pos * pitch + 2 * kx[u]] * s[u], vi = G[pos * pitch + 2 * kx[u] + 1] * s[u];
+      if (kx[u] <= hi1 && ky[u] >= g.lo2 && ky[u] <= hi2) {
+        C v; v.x = vr; v.y = vi;
+        fout[(ky[u] - g.lo2) * g.N1 + (kx[u] - g.lo1)] = v;
+      }
+      if (kx[u] >= 1 && -kx[u] >= g.lo1 && -ky[u] >= g.lo2 && -ky[u] <= hi2) {
+        C v; v.x = vr; v.y = -vi;
+        fout[(-ky[u] - g.lo2) * g.N1 + (-kx[u] - g.lo1)] = v;
+      }
     }
   }
 }
