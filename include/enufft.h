@@ -188,6 +188,8 @@ enufft_status enufft_ems(enufft_plan_t p, const void *f, const enufft_ems_params
                          const double *mode_weight, uint8_t *keep, int32_t *k_star, double *stats);
 
 /* Adjoint of the batched type-1 map (a type-2 NUFFT) and the chain rule.
+ *   x, y, h, w  device, n_points each, as for enufft_type1_batched (all four required;
+ *               NULL gives ENUFFT_EINVAL).
  *   fbar        device, n_cells * N2 * N1 complex cotangent g = dL/dRe f + i dL/dIm f
  *               (for L = sum_c lambda_c P_c this is 2 lambda_c f keep).
  *   grad_h, grad_x, grad_y  device, n_points each, or NULL to skip; written in full:

@@ -366,57 +366,62 @@ __device__ __forceinline__ void gather_point(const AdjArgs<T> &a, const T *Guv, 
   }
 }
 
-// All points of one item.  With 16-byte aligned arrays each lane takes runs of
-// 4 consecutive points (one 16-byte load per array); wave w reads 64 runs
-// contiguous (1 KiB per array) and the loads run two blocks ahead in three
-// register buffers, so the gather is not serialised behind point loads.
-// Every point of the item is read (its band decides whether it is served).
+// All points of one item; every point is read (its band decides whether it is
+// served).  Wave w takes blocks of 256 consecutive points and lane l gathers
+// points l, l + 64, l + 128 and l + 192 of a block, so at every step the 64
+// lanes work on 64 consecutive points: for points stored in raster order their
+// footprints overlap, many lanes read the same LDS words (one broadcast) and
+// the others fall on neighbouring banks.  (Runs of 4 consecutive points per
+// lane put the lanes 4 points apart, and about half of the LDS time went to
+// bank conflicts.)  The loads run two blocks ahead in three register buffers,
+// so the gather is not serialised behind point loads; each wave load reads 256
+// contiguous bytes of an array.  FP64 and the wider kernels (register budget)
+// take one point per thread and step.
 template <typename T, int W, int NT, bool POLY>
 __device__ __forceinline__ void gather_item(const AdjArgs<T> &a, const T *Guv, const T *Gy, int apitch,
                                             int band_lo, int64_t begin, int64_t end, T cx, T cy, T R) {
   const T pr = R > T(0) ? T(M_PI) / R : T(0);
-  int64_t body0 = end, body1 = end;
-  // runs of 4 points for FP32 and the narrow kernels (register budget)
-  constexpr bool kRuns = sizeof(T) == 4 && W <= 6;
-  if (kRuns && a.vec4) {
-    body0 = min(end, (begin + 3) / 4 * 4);
-    body1 = max(body0, end / 4 * 4);
-  }
-  using V = typename vec4<T>::type;
-  const V *x4 = reinterpret_cast<const V *>(a.x), *y4 = reinterpret_cast<const V *>(a.y);
-  const V *h4 = reinterpret_cast<const V *>(a.h), *w4 = reinterpret_cast<const V *>(a.w);
-  const int64_t g0 = body0 / 4, q1 = body1 / 4;
-  if constexpr (kRuns) if (q1 > g0) {
+  constexpr bool kBlocks = sizeof(T) == 4 && W <= 6;
+  if constexpr (kBlocks) {
+    constexpr int U = 4, BLK = 64 * U, NWV = NT / 64;
+    struct Pts {
+      T x[U], y[U], h[U], w[U];
+    };
     const int lane = threadIdx.x & 63;
-    int64_t q = g0 + (threadIdx.x >> 6) * 64 + lane;
-    auto load = [&](V &xb, V &yb, V &hb, V &wb, int64_t qq) {
-      const int64_t qc = qq < q1 ? qq : q1 - 1;   // past the end: re-read the last run (unused)
-      xb = x4[qc]; yb = y4[qc]; hb = h4[qc]; wb = w4[qc];
+    const int64_t stride = (int64_t)NWV * BLK;
+    auto load = [&](Pts &b, int64_t pb) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int64_t i = pb + u * 64 + lane;
+        const int64_t ic = i < end ? i : end - 1;   // past the end: re-read the last point (unused)
+        b.x[u] = a.x[ic]; b.y[u] = a.y[ic]; b.h[u] = a.h[ic]; b.w[u] = a.w[ic];
+      }
     };
-    auto step = [&](const V &xv, const V &yv, const V &hv, const V &wv, int64_t qq) {
-      if (qq >= q1) return;
-      gather_point<T, W, POLY>(a, Guv, Gy, apitch, band_lo, qq * 4 + 0, xv.x, yv.x, hv.x, wv.x, cx, cy, R, pr);
-      gather_point<T, W, POLY>(a, Guv, Gy, apitch, band_lo, qq * 4 + 1, xv.y, yv.y, hv.y, wv.y, cx, cy, R, pr);
-      gather_point<T, W, POLY>(a, Guv, Gy, apitch, band_lo, qq * 4 + 2, xv.z, yv.z, hv.z, wv.z, cx, cy, R, pr);
-      gather_point<T, W, POLY>(a, Guv, Gy, apitch, band_lo, qq * 4 + 3, xv.w, yv.w, hv.w, wv.w, cx, cy, R, pr);
+    auto step = [&](const Pts &b, int64_t pb) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int64_t i = pb + u * 64 + lane;
+        if (i < end)
+          gather_point<T, W, POLY>(a, Guv, Gy, apitch, band_lo, i, b.x[u], b.y[u], b.h[u], b.w[u], cx, cy, R, pr);
+      }
     };
-    V x0{}, y0{}, h0{}, w0{}, x1{}, y1{}, h1{}, w1{}, x2{}, y2{}, h2{}, w2{};
-    load(x0, y0, h0, w0, q);
-    load(x1, y1, h1, w1, q + NT);
-    for (int64_t qb = g0; qb < q1; qb += 3 * NT, q += 3 * NT) {
-      load(x2, y2, h2, w2, q + 2 * NT);
-      step(x0, y0, h0, w0, q);
-      load(x0, y0, h0, w0, q + 3 * NT);
-      step(x1, y1, h1, w1, q + NT);
-      load(x1, y1, h1, w1, q + 4 * NT);
-      step(x2, y2, h2, w2, q + 2 * NT);
+    if (begin < end) {
+      int64_t p = begin + (int64_t)(threadIdx.x >> 6) * BLK;
+      Pts b0, b1, b2;
+      load(b0, p);
+      load(b1, p + stride);
+      for (; p < end; p += 3 * stride) {
+        load(b2, p + 2 * stride);
+        step(b0, p);
+        load(b0, p + 3 * stride);
+        step(b1, p + stride);
+        load(b1, p + 4 * stride);
+        step(b2, p + 2 * stride);
+      }
     }
-  }
-  // points outside the aligned body (all of them when unaligned), one per thread
-  const int64_t nhead = body0 - begin, ntail = end - body1;
-  for (int64_t i = threadIdx.x; i < nhead + ntail; i += NT) {
-    const int64_t j = i < nhead ? begin + i : body1 + (i - nhead);
-    gather_point<T, W, POLY>(a, Guv, Gy, apitch, band_lo, j, a.x[j], a.y[j], a.h[j], a.w[j], cx, cy, R, pr);
+  } else {
+    for (int64_t j = begin + threadIdx.x; j < end; j += NT)
+      gather_point<T, W, POLY>(a, Guv, Gy, apitch, band_lo, j, a.x[j], a.y[j], a.h[j], a.w[j], cx, cy, R, pr);
   }
 }
 
@@ -738,7 +743,7 @@ enufft_status adjoint_common(enufft_plan_t p, const char *fn, const void *x, con
     p->last_error = std::string(fn) + ": null coefficient input";
     return ENUFFT_EINVAL;
   }
-  if (!x || !y || !w || ((grad_x || grad_y) && !h)) {
+  if (!x || !y || !h || !w) {   // every kernel reads all four arrays
     p->last_error = std::string(fn) + ": null point array";
     return ENUFFT_EINVAL;
   }

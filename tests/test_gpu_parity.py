@@ -3,6 +3,7 @@
 Tolerances: relative l2 error per cell <= 5e-5 on the FP32 path and <= 1e-10 on the
 FP64 path; EMS kept sets identical on tie-free cells; adjoint gradients <= 5e-5
 (FP32) and <= 1e-10 (FP64) relative l2 over all points."""
+import ctypes
 import math
 
 import numpy as np
@@ -277,6 +278,22 @@ def test_adjoint_small_mode_boxes(prec, n_modes):
     errs = [rel_l2(ah.cpu().numpy(), gh), rel_l2(ax.cpu().numpy(), gx), rel_l2(ay.cpu().numpy(), gy)]
     print("adjoint rel-l2 h %.3e x %.3e y %.3e" % tuple(errs), flush=True)
     assert max(errs) <= TOL[prec]
+
+
+def test_adjoint_rejects_missing_point_arrays():
+    """The C ABI refuses a NULL height array (every kernel reads it) before any launch."""
+    b = synth.uniform_box(counts=[300, 40], n_modes=(16, 16), precision="f32", window_radius=2.5)
+    gb = gpu_batch(b)
+    plan = make_plan(gb)
+    L = enf.load_library()
+    fbar = torch.zeros((b.n_cells, 16, 16), dtype=plan.cdtype, device="cuda:0")
+    gh = torch.empty(b.n_points, dtype=torch.float32, device="cuda:0")
+    p = lambda t: ctypes.c_void_p(t.data_ptr())
+    code = L.enufft_type1_adjoint(plan._h, p(gb.x), p(gb.y), None, p(gb.w), p(fbar), p(gh), None, None)
+    assert code == enf.EINVAL
+    ah, _, _ = plan.adjoint(gb.x, gb.y, gb.h, gb.w, fbar, need=(True, False, False))   # the plan stays usable
+    torch.cuda.synchronize()
+    assert torch.count_nonzero(ah).item() == 0
 
 
 def test_retained_power_autograd_fp32():
