@@ -186,7 +186,7 @@ __device__ void column_pass(const AdjArgs<T> &a, const T *st, const T *tw2, T tw
                             bool yderiv, T *db, int rows, int y0) {
   const Geom &g = a.g;
   const int per = g.K1 + 1, n2 = g.n2, M = g.N1 * g.N2;
-  const int A = fft_A(n2), B = fft_B(n2), la = fft_logA(n2), lb = fft_logB(n2);
+  const int A = fft_A(n2), B = fft_B(n2);
   ColSpecAcc<T> acc;
   acc.sf = st;
   acc.sdx = st + 2 * M;
@@ -197,8 +197,14 @@ __device__ void column_pass(const AdjArgs<T> &a, const T *st, const T *tw2, T tw
   acc.n2 = n2; acc.K2 = g.K2; acc.N1 = g.N1; acc.lo1 = g.lo1; acc.lo2 = g.lo2;
   acc.hi1 = g.lo1 + g.N1 - 1; acc.hi2 = g.lo2 + g.N2 - 1;
   acc.yderiv = yderiv;
+  // Consecutive lanes take consecutive columns (the column is the fast index of
+  // both steps), so their LDS words are adjacent: the staged coefficients of
+  // consecutive kx, the workspace elements 2 kx apart, the band spectra of
+  // consecutive kx.  (With the transform position as the fast index, lanes
+  // were a row of the staged box, or 8 or 16 workspace rows, apart: 8- and
+  // 16-way bank conflicts.)
   for (int it = threadIdx.x; it < per * B; it += NT) {
-    const int q = it >> lb, b = it & (B - 1);
+    const int b = it / per, q = it - b * per;
     ColSpecAcc<T> c = acc;
     c.kx = q;
     c.col = ws + 2 * q;
@@ -206,7 +212,7 @@ __device__ void column_pass(const AdjArgs<T> &a, const T *st, const T *tw2, T tw
   }
   __syncthreads();
   for (int it = threadIdx.x; it < per * A; it += NT) {
-    const int q = it >> la, k1 = it & (A - 1);
+    const int k1 = it / per, q = it - k1 * per;
     const T *col = ws + 2 * q;
     switch (n2) {
       case 16: col_step2_band<4, 4, T>(col, cpitch, k1, n2, db, per, q, rows, y0); break;
