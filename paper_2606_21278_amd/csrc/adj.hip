@@ -232,40 +232,12 @@ __device__ void column_pass(const AdjArgs<T> &a, const T *st, const T *tw2, T tw
 // same row still read, so the A items of a row must be one wave's lanes: a
 // wave's LDS accesses complete in issue order and every item loads before it
 // stores.  With A | 64 and 64 | NT, the items q A .. q A + A - 1 of the
-// batched loop below always share a wave.
-//
-// Between the two steps, position k1 B + b holds its value at k1 B + (b ^ s(k1)),
-// s(k1) = (k1 / 2) mod B: the lanes of a row's items (consecutive k1) would
-// otherwise read words 8 or 16 apart in the same instruction, all on one or
-// two banks of every 32; with the swizzle they spread over all of them.
-__device__ __forceinline__ int row_swz(int k1, int B) { return (k1 >> 1) & (B - 1); }
-
-// First step of the row transforms (as fft4_step1), storing with the swizzle.
-template <int A, int B, typename T, typename Acc>
-__device__ __forceinline__ void row_step1_swz(const Acc &acc, int b, const T *tw) {
-  T re[A], im[A];
-#pragma unroll
-  for (int a = 0; a < A; ++a) acc.load(a * B + b, re[a], im[a]);
-  dft_reg<A, true, T>(re, im);
-#pragma unroll
-  for (int k1 = 0; k1 < A; ++k1) {
-    T r = re[k1], i = im[k1];
-    if (k1 > 0) {
-      const int j = b * k1;
-      const T c = tw[2 * j];
-      const T sn = -tw[2 * j + 1];
-      const T nr = r * c - i * sn;
-      i = r * sn + i * c;
-      r = nr;
-    }
-    acc.store(k1 * B + (b ^ row_swz(k1, B)), r, i);
-  }
-}
-
+// batched loop below always share a wave.  The first step stores with
+// fft4_step1_swz (the inputs of item k1 sit at k1 B + (b ^ fft_swz(k1, B))).
 template <int A, int B, typename T, typename Acc>
 __device__ __forceinline__ void row_step2_natural(const Acc &acc, int k1, int n, int wrap) {
   T re[B], im[B];
-  const int sw = row_swz(k1, B);
+  const int sw = fft_swz(k1, B);
 #pragma unroll
   for (int b = 0; b < B; ++b) acc.load(k1 * B + (b ^ sw), re[b], im[b]);
   dft_reg<B, true, T>(re, im);
@@ -286,12 +258,7 @@ __device__ __forceinline__ void row_ifft_natural(int n, int count, const T *tw, 
   const int A = fft_A(n), B = fft_B(n), la = fft_logA(n), lb = fft_logB(n);
   for (int it = threadIdx.x; it < count * B; it += NT) {
     const int q = it >> lb, b = it & (B - 1);
-    switch (n) {
-      case 16: row_step1_swz<4, 4, T>(make1(q), b, tw); break;
-      case 32: row_step1_swz<8, 4, T>(make1(q), b, tw); break;
-      case 64: row_step1_swz<8, 8, T>(make1(q), b, tw); break;
-      default: row_step1_swz<16, 8, T>(make1(q), b, tw); break;
-    }
+    fft4_step1_swz_dispatch<true, T>(n, make1(q), b, tw);
   }
   __syncthreads();
   for (int it = threadIdx.x; it < count * A; it += NT) {

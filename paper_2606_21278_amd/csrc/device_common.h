@@ -340,6 +340,34 @@ __device__ __forceinline__ void fft4_step2(const Acc &acc, int k1) {
   for (int k2 = 0; k2 < B; ++k2) acc.store(k1 * B + k2, re[k2], im[k2]);
 }
 
+// The same first step storing position k1 B + b at k1 B + (b ^ fft_swz(k1, B)).
+// A second step whose items of one transform are consecutive lanes (k1 fast)
+// reads its B inputs at k1 B + (b ^ fft_swz(k1, B)): without the swizzle the
+// lanes' words are 8 or 16 apart in the same instruction and land on a few
+// of the 32 LDS banks.
+__device__ __forceinline__ int fft_swz(int k1, int B) { return (k1 >> 1) & (B - 1); }
+
+template <int A, int B, bool INV, typename T, typename Acc>
+__device__ __forceinline__ void fft4_step1_swz(const Acc &acc, int b, const T *tw) {
+  T re[A], im[A];
+#pragma unroll
+  for (int a = 0; a < A; ++a) acc.load(a * B + b, re[a], im[a]);
+  dft_reg<A, INV, T>(re, im);
+#pragma unroll
+  for (int k1 = 0; k1 < A; ++k1) {
+    T r = re[k1], i = im[k1];
+    if (k1 > 0) {
+      const int j = b * k1;
+      const T c = tw[2 * j];
+      const T s = INV ? -tw[2 * j + 1] : tw[2 * j + 1];
+      const T nr = r * c - i * s;
+      i = r * s + i * c;
+      r = nr;
+    }
+    acc.store(k1 * B + (b ^ fft_swz(k1, B)), r, i);
+  }
+}
+
 // Factorisation used for each supported length (both factors powers of two;
 // the index arithmetic below uses their logarithms, since a division by a
 // factor known only at run time would compile to a full integer division).
@@ -351,6 +379,17 @@ __host__ __device__ constexpr int fft_logB(int n) { return n == 16 ? 2 : n == 32
 __device__ __forceinline__ int fft_pos(int k, int n) {
   const int la = fft_logA(n), lb = fft_logB(n);
   return ((k & ((1 << la) - 1)) << lb) + (k >> la);
+}
+
+// First step with the swizzled store, for one (instance, column) item.
+template <bool INV, typename T, typename Acc>
+__device__ __forceinline__ void fft4_step1_swz_dispatch(int n, const Acc &acc, int idx, const T *tw) {
+  switch (n) {
+    case 16: fft4_step1_swz<4, 4, INV, T>(acc, idx, tw); break;
+    case 32: fft4_step1_swz<8, 4, INV, T>(acc, idx, tw); break;
+    case 64: fft4_step1_swz<8, 8, INV, T>(acc, idx, tw); break;
+    default: fft4_step1_swz<16, 8, INV, T>(acc, idx, tw); break;
+  }
 }
 
 // Run step 1 or 2 of a length-n transform for one (instance, column) item.
@@ -421,6 +460,25 @@ __device__ __forceinline__ void fft_batch(int n, int count, const T *tw, const M
   __syncthreads();
   for (int it = threadIdx.x; it < count * A; it += NT) {
     const int q = it >> la, k1 = it & (A - 1);
+    fft4_dispatch<INV, 2, T>(n, make(q), k1, tw);
+  }
+  __syncthreads();
+}
+
+// As fft_batch, with the instance as the fast item index of both steps:
+// consecutive lanes take consecutive instances, which suits instances stored
+// side by side (the columns of a row-major grid: their elements are adjacent
+// words, where a transform's own positions are a whole row apart).
+template <bool INV, int NT, typename T, typename Make>
+__device__ __forceinline__ void fft_batch_instfast(int n, int count, const T *tw, const Make &make) {
+  const int A = fft_A(n), B = fft_B(n);
+  for (int it = threadIdx.x; it < count * B; it += NT) {
+    const int b = it / count, q = it - b * count;
+    fft4_dispatch<INV, 1, T>(n, make(q), b, tw);
+  }
+  __syncthreads();
+  for (int it = threadIdx.x; it < count * A; it += NT) {
+    const int k1 = it / count, q = it - k1 * count;
     fft4_dispatch<INV, 2, T>(n, make(q), k1, tw);
   }
   __syncthreads();

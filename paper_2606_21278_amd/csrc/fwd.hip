@@ -386,8 +386,9 @@ __device__ __forceinline__ void grid_to_t(double *grid, const Geom &g) {
 template <int A, int B, typename T>
 __device__ __forceinline__ void row_step2_unpack(const RowPairAcc<T> &acc, int k1, int n, int K1) {
   T re[B], im[B];
+  const int sw = fft_swz(k1, B);   // the first step stored with fft4_step1_swz
 #pragma unroll
-  for (int b = 0; b < B; ++b) acc.load(k1 * B + b, re[b], im[b]);
+  for (int b = 0; b < B; ++b) acc.load(k1 * B + (b ^ sw), re[b], im[b]);
   dft_reg<B, false, T>(re, im);
 #pragma unroll
   for (int k2 = 0; k2 < B; ++k2) acc.store(k1 * B + k2, re[k2], im[k2]);
@@ -419,7 +420,7 @@ __device__ __forceinline__ void row_fft_unpack(int n, int count, const T *tw, in
   const int A = fft_A(n), B = fft_B(n), la = fft_logA(n), lb = fft_logB(n);
   for (int it = threadIdx.x; it < count * B; it += NT) {
     const int q = it >> lb, b = it & (B - 1);
-    fft4_dispatch<false, 1, T>(n, make(q), b, tw);
+    fft4_step1_swz_dispatch<false, T>(n, make(q), b, tw);
   }
   __syncthreads();
   for (int it = threadIdx.x; it < count * A; it += NT) {
@@ -453,7 +454,7 @@ __device__ void fft_deconv_store(const FwdArgs<T> &a, T *G, int cell) {
     return acc;
   });
   const int per = g.K1 + 1;
-  fft_batch<false, NT, T>(n2, per, a.tw2, [&](int q) {
+  fft_batch_instfast<false, NT, T>(n2, per, a.tw2, [&](int q) {
     ColAcc<T> acc;
     acc.base = G + 2 * q;
     acc.stride = pitch;
