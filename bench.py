@@ -309,9 +309,8 @@ def main():
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU: every box here has a single MI355X and this build has no "
-              "multi-GPU path (cells shard with no exchange; see the design notes). Run with --gpus 1.",
-              file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path (cells are independent and "
+              "would shard across GPUs with no exchange). Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
     import torch

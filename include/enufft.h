@@ -55,7 +55,7 @@ typedef enum {
     ENUFFT_EDEVICE = 3,  /* HIP runtime error or no usable gfx950 device */
     ENUFFT_EEPS = 4,     /* requested eps is not attainable at the requested precision */
     ENUFFT_ESTATE = 5,   /* plan unusable after an earlier device fault */
-    ENUFFT_EUNSUPPORTED = 6 /* valid request outside what this build implements */
+    ENUFFT_EUNSUPPORTED = 6 /* valid request outside what the library implements */
 } enufft_status;
 
 typedef enum { ENUFFT_F32 = 0, ENUFFT_F64 = 1 } enufft_precision;
