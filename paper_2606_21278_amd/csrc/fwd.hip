@@ -86,6 +86,7 @@ struct RunGeom {
   int sx[RUN_K], sy[RUN_K];
   float vx[RUN_K], vy[RUN_K];
   int cmin, rmin;
+  int cspan, rspan;   // spread of the footprint origins (columns, rows)
   bool fits, any;
 };
 
@@ -112,6 +113,8 @@ __device__ __forceinline__ RunGeom run_geom(const FwdArgs<T> &a, const float (&x
   }
   rg.any = rg.rmin != INT_MAX;   // some point inside the cell window
   rg.fits = !rg.any || (cmax - rg.cmin <= RUN_SX && rmax - rg.rmin <= RUN_SY);
+  rg.cspan = cmax - rg.cmin;
+  rg.rspan = rmax - rg.rmin;
 #pragma unroll
   for (int k = 0; k < RUN_K; ++k) {
     // points with c = 0 may lie anywhere: their shifts then match no column
@@ -176,9 +179,18 @@ __device__ __forceinline__ void run_spread(const FwdArgs<T> &a, double *grid, co
       for (int r = 0; r < WR; ++r) col[r] = (k == 0) ? KY[k][r] * xv : fmaf(KY[k][r], xv, col[r]);
     }
     double *cp = rowp + ((c0 + dc * j) & (g.n1 - 1));
+    // window cells outside the footprints' bounding box hold exact zeros: their
+    // lanes skip the add (fewer lanes per LDS atomic)
+    const bool cact = rev ? (j >= RUN_SX - rg.cspan) : (j < W + rg.cspan);
+    if (cact) {
 #pragma unroll
-    for (int r = 0; r < WR; ++r)
-      __hip_atomic_fetch_add(cp + r * pitch, (double)col[r], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      for (int r = 0; r < W; ++r)
+        __hip_atomic_fetch_add(cp + r * pitch, (double)col[r], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+#pragma unroll
+      for (int r = W; r < WR; ++r)
+        if (r < W + rg.rspan)
+          __hip_atomic_fetch_add(cp + r * pitch, (double)col[r], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    }
   }
 }
 
