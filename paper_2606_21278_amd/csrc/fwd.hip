@@ -249,19 +249,21 @@ __device__ __forceinline__ void spread_item(const FwdArgs<T> &a, double *grid, i
   const V *h4 = reinterpret_cast<const V *>(a.h), *w4 = reinterpret_cast<const V *>(a.w);
   if constexpr (kRuns) {
     // Group-to-lane map: in each block of NT consecutive groups, wave w takes
-    // the 64 groups w 64 .. w 64 + 63 and lane l the group 8 (l mod 8) + l / 8.
-    // Each wave load reads 1 KiB contiguous (whole cache lines, no re-fetch),
-    // lanes l and l + 1 hold groups 8 runs apart, so the windows they add in
-    // the same instruction start at different grid cells even when many
-    // points share a cell (LDS atomics on one address serialise), and the
-    // neighbouring groups of lanes l and l + 8 flush in opposite orders.
+    // the 64 groups w 64 .. w 64 + 63 and lane l the group 2 (l mod 32) + l / 32.
+    // Each wave load reads 1 KiB contiguous (whole cache lines, no re-fetch).
+    // Lanes l and l + 1 hold groups 2 runs apart: for raster-ordered points
+    // their windows start a few cells apart, at different grid cells (LDS
+    // atomics on one address serialise) but on nearby banks, and the
+    // neighbouring groups of lanes l and l + 32 flush in opposite orders.
+    // (Measured on C3 against lanes 1, 4, 8 and 16 groups apart: 2 was
+    // fastest, 8.9 ms against 9.3, 9.2, 9.7 and 9.8.)
     //
     // Groups that do not fit one window (a raster row ends inside the group,
     // or the points are unordered) are queued per wave and spread point by
     // point 64 at a time, so the rare misfit does not stall the other 63 lanes.
     const int lane = threadIdx.x & 63;
-    const int lane_off = (threadIdx.x >> 6) * 64 + ((lane & 7) << 3) + (lane >> 3);
-    const bool rev = (lane >> 3) & 1;
+    const int lane_off = (threadIdx.x >> 6) * 64 + ((lane & 31) << 1) + (lane >> 5);
+    const bool rev = (lane >> 5) & 1;
     const int64_t g0 = body0 / RUN_K, q1 = body1 / RUN_K;
     int64_t q = g0 + lane_off;
     int nq = 0;   // queued groups (the same in every lane)
