@@ -30,6 +30,7 @@ struct EmsArgs {
   const int4 *mode_unit;      // [M]: (rep, partner | -1, unit id, 0) of each mode's unit; rep -1: no unit
   int J;
   int M;                      // modes per cell = N1 * N2
+  int N1, N2;                 // mode box (row-major, N1 modes per row)
   int64_t cell_begin, cell_end;
   int k_min, k_max;
   double alpha_min, alpha_max, delta, w1, w2;
@@ -461,33 +462,53 @@ __global__ __launch_bounds__(64 * NW) void ems_kernel(EmsArgs a) {
   // modes (coalesced): keep flags and the retained power.  Batches of UK modes
   // per thread: all loads of a batch come before its stores (the byte stores
   // may alias the coefficients as far as the compiler knows, so a store
-  // between loads would serialise them), so a batch costs about two memory
-  // latencies instead of two per mode.
+  // between loads would serialise them).  A paired mode's other member is its
+  // mirror -k, whose index follows from the mode's own, so the coefficient
+  // loads need not wait for the mode's unit record and a batch costs about
+  // one memory latency.  The energy e(m) + e(mirror) equals the unit's
+  // e(rep) + e(partner) bit for bit (the same member terms; FP64 addition
+  // commutes).
   double pw = 0.0;
   uint8_t *kout = a.keep + cell * a.M;
   constexpr int UK = 4;
+  const int N1 = a.N1, hm1 = 2 * (a.N1 >> 1), hm2 = 2 * (a.N2 >> 1);
+  const float inv_n1 = 1.0f / (float)N1;
   for (int m0 = t; m0 < a.M; m0 += UK * NT) {
     uint8_t v[UK];
     int4 mu[UK];
-    int reps[UK], partners[UK];
+    C fm[UK], fo[UK];
+    int mm[UK], mo[UK];
 #pragma unroll
     for (int u = 0; u < UK; ++u) {
-      const int m = m0 + u * NT;
-      mu[u] = a.mode_unit[m < a.M ? m : a.M - 1];
-      reps[u] = m < a.M ? mu[u].x : -1;
-      partners[u] = mu[u].y;
+      const int m = min(m0 + u * NT, a.M - 1);
+      // row and column of m (the float quotient is within one of the true one)
+      int r = (int)((float)m * inv_n1);
+      r -= r * N1 > m;
+      r += (r + 1) * N1 <= m;
+      const int ri = hm2 - r, ii = hm1 - (m - r * N1);   // the mirror's row and column
+      mm[u] = m;
+      mo[u] = (ri < a.N2 && ii < N1) ? ri * N1 + ii : m;
+      mu[u] = a.mode_unit[m];
+      fm[u] = f[m];
+      fo[u] = f[mo[u]];
     }
     double eu[UK];
-    batch_energy<C, UK>(a, f, reps, partners, eu);
-    C fm[UK];
+    if (a.mode_weight) {
+      double wm[UK], wo[UK];
 #pragma unroll
-    for (int u = 0; u < UK; ++u) {
-      const int m = m0 + u * NT;
-      fm[u] = f[m < a.M ? m : a.M - 1];
+      for (int u = 0; u < UK; ++u) {
+        wm[u] = a.mode_weight[mm[u]];
+        wo[u] = a.mode_weight[mo[u]];
+      }
+#pragma unroll
+      for (int u = 0; u < UK; ++u) eu[u] = pair_energy_v<C>(fm[u], fo[u], wm[u], wo[u], mu[u].y >= 0);
+    } else {
+#pragma unroll
+      for (int u = 0; u < UK; ++u) eu[u] = pair_energy_v<C>(fm[u], fo[u], 1.0, 1.0, mu[u].y >= 0);
     }
 #pragma unroll
     for (int u = 0; u < UK; ++u) {
-      const bool keep = reps[u] >= 0 && kstar > 0 &&
+      const bool keep = m0 + u * NT < a.M && mu[u].x >= 0 && kstar > 0 &&
                         (eu[u] > eth || (eu[u] == eth && (!split_ties || tie_kept[mu[u].z])));
       v[u] = keep;
       if (keep) pw += (double)fm[u].x * (double)fm[u].x + (double)fm[u].y * (double)fm[u].y;
@@ -618,6 +639,7 @@ enufft_status ems_launch(enufft_plan_t p, const void *f, const enufft_ems_params
   EmsArgs a{};
   a.f = f; a.mode_weight = mode_weight; a.keep = keep; a.k_star = k_star; a.stats = stats;
   a.units = ut->d_units; a.mode_unit = ut->d_mode_unit; a.J = ut->J; a.M = p->N1 * p->N2;
+  a.N1 = p->N1; a.N2 = p->N2;
   a.cell_begin = cell_begin;
   a.cell_end = cell_begin + cell_count;
   a.k_min = prm->k_min; a.k_max = prm->k_max;
