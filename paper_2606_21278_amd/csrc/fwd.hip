@@ -165,7 +165,13 @@ __device__ __forceinline__ void run_spread(const FwdArgs<T> &a, double *grid, co
   }
   const int pitch = grid_pitch<P>(g);
   double *rowp = grid + (rg.rmin & (g.n2 - 1)) * pitch;
-  const int c0 = rev ? rg.cmin + WC - 1 : rg.cmin, dc = rev ? -1 : 1;
+  const int c0 = rev ? rg.cmin + WC - 1 : rg.cmin;
+  // The column step, tied to this group's origin by an empty asm statement so
+  // the compiler forms dc j per group instead of holding the products live
+  // across the point loop (where they had been spilled, and each reload waited
+  // for the next block's loads).
+  int dc = rev ? -1 : 1;
+  asm("" : "+v"(dc) : "v"(rg.cmin));
 #pragma unroll
   for (int j = 0; j < WC; ++j) {
     float col[WR];
