@@ -16,17 +16,19 @@
 namespace enufft {
 
 // Row pitch of the LDS grid: P > 0 is known at compile time (immediate LDS
-// offsets for the rows of a footprint), P = 0 reads it from the geometry.
+// offsets for the rows of a footprint), P <= 0 reads it from the geometry.
+// P != 0 builds evaluate the kernel polynomial without a run-time switch (the
+// switch made the compiler keep the taps in scratch memory).
 template <int P>
 __device__ __forceinline__ int grid_pitch(const Geom &g) {
   return P > 0 ? P : g.pitch;
 }
 
-// Kernel values along one axis.  The constant-pitch builds are launched only
-// when the plan carries the kernel polynomial, so they evaluate it directly.
+// Kernel values along one axis.  The P != 0 builds are launched only when the
+// plan carries the kernel polynomial, so they evaluate it directly.
 template <typename T, int W, int P>
 __device__ __forceinline__ void taps(const FwdArgs<T> &a, const FineCoord<T> &c, T (&out)[W]) {
-  if constexpr (P > 0 && sizeof(T) == 4 && W <= ES_MAXW)
+  if constexpr (P != 0 && sizeof(T) == 4 && W <= ES_MAXW)
     es_taps_poly<W>(c, float(W) * 0.5f, a.es, out);
   else
     es_taps<T, W>(c, a.beta, a.es, out);
@@ -144,7 +146,7 @@ __device__ __forceinline__ void run_spread(const FwdArgs<T> &a, double *grid, co
 #pragma unroll
   for (int k = 0; k < RUN_K; ++k) {
     float ky[W];
-    if constexpr (P > 0) {
+    if constexpr (P != 0) {
       es_taps_poly_v<W>(rg.vx[k], a.es, kx[k]);
       es_taps_poly_v<W>(rg.vy[k], a.es, ky);
     } else if (a.es.on) {
@@ -589,9 +591,9 @@ __global__ __launch_bounds__(NT) void fwd_kernel(FwdArgs<T> a) {
   }
 }
 
-// The compiled variants: FP32 with the kernel polynomial (W <= 8) also has a
-// constant-pitch build for the 128-wide grid, used when the plan carries the
-// polynomial.
+// The compiled variants: FP32 with the kernel polynomial (W <= 8) also has
+// polynomial builds, one with the constant pitch of the 128-wide grid and one
+// for any pitch, used when the plan carries the polynomial.
 template <typename T, int W>
 constexpr bool has_pitch128() {
   return sizeof(T) == 4 && W <= ES_MAXW;
@@ -604,6 +606,11 @@ static const void *fwd_fn(int threads, int pitch) {
       if (threads == 256) return (const void *)&fwd_kernel<T, W, 256, FWD_PITCH128>;
       if (threads == 512) return (const void *)&fwd_kernel<T, W, 512, FWD_PITCH128>;
       return (const void *)&fwd_kernel<T, W, 1024, FWD_PITCH128>;
+    }
+    if (pitch == FWD_POLY_ANY) {
+      if (threads == 256) return (const void *)&fwd_kernel<T, W, 256, FWD_POLY_ANY>;
+      if (threads == 512) return (const void *)&fwd_kernel<T, W, 512, FWD_POLY_ANY>;
+      return (const void *)&fwd_kernel<T, W, 1024, FWD_POLY_ANY>;
     }
   }
   if (threads == 256) return (const void *)&fwd_kernel<T, W, 256, 0>;

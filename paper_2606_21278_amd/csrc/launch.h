@@ -28,9 +28,13 @@ constexpr int FWD_PITCH128 = 130;
 // (a merged run of points spans up to W + 1 rows), then one deferred-group
 // queue per wave.
 // Pitch argument that selects the forward build: FWD_PITCH128 for the
-// constant-pitch polynomial build, 0 for the general one.
+// constant-pitch polynomial build, FWD_POLY_ANY for the polynomial build with
+// the pitch read at run time, 0 for the general one (exact kernel or
+// polynomial, chosen at run time).
+constexpr int FWD_POLY_ANY = -1;
 inline int fwd_variant_pitch(const Geom &g, const EsPoly &es) {
-  return (g.pitch == FWD_PITCH128 && es.on) ? FWD_PITCH128 : 0;
+  if (!es.on) return 0;
+  return g.pitch == FWD_PITCH128 ? FWD_PITCH128 : FWD_POLY_ANY;
 }
 
 __host__ __device__ inline size_t fwd_grid_bytes(const Geom &g, int W) {
