@@ -124,6 +124,32 @@ def test_forward_workgroup_sizes(threads, shuffled, monkeypatch):
     assert e.max() <= TOL["f32"]
 
 
+@pytest.mark.parametrize("threads", [256, 512, 1024])
+@pytest.mark.parametrize("n_modes", [(32, 32), (17, 9)])
+def test_forward_fp32_any_pitch(threads, n_modes, monkeypatch):
+    """FP32 plans whose fine grid is not 128 wide run the polynomial build that reads
+    the row pitch at run time: raster-ordered cells (merged runs of points) and an
+    unordered one, at every workgroup size."""
+    monkeypatch.setenv("ENUFFT_FWD_THREADS", str(threads))
+    b = synth.uniform_box(counts=[6000, 2500, 3001], n_modes=n_modes, precision="f32", window_radius=2.5, seed=7)
+    off = np.asarray(b.cell_offsets)
+    perm = np.arange(b.n_points)
+    for c in range(2):   # fine-row-major order in the first two cells; the third stays unordered
+        a, e = off[c], off[c + 1]
+        row = np.floor((b.y[a:e].numpy() + math.pi) / (2 * math.pi) * 64)
+        perm[a:e] = a + np.lexsort((b.x[a:e].numpy(), row))
+    idx = torch.from_numpy(perm)
+    b.x, b.y, b.h, b.w = b.x[idx], b.y[idx], b.h[idx], b.w[idx]
+    gb = gpu_batch(b)
+    plan = make_plan(gb)
+    info = plan.info()
+    assert info["fwd_threads"] == threads and info["grid"][0] != 128
+    f = plan.type1(gb.x, gb.y, gb.h, gb.w).cpu().numpy()
+    e = per_cell_rel_l2(f, oracle_f(b.to(dtype=torch.float32)))
+    print("threads", threads, "modes", n_modes, "grid", info["grid"], "per-cell rel-l2", e, flush=True)
+    assert e.max() <= TOL["f32"]
+
+
 def test_unaligned_point_arrays():
     """Arrays that are not 16-byte aligned take the point-by-point path; same result."""
     b = synth.config3(n_cells=12, count_scale=0.05)
