@@ -291,7 +291,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--shuffled", action="store_true", help="random point order within each cell")
     ap.add_argument("--no-autotune", dest="autotune", action="store_false",
-                    help="plan with the default launch shape instead of the autotuner's choice (c3)")
+                    help="plan with the default launch shape instead of the autotuner's choice")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MB",
                     help="after timing, run one plain device copy of this size (for profiler byte counters)")
     ap.add_argument("--summarize", metavar="DIR", help="write profiles/ summaries from rocprofv3 CSVs in DIR")
@@ -336,8 +336,11 @@ def main():
     gb = batch.to(device=dev, dtype=torch.float32)
     del batch.x, batch.y, batch.h, batch.w
     batch.x, batch.y, batch.h, batch.w = gb.x, gb.y, gb.h, gb.w
+    # the autotuner's trial points follow the workload's point order: C3 stores each
+    # cell's samples in raster order, C1 (and C3 --shuffled) in no spatial order
+    tune = ("unordered" if (c1 or args.shuffled) else "raster") if args.autotune else False
     plan = enf.Plan(gb.cell_offsets, gb.windows, n_modes=gb.n_modes, sigma=gb.sigma, eps=gb.eps, precision="f32",
-                    autotune=args.autotune)
+                    autotune=tune)
     info = plan.info()
     log("plan", info)
     prm = enf.EmsParams()

@@ -83,12 +83,15 @@ typedef struct { double cx, cy, radius; } enufft_window;
  *   window_kind enufft_window_kind.
  *   scale     overall factor on f (1 / |D| reproduces eq. (discrete_quadrature)).
  *   autotune  0: default launch shape; 1: timed trials at plan time on synthetic
- *             points with the plan's cell sizes (synchronises the stream; allocates
- *             trial buffers of up to 2^27 points, env ENUFFT_TUNE_MAX_POINTS,
- *             using a prefix of the cells beyond that).  The choice is cached
+ *             points with the plan's cell sizes, stored in raster order within
+ *             each cell (gridded samples); 2: the same trials on points stored in
+ *             no spatial order (scattered samples).  Other values: ENUFFT_EINVAL.
+ *             Trials synchronise the stream and allocate trial buffers of up
+ *             to 2^27 points (env ENUFFT_TUNE_MAX_POINTS; a prefix of the
+ *             cells beyond that).  The choice is cached
  *             in the file ENUFFT_TUNE_CACHE ("off" disables; default
  *             $HOME/.cache/enufft/tune_cache.txt) keyed by device, shape and
- *             the exact cell layout.
+ *             the exact cell layout and the trial point order.
  *   kernel_width 0: from eps; otherwise a width >= the eps-derived one. */
 typedef struct {
     int32_t n_modes[2];

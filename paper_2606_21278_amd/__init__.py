@@ -160,7 +160,11 @@ class Plan:
         opts.precision = F64 if precision == "f64" else F32
         opts.window_kind = WIN_HANN if window == "hann" else WIN_NONE
         opts.scale = float(scale)
-        opts.autotune = int(bool(autotune))
+        # autotune: False / True (trials on raster-ordered points) / "raster" / "unordered"
+        modes = {False: 0, True: 1, "raster": 1, "unordered": 2}
+        if autotune not in modes:
+            raise ValueError("autotune must be False, True, 'raster' or 'unordered'")
+        opts.autotune = modes[autotune]
         opts.kernel_width = int(kernel_width)
         wins = None
         if windows is not None:

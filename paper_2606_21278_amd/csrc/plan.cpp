@@ -365,6 +365,8 @@ enufft_status enufft_plan(enufft_plan_t *out, int64_t n_cells, const int64_t *ce
     return fail(nullptr, ENUFFT_EINVAL, "enufft_plan: unknown precision");
   if (opts->window_kind != ENUFFT_WIN_NONE && opts->window_kind != ENUFFT_WIN_HANN_RADIAL)
     return fail(nullptr, ENUFFT_EINVAL, "enufft_plan: unknown window kind");
+  if (opts->autotune < 0 || opts->autotune > 2)
+    return fail(nullptr, ENUFFT_EINVAL, "enufft_plan: autotune must be 0, 1 or 2");
   if (!(opts->sigma >= 1.25) || !(opts->sigma <= 16.0))
     return fail(nullptr, ENUFFT_EINVAL, "enufft_plan: sigma must be in [1.25, 16]");
   if (!(opts->eps > 0.0) || !(opts->eps < 1.0))

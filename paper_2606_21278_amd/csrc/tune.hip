@@ -35,21 +35,28 @@ __device__ __forceinline__ uint32_t mix32(uint64_t v) {
   return (uint32_t)v;
 }
 
-// One workgroup per cell: a jittered square lattice in raster order over the
-// cell's window square (the point order of gridded terrain samples), smooth
-// heights and equal weights.  Every thread stays inside [off[c], off[c+1]).
+// One workgroup per cell: a jittered square lattice over the cell's window
+// square, smooth heights and equal weights.  In raster order (the point order
+// of gridded terrain samples), or with unordered set: stored point i takes
+// lattice site (i P) mod q for a prime P that does not divide q, a bijection
+// that scatters consecutive points across the cell (scattered samples).
+// Every thread stays inside [off[c], off[c+1]).
 template <typename T>
-__global__ void tune_points_kernel(const int64_t *off, const double *win, int use_win, T *x, T *y, T *h, T *w) {
+__global__ void tune_points_kernel(const int64_t *off, const double *win, int use_win, int unordered, T *x, T *y,
+                                   T *h, T *w) {
   const int64_t c = blockIdx.x;
   const int64_t a = off[c], b = off[c + 1];
   const int64_t q = b - a;
   if (q <= 0) return;
+  // q < 2^31 cannot be a multiple of both primes; i P < 2^61
+  const int64_t P = (q % 1000003 == 0) ? 998244353 : 1000003;
   const int64_t m = (int64_t)ceil(sqrt((double)q));
   double cx = 0.0, cy = 0.0, R = 3.0;
   if (use_win) { cx = win[3 * c]; cy = win[3 * c + 1]; R = win[3 * c + 2]; }
   const double d = 2.0 * R / (double)m;
   for (int64_t i = threadIdx.x; i < q; i += blockDim.x) {
-    const int64_t r = i / m, s = i - r * m;
+    const int64_t site = unordered ? (i * P) % q : i;
+    const int64_t r = site / m, s = site - r * m;
     const uint32_t hs = mix32((uint64_t)(a + i) * 0x9e3779b97f4a7c15ULL + 12345u);
     const double jx = ((hs & 0xffffu) * (1.0 / 65536.0) - 0.5) * 0.6;
     const double jy = ((hs >> 16) * (1.0 / 65536.0) - 0.5) * 0.6;
@@ -77,9 +84,9 @@ uint64_t fnv1a(const void *data, size_t n, uint64_t h = 1469598103934665603ULL) 
 std::string cache_key(enufft_plan_t p, const char *arch) {
   uint64_t hsh = fnv1a(p->offsets.data(), p->offsets.size() * sizeof(int64_t));
   char buf[320];
-  std::snprintf(buf, sizeof(buf), "%s_cu%d_p%d_m%dx%d_g%dx%d_w%d_win%d_c%lld_q%lld_h%016llx", arch, p->n_cu, p->prec,
-                p->N1, p->N2, p->n1, p->n2, p->W, p->window_kind, (long long)p->n_cells, (long long)p->n_points,
-                (unsigned long long)hsh);
+  std::snprintf(buf, sizeof(buf), "%s_cu%d_p%d_m%dx%d_g%dx%d_w%d_win%d_o%d_c%lld_q%lld_h%016llx", arch, p->n_cu,
+                p->prec, p->N1, p->N2, p->n1, p->n2, p->W, p->window_kind, p->opts.autotune == 2 ? 1 : 0,
+                (long long)p->n_cells, (long long)p->n_points, (unsigned long long)hsh);
   std::string k(buf);
   for (char &ch : k)
     if (ch == ' ' || ch == ':') ch = '-';
@@ -170,8 +177,9 @@ enufft_status time_calls(enufft_plan_t t, F fn, int reps, hipEvent_t e0, hipEven
   return ENUFFT_OK;
 }
 
-// Timed trials on plan t (the plan itself or a plan over a prefix of its cells).
-enufft_status run_trials(enufft_plan_t t, size_t lds_limit, Choice *best) {
+// Timed trials on plan t (the plan itself or a plan over a prefix of its cells),
+// on raster-ordered or unordered synthetic points.
+enufft_status run_trials(enufft_plan_t t, size_t lds_limit, int unordered, Choice *best) {
   const int64_t Q = t->n_points;
   const size_t el = t->elem;
   const int64_t M = (int64_t)t->N1 * t->N2;
@@ -194,11 +202,11 @@ enufft_status run_trials(enufft_plan_t t, size_t lds_limit, Choice *best) {
     const int use_win = t->window_kind == ENUFFT_WIN_HANN_RADIAL;
     if (t->prec == ENUFFT_F64)
       hipLaunchKernelGGL(tune_points_kernel<double>, dim3((unsigned)t->n_cells), dim3(256), 0, t->stream,
-                         (const int64_t *)off, (const double *)t->d_windows, use_win, (double *)x, (double *)y,
+                         (const int64_t *)off, (const double *)t->d_windows, use_win, unordered, (double *)x, (double *)y,
                          (double *)h, (double *)w);
     else
       hipLaunchKernelGGL(tune_points_kernel<float>, dim3((unsigned)t->n_cells), dim3(256), 0, t->stream,
-                         (const int64_t *)off, (const double *)t->d_windows, use_win, (float *)x, (float *)y,
+                         (const int64_t *)off, (const double *)t->d_windows, use_win, unordered, (float *)x, (float *)y,
                          (float *)h, (float *)w);
     e = hipGetLastError();
   }
@@ -275,6 +283,7 @@ enufft_status autotune(enufft_plan_t p) {
   if (p->n_cells == 0 || p->n_points == 0) return ENUFFT_OK;
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, p->device) != hipSuccess) return tune_err(p, ENUFFT_EDEVICE, "device query");
+  const int unordered = p->opts.autotune == 2;
   const std::string key = cache_key(p, prop.gcnArchName);
   const std::string path = cache_path();
   Choice c;
@@ -286,7 +295,7 @@ enufft_status autotune(enufft_plan_t p) {
     if (const char *s = std::getenv("ENUFFT_TUNE_MAX_POINTS")) cap = std::max<int64_t>(1 << 16, std::atoll(s));
     enufft_status st;
     if (p->n_points <= cap) {
-      st = run_trials(p, (size_t)prop.sharedMemPerBlock, &c);
+      st = run_trials(p, (size_t)prop.sharedMemPerBlock, unordered, &c);
     } else {
       int64_t nc = 0;
       while (nc < p->n_cells && p->offsets[nc + 1] <= cap) ++nc;
@@ -297,7 +306,7 @@ enufft_status autotune(enufft_plan_t p) {
       st = enufft_plan(&sub, nc, p->offsets.data(), p->windows_host.empty() ? nullptr : p->windows_host.data(), &o,
                        p->stream);
       if (st != ENUFFT_OK) return tune_err(p, st, std::string("prefix plan: ") + enufft_last_error(nullptr));
-      st = run_trials(sub, (size_t)prop.sharedMemPerBlock, &c);
+      st = run_trials(sub, (size_t)prop.sharedMemPerBlock, unordered, &c);
       if (st != ENUFFT_OK) p->last_error = sub->last_error;
       (void)enufft_destroy(sub);
     }

@@ -414,3 +414,13 @@ def test_autotune_choice_cached_and_correct(tmp_path, monkeypatch):
         assert rel_l2(c.cpu().numpy(), a.cpu().numpy()) < 1e-6
     ref = oracle_f(b.to(dtype=torch.float32))
     assert per_cell_rel_l2(f1.cpu().numpy(), ref).max() <= TOL["f32"]
+    # trials on unordered points: a cache entry of their own, the same results
+    un = make_plan(gb, autotune="unordered")
+    ui = un.info()
+    print("unordered", {k: ui[k] for k in ("tuned", "tune_cache_hit", "fwd_chunk_min", "fwd_items_per_slot",
+                                           "tune_fwd_ms")}, flush=True)
+    assert ui["tuned"] == 1 and ui["tune_cache_hit"] == 0
+    assert make_plan(gb, autotune="unordered").info()["tune_cache_hit"] == 1
+    f2 = un.type1(gb.x, gb.y, gb.h, gb.w)
+    torch.cuda.synchronize()
+    assert rel_l2(f2.cpu().numpy(), f0.cpu().numpy()) < 1e-6

@@ -76,6 +76,8 @@ def test_default_opts():
     (dict(window_kind=5), enf.EINVAL),
     (dict(windows=False), enf.EINVAL),                     # Hann needs windows
     (dict(kernel_width=40), enf.EINVAL),
+    (dict(autotune=3), enf.EINVAL),                        # 0, 1 (raster trials) or 2 (unordered)
+    (dict(autotune=-1), enf.EINVAL),
     (dict(n_modes=(2100, 64)), enf.EUNSUPPORTED),           # fine grid above 4096
 ])
 def test_plan_argument_errors(kw, code):
