@@ -571,7 +571,6 @@ enufft_status enufft_set_timing(enufft_plan_t p, int32_t enable) {
 
 enufft_status enufft_get_timing(enufft_plan_t p, double *out8) {
   if (!p || !out8) return fail(p, ENUFFT_EINVAL, "enufft_get_timing: null argument");
-  double *out6 = out8;
   for (int i = 0; i < 8; ++i) out8[i] = 0.0;
   enufft_status st = ENUFFT_OK;
   for (size_t i = 0; i < p->tim.start.size(); ++i) {
