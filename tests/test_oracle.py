@@ -347,6 +347,97 @@ def test_ems_ties_break_by_unit_id_and_edge_cases():
     assert r2.k_star == 3
 
 
+def _box3(values):
+    """3 x 3 mode box (k in {-1, 0, 1} per axis) from a dict {(kx, ky): |f|^2}."""
+    f = np.zeros((3, 3), dtype=np.complex128)
+    for (kx, ky), v in values.items():
+        f[ky + 1, kx + 1] = math.sqrt(v) * np.exp(1j * (0.3 + kx - 2 * ky))
+    return f
+
+
+def test_ems_weighted_hand_computed():
+    """Eq. (weighted_e) on a 3 x 3 box worked out by hand.  Mode powers |f|^2 (DC excluded):
+    (1,0) 4 and (-1,0) 4; (-1,1) 1 and (1,-1) 9; (0,1) 2 and (0,-1) 2; (1,1) 3 and (-1,-1) 1.
+    Weights: 0 on (1,-1), 3 on (1,1) and (-1,-1), 1 elsewhere.  Weighted pair energies
+    (each member's power times its own weight): (1,1) 3*3 + 3*1 = 12, (1,0) 8, (0,1) 4,
+    (-1,1) 1*1 + 0*9 = 1, total 25.  At alpha = 0.75 the running fractions are 0.48, 0.8,
+    so K* = 2; the kept power is the unweighted 3 + 1 + 4 + 4 = 12; N_eff = 25^2 / 225."""
+    pw = {(1, 0): 4, (-1, 0): 4, (-1, 1): 1, (1, -1): 9, (0, 1): 2, (0, -1): 2, (1, 1): 3, (-1, -1): 1,
+          (0, 0): 100}
+    f = _box3(pw)
+    om = np.ones((3, 3))
+    om[-1 + 1, 1 + 1] = 0.0          # (kx, ky) = (1, -1)
+    om[1 + 1, 1 + 1] = 3.0           # (1, 1)
+    om[-1 + 1, -1 + 1] = 3.0         # (-1, -1)
+    prm = oracle.EmsParams(alpha_min=0.75, alpha_max=0.75)
+    r = oracle.ems(f, prm, mode_weight=om)
+    assert r.k_star == 2
+    kept = {(ix - 1, iy - 1) for iy, ix in zip(*np.nonzero(r.keep))}
+    assert kept == {(1, 1), (-1, -1), (1, 0), (-1, 0)}
+    assert np.isclose(r.stats[0], 25.0, rtol=1e-15)
+    assert np.isclose(r.stats[1], 12.0, rtol=1e-15)
+    assert np.isclose(r.stats[2], 625.0 / 225.0, rtol=1e-14)
+    assert np.isclose(r.stats[6], 20.0 / 25.0, rtol=1e-15)
+    assert np.allclose(r.sorted_e, [12, 8, 4, 1], rtol=1e-14)
+    # unweighted for contrast: (-1,1) pair 10 leads, then 8, then the tie 4 / 4 broken by id
+    r0 = oracle.ems(f, prm)
+    assert np.allclose(r0.sorted_e, [10, 8, 4, 4], rtol=1e-14)
+    assert r0.sorted_id[2] == 2 * 3 + 1 and r0.sorted_id[3] == 2 * 3 + 2
+
+
+@pytest.mark.parametrize("use_pairs", [1, 0])
+def test_ems_weighted_equals_rescaled_coefficients(use_pairs):
+    """A weight omega_k >= 0 on every signed mode multiplies that mode's power, so the
+    weighted selection on f is the unweighted selection on sqrt(omega) f (same K*, kept
+    set, T, N_eff, S_delta, C, alpha_C, theta); the retained power P stays the plain
+    sum of |f_k|^2 over the kept modes.  Weights are asymmetric (omega_k != omega_-k)
+    and include zeros."""
+    Q = 600
+    x, y, h, w = _cell(Q, rng=np.random.default_rng(77))
+    f = oracle.type1([0, Q], x, y, h, w, np.array([0.0, 0.0, 3.0]), (12, 10))[0]
+    rng = np.random.default_rng(78)
+    om = rng.uniform(0.0, 2.0, size=f.shape)
+    om[rng.random(f.shape) < 0.1] = 0.0
+    for prm in (oracle.EmsParams(alpha_min=0.9, alpha_max=0.9, use_pairs=use_pairs),
+                oracle.EmsParams(k_min=2, k_max=15, alpha_min=0.1, alpha_max=0.8, delta=0.05,
+                                 use_pairs=use_pairs)):
+        rw = oracle.ems(f, prm, mode_weight=om)
+        rs = oracle.ems(np.sqrt(om) * f, prm)
+        assert rw.k_star == rs.k_star
+        assert np.array_equal(rw.keep, rs.keep)
+        assert np.array_equal(rw.sorted_id, rs.sorted_id)
+        assert np.allclose(rw.stats[[0, 2, 3, 4, 5, 6, 7]], rs.stats[[0, 2, 3, 4, 5, 6, 7]], rtol=1e-12)
+        assert np.isclose(rw.stats[1], np.sum(np.abs(f) ** 2 * rw.keep), rtol=1e-13)
+    # omega = 1 everywhere is the unweighted selection
+    r1 = oracle.ems(f, oracle.EmsParams(use_pairs=use_pairs), mode_weight=np.ones(f.shape))
+    r0 = oracle.ems(f, oracle.EmsParams(use_pairs=use_pairs))
+    assert r1.k_star == r0.k_star and np.array_equal(r1.keep, r0.keep)
+
+
+def test_ems_weighted_zero_and_scale():
+    """A zero weight on both members of the strongest pair moves it to the end of the
+    order (it is kept only if every other unit is); scaling all weights by one factor
+    changes no selection and scales T by that factor."""
+    Q = 500
+    x, y, h, w = _cell(Q, rng=np.random.default_rng(91))
+    f = oracle.type1([0, Q], x, y, h, w, np.array([0.0, 0.0, 3.0]), (8, 8))[0]
+    prm = oracle.EmsParams(alpha_min=0.8, alpha_max=0.8)
+    r0 = oracle.ems(f, prm)
+    top = int(r0.sorted_id[0])
+    iy, ix = divmod(top, 8)
+    kx, ky = ix - 4, iy - 4
+    om = np.ones((8, 8))
+    om[iy, ix] = 0.0
+    mirror = (-ky + 4, -kx + 4) if (-4 <= -kx <= 3 and -4 <= -ky <= 3) else (iy, ix)
+    om[mirror] = 0.0
+    r = oracle.ems(f, prm, mode_weight=om)
+    assert r.sorted_id[-1] == top and r.sorted_e[-1] == 0.0
+    assert not r.keep[iy, ix] and not r.keep[mirror]
+    rs = oracle.ems(f, prm, mode_weight=7.5 * np.ones((8, 8)))
+    assert rs.k_star == r0.k_star and np.array_equal(rs.keep, r0.keep)
+    assert np.isclose(rs.stats[0], 7.5 * r0.stats[0], rtol=1e-13)
+
+
 # ----------------------------------------------------------------------------- adjoint
 
 def test_vjp_adjoint_identity():

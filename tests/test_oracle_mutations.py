@@ -30,6 +30,13 @@ MUTATIONS = [
     ("EMS N_eff clip dropped", "w1 * nclip / (double)Jmax", "w1 * neff / (double)Jmax"),
     ("EMS threshold off by one", "if (run / tot >= alphaC) { kc = j + 1; break; }", "if (run / tot >= alphaC) { kc = j + 2; break; }"),
     ("EMS no pairing", "if (use_pairs && !(kx == 0 && ky == 0)) {", "if (0) {"),
+    ("EMS weight only on the representative",
+     "const double op = mode_weight ? mode_weight[partner] : 1.0;", "const double op = 1.0;"),
+    ("EMS weight squared",
+     "e += om * (f[2 * idx] * f[2 * idx] + f[2 * idx + 1] * f[2 * idx + 1]);",
+     "e += om * om * (f[2 * idx] * f[2 * idx] + f[2 * idx + 1] * f[2 * idx + 1]);"),
+    ("EMS weight dropped",
+     "const double om = mode_weight ? mode_weight[idx] : 1.0;", "const double om = 1.0;"),
     ("EMS k_min ignored", "int k = (kc > k_min) ? kc : k_min;", "int k = kc;"),
     ("adjoint x derivative sign", "sx += -kxv * im;", "sx += kxv * im;"),
     ("adjoint phase sign", "ey[2 * i + 1] = sin(k * y[j]);", "ey[2 * i + 1] = -sin(k * y[j]);"),
