@@ -13,9 +13,20 @@ deconvolve, crop), EMS, and the type-2 adjoint giving d(sum retained power) /
 d(h, x, y).  The JSON line reports NU points/s of type-1 + EMS (kernel time
 from HIP events on the plan's stream), the fwd+bwd step time, the per-cell
 launch loop on the same GPU, the forward kernel against the HBM roofline and
-the FP64 CPU oracle timed on a bounded sample of cells.  Parity of this exact
-launch configuration against the oracle is checked by the GPU test suite
-(full-size sampled cells), not here.
+the FP64 CPU oracle timed on a bounded sample of cells (all host threads, and one).
+
+Before anything is timed, the plan that is timed passes a parity gate: on a seeded
+sample of cells (the two largest, the two smallest and four others) its FP32
+coefficients must be within 5e-5 relative l2 of the FP64 oracle's per cell, its
+EMS selection must equal the oracle's on the same coefficients, and its adjoint
+must be within 5e-5 relative l2 of the oracle's; otherwise the script exits with
+status 3 and times nothing.
+
+Timing: the headline times type-1 + EMS as the captured HIP graph
+(enufft_forward_graph), one replay per step, with HIP events on the plan's stream
+around each replay; the adjoint follows each replay inside the timed steps.  A
+second, separate set of eager steps records HIP events around every kernel
+launch for the per-kernel breakdown and the forward kernel's roofline figure.
 
 Profiles: ``--summarize DIR`` turns rocprofv3 output collected from this script
 (kernel-trace stats CSV and FETCH_SIZE / WRITE_SIZE counter CSVs) into the
@@ -67,9 +78,22 @@ def measured_traffic():
     return rec.get("bytes_per_launch")
 
 
-def cpu_baseline(batch, seconds, seed=1):
+def _omp_threads(n):
+    """Set the OpenMP thread count of the oracle's runtime (None: leave it)."""
+    import ctypes
+    import ctypes.util
+    if n is None:
+        return int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    lib = ctypes.CDLL(ctypes.util.find_library("gomp") or "libgomp.so.1")
+    lib.omp_set_num_threads(int(n))
+    return int(n)
+
+
+def cpu_baseline(batch, seconds, seed=1, threads=None):
     """The FP64 oracle (type-1 direct sums + EMS) on a seeded sample of cells."""
     import oracle
+    oracle.type1([0, 0], np.zeros(0), np.zeros(0), np.zeros(0), np.zeros(0), [[0, 0, 1]], (2, 2))  # load
+    threads = _omp_threads(threads)
     cnt = batch.counts()
     rng = np.random.default_rng(seed)
     order = [int(c) for c in rng.permutation(batch.n_cells) if cnt[c] > 0]
@@ -94,7 +118,6 @@ def cpu_baseline(batch, seconds, seed=1):
                      kind=inp["kind"])
     oracle.ems_batched(f, oracle.EmsParams())
     dt = time.perf_counter() - t0
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {"value": pts / dt, "unit": "NU points/s", "cores": threads, "kind": "oracle",
             "sample": "%d seeded cells, %d points, type-1 direct sums + EMS, %.1f s" % (len(cells), pts, dt)}
 
@@ -196,6 +219,60 @@ def bench_c4(args, torch, enf, synth, dev):
         "per_cell_loop": None, "roofline": roofline, "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+
+
+def make_plan(enf, gb, workload="c3", shuffled=False, autotune=True):
+    """The plan this script times.  The autotuner's trial points follow the workload's
+    point order: the icosahedral cells store their samples in raster order, the
+    hexagons (and the shuffled variant) in no spatial order."""
+    tune = ("unordered" if (workload == "c1" or shuffled) else "raster") if autotune else False
+    return enf.Plan(gb.cell_offsets, gb.windows, n_modes=gb.n_modes, sigma=gb.sigma, eps=gb.eps, precision="f32",
+                    autotune=tune)
+
+
+def gate_cells(counts, seed=7, n_random=4):
+    """The parity gate's cells: the two largest, the two smallest non-empty and
+    n_random seeded others."""
+    order = [int(c) for c in np.argsort(counts, kind="stable") if counts[c] > 0]
+    rng = np.random.default_rng(seed)
+    rest = [c for c in order[2:-2]]
+    pick = [int(c) for c in rng.choice(rest, size=min(n_random, len(rest)), replace=False)] if rest else []
+    return sorted(set(order[-2:] + order[:2] + pick))
+
+
+def parity_gate(plan, gb, prm, torch, tol=5e-5):
+    """Run the timed plan once (type-1, EMS, retained-power adjoint) and check a
+    seeded sample of cells against the FP64 oracle: per-cell rel-l2 of the
+    coefficients, the EMS selection on the same coefficients (exact), and the
+    adjoint's rel-l2 per gradient component over the sample's points."""
+    import oracle
+    cells = gate_cells(gb.counts())
+    f = plan.type1(gb.x, gb.y, gb.h, gb.w)
+    keep, ks, st = plan.ems(f, prm)
+    gh, gx, gy = plan.retained_power_adjoint(gb.x, gb.y, gb.h, gb.w, f, keep)
+    torch.cuda.synchronize()
+    sub = gb.subset(cells).to(device="cpu")
+    inp = oracle.batch_inputs(sub)
+    ref = oracle.type1(inp["offsets"], inp["x"], inp["y"], inp["h"], inp["w"], inp["windows"], inp["n_modes"],
+                       kind=inp["kind"])
+    fg = f[cells].cpu().numpy().astype(np.complex128)
+    rel = [float(np.linalg.norm(fg[i] - ref[i]) / max(np.linalg.norm(ref[i]), 1e-300)) for i in range(len(cells))]
+    oprm = oracle.EmsParams(**{k: getattr(prm, k) for k in oracle.EmsParams.__dataclass_fields__})
+    ok_keep, ok_ks, _ = oracle.ems_batched(fg, oprm)
+    ems_ok = bool(np.array_equal(ok_ks, ks[cells].cpu().numpy()) and
+                  np.array_equal(ok_keep, keep[cells].cpu().numpy()))
+    g = 2.0 * fg * ok_keep
+    rh, rx, ry = oracle.type1_vjp(inp["offsets"], inp["x"], inp["y"], inp["h"], inp["w"], inp["windows"],
+                                  inp["n_modes"], g, kind=inp["kind"])
+    idx = np.concatenate([np.arange(gb.cell_offsets[c], gb.cell_offsets[c + 1]) for c in cells])
+    it = torch.as_tensor(idx, device=gb.x.device)
+    grel = {}
+    for name, got, want in (("h", gh, rh), ("x", gx, rx), ("y", gy, ry)):
+        a = got[it].cpu().double().numpy()
+        grel[name] = float(np.linalg.norm(a - want) / max(np.linalg.norm(want), 1e-300))
+    ok = max(rel) <= tol and ems_ok and max(grel.values()) <= tol
+    return {"pass": bool(ok), "cells": cells, "points": int(len(idx)), "coef_rel_l2_max": max(rel),
+            "ems_identical": ems_ok, "grad_rel_l2": grel, "tol": tol}
 
 
 # ------------------------------------------------------------------ profile summaries
@@ -336,46 +413,68 @@ def main():
     gb = batch.to(device=dev, dtype=torch.float32)
     del batch.x, batch.y, batch.h, batch.w
     batch.x, batch.y, batch.h, batch.w = gb.x, gb.y, gb.h, gb.w
-    # the autotuner's trial points follow the workload's point order: C3 stores each
-    # cell's samples in raster order, C1 (and C3 --shuffled) in no spatial order
-    tune = ("unordered" if (c1 or args.shuffled) else "raster") if args.autotune else False
-    plan = enf.Plan(gb.cell_offsets, gb.windows, n_modes=gb.n_modes, sigma=gb.sigma, eps=gb.eps, precision="f32",
-                    autotune=tune)
+    plan = make_plan(enf, gb, "c1" if c1 else "c3", args.shuffled, args.autotune)
     info = plan.info()
     log("plan", info)
     prm = enf.EmsParams()
     Q = batch.n_points
     M = gb.n_modes[0] * gb.n_modes[1]
 
-    def step():
-        f = plan.type1(gb.x, gb.y, gb.h, gb.w)
-        keep, ks, st = plan.ems(f, prm)
-        grads = plan.retained_power_adjoint(gb.x, gb.y, gb.h, gb.w, f, keep)
-        return f, keep, ks, st, grads
+    gate = parity_gate(plan, gb, prm, torch)
+    log("parity gate", gate)
+    if not gate["pass"]:
+        log("parity gate FAILED: nothing is timed")
+        sys.exit(3)
+
+    # headline: type-1 + EMS as one captured graph per step, then the adjoint
+    out_t = (plan.empty_modes(), torch.empty((gb.n_cells, gb.n_modes[1], gb.n_modes[0]), dtype=torch.uint8,
+                                             device=dev),
+             torch.empty(gb.n_cells, dtype=torch.int32, device=dev),
+             torch.empty((gb.n_cells, 8), dtype=torch.float64, device=dev))
+
+    def step_graph():
+        plan.forward_graph(gb.x, gb.y, gb.h, gb.w, prm, out=out_t)
+
+    def step_adjoint():
+        return plan.retained_power_adjoint(gb.x, gb.y, gb.h, gb.w, out_t[0], out_t[1])
 
     for i in range(args.warmup):
-        step()
+        step_graph()
+        step_adjoint()
         torch.cuda.synchronize()
         log("warm-up step %d done" % (i + 1))
-    plan.get_timing()          # discard warm-up records
-    plan.set_timing(True)
     stream = torch.cuda.current_stream()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
     torch.cuda.synchronize()
-    e0.record(stream)
+    for i in range(args.steps):
+        ev[i][0].record(stream)
+        step_graph()
+        ev[i][1].record(stream)
+        step_adjoint()
+        ev[i][2].record(stream)
+    torch.cuda.synchronize()
+    ms_step = ev[0][0].elapsed_time(ev[-1][2]) / args.steps
+    graph_ms = np.array([e[0].elapsed_time(e[1]) for e in ev])
+    adj_step_ms = np.array([e[1].elapsed_time(e[2]) for e in ev])
+    t_fwd = float(np.median(graph_ms))
+    value = Q / (t_fwd * 1e-3)
+    log("graph type-1 + EMS: median %.3f ms (min %.3f, max %.3f); adjoint %.3f ms; step %.3f ms"
+        % (t_fwd, graph_ms.min(), graph_ms.max(), float(np.median(adj_step_ms)), ms_step))
+
+    # breakdown: eager launches with HIP events around every kernel launch
+    plan.get_timing()
+    plan.set_timing(True)
     for _ in range(args.steps):
-        step()
-    e1.record(stream)
+        f = plan.type1(gb.x, gb.y, gb.h, gb.w)
+        keep, ks, st = plan.ems(f, prm)
+        plan.retained_power_adjoint(gb.x, gb.y, gb.h, gb.w, f, keep)
     torch.cuda.synchronize()
     plan.set_timing(False)
-    ms_step = e0.elapsed_time(e1) / args.steps
     tm = plan.get_timing()
     t1 = tm["type1_ms"] / max(1, tm["type1_launches"])
     tems = tm["ems_ms"] / max(1, tm["ems_launches"])
     tadj = tm["adjoint_ms"] / max(1, tm["adjoint_launches"])
-    value = Q / ((t1 + tems) * 1e-3)
-    log("per step: type1 %.3f ms, ems %.3f ms, adjoint %.3f ms, step %.3f ms" % (t1, tems, tadj, ms_step))
+    log("eager per launch: type1 %.3f ms, ems %.3f ms, adjoint %.3f ms" % (t1, tems, tadj))
 
     if args.calibrate_copy > 0:
         # one streaming kernel of known traffic whose name no other kernel of this run shares
@@ -400,7 +499,7 @@ def main():
         torch.cuda.synchronize()
         pc_ms = a.elapsed_time(b)
         percell = {"value": Q / (pc_ms * 1e-3), "unit": "NU points/s", "ms": pc_ms,
-                   "launches": 2 * batch.n_cells}
+                   "launches": 2 * batch.n_cells, "batched_speedup": pc_ms / t_fwd}
         log("per-cell loop %.1f ms" % pc_ms)
 
     # algorithmic bytes of one forward launch: read x, y, h, w (16 B per point), write f (8 B per mode)
@@ -410,10 +509,12 @@ def main():
     roofline = {"bound": "hbm", "achieved": achieved, "peak": 8000.0, "unit": "GB/s",
                 "frac": achieved / 8000.0, "traffic": traffic, "kernel": "fwd_kernel (spread+FFT+deconv+crop)",
                 "bytes_per_launch": fwd_bytes, "avg_launch_ms": t1}
-    cpu = None
+    cpu = cpu1 = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(batch, args.cpu_seconds)
         log("cpu baseline", cpu)
+        cpu1 = cpu_baseline(batch, args.cpu_seconds / 2, seed=2, threads=1)
+        log("cpu baseline, one thread", cpu1)
     out = {
         "metric": "NU points/s batched type-1+EMS at rel-l2 5e-5 vs per-cell loop; fwd+bwd ms",
         "value": value, "unit": "NU points/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -429,7 +530,13 @@ def main():
                    "kernel_width": info["kernel_width"], "grid": info["grid"],
                    "fwd_threads": info["fwd_threads"], "autotuned": bool(info["tuned"])},
         "type1_ms": t1, "ems_ms": tems, "adjoint_ms": tadj, "fwd_bwd_ms": ms_step,
-        "per_cell_loop": percell, "roofline": roofline, "cpu_baseline": cpu,
+        "graph_type1_ems_ms": {"median": t_fwd, "mean": float(graph_ms.mean()), "min": float(graph_ms.min()),
+                               "max": float(graph_ms.max())},
+        "adjoint_in_step_ms": float(np.median(adj_step_ms)),
+        "parity_gate": gate, "plan": {k: info[k] for k in ("fwd_threads", "fwd_chunk_min", "fwd_items_per_slot",
+                                                           "adj_items_per_slot", "adj_band_mult", "n_items_fwd",
+                                                           "n_split_cells", "n_items_adj", "tuned")},
+        "per_cell_loop": percell, "roofline": roofline, "cpu_baseline": cpu, "cpu_baseline_1core": cpu1,
     }
     print(json.dumps(out), flush=True)
 

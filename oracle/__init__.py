@@ -60,6 +60,8 @@ def _load():
         L.oracle_strength.argtypes = [ctypes.c_int64, _dp, _dp, _dp, _dp, ctypes.c_int, _dp, _dp]
         L.oracle_type1_modes.argtypes = [ctypes.c_int64, _dp, _dp, _dp, ctypes.c_int64, _i32p, _i32p,
                                          ctypes.c_double, _dp]
+        L.oracle_type1_axes.argtypes = [ctypes.c_int64, _dp, _dp, _dp, ctypes.c_int, _i32p, ctypes.c_int, _i32p,
+                                        ctypes.c_double, _dp]
         L.oracle_ems.argtypes = [ctypes.c_int, ctypes.c_int, _dp, ctypes.c_int, ctypes.c_int,
                                  ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                  ctypes.c_double, ctypes.c_int, ctypes.c_int, _dp, _u8p, _i32p, _dp,
@@ -138,6 +140,18 @@ def type1_modes(x, y, c, kx, ky, scale=1.0) -> np.ndarray:
     L.oracle_type1_modes(len(x), px, py, pc, len(kx), kx.ctypes.data_as(_i32p), ky.ctypes.data_as(_i32p),
                          float(scale), out.ctypes.data_as(_dp))
     return out[:, 0] + 1j * out[:, 1]
+
+
+def type1_axes(x, y, c, kx_list, ky_list, scale=1.0) -> np.ndarray:
+    """Direct sums on the product set ky_list x kx_list of integer modes for given
+    strengths c -> complex128 [len(ky_list), len(kx_list)]."""
+    L = _load()
+    x, px = _d(x); y, py = _d(y); c, pc = _d(c)
+    kx = np.ascontiguousarray(kx_list, dtype=np.int32); ky = np.ascontiguousarray(ky_list, dtype=np.int32)
+    out = np.zeros((len(ky), len(kx), 2))
+    L.oracle_type1_axes(len(x), px, py, pc, len(kx), kx.ctypes.data_as(_i32p), len(ky), ky.ctypes.data_as(_i32p),
+                        float(scale), out.ctypes.data_as(_dp))
+    return out[..., 0] + 1j * out[..., 1]
 
 
 @dataclass

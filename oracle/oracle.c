@@ -14,6 +14,7 @@
  *                        term -- the exact result the NUFFT approximates
  *                        (Section 2.1.2, eqs. spreading..deconv).
  *   oracle_type1_modes   the same sum at an arbitrary list of integer modes.
+ *   oracle_type1_axes    the same sum on a product set of listed modes per axis.
  *   oracle_ems           Elastic Mode Selection, Section 2.2 eqs. (energy),
  *                        (sorted_energy), (n_eff), (s_delta), (c_score),
  *                        (alpha_c), (f_cum), (k_elastic), in the paper's order.
@@ -177,6 +178,66 @@ void oracle_type1_modes(int64_t n, const double *x, const double *y, const doubl
         out[2 * m] = scale * sr;
         out[2 * m + 1] = scale * si;
     }
+}
+
+/* The same sum on a product set of listed integer modes: for every ky in ky_list
+ * (n2 entries) and kx in kx_list (n1 entries),
+ *   out[r][i] = scale * sum_j c_j exp(-i (kx_list[i] x_j + ky_list[r] y_j)),
+ * interleaved (re, im), row-major with ky slow.  Per point the per-axis exponentials
+ * are direct sin/cos of k * x; points are summed in blocks of BLK whose partial sums
+ * are added in block order (independent of the thread count). */
+void oracle_type1_axes(int64_t n, const double *x, const double *y, const double *c,
+                       int n1, const int32_t *kx_list, int n2, const int32_t *ky_list,
+                       double scale, double *out)
+{
+    const int64_t M = (int64_t)n1 * n2;
+    const int64_t nb = (n + BLK - 1) / BLK;
+    memset(out, 0, sizeof(double) * 2 * M);
+    int64_t group = PART_BYTES_MAX / (int64_t)(sizeof(double) * 2 * M);
+    if (group < 1) group = 1;
+    for (int64_t g0 = 0; g0 < nb; g0 += group) {
+        const int64_t g1 = (g0 + group < nb) ? g0 + group : nb;
+        double *part = (double *)calloc((size_t)((g1 - g0) * 2 * M), sizeof(double));
+        #pragma omp parallel
+        {
+            double *ex = (double *)malloc(sizeof(double) * 2 * n1);
+            double *ey = (double *)malloc(sizeof(double) * 2 * n2);
+            #pragma omp for schedule(dynamic, 1)
+            for (int64_t blk = g0; blk < g1; ++blk) {
+                double *acc = part + (blk - g0) * 2 * M;
+                const int64_t j0 = blk * BLK;
+                const int64_t j1 = (j0 + BLK < n) ? j0 + BLK : n;
+                for (int64_t j = j0; j < j1; ++j) {
+                    if (c[j] == 0.0) continue;
+                    for (int i = 0; i < n1; ++i) {
+                        const double ph = (double)kx_list[i] * x[j];
+                        ex[2 * i] = cos(ph);
+                        ex[2 * i + 1] = -sin(ph);
+                    }
+                    for (int r = 0; r < n2; ++r) {
+                        const double ph = (double)ky_list[r] * y[j];
+                        ey[2 * r] = c[j] * cos(ph);
+                        ey[2 * r + 1] = -c[j] * sin(ph);
+                    }
+                    for (int r = 0; r < n2; ++r) {
+                        const double yr = ey[2 * r], yi = ey[2 * r + 1];
+                        double *dst = acc + 2 * (int64_t)r * n1;
+                        for (int i = 0; i < n1; ++i) {
+                            const double xr = ex[2 * i], xi = ex[2 * i + 1];
+                            dst[2 * i] += yr * xr - yi * xi;
+                            dst[2 * i + 1] += yr * xi + yi * xr;
+                        }
+                    }
+                }
+            }
+            free(ex);
+            free(ey);
+        }
+        for (int64_t blk = g0; blk < g1; ++blk)
+            for (int64_t m = 0; m < 2 * M; ++m) out[m] += part[(blk - g0) * 2 * M + m];
+        free(part);
+    }
+    for (int64_t q = 0; q < 2 * M; ++q) out[q] *= scale;
 }
 
 /* --------------------------------------------------------------------- EMS */

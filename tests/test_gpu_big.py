@@ -100,6 +100,25 @@ def test_big_ems_on_identical_coefficients(prm):
     assert np.allclose(st, ok_st, rtol=1e-11, atol=0)
 
 
+def test_big_ems_weighted_on_identical_coefficients():
+    """Eq. (weighted_e) on the device-sort path (above 4,096 units per cell): asymmetric
+    per-mode weights with zeros give the oracle's selection exactly."""
+    ref = oracle_f(synth.config4(Q=4000, precision="f64", n_modes=(128, 96)))
+    rng = np.random.default_rng(41)
+    om = rng.uniform(0.0, 2.0, size=ref.shape[1:])
+    om[rng.random(om.shape) < 0.1] = 0.0
+    plan = _ems_plan_for(ref, "f64")
+    for prm in (oracle.EmsParams(), oracle.EmsParams(use_pairs=0, exclude_dc=0, alpha_min=0.9, alpha_max=0.9)):
+        keep, ks, st = plan.ems(torch.from_numpy(ref).to("cuda:0"), enf.EmsParams(**prm.__dict__),
+                                mode_weight=torch.from_numpy(om))
+        ok_keep, ok_ks, ok_st = oracle.ems_batched(ref, prm, mode_weight=om)
+        print("weighted k_star", ks.cpu().numpy(), ok_ks, "J", st[:, 7].cpu().numpy(), flush=True)
+        assert st[0, 7].item() > 4096
+        assert np.array_equal(ks.cpu().numpy(), ok_ks)
+        assert np.array_equal(keep.cpu().numpy(), ok_keep)
+        assert np.allclose(st.cpu().numpy(), ok_st, rtol=1e-11, atol=0)
+
+
 def test_big_ems_ties_at_the_cut():
     """Many units share each energy level, so the cut splits a run of equal energies:
     the kept ones are the tied units of lowest id, as in the oracle.  Coefficients are
@@ -187,24 +206,19 @@ def test_big_forward_graph_replays_match_eager():
 
 # ----------------------------------------------------------- the full high-resolution cell
 
-def _sample_modes(N1, N2, n_rand, seed):
-    lo1, lo2 = -(N1 // 2), -(N2 // 2)
-    kx, ky = np.meshgrid(np.arange(-2, 2), np.arange(-2, 2))
-    rng = np.random.default_rng(seed)
-    rx = rng.integers(lo1, lo1 + N1, size=n_rand)
-    ry = rng.integers(lo2, lo2 + N2, size=n_rand)
-    return (np.concatenate([kx.ravel(), rx, [lo1, lo1 + N1 - 1]]).astype(np.int32),
-            np.concatenate([ky.ravel(), ry, [lo2, lo2 + N2 - 1]]).astype(np.int32))
-
-
 @pytest.mark.parametrize("prec", ["f32", "f64"])
 def test_full_c4_sampled(prec):
-    """1e8 clustered points, 512 x 512 modes: coefficients on 66 sampled modes (the
-    central 4 x 4, 48 seeded random ones, two corners), EMS on the GPU's own
-    coefficients, and gradients on 2,048 seeded points."""
+    """1e8 clustered points, 512 x 512 modes.  Coefficients on a central block of the box
+    and on a seeded product set of random rows and columns over the whole box (direct
+    sums on that set), EMS on the GPU's own coefficients, and gradients on 2,048 seeded
+    points.  Default sample: the central 32 x 32 modes and 8 x 32 random ones;
+    ENUFFT_C4_SPEC_SAMPLE=1 takes the central 64 x 64 and 16 x 256 = 4,096 random modes
+    (about two minutes of oracle time on 16 host threads)."""
+    import os
+    spec = os.environ.get("ENUFFT_C4_SPEC_SAMPLE") == "1"
     dev = torch.device("cuda:0")
     b = synth.config4(device=dev, precision=prec, progress=lambda m: print(m, flush=True))
-    print("C4", prec, b.n_points, flush=True)
+    print("C4", prec, b.n_points, "spec sample" if spec else "default sample", flush=True)
     plan = make_plan(b)
     f = plan.type1(b.x, b.y, b.h, b.w)
     keep, ks, st = plan.ems(f)
@@ -214,18 +228,27 @@ def test_full_c4_sampled(prec):
     N1, N2 = b.n_modes
     fg = f[0].cpu().numpy().astype(np.complex128)
     kg = keep[0].cpu().numpy()
-    kx, ky = _sample_modes(N1, N2, 48, 404)
     x = b.x.cpu().numpy().astype(np.float64)
     y = b.y.cpu().numpy().astype(np.float64)
     h = b.h.cpu().numpy().astype(np.float64)
     w = b.w.cpu().numpy().astype(np.float64)
     c = oracle.strength(x, y, h, w, b.windows[0])
-    print("oracle: direct sums at sampled modes", flush=True)
-    ref = oracle.type1_modes(x, y, c, kx, ky)
-    got = fg[ky - (-(N2 // 2)), kx - (-(N1 // 2))]
-    err = rel_l2(got, ref)
-    print("sampled-mode rel-l2 %.3e" % err, flush=True)
-    assert err <= TOL[prec]
+    lo1, lo2 = -(N1 // 2), -(N2 // 2)
+    nc, nr, ncol = (64, 16, 256) if spec else (32, 8, 32)
+    rng = np.random.default_rng(404)
+    blocks = [(np.arange(-nc // 2, nc // 2), np.arange(-nc // 2, nc // 2)),
+              # random columns and rows, with the box's first and last ones among them
+              (np.unique(np.concatenate([[lo1, lo1 + N1 - 1],
+                                         rng.choice(np.arange(lo1 + 1, lo1 + N1 - 1), ncol - 2, replace=False)])),
+               np.unique(np.concatenate([[lo2, lo2 + N2 - 1],
+                                         rng.choice(np.arange(lo2 + 1, lo2 + N2 - 1), nr - 2, replace=False)])))]
+    for name, (kxl, kyl) in zip(("central", "random rows x columns"), blocks):
+        print("oracle: direct sums on %s, %d x %d modes" % (name, len(kyl), len(kxl)), flush=True)
+        ref = oracle.type1_axes(x, y, c, kxl, kyl)
+        got = fg[np.ix_(kyl - lo2, kxl - lo1)]
+        err = rel_l2(got, ref)
+        print("%s rel-l2 %.3e" % (name, err), flush=True)
+        assert err <= TOL[prec]
     # EMS on the GPU's own coefficients
     r = oracle.ems(fg, oracle.EmsParams())
     print("k_star", int(ks[0]), r.k_star, flush=True)

@@ -1,16 +1,24 @@
-"""GPU parity at full size: the 20,480-cell icosahedral workload (~8e8 points) in
-the launch configuration bench.py times (default plan, one persistent launch),
-checked against the FP64 oracle on a seeded sample of cells that includes the
-two largest and the two smallest ones.
+"""GPU parity at full size: the 20,480-cell icosahedral workload (~8e8 points) with
+the plan bench.py times (bench.make_plan: the autotuner with trials on raster-ordered
+points), checked against the FP64 oracle on 64 seeded cells: the 8 largest, the 8
+smallest and 48 others.
 
-Tolerances as in test_gpu_parity: rel-l2 <= 5e-5 per cell on the coefficients,
-identical EMS selections on the GPU's own coefficients (and on the oracle's where
-the selection is robust to the measured deviation), adjoint gradients <= 5e-5
-rel-l2 over the sampled cells' points."""
+Checks, per the tolerances of test_gpu_parity:
+  - coefficients: rel-l2 <= 5e-5 for every sampled cell; the graph-captured
+    type-1 + EMS that the benchmark times gives the eager launches' results;
+  - EMS: on the GPU's own coefficients the selection equals the oracle's exactly
+    (every cell); against the oracle's FP64 coefficients the kept sets are identical
+    on every cell whose selection is robust to the measured coefficient deviation
+    ('inputs without ties'), and the number of excluded cells is reported and
+    bounded;
+  - adjoint: with the GPU's coefficients and kept set as the cotangent, rel-l2 <=
+    5e-5 per gradient component; end to end (oracle coefficients and selection) on
+    the cells whose kept set is identical, likewise."""
 import numpy as np
 import pytest
 import torch
 
+import bench
 import oracle
 import paper_2606_21278_amd as enf
 import synth
@@ -26,37 +34,55 @@ def full_c3():
     dev = torch.device("cuda:0")
     b = synth.config3(device=dev)
     gb = b.to(device=dev, dtype=torch.float32)
-    plan = enf.Plan(gb.cell_offsets, gb.windows, n_modes=gb.n_modes, sigma=gb.sigma, eps=gb.eps, precision="f32")
+    del b
+    plan = bench.make_plan(enf, gb, "c3", shuffled=False, autotune=True)
+    info = plan.info()
+    print("plan", {k: info[k] for k in ("tuned", "tune_cache_hit", "fwd_threads", "fwd_chunk_min",
+                                        "fwd_items_per_slot", "adj_items_per_slot", "adj_band_mult",
+                                        "n_items_fwd", "n_split_cells")}, flush=True)
+    assert info["tuned"] == 1
     f = plan.type1(gb.x, gb.y, gb.h, gb.w)
     keep, ks, st = plan.ems(f)
     gh, gx, gy = plan.retained_power_adjoint(gb.x, gb.y, gb.h, gb.w, f, keep)
+    out_g = (plan.empty_modes(), torch.empty_like(keep), torch.empty_like(ks), torch.empty_like(st))
+    plan.forward_graph(gb.x, gb.y, gb.h, gb.w, out=out_g)
+    plan.forward_graph(gb.x, gb.y, gb.h, gb.w, out=out_g)
     torch.cuda.synchronize()
+    # the replay equals the eager launches up to the order of the spreading's atomic adds
+    graph_dev = float((torch.linalg.vector_norm(out_g[0] - f) / torch.linalg.vector_norm(f)).item())
+    graph_ks_same = float((out_g[2] == ks).double().mean().item())
     cnt = gb.counts()
+    order = [int(c) for c in np.argsort(cnt, kind="stable")]
     rng = np.random.default_rng(2024)
-    order = np.argsort(cnt)
-    cells = sorted(set([int(order[-1]), int(order[-2]), int(order[0]), int(order[1])] +
-                       [int(c) for c in rng.choice(gb.n_cells, 8, replace=False)]))
-    print("sampled cells", cells, "points", [int(cnt[c]) for c in cells], "info", plan.info(), flush=True)
+    mid = order[8:-8]
+    cells = sorted(set(order[-8:] + order[:8] + [int(c) for c in rng.choice(mid, 48, replace=False)]))
+    print("sampled cells: %d, points %d (largest %d, smallest %d)"
+          % (len(cells), int(cnt[cells].sum()), int(cnt[cells].max()), int(cnt[cells].min())), flush=True)
     sub = gb.subset(cells).to(device="cpu", dtype=torch.float32)
     idx = np.concatenate([np.arange(gb.cell_offsets[c], gb.cell_offsets[c + 1]) for c in cells])
     it = torch.as_tensor(idx, device=dev)
     out = {
-        "cells": cells, "sub": sub, "info": plan.info(),
+        "cells": cells, "sub": sub, "info": info, "graph_dev": graph_dev, "graph_ks_same": graph_ks_same,
         "f": f[cells].cpu().numpy().astype(np.complex128),
         "keep": keep[cells].cpu().numpy(), "ks": ks[cells].cpu().numpy(), "st": st[cells].cpu().numpy(),
         "gh": gh[it].cpu().numpy(), "gx": gx[it].cpu().numpy(), "gy": gy[it].cpu().numpy(),
     }
-    del f, keep, ks, st, gh, gx, gy, plan, gb, b
+    del f, keep, ks, st, gh, gx, gy, plan, gb, out_g
     torch.cuda.empty_cache()
+    inp = oracle.batch_inputs(sub)
+    out["args"] = {k: inp[k] for k in ("offsets", "x", "y", "h", "w", "windows", "n_modes")} | {"kind": inp["kind"]}
+    out["ref"] = oracle.type1(**out["args"])
     return out
 
 
 def test_full_c3_coefficients_on_sampled_cells(full_c3):
     print("items", full_c3["info"]["n_items_fwd"], "split cells", full_c3["info"]["n_split_cells"], flush=True)
-    ref = oracle.type1(**_oracle_args(full_c3["sub"]))
-    err = per_cell_rel_l2(full_c3["f"], ref)
-    print("per-cell rel-l2", ["%.2e" % e for e in err], flush=True)
+    err = per_cell_rel_l2(full_c3["f"], full_c3["ref"])
+    print("per-cell rel-l2: max %.2e median %.2e" % (err.max(), np.median(err)), flush=True)
     assert err.max() <= TOL
+    print("graph replay vs eager: rel-l2 %.2e, K* equal on %.4f of the cells"
+          % (full_c3["graph_dev"], full_c3["graph_ks_same"]), flush=True)
+    assert full_c3["graph_dev"] <= 1e-6 and full_c3["graph_ks_same"] >= 0.99
 
 
 def test_full_c3_ems_on_sampled_cells(full_c3):
@@ -66,27 +92,50 @@ def test_full_c3_ems_on_sampled_cells(full_c3):
     assert np.array_equal(full_c3["ks"], ok_ks)
     assert np.array_equal(full_c3["keep"], ok_keep)
     assert np.allclose(full_c3["st"], ok_st, rtol=1e-9, atol=0)
-    ref = oracle.type1(**_oracle_args(full_c3["sub"]))
-    n_rb = 0
-    for i in range(len(full_c3["cells"])):
+    ref = full_c3["ref"]
+    n = len(full_c3["cells"])
+    robust, same_set = 0, 0
+    for i in range(n):
         r = oracle.ems(ref[i], prm)
+        same_set += int(np.array_equal(full_c3["keep"][i], r.keep))
         if robust_selection(ref[i], fg[i], r, prm):
-            n_rb += 1
-            assert full_c3["ks"][i] == r.k_star
-            assert np.array_equal(full_c3["keep"][i], r.keep)
-    print("robust cells", n_rb, "of", len(full_c3["cells"]), flush=True)
+            robust += 1
+            assert full_c3["ks"][i] == r.k_star, i
+            assert np.array_equal(full_c3["keep"][i], r.keep), i
+        else:
+            # a near-tie at this resolution: the GPU's set is still a valid selection of
+            # nearly the same size and power
+            assert abs(int(full_c3["ks"][i]) - r.k_star) <= max(2, r.k_star // 100), i
+    print("EMS: robust cells %d of %d (excluded as near-ties: %d); identical kept sets %d of %d"
+          % (robust, n, n - robust, same_set, n), flush=True)
+    assert robust >= 0.75 * n
 
 
 def test_full_c3_adjoint_on_sampled_cells(full_c3):
-    a = _oracle_args(full_c3["sub"])
+    a = full_c3["args"]
     g = 2.0 * full_c3["f"] * full_c3["keep"]
-    rh, rx, ry = oracle.type1_vjp(a["offsets"], a["x"], a["y"], a["h"], a["w"], a["windows"], a["n_modes"], g)
+    rh, rx, ry = oracle.type1_vjp(a["offsets"], a["x"], a["y"], a["h"], a["w"], a["windows"], a["n_modes"], g,
+                                  kind=a["kind"])
     for name, got, want in (("h", full_c3["gh"], rh), ("x", full_c3["gx"], rx), ("y", full_c3["gy"], ry)):
         e = rel_l2(got.astype(np.float64), want)
         print("grad_%s rel-l2 %.3e" % (name, e), flush=True)
         assert e <= TOL
 
 
-def _oracle_args(sub):
-    inp = oracle.batch_inputs(sub)
-    return {k: inp[k] for k in ("offsets", "x", "y", "h", "w", "windows", "n_modes")} | {"kind": inp["kind"]}
+def test_full_c3_gradients_end_to_end(full_c3):
+    """The oracle's own pipeline (FP64 coefficients, its selection, its VJP) against the
+    GPU's gradients on the cells whose kept set is identical."""
+    a = full_c3["args"]
+    ref = full_c3["ref"]
+    ok_keep, _, _ = oracle.ems_batched(ref, oracle.EmsParams())
+    same = np.array([np.array_equal(ok_keep[i], full_c3["keep"][i]) for i in range(len(full_c3["cells"]))])
+    g = 2.0 * ref * ok_keep * same[:, None, None]
+    rh, rx, ry = oracle.type1_vjp(a["offsets"], a["x"], a["y"], a["h"], a["w"], a["windows"], a["n_modes"], g,
+                                  kind=a["kind"])
+    mask = np.repeat(same, np.diff(a["offsets"]))
+    print("cells with identical kept sets: %d of %d" % (same.sum(), len(same)), flush=True)
+    assert same.mean() >= 0.75
+    for name, got, want in (("h", full_c3["gh"], rh), ("x", full_c3["gx"], rx), ("y", full_c3["gy"], ry)):
+        e = rel_l2(got.astype(np.float64)[mask], want[mask])
+        print("end-to-end grad_%s rel-l2 %.3e" % (name, e), flush=True)
+        assert e <= TOL

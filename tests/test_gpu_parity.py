@@ -207,6 +207,31 @@ def test_ems_on_identical_coefficients(prm):
     assert np.allclose(st, ok_st, rtol=1e-11, atol=0)
 
 
+@pytest.mark.parametrize("use_pairs", [1, 0])
+def test_ems_weighted_on_identical_coefficients(use_pairs):
+    """Eq. (weighted_e): per-mode weights (asymmetric between k and -k, a tenth of them
+    zero) through enufft_ems give the oracle's selection exactly on the same FP64
+    coefficients, on the in-register sort (up to 4,096 units per cell)."""
+    b = synth.config1(count_scale=0.003, n_cells=12, precision="f64")
+    ref = oracle_f(b)
+    rng = np.random.default_rng(31 + use_pairs)
+    om = rng.uniform(0.0, 2.0, size=ref.shape[1:])
+    om[rng.random(om.shape) < 0.1] = 0.0
+    plan = _ems_plan_for(ref, "f64")
+    f = torch.from_numpy(ref).to("cuda:0")
+    for prm in (oracle.EmsParams(use_pairs=use_pairs),
+                oracle.EmsParams(k_min=2, k_max=40, alpha_min=0.2, alpha_max=0.9, delta=0.05, use_pairs=use_pairs)):
+        keep, ks, st = plan.ems(f, enf.EmsParams(**prm.__dict__), mode_weight=torch.from_numpy(om))
+        ok_keep, ok_ks, ok_st = oracle.ems_batched(ref, prm, mode_weight=om)
+        print("weighted k_star", ks.cpu().numpy()[:6], ok_ks[:6], flush=True)
+        assert np.array_equal(ks.cpu().numpy(), ok_ks)
+        assert np.array_equal(keep.cpu().numpy(), ok_keep)
+        assert np.allclose(st.cpu().numpy(), ok_st, rtol=1e-11, atol=0)
+        # the weights change the selection (the test is not vacuous)
+        _, ks0, _ = oracle.ems_batched(ref, prm)
+        assert not np.array_equal(ks0, ok_ks)
+
+
 def test_ems_fig2_families_on_gpu():
     J = 20
     j = np.arange(1, J + 1)

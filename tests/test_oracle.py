@@ -126,6 +126,27 @@ def test_type1_modes_agrees_with_full_box():
     assert np.abs(f - g).max() <= 1e-12 * np.abs(f).max()
 
 
+def test_type1_axes_agrees_with_box_and_listed_modes():
+    """The product-set evaluation equals the full-box sum on the box's own axes, and the
+    per-mode direct sums (a separate code path) on a seeded product set of wave numbers
+    up to 300."""
+    Q = 700
+    x, y, h, w = _cell(Q, rng=np.random.default_rng(61))
+    win = np.array([0.2, -0.1, 3.0])
+    c = oracle.strength(x, y, h, w, win)
+    N1, N2 = 6, 5
+    box = oracle.type1([0, Q], x, y, h, w, win, (N1, N2), scale=1.3)[0]
+    ax = oracle.type1_axes(x, y, c, _modes(N1), _modes(N2), scale=1.3)
+    assert np.allclose(ax, box, rtol=0, atol=1e-12 * np.abs(box).max())
+    rng = np.random.default_rng(62)
+    kx = rng.integers(-300, 300, 7)
+    ky = rng.integers(-300, 300, 4)
+    ax = oracle.type1_axes(x, y, c, kx, ky)
+    KX, KY = np.meshgrid(kx, ky)
+    lm = oracle.type1_modes(x, y, c, KX.ravel(), KY.ravel()).reshape(KX.shape)
+    assert np.allclose(ax, lm, rtol=0, atol=1e-11 * np.abs(lm).max())
+
+
 def test_monte_carlo_error_law_and_leakage():
     """Appendix A3.1: for h = A cos(k_s.x) sampled at Q uniform points with uniform weights,
     the coefficient at k_s is A/2 plus an error with E|eps|^2 = A^2/(4Q).  Appendix A3.2:

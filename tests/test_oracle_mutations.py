@@ -22,6 +22,8 @@ MUTATIONS = [
     ("window dropped from the strength", "return w * W * h;", "return w * h;"),
     ("Hann sign", "*W = 0.5 * (1.0 + cos(u));", "*W = 0.5 * (1.0 - cos(u));"),
     ("Hann gradient transposed", "*dWdy = g * dy;", "*dWdy = g * dx;"),
+    ("product-set sum sign of the y phase", "ey[2 * r + 1] = -c[j] * sin(ph);",
+     "ey[2 * r + 1] = c[j] * sin(ph);"),
     ("scale dropped", "for (int64_t m = 0; m < 2 * M; ++m) out[m] *= scale;", ""),
     ("EMS tie-break reversed", "return (a->id < b->id) ? -1 : (a->id > b->id);", "return (a->id > b->id) ? -1 : (a->id < b->id);"),
     ("EMS participation ratio", "tot * tot / tot2", "tot / tot2"),
