@@ -73,6 +73,14 @@ def _load():
                                          _u8p, _i32p, _dp]
         L.oracle_type1_vjp.argtypes = [ctypes.c_int64, _i64p, _dp, _dp, _dp, _dp, _dp, ctypes.c_int,
                                        ctypes.c_int, ctypes.c_int, ctypes.c_double, _dp, _dp, _dp, _dp]
+        L.oracle_mw_weight.argtypes = [ctypes.c_int, ctypes.c_int] + [ctypes.c_double] * 6
+        L.oracle_mw_weight.restype = ctypes.c_double
+        L.oracle_ems_flow.argtypes = [ctypes.c_int, ctypes.c_int64, ctypes.c_int, ctypes.c_int, _dp, ctypes.c_int,
+                                      ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                      ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_int, _dp, _u8p, _i32p,
+                                      _dp]
+        L.oracle_reconstruct.argtypes = [ctypes.c_int64, _i64p, _dp, _dp, _dp, _dp, _dp, ctypes.c_int, ctypes.c_int,
+                                         ctypes.c_int, _dp, _u8p, _dp, _dp, _dp]
         _lib = L
     return _lib
 
@@ -200,6 +208,33 @@ def ems_batched(f: np.ndarray, prm: EmsParams = EmsParams(), mode_weight=None):
     return keep, ks, st
 
 
+def mw_weight(kx, ky, kscale, ux, uy, N, fc, rho):
+    """Launch weight |A| / |h|^2 of one mode under a flow (Appendix A7)."""
+    return _load().oracle_mw_weight(int(kx), int(ky), float(kscale), float(ux), float(uy), float(N), float(fc),
+                                    float(rho))
+
+
+def ems_flow(f: np.ndarray, flow: np.ndarray, prm: EmsParams = EmsParams()):
+    """EMS per timestep with flow-dependent launch weights on fixed coefficients f
+    (complex [n_cells, N2, N1]); flow float64 [n_steps, n_cells, 6] = (ux, uy, N, fc,
+    rho, kscale) -> (keep [n_steps, n_cells, N2, N1], k_star [n_steps, n_cells],
+    stats [n_steps, n_cells, 8])."""
+    L = _load()
+    n, N2, N1 = f.shape
+    fl = np.ascontiguousarray(flow, dtype=np.float64)
+    T = fl.shape[0]
+    assert fl.shape == (T, n, 6)
+    fr = np.ascontiguousarray(np.stack([f.real, f.imag], axis=-1), dtype=np.float64)
+    keep = np.zeros((T, n, N2, N1), dtype=np.uint8)
+    ks = np.zeros((T, n), dtype=np.int32)
+    st = np.zeros((T, n, 8))
+    L.oracle_ems_flow(T, n, N1, N2, fr.ctypes.data_as(_dp), int(prm.k_min), int(min(prm.k_max, 2**31 - 1)),
+                      float(prm.alpha_min), float(prm.alpha_max), float(prm.delta), float(prm.w1), float(prm.w2),
+                      int(prm.use_pairs), int(prm.exclude_dc), fl.ctypes.data_as(_dp), keep.ctypes.data_as(_u8p),
+                      ks.ctypes.data_as(_i32p), st.ctypes.data_as(_dp))
+    return keep, ks, st
+
+
 def type1_vjp(offsets, x, y, h, w, windows, n_modes, g, scale=1.0, kind=1):
     """Gradients (grad_h, grad_x, grad_y) of a real loss whose cotangent on f is g
     (complex [n_cells, N2, N1], g = dL/dRe f + i dL/dIm f)."""
@@ -230,6 +265,29 @@ def retained_power_grad(offsets, x, y, h, w, windows, n_modes, prm: EmsParams = 
     g = 2.0 * lam[:, None, None] * f * keep
     gh, gx, gy = type1_vjp(offsets, x, y, h, w, windows, n_modes, g, scale, kind)
     return dict(f=f, keep=keep, k_star=ks, stats=st, grad_h=gh, grad_x=gx, grad_y=gy)
+
+
+def reconstruct(offsets, x, y, h, w, windows, n_modes, coef, keep=None, area=None, kind=1):
+    """Truncated-series reconstruction at every sample from coefficients coef (complex
+    [n_cells, N2, N1]) over the kept modes (keep uint8, None: all), and the per-cell
+    diagnostics of Section 3.2 -> (h_rec [Q], diag [n_cells, 8]) with diag columns
+    (Q_c, sum (t - h_rec)^2, sum t^2, sigma2_phys, sigma2_spec (all k != 0),
+    sigma2_spec over kept k != 0, eps_rel, sigma2_spec / sigma2_phys), t = W h."""
+    L = _load()
+    off = np.ascontiguousarray(offsets, dtype=np.int64)
+    n_cells = len(off) - 1
+    N1, N2 = int(n_modes[0]), int(n_modes[1])
+    x, px = _d(x); y, py = _d(y); h, ph = _d(h); w, pw = _d(w)
+    win, pwin = _d(np.asarray(windows, dtype=np.float64).reshape(n_cells, 3))
+    cr = np.ascontiguousarray(np.stack([coef.real, coef.imag], axis=-1), dtype=np.float64)
+    kp = None if keep is None else np.ascontiguousarray(keep, dtype=np.uint8)
+    ar, par = _d(np.ones(n_cells) if area is None else np.asarray(area, dtype=np.float64))
+    hr = np.zeros(len(x))
+    dg = np.zeros((n_cells, 8))
+    L.oracle_reconstruct(n_cells, off.ctypes.data_as(_i64p), px, py, ph, pw, pwin, kind, N1, N2,
+                         cr.ctypes.data_as(_dp), _nullable(kp, _u8p), par, hr.ctypes.data_as(_dp),
+                         dg.ctypes.data_as(_dp))
+    return hr, dg
 
 
 def batch_inputs(batch, cells=None):

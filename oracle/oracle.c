@@ -18,10 +18,18 @@
  *   oracle_ems           Elastic Mode Selection, Section 2.2 eqs. (energy),
  *                        (sorted_energy), (n_eff), (s_delta), (c_score),
  *                        (alpha_c), (f_cum), (k_elastic), in the paper's order.
+ *   oracle_mw_weight,    EMS per timestep with the flow-dependent launch weight of
+ *   oracle_ems_flow      Appendix A7 (eqs. mountain_omega, mw_dispersion, mw_action)
+ *                        folded into eq. (weighted_e), on fixed coefficients.
  *   oracle_type1_vjp     the exact adjoint (a direct type-2 sum with the +i sign
  *                        of eq. (series)) and the chain rule through the window
  *                        and weights: gradients of a real loss with respect to
  *                        heights and point coordinates.
+ *   oracle_reconstruct   the truncated series of eq. (series) over the retained
+ *                        modes evaluated at every sample (a direct type-2 sum),
+ *                        and the per-cell diagnostics of Section 3.2: the relative
+ *                        reconstruction RMSE of eq. (alps_relative_rmse) and the
+ *                        two sides of Parseval's identity, eq. (spectral_variance).
  *
  * Conventions (readings of points the paper leaves open)
  *   - Local coordinates live on a periodic box of side 2*pi, so wave numbers
@@ -413,6 +421,64 @@ void oracle_ems_batched(int64_t n_cells, int N1, int N2, const double *f, int k_
                    NULL, NULL);
 }
 
+/* ------------------------------------------------------ flow-dependent EMS */
+
+/* Launch weight of one mode for an orographic gravity wave (Appendix A7), in the
+ * paper's order.  k = kscale (kx, ky) is the physical wave vector, u = (ux, uy)
+ * the background wind, N the buoyancy frequency, fc the Coriolis parameter and
+ * rho the background density.
+ *   intrinsic frequency      omega = -k . u                               (eq. mountain_omega)
+ *   vertical wave number     m^2 = |k|^2 (N^2 - omega^2) / (omega^2 - fc^2) (eq. mw_dispersion)
+ *   wave action              A = -(rho / 2) (k . u) (|k|^2 + m^2) / |k|^2 |h|^2  (eq. mw_action)
+ * The weight is |A| / |h|^2: the magnitude of the action density per unit modal power
+ * (the action and the intrinsic frequency are taken on the same signed branch, so the
+ * wave energy A omega is positive).  A mode that does not propagate vertically
+ * (|omega| <= fc or |omega| >= N, the bounds of eq. mw_dispersion) and the k = 0 mode
+ * have weight 0. */
+double oracle_mw_weight(int kx, int ky, double kscale, double ux, double uy, double N, double fc, double rho)
+{
+    const double k1 = kscale * (double)kx, k2 = kscale * (double)ky;
+    const double kk = k1 * k1 + k2 * k2;
+    if (!(kk > 0.0)) return 0.0;
+    const double omega = -(k1 * ux + k2 * uy);
+    const double aw = fabs(omega);
+    if (!(aw > fabs(fc) && aw < N)) return 0.0;
+    const double m2 = kk * (N * N - omega * omega) / (omega * omega - fc * fc);
+    const double A = -(rho / 2.0) * (k1 * ux + k2 * uy) * (kk + m2) / kk;
+    return fabs(A);
+}
+
+/* EMS per timestep on fixed coefficients: for step s and cell c the mode weights of
+ * eq. (weighted_e) are the launch weights of oracle_mw_weight under the flow record
+ * flow[6 (s n_cells + c) + (0..5)] = (ux, uy, N, fc, rho, kscale), then oracle_ems.
+ * Outputs are indexed by s n_cells + c; keep may be NULL. */
+void oracle_ems_flow(int n_steps, int64_t n_cells, int N1, int N2, const double *f, int k_min, int k_max,
+                     double alpha_min, double alpha_max, double delta, double w1, double w2,
+                     int use_pairs, int exclude_dc, const double *flow,
+                     uint8_t *keep, int32_t *k_star, double *stats)
+{
+    const int64_t M = (int64_t)N1 * N2;
+    const int64_t total = (int64_t)n_steps * n_cells;
+    #pragma omp parallel
+    {
+        double *om = (double *)malloc(sizeof(double) * (size_t)M);
+        uint8_t *kp = (uint8_t *)malloc((size_t)M);
+        #pragma omp for schedule(dynamic, 1)
+        for (int64_t v = 0; v < total; ++v) {
+            const int64_t c = v % n_cells;
+            const double *fl = flow + 6 * v;
+            for (int r = 0; r < N2; ++r)
+                for (int i = 0; i < N1; ++i)
+                    om[(int64_t)r * N1 + i] = oracle_mw_weight(mode_lo(N1) + i, mode_lo(N2) + r, fl[5], fl[0],
+                                                               fl[1], fl[2], fl[3], fl[4]);
+            oracle_ems(N1, N2, f + 2 * M * c, k_min, k_max, alpha_min, alpha_max, delta, w1, w2, use_pairs,
+                       exclude_dc, om, keep ? keep + M * v : kp, k_star + v, stats + 8 * v, NULL, NULL);
+        }
+        free(om);
+        free(kp);
+    }
+}
+
 /* ---------------------------------------------------------------- adjoint */
 
 /* Real adjoint of the type-1 map and the chain rule to heights and coordinates.
@@ -479,5 +545,86 @@ void oracle_type1_vjp(int64_t n_cells, const int64_t *off,
         free(ex);
         free(ey);
         }
+    }
+}
+
+/* ------------------------------------------------------------ reconstruction */
+
+/* Reconstruction from retained coefficients and the Section 3.2 diagnostics.
+ *
+ * For cell c with coefficients coef (interleaved complex, N2 x N1, as oracle_type1
+ * writes them) and a keep mask (NULL: every mode):
+ *   h_rec(x_q) = Re sum_{k kept} coef_k exp(+i (kx x_q + ky y_q))      (eq. series)
+ * The coefficients represent the windowed heights, so the target at sample q is
+ *   t_q = W_c(x_q, y_q) h_q   (= h_q without a window, kind == 0).
+ * diag[8 c + i]:
+ *   0  Q_c, the number of samples
+ *   1  sum_q (t_q - h_rec(x_q))^2
+ *   2  sum_q t_q^2
+ *   3  sigma^2_phys = (1 / |D_c|) sum_q w_q t_q^2                 (eq. spectral_variance, left)
+ *   4  sigma^2_spec = sum over all modes k != 0 of |coef_k|^2      (eq. spectral_variance, right)
+ *   5  the same sum over the kept modes only
+ *   6  eps_rel = sqrt(diag[1] / diag[2])                           (eq. alps_relative_rmse)
+ *   7  sigma^2_spec / sigma^2_phys (the Parseval ratio)
+ * area[c] = |D_c|.  Sums over samples are compensated (Neumaier), in sample order.
+ * h_rec may be NULL. */
+void oracle_reconstruct(int64_t n_cells, const int64_t *off,
+                        const double *x, const double *y, const double *h, const double *w,
+                        const double *windows, int kind, int N1, int N2,
+                        const double *coef, const uint8_t *keep, const double *area,
+                        double *h_rec, double *diag)
+{
+    const int64_t M = (int64_t)N1 * N2;
+    for (int64_t c = 0; c < n_cells; ++c) {
+        const int64_t a = off[c], b = off[c + 1];
+        const double *cc = coef + 2 * M * c;
+        const uint8_t *kc = keep ? keep + M * c : NULL;
+        const double *win = windows + 3 * c;
+        double *rec = (double *)malloc(sizeof(double) * (size_t)((b - a) > 0 ? (b - a) : 1));
+        #pragma omp parallel for schedule(dynamic, 64)
+        for (int64_t j = a; j < b; ++j) {
+            double s = 0.0;
+            for (int r = 0; r < N2; ++r) {
+                const double ky = (double)(mode_lo(N2) + r);
+                for (int i = 0; i < N1; ++i) {
+                    const int64_t m = (int64_t)r * N1 + i;
+                    if (kc && !kc[m]) continue;
+                    const double kx = (double)(mode_lo(N1) + i);
+                    const double ph = kx * x[j] + ky * y[j];
+                    /* Re(coef e^{+i ph}) */
+                    s += cc[2 * m] * cos(ph) - cc[2 * m + 1] * sin(ph);
+                }
+            }
+            rec[j - a] = s;
+        }
+        ksum_t e2 = {0, 0}, t2 = {0, 0}, wt2 = {0, 0}, sall = {0, 0}, skept = {0, 0};
+        for (int64_t j = a; j < b; ++j) {
+            double W, gx, gy;
+            oracle_hann(kind, x[j], y[j], win[0], win[1], win[2], &W, &gx, &gy);
+            const double t = W * h[j];
+            const double d = t - rec[j - a];
+            kadd(&e2, d * d);
+            kadd(&t2, t * t);
+            kadd(&wt2, w[j] * t * t);
+            if (h_rec) h_rec[j] = rec[j - a];
+        }
+        for (int r = 0; r < N2; ++r)
+            for (int i = 0; i < N1; ++i) {
+                if (mode_lo(N1) + i == 0 && mode_lo(N2) + r == 0) continue;
+                const int64_t m = (int64_t)r * N1 + i;
+                const double p2 = cc[2 * m] * cc[2 * m] + cc[2 * m + 1] * cc[2 * m + 1];
+                kadd(&sall, p2);
+                if (!kc || kc[m]) kadd(&skept, p2);
+            }
+        double *dg = diag + 8 * c;
+        dg[0] = (double)(b - a);
+        dg[1] = kval(&e2);
+        dg[2] = kval(&t2);
+        dg[3] = kval(&wt2) / area[c];
+        dg[4] = kval(&sall);
+        dg[5] = kval(&skept);
+        dg[6] = dg[2] > 0.0 ? sqrt(dg[1] / dg[2]) : 0.0;
+        dg[7] = dg[3] > 0.0 ? dg[4] / dg[3] : 0.0;
+        free(rec);
     }
 }

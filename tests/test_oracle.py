@@ -523,3 +523,186 @@ def test_vjp_finite_differences_on_retained_power():
             # rounding floor of a central difference of P in FP64
             noise = 64 * np.finfo(float).eps * P0 / (2 * sc)
             assert abs(fd - an) <= 1e-6 * abs(an) + noise, (name, j, fd, an, noise)
+
+
+# ----------------------------------------------------------------------------- reconstruction
+
+def _grid_points(n):
+    g = -math.pi + 2 * math.pi * np.arange(n) / n
+    X, Y = np.meshgrid(g, g)
+    return X.ravel(), Y.ravel()
+
+
+def test_reconstruct_band_limited_grid_is_exact_and_parseval_holds():
+    """Section 3.2 diagnostics where the answer is known: a zero-mean band-limited field
+    sampled on a regular n x n grid of the 2 pi box with uniform weights (2 pi / n)^2, no
+    window, |D| = (2 pi)^2 and scale 1/|D| (eq. discrete_quadrature).  The quadrature is
+    then the exact DFT, the truncated series reproduces every sample (eps_rel = 0) and
+    Parseval's identity, eq. (spectral_variance), holds exactly (ratio 1)."""
+    n, N = 24, 12
+    x, y = _grid_points(n)
+    rng = np.random.default_rng(71)
+    h = np.zeros_like(x)
+    for _ in range(9):
+        kx, ky = rng.integers(-5, 6, 2)
+        if kx == 0 and ky == 0:
+            continue
+        h += rng.normal() * np.cos(kx * x + ky * y + rng.uniform(0, 2 * np.pi))
+    Q = len(x)
+    area = (2 * math.pi) ** 2
+    w = np.full(Q, area / Q)
+    f = oracle.type1([0, Q], x, y, h, w, [0, 0, 1], (N, N), scale=1 / area, kind=0)
+    hr, dg = oracle.reconstruct([0, Q], x, y, h, w, [0, 0, 1], (N, N), f, area=[area], kind=0)
+    assert np.allclose(hr, h, rtol=0, atol=1e-12 * np.abs(h).max())
+    assert dg[0, 0] == Q and dg[0, 6] < 1e-12
+    assert np.isclose(dg[0, 3], np.mean(h ** 2), rtol=1e-13)
+    assert np.isclose(dg[0, 7], 1.0, rtol=1e-12)
+    assert np.isclose(dg[0, 4], dg[0, 5], rtol=1e-15)
+
+
+def test_reconstruct_single_mode_closed_form():
+    """h = A cos(k0 . x + phi) on a regular grid: hat h at +-k0 is (A/2) e^{+-i phi}, both
+    variances are A^2 / 2, and keeping only the pair +-k0 reconstructs h; keeping
+    nothing gives h_rec = 0 and eps_rel = 1."""
+    n, N = 16, 8
+    x, y = _grid_points(n)
+    A, phi, k0 = 3.0, 0.7, (2, -3)
+    h = A * np.cos(k0[0] * x + k0[1] * y + phi)
+    Q = len(x)
+    area = (2 * math.pi) ** 2
+    w = np.full(Q, area / Q)
+    f = oracle.type1([0, Q], x, y, h, w, [0, 0, 1], (N, N), scale=1 / area, kind=0)
+    lo = -(N // 2)
+    assert np.isclose(f[0, k0[1] - lo, k0[0] - lo], A / 2 * np.exp(1j * phi), atol=1e-13)
+    keep = np.zeros((1, N, N), dtype=np.uint8)
+    keep[0, k0[1] - lo, k0[0] - lo] = 1
+    keep[0, -k0[1] - lo, -k0[0] - lo] = 1
+    hr, dg = oracle.reconstruct([0, Q], x, y, h, w, [0, 0, 1], (N, N), f, keep=keep, area=[area], kind=0)
+    assert np.allclose(hr, h, atol=1e-12)
+    assert np.isclose(dg[0, 3], A * A / 2, rtol=1e-13) and np.isclose(dg[0, 5], A * A / 2, rtol=1e-12)
+    hr0, dg0 = oracle.reconstruct([0, Q], x, y, h, w, [0, 0, 1], (N, N), f, keep=np.zeros_like(keep),
+                                  area=[area], kind=0)
+    assert np.all(hr0 == 0) and dg0[0, 6] == 1.0 and dg0[0, 5] == 0.0
+
+
+def test_reconstruct_brute_force_with_window():
+    """Off-grid samples, random coefficients (DC included), a random kept set and the Hann
+    window: the series and every diagnostic against a numpy evaluation of their
+    definitions (target t = W h, the windowed field the coefficients represent)."""
+    rng = np.random.default_rng(72)
+    N1, N2 = 5, 6
+    offs = [0, 40, 40, 97]
+    Q = offs[-1]
+    x, y, h, w = _cell(Q, rng=rng)
+    win = np.array([[0.1, -0.2, 2.5], [0.0, 0.0, 1.0], [-0.3, 0.2, 3.1]])
+    coef = rng.normal(size=(3, N2, N1)) + 1j * rng.normal(size=(3, N2, N1))
+    keep = (rng.random((3, N2, N1)) < 0.5).astype(np.uint8)
+    area = np.array([7.0, 1.0, 11.0])
+    hr, dg = oracle.reconstruct(offs, x, y, h, w, win, (N1, N2), coef, keep=keep, area=area)
+    kx, ky = np.meshgrid(_modes(N1), _modes(N2))
+    for c in range(3):
+        a, b = offs[c], offs[c + 1]
+        ph = np.outer(x[a:b], kx.ravel()) + np.outer(y[a:b], ky.ravel())
+        rec = np.real(np.exp(1j * ph) @ (coef[c] * keep[c]).ravel())
+        assert np.allclose(hr[a:b], rec, rtol=0, atol=1e-12 * max(1.0, np.abs(rec).max() if b > a else 1.0))
+        t = np.array([oracle.hann(x[j], y[j], *win[c])[0] * h[j] for j in range(a, b)])
+        nz = (kx.ravel() != 0) | (ky.ravel() != 0)
+        p2 = np.abs(coef[c].ravel()) ** 2
+        assert dg[c, 0] == b - a
+        assert np.isclose(dg[c, 1], np.sum((t - rec) ** 2), rtol=1e-12)
+        assert np.isclose(dg[c, 2], np.sum(t ** 2), rtol=1e-12, atol=0)
+        assert np.isclose(dg[c, 3], np.sum(w[a:b] * t ** 2) / area[c], rtol=1e-12, atol=0)
+        assert np.isclose(dg[c, 4], np.sum(p2[nz]), rtol=1e-13)
+        assert np.isclose(dg[c, 5], np.sum((p2 * keep[c].ravel())[nz]), rtol=1e-13)
+        if b > a:
+            assert np.isclose(dg[c, 6], math.sqrt(dg[c, 1] / dg[c, 2]), rtol=1e-14)
+            assert np.isclose(dg[c, 7], dg[c, 4] / dg[c, 3], rtol=1e-14)
+
+
+# ----------------------------------------------------------------------------- flow-dependent EMS
+
+def _action_weight(kx, ky, ks, ux, uy, N, fc, rho):
+    """|A| / |h|^2 of eq. (mw_action) after eliminating m^2 with eq. (mw_dispersion):
+    (|k|^2 + m^2) / |k|^2 = (N^2 - fc^2) / (omega^2 - fc^2), and |k . u| = |omega|, so
+    w = (rho / 2) |omega| (N^2 - fc^2) / (omega^2 - fc^2) inside the band fc < |omega| < N."""
+    om = -(ks * kx * ux + ks * ky * uy)
+    if kx == 0 and ky == 0:
+        return 0.0
+    if not (abs(fc) < abs(om) < N):
+        return 0.0
+    return rho / 2 * abs(om) * (N * N - fc * fc) / (om * om - fc * fc)
+
+
+def test_mw_weight_closed_form_and_band():
+    """The launch weight of Appendix A7 against its closed form (the dispersion relation
+    eliminated by hand); zero outside the propagating band and at k = 0; even in k and
+    in u."""
+    rng = np.random.default_rng(81)
+    n_in = 0
+    for _ in range(400):
+        kx, ky = rng.integers(-32, 32, 2)
+        ks = 10 ** rng.uniform(-4.5, -3)
+        ux, uy = rng.normal(scale=10, size=2)
+        N, fc, rho = 10 ** rng.uniform(-2.5, -1.5), 10 ** rng.uniform(-5, -3.5), rng.uniform(0.3, 1.3)
+        w = oracle.mw_weight(kx, ky, ks, ux, uy, N, fc, rho)
+        ref = _action_weight(kx, ky, ks, ux, uy, N, fc, rho)
+        n_in += ref > 0
+        assert np.isclose(w, ref, rtol=1e-12, atol=0), (kx, ky, w, ref)
+        assert w == oracle.mw_weight(-kx, -ky, ks, ux, uy, N, fc, rho)
+        assert w == oracle.mw_weight(kx, ky, ks, -ux, -uy, N, fc, rho)
+    assert 40 < n_in < 360          # both sides of the band are exercised
+    assert oracle.mw_weight(0, 0, 1e-3, 10, 0, 0.02, 1e-4, 1) == 0.0
+    # k perpendicular to the wind: omega = 0, no launch (Section 3.3, the first mode)
+    assert oracle.mw_weight(0, 5, 1e-3, 10, 0, 0.02, 1e-4, 1) == 0.0
+
+
+def test_ems_flow_equals_ems_with_closed_form_weights():
+    """Per step and cell, the flow-dependent selection is EMS (eq. weighted_e) with the
+    closed-form launch weights; outputs are ordered step-major."""
+    Q = 500
+    rng = np.random.default_rng(82)
+    fs = []
+    for c in range(3):
+        x, y, h, w = _cell(Q, rng=rng)
+        fs.append(oracle.type1([0, Q], x, y, h, w, [0.0, 0.0, 3.0], (10, 8))[0])
+    f = np.stack(fs)
+    T = 4
+    flow = np.zeros((T, 3, 6))
+    flow[..., 0] = rng.normal(scale=8, size=(T, 3))
+    flow[..., 1] = rng.normal(scale=8, size=(T, 3))
+    flow[..., 2] = 0.02
+    flow[..., 3] = 1e-4
+    flow[..., 4] = rng.uniform(0.5, 1.2, size=(T, 3))
+    flow[..., 5] = 2 * np.pi / 20000.0
+    for prm in (oracle.EmsParams(alpha_min=0.9, alpha_max=0.9),
+                oracle.EmsParams(k_min=1, k_max=4, alpha_min=0.9, alpha_max=1.0)):
+        keep, ks, st = oracle.ems_flow(f, flow, prm)
+        for s_ in range(T):
+            for c in range(3):
+                ux, uy, N, fc, rho, k0 = flow[s_, c]
+                om = np.array([[_action_weight(kx, ky, k0, ux, uy, N, fc, rho) for kx in _modes(10)]
+                               for ky in _modes(8)])
+                r = oracle.ems(f[c], prm, mode_weight=om)
+                assert ks[s_, c] == r.k_star and np.array_equal(keep[s_, c], r.keep)
+                assert np.allclose(st[s_, c], r.stats, rtol=1e-12, atol=0)
+
+
+def test_ems_flow_mountain_wave_modes():
+    """The Section 3.3 mode set: N_mu = 4 modes k_mu = (mu - 1) 2 pi / lambda0 along x and
+    l = 2 pi / lambda0 along y with equal amplitudes, zonal wind u0.  The first mode has
+    k . u = 0, so zero launch weight: it is never kept while another mode carries
+    weight, and reversing the wind changes nothing."""
+    lam0, u0 = 10000.0, 10.0
+    N1 = N2 = 16
+    f = np.zeros((1, N2, N1), dtype=np.complex128)
+    lo = -(N1 // 2)
+    for mu in range(4):
+        f[0, 1 - lo, mu - lo] = 1.0          # (kx, ky) = (mu - 1 + 1, 1) in box units: kx = mu
+    ks = 2 * np.pi / lam0
+    flow = np.array([[[u0, 0.0, 0.02, 1e-4, 1.0, ks]], [[-u0, 0.0, 0.02, 1e-4, 1.0, ks]]])
+    prm = oracle.EmsParams(k_min=1, k_max=4, alpha_min=0.9, alpha_max=1.0, use_pairs=0, exclude_dc=1)
+    keep, kstar, st = oracle.ems_flow(f, flow, prm)
+    assert not keep[0, 0, 1 - lo, 0 - lo] and not keep[1, 0, 1 - lo, 0 - lo]
+    assert np.array_equal(keep[0], keep[1]) and kstar[0, 0] == kstar[1, 0] >= 1
+    w = [_action_weight(mu, 1, ks, u0, 0, 0.02, 1e-4, 1.0) for mu in range(4)]
+    assert w[0] == 0.0 and all(v > 0 for v in w[1:])

@@ -24,6 +24,18 @@ MUTATIONS = [
     ("Hann gradient transposed", "*dWdy = g * dy;", "*dWdy = g * dx;"),
     ("product-set sum sign of the y phase", "ey[2 * r + 1] = -c[j] * sin(ph);",
      "ey[2 * r + 1] = c[j] * sin(ph);"),
+    ("reconstruction phase sign", "s += cc[2 * m] * cos(ph) - cc[2 * m + 1] * sin(ph);",
+     "s += cc[2 * m] * cos(ph) + cc[2 * m + 1] * sin(ph);"),
+    ("reconstruction target without the window", "const double t = W * h[j];", "const double t = h[j];"),
+    ("spectral variance keeps the DC mode", "if (mode_lo(N1) + i == 0 && mode_lo(N2) + r == 0) continue;", ""),
+    ("physical variance without the weights", "kadd(&wt2, w[j] * t * t);", "kadd(&wt2, t * t);"),
+    ("launch weight: intrinsic frequency from one wind component", "const double omega = -(k1 * ux + k2 * uy);",
+     "const double omega = -(k1 * ux);"),
+    ("launch weight: propagating band not enforced", "if (!(aw > fabs(fc) && aw < N)) return 0.0;", ""),
+    ("launch weight: dispersion relation inverted",
+     "const double m2 = kk * (N * N - omega * omega) / (omega * omega - fc * fc);",
+     "const double m2 = kk * (omega * omega - fc * fc) / (N * N - omega * omega);"),
+    ("flow records indexed by cell only", "const double *fl = flow + 6 * v;", "const double *fl = flow + 6 * c;"),
     ("scale dropped", "for (int64_t m = 0; m < 2 * M; ++m) out[m] *= scale;", ""),
     ("EMS tie-break reversed", "return (a->id < b->id) ? -1 : (a->id > b->id);", "return (a->id > b->id) ? -1 : (a->id < b->id);"),
     ("EMS participation ratio", "tot * tot / tot2", "tot / tot2"),
