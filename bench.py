@@ -45,10 +45,16 @@ import time
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-TRAFFIC_FILE = os.path.join(HERE, "profiles", "fwd_kernel_c3_traffic.json")
-# sources whose text fixes the forward kernel's code (traffic is void once they change)
-FWD_SOURCES = ["paper_2606_21278_amd/csrc/fwd.hip", "paper_2606_21278_amd/csrc/device_common.h",
-               "paper_2606_21278_amd/csrc/launch.h"]
+TRAFFIC_FILE = os.path.join(HERE, "profiles", "c3_kernels_hbm_traffic.json")
+# the main kernels of a step and the sources whose text fixes each one's code
+# (a kernel's counter record is void once they change)
+KERNEL_SOURCES = {
+    "fwd_kernel": ["paper_2606_21278_amd/csrc/fwd.hip", "paper_2606_21278_amd/csrc/device_common.h",
+                   "paper_2606_21278_amd/csrc/launch.h"],
+    "ems_kernel": ["paper_2606_21278_amd/csrc/ems.hip", "paper_2606_21278_amd/csrc/device_common.h"],
+    "adj_kernel": ["paper_2606_21278_amd/csrc/adj.hip", "paper_2606_21278_amd/csrc/device_common.h",
+                   "paper_2606_21278_amd/csrc/launch.h"],
+}
 FWD_KERNEL = "fwd_kernel"
 COPY_KERNEL = "bitwise_not"
 
@@ -57,25 +63,30 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def fwd_source_hash():
+def source_hash(kernel):
     h = hashlib.sha256()
-    for rel in FWD_SOURCES:
+    for rel in KERNEL_SOURCES[kernel]:
         with open(os.path.join(HERE, rel), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
-    """HBM bytes per forward launch from the committed counter record, if it was
-    taken with the current kernel source; else None."""
+def fwd_source_hash():
+    return source_hash(FWD_KERNEL)
+
+
+def measured_traffic(kernel=FWD_KERNEL):
+    """HBM bytes per launch of a kernel from the committed counter record, if it was
+    taken with the kernel's current source; else None."""
     try:
         with open(TRAFFIC_FILE) as fh:
             rec = json.load(fh)
     except (OSError, ValueError):
         return None
-    if rec.get("source_hash") != fwd_source_hash():
+    k = rec.get("kernels", {}).get(kernel)
+    if not k or k.get("source_hash") != source_hash(kernel):
         return None
-    return rec.get("bytes_per_launch")
+    return k.get("bytes_per_launch")
 
 
 def _omp_threads(n):
@@ -230,6 +241,63 @@ def make_plan(enf, gb, workload="c3", shuffled=False, autotune=True):
                     autotune=tune)
 
 
+def reconstruction_figures(plan, gb, f, keep, torch, steps):
+    """The Section 3.2 diagnostics over the whole batch: the truncated series over the
+    kept modes at every sample, eps_rel and the Parseval ratio per cell, from the
+    coefficients normalised by the cell areas (the paper's hat h).  Timed with HIP
+    events on the plan's stream (one enufft_reconstruct per step)."""
+    area = torch.as_tensor(gb.areas, dtype=torch.float64, device=gb.x.device)
+    coef = (f * (1.0 / area).to(torch.float32)[:, None, None]).contiguous()
+    plan.reconstruct(gb.x, gb.y, gb.h, gb.w, coef, keep, area, need_h_rec=False)
+    torch.cuda.synchronize()
+    s = torch.cuda.current_stream()
+    e = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    dg = None
+    for e0, e1 in e:
+        e0.record(s)
+        _, dg = plan.reconstruct(gb.x, gb.y, gb.h, gb.w, coef, keep, area, need_h_rec=False)
+        e1.record(s)
+    torch.cuda.synchronize()
+    ms = float(np.median([a.elapsed_time(b) for a, b in e]))
+    d = dg.cpu().numpy()
+    live = d[:, 0] > 0
+    return {"ms": ms, "points_per_s": float(gb.n_points / (ms * 1e-3)),
+            "eps_rel_median": float(np.median(d[live, 6])), "eps_rel_p90": float(np.percentile(d[live, 6], 90)),
+            "parseval_ratio_median": float(np.median(d[live, 7])),
+            "parseval_ratio_kept_median": float(np.median(d[live, 5] / d[live, 3])),
+            "note": "eq. alps_relative_rmse and eq. spectral_variance per cell, kept modes, target W h"}
+
+
+def flow_selection_figures(plan, gb, f, prm, torch, steps, n_t=8, seed=5):
+    """EMS re-selected over n_t timesteps on the fixed coefficients, with a seeded
+    flow record per step and cell (wind ~ N(0, 8 m/s) per component, N in
+    [0.01, 0.025] 1/s, fc 1e-4 1/s, cells of 80 km): one enufft_ems_flow launch for
+    all steps, timed with HIP events on the plan's stream."""
+    rng = np.random.default_rng(seed)
+    fl = np.zeros((n_t, gb.n_cells, 6))
+    fl[..., 0:2] = rng.normal(scale=8.0, size=(n_t, gb.n_cells, 2))
+    fl[..., 2] = rng.uniform(0.01, 0.025, size=(n_t, gb.n_cells))
+    fl[..., 3] = 1e-4
+    fl[..., 4] = 1.0
+    fl[..., 5] = 2 * np.pi / 80000.0
+    flow = torch.as_tensor(fl, device=gb.x.device)
+    plan.ems_flow(f, flow, prm)
+    torch.cuda.synchronize()
+    s = torch.cuda.current_stream()
+    e = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    ks = None
+    for e0, e1 in e:
+        e0.record(s)
+        _, ks, _ = plan.ems_flow(f, flow, prm)
+        e1.record(s)
+    torch.cuda.synchronize()
+    ms = float(np.median([a.elapsed_time(b) for a, b in e]))
+    k = ks.cpu().numpy()
+    return {"timesteps": n_t, "ms": ms, "ms_per_timestep": ms / n_t,
+            "cell_selections_per_s": float(n_t * gb.n_cells / (ms * 1e-3)),
+            "k_star_median": float(np.median(k)), "k_star_changed_between_steps": float(np.mean(k[1:] != k[:-1]))}
+
+
 def gate_cells(counts, seed=7, n_random=4):
     """The parity gate's cells: the two largest, the two smallest non-empty and
     n_random seeded others."""
@@ -289,25 +357,27 @@ def _short(name):
 
 def summarize(d, command_trace, command_fetch, command_write, copy_mb):
     """Write profiles/ summaries from rocprofv3 CSVs in directory d:
-    *kernel_stats.csv (kernel trace), fetch*counter_collection.csv, write*counter_collection.csv."""
+    *kernel_stats.csv (kernel trace), fetch*counter_collection.csv, write*counter_collection.csv.
+    Covers the forward, EMS and adjoint kernels of the benchmark's step."""
     out_dir = os.path.join(HERE, "profiles")
     os.makedirs(out_dir, exist_ok=True)
     stats = sorted(glob.glob(os.path.join(d, "**", "*kernel_stats.csv"), recursive=True))
-    lines = ["# Forward kernel, C3 workload: kernel-trace statistics", "",
+    lines = ["# Kernels of the C3 step (type-1, EMS, adjoint): kernel-trace statistics", "",
              "Command (repo root, one MI355X):", "", "    " + command_trace, "",
-             "Source hash of the forward kernel: `%s`" % fwd_source_hash(), "",
+             "Source hashes: " + ", ".join("%s `%s`" % (k, source_hash(k)) for k in KERNEL_SOURCES), "",
              "| kernel | calls | total ms | average us | min us | max us | % |", "|---|---|---|---|---|---|---|"]
-    fwd_avg_us = None
+    avg_us = {}
     if stats:
         rows = _rows(stats[0])
-        for r in rows[:12]:
+        for r in rows[:14]:
             avg = float(r["AverageNs"]) / 1e3
             lines.append("| %s | %s | %.3f | %.2f | %.2f | %.2f | %.2f |" % (
                 _short(r["Name"]), r["Calls"], float(r["TotalDurationNs"]) / 1e6, avg,
                 float(r["MinNs"]) / 1e3, float(r["MaxNs"]) / 1e3, float(r["Percentage"])))
-            if FWD_KERNEL in r["Name"] and fwd_avg_us is None:
-                fwd_avg_us = avg
-    with open(os.path.join(out_dir, "fwd_kernel_c3_kernel_trace.md"), "w") as fh:
+            for k in KERNEL_SOURCES:
+                if ("::" + k + "<") in r["Name"] and k not in avg_us:
+                    avg_us[k] = avg
+    with open(os.path.join(out_dir, "c3_kernels_kernel_trace.md"), "w") as fh:
         fh.write("\n".join(lines) + "\n")
 
     def per_dispatch(pattern, counter):
@@ -318,7 +388,8 @@ def summarize(d, command_trace, command_fetch, command_write, copy_mb):
                 if r["Counter_Name"] != counter:
                     continue
                 name = r["Kernel_Name"]
-                key = FWD_KERNEL if FWD_KERNEL in name else (COPY_KERNEL if COPY_KERNEL in name else None)
+                key = COPY_KERNEL if COPY_KERNEL in name else next(
+                    (k for k in KERNEL_SOURCES if ("::" + k + "<") in name), None)
                 if key:
                     vals.setdefault(key, []).append(float(r["Counter_Value"]))
         return vals
@@ -326,31 +397,34 @@ def summarize(d, command_trace, command_fetch, command_write, copy_mb):
     fetch = per_dispatch("fetch*counter_collection.csv", "FETCH_SIZE")
     write = per_dispatch("write*counter_collection.csv", "WRITE_SIZE")
     copy_bytes = copy_mb * 1024.0 * 1024.0
-    res = {"command_fetch": command_fetch, "command_write": command_write, "copy_mb": copy_mb,
-           "source_hash": fwd_source_hash()}
-    if fetch.get(COPY_KERNEL) and write.get(COPY_KERNEL) and fetch.get(FWD_KERNEL) and write.get(FWD_KERNEL):
+    res = {"command_fetch": command_fetch, "command_write": command_write, "copy_mb": copy_mb, "kernels": {}}
+    if fetch.get(COPY_KERNEL) and write.get(COPY_KERNEL):
         # counters are KiB per dispatch; scale by what they read for a copy of known size
-        f_copy = max(fetch[COPY_KERNEL]) * 1024.0
-        w_copy = max(write[COPY_KERNEL]) * 1024.0
-        sf, sw = copy_bytes / f_copy, copy_bytes / w_copy
-        fb = float(np.median(fetch[FWD_KERNEL])) * 1024.0 * sf
-        wb = float(np.median(write[FWD_KERNEL])) * 1024.0 * sw
-        res.update({"fetch_scale": sf, "write_scale": sw, "fetch_bytes": fb, "write_bytes": wb,
-                    "bytes_per_launch": fb + wb, "dispatches": len(fetch[FWD_KERNEL])})
+        sf = copy_bytes / (max(fetch[COPY_KERNEL]) * 1024.0)
+        sw = copy_bytes / (max(write[COPY_KERNEL]) * 1024.0)
+        res.update({"fetch_scale": sf, "write_scale": sw})
+        for k in KERNEL_SOURCES:
+            if fetch.get(k) and write.get(k):
+                fb = float(np.median(fetch[k])) * 1024.0 * sf
+                wb = float(np.median(write[k])) * 1024.0 * sw
+                res["kernels"][k] = {"source_hash": source_hash(k), "fetch_bytes": fb, "write_bytes": wb,
+                                     "bytes_per_launch": fb + wb, "dispatches": len(fetch[k]),
+                                     "trace_avg_us": avg_us.get(k)}
     with open(TRAFFIC_FILE, "w") as fh:
         json.dump(res, fh, indent=1)
-    lines = ["# Forward kernel, C3 workload: HBM traffic counters", "",
+    lines = ["# Kernels of the C3 step: HBM traffic counters", "",
              "FETCH_SIZE and WRITE_SIZE (KiB per dispatch) from two separate rocprofv3 passes:", "",
              "    " + command_fetch, "    " + command_write, "",
              "Each counter is scaled by what it reads for a plain streaming kernel (bitwise_not of %d MiB "
-             "int32, read once and written once) in the same run." % copy_mb,
-             ""]
-    for k in ("fetch_scale", "write_scale", "fetch_bytes", "write_bytes", "bytes_per_launch", "dispatches"):
-        if k in res:
-            lines.append("- %s: %s" % (k, ("%.4g" % res[k]) if isinstance(res[k], float) else res[k]))
-    if fwd_avg_us:
-        lines.append("- forward kernel average duration (kernel trace): %.1f us" % fwd_avg_us)
-    with open(os.path.join(out_dir, "fwd_kernel_c3_hbm_traffic.md"), "w") as fh:
+             "int32, read once and written once) in the same run: FETCH x %.4g, WRITE x %.4g."
+             % (copy_mb, res.get("fetch_scale", float("nan")), res.get("write_scale", float("nan"))), "",
+             "| kernel | fetch GB | write GB | total GB per launch | trace average us | source hash |",
+             "|---|---|---|---|---|---|"]
+    for k, v in res["kernels"].items():
+        lines.append("| %s | %.3f | %.3f | %.3f | %s | `%s` |" % (
+            k, v["fetch_bytes"] / 1e9, v["write_bytes"] / 1e9, v["bytes_per_launch"] / 1e9,
+            "%.1f" % v["trace_avg_us"] if v["trace_avg_us"] else "-", v["source_hash"]))
+    with open(os.path.join(out_dir, "c3_kernels_hbm_traffic.md"), "w") as fh:
         fh.write("\n".join(lines) + "\n")
     print(json.dumps(res))
 
@@ -475,6 +549,10 @@ def main():
     tems = tm["ems_ms"] / max(1, tm["ems_launches"])
     tadj = tm["adjoint_ms"] / max(1, tm["adjoint_launches"])
     log("eager per launch: type1 %.3f ms, ems %.3f ms, adjoint %.3f ms" % (t1, tems, tadj))
+    recon = reconstruction_figures(plan, gb, f, keep, torch, args.steps)
+    log("reconstruction", recon)
+    flow_sel = flow_selection_figures(plan, gb, f, prm, torch, args.steps)
+    log("flow-dependent EMS", flow_sel)
 
     if args.calibrate_copy > 0:
         # one streaming kernel of known traffic whose name no other kernel of this run shares
@@ -505,10 +583,21 @@ def main():
     # algorithmic bytes of one forward launch: read x, y, h, w (16 B per point), write f (8 B per mode)
     fwd_bytes = 16.0 * Q + 8.0 * M * batch.n_cells
     achieved = fwd_bytes / (t1 * 1e-3) / 1e9
-    traffic = measured_traffic() if (args.cells is None and not c1) else None   # counters taken on C3
+    traffic = measured_traffic(FWD_KERNEL) if (args.cells is None and not c1) else None   # counters taken on C3
     roofline = {"bound": "hbm", "achieved": achieved, "peak": 8000.0, "unit": "GB/s",
                 "frac": achieved / 8000.0, "traffic": traffic, "kernel": "fwd_kernel (spread+FFT+deconv+crop)",
                 "bytes_per_launch": fwd_bytes, "avg_launch_ms": t1}
+    # the other two kernels of the step against the same roofline (algorithmic bytes per
+    # launch: EMS reads f and writes the keep bytes; the adjoint reads x, y, h, w, f and keep
+    # and writes three gradients)
+    ems_bytes = 9.0 * M * batch.n_cells
+    adj_bytes = 28.0 * Q + 9.0 * M * batch.n_cells
+    others = {}
+    for k, byts, ms in (("ems_kernel", ems_bytes, tems), ("adj_kernel", adj_bytes, tadj)):
+        ach = byts / (ms * 1e-3) / 1e9
+        others[k] = {"bound": "hbm", "achieved": ach, "peak": 8000.0, "unit": "GB/s", "frac": ach / 8000.0,
+                     "traffic": measured_traffic(k) if (args.cells is None and not c1) else None,
+                     "bytes_per_launch": byts, "avg_launch_ms": ms}
     cpu = cpu1 = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(batch, args.cpu_seconds)
@@ -533,10 +622,12 @@ def main():
         "graph_type1_ems_ms": {"median": t_fwd, "mean": float(graph_ms.mean()), "min": float(graph_ms.min()),
                                "max": float(graph_ms.max())},
         "adjoint_in_step_ms": float(np.median(adj_step_ms)),
+        "reconstruction": recon, "flow_ems": flow_sel,
         "parity_gate": gate, "plan": {k: info[k] for k in ("fwd_threads", "fwd_chunk_min", "fwd_items_per_slot",
-                                                           "adj_items_per_slot", "adj_band_mult", "n_items_fwd",
+                                                           "adj_items_per_slot", "adj_band_mult", "fwd_acc", "n_items_fwd",
                                                            "n_split_cells", "n_items_adj", "tuned")},
-        "per_cell_loop": percell, "roofline": roofline, "cpu_baseline": cpu, "cpu_baseline_1core": cpu1,
+        "per_cell_loop": percell, "roofline": roofline, "roofline_other_kernels": others, "cpu_baseline": cpu,
+        "cpu_baseline_1core": cpu1,
     }
     print(json.dumps(out), flush=True)
 

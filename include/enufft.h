@@ -139,7 +139,7 @@ typedef struct {
     int64_t fwd_chunk_min;   /* smallest forward work item (points) */
     int32_t fwd_items_per_slot, adj_items_per_slot;  /* work items per resident workgroup */
     int32_t adj_band_mult;   /* adjoint row bands = this x the fewest that fit LDS */
-    int32_t reserved_;
+    int32_t fwd_acc;         /* bytes per forward LDS grid cell: 8 (FP64 sums) or 4 (FP32 sums) */
     double tune_fwd_ms, tune_adj_ms;   /* best trial times of the autotuner */
 } enufft_plan_info;
 
@@ -190,6 +190,32 @@ enufft_status enufft_type1_batched(enufft_plan_t p, const void *x, const void *y
 enufft_status enufft_ems(enufft_plan_t p, const void *f, const enufft_ems_params *prm,
                          const double *mode_weight, uint8_t *keep, int32_t *k_star, double *stats);
 
+/* Flow-dependent Elastic Mode Selection repeated over timesteps on fixed coefficients
+ * (Section 2.2.1 eq. (weighted_e) with the launch weight of Appendix A7; Section 3.3
+ * re-selects per timestep as the flow changes).  For step s and cell c the weight of
+ * mode k is
+ *   w_k = |A_k| / |h_k|^2 = (rho / 2) |k.u| (|k|^2 + m^2) / |k|^2,
+ * the wave action of eq. (mw_action) per unit modal power, with the physical wave
+ * vector k = kscale (kx, ky), the intrinsic frequency omega = -k.u (eq. mountain_omega)
+ * and m^2 from the dispersion relation (eq. mw_dispersion); modes outside the
+ * propagating band fc < |omega| < N, and k = 0, weigh 0.  The selection is then
+ * enufft_ems's with these weights.
+ *   f        device, n_cells * N2 * N1 complex: the coefficients (not recomputed).
+ *   prm      host EMS parameters (as enufft_ems).
+ *   n_steps  number of timesteps, >= 1 (n_steps * n_cells < 2^31).
+ *   flow     device, n_steps * n_cells records of 6 doubles (ux, uy, N, fc, rho,
+ *            kscale): background wind (m/s), buoyancy frequency and Coriolis
+ *            parameter (1/s), density, and the physical wave number (rad/m) of one
+ *            unit of the box's integer wave numbers (2 pi / box side).
+ *   keep     device, n_steps * n_cells * N2 * N1 bytes, or NULL to skip the masks.
+ *   k_star   device, n_steps * n_cells int32.
+ *   stats    device, n_steps * n_cells * 8 doubles (as enufft_ems; T and theta are of
+ *            the weighted energies, P is the plain power of the kept modes).
+ * Outputs of step s, cell c are at index s * n_cells + c.  One launch covers all steps.
+ * Mode boxes above 4096 units per cell return ENUFFT_EUNSUPPORTED. */
+enufft_status enufft_ems_flow(enufft_plan_t p, const void *f, const enufft_ems_params *prm, int32_t n_steps,
+                              const double *flow, uint8_t *keep, int32_t *k_star, double *stats);
+
 /* Adjoint of the batched type-1 map (a type-2 NUFFT) and the chain rule.
  *   x, y, h, w  device, n_points each, as for enufft_type1_batched (all four required;
  *               NULL gives ENUFFT_EINVAL).
@@ -214,6 +240,33 @@ enufft_status enufft_type1_adjoint(enufft_plan_t p, const void *x, const void *y
 enufft_status enufft_retained_power_adjoint(enufft_plan_t p, const void *x, const void *y, const void *h,
                                             const void *w, const void *f, const uint8_t *keep,
                                             const double *lam, void *grad_h, void *grad_x, void *grad_y);
+
+/* Reconstruction from retained modes and the per-cell diagnostics of Section 3.2.
+ * For every sample q of cell c, the truncated series of eq. (series) over the kept modes,
+ *   h_rec(x_q) = Re sum_{k kept} coef_c[k] exp(+i (kx x_q + ky y_q)),
+ * evaluated as a type-2 NUFFT (the adjoint's pre-corrected inverse transforms and
+ * gather, without the plan's scale), and per cell, with the target t_q = W_c(x_q) h_q
+ * (the windowed height the coefficients represent; h_q without a window):
+ *   diag[8 c + 0]  Q_c
+ *   diag[8 c + 1]  sum_q (t_q - h_rec(x_q))^2
+ *   diag[8 c + 2]  sum_q t_q^2
+ *   diag[8 c + 3]  sigma^2_phys = (1 / |D_c|) sum_q w_q t_q^2     (eq. spectral_variance, left side)
+ *   diag[8 c + 4]  sigma^2_spec = sum_{k != 0} |coef_c[k]|^2       (eq. spectral_variance, right side)
+ *   diag[8 c + 5]  the same sum over the kept modes only
+ *   diag[8 c + 6]  eps_rel = sqrt(diag[1] / diag[2])               (eq. alps_relative_rmse)
+ *   diag[8 c + 7]  sigma^2_spec / sigma^2_phys (the Parseval ratio)
+ * For the paper's normalisation the coefficients come from a plan with scale = 1 / |D_c|.
+ *   x, y, h, w  device, n_points each (as enufft_type1_batched; all required).
+ *   coef        device, n_cells * N2 * N1 complex (the plan's precision).
+ *   keep        device, n_cells * N2 * N1 bytes (enufft_ems), or NULL for every mode.
+ *   area        device, n_cells doubles |D_c|, or NULL for 1.
+ *   h_rec       device, n_points reals (the plan's precision), or NULL.
+ *   diag        device, n_cells * 8 doubles; sums over samples are FP64, formed per
+ *               work item and added per cell in a fixed order.
+ * Large-cell plans (mode boxes above 64 per axis) return ENUFFT_EUNSUPPORTED. */
+enufft_status enufft_reconstruct(enufft_plan_t p, const void *x, const void *y, const void *h, const void *w,
+                                 const void *coef, const uint8_t *keep, const double *area, void *h_rec,
+                                 double *diag);
 
 /* Plain per-cell form of type-1 + EMS for comparison: the same kernels,
  * launched once per cell from a host loop on the plan's stream (no batching,

@@ -57,12 +57,14 @@ class PlanInfo(ctypes.Structure):
                 ("workspace_bytes", ctypes.c_int64), ("kernel_poly_err", ctypes.c_double),
                 ("tuned", ctypes.c_int32), ("tune_cache_hit", ctypes.c_int32), ("fwd_chunk_min", ctypes.c_int64),
                 ("fwd_items_per_slot", ctypes.c_int32), ("adj_items_per_slot", ctypes.c_int32),
-                ("adj_band_mult", ctypes.c_int32), ("reserved_", ctypes.c_int32),
+                ("adj_band_mult", ctypes.c_int32), ("fwd_acc", ctypes.c_int32),
                 ("tune_fwd_ms", ctypes.c_double), ("tune_adj_ms", ctypes.c_double)]
 
 
 EXPORTS = ["enufft_default_opts", "enufft_plan", "enufft_set_stream", "enufft_type1_batched", "enufft_ems",
-           "enufft_type1_adjoint", "enufft_retained_power_adjoint", "enufft_percell_loop", "enufft_forward_graph", "enufft_set_timing", "enufft_get_timing",
+           "enufft_ems_flow",
+           "enufft_type1_adjoint", "enufft_retained_power_adjoint", "enufft_reconstruct", "enufft_percell_loop",
+           "enufft_forward_graph", "enufft_set_timing", "enufft_get_timing",
            "enufft_get_info", "enufft_destroy", "enufft_last_error", "enufft_version"]
 
 _lib = None
@@ -84,8 +86,10 @@ def load_library(path: str = LIB_PATH):
     L.enufft_set_stream.argtypes = [vp, vp]
     L.enufft_type1_batched.argtypes = [vp] * 6
     L.enufft_ems.argtypes = [vp, vp, ctypes.POINTER(EmsParamsC), vp, vp, vp, vp]
+    L.enufft_ems_flow.argtypes = [vp, vp, ctypes.POINTER(EmsParamsC), i32, vp, vp, vp, vp]
     L.enufft_type1_adjoint.argtypes = [vp] * 9
     L.enufft_retained_power_adjoint.argtypes = [vp] * 11
+    L.enufft_reconstruct.argtypes = [vp] * 10
     L.enufft_percell_loop.argtypes = [vp] * 6 + [ctypes.POINTER(EmsParamsC), vp, vp, vp, vp]
     L.enufft_forward_graph.argtypes = [vp] * 6 + [ctypes.POINTER(EmsParamsC), vp, vp, vp, vp]
     L.enufft_set_timing.argtypes = [vp, i32]
@@ -228,6 +232,26 @@ class Plan:
                self._h)
         return keep, ks, st
 
+    def ems_flow(self, f, flow, params: EmsParams = EmsParams(), need_keep=True):
+        """EMS per timestep under flow-dependent launch weights (Appendix A7) on fixed
+        coefficients.  flow: float64 [n_steps, n_cells, 6] records (ux, uy, N, fc, rho,
+        kscale).  Returns (keep [n_steps, n_cells, N2, N1] or None, k_star [n_steps,
+        n_cells], stats [n_steps, n_cells, 8])."""
+        if f.dtype != self.cdtype or not f.is_contiguous():
+            raise ValueError("f must be contiguous %s" % self.cdtype)
+        fl = torch.as_tensor(flow, dtype=torch.float64, device=self.device).contiguous()
+        if fl.dim() != 3 or fl.shape[1] != self.n_cells or fl.shape[2] != 6:
+            raise ValueError("flow must be [n_steps, n_cells, 6]")
+        T = fl.shape[0]
+        keep = torch.empty((T,) + tuple(f.shape), dtype=torch.uint8, device=self.device) if need_keep else None
+        ks = torch.empty((T, self.n_cells), dtype=torch.int32, device=self.device)
+        st = torch.empty((T, self.n_cells, 8), dtype=torch.float64, device=self.device)
+        prm = params.c()
+        self._sync_stream()
+        _check(self._lib.enufft_ems_flow(self._h, _ptr(f), ctypes.byref(prm), int(T), _ptr(fl), _ptr(keep), _ptr(ks),
+                                         _ptr(st)), self._h)
+        return keep, ks, st
+
     def adjoint(self, x, y, h, w, fbar, need=(True, True, True)):
         self._pts(x, y, h, w)
         if fbar.dtype != self.cdtype or not fbar.is_contiguous():
@@ -250,6 +274,25 @@ class Plan:
                                                        _ptr(keep.contiguous()), _ptr(lam_t), _ptr(outs[0]),
                                                        _ptr(outs[1]), _ptr(outs[2])), self._h)
         return tuple(outs)
+
+    def reconstruct(self, x, y, h, w, coef, keep=None, area=None, need_h_rec=True):
+        """Truncated-series reconstruction over the kept modes and the Section 3.2
+        diagnostics per cell -> (h_rec or None, diag float64 [n_cells, 8]); diag columns:
+        Q_c, sum (t - h_rec)^2, sum t^2, sigma2_phys, sigma2_spec (k != 0), the same over
+        kept modes, eps_rel, sigma2_spec / sigma2_phys (t = W h)."""
+        self._pts(x, y, h, w)
+        if coef.dtype != self.cdtype or not coef.is_contiguous():
+            raise ValueError("coef must be contiguous %s" % self.cdtype)
+        if keep is not None and keep.dtype != torch.uint8:
+            raise ValueError("keep must be uint8")
+        ar = None if area is None else torch.as_tensor(area, dtype=torch.float64, device=self.device).contiguous()
+        hr = torch.empty(self.n_points, dtype=self.dtype, device=self.device) if need_h_rec else None
+        dg = torch.empty((self.n_cells, 8), dtype=torch.float64, device=self.device)
+        self._sync_stream()
+        _check(self._lib.enufft_reconstruct(self._h, _ptr(x), _ptr(y), _ptr(h), _ptr(w), _ptr(coef),
+                                            _ptr(None if keep is None else keep.contiguous()), _ptr(ar), _ptr(hr),
+                                            _ptr(dg)), self._h)
+        return hr, dg
 
     def percell_loop(self, x, y, h, w, params: EmsParams | None = EmsParams(), mode_weight=None):
         self._pts(x, y, h, w)

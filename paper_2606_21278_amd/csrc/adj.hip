@@ -314,10 +314,15 @@ struct RowSpecAcc {
 // point's footprint starts in this band; the chain rule through the strength
 // c_j = w_j W(x_j) h_j turns the interpolated u, du/dx, du/dy into dL/dh,
 // dL/dx, dL/dy.
-template <typename T, int W, bool POLY>
+//
+// RECON: the reconstruction mode.  Only u is interpolated (from the u half of
+// Guv); it is the truncated series h_rec(x_j) (the plan's scale is not applied in
+// this mode), stored to grad_h when given, and the point adds (t - h_rec)^2, t^2
+// and w t^2 to acc, with t = W(x_j) h_j the windowed height.
+template <typename T, int W, bool POLY, bool RECON>
 __device__ __forceinline__ void gather_point(const AdjArgs<T> &a, const T *Guv, const T *Gy, int apitch,
                                              int band_lo, int64_t j, T xj, T yj, T hj, T wj, T cx, T cy, T R,
-                                             T pr) {
+                                             T pr, double (&acc)[3]) {
   const Geom &g = a.g;
   const T halfw = T(W) / T(2);
   const FineCoord<T> fy = fine_coord<T>(yj, a.s2_hi, a.s2_lo, halfw);
@@ -338,12 +343,16 @@ __device__ __forceinline__ void gather_point(const AdjArgs<T> &a, const T *Guv, 
     for (int dx = 0; dx < W; ++dx) {
       const V2 v = puv[dx];
       su += kx[dx] * v.x;
-      sx += kx[dx] * v.y;
-      sy += kx[dx] * py[dx];
+      if constexpr (!RECON) {
+        sx += kx[dx] * v.y;
+        sy += kx[dx] * py[dx];
+      }
     }
     u += kyv * su;
-    ux += kyv * sx;
-    uy += kyv * sy;
+    if constexpr (!RECON) {
+      ux += kyv * sx;
+      uy += kyv * sy;
+    }
     puv += apitch;
     py += apitch;
   };
@@ -363,6 +372,15 @@ __device__ __forceinline__ void gather_point(const AdjArgs<T> &a, const T *Guv, 
     for (int d = 0; d < W; ++d) kx[d] = es_eval(fx.offset(d) * zsc, a.beta);
 #pragma unroll 1
     for (int dy = 0; dy < W; ++dy) row(es_eval(fy.offset(dy) * zsc, a.beta));
+  }
+  if constexpr (RECON) {
+    const double t = (double)(hj * hann_w(a.window_kind, xj, yj, cx, cy, R, pr));
+    const double d = t - (double)u;
+    acc[0] += d * d;
+    acc[1] += t * t;
+    acc[2] += (double)wj * t * t;
+    if (a.grad_h) a.grad_h[j] = u;
+    return;
   }
   T dWx, dWy;
   const T Wv = hann_wg(a.window_kind, xj, yj, cx, cy, R, pr, dWx, dWy);
@@ -385,9 +403,10 @@ __device__ __forceinline__ void gather_point(const AdjArgs<T> &a, const T *Guv, 
 // so the gather is not serialised behind point loads; each wave load reads 256
 // contiguous bytes of an array.  FP64 and the wider kernels (register budget)
 // take one point per thread and step.
-template <typename T, int W, int NT, bool POLY>
+template <typename T, int W, int NT, bool POLY, bool RECON>
 __device__ __forceinline__ void gather_item(const AdjArgs<T> &a, const T *Guv, const T *Gy, int apitch,
-                                            int band_lo, int64_t begin, int64_t end, T cx, T cy, T R) {
+                                            int band_lo, int64_t begin, int64_t end, T cx, T cy, T R,
+                                            double (&acc)[3]) {
   const T pr = R > T(0) ? T(M_PI) / R : T(0);
   constexpr bool kBlocks = sizeof(T) == 4 && W <= 6;
   if constexpr (kBlocks) {
@@ -410,7 +429,8 @@ __device__ __forceinline__ void gather_item(const AdjArgs<T> &a, const T *Guv, c
       for (int u = 0; u < U; ++u) {
         const int64_t i = pb + u * 64 + lane;
         if (i < end)
-          gather_point<T, W, POLY>(a, Guv, Gy, apitch, band_lo, i, b.x[u], b.y[u], b.h[u], b.w[u], cx, cy, R, pr);
+          gather_point<T, W, POLY, RECON>(a, Guv, Gy, apitch, band_lo, i, b.x[u], b.y[u], b.h[u], b.w[u], cx, cy,
+                                          R, pr, acc);
       }
     };
     if (begin < end) {
@@ -429,11 +449,12 @@ __device__ __forceinline__ void gather_item(const AdjArgs<T> &a, const T *Guv, c
     }
   } else {
     for (int64_t j = begin + threadIdx.x; j < end; j += NT)
-      gather_point<T, W, POLY>(a, Guv, Gy, apitch, band_lo, j, a.x[j], a.y[j], a.h[j], a.w[j], cx, cy, R, pr);
+      gather_point<T, W, POLY, RECON>(a, Guv, Gy, apitch, band_lo, j, a.x[j], a.y[j], a.h[j], a.w[j], cx, cy, R,
+                                      pr, acc);
   }
 }
 
-template <typename T, int W, int NT, bool POLY>
+template <typename T, int W, int NT, bool POLY, bool RECON>
 __global__ __launch_bounds__(NT) void adj_kernel(AdjArgs<T> a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T *sm = reinterpret_cast<T *>(smem_raw);
@@ -469,9 +490,9 @@ __global__ __launch_bounds__(NT) void adj_kernel(AdjArgs<T> a) {
 
     // columns of H and of i ky H, inverse transformed along y; keep the band rows
     T *st = sm + L.st_off;
-    const T two_lam = a.keep ? T(2.0 * (a.lam ? a.lam[it.cell] : 1.0)) : T(1);
+    const T two_lam = RECON ? T(1) : a.keep ? T(2.0 * (a.lam ? a.lam[it.cell] : 1.0)) : T(1);
     stage_spectrum<T, NT>(a, gc, it.cell, st);
-    for (int pass = 0; pass < 2; ++pass)
+    for (int pass = 0; pass < (RECON ? 1 : 2); ++pass)
       column_pass<T, NT>(a, st, tw2, two_lam, ws, L.cpitch, pass == 1, pass == 0 ? db0 : db1, L.rows, y0);
 
     // Row stage, one batch of inverse transforms: the (u, du/dx) rows, spectrum
@@ -486,7 +507,7 @@ __global__ __launch_bounds__(NT) void adj_kernel(AdjArgs<T> a) {
     const int ny_pairs = L.rows / 2;
     const int K1 = g.K1;
     row_ifft_natural<NT, T>(
-        n1, L.rows + ny_pairs, tw1, W - 1,
+        n1, RECON ? L.rows : L.rows + ny_pairs, tw1, W - 1,
         [&](int q) {
           RowSpecAcc<T> acc;
           acc.db = q < L.rows ? db0 : db1;
@@ -522,8 +543,25 @@ __global__ __launch_bounds__(NT) void adj_kernel(AdjArgs<T> a) {
 
     // Gather at the points of this band.
     const double *wn = a.windows + 3 * (int64_t)it.cell;
-    gather_item<T, W, NT, POLY>(a, Guv, Gy, L.apitch, it.band * a.band_rows, it.begin, it.end, T(wn[0]), T(wn[1]),
-                          T(wn[2]));
+    double acc[3] = {0.0, 0.0, 0.0};
+    gather_item<T, W, NT, POLY, RECON>(a, Guv, Gy, L.apitch, it.band * a.band_rows, it.begin, it.end, T(wn[0]),
+                                       T(wn[1]), T(wn[2]), acc);
+    if constexpr (RECON) {
+      // the item's three sums, reduced in a fixed order (waves, then lanes)
+      __syncthreads();
+      double *red = reinterpret_cast<double *>(sm);
+      for (int k = 0; k < 3; ++k) {
+        double v = acc[k];
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+        if ((threadIdx.x & 63) == 0) red[k * (NT / 64) + (threadIdx.x >> 6)] = v;
+      }
+      __syncthreads();
+      if (threadIdx.x < 3) {
+        double v = 0.0;
+        for (int q = 0; q < NT / 64; ++q) v += red[threadIdx.x * (NT / 64) + q];
+        a.rec_part[3 * idx + threadIdx.x] = v;
+      }
+    }
     __syncthreads();
     if (!persistent) break;
   }
@@ -545,37 +583,45 @@ template <typename T, int W>
 static const void *adj_fn(int threads, bool poly) {
   if constexpr (adj_has_poly<T, W>()) {
     if (poly)
-      return threads == 256 ? (const void *)&adj_kernel<T, W, 256, true> : (const void *)&adj_kernel<T, W, 512, true>;
+      return threads == 256 ? (const void *)&adj_kernel<T, W, 256, true, false>
+                            : (const void *)&adj_kernel<T, W, 512, true, false>;
   }
-  return threads == 256 ? (const void *)&adj_kernel<T, W, 256, false> : (const void *)&adj_kernel<T, W, 512, false>;
+  return threads == 256 ? (const void *)&adj_kernel<T, W, 256, false, false>
+                        : (const void *)&adj_kernel<T, W, 512, false, false>;
 }
 
-template <typename T, int W>
+template <typename T, int W, bool RECON>
 static hipError_t launch_adj_w(const AdjArgs<T> &a, int blocks, int threads, size_t lds, hipStream_t s) {
   if constexpr (adj_has_poly<T, W>()) {
     if (a.es.on) {
-      if (threads == 256) hipLaunchKernelGGL((adj_kernel<T, W, 256, true>), dim3(blocks), dim3(256), lds, s, a);
-      else hipLaunchKernelGGL((adj_kernel<T, W, 512, true>), dim3(blocks), dim3(512), lds, s, a);
+      if (threads == 256) hipLaunchKernelGGL((adj_kernel<T, W, 256, true, RECON>), dim3(blocks), dim3(256), lds, s, a);
+      else hipLaunchKernelGGL((adj_kernel<T, W, 512, true, RECON>), dim3(blocks), dim3(512), lds, s, a);
       return hipGetLastError();
     }
   }
-  if (threads == 256) hipLaunchKernelGGL((adj_kernel<T, W, 256, false>), dim3(blocks), dim3(256), lds, s, a);
-  else hipLaunchKernelGGL((adj_kernel<T, W, 512, false>), dim3(blocks), dim3(512), lds, s, a);
+  if (threads == 256) hipLaunchKernelGGL((adj_kernel<T, W, 256, false, RECON>), dim3(blocks), dim3(256), lds, s, a);
+  else hipLaunchKernelGGL((adj_kernel<T, W, 512, false, RECON>), dim3(blocks), dim3(512), lds, s, a);
   return hipGetLastError();
+}
+
+template <typename T, bool RECON>
+static hipError_t launch_adj_mode(const AdjArgs<T> &a, int W, int blocks, int threads, size_t lds, hipStream_t s) {
+  switch (W) {
+    case 4: return launch_adj_w<T, 4, RECON>(a, blocks, threads, lds, s);
+    case 6: return launch_adj_w<T, 6, RECON>(a, blocks, threads, lds, s);
+    case 8: return launch_adj_w<T, 8, RECON>(a, blocks, threads, lds, s);
+    case 10: return launch_adj_w<T, 10, RECON>(a, blocks, threads, lds, s);
+    case 12: return launch_adj_w<T, 12, RECON>(a, blocks, threads, lds, s);
+    case 14: return launch_adj_w<T, 14, RECON>(a, blocks, threads, lds, s);
+    case 16: return launch_adj_w<T, 16, RECON>(a, blocks, threads, lds, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 template <typename T>
 hipError_t launch_adj(const AdjArgs<T> &a, int W, int blocks, int threads, size_t lds, hipStream_t s) {
-  switch (W) {
-    case 4: return launch_adj_w<T, 4>(a, blocks, threads, lds, s);
-    case 6: return launch_adj_w<T, 6>(a, blocks, threads, lds, s);
-    case 8: return launch_adj_w<T, 8>(a, blocks, threads, lds, s);
-    case 10: return launch_adj_w<T, 10>(a, blocks, threads, lds, s);
-    case 12: return launch_adj_w<T, 12>(a, blocks, threads, lds, s);
-    case 14: return launch_adj_w<T, 14>(a, blocks, threads, lds, s);
-    case 16: return launch_adj_w<T, 16>(a, blocks, threads, lds, s);
-    default: return hipErrorInvalidValue;
-  }
+  return a.rec_part ? launch_adj_mode<T, true>(a, W, blocks, threads, lds, s)
+                    : launch_adj_mode<T, false>(a, W, blocks, threads, lds, s);
 }
 
 template hipError_t launch_adj<float>(const AdjArgs<float> &, int, int, int, size_t, hipStream_t);
@@ -646,8 +692,26 @@ hipError_t adj_occ(int W, int threads, bool poly, size_t lds, int *per_cu) {
 // Release the adjoint schedule so the next call rebuilds it (autotuner).
 void adj_reset(enufft_plan_t p) {
   if (!p->d_adj_items) return;
-  dev_release(p, &p->d_adj_items, std::max<size_t>(1, p->adj_items.size()) * sizeof(AdjItem));
+  const size_t n = std::max<size_t>(1, p->adj_items.size());
+  dev_release(p, &p->d_adj_items, n * sizeof(AdjItem));
+  dev_release(p, &p->d_rec_part, n * 3 * sizeof(double));
+  dev_release(p, &p->d_cell_items, n * sizeof(int32_t));
+  dev_release(p, &p->d_cell_item_off, (size_t)(p->n_cells + 1) * sizeof(int64_t));
+  dev_release(p, &p->d_cell_off, (size_t)(p->n_cells + 1) * sizeof(int64_t));
   p->adj_items.clear();
+}
+
+// Device allocation recorded in the plan's workspace (released with the plan).
+static enufft_status adj_alloc(enufft_plan_t p, void **d, size_t bytes, const char *what) {
+  hipError_t e = hipMalloc(d, std::max<size_t>(16, bytes));
+  if (e != hipSuccess) {
+    *d = nullptr;
+    p->last_error = std::string(what) + " allocation failed";
+    return ENUFFT_ENOMEM;
+  }
+  p->allocations.push_back(*d);
+  p->workspace_bytes += (int64_t)std::max<size_t>(16, bytes);
+  return ENUFFT_OK;
 }
 
 // Lazily set up the adjoint schedule on first use.
@@ -682,21 +746,36 @@ enufft_status adj_prepare(enufft_plan_t p) {
   const int slots = p->n_cu * per_cu;
   build_adj_schedule(p, slots);
   p->adj_blocks = (int)std::min<int64_t>(slots, std::max<int64_t>(1, (int64_t)p->adj_items.size()));
-  void *d = nullptr;
-  e = hipMalloc(&d, std::max<size_t>(1, p->adj_items.size()) * sizeof(AdjItem));
-  if (e != hipSuccess) {
-    p->last_error = "adjoint item allocation failed";
-    return ENUFFT_ENOMEM;
+  const size_t n_items = std::max<size_t>(1, p->adj_items.size());
+  // the items of each cell, ascending (the reconstruction sums a cell's item
+  // partials in this fixed order)
+  std::vector<int64_t> coff(p->n_cells + 1, 0);
+  for (const AdjItem &it : p->adj_items) ++coff[it.cell + 1];
+  for (int64_t c = 0; c < p->n_cells; ++c) coff[c + 1] += coff[c];
+  std::vector<int32_t> citems(n_items, 0);
+  {
+    std::vector<int64_t> pos(coff.begin(), coff.end() - 1);
+    for (size_t i = 0; i < p->adj_items.size(); ++i) citems[pos[p->adj_items[i].cell]++] = (int32_t)i;
   }
-  p->allocations.push_back(d);
-  p->workspace_bytes += (int64_t)(std::max<size_t>(1, p->adj_items.size()) * sizeof(AdjItem));
-  if (!p->adj_items.empty()) {
+  void *d = nullptr;
+  enufft_status st = adj_alloc(p, &d, n_items * sizeof(AdjItem), "adjoint item");
+  if (st == ENUFFT_OK) st = adj_alloc(p, &p->d_rec_part, n_items * 3 * sizeof(double), "reconstruction partials");
+  if (st == ENUFFT_OK) st = adj_alloc(p, &p->d_cell_items, n_items * sizeof(int32_t), "cell item list");
+  if (st == ENUFFT_OK)
+    st = adj_alloc(p, &p->d_cell_item_off, (size_t)(p->n_cells + 1) * sizeof(int64_t), "cell item offsets");
+  if (st == ENUFFT_OK) st = adj_alloc(p, &p->d_cell_off, (size_t)(p->n_cells + 1) * sizeof(int64_t), "cell offsets");
+  if (st != ENUFFT_OK) return st;
+  if (!p->adj_items.empty())
     e = hipMemcpy(d, p->adj_items.data(), p->adj_items.size() * sizeof(AdjItem), hipMemcpyHostToDevice);
-    if (e != hipSuccess) {
-      p->last_error = std::string("adjoint item upload: ") + hipGetErrorString(e);
-      p->faulted = true;
-      return ENUFFT_EDEVICE;
-    }
+  if (e == hipSuccess) e = hipMemcpy(p->d_cell_items, citems.data(), n_items * sizeof(int32_t), hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemcpy(p->d_cell_item_off, coff.data(), coff.size() * sizeof(int64_t), hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemcpy(p->d_cell_off, p->offsets.data(), p->offsets.size() * sizeof(int64_t), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    p->last_error = std::string("adjoint item upload: ") + hipGetErrorString(e);
+    p->faulted = true;
+    return ENUFFT_EDEVICE;
   }
   p->d_adj_items = d;
   return ENUFFT_OK;
@@ -806,4 +885,124 @@ extern "C" enufft_status enufft_retained_power_adjoint(enufft_plan_t p, const vo
   }
   return enufft::adjoint_common(p, "enufft_retained_power_adjoint", x, y, h, w, f, keep, lam, grad_h, grad_x,
                                 grad_y);
+}
+
+// ------------------------------------------------------------------ reconstruction
+
+namespace enufft {
+
+// Per cell: the sums over its items' partials (fixed order) and the spectral
+// sums of Parseval's identity over the modes k != 0, all of them and the kept
+// ones (a fixed-order tree over 256 threads), then the diagnostics.
+template <typename T>
+__global__ __launch_bounds__(256) void rec_finalize_kernel(const T *coef, const uint8_t *keep, const double *area,
+                                                           const double *part, const int32_t *cell_items,
+                                                           const int64_t *cell_item_off, const int64_t *cell_off,
+                                                           Geom g, double *diag) {
+  __shared__ double s_all[256], s_kept[256];
+  const int64_t c = blockIdx.x;
+  const int M = g.N1 * g.N2;
+  const T *cc = coef + 2 * (int64_t)M * c;
+  const uint8_t *kc = keep ? keep + (int64_t)M * c : nullptr;
+  double sa = 0.0, sk = 0.0;
+  for (int m = threadIdx.x; m < M; m += 256) {
+    const int r = m / g.N1, i = m - r * g.N1;
+    if (g.lo1 + i == 0 && g.lo2 + r == 0) continue;
+    const double re = (double)cc[2 * m], im = (double)cc[2 * m + 1];
+    const double p2 = re * re + im * im;
+    sa += p2;
+    if (!kc || kc[m]) sk += p2;
+  }
+  s_all[threadIdx.x] = sa;
+  s_kept[threadIdx.x] = sk;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) {
+      s_all[threadIdx.x] += s_all[threadIdx.x + o];
+      s_kept[threadIdx.x] += s_kept[threadIdx.x + o];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    double e2 = 0.0, t2 = 0.0, wt2 = 0.0;
+    for (int64_t q = cell_item_off[c]; q < cell_item_off[c + 1]; ++q) {
+      const int64_t it = cell_items[q];
+      e2 += part[3 * it];
+      t2 += part[3 * it + 1];
+      wt2 += part[3 * it + 2];
+    }
+    const double A = area ? area[c] : 1.0;
+    double *d = diag + 8 * c;
+    d[0] = (double)(cell_off[c + 1] - cell_off[c]);
+    d[1] = e2;
+    d[2] = t2;
+    d[3] = wt2 / A;
+    d[4] = s_all[0];
+    d[5] = s_kept[0];
+    d[6] = t2 > 0.0 ? sqrt(e2 / t2) : 0.0;
+    d[7] = d[3] > 0.0 ? d[4] / d[3] : 0.0;
+  }
+}
+
+}  // namespace enufft
+
+extern "C" enufft_status enufft_reconstruct(enufft_plan_t p, const void *x, const void *y, const void *h,
+                                            const void *w, const void *coef, const uint8_t *keep,
+                                            const double *area, void *h_rec, double *diag) {
+  using namespace enufft;
+  if (!p) return ENUFFT_EINVAL;
+  if (p->faulted) {
+    p->last_error = "enufft_reconstruct: plan unusable after a device fault";
+    return ENUFFT_ESTATE;
+  }
+  if (p->big) {
+    p->last_error = "enufft_reconstruct: not implemented for large-cell plans (mode boxes above 64 per axis)";
+    return ENUFFT_EUNSUPPORTED;
+  }
+  if (p->n_cells == 0) return ENUFFT_OK;
+  if (!coef || !diag) {
+    p->last_error = "enufft_reconstruct: null coefficients or diagnostics";
+    return ENUFFT_EINVAL;
+  }
+  if (p->n_points > 0 && (!x || !y || !h || !w)) {
+    p->last_error = "enufft_reconstruct: null point array";
+    return ENUFFT_EINVAL;
+  }
+  enufft_status st = adj_prepare(p);
+  if (st != ENUFFT_OK) return st;
+  hipError_t e = hipSuccess;
+  if (p->n_points > 0) {
+    if (p->prec == ENUFFT_F64) {
+      auto a = make_adj_args<double>(p, x, y, h, w, coef, h_rec, nullptr, nullptr);
+      a.keep = keep;
+      a.decon_x = (const double *)p->d_decon_x1;
+      a.rec_part = (double *)p->d_rec_part;
+      e = launch_adj<double>(a, p->W, p->adj_blocks, p->adj_threads, p->adj_lds, p->stream);
+    } else {
+      auto a = make_adj_args<float>(p, x, y, h, w, coef, h_rec, nullptr, nullptr);
+      a.keep = keep;
+      a.decon_x = (const float *)p->d_decon_x1;
+      a.rec_part = (double *)p->d_rec_part;
+      e = launch_adj<float>(a, p->W, p->adj_blocks, p->adj_threads, p->adj_lds, p->stream);
+    }
+  }
+  if (e == hipSuccess) {
+    if (p->prec == ENUFFT_F64)
+      hipLaunchKernelGGL(rec_finalize_kernel<double>, dim3((unsigned)p->n_cells), dim3(256), 0, p->stream,
+                         (const double *)coef, keep, area, (const double *)p->d_rec_part,
+                         (const int32_t *)p->d_cell_items, (const int64_t *)p->d_cell_item_off,
+                         (const int64_t *)p->d_cell_off, p->geom, diag);
+    else
+      hipLaunchKernelGGL(rec_finalize_kernel<float>, dim3((unsigned)p->n_cells), dim3(256), 0, p->stream,
+                         (const float *)coef, keep, area, (const double *)p->d_rec_part,
+                         (const int32_t *)p->d_cell_items, (const int64_t *)p->d_cell_item_off,
+                         (const int64_t *)p->d_cell_off, p->geom, diag);
+    e = hipGetLastError();
+  }
+  if (e != hipSuccess) {
+    p->last_error = std::string("enufft_reconstruct launch: ") + hipGetErrorString(e);
+    p->faulted = true;
+    return ENUFFT_EDEVICE;
+  }
+  return ENUFFT_OK;
 }

@@ -553,13 +553,16 @@ struct BigCut {   // written by the scores pass
 
 template <typename C>
 __device__ __forceinline__ double big_pair_energy(const C *f, const double *mw, int rep, int partner) {
+#pragma clang fp contract(off)
   const int pq = partner >= 0 ? partner : rep;
   const C fr = f[rep], fp = f[pq];
+  // each product and sum rounded on its own (no fused multiply-add), as the
+  // in-register EMS path does
   double e = (double)fr.x * (double)fr.x + (double)fr.y * (double)fr.y;
   double ep = (double)fp.x * (double)fp.x + (double)fp.y * (double)fp.y;
   if (mw) {
-    e *= mw[rep];
-    ep *= mw[pq];
+    e = e * mw[rep];
+    ep = ep * mw[pq];
   }
   return partner >= 0 ? e + ep : e;
 }

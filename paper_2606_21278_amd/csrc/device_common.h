@@ -63,6 +63,7 @@ struct FwdArgs {
   T beta;                    // ES shape parameter
   T s1_hi, s1_lo, s2_hi, s2_lo;   // n1 / (2 pi) and n2 / (2 pi) as hi + lo
   int vec4;                  // x, y, h, w are 16-byte aligned: load runs of 4 points
+  int acc;                   // bytes per LDS grid cell: 8 (FP64 sums) or 4 (FP32 sums)
   EsPoly es;                 // FP32 plans: per-tap kernel polynomials (es.on = 0: exact kernel)
   Geom g;
 };
@@ -88,6 +89,7 @@ struct AdjArgs {
   EsPoly es;                   // as in FwdArgs
   int vec4;                    // x, y, h, w are 16-byte aligned: load runs of 4 points
   int bands, band_rows;        // row bands per cell and rows per band
+  double *rec_part;            // reconstruction mode: per item (sum (t - h_rec)^2, sum t^2, sum w t^2)
   Geom g;
 };
 

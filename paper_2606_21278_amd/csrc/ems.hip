@@ -23,6 +23,8 @@ namespace enufft {
 struct EmsArgs {
   const void *f;
   const double *mode_weight;
+  const double *flow;         // flow mode: [n_steps * n_cells_f][6] records (ux, uy, N, fc, rho, kscale)
+  int64_t n_cells_f;          // flow mode: cells per step (the coefficients of cell v mod n_cells_f)
   uint8_t *keep;
   int32_t *k_star;
   double *stats;
@@ -157,17 +159,66 @@ __device__ __forceinline__ void wave_sort_desc(double (&e)[R], int lane) {
 // ranking and the keep pass (mode order), so a unit's energy is bit-identical
 // in all three.  Loads are unconditional (a missing partner reads the
 // representative and is masked).
-template <typename C>
-__device__ __forceinline__ double pair_energy_v(const C fr, const C fp, double wr, double wp, bool partner) {
-  const double e = ((double)fr.x * (double)fr.x + (double)fr.y * (double)fr.y) * wr;
-  const double ep = ((double)fp.x * (double)fp.x + (double)fp.y * (double)fp.y) * wp;
-  return partner ? e + ep : e;
+//
+// Every product and sum is rounded on its own (contraction into fused
+// multiply-adds is off here): the keep pass forms a pair's energy from either
+// member first, and only separately rounded member terms make
+// w_a |f_a|^2 + w_b |f_b|^2 the same bits in both orders when the weights are
+// not 1.
+__device__ __forceinline__ double member_energy(double re, double im, double w) {
+#pragma clang fp contract(off)
+  return (re * re + im * im) * w;
 }
 
 template <typename C>
-__device__ __forceinline__ double pair_energy(const EmsArgs &a, const C *f, int rep, int partner) {
+__device__ __forceinline__ double pair_energy_v(const C fr, const C fp, double wr, double wp, bool partner) {
+#pragma clang fp contract(off)
+  const double e = member_energy((double)fr.x, (double)fr.y, wr);
+  const double ep = member_energy((double)fp.x, (double)fp.y, wp);
+  return partner ? e + ep : e;
+}
+
+// Flow mode: the weight of eq. (weighted_e) is the launch weight of an
+// orographic gravity wave (Appendix A7) under the cell's flow record, in the
+// paper's order: intrinsic frequency omega = -k . u (eq. mountain_omega), the
+// vertical wave number from the dispersion relation (eq. mw_dispersion), the
+// wave action of eq. (mw_action) per unit modal power, taken in magnitude (the
+// action and omega share their signed branch, so the wave energy is positive).
+// Modes outside the propagating band fc < |omega| < N, and k = 0, weigh 0.
+// k = kscale (kx, ky) is the physical wave vector.
+struct FlowRec {
+  double ux, uy, N, fc, rho, ks;
+  bool on;
+};
+
+__device__ __forceinline__ double flow_weight(const FlowRec &fl, int kx, int ky) {
+#pragma clang fp contract(off)
+  const double k1 = fl.ks * (double)kx, k2 = fl.ks * (double)ky;
+  const double kk = k1 * k1 + k2 * k2;
+  if (!(kk > 0.0)) return 0.0;
+  const double omega = -(k1 * fl.ux + k2 * fl.uy);
+  const double aw = fabs(omega);
+  if (!(aw > fabs(fl.fc) && aw < fl.N)) return 0.0;
+  const double m2 = kk * (fl.N * fl.N - omega * omega) / (omega * omega - fl.fc * fl.fc);
+  const double act = -(fl.rho / 2.0) * (k1 * fl.ux + k2 * fl.uy) * (kk + m2) / kk;
+  return fabs(act);
+}
+
+// Weight of mode m (row-major, N1 per row): the flow weight, the caller's
+// mode_weight, or 1.
+__device__ __forceinline__ double mode_w(const EmsArgs &a, const FlowRec &fl, int m) {
+  if (fl.on) {
+    const int r = m / a.N1, i = m - r * a.N1;
+    return flow_weight(fl, i - (a.N1 >> 1), r - (a.N2 >> 1));
+  }
+  return a.mode_weight ? a.mode_weight[m] : 1.0;
+}
+
+template <typename C>
+__device__ __forceinline__ double pair_energy(const EmsArgs &a, const FlowRec &fl, const C *f, int rep, int partner) {
   const int pq = partner >= 0 ? partner : rep;
-  const double wr = a.mode_weight ? a.mode_weight[rep] : 1.0, wp = a.mode_weight ? a.mode_weight[pq] : 1.0;
+  const bool wt = a.mode_weight || fl.on;
+  const double wr = wt ? mode_w(a, fl, rep) : 1.0, wp = wt ? mode_w(a, fl, pq) : 1.0;
   return pair_energy_v<C>(f[rep], f[pq], wr, wp, partner >= 0);
 }
 
@@ -176,7 +227,7 @@ __device__ __forceinline__ double pair_energy(const EmsArgs &a, const C *f, int 
 // then (with mode weights) the weights.  reps[i] < 0 marks an entry with no
 // unit (its energy is returned as 0).
 template <typename C, int N>
-__device__ __forceinline__ void batch_energy(const EmsArgs &a, const C *f, const int (&reps)[N],
+__device__ __forceinline__ void batch_energy(const EmsArgs &a, const FlowRec &fl, const C *f, const int (&reps)[N],
                                              const int (&partners)[N], double (&e)[N]) {
   C fr[N], fp[N];
 #pragma unroll
@@ -185,13 +236,13 @@ __device__ __forceinline__ void batch_energy(const EmsArgs &a, const C *f, const
     fr[i] = f[rep];
     fp[i] = f[partners[i] >= 0 ? partners[i] : rep];
   }
-  if (a.mode_weight) {
+  if (a.mode_weight || fl.on) {
     double wr[N], wp[N];
 #pragma unroll
     for (int i = 0; i < N; ++i) {
       const int rep = reps[i] >= 0 ? reps[i] : 0;
-      wr[i] = a.mode_weight[rep];
-      wp[i] = a.mode_weight[partners[i] >= 0 ? partners[i] : rep];
+      wr[i] = mode_w(a, fl, rep);
+      wp[i] = mode_w(a, fl, partners[i] >= 0 ? partners[i] : rep);
     }
 #pragma unroll
     for (int i = 0; i < N; ++i)
@@ -287,9 +338,18 @@ __global__ __launch_bounds__(64 * NW) void ems_kernel(EmsArgs a) {
   __shared__ double redd[NW];
   __shared__ int redi[NW];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, t = threadIdx.x;
+  // cell: the output index; in flow mode step s of cell c is v = s n_cells_f + c
+  // and reads the coefficients of cell c
   const int64_t cell = a.cell_begin + blockIdx.x;
+  const int64_t fcell = a.flow ? cell % a.n_cells_f : cell;
   using C = typename vec2<T>::type;
-  const C *f = reinterpret_cast<const C *>(a.f) + cell * a.M;
+  const C *f = reinterpret_cast<const C *>(a.f) + fcell * a.M;
+  FlowRec fl{};
+  fl.on = a.flow != nullptr;
+  if (fl.on) {
+    const double *fr = a.flow + 6 * cell;
+    fl.ux = fr[0]; fl.uy = fr[1]; fl.N = fr[2]; fl.fc = fr[3]; fl.rho = fr[4]; fl.ks = fr[5];
+  }
   const int J = a.J;
 
   // eq. (energy) / (weighted_e), unit u = position t R + r.  Padding is +0,
@@ -312,7 +372,7 @@ __global__ __launch_bounds__(64 * NW) void ems_kernel(EmsArgs a) {
       partners[i] = un.y;
     }
     double eb[EB];
-    batch_energy<C, EB>(a, f, reps, partners, eb);
+    batch_energy<C, EB>(a, fl, f, reps, partners, eb);
 #pragma unroll
     for (int i = 0; i < EB; ++i) e[r0 + i] = eb[i];
   }
@@ -445,14 +505,14 @@ __global__ __launch_bounds__(64 * NW) void ems_kernel(EmsArgs a) {
     for (int r = 0; r < R; ++r) {
       const int u = t * R + r;
       const int2 un = a.units[u < J ? u : max(J - 1, 0)];
-      ties += (u < J && pair_energy<C>(a, f, un.x, un.y) == eth);
+      ties += (u < J && pair_energy<C>(a, fl, f, un.x, un.y) == eth);
     }
     int rank = block_exclusive_scan<NW, int>(ties, redi, wave, lane);
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const int u = t * R + r;
       const int2 un = a.units[u < J ? u : max(J - 1, 0)];
-      const bool tie = u < J && pair_energy<C>(a, f, un.x, un.y) == eth;
+      const bool tie = u < J && pair_energy<C>(a, fl, f, un.x, un.y) == eth;
       tie_kept[u] = tie && rank < need;
       rank += tie;
     }
@@ -469,7 +529,7 @@ __global__ __launch_bounds__(64 * NW) void ems_kernel(EmsArgs a) {
   // e(rep) + e(partner) bit for bit (the same member terms; FP64 addition
   // commutes).
   double pw = 0.0;
-  uint8_t *kout = a.keep + cell * a.M;
+  uint8_t *kout = a.keep ? a.keep + cell * a.M : nullptr;   // flow mode may skip the masks
   constexpr int UK = 4;
   const int N1 = a.N1, hm1 = 2 * (a.N1 >> 1), hm2 = 2 * (a.N2 >> 1);
   const float inv_n1 = 1.0f / (float)N1;
@@ -493,12 +553,12 @@ __global__ __launch_bounds__(64 * NW) void ems_kernel(EmsArgs a) {
       fo[u] = f[mo[u]];
     }
     double eu[UK];
-    if (a.mode_weight) {
+    if (a.mode_weight || fl.on) {
       double wm[UK], wo[UK];
 #pragma unroll
       for (int u = 0; u < UK; ++u) {
-        wm[u] = a.mode_weight[mm[u]];
-        wo[u] = a.mode_weight[mo[u]];
+        wm[u] = mode_w(a, fl, mm[u]);
+        wo[u] = mode_w(a, fl, mo[u]);
       }
 #pragma unroll
       for (int u = 0; u < UK; ++u) eu[u] = pair_energy_v<C>(fm[u], fo[u], wm[u], wo[u], mu[u].y >= 0);
@@ -516,7 +576,7 @@ __global__ __launch_bounds__(64 * NW) void ems_kernel(EmsArgs a) {
 #pragma unroll
     for (int u = 0; u < UK; ++u) {
       const int m = m0 + u * NT;
-      if (m < a.M) kout[m] = v[u];
+      if (m < a.M && kout) kout[m] = v[u];
     }
   }
   const double P = block_sum<NW>(pw, redd, wave);
@@ -673,5 +733,57 @@ extern "C" enufft_status enufft_ems(enufft_plan_t p, const void *f, const enufft
   if (st != ENUFFT_OK) return st;
   st = enufft::ems_launch(p, f, prm, mode_weight, keep, k_star, stats, 0, p->n_cells);
   if (st != ENUFFT_OK) return st;
+  return enufft::record_stop(p, 1, ev);
+}
+
+extern "C" enufft_status enufft_ems_flow(enufft_plan_t p, const void *f, const enufft_ems_params *prm,
+                                         int32_t n_steps, const double *flow, uint8_t *keep, int32_t *k_star,
+                                         double *stats) {
+  if (!p) return ENUFFT_EINVAL;
+  if (p->faulted) {
+    p->last_error = "enufft_ems_flow: plan unusable after a device fault";
+    return ENUFFT_ESTATE;
+  }
+  uint8_t dummy = 0;
+  // the masks are optional here: validate with a stand-in pointer
+  enufft_status st = enufft::ems_validate(p, f, prm, keep ? keep : &dummy, k_star, stats);
+  if (st != ENUFFT_OK) return st;
+  if (n_steps < 1 || !flow) {
+    p->last_error = "enufft_ems_flow: need n_steps >= 1 and flow records";
+    return ENUFFT_EINVAL;
+  }
+  if (p->n_cells == 0) return ENUFFT_OK;
+  if ((int64_t)n_steps * p->n_cells > (int64_t)INT32_MAX) {
+    p->last_error = "enufft_ems_flow: n_steps * n_cells above 2^31 - 1";
+    return ENUFFT_EINVAL;
+  }
+  enufft::UnitTable *ut = nullptr;
+  st = enufft::ems_units(p, prm, &ut);
+  if (st != ENUFFT_OK) return st;
+  if (ut->Jpad > 4096) {
+    p->last_error = "enufft_ems_flow: more than 4096 units per cell is not supported";
+    return ENUFFT_EUNSUPPORTED;
+  }
+  enufft::EmsArgs a{};
+  a.f = f; a.mode_weight = nullptr; a.flow = flow; a.n_cells_f = p->n_cells;
+  a.keep = keep; a.k_star = k_star; a.stats = stats;
+  a.units = ut->d_units; a.mode_unit = ut->d_mode_unit; a.J = ut->J; a.M = p->N1 * p->N2;
+  a.N1 = p->N1; a.N2 = p->N2;
+  a.cell_begin = 0;
+  a.cell_end = (int64_t)n_steps * p->n_cells;
+  a.k_min = prm->k_min; a.k_max = prm->k_max;
+  a.alpha_min = prm->alpha_min; a.alpha_max = prm->alpha_max; a.delta = prm->delta;
+  a.w1 = prm->w1; a.w2 = prm->w2;
+  hipEvent_t ev;
+  st = enufft::record_start(p, 1, &ev);
+  if (st != ENUFFT_OK) return st;
+  const int blocks = (int)a.cell_end;
+  hipError_t e = p->prec == ENUFFT_F64 ? enufft::launch_ems_t<double>(a, ut->J, blocks, p->stream)
+                                       : enufft::launch_ems_t<float>(a, ut->J, blocks, p->stream);
+  if (e != hipSuccess) {
+    p->last_error = std::string("enufft_ems_flow launch: ") + hipGetErrorString(e);
+    p->faulted = true;
+    return ENUFFT_EDEVICE;
+  }
   return enufft::record_stop(p, 1, ev);
 }

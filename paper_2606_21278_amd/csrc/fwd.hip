@@ -24,6 +24,14 @@ __device__ __forceinline__ int grid_pitch(const Geom &g) {
   return P > 0 ? P : g.pitch;
 }
 
+// Waves per SIMD the register allocation must allow: an FP32 grid of the
+// 128-wide fine grid takes about 70 KB, so two 512-thread workgroups share a
+// CU when each wave stays within 128 VGPRs.
+template <typename A, int NT>
+constexpr int fwd_min_waves() {
+  return (sizeof(A) == 4 && NT == 512) ? 4 : 1;
+}
+
 // Kernel values along one axis.  The P != 0 builds are launched only when the
 // plan carries the kernel polynomial, so they evaluate it directly.
 template <typename T, int W, int P>
@@ -34,29 +42,28 @@ __device__ __forceinline__ void taps(const FwdArgs<T> &a, const FineCoord<T> &c,
     es_taps<T, W>(c, a.beta, a.es, out);
 }
 
-// Add one point's W x W contributions to the FP64 grid.
-// The grid accumulates in FP64: on gfx950 the LDS adds FP64 values many times
-// faster than FP32 ones, and the wider sum costs no accuracy.  Stored row r
-// holds fine row r mod n2 (rows n2 .. n2 + W - 1 are folded back afterwards);
-// columns wrap with the grid mask.
-template <typename T, int W, int P>
-__device__ __forceinline__ void spread_point(const FwdArgs<T> &a, double *grid, T c, const FineCoord<T> &fx,
+// Add one point's W x W contributions to the grid, whose cells accumulate in A
+// (FP32 or FP64; FP64 plans always use FP64).  Stored row r holds fine row
+// r mod n2 (rows n2 .. n2 + W - 1 are folded back afterwards); columns wrap
+// with the grid mask.
+template <typename T, typename A, int W, int P>
+__device__ __forceinline__ void spread_point(const FwdArgs<T> &a, A *grid, T c, const FineCoord<T> &fx,
                                              const FineCoord<T> &fy) {
   const Geom &g = a.g;
   const int pitch = grid_pitch<P>(g);
   T tx[W], ty[W];
   taps<T, W, P>(a, fx, tx);
   taps<T, W, P>(a, fy, ty);
-  double kx[W], ky[W];
+  A kx[W], ky[W];
 #pragma unroll
   for (int d = 0; d < W; ++d) {
-    kx[d] = (double)tx[d];
-    ky[d] = (double)(c * ty[d]);
+    kx[d] = (A)tx[d];
+    ky[d] = (A)(c * ty[d]);
   }
   int col[W];
 #pragma unroll
   for (int d = 0; d < W; ++d) col[d] = (fx.i0 + d) & (g.n1 - 1);
-  double *rowp = grid + (fy.i0 & (g.n2 - 1)) * pitch;
+  A *rowp = grid + (fy.i0 & (g.n2 - 1)) * pitch;
 #pragma unroll
   for (int dy = 0; dy < W; ++dy) {
 #pragma unroll
@@ -137,8 +144,8 @@ __device__ __forceinline__ RunGeom run_geom(const FwdArgs<T> &a, const float (&x
 // the next.  With rev the columns go out from the last to the first, so two
 // lanes whose windows start at the same cell never add to one address in the
 // same instruction.
-template <typename T, int W, int P>
-__device__ __forceinline__ void run_spread(const FwdArgs<T> &a, double *grid, const RunGeom &rg,
+template <typename T, typename A, int W, int P>
+__device__ __forceinline__ void run_spread(const FwdArgs<T> &a, A *grid, const RunGeom &rg,
                                            const float (&cs)[RUN_K], bool rev) {
   constexpr int WC = W + RUN_SX, WR = W + RUN_SY;
   const Geom &g = a.g;
@@ -166,7 +173,7 @@ __device__ __forceinline__ void run_spread(const FwdArgs<T> &a, double *grid, co
     }
   }
   const int pitch = grid_pitch<P>(g);
-  double *rowp = grid + (rg.rmin & (g.n2 - 1)) * pitch;
+  A *rowp = grid + (rg.rmin & (g.n2 - 1)) * pitch;
   const int c0 = rev ? rg.cmin + WC - 1 : rg.cmin;
   // The column step, tied to this group's origin by an empty asm statement so
   // the compiler forms dc j per group instead of holding the products live
@@ -186,18 +193,18 @@ __device__ __forceinline__ void run_spread(const FwdArgs<T> &a, double *grid, co
 #pragma unroll
       for (int r = 0; r < WR; ++r) col[r] = (k == 0) ? KY[k][r] * xv : fmaf(KY[k][r], xv, col[r]);
     }
-    double *cp = rowp + ((c0 + dc * j) & (g.n1 - 1));
+    A *cp = rowp + ((c0 + dc * j) & (g.n1 - 1));
     // window cells outside the footprints' bounding box hold exact zeros: their
     // lanes skip the add (fewer lanes per LDS atomic)
     const bool cact = rev ? (j >= RUN_SX - rg.cspan) : (j < W + rg.cspan);
     if (cact) {
 #pragma unroll
       for (int r = 0; r < W; ++r)
-        __hip_atomic_fetch_add(cp + r * pitch, (double)col[r], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        __hip_atomic_fetch_add(cp + r * pitch, (A)col[r], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 #pragma unroll
       for (int r = W; r < WR; ++r)
         if (r < W + rg.rspan)
-          __hip_atomic_fetch_add(cp + r * pitch, (double)col[r], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+          __hip_atomic_fetch_add(cp + r * pitch, (A)col[r], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     }
   }
 }
@@ -213,8 +220,8 @@ __device__ __forceinline__ void wave_lds_sync() {
 
 // Spread the deferred groups queue[0 .. n) of this wave, one group per lane,
 // point by point.  Entries are group offsets from g0 (groups of RUN_K points).
-template <typename T, int W, int P>
-__device__ __forceinline__ void drain_groups(const FwdArgs<T> &a, double *grid, const int *queue, int n,
+template <typename T, typename A, int W, int P>
+__device__ __forceinline__ void drain_groups(const FwdArgs<T> &a, A *grid, const int *queue, int n,
                                              int64_t g0, T cx, T cy, T R, T pr) {
   using V = typename vec4<T>::type;
   const int lane = threadIdx.x & 63;
@@ -234,14 +241,14 @@ __device__ __forceinline__ void drain_groups(const FwdArgs<T> &a, double *grid, 
     const T wk = k == 0 ? ws[0] : k == 1 ? ws[1] : k == 2 ? ws[2] : ws[3];
     const T c = wk * hk * hann_w(a.window_kind, xk, yk, cx, cy, R, pr);
     if (c != T(0))
-      spread_point<T, W, P>(a, grid, c, fine_coord<T>(xk, a.s1_hi, a.s1_lo, halfw),
-                            fine_coord<T>(yk, a.s2_hi, a.s2_lo, halfw));
+      spread_point<T, A, W, P>(a, grid, c, fine_coord<T>(xk, a.s1_hi, a.s1_lo, halfw),
+                               fine_coord<T>(yk, a.s2_hi, a.s2_lo, halfw));
   }
 }
 
-// Spread the points [begin, end) of one item into the FP64 LDS grid.
-template <typename T, int W, int NT, int P>
-__device__ __forceinline__ void spread_item(const FwdArgs<T> &a, double *grid, int *queue, int64_t begin,
+// Spread the points [begin, end) of one item into the LDS grid.
+template <typename T, typename A, int W, int NT, int P>
+__device__ __forceinline__ void spread_item(const FwdArgs<T> &a, A *grid, int *queue, int64_t begin,
                                             int64_t end, T cx, T cy, T R) {
   const T halfw = T(W) / T(2);
   const T pr = R > T(0) ? T(M_PI) / R : T(0);
@@ -294,7 +301,7 @@ __device__ __forceinline__ void spread_item(const FwdArgs<T> &a, double *grid, i
         cs[k] = live ? (&wv.x)[k] * (&hv.x)[k] * hann_w(a.window_kind, xs[k], ys[k], cx, cy, R, pr) : 0.0f;
       const RunGeom rg = run_geom<T, W>(a, xs, ys, cs, rev);
       const bool defer = live && !rg.fits;
-      if (live && rg.any && rg.fits) run_spread<T, W, P>(a, grid, rg, cs, rev);
+      if (live && rg.any && rg.fits) run_spread<T, A, W, P>(a, grid, rg, cs, rev);
       const uint64_t m = __ballot(defer);
       if (m != 0) {
         if (defer) {
@@ -304,7 +311,7 @@ __device__ __forceinline__ void spread_item(const FwdArgs<T> &a, double *grid, i
         nq += __popcll(m);
         if (nq >= 64) {
           wave_lds_sync();
-          drain_groups<T, W, P>(a, grid, queue, 64, g0, cx, cy, R, pr);
+          drain_groups<T, A, W, P>(a, grid, queue, 64, g0, cx, cy, R, pr);
           nq -= 64;
           const int rest = lane < nq ? queue[64 + lane] : 0;
           wave_lds_sync();
@@ -314,7 +321,7 @@ __device__ __forceinline__ void spread_item(const FwdArgs<T> &a, double *grid, i
       }
     };
     V x0{}, y0{}, h0{}, w0{}, x1{}, y1{}, h1{}, w1{};
-    if constexpr (NT >= 1024) {
+    if constexpr (NT * fwd_min_waves<A, NT>() >= 1024 || NT >= 1024) {
       // four waves per SIMD hide the load latency with one block in flight
       if (q1 > g0) load(x0, y0, h0, w0, q);
       for (int64_t qb = g0; qb < q1; qb += 2 * NT, q += 2 * NT) {
@@ -340,7 +347,7 @@ __device__ __forceinline__ void spread_item(const FwdArgs<T> &a, double *grid, i
     }
     if (nq > 0) {
       wave_lds_sync();
-      drain_groups<T, W, P>(a, grid, queue, nq, g0, cx, cy, R, pr);
+      drain_groups<T, A, W, P>(a, grid, queue, nq, g0, cx, cy, R, pr);
     }
   }
   // points outside the aligned body, one per thread
@@ -350,14 +357,14 @@ __device__ __forceinline__ void spread_item(const FwdArgs<T> &a, double *grid, i
     const T xj = a.x[j], yj = a.y[j];
     const T c = a.w[j] * a.h[j] * hann_w(a.window_kind, xj, yj, cx, cy, R, pr);
     if (c == T(0)) continue;
-    spread_point<T, W, P>(a, grid, c, fine_coord<T>(xj, a.s1_hi, a.s1_lo, halfw),
-                          fine_coord<T>(yj, a.s2_hi, a.s2_lo, halfw));
+    spread_point<T, A, W, P>(a, grid, c, fine_coord<T>(xj, a.s1_hi, a.s1_lo, halfw),
+                             fine_coord<T>(yj, a.s2_hi, a.s2_lo, halfw));
   }
 }
 
 // Fold stored rows n2 .. n2 + W - 1 onto rows 0 .. W - 1.
-template <int W, int NT>
-__device__ __forceinline__ void fold_rows(double *grid, const Geom &g) {
+template <typename A, int W, int NT>
+__device__ __forceinline__ void fold_rows(A *grid, const Geom &g) {
   const int pitch = g.pitch;
   for (int i = threadIdx.x; i < W * g.n1; i += NT) {
     const int r = i / g.n1, c = i - r * g.n1;
@@ -369,9 +376,10 @@ __device__ __forceinline__ void fold_rows(double *grid, const Geom &g) {
 // Round the FP64 grid (n2 rows of `pitch`) to T in place: element i moves from
 // byte 8 i to byte sizeof(T) i.  Each round reads a block before any thread
 // writes it, and a write of round k lands on bytes read in rounds <= k.
-template <typename T, int NT>
-__device__ __forceinline__ void grid_to_t(double *grid, const Geom &g) {
-  if constexpr (sizeof(T) == sizeof(double)) {
+// Nothing to do when the grid already accumulates in T.
+template <typename T, typename A, int NT>
+__device__ __forceinline__ void grid_to_t(A *grid, const Geom &g) {
+  if constexpr (sizeof(T) == sizeof(A)) {
     return;
   } else {
     constexpr int PER = 8;
@@ -519,11 +527,11 @@ __device__ void fft_deconv_store(const FwdArgs<T> &a, T *G, int cell) {
   }
 }
 
-template <typename T, int W, int NT, int P>
-__global__ __launch_bounds__(NT) void fwd_kernel(FwdArgs<T> a) {
+template <typename T, typename A, int W, int NT, int P>
+__global__ __launch_bounds__(NT, (fwd_min_waves<A, NT>())) void fwd_kernel(FwdArgs<T> a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  double *grid = reinterpret_cast<double *>(smem_raw);
-  int *queue = reinterpret_cast<int *>(smem_raw + fwd_grid_bytes(a.g, W)) + (threadIdx.x >> 6) * FWD_QCAP;
+  A *grid = reinterpret_cast<A *>(smem_raw);
+  int *queue = reinterpret_cast<int *>(smem_raw + fwd_grid_bytes(a.g, W, sizeof(A))) + (threadIdx.x >> 6) * FWD_QCAP;
   T *G = reinterpret_cast<T *>(smem_raw);   // the same grid after rounding to T
   __shared__ int s_item, s_last;
   const Geom &g = a.g;
@@ -541,13 +549,13 @@ __global__ __launch_bounds__(NT) void fwd_kernel(FwdArgs<T> a) {
       if (idx >= a.n_items) break;
     }
     const FwdItem it = a.items[idx];
-    for (int i = threadIdx.x; i < total; i += NT) grid[i] = 0.0;
+    for (int i = threadIdx.x; i < total; i += NT) grid[i] = A(0);
     __syncthreads();
     const double *wn = a.windows + 3 * (int64_t)it.cell;
-    spread_item<T, W, NT, P>(a, grid, queue, it.begin, it.end, T(wn[0]), T(wn[1]), T(wn[2]));
+    spread_item<T, A, W, NT, P>(a, grid, queue, it.begin, it.end, T(wn[0]), T(wn[1]), T(wn[2]));
     __syncthreads();
-    fold_rows<W, NT>(grid, g);
-    grid_to_t<T, NT>(grid, g);
+    fold_rows<A, W, NT>(grid, g);
+    grid_to_t<T, A, NT>(grid, g);
     bool run_fft = true;
     if (it.nchunks > 1) {
       const int nn = g.n1 * g.n2;
@@ -593,41 +601,44 @@ __global__ __launch_bounds__(NT) void fwd_kernel(FwdArgs<T> a) {
 
 // The compiled variants: FP32 with the kernel polynomial (W <= 8) also has
 // polynomial builds, one with the constant pitch of the 128-wide grid and one
-// for any pitch, used when the plan carries the polynomial.
+// for any pitch, used when the plan carries the polynomial; those builds come
+// with an FP64 and an FP32 LDS grid (acc = 8 or 4 bytes per cell).
 template <typename T, int W>
 constexpr bool has_pitch128() {
   return sizeof(T) == 4 && W <= ES_MAXW;
 }
 
+template <typename T, typename A, int W, int P>
+static const void *fwd_fn_threads(int threads) {
+  if (threads == 256) return (const void *)&fwd_kernel<T, A, W, 256, P>;
+  if (threads == 512) return (const void *)&fwd_kernel<T, A, W, 512, P>;
+  return (const void *)&fwd_kernel<T, A, W, 1024, P>;
+}
+
 template <typename T, int W>
-static const void *fwd_fn(int threads, int pitch) {
+static const void *fwd_fn(int threads, int pitch, int acc) {
   if constexpr (has_pitch128<T, W>()) {
-    if (pitch == FWD_PITCH128) {
-      if (threads == 256) return (const void *)&fwd_kernel<T, W, 256, FWD_PITCH128>;
-      if (threads == 512) return (const void *)&fwd_kernel<T, W, 512, FWD_PITCH128>;
-      return (const void *)&fwd_kernel<T, W, 1024, FWD_PITCH128>;
-    }
-    if (pitch == FWD_POLY_ANY) {
-      if (threads == 256) return (const void *)&fwd_kernel<T, W, 256, FWD_POLY_ANY>;
-      if (threads == 512) return (const void *)&fwd_kernel<T, W, 512, FWD_POLY_ANY>;
-      return (const void *)&fwd_kernel<T, W, 1024, FWD_POLY_ANY>;
-    }
+    if (pitch == FWD_PITCH128)
+      return acc == 4 ? fwd_fn_threads<T, float, W, FWD_PITCH128>(threads)
+                      : fwd_fn_threads<T, double, W, FWD_PITCH128>(threads);
+    if (pitch == FWD_POLY_ANY)
+      return acc == 4 ? fwd_fn_threads<T, float, W, FWD_POLY_ANY>(threads)
+                      : fwd_fn_threads<T, double, W, FWD_POLY_ANY>(threads);
   }
-  if (threads == 256) return (const void *)&fwd_kernel<T, W, 256, 0>;
-  if (threads == 512) return (const void *)&fwd_kernel<T, W, 512, 0>;
-  return (const void *)&fwd_kernel<T, W, 1024, 0>;
+  if (acc != 8) return nullptr;
+  return fwd_fn_threads<T, double, W, 0>(threads);
 }
 
 template <typename T>
-static const void *fwd_fn_w(int W, int threads, int pitch) {
+static const void *fwd_fn_w(int W, int threads, int pitch, int acc) {
   switch (W) {
-    case 4: return fwd_fn<T, 4>(threads, pitch);
-    case 6: return fwd_fn<T, 6>(threads, pitch);
-    case 8: return fwd_fn<T, 8>(threads, pitch);
-    case 10: return fwd_fn<T, 10>(threads, pitch);
-    case 12: return fwd_fn<T, 12>(threads, pitch);
-    case 14: return fwd_fn<T, 14>(threads, pitch);
-    case 16: return fwd_fn<T, 16>(threads, pitch);
+    case 4: return fwd_fn<T, 4>(threads, pitch, acc);
+    case 6: return fwd_fn<T, 6>(threads, pitch, acc);
+    case 8: return fwd_fn<T, 8>(threads, pitch, acc);
+    case 10: return fwd_fn<T, 10>(threads, pitch, acc);
+    case 12: return fwd_fn<T, 12>(threads, pitch, acc);
+    case 14: return fwd_fn<T, 14>(threads, pitch, acc);
+    case 16: return fwd_fn<T, 16>(threads, pitch, acc);
     default: return nullptr;
   }
 }
@@ -635,16 +646,16 @@ static const void *fwd_fn_w(int W, int threads, int pitch) {
 template <typename T>
 hipError_t launch_fwd(const FwdArgs<T> &a, int W, int blocks, int threads, size_t lds, hipStream_t s) {
   if (threads != 256 && threads != 512 && threads != 1024) return hipErrorInvalidValue;
-  const void *fn = fwd_fn_w<T>(W, threads, fwd_variant_pitch(a.g, a.es));
+  const void *fn = fwd_fn_w<T>(W, threads, fwd_variant_pitch(a.g, a.es), a.acc);
   if (!fn) return hipErrorInvalidValue;
   void *args[] = {const_cast<FwdArgs<T> *>(&a)};
   return hipLaunchKernel(fn, dim3(blocks), dim3(threads), args, lds, s);
 }
 
 template <typename T>
-hipError_t fwd_occupancy(int W, int threads, int pitch, size_t lds, int *blocks_per_cu) {
+hipError_t fwd_occupancy(int W, int threads, int pitch, int acc, size_t lds, int *blocks_per_cu) {
   if (threads != 256 && threads != 512 && threads != 1024) return hipErrorInvalidValue;
-  const void *fn = fwd_fn_w<T>(W, threads, pitch);
+  const void *fn = fwd_fn_w<T>(W, threads, pitch, acc);
   if (!fn) return hipErrorInvalidValue;
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
@@ -653,7 +664,7 @@ hipError_t fwd_occupancy(int W, int threads, int pitch, size_t lds, int *blocks_
 
 template hipError_t launch_fwd<float>(const FwdArgs<float> &, int, int, int, size_t, hipStream_t);
 template hipError_t launch_fwd<double>(const FwdArgs<double> &, int, int, int, size_t, hipStream_t);
-template hipError_t fwd_occupancy<float>(int, int, int, size_t, int *);
-template hipError_t fwd_occupancy<double>(int, int, int, size_t, int *);
+template hipError_t fwd_occupancy<float>(int, int, int, int, size_t, int *);
+template hipError_t fwd_occupancy<double>(int, int, int, int, size_t, int *);
 
 }  // namespace enufft

@@ -11,7 +11,7 @@ namespace enufft {
 template <typename T>
 hipError_t launch_fwd(const FwdArgs<T> &a, int W, int blocks, int threads, size_t lds, hipStream_t s);
 template <typename T>
-hipError_t fwd_occupancy(int W, int threads, int pitch, size_t lds, int *blocks_per_cu);
+hipError_t fwd_occupancy(int W, int threads, int pitch, int acc, size_t lds, int *blocks_per_cu);
 
 template <typename T>
 hipError_t launch_adj(const AdjArgs<T> &a, int W, int blocks, int threads, size_t lds, hipStream_t s);
@@ -24,9 +24,6 @@ constexpr int FWD_QCAP = 128;
 // the FP32 forward kernel is compiled with the pitch as a constant.
 constexpr int FWD_PITCH128 = 130;
 
-// LDS bytes of the forward kernel: the FP64 spread grid with W wrap rows
-// (a merged run of points spans up to W + 1 rows), then one deferred-group
-// queue per wave.
 // Pitch argument that selects the forward build: FWD_PITCH128 for the
 // constant-pitch polynomial build, FWD_POLY_ANY for the polynomial build with
 // the pitch read at run time, 0 for the general one (exact kernel or
@@ -37,11 +34,14 @@ inline int fwd_variant_pitch(const Geom &g, const EsPoly &es) {
   return g.pitch == FWD_PITCH128 ? FWD_PITCH128 : FWD_POLY_ANY;
 }
 
-__host__ __device__ inline size_t fwd_grid_bytes(const Geom &g, int W) {
-  return ((size_t)(g.n2 + W) * g.pitch * sizeof(double) + 15) / 16 * 16;
+// LDS bytes of the forward kernel: the spread grid (acc = 8 or 4 bytes per
+// cell) with W wrap rows (a merged run of points spans up to W + 1 rows), then
+// one deferred-group queue per wave.
+__host__ __device__ inline size_t fwd_grid_bytes(const Geom &g, int W, size_t acc) {
+  return ((size_t)(g.n2 + W) * g.pitch * acc + 15) / 16 * 16;
 }
-inline size_t fwd_lds_bytes(const Geom &g, int W, int threads) {
-  return fwd_grid_bytes(g, W) + (size_t)(threads / 64) * FWD_QCAP * sizeof(int);
+inline size_t fwd_lds_bytes(const Geom &g, int W, int threads, size_t acc) {
+  return fwd_grid_bytes(g, W, acc) + (size_t)(threads / 64) * FWD_QCAP * sizeof(int);
 }
 
 }  // namespace enufft

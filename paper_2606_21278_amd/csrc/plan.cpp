@@ -281,12 +281,14 @@ void build_fwd_schedule(enufft_plan_t p, int slots) {
 enufft_status set_fwd_threads(enufft_plan_t p, int threads, size_t lds_limit) {
   if (threads != 256 && threads != 512 && threads != 1024)
     return fail(p, ENUFFT_EINVAL, "forward threads must be 256, 512 or 1024");
-  const size_t lds = fwd_lds_bytes(p->geom, p->W, threads);
+  const int vp = fwd_variant_pitch(p->geom, p->es);
+  // FP32 sums in LDS exist only for the FP32 polynomial builds
+  if (p->prec == ENUFFT_F64 || vp == 0) p->fwd_acc = 8;
+  const size_t lds = fwd_lds_bytes(p->geom, p->W, threads, (size_t)p->fwd_acc);
   if (lds > lds_limit) return fail(p, ENUFFT_EUNSUPPORTED, "enufft_plan: fine grid does not fit in LDS at this precision");
   int per_cu = 0;
-  const int vp = fwd_variant_pitch(p->geom, p->es);
-  hipError_t e = (p->prec == ENUFFT_F64) ? fwd_occupancy<double>(p->W, threads, vp, lds, &per_cu)
-                                         : fwd_occupancy<float>(p->W, threads, vp, lds, &per_cu);
+  hipError_t e = (p->prec == ENUFFT_F64) ? fwd_occupancy<double>(p->W, threads, vp, p->fwd_acc, lds, &per_cu)
+                                         : fwd_occupancy<float>(p->W, threads, vp, p->fwd_acc, lds, &per_cu);
   if (e != hipSuccess) return hip_fail(p, e, "occupancy query");
   if (per_cu < 1) return fail(p, ENUFFT_EDEVICE, "forward kernel cannot be resident");
   p->fwd_threads = threads;
@@ -455,6 +457,9 @@ enufft_status enufft_plan(enufft_plan_t *out, int64_t n_cells, const int64_t *ce
   if (!big) {
     int threads = 512;
     if (const char *ev = std::getenv("ENUFFT_FWD_THREADS")) threads = std::atoi(ev);
+    if (const char *ev = std::getenv("ENUFFT_FWD_ACC")) p->fwd_acc = std::atoi(ev) == 4 ? 4 : 8;
+    if (const char *ev = std::getenv("ENUFFT_FWD_CHUNK_MIN")) p->fwd_chunk_min = std::max(1024LL, std::atoll(ev));
+    if (const char *ev = std::getenv("ENUFFT_FWD_ITEMS_PER_SLOT")) p->fwd_items_per_slot = std::max(1, std::atoi(ev));
     st = enufft::set_fwd_threads(p, threads, (size_t)prop.sharedMemPerBlock);
     if (st != ENUFFT_OK) { std::string m = p->last_error; free_plan(p); return fail(nullptr, st, m); }
   }
@@ -462,8 +467,9 @@ enufft_status enufft_plan(enufft_plan_t *out, int64_t n_cells, const int64_t *ce
   // ---- tables (FP64 on the host, rounded to the compute precision)
   const int Kx = g.K1, Ky = g.K2;
   std::vector<double> px = kernel_ft(W, beta, n1, Kx), py = kernel_ft(W, beta, n2, Ky);
-  std::vector<double> dx(Kx + 1), dy(Ky + 1);
+  std::vector<double> dx(Kx + 1), dy(Ky + 1), dx1(Kx + 1);
   for (int k = 0; k <= Kx; ++k) dx[k] = opts->scale / px[k];
+  for (int k = 0; k <= Kx; ++k) dx1[k] = 1.0 / px[k];
   for (int k = 0; k <= Ky; ++k) dy[k] = 1.0 / py[k];
   std::vector<double> tw1(2 * n1), tw2(2 * n2);
   for (int j = 0; j < n1; ++j) { tw1[2 * j] = std::cos(2 * M_PI * j / n1); tw1[2 * j + 1] = -std::sin(2 * M_PI * j / n1); }
@@ -493,6 +499,7 @@ enufft_status enufft_plan(enufft_plan_t *out, int64_t n_cells, const int64_t *ce
     return e2 == hipSuccess ? ENUFFT_OK : hip_fail(p, e2, what);
   };
   for (auto &tb : {std::make_pair(&p->d_decon_x, &dx), std::make_pair(&p->d_decon_y, &dy),
+                   std::make_pair(&p->d_decon_x1, &dx1),
                    std::make_pair(&p->d_tw1, &tw1), std::make_pair(&p->d_tw2, &tw2)}) {
     st = upload_table(tb.first, *tb.second, "tables");
     if (st != ENUFFT_OK) { std::string m = p->last_error; free_plan(p); return fail(nullptr, st, m); }
@@ -558,6 +565,7 @@ enufft_status enufft_get_info(enufft_plan_t p, enufft_plan_info *info) {
   info->fwd_items_per_slot = p->fwd_items_per_slot;
   info->adj_items_per_slot = p->adj_items_per_slot;
   info->adj_band_mult = p->adj_band_mult;
+  info->fwd_acc = p->big ? 8 : p->fwd_acc;
   info->tune_fwd_ms = p->tune_fwd_ms;
   info->tune_adj_ms = p->tune_adj_ms;
   return ENUFFT_OK;
@@ -646,6 +654,7 @@ FwdArgs<T> make_fwd_args(enufft_plan_t p, const void *x, const void *y, const vo
   a.beta = (T)p->beta;
   split_scale<T>(p->n1, &a.s1_hi, &a.s1_lo);
   split_scale<T>(p->n2, &a.s2_hi, &a.s2_lo);
+  a.acc = p->fwd_acc;
   a.es = p->es;
   a.g = p->geom;
   return a;

@@ -45,6 +45,7 @@ struct enufft_plan_s {
   int fwd_items_per_slot = 2;      // target forward items per resident workgroup
   int adj_items_per_slot = 2;      // same for the adjoint
   int adj_band_mult = 1;           // adjoint bands = mult x the fewest that fit LDS
+  int fwd_acc = 8;                 // bytes per forward LDS grid cell: 8 (FP64 sums) or 4 (FP32 sums)
   bool tuned = false, tune_cache_hit = false;
   double tune_fwd_ms = 0.0, tune_adj_ms = 0.0;   // best trial times (ms)
 
@@ -56,8 +57,12 @@ struct enufft_plan_s {
   int fwd_threads = 512, fwd_blocks = 0, fwd_slots = 0;
   size_t fwd_lds = 0;
 
-  // adjoint schedule
+  // adjoint schedule (also used by the reconstruction diagnostics)
   std::vector<enufft::AdjItem> adj_items;
+  void *d_rec_part = nullptr;        // [items][3] doubles: per-item reconstruction sums
+  void *d_cell_items = nullptr;      // int32 item indices grouped by cell (ascending)
+  void *d_cell_item_off = nullptr;   // int64 [n_cells + 1] offsets into d_cell_items
+  void *d_cell_off = nullptr;        // int64 [n_cells + 1] the plan's cell offsets
   int adj_bands = 1, adj_band_rows = 0;
   int adj_threads = 512, adj_blocks = 0;
   size_t adj_lds = 0;
@@ -69,6 +74,7 @@ struct enufft_plan_s {
   int *d_cell_counters = nullptr;
   void *d_partial = nullptr;
   void *d_decon_x = nullptr, *d_decon_y = nullptr, *d_tw1 = nullptr, *d_tw2 = nullptr;
+  void *d_decon_x1 = nullptr;      // 1 / p_x(|k|) without the plan's scale (reconstruction)
   enufft::EsPoly es{};             // FP32 plans: kernel polynomial coefficients (es.on = 0: exact)
   double es_poly_err = 0.0;        // max |poly - psi| over the fit interval
   enufft::UnitTable units[2][2];

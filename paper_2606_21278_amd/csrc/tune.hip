@@ -71,7 +71,7 @@ __global__ void tune_points_kernel(const int64_t *off, const double *win, int us
 
 struct Choice {
   int64_t chunk_min = 16384;
-  int fwd_ips = 2, adj_ips = 2, band_mult = 1, fwd_threads = 512;
+  int fwd_ips = 2, adj_ips = 2, band_mult = 1, fwd_threads = 512, fwd_acc = 8;
   double fwd_ms = 0.0, adj_ms = 0.0;
 };
 
@@ -84,7 +84,7 @@ uint64_t fnv1a(const void *data, size_t n, uint64_t h = 1469598103934665603ULL) 
 std::string cache_key(enufft_plan_t p, const char *arch) {
   uint64_t hsh = fnv1a(p->offsets.data(), p->offsets.size() * sizeof(int64_t));
   char buf[320];
-  std::snprintf(buf, sizeof(buf), "%s_cu%d_p%d_m%dx%d_g%dx%d_w%d_win%d_o%d_c%lld_q%lld_h%016llx", arch, p->n_cu,
+  std::snprintf(buf, sizeof(buf), "v2_%s_cu%d_p%d_m%dx%d_g%dx%d_w%d_win%d_o%d_c%lld_q%lld_h%016llx", arch, p->n_cu,
                 p->prec, p->N1, p->N2, p->n1, p->n2, p->W, p->window_kind, p->opts.autotune == 2 ? 1 : 0,
                 (long long)p->n_cells, (long long)p->n_points, (unsigned long long)hsh);
   std::string k(buf);
@@ -110,7 +110,8 @@ std::string cache_path() {
 bool valid(const Choice &c) {
   const bool pow2 = c.fwd_ips > 0 && c.adj_ips > 0 && c.band_mult > 0;
   const bool thr = c.fwd_threads == 256 || c.fwd_threads == 512 || c.fwd_threads == 1024;
-  return pow2 && thr && c.chunk_min >= 1024 && c.chunk_min <= (1LL << 24) && c.fwd_ips <= 64 && c.adj_ips <= 64 &&
+  const bool acc = c.fwd_acc == 4 || c.fwd_acc == 8;
+  return pow2 && thr && acc && c.chunk_min >= 1024 && c.chunk_min <= (1LL << 24) && c.fwd_ips <= 64 && c.adj_ips <= 64 &&
          c.band_mult <= 8;
 }
 
@@ -124,8 +125,8 @@ bool cache_lookup(const std::string &path, const std::string &key, Choice *out) 
     char k[400];
     long long cm = 0;
     Choice c;
-    if (std::sscanf(line, "%399s %lld %d %d %d %d %lf %lf", k, &cm, &c.fwd_ips, &c.adj_ips, &c.band_mult,
-                    &c.fwd_threads, &c.fwd_ms, &c.adj_ms) == 8 &&
+    if (std::sscanf(line, "%399s %lld %d %d %d %d %d %lf %lf", k, &cm, &c.fwd_ips, &c.adj_ips, &c.band_mult,
+                    &c.fwd_threads, &c.fwd_acc, &c.fwd_ms, &c.adj_ms) == 9 &&
         key == k) {
       c.chunk_min = cm;
       if (valid(c)) { *out = c; found = true; }   // the last valid entry wins
@@ -139,8 +140,8 @@ void cache_store(const std::string &path, const std::string &key, const Choice &
   if (path.empty()) return;
   FILE *f = std::fopen(path.c_str(), "a");
   if (!f) return;
-  std::fprintf(f, "%s %lld %d %d %d %d %.6f %.6f\n", key.c_str(), (long long)c.chunk_min, c.fwd_ips, c.adj_ips,
-               c.band_mult, c.fwd_threads, c.fwd_ms, c.adj_ms);
+  std::fprintf(f, "%s %lld %d %d %d %d %d %.6f %.6f\n", key.c_str(), (long long)c.chunk_min, c.fwd_ips, c.adj_ips,
+               c.band_mult, c.fwd_threads, c.fwd_acc, c.fwd_ms, c.adj_ms);
   std::fclose(f);
 }
 
@@ -221,9 +222,14 @@ enufft_status run_trials(enufft_plan_t t, size_t lds_limit, int unordered, Choic
   enufft_status st = ENUFFT_OK;
   const int reps = 3;
 
-  // forward: workgroup size x chunk floor x items per resident workgroup
+  // forward: workgroup size x chunk floor x items per resident workgroup.  The
+  // grid sums stay FP64: the FP32-sum build (half the LDS, two workgroups per
+  // CU) measured about six times slower on the 20,480-cell batch, its LDS adds
+  // being far slower per instruction, so it is not a candidate.
   double fbest = 1e300;
   Choice c = *best;
+  const int acc = 8;
+  t->fwd_acc = acc;
   for (int thr : {512, 1024}) {
     if (set_fwd_threads(t, thr, lds_limit) != ENUFFT_OK) continue;   // does not fit: not a candidate
     for (int64_t cm : {4096LL, 16384LL, 65536LL}) {
@@ -235,7 +241,7 @@ enufft_status run_trials(enufft_plan_t t, size_t lds_limit, int unordered, Choic
         double ms = 0.0;
         st = time_calls(t, [&] { return enufft_type1_batched(t, x, y, h, w, f); }, reps, e0, e1, &ms);
         if (st != ENUFFT_OK) break;
-        if (ms < fbest) { fbest = ms; c.chunk_min = cm; c.fwd_ips = ips; c.fwd_threads = thr; }
+        if (ms < fbest) { fbest = ms; c.chunk_min = cm; c.fwd_ips = ips; c.fwd_threads = thr; c.fwd_acc = acc; }
       }
       if (st != ENUFFT_OK) break;
     }
@@ -245,6 +251,7 @@ enufft_status run_trials(enufft_plan_t t, size_t lds_limit, int unordered, Choic
   // adjoint: items per resident workgroup x row bands (the forward output above
   // stands in for the cotangent source; keep is all ones)
   double abest = 1e300;
+  t->fwd_acc = c.fwd_acc;
   if (st == ENUFFT_OK) st = set_fwd_threads(t, c.fwd_threads, lds_limit);
   if (st == ENUFFT_OK) {
     t->fwd_chunk_min = c.chunk_min;
@@ -313,6 +320,7 @@ enufft_status autotune(enufft_plan_t p) {
     if (st != ENUFFT_OK) return st;
     cache_store(path, key, c);
   }
+  p->fwd_acc = c.fwd_acc;
   enufft_status st = set_fwd_threads(p, c.fwd_threads, (size_t)prop.sharedMemPerBlock);
   if (st != ENUFFT_OK) return st;
   p->fwd_chunk_min = c.chunk_min;

@@ -108,7 +108,7 @@ def test_full_c3_ems_on_sampled_cells(full_c3):
             assert abs(int(full_c3["ks"][i]) - r.k_star) <= max(2, r.k_star // 100), i
     print("EMS: robust cells %d of %d (excluded as near-ties: %d); identical kept sets %d of %d"
           % (robust, n, n - robust, same_set, n), flush=True)
-    assert robust >= 0.75 * n
+    assert robust >= 0.85 * n and same_set >= 0.9 * n   # measured: 59 and 63 of 64
 
 
 def test_full_c3_adjoint_on_sampled_cells(full_c3):
@@ -134,7 +134,7 @@ def test_full_c3_gradients_end_to_end(full_c3):
                                   kind=a["kind"])
     mask = np.repeat(same, np.diff(a["offsets"]))
     print("cells with identical kept sets: %d of %d" % (same.sum(), len(same)), flush=True)
-    assert same.mean() >= 0.75
+    assert same.mean() >= 0.9   # measured: 63 of 64
     for name, got, want in (("h", full_c3["gh"], rh), ("x", full_c3["gx"], rx), ("y", full_c3["gy"], ry)):
         e = rel_l2(got.astype(np.float64)[mask], want[mask])
         print("end-to-end grad_%s rel-l2 %.3e" % (name, e), flush=True)
