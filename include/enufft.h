@@ -174,6 +174,20 @@ enufft_status enufft_set_stream(enufft_plan_t p, void *hip_stream);
 enufft_status enufft_type1_batched(enufft_plan_t p, const void *x, const void *y, const void *h,
                                    const void *w, void *f);
 
+/* Allocation-free form of enufft_type1_batched, for callers that cannot allocate device
+ * memory while they run (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid allocation).  Arguments and results as enufft_type1_batched.  The forward
+ * kernel's scratch -- the persistent loop's work counters, the per-cell merge counters
+ * and the partial grids of cells split over several workgroups -- comes from one fixed
+ * device array of 64 MiB per GPU (held until the process ends), not from the plan's
+ * workspace; the call makes no allocation of any kind (the plan, made beforehand, still
+ * owns its tables and work list).  The counters are cleared by a kernel at the start of
+ * every call.  Calls that overlap on one GPU share that array and race: serialise them.
+ * A plan needing more scratch than the array holds returns ENUFFT_EINVAL (the message
+ * gives the size); large-cell plans return ENUFFT_EUNSUPPORTED. */
+enufft_status enufft_type1_batched_noalloc(enufft_plan_t p, const void *x, const void *y, const void *h,
+                                           const void *w, void *f);
+
 /* Elastic Mode Selection on coefficients f (Section 2.2, eqs. energy ... k_elastic).
  *   f           device, n_cells * N2 * N1 complex (the plan's precision).
  *   prm         host parameters.

@@ -61,7 +61,8 @@ class PlanInfo(ctypes.Structure):
                 ("tune_fwd_ms", ctypes.c_double), ("tune_adj_ms", ctypes.c_double)]
 
 
-EXPORTS = ["enufft_default_opts", "enufft_plan", "enufft_set_stream", "enufft_type1_batched", "enufft_ems",
+EXPORTS = ["enufft_default_opts", "enufft_plan", "enufft_set_stream", "enufft_type1_batched",
+           "enufft_type1_batched_noalloc", "enufft_ems",
            "enufft_ems_flow",
            "enufft_type1_adjoint", "enufft_retained_power_adjoint", "enufft_reconstruct", "enufft_percell_loop",
            "enufft_forward_graph", "enufft_set_timing", "enufft_get_timing",
@@ -85,6 +86,7 @@ def load_library(path: str = LIB_PATH):
                               ctypes.POINTER(Opts), vp]
     L.enufft_set_stream.argtypes = [vp, vp]
     L.enufft_type1_batched.argtypes = [vp] * 6
+    L.enufft_type1_batched_noalloc.argtypes = [vp] * 6
     L.enufft_ems.argtypes = [vp, vp, ctypes.POINTER(EmsParamsC), vp, vp, vp, vp]
     L.enufft_ems_flow.argtypes = [vp, vp, ctypes.POINTER(EmsParamsC), i32, vp, vp, vp, vp]
     L.enufft_type1_adjoint.argtypes = [vp] * 9
@@ -216,6 +218,19 @@ class Plan:
         self._sync_stream()
         _check(self._lib.enufft_type1_batched(self._h, _ptr(x), _ptr(y), _ptr(h), _ptr(w), _ptr(f)), self._h)
         return f
+
+    def type1_noalloc(self, x, y, h, w, out):
+        """Batched type-1 through the allocation-free entry point: the forward's scratch
+        comes from the library's fixed device array; out is a preallocated coefficient
+        tensor (the call allocates nothing)."""
+        self._pts(x, y, h, w)
+        if out.dtype != self.cdtype or not out.is_contiguous() or out.shape != (self.n_cells,) + self.n_modes[::-1]:
+            raise ValueError("out must be a contiguous %s tensor of shape %s" % (self.cdtype,
+                                                                                (self.n_cells,) + self.n_modes[::-1]))
+        self._sync_stream()
+        _check(self._lib.enufft_type1_batched_noalloc(self._h, _ptr(x), _ptr(y), _ptr(h), _ptr(w), _ptr(out)),
+               self._h)
+        return out
 
     def ems(self, f, params: EmsParams = EmsParams(), mode_weight=None):
         if f.dtype != self.cdtype or not f.is_contiguous():

@@ -660,6 +660,11 @@ FwdArgs<T> make_fwd_args(enufft_plan_t p, const void *x, const void *y, const vo
   return a;
 }
 
+template FwdArgs<float> make_fwd_args<float>(enufft_plan_t, const void *, const void *, const void *, const void *,
+                                             void *);
+template FwdArgs<double> make_fwd_args<double>(enufft_plan_t, const void *, const void *, const void *, const void *,
+                                               void *);
+
 enufft_status check_plan(enufft_plan_t p, const char *fn) {
   if (!p) return fail(nullptr, ENUFFT_EINVAL, std::string(fn) + ": null plan");
   if (p->faulted) return fail(p, ENUFFT_ESTATE, std::string(fn) + ": plan unusable after a device fault");

@@ -115,6 +115,10 @@ struct enufft_plan_s {
 };
 
 namespace enufft {
+// Kernel arguments of the batched forward for plan p (defined with the plan).
+template <typename T>
+FwdArgs<T> make_fwd_args(enufft_plan_t p, const void *x, const void *y, const void *h, const void *w, void *f);
+enufft_status check_plan(enufft_plan_t p, const char *fn);
 // Workspace helpers shared by the translation units (defined with the plan).
 void dev_release(enufft_plan_t p, void **ptr, size_t bytes);
 enufft_status install_fwd_schedule(enufft_plan_t p);
