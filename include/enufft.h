@@ -65,6 +65,15 @@ typedef enum { ENUFFT_F32 = 0, ENUFFT_F64 = 1 } enufft_precision;
  * indicator masks of Appendix A1; radius must be > 0). */
 typedef enum { ENUFFT_WIN_NONE = 0, ENUFFT_WIN_HANN_RADIAL = 1 } enufft_window_kind;
 
+/* Spreading kernel (Section 2.1.2, Step 1).  ES: the exponential of a semicircle,
+ * psi(z) = exp(beta (sqrt(1 - z^2) - 1)), beta = 2.30 W at sigma 2.  KB_MIRT and
+ * KB_FESSLER: the Kaiser-Bessel kernel of eq. (kb_compact) with half-width a = W / 2 and
+ * the shape of eq. (kaisal_bessel_coeffs) (gamma = pi sqrt((2 a 2.34 / pi)^2 - 0.8)) or
+ * of eq. (kb_type_2) (gamma = 2.34); its deconvolution factors come from the closed
+ * form of eq. (kb_fourier).  The kernel's constant factor 1 / I0(beta) cancels between
+ * spreading and deconvolution, so the KB kernels are used normalised to 1 at 0. */
+typedef enum { ENUFFT_KERNEL_ES = 0, ENUFFT_KERNEL_KB_MIRT = 1, ENUFFT_KERNEL_KB_FESSLER = 2 } enufft_kernel_kind;
+
 typedef struct { double cx, cy, radius; } enufft_window;
 
 /* Transform options.
@@ -92,7 +101,9 @@ typedef struct { double cx, cy, radius; } enufft_window;
  *             in the file ENUFFT_TUNE_CACHE ("off" disables; default
  *             $HOME/.cache/enufft/tune_cache.txt) keyed by device, shape and
  *             the exact cell layout and the trial point order.
- *   kernel_width 0: from eps; otherwise a width >= the eps-derived one. */
+ *   kernel_width 0: from eps; otherwise a width >= the eps-derived one (ES), or the
+ *             width itself (KB kernels: W = 2 a, even, 4..16).
+ *   kernel_kind enufft_kernel_kind. */
 typedef struct {
     int32_t n_modes[2];
     double sigma;
@@ -102,6 +113,7 @@ typedef struct {
     double scale;
     int32_t autotune;
     int32_t kernel_width;
+    int32_t kernel_kind;
 } enufft_opts;
 
 /* Elastic Mode Selection parameters (Section 2.2).
@@ -123,7 +135,7 @@ typedef struct {
     int32_t n_modes[2];      /* N1, N2 */
     int32_t grid[2];         /* fine grid n1, n2 */
     int32_t kernel_width;    /* spreading kernel width in fine-grid cells */
-    double beta;             /* ES shape: psi(z) = exp(beta (sqrt(1 - z^2) - 1)) */
+    double beta;             /* kernel shape: ES beta, or KB gamma */
     int64_t n_cells;
     int64_t n_points;
     int64_t n_items_fwd;     /* work items of the batched forward launch */
@@ -141,10 +153,12 @@ typedef struct {
     int32_t adj_band_mult;   /* adjoint row bands = this x the fewest that fit LDS */
     int32_t fwd_acc;         /* bytes per forward LDS grid cell: 8 (FP64 sums) or 4 (FP32 sums) */
     double tune_fwd_ms, tune_adj_ms;   /* best trial times of the autotuner */
+    int32_t kernel_kind;     /* enufft_kernel_kind of the plan */
+    int32_t reserved_;
 } enufft_plan_info;
 
 /* Fill *o with defaults: 64 x 64 modes, sigma 2, eps 1e-5, F32, Hann window,
- * scale 1, no autotuning. */
+ * scale 1, no autotuning, ES kernel. */
 enufft_status enufft_default_opts(enufft_opts *o);
 
 /* Create a plan for a fixed batch layout.

@@ -23,6 +23,7 @@ _STATUS = {0: "ENUFFT_OK", 1: "ENUFFT_EINVAL", 2: "ENUFFT_ENOMEM", 3: "ENUFFT_ED
            5: "ENUFFT_ESTATE", 6: "ENUFFT_EUNSUPPORTED"}
 F32, F64 = 0, 1
 WIN_NONE, WIN_HANN = 0, 1
+KERNELS = {"es": 0, "kb_mirt": 1, "kb_fessler": 2}
 
 
 class EnufftError(RuntimeError):
@@ -34,7 +35,7 @@ class EnufftError(RuntimeError):
 class Opts(ctypes.Structure):
     _fields_ = [("n_modes", ctypes.c_int32 * 2), ("sigma", ctypes.c_double), ("eps", ctypes.c_double),
                 ("precision", ctypes.c_int32), ("window_kind", ctypes.c_int32), ("scale", ctypes.c_double),
-                ("autotune", ctypes.c_int32), ("kernel_width", ctypes.c_int32)]
+                ("autotune", ctypes.c_int32), ("kernel_width", ctypes.c_int32), ("kernel_kind", ctypes.c_int32)]
 
 
 class Window(ctypes.Structure):
@@ -58,7 +59,8 @@ class PlanInfo(ctypes.Structure):
                 ("tuned", ctypes.c_int32), ("tune_cache_hit", ctypes.c_int32), ("fwd_chunk_min", ctypes.c_int64),
                 ("fwd_items_per_slot", ctypes.c_int32), ("adj_items_per_slot", ctypes.c_int32),
                 ("adj_band_mult", ctypes.c_int32), ("fwd_acc", ctypes.c_int32),
-                ("tune_fwd_ms", ctypes.c_double), ("tune_adj_ms", ctypes.c_double)]
+                ("tune_fwd_ms", ctypes.c_double), ("tune_adj_ms", ctypes.c_double),
+                ("kernel_kind", ctypes.c_int32), ("reserved_", ctypes.c_int32)]
 
 
 EXPORTS = ["enufft_default_opts", "enufft_plan", "enufft_set_stream", "enufft_type1_batched",
@@ -149,7 +151,7 @@ class Plan:
 
     def __init__(self, cell_offsets, windows=None, n_modes=(64, 64), sigma=2.0, eps=1e-5,
                  precision="f32", window="hann", scale=1.0, autotune=False, kernel_width=0,
-                 device=None, stream=None):
+                 kernel="es", device=None, stream=None):
         self._lib = load_library()
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
         off = np.ascontiguousarray(np.asarray(cell_offsets, dtype=np.int64))
@@ -172,6 +174,9 @@ class Plan:
             raise ValueError("autotune must be False, True, 'raster' or 'unordered'")
         opts.autotune = modes[autotune]
         opts.kernel_width = int(kernel_width)
+        if kernel not in KERNELS:
+            raise ValueError("kernel must be one of %s" % sorted(KERNELS))
+        opts.kernel_kind = KERNELS[kernel]
         wins = None
         if windows is not None:
             wa = np.ascontiguousarray(np.asarray(windows, dtype=np.float64).reshape(-1, 3))

@@ -369,9 +369,9 @@ __device__ __forceinline__ void gather_point(const AdjArgs<T> &a, const T *Guv, 
   } else {
     const T zsc = T(2) / T(W);
 #pragma unroll
-    for (int d = 0; d < W; ++d) kx[d] = es_eval(fx.offset(d) * zsc, a.beta);
+    for (int d = 0; d < W; ++d) kx[d] = ker_eval(fx.offset(d) * zsc, a.beta);
 #pragma unroll 1
-    for (int dy = 0; dy < W; ++dy) row(es_eval(fy.offset(dy) * zsc, a.beta));
+    for (int dy = 0; dy < W; ++dy) row(ker_eval(fy.offset(dy) * zsc, a.beta));
   }
   if constexpr (RECON) {
     const double t = (double)(hj * hann_w(a.window_kind, xj, yj, cx, cy, R, pr));

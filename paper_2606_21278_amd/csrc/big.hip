@@ -86,7 +86,7 @@ __device__ __forceinline__ void big_taps(const FineCoord<T> &c, T beta, const Es
   } else {
     const T zsc = T(2) / T(W);
 #pragma unroll
-    for (int d = 0; d < W; ++d) out[d] = es_eval(c.offset(d) * zsc, beta);
+    for (int d = 0; d < W; ++d) out[d] = ker_eval(c.offset(d) * zsc, beta);
   }
 }
 
@@ -1015,7 +1015,7 @@ __global__ __launch_bounds__(256) void big_gather_kernel(BigTileArgs<T> a) {
       } else {
         const T zsc = T(2) / T(W);
 #pragma unroll 1
-        for (int dy = 0; dy < W; ++dy) row(dy, es_eval(fy.offset(dy) * zsc, a.beta));
+        for (int dy = 0; dy < W; ++dy) row(dy, ker_eval(fy.offset(dy) * zsc, a.beta));
       }
       T dWx, dWy;
       const T Wv = hann_wg(a.window_kind, xj, yj, cx, cy, R, pr, dWx, dWy);

@@ -60,7 +60,7 @@ struct FwdArgs {
   const T *decon_x;          // [K1 + 1]: scale / p_x(|k|)
   const T *decon_y;          // [K2 + 1]: 1 / p_y(|k|)
   const T *tw1, *tw2;        // forward twiddles exp(-2 pi i j / n), interleaved, n entries
-  T beta;                    // ES shape parameter
+  T beta;                    // kernel shape: ES beta (> 0) or -gamma of the Kaiser-Bessel kernel
   T s1_hi, s1_lo, s2_hi, s2_lo;   // n1 / (2 pi) and n2 / (2 pi) as hi + lo
   int vec4;                  // x, y, h, w are 16-byte aligned: load runs of 4 points
   int acc;                   // bytes per LDS grid cell: 8 (FP64 sums) or 4 (FP32 sums)
@@ -107,6 +107,38 @@ __device__ __forceinline__ double es_eval(double z, double beta) {
   const double z2 = z * z;
   const double s = sqrt(fmax(1.0 - z2, 0.0));
   return exp(-beta * z2 / (1.0 + s));
+}
+
+// Modified Bessel function I0 by its power series sum_k ((x/2)^2)^k / (k!)^2, summed
+// until a term no longer changes the sum (at most 120 terms: enough for x <= 60).
+template <typename T>
+__device__ __forceinline__ T bessel_i0(T x) {
+  const T t = T(0.25) * x * x;
+  T term = T(1), sum = T(1);
+  for (int k = 1; k < 120; ++k) {
+    term *= t / T(k * k);
+    const T next = sum + term;
+    if (next == sum) break;
+    sum = next;
+  }
+  return sum;
+}
+
+// The Kaiser-Bessel kernel of eq. (kb_compact) on z = x / a in [-1, 1], normalised to
+// 1 at z = 0: I0(gamma sqrt(1 - z^2)) / I0(gamma).
+template <typename T>
+__device__ __forceinline__ T kb_eval(T z, T gamma) {
+  const T s = sqrt(fmax(T(1) - z * z, T(0)));
+  return bessel_i0<T>(gamma * s) / bessel_i0<T>(gamma);
+}
+
+// The plan's spreading kernel at z in [-1, 1]: shape > 0 is the exponential of a
+// semicircle with beta = shape, shape < 0 the Kaiser-Bessel kernel with gamma = -shape.
+__device__ __forceinline__ float ker_eval(float z, float shape) {
+  return shape > 0.0f ? es_eval(z, shape) : kb_eval<float>(z, -shape);
+}
+__device__ __forceinline__ double ker_eval(double z, double shape) {
+  return shape > 0.0 ? es_eval(z, shape) : kb_eval<double>(z, -shape);
 }
 
 // Fine-grid coordinate t = x n / (2 pi), kept as t_hi + t_lo with the scale
@@ -231,7 +263,7 @@ template <int W>
 __device__ __forceinline__ void es_taps_exact_v(float v, float beta, float (&out)[W]) {
   const float zsc = 2.0f / float(W);
 #pragma unroll
-  for (int d = 0; d < W; ++d) out[d] = es_eval((v + float(d - W / 2)) * zsc, beta);
+  for (int d = 0; d < W; ++d) out[d] = ker_eval((v + float(d - W / 2)) * zsc, beta);
 }
 
 // The W kernel values of one point along one axis: polynomial form when the
@@ -246,7 +278,7 @@ __device__ __forceinline__ void es_taps(const FineCoord<T> &c, T beta, const EsP
   }
   const T zsc = T(2) / T(W);
 #pragma unroll
-  for (int d = 0; d < W; ++d) out[d] = es_eval(c.offset(d) * zsc, beta);
+  for (int d = 0; d < W; ++d) out[d] = ker_eval(c.offset(d) * zsc, beta);
 }
 
 // ------------------------------------------------------------------ small DFTs

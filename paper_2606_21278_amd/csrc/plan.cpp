@@ -132,9 +132,65 @@ double es_host(double z, double beta) {
   return std::exp(-beta * z * z / (1.0 + std::sqrt(1.0 - z * z)));
 }
 
+// I0 by its power series (x <= 60 needs at most about 100 terms).
+double bessel_i0_host(double x) {
+  const double t = 0.25 * x * x;
+  double term = 1.0, sum = 1.0;
+  for (int k = 1; k < 200; ++k) {
+    term *= t / ((double)k * k);
+    const double next = sum + term;
+    if (next == sum) break;
+    sum = next;
+  }
+  return sum;
+}
+
+// Kaiser-Bessel shape gamma of eq. (kaisal_bessel_coeffs) (MIRT form, beta = 2.34) or
+// eq. (kb_type_2) (gamma = 2.34), for half-width a = W / 2 grid cells.
+double kb_gamma(int kind, int W) {
+  const double a = 0.5 * W, b = 2.34;
+  if (kind == ENUFFT_KERNEL_KB_FESSLER) return b;
+  const double r = 2.0 * a * b / M_PI;
+  return M_PI * std::sqrt(r * r - 0.8);
+}
+
+// The plan's kernel at z in [-1, 1] (shape > 0: ES beta; shape < 0: KB with gamma = -shape,
+// normalised to 1 at 0).
+double kernel_host(double z, double shape) {
+  if (std::fabs(z) > 1.0) return 0.0;
+  if (shape > 0.0) return es_host(z, shape);
+  const double g = -shape;
+  return bessel_i0_host(g * std::sqrt(std::max(0.0, 1.0 - z * z))) / bessel_i0_host(g);
+}
+
+// Deconvolution factor of the normalised Kaiser-Bessel kernel, the closed form of
+// eq. (kb_fourier) divided by I0(gamma) / I0(beta): at kappa = 2 pi k / n radians per
+// grid cell, p(k) = (2 a / I0(gamma)) sinh(r) / r with r = sqrt(gamma^2 - (a kappa)^2),
+// continued as sin(r') / r' with r' = sqrt((a kappa)^2 - gamma^2) beyond gamma.
+std::vector<double> kb_ft(int W, double gamma, int n, int kmax) {
+  std::vector<double> p(kmax + 1);
+  const double a = 0.5 * W, i0 = bessel_i0_host(gamma);
+  for (int k = 0; k <= kmax; ++k) {
+    const double ak = a * 2.0 * M_PI * k / n;
+    const double d = gamma * gamma - ak * ak;
+    double f;
+    if (d > 0.0) {
+      const double r = std::sqrt(d);
+      f = std::sinh(r) / r;
+    } else if (d < 0.0) {
+      const double r = std::sqrt(-d);
+      f = std::sin(r) / r;
+    } else {
+      f = 1.0;
+    }
+    p[k] = 2.0 * a * f / i0;
+  }
+  return p;
+}
+
 // Per-tap polynomials of the kernel in u = 2 v - 1, v = i0 - t + W/2 in [0, 1):
 // Chebyshev interpolation at deg + 1 nodes, converted to monomial coefficients
-// (ascending).  Returns the largest deviation from psi on a fine sample.
+// (ascending).  Returns the largest deviation from the kernel on a fine sample.
 double fit_es_poly(int W, double beta, int deg, std::vector<double> &coef) {
   coef.assign((size_t)W * (deg + 1), 0.0);
   double maxerr = 0.0;
@@ -143,7 +199,7 @@ double fit_es_poly(int W, double beta, int deg, std::vector<double> &coef) {
     std::vector<double> cheb(n, 0.0), yn(n), un(n);
     for (int i = 0; i < n; ++i) {
       un[i] = std::cos(M_PI * (i + 0.5) / n);
-      yn[i] = es_host(((0.5 * (un[i] + 1.0)) + d - 0.5 * W) * 2.0 / W, beta);
+      yn[i] = kernel_host(((0.5 * (un[i] + 1.0)) + d - 0.5 * W) * 2.0 / W, beta);
     }
     for (int j = 0; j < n; ++j) {
       double s = 0.0;
@@ -166,7 +222,7 @@ double fit_es_poly(int W, double beta, int deg, std::vector<double> &coef) {
       const double v = i / 2000.0, u = 2.0 * v - 1.0;
       double acc = coef[(size_t)d * n + deg];
       for (int k = deg - 1; k >= 0; --k) acc = acc * u + coef[(size_t)d * n + k];
-      maxerr = std::max(maxerr, std::fabs(acc - es_host((v + d - 0.5 * W) * 2.0 / W, beta)));
+      maxerr = std::max(maxerr, std::fabs(acc - kernel_host((v + d - 0.5 * W) * 2.0 / W, beta)));
     }
   }
   return maxerr;
@@ -346,6 +402,7 @@ enufft_status enufft_default_opts(enufft_opts *o) {
   o->scale = 1.0;
   o->autotune = 0;
   o->kernel_width = 0;
+  o->kernel_kind = ENUFFT_KERNEL_ES;
   return ENUFFT_OK;
 }
 
@@ -380,6 +437,9 @@ enufft_status enufft_plan(enufft_plan_t *out, int64_t n_cells, const int64_t *ce
   if (!std::isfinite(opts->scale)) return fail(nullptr, ENUFFT_EINVAL, "enufft_plan: scale must be finite");
   if (opts->kernel_width < 0 || opts->kernel_width > 16)
     return fail(nullptr, ENUFFT_EINVAL, "enufft_plan: kernel_width must be in [0, 16]");
+  if (opts->kernel_kind != ENUFFT_KERNEL_ES && opts->kernel_kind != ENUFFT_KERNEL_KB_MIRT &&
+      opts->kernel_kind != ENUFFT_KERNEL_KB_FESSLER)
+    return fail(nullptr, ENUFFT_EINVAL, "enufft_plan: unknown kernel kind");
   if (opts->window_kind == ENUFFT_WIN_HANN_RADIAL && n_cells > 0) {
     if (!windows) return fail(nullptr, ENUFFT_EINVAL, "enufft_plan: Hann window needs windows");
     for (int64_t c = 0; c < n_cells; ++c)
@@ -396,6 +456,15 @@ enufft_status enufft_plan(enufft_plan_t *out, int64_t n_cells, const int64_t *ce
   int W;
   double beta;
   kernel_params(opts->eps, sigma_eff, opts->kernel_width, &W, &beta);
+  // Kaiser-Bessel: the given width (or the eps-derived one) and its shape gamma, stored
+  // negated so the kernels can tell the two kernels apart by the sign
+  const bool kb = opts->kernel_kind != ENUFFT_KERNEL_ES;
+  if (kb && opts->kernel_width > 0) {
+    W = 16;
+    for (int c : kWidths)
+      if (c >= opts->kernel_width) { W = c; break; }
+  }
+  if (kb) beta = -kb_gamma(opts->kernel_kind, W);
   n1 = std::max(n1, next_pow2(2 * W));
   n2 = std::max(n2, next_pow2(2 * W));
   // Mode boxes above 64 per axis (or grids above 128) take the large-cell path:
@@ -466,7 +535,8 @@ enufft_status enufft_plan(enufft_plan_t *out, int64_t n_cells, const int64_t *ce
 
   // ---- tables (FP64 on the host, rounded to the compute precision)
   const int Kx = g.K1, Ky = g.K2;
-  std::vector<double> px = kernel_ft(W, beta, n1, Kx), py = kernel_ft(W, beta, n2, Ky);
+  std::vector<double> px = kb ? kb_ft(W, -beta, n1, Kx) : kernel_ft(W, beta, n1, Kx);
+  std::vector<double> py = kb ? kb_ft(W, -beta, n2, Ky) : kernel_ft(W, beta, n2, Ky);
   std::vector<double> dx(Kx + 1), dy(Ky + 1), dx1(Kx + 1);
   for (int k = 0; k <= Kx; ++k) dx[k] = opts->scale / px[k];
   for (int k = 0; k <= Kx; ++k) dx1[k] = 1.0 / px[k];
@@ -548,7 +618,8 @@ enufft_status enufft_get_info(enufft_plan_t p, enufft_plan_info *info) {
   info->n_modes[0] = p->N1; info->n_modes[1] = p->N2;
   info->grid[0] = p->n1; info->grid[1] = p->n2;
   info->kernel_width = p->W;
-  info->beta = p->beta;
+  info->beta = std::fabs(p->beta);
+  info->kernel_kind = p->opts.kernel_kind;
   info->n_cells = p->n_cells;
   info->n_points = p->n_points;
   info->n_items_fwd = (int64_t)p->fwd_items.size();

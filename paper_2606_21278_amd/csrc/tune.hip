@@ -84,8 +84,9 @@ uint64_t fnv1a(const void *data, size_t n, uint64_t h = 1469598103934665603ULL) 
 std::string cache_key(enufft_plan_t p, const char *arch) {
   uint64_t hsh = fnv1a(p->offsets.data(), p->offsets.size() * sizeof(int64_t));
   char buf[320];
-  std::snprintf(buf, sizeof(buf), "v2_%s_cu%d_p%d_m%dx%d_g%dx%d_w%d_win%d_o%d_c%lld_q%lld_h%016llx", arch, p->n_cu,
-                p->prec, p->N1, p->N2, p->n1, p->n2, p->W, p->window_kind, p->opts.autotune == 2 ? 1 : 0,
+  std::snprintf(buf, sizeof(buf), "v2_%s_cu%d_p%d_m%dx%d_g%dx%d_w%d_k%d_win%d_o%d_c%lld_q%lld_h%016llx", arch,
+                p->n_cu, p->prec, p->N1, p->N2, p->n1, p->n2, p->W, p->opts.kernel_kind, p->window_kind,
+                p->opts.autotune == 2 ? 1 : 0,
                 (long long)p->n_cells, (long long)p->n_points, (unsigned long long)hsh);
   std::string k(buf);
   for (char &ch : k)

@@ -499,3 +499,22 @@ def uniform_box(device="cpu", counts=(1000,), n_modes=(16, 16), seed: int = 11, 
     areas = np.full(len(counts), (hi - lo) ** 2)
     return _finish("uniform box", x, y, h, off, areas, win, n_modes, 2.0,
                    1e-10 if precision == "f64" else 1e-5, precision)
+
+
+def square_terrain(device="cpu", Q: int = 2000, n_modes=(41, 41), seed: int = 0, precision: str = "f64") -> Batch:
+    """One square cell (the whole 2 pi box), Q uniform points, 200-sinusoid power-law
+    terrain (|k| area-uniform in [1, 20], amplitude |k|^-1.5, std 500 m), weights
+    box-area/Q, no window: the setting of the kernel comparison of Section 2.1.2 (a
+    rectangular domain of 2,000 samples, modes |m|, |n| <= 20), with seeded power-law
+    terrains standing in for its three unspecified synthetic terrains."""
+    rng = np.random.Generator(np.random.PCG64(1000 * 9 + seed))
+    kx, ky, am, ph = _draw_terrain(rng, 200, 20.0, 1.5)
+    terr = Terrain(kx[None], ky[None], am[None], ph[None], np.array([500.0]), 0.0)
+    gen = torch.Generator(device=device).manual_seed(1000 * 9 + 7 + seed)
+    x = -math.pi + TWO_PI * torch.rand(Q, dtype=torch.float64, device=device, generator=gen)
+    y = -math.pi + TWO_PI * torch.rand(Q, dtype=torch.float64, device=device, generator=gen)
+    off = np.array([0, Q], dtype=np.int64)
+    h = _eval_terrain(x, y, _cell_index(off, device), terr, off, gen)
+    win = np.array([[0.0, 0.0, 0.0]])
+    return _finish("square terrain seed %d" % seed, x, y, h, off, np.array([TWO_PI * TWO_PI]), win, n_modes,
+                   2.0, 1e-10 if precision == "f64" else 1e-5, precision)
