@@ -79,6 +79,10 @@ def _load():
                                       ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                       ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_int, _dp, _u8p, _i32p,
                                       _dp]
+        L.oracle_cell_geometry.argtypes = [ctypes.c_int64, _i64p, _dp, _dp, _dp, _dp, ctypes.c_int, ctypes.c_int,
+                                           ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                                           _dp, _dp, _dp, _dp, _u8p, _dp, _i32p]
+        L.oracle_cell_geometry.restype = ctypes.c_int
         L.oracle_reconstruct.argtypes = [ctypes.c_int64, _i64p, _dp, _dp, _dp, _dp, _dp, ctypes.c_int, ctypes.c_int,
                                          ctypes.c_int, _dp, _u8p, _dp, _dp, _dp]
         _lib = L
@@ -288,6 +292,37 @@ def reconstruct(offsets, x, y, h, w, windows, n_modes, coef, keep=None, area=Non
                          cr.ctypes.data_as(_dp), _nullable(kp, _u8p), par, hr.ctypes.data_as(_dp),
                          dg.ctypes.data_as(_dp))
     return hr, dg
+
+
+FRAMES = {"centroid": 0, "edge": 1}
+MASKS = {"square": 0, "triangle": 1, "circle": 2}
+WEIGHTS = {"uniform": 0, "voronoi": 1}
+
+
+def cell_geometry(offsets, tri, x, y, h, frame="edge", mask="triangle", weights="uniform", raster=64, eta=1.0,
+                  floor_frac=0.5, deplane=True):
+    """Local frames, masks, quadrature weights and deplaning of Appendices A1, A2, A6 ->
+    dict(xb, yb, hb, wb (w_q / |D|, 0 outside), inside, counts (raster points per
+    sample), info [n_cells, 8] = (xbar_x, xbar_y, cos, sin, H, |D|, Q_in, hbar))."""
+    L = _load()
+    off = np.ascontiguousarray(offsets, dtype=np.int64)
+    n_cells = len(off) - 1
+    tr, ptr = _d(np.asarray(tri, dtype=np.float64).reshape(n_cells, 6))
+    x, px = _d(x); y, py = _d(y); h, ph = _d(h)
+    n = len(x)
+    out = {k: np.zeros(n) for k in ("xb", "yb", "hb", "wb")}
+    inside = np.zeros(n, dtype=np.uint8)
+    counts = np.zeros(n, dtype=np.int32)
+    info = np.zeros((n_cells, 8))
+    r = L.oracle_cell_geometry(n_cells, off.ctypes.data_as(_i64p), ptr, px, py, ph, FRAMES[frame], MASKS[mask],
+                               WEIGHTS[weights], int(raster), float(eta), float(floor_frac), int(deplane),
+                               out["xb"].ctypes.data_as(_dp), out["yb"].ctypes.data_as(_dp),
+                               out["hb"].ctypes.data_as(_dp), out["wb"].ctypes.data_as(_dp),
+                               inside.ctypes.data_as(_u8p), info.ctypes.data_as(_dp), counts.ctypes.data_as(_i32p))
+    if r != 0:
+        raise ValueError("oracle_cell_geometry: bad arguments")
+    out.update(inside=inside, counts=counts, info=info)
+    return out
 
 
 def batch_inputs(batch, cells=None):

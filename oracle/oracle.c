@@ -628,3 +628,182 @@ void oracle_reconstruct(int64_t n_cells, const int64_t *off,
         free(rec);
     }
 }
+
+/* ---------------------------------------------------------- cell geometry */
+
+/* Local frame, support mask, quadrature weights and deplaning of Appendices A1, A2 and
+ * A6 for triangular cells, in the paper's order.
+ *
+ * tri[6 c .. 6 c + 5] = (v1x, v1y, v2x, v2y, v3x, v3y), in the plane of the samples.
+ *   centroid        xbar = (v1 + v2 + v3) / 3
+ *   orientation     frame 0: R = I (centroid-aligned); frame 1: the rotation of
+ *                   eq. (rotation_matrix) that takes the longest of the edges
+ *                   e1 = v2 - v1, e2 = v3 - v2, e3 = v1 - v3 onto the +x axis
+ *                   (the first of equal longest edges)
+ *   local coords    u = R (x - xbar)
+ *   half-width      H = (eta / 2) max(extent of the rotated vertices along x, along y)
+ *   box coordinates (u_x, u_y) pi / H: the square [-H, H]^2 of period 2H mapped onto the
+ *                   2 pi box, so the integer wave numbers are k_m = 2 pi m / (2H)
+ *   mask            0 square (|u_x|, |u_y| <= H), 1 triangle (u inside the rotated
+ *                   triangle, edges included, and inside the square: the square is
+ *                   centred on the centroid, so it can cut the triangle), 2 circle
+ *                   (|u| <= H); |D| the area of the mask within the square
+ *   weights         0 uniform: w_q = |D| / Q_in (eq. uniform_weights) for the Q_in
+ *                   samples inside the mask;
+ *                   1 Voronoi by raster sampling (eqs. raster_grid .. voronoi_weights):
+ *                   raster N_g x N_g cell centres over the square, those inside the
+ *                   mask each assigned to the nearest inside sample (the lowest index
+ *                   among equally near ones), A_q = n_q |D| / |G|; a sample with no
+ *                   raster point gets floor_frac |D| / |G| and all areas are then
+ *                   scaled so that they sum to |D|
+ *   deplaning       h' = h - hbar, hbar = (1 / |D|) sum_{inside} w_q h_q (eq.
+ *                   alps_deplaning), when deplane is set; else h' = h
+ * Outputs per sample: xb, yb (box coordinates), hb (h'), wb = w_q / |D| (0 outside
+ * the mask: the factor eq. (discrete_quadrature) puts on h_q), inside (0 / 1) and, when
+ * counts is not NULL, n_q.  Per cell, info[8 c ..] = (xbar_x, xbar_y, cos, sin, H, |D|,
+ * Q_in, hbar).  Returns 0, or -1 on bad arguments. */
+static int point_in_triangle(double px, double py, const double *t)
+{
+    /* signs of the three edge cross products; inside (or on an edge) when none of
+     * them has the opposite sign of another */
+    double d1 = (px - t[2]) * (t[1] - t[3]) - (t[0] - t[2]) * (py - t[3]);
+    double d2 = (px - t[4]) * (t[3] - t[5]) - (t[2] - t[4]) * (py - t[5]);
+    double d3 = (px - t[0]) * (t[5] - t[1]) - (t[4] - t[0]) * (py - t[1]);
+    int neg = (d1 < 0) || (d2 < 0) || (d3 < 0);
+    int pos = (d1 > 0) || (d2 > 0) || (d3 > 0);
+    return !(neg && pos);
+}
+
+static int in_mask(int mask, double ux, double uy, double H, const double *ut)
+{
+    if (mask == 0) return fabs(ux) <= H && fabs(uy) <= H;
+    if (mask == 2) return ux * ux + uy * uy <= H * H;
+    return fabs(ux) <= H && fabs(uy) <= H && point_in_triangle(ux, uy, ut);
+}
+
+/* Area of the triangle ut clipped to the square [-H, H]^2: the polygon cut by the four
+ * half-planes one after the other, then the shoelace formula. */
+static double clipped_triangle_area(const double *ut, double H)
+{
+    double P[16][2], Qp[16][2];
+    int n = 3;
+    for (int i = 0; i < 3; ++i) { P[i][0] = ut[2 * i]; P[i][1] = ut[2 * i + 1]; }
+    for (int side = 0; side < 4; ++side) {
+        /* keep s * coordinate <= H, coordinate axis = side / 2, s = +-1 */
+        const int ax = side >> 1;
+        const double sg = (side & 1) ? -1.0 : 1.0;
+        int m = 0;
+        for (int i = 0; i < n; ++i) {
+            const double *A = P[i], *B = P[(i + 1) % n];
+            const double da = sg * A[ax] - H, db = sg * B[ax] - H;
+            if (da <= 0) { Qp[m][0] = A[0]; Qp[m][1] = A[1]; ++m; }
+            if ((da < 0 && db > 0) || (da > 0 && db < 0)) {
+                const double t = da / (da - db);
+                Qp[m][0] = A[0] + t * (B[0] - A[0]);
+                Qp[m][1] = A[1] + t * (B[1] - A[1]);
+                ++m;
+            }
+        }
+        n = m;
+        for (int i = 0; i < n; ++i) { P[i][0] = Qp[i][0]; P[i][1] = Qp[i][1]; }
+    }
+    double s2 = 0.0;
+    for (int i = 0; i < n; ++i) s2 += P[i][0] * P[(i + 1) % n][1] - P[(i + 1) % n][0] * P[i][1];
+    return 0.5 * fabs(s2);
+}
+
+int oracle_cell_geometry(int64_t n_cells, const int64_t *off, const double *tri,
+                         const double *x, const double *y, const double *h,
+                         int frame, int mask, int weights, int raster, double eta, double floor_frac, int deplane,
+                         double *xb, double *yb, double *hb, double *wb, uint8_t *inside, double *info,
+                         int32_t *counts)
+{
+    if (frame < 0 || frame > 1 || mask < 0 || mask > 2 || weights < 0 || weights > 1) return -1;
+    if (!(eta >= 1.0) || (weights == 1 && raster < 1) || !(floor_frac >= 0.0)) return -1;
+    for (int64_t c = 0; c < n_cells; ++c) {
+        const double *v = tri + 6 * c;
+        const double cx = (v[0] + v[2] + v[4]) / 3.0, cy = (v[1] + v[3] + v[5]) / 3.0;
+        double cs = 1.0, sn = 0.0;
+        if (frame == 1) {
+            const double e[3][2] = {{v[2] - v[0], v[3] - v[1]}, {v[4] - v[2], v[5] - v[3]}, {v[0] - v[4], v[1] - v[5]}};
+            int m = 0;
+            double best = -1.0;
+            for (int i = 0; i < 3; ++i) {
+                const double L = sqrt(e[i][0] * e[i][0] + e[i][1] * e[i][1]);
+                if (L > best) { best = L; m = i; }
+            }
+            cs = e[m][0] / best;
+            sn = e[m][1] / best;
+        }
+        /* rotated vertices and the half-width */
+        double ut[6];
+        for (int i = 0; i < 3; ++i) {
+            const double dx = v[2 * i] - cx, dy = v[2 * i + 1] - cy;
+            ut[2 * i] = cs * dx + sn * dy;
+            ut[2 * i + 1] = -sn * dx + cs * dy;
+        }
+        const double ex = fmax(fmax(ut[0], ut[2]), ut[4]) - fmin(fmin(ut[0], ut[2]), ut[4]);
+        const double ey = fmax(fmax(ut[1], ut[3]), ut[5]) - fmin(fmin(ut[1], ut[3]), ut[5]);
+        const double H = 0.5 * eta * fmax(ex, ey);
+        double area;
+        if (mask == 0) area = 4.0 * H * H;
+        else if (mask == 2) area = M_PI * H * H;
+        else area = clipped_triangle_area(ut, H);
+        const int64_t a = off[c], b = off[c + 1];
+        int64_t qin = 0;
+        for (int64_t j = a; j < b; ++j) {
+            const double dx = x[j] - cx, dy = y[j] - cy;
+            const double ux = cs * dx + sn * dy, uy = -sn * dx + cs * dy;
+            xb[j] = ux * M_PI / H;
+            yb[j] = uy * M_PI / H;
+            inside[j] = (uint8_t)in_mask(mask, ux, uy, H, ut);
+            qin += inside[j];
+            wb[j] = 0.0;
+            if (counts) counts[j] = 0;
+        }
+        if (weights == 0) {
+            for (int64_t j = a; j < b; ++j) wb[j] = inside[j] ? 1.0 / (double)qin : 0.0;
+        } else if (qin > 0) {
+            /* raster cell centres over the square [-H, H]^2, nearest inside sample */
+            int64_t *n = (int64_t *)calloc((size_t)(b - a), sizeof(int64_t));
+            int64_t ng = 0;
+            const double step = 2.0 * H / raster;
+            for (int ib = 0; ib < raster; ++ib) {
+                const double gy = -H + step * (ib + 0.5);
+                for (int ia = 0; ia < raster; ++ia) {
+                    const double gx = -H + step * (ia + 0.5);
+                    if (!in_mask(mask, gx, gy, H, ut)) continue;
+                    ++ng;
+                    int64_t arg = -1;
+                    double bd = 0.0;
+                    for (int64_t j = a; j < b; ++j) {
+                        if (!inside[j]) continue;
+                        const double dx = x[j] - cx, dy = y[j] - cy;
+                        const double ux = cs * dx + sn * dy, uy = -sn * dx + cs * dy;
+                        const double d = (ux - gx) * (ux - gx) + (uy - gy) * (uy - gy);
+                        if (arg < 0 || d < bd) { bd = d; arg = j; }
+                    }
+                    n[arg - a] += 1;
+                }
+            }
+            double tot = 0.0;
+            for (int64_t j = a; j < b; ++j) {
+                if (!inside[j]) continue;
+                const double A = ng > 0 ? area * (n[j - a] > 0 ? (double)n[j - a] : floor_frac) / (double)ng : 0.0;
+                wb[j] = A;
+                tot += A;
+                if (counts) counts[j] = (int32_t)n[j - a];
+            }
+            for (int64_t j = a; j < b; ++j) wb[j] = tot > 0.0 ? wb[j] / tot : 0.0;
+            free(n);
+        }
+        /* wb now holds w_q / |D|; deplaning by the weighted mean over the mask */
+        double hbar = 0.0;
+        for (int64_t j = a; j < b; ++j) hbar += wb[j] * h[j];
+        for (int64_t j = a; j < b; ++j) hb[j] = deplane ? h[j] - hbar : h[j];
+        double *ci = info + 8 * c;
+        ci[0] = cx; ci[1] = cy; ci[2] = cs; ci[3] = sn; ci[4] = H; ci[5] = area; ci[6] = (double)qin;
+        ci[7] = deplane ? hbar : 0.0;
+    }
+    return 0;
+}

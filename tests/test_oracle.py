@@ -706,3 +706,155 @@ def test_ems_flow_mountain_wave_modes():
     assert np.array_equal(keep[0], keep[1]) and kstar[0, 0] == kstar[1, 0] >= 1
     w = [_action_weight(mu, 1, ks, u0, 0, 0.02, 1e-4, 1.0) for mu in range(4)]
     assert w[0] == 0.0 and all(v > 0 for v in w[1:])
+
+
+# ----------------------------------------------------------------------------- cell geometry
+
+def test_geometry_edge_frame_hand_worked():
+    """Triangle (0,0), (4,0), (1,3): edges (4,0), (-3,3), (-1,-3); the longest is (-3,3)
+    (length 3 sqrt 2), at 135 degrees, so cos = -1/sqrt 2, sin = 1/sqrt 2 and that edge
+    maps onto +x with length 3 sqrt 2.  Centroid (5/3, 1).  Rotated vertices span
+    3 sqrt 2 along x; the height of the triangle over that edge is area * 2 / base =
+    12 / (3 sqrt 2) = 2 sqrt 2 along y, so H = (eta / 2) 3 sqrt 2.  The vertex (4, 0) lies
+    7 / (3 sqrt 2) from the centroid along the local x axis, outside the square at eta = 1
+    (H = 3 / sqrt 2), inside at eta = 1.5."""
+    tri = np.array([0.0, 0.0, 4.0, 0.0, 1.0, 3.0])
+    x = np.array([5 / 3, 0.0, 4.0, 1.0, 10.0])
+    y = np.array([1.0, 0.0, 0.0, 3.0, 10.0])
+    h = np.array([1.0, 2.0, 3.0, 4.0, 5.0])
+    for eta in (1.0, 1.5):
+        g = oracle.cell_geometry([0, 5], tri, x, y, h, frame="edge", mask="triangle", eta=eta, deplane=False)
+        cx, cy, cs, sn, H, A, qin, hbar = g["info"][0]
+        s2 = math.sqrt(2)
+        assert np.allclose([cx, cy, cs, sn], [5 / 3, 1.0, -1 / s2, 1 / s2], atol=1e-15)
+        assert np.isclose(H, eta / 2 * 3 * s2, rtol=1e-15)
+        if eta == 1.0:
+            assert list(g["inside"]) == [1, 1, 0, 1, 0] and A < 6.0
+            continue
+        assert np.isclose(A, 6.0, rtol=1e-15)                 # the triangle's area
+        assert list(g["inside"]) == [1, 1, 1, 1, 0]            # vertices count as inside
+        # the longest edge (from (4,0) to (1,3)) is parallel to x in the local frame
+        assert np.isclose(g["yb"][2], g["yb"][3], atol=1e-14) and g["xb"][3] > g["xb"][2]
+        assert np.isclose(g["xb"][3] - g["xb"][2], 3 * s2 * math.pi / H, rtol=1e-14)
+        assert np.allclose(g["wb"], [0.25, 0.25, 0.25, 0.25, 0.0])
+        assert np.array_equal(g["hb"], h)
+    gc = oracle.cell_geometry([0, 5], tri, x, y, h, frame="centroid", mask="square", eta=1.0)
+    cx, cy, cs, sn, H, A, qin, hbar = gc["info"][0]
+    assert (cs, sn) == (1.0, 0.0) and np.isclose(H, 2.0) and np.isclose(A, 16.0)   # extents 4 and 3
+    # the square is centred on the centroid (5/3, 1): the vertex (4, 0) is 7/3 > H away
+    assert list(gc["inside"]) == [1, 1, 0, 1, 0]
+
+
+def test_geometry_triangle_clipped_by_its_square():
+    """An equilateral triangle of side s in the edge-aligned frame at eta = 1: H = s / 2
+    and the centroid-centred square cuts off the apex above y = s / 2 (the apex sits at
+    s / sqrt 3).  |D| = sqrt 3 s^2 / 4 minus the cut-off triangle, whose height is
+    s / sqrt 3 - s / 2 and whose base is that height times 2 / sqrt 3."""
+    s_ = 2.0
+    tri = np.array([0.0, 0.0, s_, 0.0, s_ / 2, s_ * math.sqrt(3) / 2])
+    g = oracle.cell_geometry([0, 0], tri, np.zeros(0), np.zeros(0), np.zeros(0), frame="edge", mask="triangle",
+                             eta=1.0)
+    H, A = g["info"][0, 4], g["info"][0, 5]
+    hc = s_ / math.sqrt(3) - s_ / 2
+    assert np.isclose(H, s_ / 2, rtol=1e-15)
+    assert np.isclose(A, math.sqrt(3) / 4 * s_ * s_ - 0.5 * hc * (2 * hc / math.sqrt(3)), rtol=1e-13)
+    # a looser square (eta = 1.3) holds the whole triangle
+    g = oracle.cell_geometry([0, 0], tri, np.zeros(0), np.zeros(0), np.zeros(0), frame="edge", mask="triangle",
+                             eta=1.3)
+    assert np.isclose(g["info"][0, 5], math.sqrt(3) / 4 * s_ * s_, rtol=1e-13)
+
+
+def test_geometry_masks_and_deplaning():
+    """Circle and square masks on a random cloud, uniform weights 1/Q_in, and the deplaned
+    heights have zero weighted mean over the mask (eq. alps_deplaning)."""
+    rng = np.random.default_rng(101)
+    tri = np.array([-1.0, -0.5, 2.0, -0.2, 0.3, 1.9])
+    x = rng.uniform(-2, 3, 600)
+    y = rng.uniform(-2, 3, 600)
+    h = rng.normal(size=600) + 3.0
+    for mask in ("square", "circle", "triangle"):
+        g = oracle.cell_geometry([0, 600], tri, x, y, h, frame="edge", mask=mask, eta=1.2)
+        cx, cy, cs, sn, H, A, qin, hbar = g["info"][0]
+        u = np.stack([cs * (x - cx) + sn * (y - cy), -sn * (x - cx) + cs * (y - cy)])
+        if mask == "square":
+            ref = (np.abs(u[0]) <= H) & (np.abs(u[1]) <= H)
+            assert np.isclose(A, 4 * H * H)
+        elif mask == "circle":
+            ref = u[0] ** 2 + u[1] ** 2 <= H * H
+            assert np.isclose(A, math.pi * H * H)
+        else:
+            ref = g["inside"].astype(bool)
+            # at eta = 1.2 this triangle fits its square: |D| is the triangle's area
+            assert np.isclose(A, 0.5 * abs((tri[2] - tri[0]) * (tri[5] - tri[1]) - (tri[4] - tri[0]) * (tri[3] - tri[1])))
+            assert np.all(np.abs(u[:, ref]) <= H)
+        assert np.array_equal(g["inside"].astype(bool), ref)
+        assert qin == ref.sum() > 0
+        assert np.allclose(g["wb"][ref], 1.0 / qin) and np.all(g["wb"][~ref] == 0)
+        assert np.isclose(hbar, np.mean(h[ref]), rtol=1e-13)
+        assert abs(np.sum(g["wb"] * g["hb"])) < 1e-12
+        assert np.allclose(g["xb"], u[0] * math.pi / H) and np.allclose(g["yb"], u[1] * math.pi / H)
+
+
+def test_geometry_voronoi_closed_forms():
+    """Raster Voronoi weights where the answer is exact: two samples split the square
+    along their perpendicular bisector (here a raster line), so the weights are the two
+    area fractions; a regular lattice with the raster aligned to it gets equal weights;
+    weights sum to 1; an isolated empty sample gets the floor and the rest renormalise."""
+    # square mask, centroid frame, H = 2: samples at x = -1 and x = +0.5 -> bisector at -0.25
+    tri = np.array([-2.0, -2.0, 2.0, -2.0, 0.0, 2.0])       # extents 4 x 4, centroid (0, -2/3)
+    cy = -2 / 3
+    x = np.array([-1.0, 0.5])
+    y = np.array([cy, cy])
+    g = oracle.cell_geometry([0, 2], tri, x, y, np.zeros(2), frame="centroid", mask="square",
+                             weights="voronoi", raster=16, eta=1.0)
+    assert np.isclose(g["info"][0, 4], 2.0)
+    assert np.allclose(g["wb"], [(2 - 0.25) / 4, (2 + 0.25) / 4], atol=1e-15)
+    assert g["counts"].sum() == 256
+    # 8 x 8 lattice of samples at raster-aligned cell centres: equal weights
+    gx = -2 + 0.5 * (np.arange(8) + 0.5)
+    X, Y = np.meshgrid(gx, gx + cy)
+    g = oracle.cell_geometry([0, 64], tri, X.ravel(), Y.ravel(), np.zeros(64), frame="centroid", mask="square",
+                             weights="voronoi", raster=32, eta=1.0)
+    assert np.allclose(g["wb"], 1 / 64, atol=1e-15) and np.all(g["counts"] == 16)
+    # a sample with no raster point of its own (an exact duplicate: ties go to the lower
+    # index) gets the floor weight
+    x3 = np.array([-1.0, 0.5, 0.5])
+    y3 = np.array([cy, cy, cy])
+    g = oracle.cell_geometry([0, 3], tri, x3, y3, np.zeros(3), frame="centroid", mask="square",
+                             weights="voronoi", raster=16, eta=1.0, floor_frac=0.5)
+    assert g["counts"][2] == 0 and g["counts"][1] > 0
+    assert np.isclose(g["wb"].sum(), 1.0, rtol=1e-15)
+    assert np.isclose(g["wb"][2] / g["wb"][0], 0.5 / g["counts"][0], rtol=1e-13)
+
+
+def test_geometry_voronoi_brute_force():
+    """Raster Voronoi counts on a random cloud and the triangle mask against a numpy
+    nearest-sample assignment of the raster cell centres inside the rotated triangle."""
+    rng = np.random.default_rng(102)
+    tri = np.array([0.3, 0.1, 3.1, 0.8, 1.0, 2.7])
+    x = rng.uniform(0, 3.2, 120)
+    y = rng.uniform(0, 2.8, 120)
+    g = oracle.cell_geometry([0, 120], tri, x, y, np.ones(120), frame="edge", mask="triangle", weights="voronoi",
+                             raster=48, eta=1.1)
+    cx, cy, cs, sn, H, A, qin, hbar = g["info"][0]
+    ins = g["inside"].astype(bool)
+    ux = cs * (x - cx) + sn * (y - cy)
+    uy = -sn * (x - cx) + cs * (y - cy)
+    vt = np.array([[cs * (tri[2 * i] - cx) + sn * (tri[2 * i + 1] - cy),
+                    -sn * (tri[2 * i] - cx) + cs * (tri[2 * i + 1] - cy)] for i in range(3)])
+    step = 2 * H / 48
+    c = -H + step * (np.arange(48) + 0.5)
+    GX, GY = np.meshgrid(c, c)
+    P = np.stack([GX.ravel(), GY.ravel()], 1)
+
+    def side(p, a, b):
+        return (p[:, 0] - b[0]) * (a[1] - b[1]) - (a[0] - b[0]) * (p[:, 1] - b[1])
+    d = np.stack([side(P, vt[0], vt[1]), side(P, vt[1], vt[2]), side(P, vt[2], vt[0])], 1)
+    inside_g = ~((d < 0).any(1) & (d > 0).any(1))
+    P = P[inside_g]
+    idx = np.nonzero(ins)[0]
+    D2 = (P[:, None, 0] - ux[idx][None]) ** 2 + (P[:, None, 1] - uy[idx][None]) ** 2
+    near = idx[np.argmin(D2, axis=1)]
+    counts = np.bincount(near, minlength=120)
+    assert np.array_equal(g["counts"], counts)
+    assert np.isclose(g["wb"].sum(), 1.0) and np.all(g["wb"][~ins] == 0)

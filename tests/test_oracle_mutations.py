@@ -56,6 +56,20 @@ MUTATIONS = [
     ("adjoint phase sign", "ey[2 * i + 1] = sin(k * y[j]);", "ey[2 * i + 1] = -sin(k * y[j]);"),
     ("adjoint grad_x uses y derivative", "(dWx * u + W * ux)", "(dWx * u + W * uy)"),
     ("adjoint window derivative dropped", "(dWy * u + W * uy)", "(W * uy)"),
+    ("frame: shortest edge instead of the longest", "if (L > best) { best = L; m = i; }",
+     "if (best < 0 || L < best) { best = L; m = i; }"),
+    ("frame: rotation transposed", "ut[2 * i + 1] = -sn * dx + cs * dy;", "ut[2 * i + 1] = sn * dx + cs * dy;"),
+    ("frame: half-width without the factor 1/2", "const double H = 0.5 * eta * fmax(ex, ey);",
+     "const double H = eta * fmax(ex, ey);"),
+    ("box coordinates without pi", "xb[j] = ux * M_PI / H;", "xb[j] = ux / H;"),
+    ("circle area taken as the square's", "else if (mask == 2) area = M_PI * H * H;",
+     "else if (mask == 2) area = 4.0 * H * H;"),
+    ("triangle mask: edge test sign", "int neg = (d1 < 0) || (d2 < 0) || (d3 < 0);",
+     "int neg = (d1 < 0) || (d2 > 0) || (d3 < 0);"),
+    ("clipping: intersection parameter", "const double t = da / (da - db);", "const double t = db / (da - db);"),
+    ("Voronoi: raster points outside the mask counted", "if (!in_mask(mask, gx, gy, H, ut)) continue;", ""),
+    ("Voronoi: empty-cell floor dropped", "(double)n[j - a] : floor_frac)", "(double)n[j - a] : 0.0)"),
+    ("deplaning by the unweighted mean of all samples", "hbar += wb[j] * h[j];", "hbar += h[j] / (double)(b - a);"),
 ]
 
 
