@@ -296,6 +296,64 @@ enufft_status enufft_reconstruct(enufft_plan_t p, const void *x, const void *y, 
                                  const void *coef, const uint8_t *keep, const double *area, void *h_rec,
                                  double *diag);
 
+/* Per-cell geometry of a triangular mesh (Appendix A1 local windowing, Appendix A2
+ * quadrature weights, Appendix A6 deplaning): turns tangent-plane samples of cell c,
+ * which lies on triangle T_c, into the inputs of enufft_type1_batched.
+ *   frame    ENUFFT_FRAME_CENTROID: R = I; ENUFFT_FRAME_EDGE: the rotation of eq.
+ *            (rotation_matrix) that takes the longest of the edges v2 - v1, v3 - v2,
+ *            v1 - v3 onto +x (the first of equally long edges).
+ *   local    u = R (x - xbar), xbar the centroid; half-width H = (eta / 2) max(extent
+ *            of the rotated vertices along x, along y); square box B = [-H, H]^2.
+ *   xb, yb   u * pi / H: B mapped onto the library's 2 pi box (period 2H), centred on
+ *            the centroid (the square-domain shift (x', y') = u + H of Appendix A1 only
+ *            multiplies every coefficient by (-1)^(kx + ky)).
+ *   mask     ENUFFT_MASK_SQUARE (B), ENUFFT_MASK_TRIANGLE (the rotated triangle within
+ *            B, edges included), ENUFFT_MASK_CIRCLE (|u| <= H); |D_c| is the mask's area
+ *            in B (the triangle clipped to B, exactly).
+ *   weights  ENUFFT_WEIGHTS_UNIFORM: w_q = |D| / Q_in over the Q_in samples inside the
+ *            mask (eq. uniform_weights).  ENUFFT_WEIGHTS_VORONOI: raster N_g x N_g cell
+ *            centres over B (eq. raster_grid); each one inside the mask goes to its
+ *            nearest inside sample (eq. nn_assignment; ties to the lowest index), A_q =
+ *            n_q |D| / |G| (eq. raster_area); a sample with n_q = 0 gets floor_frac
+ *            |D| / |G| and all areas are rescaled to sum to |D| (eq. voronoi_weights).
+ *   wb       w_q / |D_c|, 0 outside the mask: the factor eq. (discrete_quadrature) puts on
+ *            h_q.  Type-1 with window ENUFFT_WIN_NONE, scale 1 and w = wb gives eq.
+ *            (discrete_quadrature) on (xb, yb, hb).
+ *   hb       h - hbar with hbar = sum_q wb_q h_q, the weighted mean over the mask (eq.
+ *            alps_deplaning), when deplane is set; else h.
+ * Arguments:
+ *   tri      device, n_cells * 6 doubles (v1x, v1y, v2x, v2y, v3x, v3y) per cell.
+ *   x, y, h  device, n_points reals (the plan's precision), grouped by the plan's cells.
+ *   opts     host; raster in [1, 4096] for Voronoi weights, eta >= 1, floor_frac >= 0.
+ *   xb, yb, hb, wb  device, n_points reals (the plan's precision), all required.
+ *   inside   device, n_points bytes (1 inside the mask), or NULL.
+ *   info     device, n_cells * 8 doubles (xbar_x, xbar_y, cos, sin, H, |D|, Q_in, hbar;
+ *            hbar 0 without deplaning), or NULL.
+ *   counts   device, n_points int32 (n_q; 0 for uniform weights), or NULL.
+ * Frames, masks and the raster assignment are FP64 with the products and sums rounded
+ * one by one (no fused multiply-add), so flags and counts are exact functions of the
+ * FP64 inputs; the weight and mean sums are FP64 in the kernel's order.  Voronoi
+ * weights keep a sorted copy of the inside samples in plan workspace (20 bytes per
+ * point of the largest group of consecutive cells launched together, at most 2^26
+ * points or the largest cell). */
+typedef enum { ENUFFT_FRAME_CENTROID = 0, ENUFFT_FRAME_EDGE = 1 } enufft_frame_kind;
+typedef enum { ENUFFT_MASK_SQUARE = 0, ENUFFT_MASK_TRIANGLE = 1, ENUFFT_MASK_CIRCLE = 2 } enufft_mask_kind;
+typedef enum { ENUFFT_WEIGHTS_UNIFORM = 0, ENUFFT_WEIGHTS_VORONOI = 1 } enufft_weights_kind;
+typedef struct {
+    int32_t frame;       /* enufft_frame_kind */
+    int32_t mask;        /* enufft_mask_kind */
+    int32_t weights;     /* enufft_weights_kind */
+    int32_t raster;      /* N_g (Voronoi weights) */
+    double eta;          /* expansion factor, >= 1 */
+    double floor_frac;   /* empty-cell floor, in raster points */
+    int32_t deplane;     /* 1: subtract the weighted cell mean */
+    int32_t reserved_;
+} enufft_geometry_opts;
+
+enufft_status enufft_cell_geometry(enufft_plan_t p, const double *tri, const void *x, const void *y,
+                                   const void *h, const enufft_geometry_opts *opts, void *xb, void *yb,
+                                   void *hb, void *wb, uint8_t *inside, double *info, int32_t *counts);
+
 /* Plain per-cell form of type-1 + EMS for comparison: the same kernels,
  * launched once per cell from a host loop on the plan's stream (no batching,
  * no graph).  Arguments as enufft_type1_batched and enufft_ems. */

@@ -63,10 +63,22 @@ class PlanInfo(ctypes.Structure):
                 ("kernel_kind", ctypes.c_int32), ("reserved_", ctypes.c_int32)]
 
 
+class GeometryOptsC(ctypes.Structure):
+    _fields_ = [("frame", ctypes.c_int32), ("mask", ctypes.c_int32), ("weights", ctypes.c_int32),
+                ("raster", ctypes.c_int32), ("eta", ctypes.c_double), ("floor_frac", ctypes.c_double),
+                ("deplane", ctypes.c_int32), ("reserved_", ctypes.c_int32)]
+
+
+FRAMES = {"centroid": 0, "edge": 1}
+MASKS = {"square": 0, "triangle": 1, "circle": 2}
+WEIGHTS = {"uniform": 0, "voronoi": 1}
+
+
 EXPORTS = ["enufft_default_opts", "enufft_plan", "enufft_set_stream", "enufft_type1_batched",
            "enufft_type1_batched_noalloc", "enufft_ems",
            "enufft_ems_flow",
-           "enufft_type1_adjoint", "enufft_retained_power_adjoint", "enufft_reconstruct", "enufft_percell_loop",
+           "enufft_type1_adjoint", "enufft_retained_power_adjoint", "enufft_reconstruct", "enufft_cell_geometry",
+           "enufft_percell_loop",
            "enufft_forward_graph", "enufft_set_timing", "enufft_get_timing",
            "enufft_get_info", "enufft_destroy", "enufft_last_error", "enufft_version"]
 
@@ -94,6 +106,7 @@ def load_library(path: str = LIB_PATH):
     L.enufft_type1_adjoint.argtypes = [vp] * 9
     L.enufft_retained_power_adjoint.argtypes = [vp] * 11
     L.enufft_reconstruct.argtypes = [vp] * 10
+    L.enufft_cell_geometry.argtypes = [vp] * 5 + [ctypes.POINTER(GeometryOptsC)] + [vp] * 7
     L.enufft_percell_loop.argtypes = [vp] * 6 + [ctypes.POINTER(EmsParamsC), vp, vp, vp, vp]
     L.enufft_forward_graph.argtypes = [vp] * 6 + [ctypes.POINTER(EmsParamsC), vp, vp, vp, vp]
     L.enufft_set_timing.argtypes = [vp, i32]
@@ -313,6 +326,29 @@ class Plan:
                                             _ptr(None if keep is None else keep.contiguous()), _ptr(ar), _ptr(hr),
                                             _ptr(dg)), self._h)
         return hr, dg
+
+    def cell_geometry(self, tri, x, y, h, frame="edge", mask="triangle", weights="uniform", raster=64, eta=1.0,
+                      floor_frac=0.5, deplane=True, need_inside=True, need_info=True, need_counts=False):
+        """Local frames, masks, quadrature weights and deplaning of a triangular mesh
+        (Appendices A1, A2, A6) -> dict of device tensors xb, yb, hb, wb (the plan's
+        precision; wb = w_q / |D|), inside (uint8), info float64 [n_cells, 8] = (xbar_x,
+        xbar_y, cos, sin, H, |D|, Q_in, hbar), counts (int32 raster points per sample)."""
+        tri = torch.as_tensor(tri, dtype=torch.float64, device=self.device).reshape(self.n_cells, 6).contiguous()
+        for v in (x, y, h):
+            if v.dtype != self.dtype or v.device != self.device or not v.is_contiguous() or v.numel() != self.n_points:
+                raise ValueError("x, y, h must be contiguous %s of length %d on %s"
+                                 % (self.dtype, self.n_points, self.device))
+        o = GeometryOptsC(FRAMES[frame], MASKS[mask], WEIGHTS[weights], int(raster), float(eta), float(floor_frac),
+                          int(bool(deplane)), 0)
+        out = {k: torch.empty(self.n_points, dtype=self.dtype, device=self.device) for k in ("xb", "yb", "hb", "wb")}
+        out["inside"] = torch.empty(self.n_points, dtype=torch.uint8, device=self.device) if need_inside else None
+        out["info"] = torch.empty((self.n_cells, 8), dtype=torch.float64, device=self.device) if need_info else None
+        out["counts"] = torch.empty(self.n_points, dtype=torch.int32, device=self.device) if need_counts else None
+        self._sync_stream()
+        _check(self._lib.enufft_cell_geometry(self._h, _ptr(tri), _ptr(x), _ptr(y), _ptr(h), ctypes.byref(o),
+                                              _ptr(out["xb"]), _ptr(out["yb"]), _ptr(out["hb"]), _ptr(out["wb"]),
+                                              _ptr(out["inside"]), _ptr(out["info"]), _ptr(out["counts"])), self._h)
+        return out
 
     def percell_loop(self, x, y, h, w, params: EmsParams | None = EmsParams(), mode_weight=None):
         self._pts(x, y, h, w)

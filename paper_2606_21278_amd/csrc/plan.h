@@ -100,6 +100,10 @@ struct enufft_plan_s {
   double *big_sort = nullptr;                // EMS sort buffer, partials, cut record, tie flags
   int64_t big_sort_jpad = 0, big_ems_parts = 0;
 
+  // cell geometry (Voronoi weights): sorted sample copy (double2) and index + slot (2 x int32)
+  void *geo_ws = nullptr, *geo_ws_i = nullptr;
+  int64_t geo_ws_points = 0;
+
   // captured forward (type-1 + EMS) graph and the arguments it was captured with
   hipStream_t capture_stream = nullptr;
   hipGraph_t graph = nullptr;

@@ -518,3 +518,43 @@ def square_terrain(device="cpu", Q: int = 2000, n_modes=(41, 41), seed: int = 0,
     win = np.array([[0.0, 0.0, 0.0]])
     return _finish("square terrain seed %d" % seed, x, y, h, off, np.array([TWO_PI * TWO_PI]), win, n_modes,
                    2.0, 1e-10 if precision == "f64" else 1e-5, precision)
+
+
+def mesh_cells(device="cpu", n_cells: int = 24, count_scale: float = 0.05, seed: int = 31, precision: str = "f64",
+               clustered: float = 0.0, n_modes=(32, 32)):
+    """Triangular-mesh cells as a mesh pipeline hands them over: C3's first ``n_cells``
+    triangles and samples, each cell turned by a seeded angle and moved by a seeded
+    offset (so the local frames are not the identity).  With ``clustered`` > 0 that
+    fraction of each cell's samples is redrawn around one seeded point of the
+    triangle (normal spread 0.15), giving the strongly non-uniform sampling Voronoi
+    weights are meant for.  Returns (Batch without windows, tri float64 [n_cells, 6])."""
+    b = config3(n_cells=n_cells, count_scale=count_scale, precision="f64", seed_config=3)
+    tris = local_triangles(5)[:n_cells]
+    rng = np.random.Generator(np.random.PCG64(seed))
+    th = rng.uniform(0.0, TWO_PI, n_cells)
+    sh = rng.uniform(-5.0, 5.0, (n_cells, 2))
+    off = b.cell_offsets
+    x = b.x.numpy().copy()
+    y = b.y.numpy().copy()
+    for c in range(n_cells):
+        a0, a1 = int(off[c]), int(off[c + 1])
+        if clustered > 0 and a1 > a0:
+            m = int(round(clustered * (a1 - a0)))
+            bary = rng.dirichlet([2.0, 2.0, 2.0])
+            p = bary @ tris[c]
+            x[a0:a0 + m] = p[0] + rng.normal(scale=0.15, size=m)
+            y[a0:a0 + m] = p[1] + rng.normal(scale=0.15, size=m)
+    tri = np.zeros((n_cells, 6))
+    cs, sn = np.cos(th), np.sin(th)
+    cell = np.repeat(np.arange(n_cells), np.diff(off))
+    xr = cs[cell] * x - sn[cell] * y + sh[cell, 0]
+    yr = sn[cell] * x + cs[cell] * y + sh[cell, 1]
+    for i in range(3):
+        tri[:, 2 * i] = cs * tris[:, i, 0] - sn * tris[:, i, 1] + sh[:, 0]
+        tri[:, 2 * i + 1] = sn * tris[:, i, 0] + cs * tris[:, i, 1] + sh[:, 1]
+    dt = torch.float64 if precision == "f64" else torch.float32
+    t = lambda v: torch.as_tensor(v, dtype=torch.float64).to(device=device, dtype=dt).contiguous()
+    win = np.zeros((n_cells, 3))
+    batch = Batch("mesh cells", t(xr), t(yr), t(b.h.numpy()), t(b.w.numpy()), off.copy(), win, tuple(n_modes), 2.0,
+                  1e-10 if precision == "f64" else 1e-5, precision, b.areas.copy())
+    return batch, tri

@@ -27,6 +27,7 @@ from helpers import per_cell_rel_l2, rel_l2, robust_selection
 pytestmark = pytest.mark.gpu
 
 TOL = 5e-5
+GEO = dict(frame="edge", mask="triangle", weights="voronoi", raster=64, eta=1.0, deplane=True)
 
 
 @pytest.fixture(scope="module")
@@ -61,7 +62,15 @@ def full_c3():
     sub = gb.subset(cells).to(device="cpu", dtype=torch.float32)
     idx = np.concatenate([np.arange(gb.cell_offsets[c], gb.cell_offsets[c + 1]) for c in cells])
     it = torch.as_tensor(idx, device=dev)
+    # mesh geometry (edge frame, triangle mask, raster-Voronoi weights, deplaning) over
+    # all cells at once, in the launch runs the workspace allows
+    tri = synth.local_triangles(5).reshape(-1, 6)
+    geo = plan.cell_geometry(tri, gb.x, gb.y, gb.h, need_counts=True, **GEO)
+    torch.cuda.synchronize()
+    geo = {k: (v[it].cpu().numpy() if k != "info" else v[cells].cpu().numpy()) for k, v in geo.items()}
+    geo["tri"] = tri[cells]
     out = {
+        "geo": geo,
         "cells": cells, "sub": sub, "info": info, "graph_dev": graph_dev, "graph_ks_same": graph_ks_same,
         "f": f[cells].cpu().numpy().astype(np.complex128),
         "keep": keep[cells].cpu().numpy(), "ks": ks[cells].cpu().numpy(), "st": st[cells].cpu().numpy(),
@@ -139,3 +148,24 @@ def test_full_c3_gradients_end_to_end(full_c3):
         e = rel_l2(got.astype(np.float64)[mask], want[mask])
         print("end-to-end grad_%s rel-l2 %.3e" % (name, e), flush=True)
         assert e <= TOL
+
+
+def test_full_c3_geometry_on_sampled_cells(full_c3):
+    """enufft_cell_geometry over all 20,480 cells (several launches over runs of cells)
+    against the oracle on the sampled cells: identical mask flags, raster counts, Q_in,
+    frames and box coordinates; weights and deplaned heights to one FP32 rounding."""
+    g = full_c3["geo"]
+    sub = full_c3["sub"]
+    d = lambda t: t.double().numpy()
+    ref = oracle.cell_geometry(sub.cell_offsets, g["tri"], d(sub.x), d(sub.y), d(sub.h), **GEO)
+    print("geometry: Q_in %d of %d sampled points; raster points per sample max %d"
+          % (int(ref["info"][:, 6].sum()), sub.n_points, int(ref["counts"].max())), flush=True)
+    assert np.array_equal(g["inside"], ref["inside"])
+    assert np.array_equal(g["counts"], ref["counts"])
+    assert np.array_equal(g["info"][:, :5], ref["info"][:, :5]) and np.array_equal(g["info"][:, 6], ref["info"][:, 6])
+    assert np.allclose(g["info"][:, 5], ref["info"][:, 5], rtol=1e-13, atol=0)
+    f32 = lambda v: v.astype(np.float32)
+    assert np.array_equal(g["xb"], f32(ref["xb"])) and np.array_equal(g["yb"], f32(ref["yb"]))
+    ulp = lambda v: np.spacing(np.abs(f32(v))).astype(np.float64)
+    assert np.all(np.abs(g["wb"] - ref["wb"]) <= ulp(ref["wb"]))
+    assert np.all(np.abs(g["hb"] - ref["hb"]) <= ulp(ref["hb"]) + 1e-12 * np.abs(ref["info"][:, 7]).max())
