@@ -309,6 +309,35 @@ def flow_selection_figures(plan, gb, f, prm, torch, steps, n_t=8, seed=5):
             "k_star_median": float(np.median(k)), "k_star_changed_between_steps": float(np.mean(k[1:] != k[:-1]))}
 
 
+def geometry_figures(plan, gb, torch, synth, steps):
+    """enufft_cell_geometry over the whole batch (the icosahedral triangles the cells
+    lie on): edge frame, triangle mask, deplaning, with raster-Voronoi weights (N_g =
+    64) and with uniform weights; HIP events on the plan's stream.  Algorithmic bytes
+    per point: x, y, h read (3 reals) and xb, yb, hb, wb and the mask byte written."""
+    tri = synth.local_triangles(5)[:gb.n_cells].reshape(-1, 6)
+    out = {}
+    el = gb.x.element_size()
+    for wk in ("voronoi", "uniform"):
+        kw = dict(frame="edge", mask="triangle", weights=wk, raster=64, eta=1.0, deplane=True, need_info=False)
+        plan.cell_geometry(tri, gb.x, gb.y, gb.h, **kw)
+        torch.cuda.synchronize()
+        s = torch.cuda.current_stream()
+        e = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+        for e0, e1 in e:
+            e0.record(s)
+            g = plan.cell_geometry(tri, gb.x, gb.y, gb.h, **kw)
+            e1.record(s)
+            del g
+        torch.cuda.synchronize()
+        ms = float(np.median([a.elapsed_time(b) for a, b in e]))
+        byts = (7 * el + 1) * gb.n_points
+        out[wk] = {"ms": ms, "points_per_s": float(gb.n_points / (ms * 1e-3)),
+                   "achieved_GBps": byts / (ms * 1e-3) / 1e9, "hbm_frac": byts / (ms * 1e-3) / 8e12}
+    torch.cuda.empty_cache()
+    out["note"] = "edge frame, triangle mask, deplaning; Voronoi N_g = 64 raster"
+    return out
+
+
 def gate_cells(counts, seed=7, n_random=4):
     """The parity gate's cells: the two largest, the two smallest non-empty and
     n_random seeded others."""
@@ -621,6 +650,10 @@ def main():
     log("reconstruction", recon)
     flow_sel = flow_selection_figures(plan, gb, f, prm, torch, args.steps)
     log("flow-dependent EMS", flow_sel)
+    geo = None
+    if not c1:
+        geo = geometry_figures(plan, gb, torch, synth, args.steps)
+        log("mesh geometry", geo)
 
     if args.calibrate_copy > 0:
         # one streaming kernel of known traffic whose name no other kernel of this run shares
@@ -690,7 +723,7 @@ def main():
         "graph_type1_ems_ms": {"median": t_fwd, "mean": float(graph_ms.mean()), "min": float(graph_ms.min()),
                                "max": float(graph_ms.max())},
         "adjoint_in_step_ms": float(np.median(adj_step_ms)),
-        "reconstruction": recon, "flow_ems": flow_sel,
+        "reconstruction": recon, "flow_ems": flow_sel, "mesh_geometry": geo,
         "parity_gate": gate, "plan": {k: info[k] for k in ("fwd_threads", "fwd_chunk_min", "fwd_items_per_slot",
                                                            "adj_items_per_slot", "adj_band_mult", "fwd_acc", "n_items_fwd",
                                                            "n_split_cells", "n_items_adj", "tuned")},
