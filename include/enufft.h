@@ -154,7 +154,9 @@ typedef struct {
     int32_t fwd_acc;         /* bytes per forward LDS grid cell: 8 (FP64 sums) or 4 (FP32 sums) */
     double tune_fwd_ms, tune_adj_ms;   /* best trial times of the autotuner */
     int32_t kernel_kind;     /* enufft_kernel_kind of the plan */
-    int32_t reserved_;
+    int32_t adj_kernel_width; /* adjoint: width of its own kernel when it gathers value and derivative
+                                 taps from one LDS grid per cell (FP32, forward width + 2); 0 when it
+                                 gathers from three grids in row bands with the forward's kernel */
 } enufft_plan_info;
 
 /* Fill *o with defaults: 64 x 64 modes, sigma 2, eps 1e-5, F32, Hann window,

@@ -60,7 +60,7 @@ class PlanInfo(ctypes.Structure):
                 ("fwd_items_per_slot", ctypes.c_int32), ("adj_items_per_slot", ctypes.c_int32),
                 ("adj_band_mult", ctypes.c_int32), ("fwd_acc", ctypes.c_int32),
                 ("tune_fwd_ms", ctypes.c_double), ("tune_adj_ms", ctypes.c_double),
-                ("kernel_kind", ctypes.c_int32), ("reserved_", ctypes.c_int32)]
+                ("kernel_kind", ctypes.c_int32), ("adj_kernel_width", ctypes.c_int32)]
 
 
 class GeometryOptsC(ctypes.Structure):

@@ -627,6 +627,243 @@ hipError_t launch_adj(const AdjArgs<T> &a, int W, int blocks, int threads, size_
 template hipError_t launch_adj<float>(const AdjArgs<float> &, int, int, int, size_t, hipStream_t);
 template hipError_t launch_adj<double>(const AdjArgs<double> &, int, int, int, size_t, hipStream_t);
 
+// ------------------------------------------------------------------ single-grid adjoint
+//
+// FP32 plans whose kernel takes the polynomial path: the cell's whole real grid
+// of u (the inverse transform of the pre-corrected, Hermitian spectrum) fits
+// LDS, and du/dx, du/dy come from the same grid through the derivatives of the
+// kernel taps: u(t) = sum_m G_m psi_x psi_y, du/dt_x = sum_m G_m psi_x' psi_y.
+// The interpolant's derivative converges more slowly than the interpolant, so
+// this path uses its own kernel two cells wider than the forward's (with its
+// own deconvolution factors).  One pass per cell: one column transform pass,
+// half as many row transforms as rows (real rows in pairs), then the gather.
+
+struct Adj1Layout {
+  int rows;      // grid rows stored: n2 + W (the first W - 1 repeated after the last)
+  int apitch;    // row pitch: n1 + W - 1 rounded up to even (first W - 1 columns repeated)
+  int cpitch;    // column-workspace pitch
+  size_t g_off, ws_off, st_off, db_off, tw_off, total;   // element offsets
+};
+
+__host__ __device__ inline Adj1Layout adj1_layout(const Geom &g, int W, size_t elem) {
+  Adj1Layout L;
+  L.rows = g.n2 + W;
+  L.apitch = (g.n1 + W - 1 + 1) & ~1;
+  L.cpitch = 2 * (g.K1 + 1) + 2;
+  L.g_off = 0;
+  // the column workspace and the staged spectrum alias the grid (both are dead
+  // before the row transforms write it); the column output db does not
+  L.ws_off = 0;
+  const size_t ws = (size_t)g.n2 * L.cpitch;
+  L.st_off = ws;
+  const size_t gsz = (size_t)L.rows * L.apitch, wst = ws + adj_stage_elems(g, elem);
+  L.db_off = gsz > wst ? gsz : wst;
+  L.tw_off = L.db_off + (size_t)g.n2 * (g.K1 + 1) * 2;
+  L.total = L.tw_off + 2 * (size_t)(g.n1 + g.n2);
+  return L;
+}
+
+// Derivative taps from the mirror-pair polynomials: tap d is E + u O and, the
+// derivative of an even kernel being odd, tap W - 1 - d is u O - E.
+template <int W>
+__device__ __forceinline__ void es_dtaps_poly_v(float v, const EsPoly &cf, float (&out)[W]) {
+  const float u = 2.0f * v - 1.0f;
+  const float s = u * u;
+#pragma unroll
+  for (int d = 0; d < W / 2; ++d) {
+    const float *cd = cf.c + d * (ES_DEG + 1);
+    float e = cd[ES_DEG - 1], o = cd[ES_DEG];
+#pragma unroll
+    for (int k = ES_DEG - 3; k >= 0; k -= 2) {
+      e = fmaf(e, s, cd[k]);
+      o = fmaf(o, s, cd[k + 1]);
+    }
+    out[d] = fmaf(u, o, e);
+    out[W - 1 - d] = fmaf(u, o, -e);
+  }
+}
+
+// Gradients at one point: W x W taps of the grid with value and derivative
+// weights (row sums with psi_x and psi_x', then combined with psi_y, psi_y'),
+// then the chain rule through the strength as in gather_point.
+template <int W>
+__device__ __forceinline__ void gather1_point(const AdjArgs<float> &a, const float *G, int apitch, int64_t j, float xj,
+                                              float yj, float hj, float wj, float cx, float cy, float R, float pr) {
+  const Geom &g = a.g;
+  const float halfw = float(W) * 0.5f;
+  const FineCoord<float> fx = fine_coord<float>(xj, a.s1_hi, a.s1_lo, halfw);
+  const FineCoord<float> fy = fine_coord<float>(yj, a.s2_hi, a.s2_lo, halfw);
+  const float vx = tap_v(fx, halfw), vy = tap_v(fy, halfw);
+  float kx[W], kxd[W], ky[W], kyd[W];
+  es_taps_poly_v<W>(vx, a.es, kx);
+  es_dtaps_poly_v<W>(vx, a.esd, kxd);
+  es_taps_poly_v<W>(vy, a.es, ky);
+  es_dtaps_poly_v<W>(vy, a.esd, kyd);
+  const float *p = G + (fy.i0 & (g.n2 - 1)) * apitch + (fx.i0 & (g.n1 - 1));
+  float u = 0.0f, ux = 0.0f, uy = 0.0f;
+#pragma unroll
+  for (int dy = 0; dy < W; ++dy) {
+    float s = 0.0f, sd = 0.0f;
+#pragma unroll
+    for (int dx = 0; dx < W; ++dx) {
+      const float v = p[dx];
+      s = fmaf(kx[dx], v, s);
+      sd = fmaf(kxd[dx], v, sd);
+    }
+    u = fmaf(ky[dy], s, u);
+    ux = fmaf(ky[dy], sd, ux);
+    uy = fmaf(kyd[dy], s, uy);
+    p += apitch;
+  }
+  // the derivative sums are formed here, in the row loop, not sunk into the
+  // branch that stores them (which kept all W x W grid values live)
+  asm volatile("" : "+v"(ux), "+v"(uy));
+  ux *= a.dsx;
+  uy *= a.dsy;
+  float dWx, dWy;
+  const float Wv = hann_wg(a.window_kind, xj, yj, cx, cy, R, pr, dWx, dWy);
+  if (a.grad_h) a.grad_h[j] = wj * Wv * u;
+  if (a.grad_x || a.grad_y) {
+    const float wh = wj * hj;
+    if (a.grad_x) a.grad_x[j] = wh * (dWx * u + Wv * ux);
+    if (a.grad_y) a.grad_y[j] = wh * (dWy * u + Wv * uy);
+  }
+}
+
+// All points of one item, in the order of gather_item (wave w: blocks of 256
+// consecutive points, lane l the points l, l + 64, l + 128, l + 192 of a
+// block); the loads run one block ahead in two register buffers.
+template <int W, int NT>
+__device__ __forceinline__ void gather1_item(const AdjArgs<float> &a, const float *G, int apitch, int64_t begin,
+                                             int64_t end, float cx, float cy, float R) {
+  const float pr = R > 0.0f ? float(M_PI) / R : 0.0f;
+  constexpr int U = 4, BLK = 64 * U, NWV = NT / 64;
+  struct Pts {
+    float x[U], y[U], h[U], w[U];
+  };
+  const int lane = threadIdx.x & 63;
+  const int64_t stride = (int64_t)NWV * BLK;
+  auto load = [&](Pts &b, int64_t pb) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t i = pb + u * 64 + lane;
+      const int64_t ic = i < end ? i : end - 1;   // past the end: re-read the last point (unused)
+      b.x[u] = a.x[ic]; b.y[u] = a.y[ic]; b.h[u] = a.h[ic]; b.w[u] = a.w[ic];
+    }
+  };
+  // one copy of the point code (its taps and row sums are not interleaved
+  // across the U points, which would multiply the registers they hold)
+  auto pick = [](const float (&v)[U], int u) {
+    float r = v[0];
+#pragma unroll
+    for (int k = 1; k < U; ++k) r = u == k ? v[k] : r;
+    return r;
+  };
+  auto step = [&](const Pts &b, int64_t pb) {
+#pragma unroll 1
+    for (int u = 0; u < U; ++u) {
+      const int64_t i = pb + u * 64 + lane;
+      if (i < end) gather1_point<W>(a, G, apitch, i, pick(b.x, u), pick(b.y, u), pick(b.h, u), pick(b.w, u), cx, cy, R, pr);
+    }
+  };
+  if (begin >= end) return;
+  int64_t p = begin + (int64_t)(threadIdx.x >> 6) * BLK;
+  Pts b0, b1;
+  load(b0, p);
+  for (; p < end; p += 2 * stride) {
+    load(b1, p + stride);
+    step(b0, p);
+    load(b0, p + 2 * stride);
+    step(b1, p + stride);
+  }
+}
+
+template <int W, int NT>
+__global__ __launch_bounds__(NT) void adj1_kernel(AdjArgs<float> a) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  float *sm = reinterpret_cast<float *>(smem_raw);
+  __shared__ int s_item;
+  const Geom &g = a.g;
+  const Adj1Layout L = adj1_layout(g, W, sizeof(float));
+  float *G = sm + L.g_off, *ws = sm + L.ws_off, *st = sm + L.st_off, *db = sm + L.db_off;
+  float *tw1 = sm + L.tw_off, *tw2 = tw1 + 2 * g.n1;
+  const int per = g.K1 + 1, pitch = L.apitch;
+  const bool persistent = a.work_counter != nullptr;
+  int64_t idx = a.item_base + blockIdx.x;
+  if (!persistent && idx >= a.n_items) return;
+  for (int i = threadIdx.x; i < 2 * g.n1; i += NT) tw1[i] = a.tw1[i];
+  for (int i = threadIdx.x; i < 2 * g.n2; i += NT) tw2[i] = a.tw2[i];
+  if (!persistent) __syncthreads();
+  for (;;) {
+    if (persistent) {
+      if (threadIdx.x == 0) s_item = atomicAdd(a.work_counter, 1);
+      __syncthreads();
+      idx = s_item;
+      __syncthreads();
+      if (idx >= a.n_items) break;
+    }
+    const AdjItem it = a.items[idx];
+    const float *gc = a.fbar + (int64_t)it.cell * g.N1 * g.N2 * 2;
+    const float two_lam = a.keep ? float(2.0 * (a.lam ? a.lam[it.cell] : 1.0)) : 1.0f;
+    stage_spectrum<float, NT>(a, gc, it.cell, st);
+    // columns kx = 0 .. K1 of the pre-corrected spectrum, inverse transformed along y
+    column_pass<float, NT>(a, st, tw2, two_lam, ws, L.cpitch, false, db, g.n2, 0);
+    // rows in pairs: Z(k) = D_2q(k) + i D_2q+1(k) gives rows 2q and 2q + 1 as its real
+    // and imaginary parts (both rows' spectra are Hermitian)
+    const int n1 = g.n1, K1 = g.K1;
+    row_ifft_natural<NT, float>(
+        n1, g.n2 / 2, tw1, W - 1,
+        [&](int q) {
+          RowSpecAcc<float> acc;
+          acc.db = db;
+          acc.row = 2 * q;
+          acc.pair = true;
+          acc.per = per;
+          acc.n1 = n1;
+          acc.K1 = K1;
+          acc.r0 = G + 2 * q * pitch;
+          acc.r1 = acc.r0 + pitch;
+          acc.stride = 1;
+          return acc;
+        },
+        [&](int q) {
+          StridedPairAcc<float> acc;
+          acc.r0 = G + 2 * q * pitch;
+          acc.r1 = acc.r0 + pitch;
+          acc.stride = 1;
+          return acc;
+        });
+    // the first W - 1 rows again after the last (with their repeated columns)
+    for (int i = threadIdx.x; i < (W - 1) * pitch; i += NT) G[g.n2 * pitch + i] = G[i];
+    __syncthreads();
+    const double *wn = a.windows + 3 * (int64_t)it.cell;
+    gather1_item<W, NT>(a, G, pitch, it.begin, it.end, float(wn[0]), float(wn[1]), float(wn[2]));
+    __syncthreads();
+    if (!persistent) break;
+  }
+  if (persistent && threadIdx.x == 0) {
+    __threadfence();
+    const int old = atomicAdd(a.done_counter, 1);
+    if (old == (int)gridDim.x - 1) {
+      *a.work_counter = 0;
+      *a.done_counter = 0;
+    }
+  }
+}
+
+static const void *adj1_fn(int W, int threads) {
+  if (W == 6) return threads == 512 ? (const void *)&adj1_kernel<6, 512> : (const void *)&adj1_kernel<6, 1024>;
+  if (W == 8) return threads == 512 ? (const void *)&adj1_kernel<8, 512> : (const void *)&adj1_kernel<8, 1024>;
+  return nullptr;
+}
+
+static hipError_t launch_adj1(const AdjArgs<float> &a, int W, int blocks, int threads, size_t lds, hipStream_t s) {
+  const void *fn = adj1_fn(W, threads);
+  if (!fn) return hipErrorInvalidValue;
+  void *args[] = {const_cast<AdjArgs<float> *>(&a)};
+  return hipLaunchKernel(fn, dim3(blocks), dim3(threads), args, lds, s);
+}
+
 // ------------------------------------------------------------------ host side
 
 enufft_status record_start(enufft_plan_t p, int kind, hipEvent_t *ev);
@@ -654,12 +891,11 @@ int choose_bands(const Geom &g, int W, size_t elem, size_t lds_max, int *band_ro
 
 // Adjoint work list: every (cell, band) pair, cells above the chunk target cut
 // into point chunks (gathers need no merge), longest first.
-void build_adj_schedule(enufft_plan_t p, int slots) {
+void build_adj_schedule(enufft_plan_t p, int slots, int B, std::vector<AdjItem> &items) {
   const int64_t Q = p->n_points;
-  const int B = p->adj_bands;
   const int64_t per = (int64_t)p->adj_items_per_slot * std::max(1, slots);
   const int64_t T = std::max<int64_t>(16384, (Q * B + per - 1) / per);
-  p->adj_items.clear();
+  items.clear();
   for (int64_t c = 0; c < p->n_cells; ++c) {
     const int64_t a = p->offsets[c], b = p->offsets[c + 1];
     const int64_t q = b - a;
@@ -667,9 +903,9 @@ void build_adj_schedule(enufft_plan_t p, int slots) {
     const int64_t nch = std::max<int64_t>(1, (q + T - 1) / T);
     for (int band = 0; band < B; ++band)
       for (int64_t i = 0; i < nch; ++i)
-        p->adj_items.push_back(AdjItem{a + q * i / nch, a + q * (i + 1) / nch, (int32_t)c, band, 0, 0});
+        items.push_back(AdjItem{a + q * i / nch, a + q * (i + 1) / nch, (int32_t)c, band, 0, 0});
   }
-  std::stable_sort(p->adj_items.begin(), p->adj_items.end(), [](const AdjItem &x, const AdjItem &y) {
+  std::stable_sort(items.begin(), items.end(), [](const AdjItem &x, const AdjItem &y) {
     return (x.end - x.begin) > (y.end - y.begin);
   });
 }
@@ -699,6 +935,8 @@ void adj_reset(enufft_plan_t p) {
   dev_release(p, &p->d_cell_item_off, (size_t)(p->n_cells + 1) * sizeof(int64_t));
   dev_release(p, &p->d_cell_off, (size_t)(p->n_cells + 1) * sizeof(int64_t));
   p->adj_items.clear();
+  dev_release(p, &p->d_adj1_items, std::max<size_t>(1, p->adj1_items.size()) * sizeof(AdjItem));
+  p->adj1_items.clear();
 }
 
 // Device allocation recorded in the plan's workspace (released with the plan).
@@ -744,7 +982,7 @@ enufft_status adj_prepare(enufft_plan_t p) {
     return ENUFFT_EDEVICE;
   }
   const int slots = p->n_cu * per_cu;
-  build_adj_schedule(p, slots);
+  build_adj_schedule(p, slots, p->adj_bands, p->adj_items);
   p->adj_blocks = (int)std::min<int64_t>(slots, std::max<int64_t>(1, (int64_t)p->adj_items.size()));
   const size_t n_items = std::max<size_t>(1, p->adj_items.size());
   // the items of each cell, ascending (the reconstruction sums a cell's item
@@ -776,6 +1014,33 @@ enufft_status adj_prepare(enufft_plan_t p) {
     p->last_error = std::string("adjoint item upload: ") + hipGetErrorString(e);
     p->faulted = true;
     return ENUFFT_EDEVICE;
+  }
+  if (p->adj1) {
+    // single-grid adjoint: one item per cell (or chunk of a large cell), no bands
+    p->adj1_lds = adj1_layout(p->geom, p->adj1_W, sizeof(float)).total * sizeof(float);
+    const void *fn = adj1_fn(p->adj1_W, p->adj1_threads);
+    int per1 = 0;
+    e = fn ? hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)p->adj1_lds)
+           : hipErrorInvalidValue;
+    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per1, fn, p->adj1_threads, p->adj1_lds);
+    if (e != hipSuccess || per1 < 1) {
+      p->last_error = "single-grid adjoint kernel cannot be resident";
+      return ENUFFT_EDEVICE;
+    }
+    const int slots1 = p->n_cu * per1;
+    build_adj_schedule(p, slots1, 1, p->adj1_items);
+    p->adj1_blocks = (int)std::min<int64_t>(slots1, std::max<int64_t>(1, (int64_t)p->adj1_items.size()));
+    void *d1 = nullptr;
+    st = adj_alloc(p, &d1, std::max<size_t>(1, p->adj1_items.size()) * sizeof(AdjItem), "adjoint item");
+    if (st != ENUFFT_OK) return st;
+    if (!p->adj1_items.empty())
+      e = hipMemcpy(d1, p->adj1_items.data(), p->adj1_items.size() * sizeof(AdjItem), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      p->last_error = std::string("adjoint item upload: ") + hipGetErrorString(e);
+      p->faulted = true;
+      return ENUFFT_EDEVICE;
+    }
+    p->d_adj1_items = d1;
   }
   p->d_adj_items = d;
   return ENUFFT_OK;
@@ -853,6 +1118,21 @@ enufft_status adjoint_common(enufft_plan_t p, const char *fn, const void *x, con
     a.keep = keep;
     a.lam = lam;
     e = launch_adj<double>(a, p->W, p->adj_blocks, p->adj_threads, p->adj_lds, p->stream);
+  } else if (p->adj1) {
+    auto a = make_adj_args<float>(p, x, y, h, w, fin, grad_h, grad_x, grad_y);
+    a.keep = keep;
+    a.lam = lam;
+    a.items = (const AdjItem *)p->d_adj1_items;
+    a.n_items = (int64_t)p->adj1_items.size();
+    a.decon_x = (const float *)p->d_adj1_decon_x;
+    a.decon_y = (const float *)p->d_adj1_decon_y;
+    a.es = p->adj1_es;
+    a.esd = p->adj1_esd;
+    a.dsx = (float)(p->n1 / (2.0 * M_PI));
+    a.dsy = (float)(p->n2 / (2.0 * M_PI));
+    a.bands = 1;
+    a.band_rows = p->n2;
+    e = launch_adj1(a, p->adj1_W, p->adj1_blocks, p->adj1_threads, p->adj1_lds, p->stream);
   } else {
     auto a = make_adj_args<float>(p, x, y, h, w, fin, grad_h, grad_x, grad_y);
     a.keep = keep;

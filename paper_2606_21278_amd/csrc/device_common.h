@@ -87,6 +87,8 @@ struct AdjArgs {
   T beta;
   T s1_hi, s1_lo, s2_hi, s2_lo;
   EsPoly es;                   // as in FwdArgs
+  EsPoly esd;                  // single-grid adjoint: derivative taps d/dt
+  T dsx, dsy;                  // single-grid adjoint: n1 / (2 pi), n2 / (2 pi)
   int vec4;                    // x, y, h, w are 16-byte aligned: load runs of 4 points
   int bands, band_rows;        // row bands per cell and rows per band
   double *rec_part;            // reconstruction mode: per item (sum (t - h_rec)^2, sum t^2, sum w t^2)

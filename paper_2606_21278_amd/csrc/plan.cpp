@@ -188,10 +188,37 @@ std::vector<double> kb_ft(int W, double gamma, int n, int kmax) {
   return p;
 }
 
-// Per-tap polynomials of the kernel in u = 2 v - 1, v = i0 - t + W/2 in [0, 1):
-// Chebyshev interpolation at deg + 1 nodes, converted to monomial coefficients
-// (ascending).  Returns the largest deviation from the kernel on a fine sample.
-double fit_es_poly(int W, double beta, int deg, std::vector<double> &coef) {
+// d psi / dz of the plan's kernel on |z| < 1 (ES: psi beta (-z / sqrt(1 - z^2)); KB:
+// -gamma z I1(gamma s) / (s I0(gamma)), s = sqrt(1 - z^2)), zero outside.
+double bessel_i1_host(double x) {
+  const double t = 0.25 * x * x;
+  double term = 0.5 * x, sum = term;
+  for (int k = 1; k < 200; ++k) {
+    term *= t / ((double)k * (k + 1));
+    const double next = sum + term;
+    if (next == sum) break;
+    sum = next;
+  }
+  return sum;
+}
+
+double kernel_deriv_host(double z, double shape) {
+  if (!(std::fabs(z) < 1.0)) return 0.0;
+  const double s = std::sqrt(1.0 - z * z);
+  if (shape > 0.0) return es_host(z, shape) * shape * (-z / s);
+  const double g = -shape;
+  const double gs = g * s;
+  // I1(g s) / s = g (I1(g s) / (g s)), finite as s -> 0
+  const double i1_over = gs > 1e-8 ? bessel_i1_host(gs) / gs : 0.5;
+  return -g * g * z * i1_over / bessel_i0_host(g);
+}
+
+// Per-tap polynomials in u = 2 v - 1, v = i0 - t + W/2 in [0, 1) (tap d sits at
+// z = (v + d - W/2) 2 / W): Chebyshev interpolation of f(d, z) at deg + 1 nodes,
+// converted to monomial coefficients (ascending).  Returns the largest deviation on
+// a fine sample.
+template <typename F>
+double fit_tap_poly(int W, int deg, const F &f, std::vector<double> &coef) {
   coef.assign((size_t)W * (deg + 1), 0.0);
   double maxerr = 0.0;
   const int n = deg + 1;
@@ -199,7 +226,7 @@ double fit_es_poly(int W, double beta, int deg, std::vector<double> &coef) {
     std::vector<double> cheb(n, 0.0), yn(n), un(n);
     for (int i = 0; i < n; ++i) {
       un[i] = std::cos(M_PI * (i + 0.5) / n);
-      yn[i] = kernel_host(((0.5 * (un[i] + 1.0)) + d - 0.5 * W) * 2.0 / W, beta);
+      yn[i] = f(d, ((0.5 * (un[i] + 1.0)) + d - 0.5 * W) * 2.0 / W);
     }
     for (int j = 0; j < n; ++j) {
       double s = 0.0;
@@ -222,10 +249,21 @@ double fit_es_poly(int W, double beta, int deg, std::vector<double> &coef) {
       const double v = i / 2000.0, u = 2.0 * v - 1.0;
       double acc = coef[(size_t)d * n + deg];
       for (int k = deg - 1; k >= 0; --k) acc = acc * u + coef[(size_t)d * n + k];
-      maxerr = std::max(maxerr, std::fabs(acc - kernel_host((v + d - 0.5 * W) * 2.0 / W, beta)));
+      maxerr = std::max(maxerr, std::fabs(acc - f(d, (v + d - 0.5 * W) * 2.0 / W)));
     }
   }
   return maxerr;
+}
+
+// The kernel's taps as polynomials (the forward and both adjoints).
+double fit_es_poly(int W, double beta, int deg, std::vector<double> &coef) {
+  return fit_tap_poly(W, deg, [&](int, double z) { return kernel_host(z, beta); }, coef);
+}
+
+// The taps' derivatives with respect to the fine coordinate t: d/dt psi((i0 + d - t) 2 / W)
+// = -(2 / W) psi'(z).
+double fit_es_dpoly(int W, double beta, int deg, std::vector<double> &coef) {
+  return fit_tap_poly(W, deg, [&](int, double z) { return -(2.0 / W) * kernel_deriv_host(z, beta); }, coef);
 }
 
 int64_t alloc_cap_bytes() {
@@ -521,6 +559,41 @@ enufft_status enufft_plan(enufft_plan_t *out, int64_t n_cells, const int64_t *ce
     }
   }
 
+  // Single-grid adjoint: FP32 plans whose kernel takes the polynomial path use one LDS
+  // grid per cell with value and derivative taps of a kernel two cells wider (the
+  // derivative of the interpolant converges more slowly than the interpolant itself).
+  if (p->prec == ENUFFT_F32 && !big && p->es.on && W + 2 <= enufft::ES_MAXW) {
+    const char *ev = std::getenv("ENUFFT_ADJ_SINGLE");
+    if (!(ev && std::atoi(ev) == 0)) {
+      const int Wa = W + 2;
+      double ba = 0.0;
+      if (kb) {
+        ba = -kb_gamma(opts->kernel_kind, Wa);
+      } else {
+        int Wt = 0;
+        kernel_params(opts->eps, sigma_eff, Wa, &Wt, &ba);
+        if (Wt != Wa) ba = 0.0;
+      }
+      std::vector<double> cf, cd;
+      const double e0 = ba != 0.0 ? fit_es_poly(Wa, ba, enufft::ES_DEG, cf) : 1.0;
+      const double e1 = ba != 0.0 ? fit_es_dpoly(Wa, ba, enufft::ES_DEG, cd) : 1.0;
+      if (e0 <= std::max(0.1 * opts->eps, 1e-6) && e1 <= std::max(opts->eps, 1e-5)) {
+        p->adj1 = true;
+        p->adj1_avail = true;
+        p->adj1_W = Wa;
+        p->adj1_beta = ba;
+        p->adj1_poly_err = e0;
+        p->adj1_dpoly_err = e1;
+        p->adj1_es.on = 1;
+        p->adj1_esd.on = 1;
+        for (size_t i = 0; i < (size_t)(Wa / 2) * (enufft::ES_DEG + 1); ++i) {
+          p->adj1_es.c[i] = (float)cf[i];
+          p->adj1_esd.c[i] = (float)cd[i];
+        }
+      }
+    }
+  }
+
   // ---- forward launch shape (threads per workgroup: ENUFFT_FWD_THREADS, or the autotuner)
   enufft_status st = ENUFFT_OK;
   if (!big) {
@@ -541,6 +614,15 @@ enufft_status enufft_plan(enufft_plan_t *out, int64_t n_cells, const int64_t *ce
   for (int k = 0; k <= Kx; ++k) dx[k] = opts->scale / px[k];
   for (int k = 0; k <= Kx; ++k) dx1[k] = 1.0 / px[k];
   for (int k = 0; k <= Ky; ++k) dy[k] = 1.0 / py[k];
+  std::vector<double> adx, ady;
+  if (p->adj1) {
+    const int Wa = p->adj1_W;
+    const double ba = p->adj1_beta;
+    std::vector<double> qx = kb ? kb_ft(Wa, -ba, n1, Kx) : kernel_ft(Wa, ba, n1, Kx);
+    std::vector<double> qy = kb ? kb_ft(Wa, -ba, n2, Ky) : kernel_ft(Wa, ba, n2, Ky);
+    for (int k = 0; k <= Kx; ++k) adx.push_back(opts->scale / qx[k]);
+    for (int k = 0; k <= Ky; ++k) ady.push_back(1.0 / qy[k]);
+  }
   std::vector<double> tw1(2 * n1), tw2(2 * n2);
   for (int j = 0; j < n1; ++j) { tw1[2 * j] = std::cos(2 * M_PI * j / n1); tw1[2 * j + 1] = -std::sin(2 * M_PI * j / n1); }
   for (int j = 0; j < n2; ++j) { tw2[2 * j] = std::cos(2 * M_PI * j / n2); tw2[2 * j + 1] = -std::sin(2 * M_PI * j / n2); }
@@ -572,6 +654,11 @@ enufft_status enufft_plan(enufft_plan_t *out, int64_t n_cells, const int64_t *ce
                    std::make_pair(&p->d_decon_x1, &dx1),
                    std::make_pair(&p->d_tw1, &tw1), std::make_pair(&p->d_tw2, &tw2)}) {
     st = upload_table(tb.first, *tb.second, "tables");
+    if (st != ENUFFT_OK) { std::string m = p->last_error; free_plan(p); return fail(nullptr, st, m); }
+  }
+  if (p->adj1) {
+    st = upload_table(&p->d_adj1_decon_x, adx, "adjoint tables");
+    if (st == ENUFFT_OK) st = upload_table(&p->d_adj1_decon_y, ady, "adjoint tables");
     if (st != ENUFFT_OK) { std::string m = p->last_error; free_plan(p); return fail(nullptr, st, m); }
   }
 
@@ -620,6 +707,7 @@ enufft_status enufft_get_info(enufft_plan_t p, enufft_plan_info *info) {
   info->kernel_width = p->W;
   info->beta = std::fabs(p->beta);
   info->kernel_kind = p->opts.kernel_kind;
+  info->adj_kernel_width = p->adj1 ? p->adj1_W : 0;
   info->n_cells = p->n_cells;
   info->n_points = p->n_points;
   info->n_items_fwd = (int64_t)p->fwd_items.size();

@@ -57,6 +57,20 @@ struct enufft_plan_s {
   int fwd_threads = 512, fwd_blocks = 0, fwd_slots = 0;
   size_t fwd_lds = 0;
 
+  // single-grid adjoint (FP32 plans, kernel width W + 2 <= 8): one LDS grid of the cell with
+  // value and derivative taps of its own, wider kernel (adj1_W, adj1_beta) and tables
+  bool adj1 = false;                 // in use (the autotuner may choose the banded adjoint instead)
+  bool adj1_avail = false;           // its kernel and tables are set up
+  int adj1_W = 0;
+  double adj1_beta = 0.0;
+  enufft::EsPoly adj1_es{}, adj1_esd{};   // taps and their derivatives d/dt (t in grid cells)
+  double adj1_poly_err = 0.0, adj1_dpoly_err = 0.0;
+  void *d_adj1_decon_x = nullptr, *d_adj1_decon_y = nullptr;
+  std::vector<enufft::AdjItem> adj1_items;
+  void *d_adj1_items = nullptr;
+  int adj1_threads = 1024, adj1_blocks = 0;
+  size_t adj1_lds = 0;
+
   // adjoint schedule (also used by the reconstruction diagnostics)
   std::vector<enufft::AdjItem> adj_items;
   void *d_rec_part = nullptr;        // [items][3] doubles: per-item reconstruction sums

@@ -84,7 +84,7 @@ uint64_t fnv1a(const void *data, size_t n, uint64_t h = 1469598103934665603ULL) 
 std::string cache_key(enufft_plan_t p, const char *arch) {
   uint64_t hsh = fnv1a(p->offsets.data(), p->offsets.size() * sizeof(int64_t));
   char buf[320];
-  std::snprintf(buf, sizeof(buf), "v2_%s_cu%d_p%d_m%dx%d_g%dx%d_w%d_k%d_win%d_o%d_c%lld_q%lld_h%016llx", arch,
+  std::snprintf(buf, sizeof(buf), "v4_%s_cu%d_p%d_m%dx%d_g%dx%d_w%d_k%d_win%d_o%d_c%lld_q%lld_h%016llx", arch,
                 p->n_cu, p->prec, p->N1, p->N2, p->n1, p->n2, p->W, p->opts.kernel_kind, p->window_kind,
                 p->opts.autotune == 2 ? 1 : 0,
                 (long long)p->n_cells, (long long)p->n_points, (unsigned long long)hsh);
@@ -109,7 +109,8 @@ std::string cache_path() {
 }
 
 bool valid(const Choice &c) {
-  const bool pow2 = c.fwd_ips > 0 && c.adj_ips > 0 && c.band_mult > 0;
+  // band_mult 0: the single-grid adjoint
+  const bool pow2 = c.fwd_ips > 0 && c.adj_ips > 0 && c.band_mult >= 0;
   const bool thr = c.fwd_threads == 256 || c.fwd_threads == 512 || c.fwd_threads == 1024;
   const bool acc = c.fwd_acc == 4 || c.fwd_acc == 8;
   return pow2 && thr && acc && c.chunk_min >= 1024 && c.chunk_min <= (1LL << 24) && c.fwd_ips <= 64 && c.adj_ips <= 64 &&
@@ -260,10 +261,12 @@ enufft_status run_trials(enufft_plan_t t, size_t lds_limit, int unordered, Choic
     st = install_fwd_schedule(t);
   }
   if (st == ENUFFT_OK) st = enufft_type1_batched(t, x, y, h, w, f);
-  for (int bm : {1, 2}) {
+  for (int bm : {0, 1, 2}) {
     if (st != ENUFFT_OK) break;
+    if (bm == 0 && !t->adj1_avail) continue;
     for (int ips : {1, 2, 4}) {
-      t->adj_band_mult = bm;
+      t->adj1 = bm == 0;
+      t->adj_band_mult = bm == 0 ? 1 : bm;
       t->adj_items_per_slot = ips;
       adj_reset(t);
       double ms = 0.0;
@@ -275,6 +278,8 @@ enufft_status run_trials(enufft_plan_t t, size_t lds_limit, int unordered, Choic
     }
   }
   adj_reset(t);
+  t->adj1 = t->adj1_avail;
+  t->adj_band_mult = 1;
   t->timing = timing;
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
@@ -327,7 +332,8 @@ enufft_status autotune(enufft_plan_t p) {
   p->fwd_chunk_min = c.chunk_min;
   p->fwd_items_per_slot = c.fwd_ips;
   p->adj_items_per_slot = c.adj_ips;
-  p->adj_band_mult = c.band_mult;
+  p->adj1 = p->adj1_avail && c.band_mult == 0;
+  p->adj_band_mult = c.band_mult == 0 ? 1 : c.band_mult;
   p->tuned = true;
   p->tune_cache_hit = hit;
   p->tune_fwd_ms = c.fwd_ms;

@@ -339,6 +339,32 @@ def test_adjoint_small_mode_boxes(prec, n_modes):
     assert max(errs) <= TOL[prec]
 
 
+@pytest.mark.parametrize("single", [True, False])
+def test_adjoint_single_grid_and_banded(single, monkeypatch):
+    """FP32 plans gather from one LDS grid per cell with value and derivative taps of a
+    kernel two cells wider than the forward's (the default); ENUFFT_ADJ_SINGLE=0 keeps
+    the three-grid, row-band adjoint with the forward's kernel.  Both against the
+    oracle's analytic VJP at the FP32 tolerance, with a random cotangent (every mode
+    active, so the derivative sums see the whole spectrum)."""
+    if not single:
+        monkeypatch.setenv("ENUFFT_ADJ_SINGLE", "0")
+    b = synth.config1(count_scale=0.004, n_cells=12, precision="f32")
+    inp = oracle.batch_inputs(b)
+    g = np.random.default_rng(12).standard_normal((b.n_cells, 64, 64, 2)) @ np.array([1.0, 1j])
+    gh, gx, gy = oracle.type1_vjp(inp["offsets"], inp["x"], inp["y"], inp["h"], inp["w"], inp["windows"],
+                                  inp["n_modes"], g)
+    gb = gpu_batch(b)
+    plan = make_plan(gb)
+    info = plan.info()
+    assert info["adj_kernel_width"] == (info["kernel_width"] + 2 if single else 0)
+    fbar = torch.from_numpy(g).to("cuda:0", plan.cdtype)
+    ah, ax, ay = plan.adjoint(gb.x, gb.y, gb.h, gb.w, fbar)
+    errs = [rel_l2(ah.cpu().numpy(), gh), rel_l2(ax.cpu().numpy(), gx), rel_l2(ay.cpu().numpy(), gy)]
+    print("single grid" if single else "banded", "W_adj", info["adj_kernel_width"],
+          "rel-l2 h %.3e x %.3e y %.3e" % tuple(errs), flush=True)
+    assert max(errs) <= TOL["f32"]
+
+
 def test_adjoint_rejects_missing_point_arrays():
     """The C ABI refuses a NULL height array (every kernel reads it) before any launch."""
     b = synth.uniform_box(counts=[300, 40], n_modes=(16, 16), precision="f32", window_radius=2.5)
