@@ -356,6 +356,25 @@ enufft_status enufft_cell_geometry(enufft_plan_t p, const double *tri, const voi
                                    const void *h, const enufft_geometry_opts *opts, void *xb, void *yb,
                                    void *hb, void *wb, uint8_t *inside, double *info, int32_t *counts);
 
+/* Sort every cell's samples by the fine-grid cell where their kernel footprint starts
+ * (row-major; the footprint of eq. spreading, Section 2.1.2 Step 1): a one-time device
+ * counting sort that writes sorted copies.  In that order the batched type-1 spreads
+ * consecutive samples as merged runs; samples in no spatial order (shuffled, or grouped
+ * by something other than position) otherwise go one point at a time.  The caller then
+ * works on the sorted arrays (the coefficients are those of the original order up to
+ * rounding; gradients come out in the sorted order, perm maps them back).
+ *   x, y, h, w      device, n_points reals each (the plan's precision), grouped by the
+ *                   plan's cells; h and w may be NULL when hs, ws are.
+ *   xs, ys, hs, ws  device outputs, n_points reals each; hs, ws may be NULL.  Must not
+ *                   alias the inputs.
+ *   perm            device, n_points int32, or NULL: perm[i] is the input index of the
+ *                   sample at sorted position i (a permutation inside each cell).
+ * The order of samples that share a fine cell is not specified.  Large-cell plans (which
+ * sort by tile in every call) return ENUFFT_EUNSUPPORTED, as do batches of 2^31 points or
+ * more. */
+enufft_status enufft_sort_points(enufft_plan_t p, const void *x, const void *y, const void *h, const void *w,
+                                 void *xs, void *ys, void *hs, void *ws, int32_t *perm);
+
 /* Plain per-cell form of type-1 + EMS for comparison: the same kernels,
  * launched once per cell from a host loop on the plan's stream (no batching,
  * no graph).  Arguments as enufft_type1_batched and enufft_ems. */

@@ -77,7 +77,7 @@ WEIGHTS = {"uniform": 0, "voronoi": 1}
 EXPORTS = ["enufft_default_opts", "enufft_plan", "enufft_set_stream", "enufft_type1_batched",
            "enufft_type1_batched_noalloc", "enufft_ems",
            "enufft_ems_flow",
-           "enufft_type1_adjoint", "enufft_retained_power_adjoint", "enufft_reconstruct", "enufft_cell_geometry",
+           "enufft_type1_adjoint", "enufft_retained_power_adjoint", "enufft_reconstruct", "enufft_cell_geometry", "enufft_sort_points",
            "enufft_percell_loop",
            "enufft_forward_graph", "enufft_set_timing", "enufft_get_timing",
            "enufft_get_info", "enufft_destroy", "enufft_last_error", "enufft_version"]
@@ -107,6 +107,7 @@ def load_library(path: str = LIB_PATH):
     L.enufft_retained_power_adjoint.argtypes = [vp] * 11
     L.enufft_reconstruct.argtypes = [vp] * 10
     L.enufft_cell_geometry.argtypes = [vp] * 5 + [ctypes.POINTER(GeometryOptsC)] + [vp] * 7
+    L.enufft_sort_points.argtypes = [vp] * 10
     L.enufft_percell_loop.argtypes = [vp] * 6 + [ctypes.POINTER(EmsParamsC), vp, vp, vp, vp]
     L.enufft_forward_graph.argtypes = [vp] * 6 + [ctypes.POINTER(EmsParamsC), vp, vp, vp, vp]
     L.enufft_set_timing.argtypes = [vp, i32]
@@ -326,6 +327,26 @@ class Plan:
                                             _ptr(None if keep is None else keep.contiguous()), _ptr(ar), _ptr(hr),
                                             _ptr(dg)), self._h)
         return hr, dg
+
+    def sort_points(self, x, y, h=None, w=None, need_perm=True):
+        """Sorted copies of the samples, every cell ordered by the fine cell its kernel
+        footprint starts in (enufft_sort_points) -> (xs, ys, hs, ws, perm); hs / ws are
+        None when h / w are, perm int32 (input index of each sorted sample) or None."""
+        for v in (x, y, h, w):
+            if v is None:
+                continue
+            if v.dtype != self.dtype or v.device != self.device or not v.is_contiguous() or v.numel() != self.n_points:
+                raise ValueError("x, y, h, w must be contiguous %s of length %d on %s"
+                                 % (self.dtype, self.n_points, self.device))
+        new = lambda: torch.empty(self.n_points, dtype=self.dtype, device=self.device)
+        xs, ys = new(), new()
+        hs = new() if h is not None else None
+        ws = new() if w is not None else None
+        perm = torch.empty(self.n_points, dtype=torch.int32, device=self.device) if need_perm else None
+        self._sync_stream()
+        _check(self._lib.enufft_sort_points(self._h, _ptr(x), _ptr(y), _ptr(h), _ptr(w), _ptr(xs), _ptr(ys),
+                                            _ptr(hs), _ptr(ws), _ptr(perm)), self._h)
+        return xs, ys, hs, ws, perm
 
     def cell_geometry(self, tri, x, y, h, frame="edge", mask="triangle", weights="uniform", raster=64, eta=1.0,
                       floor_frac=0.5, deplane=True, need_inside=True, need_info=True, need_counts=False):

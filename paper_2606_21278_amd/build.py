@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libenufft.so")
-SOURCES = ["plan.cpp", "fwd.hip", "ems.hip", "adj.hip", "tune.hip", "big.hip", "noalloc.hip", "geometry.hip"]
+SOURCES = ["plan.cpp", "fwd.hip", "ems.hip", "adj.hip", "tune.hip", "big.hip", "noalloc.hip", "geometry.hip", "sort.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

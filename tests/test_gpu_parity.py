@@ -463,7 +463,7 @@ def test_autotune_choice_cached_and_correct(tmp_path, monkeypatch):
     assert info["tuned"] == 1 and info["tune_cache_hit"] == 0
     again = make_plan(gb, autotune=True).info()
     assert again["tune_cache_hit"] == 1
-    for k in ("fwd_chunk_min", "fwd_items_per_slot", "adj_items_per_slot", "adj_band_mult"):
+    for k in ("fwd_chunk_min", "fwd_items_per_slot", "adj_items_per_slot", "adj_band_mult", "adj_kernel_width"):
         assert again[k] == info[k]
     f0 = base.type1(gb.x, gb.y, gb.h, gb.w)
     f1 = tuned.type1(gb.x, gb.y, gb.h, gb.w)
@@ -472,8 +472,11 @@ def test_autotune_choice_cached_and_correct(tmp_path, monkeypatch):
     g1 = tuned.retained_power_adjoint(gb.x, gb.y, gb.h, gb.w, f0, keep)
     torch.cuda.synchronize()
     assert rel_l2(f1.cpu().numpy(), f0.cpu().numpy()) < 1e-6
+    # the tuner may pick the other adjoint (the banded one, with the forward's kernel):
+    # then the two are different approximations, each within the FP32 tolerance
+    same_adj = info["adj_kernel_width"] == base.info()["adj_kernel_width"]
     for a, c in zip(g0, g1):
-        assert rel_l2(c.cpu().numpy(), a.cpu().numpy()) < 1e-6
+        assert rel_l2(c.cpu().numpy(), a.cpu().numpy()) < (1e-6 if same_adj else 2 * TOL["f32"])
     ref = oracle_f(b.to(dtype=torch.float32))
     assert per_cell_rel_l2(f1.cpu().numpy(), ref).max() <= TOL["f32"]
     # trials on unordered points: a cache entry of their own, the same results
