@@ -334,10 +334,10 @@ enufft_status enufft_reconstruct(enufft_plan_t p, const void *x, const void *y, 
  *   counts   device, n_points int32 (n_q; 0 for uniform weights), or NULL.
  * Frames, masks and the raster assignment are FP64 with the products and sums rounded
  * one by one (no fused multiply-add), so flags and counts are exact functions of the
- * FP64 inputs; the weight and mean sums are FP64 in the kernel's order.  Voronoi
- * weights keep a sorted copy of the inside samples in plan workspace (20 bytes per
- * point of the largest group of consecutive cells launched together, at most 2^26
- * points or the largest cell). */
+ * FP64 inputs; the weight and mean sums are FP64 in the kernel's order.  One launch:
+ * resident workgroups take cells largest first; with Voronoi weights each keeps a
+ * binned copy of its cell's inside samples in plan workspace (24 bytes per point of
+ * the largest cell, per resident workgroup). */
 typedef enum { ENUFFT_FRAME_CENTROID = 0, ENUFFT_FRAME_EDGE = 1 } enufft_frame_kind;
 typedef enum { ENUFFT_MASK_SQUARE = 0, ENUFFT_MASK_TRIANGLE = 1, ENUFFT_MASK_CIRCLE = 2 } enufft_mask_kind;
 typedef enum { ENUFFT_WEIGHTS_UNIFORM = 0, ENUFFT_WEIGHTS_VORONOI = 1 } enufft_weights_kind;

@@ -31,7 +31,6 @@ namespace {
 
 constexpr int kGeoThreads = 512;
 constexpr int kGeoMaxBins = 128;                 // bins per axis
-constexpr int64_t kGeoChunkPoints = int64_t(1) << 26;
 
 struct GeoParams {
   int frame, mask, weights, raster, deplane;
@@ -159,9 +158,13 @@ __device__ double wg_sum(double v, double *red) {
   return red[0];
 }
 
+// Persistent workgroups take cells from a counter, largest cells first (the order
+// array), so the largest cells do not end the launch alone; each workgroup keeps
+// its Voronoi workspace in its own slice (the size of the largest cell).
 template <typename T>
 __global__ void __launch_bounds__(kGeoThreads) geometry_kernel(
-    GeoParams g, int64_t c0, const int64_t *__restrict__ off, const double *__restrict__ tri,
+    GeoParams g, const int32_t *__restrict__ order, int64_t n_cells, int *counter, int *done, int64_t slice,
+    const int64_t *__restrict__ off, const double *__restrict__ tri,
     const T *__restrict__ x, const T *__restrict__ y, const T *__restrict__ h, T *__restrict__ xb,
     T *__restrict__ yb, T *__restrict__ hb, T *__restrict__ wb, uint8_t *__restrict__ inside,
     double *__restrict__ info, int32_t *__restrict__ counts, double2 *__restrict__ ws_u,
@@ -171,13 +174,19 @@ __global__ void __launch_bounds__(kGeoThreads) geometry_kernel(
   __shared__ GeoFrame F;
   __shared__ double red[kGeoThreads];
   __shared__ int part[kGeoThreads];
-  __shared__ int qin_s, ng_s;
+  __shared__ int qin_s, ng_s, s_idx;
   int *bins = reinterpret_cast<int *>(geo_lds);   // [nb * nb + 1] (Voronoi only)
 
   const int t = threadIdx.x;
-  const int64_t c = c0 + blockIdx.x;
+  const int64_t base = (int64_t)blockIdx.x * slice;   // this workgroup's workspace slice
+  for (;;) {
+  if (t == 0) s_idx = atomicAdd(counter, 1);
+  __syncthreads();
+  const int64_t idx = s_idx;
+  __syncthreads();
+  if (idx >= n_cells) break;
+  const int64_t c = order[idx];
   const int64_t a = off[c], b = off[c + 1];
-  const int64_t base = a - off[c0];              // this cell's start in the workspace
   const int64_t Q = b - a;
   const bool vor = g.weights == ENUFFT_WEIGHTS_VORONOI;
   const int nb = vor ? (int)min<int64_t>(kGeoMaxBins, max<int64_t>(1, (int64_t)sqrt((double)Q / 3.0))) : 1;
@@ -351,6 +360,15 @@ __global__ void __launch_bounds__(kGeoThreads) geometry_kernel(
     ci[0] = F.cx; ci[1] = F.cy; ci[2] = F.cs; ci[3] = F.sn;
     ci[4] = F.H; ci[5] = F.area; ci[6] = (double)qin; ci[7] = g.deplane ? hbar : 0.0;
   }
+  __syncthreads();   // the frame, bins and sums are the next cell's
+  }
+  if (t == 0) {
+    __threadfence();
+    if (atomicAdd(done, 1) == (int)gridDim.x - 1) {   // the last workgroup resets the counters
+      *counter = 0;
+      *done = 0;
+    }
+  }
 }
 
 }  // namespace
@@ -383,17 +401,24 @@ enufft_status geo_fail(enufft_plan_t p, enufft_status st, const std::string &msg
 }
 
 template <typename T>
-hipError_t geo_launch(enufft_plan_t p, const GeoParams &g, int64_t c0, int64_t c1, size_t lds, const double *tri,
+hipError_t geo_launch(enufft_plan_t p, const GeoParams &g, int blocks, int64_t slice, size_t lds, const double *tri,
                       const void *x, const void *y, const void *h, void *xb, void *yb, void *hb, void *wb,
                       uint8_t *inside, double *info, int32_t *counts, double2 *ws_u, int32_t *ws_idx,
                       int32_t *ws_slot) {
   auto fn = geometry_kernel<T>;
-  hipError_t e = hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(fn, dim3((unsigned)(c1 - c0)), dim3(kGeoThreads), lds, p->stream, g, c0,
-                     (const int64_t *)p->d_cell_off, tri, (const T *)x, (const T *)y, (const T *)h, (T *)xb,
-                     (T *)yb, (T *)hb, (T *)wb, inside, info, counts, ws_u, ws_idx, ws_slot);
+  hipLaunchKernelGGL(fn, dim3((unsigned)blocks), dim3(kGeoThreads), lds, p->stream, g, (const int32_t *)p->geo_order,
+                     p->n_cells, p->d_counters + 6, p->d_counters + 7, slice, (const int64_t *)p->d_cell_off, tri,
+                     (const T *)x, (const T *)y, (const T *)h, (T *)xb, (T *)yb, (T *)hb, (T *)wb, inside, info,
+                     counts, ws_u, ws_idx, ws_slot);
   return hipGetLastError();
+}
+
+template <typename T>
+hipError_t geo_occupancy(size_t lds, int *per_cu) {
+  hipError_t e = hipFuncSetAttribute((const void *)geometry_kernel<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)lds);
+  if (e != hipSuccess) return e;
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, (const void *)geometry_kernel<T>, kGeoThreads, lds);
 }
 
 }  // namespace
@@ -427,12 +452,34 @@ extern "C" enufft_status enufft_cell_geometry(enufft_plan_t p, const double *tri
   const bool vor = o.weights == ENUFFT_WEIGHTS_VORONOI;
   GeoParams g{o.frame, o.mask, o.weights, o.raster, o.deplane ? 1 : 0, o.eta, o.floor_frac};
 
-  // launches over runs of consecutive cells, each within the workspace
+  // cells largest first (computed once per plan)
   int64_t largest = 0;
   for (int64_t c = 0; c < p->n_cells; ++c) largest = std::max(largest, p->offsets[c + 1] - p->offsets[c]);
   if (largest >= (int64_t(1) << 31)) return geo_fail(p, ENUFFT_EUNSUPPORTED, "cells of 2^31 points or more");
-  const int64_t cap = std::max(largest, kGeoChunkPoints);
-  const int64_t need = std::min<int64_t>(cap, p->n_points);
+  if (!p->geo_order) {
+    std::vector<int32_t> order((size_t)p->n_cells);
+    for (int64_t c = 0; c < p->n_cells; ++c) order[c] = (int32_t)c;
+    std::stable_sort(order.begin(), order.end(), [&](int32_t u, int32_t v) {
+      return p->offsets[u + 1] - p->offsets[u] > p->offsets[v + 1] - p->offsets[v];
+    });
+    st = geo_alloc(p, &p->geo_order, order.size() * sizeof(int32_t), "geometry cell order");
+    if (st != ENUFFT_OK) return st;
+    hipError_t e0 = hipMemcpy(p->geo_order, order.data(), order.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+    if (e0 != hipSuccess) {
+      dev_release(p, &p->geo_order, order.size() * sizeof(int32_t));
+      return geo_fail(p, ENUFFT_EDEVICE, std::string("cell order upload: ") + hipGetErrorString(e0));
+    }
+  }
+  // persistent workgroups: as many as are resident (the Voronoi bins take the LDS
+  // of the largest cell's bin grid)
+  const int nbl = vor ? std::min(kGeoMaxBins, geo_bins(largest) + 1) : 0;
+  const size_t lds = vor ? (size_t)(nbl * nbl + 1) * sizeof(int) : 16;
+  int per_cu = 0;
+  hipError_t e = p->prec == ENUFFT_F64 ? geo_occupancy<double>(lds, &per_cu) : geo_occupancy<float>(lds, &per_cu);
+  if (e != hipSuccess || per_cu < 1) return geo_fail(p, ENUFFT_EDEVICE, "geometry kernel cannot be resident");
+  const int blocks = (int)std::min<int64_t>(p->n_cells, (int64_t)p->n_cu * per_cu);
+  const int64_t slice = vor ? largest : 0;
+  const int64_t need = (int64_t)blocks * slice;
   if (vor && need > p->geo_ws_points) {
     dev_release(p, &p->geo_ws, (size_t)p->geo_ws_points * 16);
     dev_release(p, &p->geo_ws_i, (size_t)p->geo_ws_points * 8);
@@ -446,28 +493,12 @@ extern "C" enufft_status enufft_cell_geometry(enufft_plan_t p, const double *tri
   double2 *ws_u = vor ? (double2 *)p->geo_ws : nullptr;
   int32_t *ws_idx = vor ? (int32_t *)p->geo_ws_i : nullptr;
   int32_t *ws_slot = vor ? ws_idx + p->geo_ws_points : nullptr;
-  hipError_t e = hipSuccess;
-  int64_t c0 = 0;
-  while (c0 < p->n_cells && e == hipSuccess) {
-    int64_t c1 = c0, pts = 0;
-    int nbmax = 1;
-    while (c1 < p->n_cells) {
-      const int64_t q = p->offsets[c1 + 1] - p->offsets[c1];
-      if (c1 > c0 && pts + q > cap) break;
-      pts += q;
-      nbmax = std::max(nbmax, geo_bins(q));
-      ++c1;
-    }
-    const int nbl = vor ? std::min(kGeoMaxBins, nbmax + 1) : 0;
-    const size_t lds = vor ? (size_t)(nbl * nbl + 1) * sizeof(int) : 16;
-    if (p->prec == ENUFFT_F64)
-      e = geo_launch<double>(p, g, c0, c1, lds, tri, x, y, h, xb, yb, hb, wb, inside, info, counts, ws_u, ws_idx,
-                             ws_slot);
-    else
-      e = geo_launch<float>(p, g, c0, c1, lds, tri, x, y, h, xb, yb, hb, wb, inside, info, counts, ws_u, ws_idx,
-                            ws_slot);
-    c0 = c1;
-  }
+  if (p->prec == ENUFFT_F64)
+    e = geo_launch<double>(p, g, blocks, slice, lds, tri, x, y, h, xb, yb, hb, wb, inside, info, counts, ws_u, ws_idx,
+                           ws_slot);
+  else
+    e = geo_launch<float>(p, g, blocks, slice, lds, tri, x, y, h, xb, yb, hb, wb, inside, info, counts, ws_u, ws_idx,
+                          ws_slot);
   if (e != hipSuccess) {
     p->last_error = std::string("enufft_cell_geometry launch: ") + hipGetErrorString(e);
     p->faulted = true;

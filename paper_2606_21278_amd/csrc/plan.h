@@ -117,6 +117,7 @@ struct enufft_plan_s {
   // cell geometry (Voronoi weights): sorted sample copy (double2) and index + slot (2 x int32)
   void *geo_ws = nullptr, *geo_ws_i = nullptr;
   int64_t geo_ws_points = 0;
+  void *geo_order = nullptr;       // int32 cells, largest first
 
   // captured forward (type-1 + EMS) graph and the arguments it was captured with
   hipStream_t capture_stream = nullptr;
