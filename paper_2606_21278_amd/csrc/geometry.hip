@@ -401,12 +401,12 @@ enufft_status geo_fail(enufft_plan_t p, enufft_status st, const std::string &msg
 }
 
 template <typename T>
-hipError_t geo_launch(enufft_plan_t p, const GeoParams &g, int blocks, int64_t slice, size_t lds, const double *tri,
+hipError_t geo_launch(enufft_plan_t p, const GeoParams &g, const int32_t *order, int blocks, int64_t slice, size_t lds, const double *tri,
                       const void *x, const void *y, const void *h, void *xb, void *yb, void *hb, void *wb,
                       uint8_t *inside, double *info, int32_t *counts, double2 *ws_u, int32_t *ws_idx,
                       int32_t *ws_slot) {
   auto fn = geometry_kernel<T>;
-  hipLaunchKernelGGL(fn, dim3((unsigned)blocks), dim3(kGeoThreads), lds, p->stream, g, (const int32_t *)p->geo_order,
+  hipLaunchKernelGGL(fn, dim3((unsigned)blocks), dim3(kGeoThreads), lds, p->stream, g, order,
                      p->n_cells, p->d_counters + 6, p->d_counters + 7, slice, (const int64_t *)p->d_cell_off, tri,
                      (const T *)x, (const T *)y, (const T *)h, (T *)xb, (T *)yb, (T *)hb, (T *)wb, inside, info,
                      counts, ws_u, ws_idx, ws_slot);
@@ -456,20 +456,9 @@ extern "C" enufft_status enufft_cell_geometry(enufft_plan_t p, const double *tri
   int64_t largest = 0;
   for (int64_t c = 0; c < p->n_cells; ++c) largest = std::max(largest, p->offsets[c + 1] - p->offsets[c]);
   if (largest >= (int64_t(1) << 31)) return geo_fail(p, ENUFFT_EUNSUPPORTED, "cells of 2^31 points or more");
-  if (!p->geo_order) {
-    std::vector<int32_t> order((size_t)p->n_cells);
-    for (int64_t c = 0; c < p->n_cells; ++c) order[c] = (int32_t)c;
-    std::stable_sort(order.begin(), order.end(), [&](int32_t u, int32_t v) {
-      return p->offsets[u + 1] - p->offsets[u] > p->offsets[v + 1] - p->offsets[v];
-    });
-    st = geo_alloc(p, &p->geo_order, order.size() * sizeof(int32_t), "geometry cell order");
-    if (st != ENUFFT_OK) return st;
-    hipError_t e0 = hipMemcpy(p->geo_order, order.data(), order.size() * sizeof(int32_t), hipMemcpyHostToDevice);
-    if (e0 != hipSuccess) {
-      dev_release(p, &p->geo_order, order.size() * sizeof(int32_t));
-      return geo_fail(p, ENUFFT_EDEVICE, std::string("cell order upload: ") + hipGetErrorString(e0));
-    }
-  }
+  const int32_t *order = nullptr;
+  st = cells_largest_first(p, &order);
+  if (st != ENUFFT_OK) return st;
   // persistent workgroups: as many as are resident (the Voronoi bins take the LDS
   // of the largest cell's bin grid)
   const int nbl = vor ? std::min(kGeoMaxBins, geo_bins(largest) + 1) : 0;
@@ -494,10 +483,10 @@ extern "C" enufft_status enufft_cell_geometry(enufft_plan_t p, const double *tri
   int32_t *ws_idx = vor ? (int32_t *)p->geo_ws_i : nullptr;
   int32_t *ws_slot = vor ? ws_idx + p->geo_ws_points : nullptr;
   if (p->prec == ENUFFT_F64)
-    e = geo_launch<double>(p, g, blocks, slice, lds, tri, x, y, h, xb, yb, hb, wb, inside, info, counts, ws_u, ws_idx,
+    e = geo_launch<double>(p, g, order, blocks, slice, lds, tri, x, y, h, xb, yb, hb, wb, inside, info, counts, ws_u, ws_idx,
                            ws_slot);
   else
-    e = geo_launch<float>(p, g, blocks, slice, lds, tri, x, y, h, xb, yb, hb, wb, inside, info, counts, ws_u, ws_idx,
+    e = geo_launch<float>(p, g, order, blocks, slice, lds, tri, x, y, h, xb, yb, hb, wb, inside, info, counts, ws_u, ws_idx,
                           ws_slot);
   if (e != hipSuccess) {
     p->last_error = std::string("enufft_cell_geometry launch: ") + hipGetErrorString(e);

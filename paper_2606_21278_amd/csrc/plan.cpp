@@ -824,6 +824,27 @@ template FwdArgs<float> make_fwd_args<float>(enufft_plan_t, const void *, const 
 template FwdArgs<double> make_fwd_args<double>(enufft_plan_t, const void *, const void *, const void *, const void *,
                                                void *);
 
+enufft_status cells_largest_first(enufft_plan_t p, const int32_t **order) {
+  if (!p->cell_order) {
+    std::vector<int32_t> o((size_t)std::max<int64_t>(1, p->n_cells), 0);
+    for (int64_t c = 0; c < p->n_cells; ++c) o[c] = (int32_t)c;
+    std::stable_sort(o.begin(), o.begin() + p->n_cells, [&](int32_t u, int32_t v) {
+      return p->offsets[u + 1] - p->offsets[u] > p->offsets[v + 1] - p->offsets[v];
+    });
+    void *d = nullptr;
+    enufft_status st = dev_alloc(p, &d, o.size() * sizeof(int32_t), "cell order");
+    if (st != ENUFFT_OK) return st;
+    hipError_t e = hipMemcpy(d, o.data(), o.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      dev_release(p, &d, o.size() * sizeof(int32_t));
+      return hip_fail(p, e, "cell order upload");
+    }
+    p->cell_order = d;
+  }
+  *order = (const int32_t *)p->cell_order;
+  return ENUFFT_OK;
+}
+
 enufft_status check_plan(enufft_plan_t p, const char *fn) {
   if (!p) return fail(nullptr, ENUFFT_EINVAL, std::string(fn) + ": null plan");
   if (p->faulted) return fail(p, ENUFFT_ESTATE, std::string(fn) + ": plan unusable after a device fault");

@@ -117,7 +117,7 @@ struct enufft_plan_s {
   // cell geometry (Voronoi weights): sorted sample copy (double2) and index + slot (2 x int32)
   void *geo_ws = nullptr, *geo_ws_i = nullptr;
   int64_t geo_ws_points = 0;
-  void *geo_order = nullptr;       // int32 cells, largest first
+  void *cell_order = nullptr;      // int32 cells, largest first (geometry)
 
   // captured forward (type-1 + EMS) graph and the arguments it was captured with
   hipStream_t capture_stream = nullptr;
@@ -144,6 +144,8 @@ enufft_status install_fwd_schedule(enufft_plan_t p);
 enufft_status set_fwd_threads(enufft_plan_t p, int threads, size_t lds_limit);
 void adj_reset(enufft_plan_t p);
 enufft_status autotune(enufft_plan_t p);
+// Device array of the cells ordered by point count, largest first (built once).
+enufft_status cells_largest_first(enufft_plan_t p, const int32_t **order);
 enufft_status ems_units(enufft_plan_t p, const enufft_ems_params *prm, UnitTable **ut);
 // Large-cell path (fine grid in HBM).
 enufft_status big_prepare(enufft_plan_t p);

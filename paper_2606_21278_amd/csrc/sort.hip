@@ -140,6 +140,8 @@ extern "C" enufft_status enufft_sort_points(enufft_plan_t p, const void *x, cons
   if (p->n_cells == 0 || p->n_points == 0) return ENUFFT_OK;
   st = adj_prepare(p);   // device copy of the cell offsets
   if (st != ENUFFT_OK) return st;
+  // cells in their own order: largest first was slower (92.7 against 70 ms for 8e8 shuffled points in
+  // 20,480 cells), more large cells' output ranges being written at once
   hipError_t e = p->prec == ENUFFT_F64 ? launch_sort<double>(p, x, y, h, w, xs, ys, hs, ws, perm)
                                        : launch_sort<float>(p, x, y, h, w, xs, ys, hs, ws, perm);
   if (e != hipSuccess) {
