@@ -180,6 +180,21 @@ def bench_c4(args, torch, enf, synth, dev):
     prm = enf.EmsParams()
     Q = b.n_points
     N1, N2 = b.n_modes
+    sort_rec = None
+    if not args.no_sort:
+        # sorted once by tile: every later call's counting pass finds the order and skips
+        # its scatter
+        plan.sort_points(b.x, b.y, b.h, b.w)
+        torch.cuda.synchronize()
+        s0, s1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        s0.record(torch.cuda.current_stream())
+        xs, ys, hs, ws, _ = plan.sort_points(b.x, b.y, b.h, b.w)
+        s1.record(torch.cuda.current_stream())
+        torch.cuda.synchronize()
+        sort_rec = {"ms": s0.elapsed_time(s1), "note": "tile sort of the cell (enufft_sort_points), once, before "
+                                                        "timing; the timed calls run on the sorted copies"}
+        log("sort", sort_rec)
+        b.x, b.y, b.h, b.w = xs, ys, hs, ws
 
     def step():
         f = plan.type1(b.x, b.y, b.h, b.w)
@@ -229,7 +244,7 @@ def bench_c4(args, torch, enf, synth, dev):
                    "n_cells": 1, "n_points": Q, "modes": [N1, N2], "sigma": 2.0, "eps": b.eps,
                    "kernel_width": info["kernel_width"], "grid": info["grid"]},
         "type1_ms": t1, "ems_ms": tems, "adjoint_ms": tadj, "fwd_bwd_ms": ms_step,
-        "per_cell_loop": None, "roofline": roofline, "cpu_baseline": cpu,
+        "per_cell_loop": None, "roofline": roofline, "cpu_baseline": cpu, "sort": sort_rec,
     }
     print(json.dumps(out), flush=True)
 

@@ -145,6 +145,8 @@ struct BigSortArgs {
   int *unit_base;           // [ntiles + 1] first work unit of each tile; [ntiles] = units in all
   int *inv;                 // [n] sorted position of each input point
   T *xs, *ys, *hs, *ws;     // [n] points in tile order
+  int *chunk_fl;            // [nchunks][2] first tile, last tile (-1: tiles descend inside the chunk)
+  int *presorted;           // set when the input is already in tile order (NULL: always scatter)
 };
 
 template <typename T>
@@ -193,17 +195,35 @@ __device__ int big_block_scan(const int *cnt, O *out, int n, int *wsum) {
   return total;
 }
 
-// Tile histogram of each chunk, written in full.
+// Tile histogram of each chunk, written in full, and whether the chunk's tiles
+// never descend (its first and last tile, or -1 for the last when they do): the
+// tile scan concludes from these whether the whole input is in tile order.
 template <typename T>
 __global__ __launch_bounds__(BIG_SORT_THREADS) void big_count_kernel(BigSortArgs<T> a) {
-  extern __shared__ int hist[];
+  extern __shared__ int hist[];            // [ntiles], then the chunk's tiles [BIG_SORT_CHUNK]
+  int *tiles = hist + a.ntiles;
+  __shared__ int s_desc;
   for (int i = threadIdx.x; i < a.ntiles; i += blockDim.x) hist[i] = 0;
+  if (threadIdx.x == 0) s_desc = 0;
   __syncthreads();
   const int64_t s = (int64_t)blockIdx.x * BIG_SORT_CHUNK, e = min(a.n, s + BIG_SORT_CHUNK);
-  for (int64_t j = s + threadIdx.x; j < e; j += blockDim.x) atomicAdd(&hist[big_tile<T>(a, a.x[j], a.y[j])], 1);
+  const int cnt = (int)(e - s);
+  for (int64_t j = s + threadIdx.x; j < e; j += blockDim.x) {
+    const int t = big_tile<T>(a, a.x[j], a.y[j]);
+    tiles[j - s] = t;
+    atomicAdd(&hist[t], 1);
+  }
   __syncthreads();
+  int desc = 0;
+  for (int i = threadIdx.x; i + 1 < cnt; i += blockDim.x) desc |= tiles[i] > tiles[i + 1];
+  if (desc) s_desc = 1;
   int *row = a.chunk_hist + (int64_t)blockIdx.x * a.ntiles;
   for (int i = threadIdx.x; i < a.ntiles; i += blockDim.x) row[i] = hist[i];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    a.chunk_fl[2 * blockIdx.x] = tiles[0];
+    a.chunk_fl[2 * blockIdx.x + 1] = s_desc ? -1 : tiles[cnt - 1];
+  }
 }
 
 // Per tile, the sum over each group of BIG_SCAN_GROUP chunks.
@@ -221,9 +241,19 @@ __global__ __launch_bounds__(256) void big_group_sum_kernel(const int *chunk_his
 // its total; the tile offsets (exclusive scan of the totals); the number of
 // work units of each tile (the unit chunks its range touches) and their scan.
 __global__ __launch_bounds__(1024) void big_tile_scan_kernel(int *group_sum, int ngroups, int ntiles,
-                                                             int64_t *offsets, int *unit_base) {
+                                                             int64_t *offsets, int *unit_base, const int *chunk_fl,
+                                                             int nchunks, int *presorted) {
   extern __shared__ int tot[];   // [ntiles]
   __shared__ int wsum[16];
+  // the input is in tile order when no chunk descends inside and each chunk's
+  // last tile is at most the next chunk's first
+  int bad = 0;
+  for (int b = threadIdx.x; b < nchunks; b += blockDim.x) {
+    const int last = chunk_fl[2 * b + 1];
+    bad |= last < 0 || (b + 1 < nchunks && last > chunk_fl[2 * (b + 1)]);
+  }
+  bad = __syncthreads_or(bad);
+  if (threadIdx.x == 0 && presorted) *presorted = bad ? 0 : 1;
   for (int t = threadIdx.x; t < ntiles; t += blockDim.x) {
     int run = 0;
     for (int g = 0; g < ngroups; ++g) {
@@ -277,6 +307,7 @@ constexpr int big_scatter_sub() { return sizeof(T) == 4 ? 4096 : 2048; }
 
 template <typename T>
 __global__ __launch_bounds__(BIG_SORT_THREADS) void big_scatter_kernel(BigSortArgs<T> a) {
+  if (a.presorted && *a.presorted) return;   // the tile ranges are the input's own: nothing to move
   using V4 = typename vec4<T>::type;
   constexpr int SUB = big_scatter_sub<T>();
   extern __shared__ __align__(32) unsigned char sm_raw[];
@@ -353,6 +384,8 @@ __global__ __launch_bounds__(BIG_SORT_THREADS) void big_scatter_kernel(BigSortAr
 template <typename T>
 struct BigTileArgs {
   const T *xs, *ys, *hs, *ws;
+  const T *xi, *yi, *hi, *wi;   // the input points (read instead when *presorted)
+  const int *presorted;
   const int64_t *offsets;    // [ntiles + 1]
   const int *unit_base;      // [ntiles + 1]; [ntiles] = number of units
   int ntiles, ntx;
@@ -416,13 +449,15 @@ __global__ __launch_bounds__(BIG_SPREAD_THREADS) void big_spread_kernel(BigTileA
   const double *wn = a.windows + 3 * a.cell;
   const T cx = T(wn[0]), cy = T(wn[1]), R = T(wn[2]);
   const T pr = R > T(0) ? T(M_PI) / R : T(0);
+  const bool pre = *a.presorted;
+  const T *X = pre ? a.xi : a.xs, *Y = pre ? a.yi : a.ys, *Hh = pre ? a.hi : a.hs, *Wq = pre ? a.wi : a.ws;
   big_units<T>(a, &s_unit, [&](int t, int64_t lo, int64_t hi, int u) {
     for (int i = threadIdx.x; i < S * S; i += blockDim.x) sub[i] = 0.0;
     __syncthreads();
     const int tx0 = (t % a.ntx) * BIG_TS, ty0 = (t / a.ntx) * BIG_TS;
     for (int64_t k = lo + threadIdx.x; k < hi; k += blockDim.x) {
-      const T xj = a.xs[k], yj = a.ys[k];
-      const T cj = a.ws[k] * a.hs[k] * hann_w(a.window_kind, xj, yj, cx, cy, R, pr);
+      const T xj = X[k], yj = Y[k];
+      const T cj = Wq[k] * Hh[k] * hann_w(a.window_kind, xj, yj, cx, cy, R, pr);
       const FineCoord<T> fx = fine_coord<T>(xj, a.s1h, a.s1l, halfw);
       const FineCoord<T> fy = fine_coord<T>(yj, a.s2h, a.s2l, halfw);
       const int lx = big_local(fx.i0 & (g.n1 - 1), tx0, g.n1);
@@ -971,6 +1006,8 @@ __global__ __launch_bounds__(256) void big_gather_kernel(BigTileArgs<T> a) {
   const double *wn = a.windows + 3 * a.cell;
   const T cx = T(wn[0]), cy = T(wn[1]), R = T(wn[2]);
   const T pr = R > T(0) ? T(M_PI) / R : T(0);
+  const bool pre = *a.presorted;
+  const T *X = pre ? a.xi : a.xs, *Y = pre ? a.yi : a.ys, *Hh = pre ? a.hi : a.hs, *Wq = pre ? a.wi : a.ws;
   big_units<T>(a, &s_unit, [&](int t, int64_t lo, int64_t hi, int) {
     const int tx0 = (t % a.ntx) * BIG_TS, ty0 = (t / a.ntx) * BIG_TS;
     for (int i = threadIdx.x; i < S * S; i += blockDim.x) {
@@ -979,7 +1016,7 @@ __global__ __launch_bounds__(256) void big_gather_kernel(BigTileArgs<T> a) {
     }
     __syncthreads();
     for (int64_t k = lo + threadIdx.x; k < hi; k += blockDim.x) {
-      const T xj = a.xs[k], yj = a.ys[k];
+      const T xj = X[k], yj = Y[k];
       const FineCoord<T> fx = fine_coord<T>(xj, a.s1h, a.s1l, halfw);
       const FineCoord<T> fy = fine_coord<T>(yj, a.s2h, a.s2l, halfw);
       const int lx = big_local(fx.i0 & (g.n1 - 1), tx0, g.n1);
@@ -1019,7 +1056,7 @@ __global__ __launch_bounds__(256) void big_gather_kernel(BigTileArgs<T> a) {
       }
       T dWx, dWy;
       const T Wv = hann_wg(a.window_kind, xj, yj, cx, cy, R, pr, dWx, dWy);
-      const T wj = a.ws[k], wh = wj * a.hs[k];
+      const T wj = Wq[k], wh = wj * Hh[k];
       V4 o;
       o.x = wj * Wv * u;
       o.y = wh * (dWx * u + Wv * ux);
@@ -1035,7 +1072,8 @@ __global__ __launch_bounds__(256) void big_gather_kernel(BigTileArgs<T> a) {
 // (at its sorted position) and coalesced writes of the three outputs.
 template <typename T>
 __global__ __launch_bounds__(256) void big_unpermute_kernel(const typename vec4<T>::type *gout, const int *inv,
-                                                            int64_t n, T *gh, T *gx, T *gy) {
+                                                            const int *presorted, int64_t n, T *gh, T *gx, T *gy) {
+  const bool pre = *presorted;   // sorted order is the input order
   // U points per thread and round, all loads of a round before its stores (the
   // stores could alias the records as far as the compiler knows, so a store
   // between loads would serialise them)
@@ -1048,7 +1086,7 @@ __global__ __launch_bounds__(256) void big_unpermute_kernel(const typename vec4<
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int64_t j = j0 + u * stride;
-      k[u] = j < n ? inv[j] : -1;
+      k[u] = j < n ? (pre ? (int)j : inv[j]) : -1;
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
@@ -1063,6 +1101,14 @@ __global__ __launch_bounds__(256) void big_unpermute_kernel(const typename vec4<
       if (gx) gx[j] = v[u].y;
       if (gy) gy[j] = v[u].z;
     }
+  }
+}
+
+// perm[inv[j]] = base + j: the input index of each sorted position.
+__global__ __launch_bounds__(256) void big_perm_kernel(const int *inv, int64_t n, int32_t base, int32_t *perm) {
+  for (int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x; j < n; j += (int64_t)gridDim.x * 256) {
+    const int k = inv[j];
+    if (k >= 0 && k < n) perm[k] = base + (int32_t)j;
   }
 }
 
@@ -1085,13 +1131,15 @@ size_t sort_lds(int ntiles) {
   return (size_t)big_scatter_sub<T>() * sizeof(typename vec4<T>::type) + (size_t)3 * ntiles * sizeof(int);
 }
 
+size_t count_lds(int ntiles) { return ((size_t)ntiles + BIG_SORT_CHUNK) * sizeof(int); }
+
 template <typename T>
 hipError_t set_attrs_t(int n1, int n2, int ntiles) {
   const size_t el = sizeof(T);
   auto set = [](const void *fn, size_t bytes) {
     return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
   };
-  hipError_t e = set((const void *)&big_count_kernel<T>, (size_t)ntiles * sizeof(int));
+  hipError_t e = set((const void *)&big_count_kernel<T>, count_lds(ntiles));
   if (e == hipSuccess) e = set((const void *)&big_scatter_kernel<T>, sort_lds<T>(ntiles));
   if (e == hipSuccess) e = set((const void *)&big_tile_scan_kernel, (size_t)ntiles * sizeof(int));
   if (e == hipSuccess) e = set((const void *)&big_rows_kernel<T>, 4 * (size_t)n1 * el);
@@ -1116,16 +1164,17 @@ BigSortArgs<T> sort_args(enufft_plan_t p, int64_t c, const T *x, const T *y, con
   a.chunk_hist = p->big_chunk_hist; a.group_sum = p->big_group_sum;
   a.offsets = p->big_offsets; a.unit_base = p->big_unit_base; a.inv = p->big_inv;
   a.xs = (T *)p->big_xs; a.ys = (T *)p->big_ys; a.hs = (T *)p->big_hs; a.ws = (T *)p->big_ws;
+  a.chunk_fl = p->big_chunk_fl;
+  a.presorted = p->big_flags;
   return a;
 }
 
 // Sort the points of cell c (n > 0) by tile into the plan's buffers: chunk
 // histograms, group sums, the tile scan, chunk starts, scatter.
 template <typename T>
-hipError_t sort_cell(enufft_plan_t p, int64_t c, const T *x, const T *y, const T *h, const T *w) {
-  const BigSortArgs<T> a = sort_args<T>(p, c, x, y, h, w);
+hipError_t sort_launch(enufft_plan_t p, const BigSortArgs<T> &a) {
   const dim3 tg((a.ntiles + 255) / 256, a.ngroups);
-  hipLaunchKernelGGL((big_count_kernel<T>), dim3(a.nchunks), dim3(BIG_SORT_THREADS), (size_t)a.ntiles * sizeof(int),
+  hipLaunchKernelGGL((big_count_kernel<T>), dim3(a.nchunks), dim3(BIG_SORT_THREADS), count_lds(a.ntiles),
                      p->stream, a);
   hipError_t e = hipGetLastError();
   if (e == hipSuccess) {
@@ -1135,7 +1184,8 @@ hipError_t sort_cell(enufft_plan_t p, int64_t c, const T *x, const T *y, const T
   }
   if (e == hipSuccess) {
     hipLaunchKernelGGL(big_tile_scan_kernel, dim3(1), dim3(1024), (size_t)a.ntiles * sizeof(int), p->stream,
-                       a.group_sum, a.ngroups, a.ntiles, a.offsets, a.unit_base);
+                       a.group_sum, a.ngroups, a.ntiles, a.offsets, a.unit_base, (const int *)a.chunk_fl, a.nchunks,
+                       a.presorted);
     e = hipGetLastError();
   }
   if (e == hipSuccess) {
@@ -1152,9 +1202,17 @@ hipError_t sort_cell(enufft_plan_t p, int64_t c, const T *x, const T *y, const T
 }
 
 template <typename T>
-BigTileArgs<T> tile_args(enufft_plan_t p, int64_t c) {
+hipError_t sort_cell(enufft_plan_t p, int64_t c, const T *x, const T *y, const T *h, const T *w) {
+  return sort_launch<T>(p, sort_args<T>(p, c, x, y, h, w));
+}
+
+template <typename T>
+BigTileArgs<T> tile_args(enufft_plan_t p, int64_t c, const T *x, const T *y, const T *h, const T *w) {
   BigTileArgs<T> a{};
   a.xs = (const T *)p->big_xs; a.ys = (const T *)p->big_ys; a.hs = (const T *)p->big_hs; a.ws = (const T *)p->big_ws;
+  const int64_t a0 = p->offsets[c];
+  a.xi = x + a0; a.yi = y + a0; a.hi = h + a0; a.wi = w + a0;
+  a.presorted = p->big_flags;
   a.offsets = p->big_offsets;
   a.unit_base = p->big_unit_base;
   a.ntiles = p->big_ntx * p->big_nty;
@@ -1255,7 +1313,7 @@ enufft_status type1_t(enufft_plan_t p, const T *x, const T *y, const T *h, const
     } else {
       e = sort_cell<T>(p, c, x, y, h, w);
       if (e == hipSuccess) {
-        BigTileArgs<T> a = tile_args<T>(p, c);
+        BigTileArgs<T> a = tile_args<T>(p, c, x, y, h, w);
         a.partial = p->big_partial;
         a.work_counter = p->big_work;
         a.done_counter = p->big_work + 1;
@@ -1308,7 +1366,7 @@ enufft_status adjoint_t(enufft_plan_t p, const T *x, const T *y, const T *h, con
       e = hipGetLastError();
     }
     if (e == hipSuccess) {
-      BigTileArgs<T> a = tile_args<T>(p, c);
+      BigTileArgs<T> a = tile_args<T>(p, c, x, y, h, w);
       a.G4 = (const V4 *)p->big_gu;
       a.gout = (V4 *)p->big_gout;
       a.work_counter = p->big_work + 2;
@@ -1318,7 +1376,7 @@ enufft_status adjoint_t(enufft_plan_t p, const T *x, const T *y, const T *h, con
     if (e == hipSuccess) {
       const int blocks = (int)std::min<int64_t>(8192, (n + 255) / 256);
       hipLaunchKernelGGL((big_unpermute_kernel<T>), dim3(blocks), dim3(256), 0, p->stream, (const V4 *)p->big_gout,
-                         (const int *)p->big_inv, n, gh ? gh + a0 : nullptr, gx ? gx + a0 : nullptr,
+                         (const int *)p->big_inv, (const int *)p->big_flags, n, gh ? gh + a0 : nullptr, gx ? gx + a0 : nullptr,
                          gy ? gy + a0 : nullptr);
       e = hipGetLastError();
     }
@@ -1375,6 +1433,8 @@ enufft_status big_prepare(enufft_plan_t p) {
       {(void **)&p->big_offsets, (size_t)(ntiles + 1) * sizeof(int64_t), "tile offsets"},
       {(void **)&p->big_unit_base, (size_t)(ntiles + 1) * sizeof(int), "tile unit offsets"},
       {(void **)&p->big_inv, (size_t)q1 * sizeof(int), "inverse permutation"},
+      {(void **)&p->big_chunk_fl, (size_t)(nchunks * 2) * sizeof(int), "chunk tile bounds"},
+      {(void **)&p->big_flags, 4 * sizeof(int), "input order flag"},
       {(void **)&p->big_partial, (size_t)(p->big_units_max * S * S) * sizeof(double), "unit sub-grids"},
       {&p->big_gout, (size_t)q1 * 4 * el, "sorted-order gradients"},
       {&p->big_xs, (size_t)q1 * el, "sorted x"},
@@ -1405,6 +1465,41 @@ enufft_status big_prepare(enufft_plan_t p) {
   if (e == hipSuccess) e = p->prec == ENUFFT_F64 ? gather_attrs<double>() : gather_attrs<float>();
   if (e == hipSuccess) e = hipDeviceSynchronize();
   return big_fail(p, e, "large-cell workspace");
+}
+
+namespace {
+template <typename T>
+enufft_status sort_points_t(enufft_plan_t p, const T *x, const T *y, const T *h, const T *w, T *xs, T *ys, T *hs,
+                            T *ws, int32_t *perm) {
+  for (int64_t c = 0; c < p->n_cells; ++c) {
+    const int64_t a0 = p->offsets[c], n = p->offsets[c + 1] - a0;
+    if (n == 0) continue;
+    // the scatter writes straight into the caller's arrays (the plan's buffers
+    // stand in for outputs not asked for); always scatter, sorted input or not
+    BigSortArgs<T> a = sort_args<T>(p, c, x, y, h, w ? w : x);
+    a.presorted = nullptr;
+    a.xs = xs + a0; a.ys = ys + a0;
+    a.hs = hs ? hs + a0 : (T *)p->big_hs;
+    a.ws = ws ? ws + a0 : (T *)p->big_ws;
+    hipError_t e = sort_launch<T>(p, a);
+    if (e == hipSuccess && perm) {
+      hipLaunchKernelGGL(big_perm_kernel, dim3((unsigned)std::min<int64_t>(8192, (n + 255) / 256)), dim3(256), 0,
+                         p->stream, (const int *)p->big_inv, n, (int32_t)a0, perm + a0);
+      e = hipGetLastError();
+    }
+    if (e != hipSuccess) return big_fail(p, e, "large-cell point sort");
+  }
+  return ENUFFT_OK;
+}
+}  // namespace
+
+enufft_status big_sort_points(enufft_plan_t p, const void *x, const void *y, const void *h, const void *w, void *xs,
+                              void *ys, void *hs, void *ws, int32_t *perm) {
+  if (p->prec == ENUFFT_F64)
+    return sort_points_t<double>(p, (const double *)x, (const double *)y, (const double *)h, (const double *)w,
+                                 (double *)xs, (double *)ys, (double *)hs, (double *)ws, perm);
+  return sort_points_t<float>(p, (const float *)x, (const float *)y, (const float *)h, (const float *)w, (float *)xs,
+                              (float *)ys, (float *)hs, (float *)ws, perm);
 }
 
 enufft_status big_type1(enufft_plan_t p, const void *x, const void *y, const void *h, const void *w, void *f,

@@ -103,6 +103,8 @@ struct enufft_plan_s {
   int64_t *big_offsets = nullptr;            // [tiles + 1] tile ranges of the sorted order
   int *big_unit_base = nullptr;              // [tiles + 1] first work unit of each tile
   int *big_inv = nullptr;                    // [largest cell] sorted position of each input point
+  int *big_chunk_fl = nullptr;               // [chunks][2] first and last tile of each sort chunk
+  int *big_flags = nullptr;                  // [0]: the current cell's input is already in tile order
   void *big_xs = nullptr, *big_ys = nullptr, *big_hs = nullptr, *big_ws = nullptr;
   double *big_partial = nullptr;             // [units][S x S] FP64 sub-grids of the spreading units
   int64_t big_units_max = 0;
@@ -153,6 +155,8 @@ enufft_status big_type1(enufft_plan_t p, const void *x, const void *y, const voi
                         int64_t c0, int64_t c1);
 enufft_status big_adjoint(enufft_plan_t p, const void *x, const void *y, const void *h, const void *w,
                           const void *fin, const uint8_t *keep, const double *lam, void *gh, void *gx, void *gy);
+enufft_status big_sort_points(enufft_plan_t p, const void *x, const void *y, const void *h, const void *w, void *xs,
+                              void *ys, void *hs, void *ws, int32_t *perm);
 enufft_status big_ems(enufft_plan_t p, const void *f, const enufft_ems_params *prm, const double *mode_weight,
                       uint8_t *keep, int32_t *k_star, double *stats, const UnitTable *ut, int64_t cell_begin,
                       int64_t cell_count);

@@ -89,8 +89,7 @@ def test_sorted_gradients_map_back():
 
 
 def test_sort_edge_cases():
-    """Empty cells and a one-point cell, optional outputs, argument checks, and the
-    large-cell plans that refuse."""
+    """Empty cells and a one-point cell, optional outputs, argument checks."""
     b = synth.uniform_box(counts=[0, 1, 3000, 0, 800], n_modes=(32, 32), precision="f32", window_radius=2.5)
     gb = gpu_batch(b)
     off = gb.cell_offsets
@@ -111,9 +110,40 @@ def test_sort_edge_cases():
     with pytest.raises(enf.EnufftError):
         enf._check(plan._lib.enufft_sort_points(plan._h, enf._ptr(x), enf._ptr(y), None, None, None, enf._ptr(ys),
                                                 None, None, None), plan._h)
-    big = synth.config4(Q=2000, precision="f32", n_modes=(128, 96))
-    gbb = gpu_batch(big)
-    pb = make_plan(gbb)
-    with pytest.raises(enf.EnufftError) as e:
-        pb.sort_points(gbb.x, gbb.y)
-    assert e.value.status == enf.EUNSUPPORTED
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_large_cell_sorted_input(prec):
+    """Large cells: sorted by tile, the input lets type-1 and the adjoint skip their
+    scatter (each call's counting pass finds the order) with the same results; one pair of
+    far-apart samples swapped makes the order fail the check and the full sort runs."""
+    b = synth.config4(Q=30000, precision=prec, n_modes=(128, 96))
+    if prec == "f64":
+        b.eps = 1e-10
+    gb = gpu_batch(b)
+    plan = make_plan(gb)
+    f0 = plan.type1(gb.x, gb.y, gb.h, gb.w)
+    xs, ys, hs, ws, perm = plan.sort_points(gb.x, gb.y, gb.h, gb.w)
+    f1 = plan.type1(xs, ys, hs, ws)
+    keep = torch.ones(f0.shape, dtype=torch.uint8, device="cuda:0")
+    g0 = plan.retained_power_adjoint(gb.x, gb.y, gb.h, gb.w, f0, keep)
+    g1 = plan.retained_power_adjoint(xs, ys, hs, ws, f0, keep)
+    # a swap between the first and the last sorted sample
+    i, j = 0, gb.n_points - 1
+    xw, yw, hw, ww = xs.clone(), ys.clone(), hs.clone(), ws.clone()
+    for t in (xw, yw, hw, ww):
+        t[[i, j]] = t[[j, i]]
+    f2 = plan.type1(xw, yw, hw, ww)
+    torch.cuda.synchronize()
+    x, xsn = gb.x.cpu().numpy(), xs.cpu().numpy()
+    assert np.array_equal(np.sort(perm.cpu().numpy()), np.arange(gb.n_points))
+    assert np.array_equal(xsn, x[perm.cpu().numpy()])
+    lim = 1e-6 if prec == "f32" else 1e-13
+    assert rel_l2(f1.cpu().numpy(), f0.cpu().numpy()) <= lim
+    assert rel_l2(f2.cpu().numpy(), f0.cpu().numpy()) <= lim
+    assert rel_l2(f0.cpu().numpy(), oracle_f(b)) <= TOL[prec]
+    p = perm.long()
+    for a, s in zip(g0, g1):
+        back = torch.empty_like(s)
+        back[p] = s
+        assert rel_l2(back.cpu().numpy(), a.cpu().numpy()) <= lim
