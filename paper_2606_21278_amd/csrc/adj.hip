@@ -663,23 +663,33 @@ __host__ __device__ inline Adj1Layout adj1_layout(const Geom &g, int W, size_t e
   return L;
 }
 
-// Derivative taps from the mirror-pair polynomials: tap d is E + u O and, the
-// derivative of an even kernel being odd, tap W - 1 - d is u O - E.
+// Taps and their derivatives with respect to the fine coordinate t from the
+// mirror-pair polynomials of the taps alone (no second set of coefficients, so
+// the kernel's scalar registers hold one table).  With P_d(u) = E(s) + u O(s),
+// s = u^2 and u = 2 v - 1 = 2 (i0 - t + W/2) - 1: dP_d/dt = -2 dP_d/du =
+// -2 (O + 2 u (E' + u O')), and the mirror tap W - 1 - d, E - u O, has
+// -2 (-O + 2 u (E' - u O')); E' and O' (d/ds) come out of the same Horner steps.
 template <int W>
-__device__ __forceinline__ void es_dtaps_poly_v(float v, const EsPoly &cf, float (&out)[W]) {
+__device__ __forceinline__ void es_taps_dtaps_poly_v(float v, const EsPoly &cf, float (&out)[W],
+                                                     float (&dout)[W]) {
   const float u = 2.0f * v - 1.0f;
   const float s = u * u;
 #pragma unroll
   for (int d = 0; d < W / 2; ++d) {
     const float *cd = cf.c + d * (ES_DEG + 1);
-    float e = cd[ES_DEG - 1], o = cd[ES_DEG];
+    float e = cd[ES_DEG - 1], o = cd[ES_DEG], de = 0.0f, dO = 0.0f;
 #pragma unroll
     for (int k = ES_DEG - 3; k >= 0; k -= 2) {
+      de = fmaf(de, s, e);
+      dO = fmaf(dO, s, o);
       e = fmaf(e, s, cd[k]);
       o = fmaf(o, s, cd[k + 1]);
     }
     out[d] = fmaf(u, o, e);
-    out[W - 1 - d] = fmaf(u, o, -e);
+    out[W - 1 - d] = fmaf(-u, o, e);
+    const float u2 = 2.0f * u;
+    dout[d] = -2.0f * fmaf(u2, fmaf(u, dO, de), o);
+    dout[W - 1 - d] = -2.0f * fmaf(u2, fmaf(-u, dO, de), -o);
   }
 }
 
@@ -695,10 +705,8 @@ __device__ __forceinline__ void gather1_point(const AdjArgs<float> &a, const flo
   const FineCoord<float> fy = fine_coord<float>(yj, a.s2_hi, a.s2_lo, halfw);
   const float vx = tap_v(fx, halfw), vy = tap_v(fy, halfw);
   float kx[W], kxd[W], ky[W], kyd[W];
-  es_taps_poly_v<W>(vx, a.es, kx);
-  es_dtaps_poly_v<W>(vx, a.esd, kxd);
-  es_taps_poly_v<W>(vy, a.es, ky);
-  es_dtaps_poly_v<W>(vy, a.esd, kyd);
+  es_taps_dtaps_poly_v<W>(vx, a.es, kx, kxd);
+  es_taps_dtaps_poly_v<W>(vy, a.es, ky, kyd);
   const float *p = G + (fy.i0 & (g.n2 - 1)) * apitch + (fx.i0 & (g.n1 - 1));
   float u = 0.0f, ux = 0.0f, uy = 0.0f;
 #pragma unroll
@@ -1127,7 +1135,6 @@ enufft_status adjoint_common(enufft_plan_t p, const char *fn, const void *x, con
     a.decon_x = (const float *)p->d_adj1_decon_x;
     a.decon_y = (const float *)p->d_adj1_decon_y;
     a.es = p->adj1_es;
-    a.esd = p->adj1_esd;
     a.dsx = (float)(p->n1 / (2.0 * M_PI));
     a.dsy = (float)(p->n2 / (2.0 * M_PI));
     a.bands = 1;

@@ -86,8 +86,7 @@ struct AdjArgs {
   const T *tw1, *tw2;          // forward twiddles (the inverse uses their conjugates)
   T beta;
   T s1_hi, s1_lo, s2_hi, s2_lo;
-  EsPoly es;                   // as in FwdArgs
-  EsPoly esd;                  // single-grid adjoint: derivative taps d/dt
+  EsPoly es;                   // as in FwdArgs (the single-grid adjoint: its own kernel's taps)
   T dsx, dsy;                  // single-grid adjoint: n1 / (2 pi), n2 / (2 pi)
   int vec4;                    // x, y, h, w are 16-byte aligned: load runs of 4 points
   int bands, band_rows;        // row bands per cell and rows per band

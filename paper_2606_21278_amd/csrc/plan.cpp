@@ -260,10 +260,21 @@ double fit_es_poly(int W, double beta, int deg, std::vector<double> &coef) {
   return fit_tap_poly(W, deg, [&](int, double z) { return kernel_host(z, beta); }, coef);
 }
 
-// The taps' derivatives with respect to the fine coordinate t: d/dt psi((i0 + d - t) 2 / W)
-// = -(2 / W) psi'(z).
-double fit_es_dpoly(int W, double beta, int deg, std::vector<double> &coef) {
-  return fit_tap_poly(W, deg, [&](int, double z) { return -(2.0 / W) * kernel_deriv_host(z, beta); }, coef);
+// Largest deviation of the fitted taps' derivatives with respect to the fine coordinate t,
+// -2 dP_d/du (u = 2 v - 1, v = i0 - t + W/2), from d/dt psi((i0 + d - t) 2 / W) = -(2 / W) psi'(z).
+double tap_deriv_error(int W, double beta, int deg, const std::vector<double> &coef) {
+  double maxerr = 0.0;
+  for (int d = 0; d < W; ++d) {
+    const double *c = coef.data() + (size_t)d * (deg + 1);
+    for (int i = 0; i <= 2000; ++i) {
+      const double v = i / 2000.0, u = 2.0 * v - 1.0;
+      double dp = deg * c[deg];
+      for (int k = deg - 1; k >= 1; --k) dp = dp * u + k * c[k];
+      const double want = -(2.0 / W) * kernel_deriv_host((v + d - 0.5 * W) * 2.0 / W, beta);
+      maxerr = std::max(maxerr, std::fabs(-2.0 * dp - want));
+    }
+  }
+  return maxerr;
 }
 
 int64_t alloc_cap_bytes() {
@@ -574,9 +585,10 @@ enufft_status enufft_plan(enufft_plan_t *out, int64_t n_cells, const int64_t *ce
         kernel_params(opts->eps, sigma_eff, Wa, &Wt, &ba);
         if (Wt != Wa) ba = 0.0;
       }
-      std::vector<double> cf, cd;
+      std::vector<double> cf;
       const double e0 = ba != 0.0 ? fit_es_poly(Wa, ba, enufft::ES_DEG, cf) : 1.0;
-      const double e1 = ba != 0.0 ? fit_es_dpoly(Wa, ba, enufft::ES_DEG, cd) : 1.0;
+      // the kernel takes the derivative taps from the same polynomials
+      const double e1 = ba != 0.0 ? tap_deriv_error(Wa, ba, enufft::ES_DEG, cf) : 1.0;
       if (e0 <= std::max(0.1 * opts->eps, 1e-6) && e1 <= std::max(opts->eps, 1e-5)) {
         p->adj1 = true;
         p->adj1_avail = true;
@@ -585,11 +597,7 @@ enufft_status enufft_plan(enufft_plan_t *out, int64_t n_cells, const int64_t *ce
         p->adj1_poly_err = e0;
         p->adj1_dpoly_err = e1;
         p->adj1_es.on = 1;
-        p->adj1_esd.on = 1;
-        for (size_t i = 0; i < (size_t)(Wa / 2) * (enufft::ES_DEG + 1); ++i) {
-          p->adj1_es.c[i] = (float)cf[i];
-          p->adj1_esd.c[i] = (float)cd[i];
-        }
+        for (size_t i = 0; i < (size_t)(Wa / 2) * (enufft::ES_DEG + 1); ++i) p->adj1_es.c[i] = (float)cf[i];
       }
     }
   }

@@ -63,7 +63,7 @@ struct enufft_plan_s {
   bool adj1_avail = false;           // its kernel and tables are set up
   int adj1_W = 0;
   double adj1_beta = 0.0;
-  enufft::EsPoly adj1_es{}, adj1_esd{};   // taps and their derivatives d/dt (t in grid cells)
+  enufft::EsPoly adj1_es{};        // taps (their derivatives d/dt come from the same polynomials)
   double adj1_poly_err = 0.0, adj1_dpoly_err = 0.0;
   void *d_adj1_decon_x = nullptr, *d_adj1_decon_y = nullptr;
   std::vector<enufft::AdjItem> adj1_items;
