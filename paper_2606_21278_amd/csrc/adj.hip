@@ -738,51 +738,34 @@ __device__ __forceinline__ void gather1_point(const AdjArgs<float> &a, const flo
   }
 }
 
-// All points of one item, in the order of gather_item (wave w: blocks of 256
-// consecutive points, lane l the points l, l + 64, l + 128, l + 192 of a
-// block); the loads run one block ahead in two register buffers.
+// All points of one item: wave w takes blocks of 64 consecutive points, one per
+// lane (so the 64 lanes of a step read overlapping footprints of raster-ordered
+// points); each lane's next point is loaded while the current one is gathered.
+// (Four points per lane and block, picked by a run-time index, had put the
+// buffers in scratch memory: 16 bytes per point written and read back.)
 template <int W, int NT>
 __device__ __forceinline__ void gather1_item(const AdjArgs<float> &a, const float *G, int apitch, int64_t begin,
                                              int64_t end, float cx, float cy, float R) {
   const float pr = R > 0.0f ? float(M_PI) / R : 0.0f;
-  constexpr int U = 4, BLK = 64 * U, NWV = NT / 64;
-  struct Pts {
-    float x[U], y[U], h[U], w[U];
-  };
+  constexpr int NWV = NT / 64;
   const int lane = threadIdx.x & 63;
-  const int64_t stride = (int64_t)NWV * BLK;
-  auto load = [&](Pts &b, int64_t pb) {
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int64_t i = pb + u * 64 + lane;
-      const int64_t ic = i < end ? i : end - 1;   // past the end: re-read the last point (unused)
-      b.x[u] = a.x[ic]; b.y[u] = a.y[ic]; b.h[u] = a.h[ic]; b.w[u] = a.w[ic];
-    }
+  const int64_t stride = (int64_t)NWV * 64;
+  struct Pt {
+    float x, y, h, w;
   };
-  // one copy of the point code (its taps and row sums are not interleaved
-  // across the U points, which would multiply the registers they hold)
-  auto pick = [](const float (&v)[U], int u) {
-    float r = v[0];
-#pragma unroll
-    for (int k = 1; k < U; ++k) r = u == k ? v[k] : r;
-    return r;
-  };
-  auto step = [&](const Pts &b, int64_t pb) {
-#pragma unroll 1
-    for (int u = 0; u < U; ++u) {
-      const int64_t i = pb + u * 64 + lane;
-      if (i < end) gather1_point<W>(a, G, apitch, i, pick(b.x, u), pick(b.y, u), pick(b.h, u), pick(b.w, u), cx, cy, R, pr);
-    }
+  auto load = [&](Pt &b, int64_t i) {
+    const int64_t ic = i < end ? i : end - 1;   // past the end: re-read the last point (unused)
+    b.x = a.x[ic]; b.y = a.y[ic]; b.h = a.h[ic]; b.w = a.w[ic];
   };
   if (begin >= end) return;
-  int64_t p = begin + (int64_t)(threadIdx.x >> 6) * BLK;
-  Pts b0, b1;
-  load(b0, p);
-  for (; p < end; p += 2 * stride) {
-    load(b1, p + stride);
-    step(b0, p);
-    load(b0, p + 2 * stride);
-    step(b1, p + stride);
+  int64_t i = begin + (int64_t)(threadIdx.x >> 6) * 64 + lane;
+  Pt b0, b1;
+  load(b0, i);
+  for (; i - lane < end; i += 2 * stride) {
+    load(b1, i + stride);
+    if (i < end) gather1_point<W>(a, G, apitch, i, b0.x, b0.y, b0.h, b0.w, cx, cy, R, pr);
+    load(b0, i + 2 * stride);
+    if (i + stride < end) gather1_point<W>(a, G, apitch, i + stride, b1.x, b1.y, b1.h, b1.w, cx, cy, R, pr);
   }
 }
 
