@@ -642,25 +642,83 @@ struct Adj1Layout {
   int rows;      // grid rows stored: n2 + W (the first W - 1 repeated after the last)
   int apitch;    // row pitch: n1 + W - 1 rounded up to even (first W - 1 columns repeated)
   int cpitch;    // column-workspace pitch
+  int rsplit;    // compact layout: rows [rsplit, n2) are transformed in the staged batch; 0: not compact
   size_t g_off, ws_off, st_off, db_off, tw_off, total;   // element offsets
 };
 
-__host__ __device__ inline Adj1Layout adj1_layout(const Geom &g, int W, size_t elem) {
+// The column output db ([n2][K1 + 1] complex) must not overlap the column
+// workspace while the column pass writes it.  Compact layout: db ends where the
+// grid does, so it shares the grid's last rows; the row transforms then run in
+// two batches, rows [0, rsplit) (which lie below db) and rows [rsplit, n2), whose
+// first step loads every input before any store (at most one item per thread of
+// the NT-thread workgroup).  Otherwise db follows the grid.
+__host__ __device__ inline Adj1Layout adj1_layout(const Geom &g, int W, size_t elem, int NT) {
   Adj1Layout L;
   L.rows = g.n2 + W;
   L.apitch = (g.n1 + W - 1 + 1) & ~1;
   L.cpitch = 2 * (g.K1 + 1) + 2;
   L.g_off = 0;
   // the column workspace and the staged spectrum alias the grid (both are dead
-  // before the row transforms write it); the column output db does not
+  // before the row transforms write it)
   L.ws_off = 0;
   const size_t ws = (size_t)g.n2 * L.cpitch;
   L.st_off = ws;
   const size_t gsz = (size_t)L.rows * L.apitch, wst = ws + adj_stage_elems(g, elem);
-  L.db_off = gsz > wst ? gsz : wst;
-  L.tw_off = L.db_off + (size_t)g.n2 * (g.K1 + 1) * 2;
+  const size_t dbsz = (size_t)g.n2 * (g.K1 + 1) * 2;
+  L.rsplit = 0;
+  size_t db = gsz > wst ? gsz : wst;
+  if (gsz >= dbsz && gsz - dbsz >= ws) {
+    const size_t dc = gsz - dbsz;
+    int rs = (int)(dc / L.apitch) & ~1;                 // rows [0, rs) end at or below db
+    const int items = (g.n2 - rs) / 2 * fft_B(g.n1);    // first-step items of the staged batch
+    if (rs >= 2 && rs < g.n2 && items <= NT) {
+      L.rsplit = rs;
+      db = dc;
+    }
+  }
+  L.db_off = db;
+  const size_t end = db + dbsz;
+  const size_t top = end > gsz ? end : gsz;
+  L.tw_off = top > wst ? top : wst;
   L.total = L.tw_off + 2 * (size_t)(g.n1 + g.n2);
   return L;
+}
+
+// First step of the row-pair inverse transforms for pairs [q0, q0 + count) whose
+// spectra are read from LDS that the step's own stores overwrite: every item
+// loads its A inputs, the workgroup waits, then every item transforms and
+// stores (one item per thread, count * B <= NT).  The same arithmetic as
+// fft4_step1_swz.
+template <int A, int B, int NT, typename Make>
+__device__ __forceinline__ void row_step1_staged(int q0, int count, const float *tw, const Make &make1) {
+  const int it = threadIdx.x;
+  const bool on = it < count * B;
+  const int q = q0 + (on ? it / B : 0), b = on ? it % B : 0;
+  const auto acc = make1(q);
+  float re[A], im[A];
+#pragma unroll
+  for (int a = 0; a < A; ++a) {
+    re[a] = 0.0f;
+    im[a] = 0.0f;
+    if (on) acc.load(a * B + b, re[a], im[a]);
+  }
+  __syncthreads();
+  if (on) {
+    dft_reg<A, true, float>(re, im);
+#pragma unroll
+    for (int k1 = 0; k1 < A; ++k1) {
+      float r = re[k1], i = im[k1];
+      if (k1 > 0) {
+        const int j = b * k1;
+        const float c = tw[2 * j], sn = -tw[2 * j + 1];
+        const float nr = r * c - i * sn;
+        i = r * sn + i * c;
+        r = nr;
+      }
+      acc.store(k1 * B + (b ^ fft_swz(k1, B)), r, i);
+    }
+  }
+  __syncthreads();
 }
 
 // Taps and their derivatives with respect to the fine coordinate t from the
@@ -769,13 +827,15 @@ __device__ __forceinline__ void gather1_item(const AdjArgs<float> &a, const floa
   }
 }
 
+// Four waves per SIMD: two 512-thread workgroups per CU with the compact layout
+// (each thread then within 128 VGPRs).
 template <int W, int NT>
-__global__ __launch_bounds__(NT) void adj1_kernel(AdjArgs<float> a) {
+__global__ __launch_bounds__(NT, (NT == 512 ? 4 : 1)) void adj1_kernel(AdjArgs<float> a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   float *sm = reinterpret_cast<float *>(smem_raw);
   __shared__ int s_item;
   const Geom &g = a.g;
-  const Adj1Layout L = adj1_layout(g, W, sizeof(float));
+  const Adj1Layout L = adj1_layout(g, W, sizeof(float), NT);
   float *G = sm + L.g_off, *ws = sm + L.ws_off, *st = sm + L.st_off, *db = sm + L.db_off;
   float *tw1 = sm + L.tw_off, *tw2 = tw1 + 2 * g.n1;
   const int per = g.K1 + 1, pitch = L.apitch;
@@ -802,28 +862,50 @@ __global__ __launch_bounds__(NT) void adj1_kernel(AdjArgs<float> a) {
     // rows in pairs: Z(k) = D_2q(k) + i D_2q+1(k) gives rows 2q and 2q + 1 as its real
     // and imaginary parts (both rows' spectra are Hermitian)
     const int n1 = g.n1, K1 = g.K1;
-    row_ifft_natural<NT, float>(
-        n1, g.n2 / 2, tw1, W - 1,
-        [&](int q) {
-          RowSpecAcc<float> acc;
-          acc.db = db;
-          acc.row = 2 * q;
-          acc.pair = true;
-          acc.per = per;
-          acc.n1 = n1;
-          acc.K1 = K1;
-          acc.r0 = G + 2 * q * pitch;
-          acc.r1 = acc.r0 + pitch;
-          acc.stride = 1;
-          return acc;
-        },
-        [&](int q) {
-          StridedPairAcc<float> acc;
-          acc.r0 = G + 2 * q * pitch;
-          acc.r1 = acc.r0 + pitch;
-          acc.stride = 1;
-          return acc;
-        });
+    auto make1 = [&](int q) {
+      RowSpecAcc<float> acc;
+      acc.db = db;
+      acc.row = 2 * q;
+      acc.pair = true;
+      acc.per = per;
+      acc.n1 = n1;
+      acc.K1 = K1;
+      acc.r0 = G + 2 * q * pitch;
+      acc.r1 = acc.r0 + pitch;
+      acc.stride = 1;
+      return acc;
+    };
+    auto make2 = [&](int q) {
+      StridedPairAcc<float> acc;
+      acc.r0 = G + 2 * q * pitch;
+      acc.r1 = acc.r0 + pitch;
+      acc.stride = 1;
+      return acc;
+    };
+    if (L.rsplit == 0) {
+      row_ifft_natural<NT, float>(n1, g.n2 / 2, tw1, W - 1, make1, make2);
+    } else {
+      // rows below db first, then the rows that share its space
+      const int qs = L.rsplit / 2, qn = g.n2 / 2 - qs;
+      row_ifft_natural<NT, float>(n1, qs, tw1, W - 1, make1, make2);
+      switch (n1) {
+        case 16: row_step1_staged<4, 4, NT>(qs, qn, tw1, make1); break;
+        case 32: row_step1_staged<8, 4, NT>(qs, qn, tw1, make1); break;
+        case 64: row_step1_staged<8, 8, NT>(qs, qn, tw1, make1); break;
+        default: row_step1_staged<16, 8, NT>(qs, qn, tw1, make1); break;
+      }
+      const int A2 = fft_A(n1), la = fft_logA(n1);
+      for (int it = threadIdx.x; it < qn * A2; it += NT) {
+        const int q = qs + (it >> la), k1 = it & (A2 - 1);
+        switch (n1) {
+          case 16: row_step2_natural<4, 4, float>(make2(q), k1, n1, W - 1); break;
+          case 32: row_step2_natural<8, 4, float>(make2(q), k1, n1, W - 1); break;
+          case 64: row_step2_natural<8, 8, float>(make2(q), k1, n1, W - 1); break;
+          default: row_step2_natural<16, 8, float>(make2(q), k1, n1, W - 1); break;
+        }
+      }
+      __syncthreads();
+    }
     // the first W - 1 rows again after the last (with their repeated columns)
     for (int i = threadIdx.x; i < (W - 1) * pitch; i += NT) G[g.n2 * pitch + i] = G[i];
     __syncthreads();
@@ -1007,8 +1089,10 @@ enufft_status adj_prepare(enufft_plan_t p) {
     return ENUFFT_EDEVICE;
   }
   if (p->adj1) {
-    // single-grid adjoint: one item per cell (or chunk of a large cell), no bands
-    p->adj1_lds = adj1_layout(p->geom, p->adj1_W, sizeof(float)).total * sizeof(float);
+    // single-grid adjoint: one item per cell (or chunk of a large cell), no bands;
+    // 512 threads, so two workgroups fit a CU with the compact layout
+    if (const char *ev = std::getenv("ENUFFT_ADJ1_THREADS")) p->adj1_threads = std::atoi(ev) == 1024 ? 1024 : 512;
+    p->adj1_lds = adj1_layout(p->geom, p->adj1_W, sizeof(float), p->adj1_threads).total * sizeof(float);
     const void *fn = adj1_fn(p->adj1_W, p->adj1_threads);
     int per1 = 0;
     e = fn ? hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)p->adj1_lds)

@@ -68,7 +68,7 @@ struct enufft_plan_s {
   void *d_adj1_decon_x = nullptr, *d_adj1_decon_y = nullptr;
   std::vector<enufft::AdjItem> adj1_items;
   void *d_adj1_items = nullptr;
-  int adj1_threads = 1024, adj1_blocks = 0;
+  int adj1_threads = 512, adj1_blocks = 0;
   size_t adj1_lds = 0;
 
   // adjoint schedule (also used by the reconstruction diagnostics)
