@@ -721,33 +721,54 @@ __device__ __forceinline__ void row_step1_staged(int q0, int count, const float 
   __syncthreads();
 }
 
-// Taps and their derivatives with respect to the fine coordinate t from the
-// mirror-pair polynomials of the taps alone (no second set of coefficients, so
-// the kernel's scalar registers hold one table).  With P_d(u) = E(s) + u O(s),
-// s = u^2 and u = 2 v - 1 = 2 (i0 - t + W/2) - 1: dP_d/dt = -2 dP_d/du =
-// -2 (O + 2 u (E' + u O')), and the mirror tap W - 1 - d, E - u O, has
-// -2 (-O + 2 u (E' - u O')); E' and O' (d/ds) come out of the same Horner steps.
+// Taps and their derivatives from the mirror-pair polynomials of the taps alone
+// (no second set of coefficients, so the kernel's scalar registers hold one
+// table).  With P_d(u) = E(s) + u O(s) and s = u^2: dP_d/du = O + 2 u (E' + u O'),
+// and the mirror tap W - 1 - d, E - u O, has -O + 2 u (E' - u O'); E' and O'
+// (d/ds) come out of the same Horner steps.
+// Mirror pair d of the taps and of their u-derivatives: tap d, tap W - 1 - d and
+// the two derivatives dP/du, from the pair's coefficients cd at u and s = u^2.
+// (With u = 2 (i0 - t + W/2) - 1, d/dt = -2 d/du: the caller's scale carries the
+// factor -2, so it is not multiplied into every tap.)
+__device__ __forceinline__ void es_pair_dtaps(float u, float s, const float *cd, float &t0, float &t1, float &d0,
+                                              float &d1) {
+  float e = cd[ES_DEG - 1], o = cd[ES_DEG], de = 0.0f, dO = 0.0f;
+#pragma unroll
+  for (int k = ES_DEG - 3; k >= 0; k -= 2) {
+    de = fmaf(de, s, e);
+    dO = fmaf(dO, s, o);
+    e = fmaf(e, s, cd[k]);
+    o = fmaf(o, s, cd[k + 1]);
+  }
+  t0 = fmaf(u, o, e);
+  t1 = fmaf(-u, o, e);
+  const float u2 = 2.0f * u;
+  d0 = fmaf(u2, fmaf(u, dO, de), o);
+  d1 = fmaf(u2, fmaf(-u, dO, de), -o);
+}
+
 template <int W>
 __device__ __forceinline__ void es_taps_dtaps_poly_v(float v, const EsPoly &cf, float (&out)[W],
                                                      float (&dout)[W]) {
   const float u = 2.0f * v - 1.0f;
   const float s = u * u;
 #pragma unroll
-  for (int d = 0; d < W / 2; ++d) {
-    const float *cd = cf.c + d * (ES_DEG + 1);
-    float e = cd[ES_DEG - 1], o = cd[ES_DEG], de = 0.0f, dO = 0.0f;
-#pragma unroll
-    for (int k = ES_DEG - 3; k >= 0; k -= 2) {
-      de = fmaf(de, s, e);
-      dO = fmaf(dO, s, o);
-      e = fmaf(e, s, cd[k]);
-      o = fmaf(o, s, cd[k + 1]);
-    }
-    out[d] = fmaf(u, o, e);
-    out[W - 1 - d] = fmaf(-u, o, e);
-    const float u2 = 2.0f * u;
-    dout[d] = -2.0f * fmaf(u2, fmaf(u, dO, de), o);
-    dout[W - 1 - d] = -2.0f * fmaf(u2, fmaf(-u, dO, de), -o);
+  for (int d = 0; d < W / 2; ++d)
+    es_pair_dtaps(u, s, cf.c + d * (ES_DEG + 1), out[d], out[W - 1 - d], dout[d], dout[W - 1 - d]);
+}
+
+// Holds the two rows' grid values until every read of the pair has returned,
+// so the reads are issued together and waited for once (left to itself the
+// compiler waited after each read, one LDS round trip per two values).
+template <int W>
+__device__ __forceinline__ void hold_rows(float (&ra)[W], float (&rb)[W]) {
+  if constexpr (W == 8) {
+    asm volatile("" : "+v"(ra[0]), "+v"(ra[1]), "+v"(ra[2]), "+v"(ra[3]), "+v"(ra[4]), "+v"(ra[5]), "+v"(ra[6]),
+                      "+v"(ra[7]), "+v"(rb[0]), "+v"(rb[1]), "+v"(rb[2]), "+v"(rb[3]), "+v"(rb[4]), "+v"(rb[5]),
+                      "+v"(rb[6]), "+v"(rb[7]));
+  } else if constexpr (W == 6) {
+    asm volatile("" : "+v"(ra[0]), "+v"(ra[1]), "+v"(ra[2]), "+v"(ra[3]), "+v"(ra[4]), "+v"(ra[5]), "+v"(rb[0]),
+                      "+v"(rb[1]), "+v"(rb[2]), "+v"(rb[3]), "+v"(rb[4]), "+v"(rb[5]));
   }
 }
 
@@ -762,29 +783,43 @@ __device__ __forceinline__ void gather1_point(const AdjArgs<float> &a, const flo
   const FineCoord<float> fx = fine_coord<float>(xj, a.s1_hi, a.s1_lo, halfw);
   const FineCoord<float> fy = fine_coord<float>(yj, a.s2_hi, a.s2_lo, halfw);
   const float vx = tap_v(fx, halfw), vy = tap_v(fy, halfw);
-  float kx[W], kxd[W], ky[W], kyd[W];
+  float kx[W], kxd[W];
   es_taps_dtaps_poly_v<W>(vx, a.es, kx, kxd);
-  es_taps_dtaps_poly_v<W>(vy, a.es, ky, kyd);
+  const float uyv = 2.0f * vy - 1.0f, syv = uyv * uyv;
   const float *p = G + (fy.i0 & (g.n2 - 1)) * apitch + (fx.i0 & (g.n1 - 1));
   float u = 0.0f, ux = 0.0f, uy = 0.0f;
+  // rows in mirror pairs (d, W - 1 - d), whose y taps come from one polynomial pair
 #pragma unroll
-  for (int dy = 0; dy < W; ++dy) {
-    float s = 0.0f, sd = 0.0f;
+  for (int d = 0; d < W / 2; ++d) {
+    const float *pa = p + d * apitch, *pb = p + (W - 1 - d) * apitch;
+    float ra[W], rb[W];
 #pragma unroll
     for (int dx = 0; dx < W; ++dx) {
-      const float v = p[dx];
-      s = fmaf(kx[dx], v, s);
-      sd = fmaf(kxd[dx], v, sd);
+      ra[dx] = pa[dx];
+      rb[dx] = pb[dx];
     }
-    u = fmaf(ky[dy], s, u);
-    ux = fmaf(ky[dy], sd, ux);
-    uy = fmaf(kyd[dy], s, uy);
-    p += apitch;
+    float ta, tb, da, db;
+    es_pair_dtaps(uyv, syv, a.es.c + d * (ES_DEG + 1), ta, tb, da, db);
+    hold_rows<W>(ra, rb);
+    float sa = 0.0f, sda = 0.0f, sb = 0.0f, sdb = 0.0f;
+#pragma unroll
+    for (int dx = 0; dx < W; ++dx) {
+      sa = fmaf(kx[dx], ra[dx], sa);
+      sda = fmaf(kxd[dx], ra[dx], sda);
+      sb = fmaf(kx[dx], rb[dx], sb);
+      sdb = fmaf(kxd[dx], rb[dx], sdb);
+    }
+    u = fmaf(ta, sa, u);
+    ux = fmaf(ta, sda, ux);
+    uy = fmaf(da, sa, uy);
+    u = fmaf(tb, sb, u);
+    ux = fmaf(tb, sdb, ux);
+    uy = fmaf(db, sb, uy);
   }
   // the derivative sums are formed here, in the row loop, not sunk into the
   // branch that stores them (which kept all W x W grid values live)
   asm volatile("" : "+v"(ux), "+v"(uy));
-  ux *= a.dsx;
+  ux *= a.dsx;   // -2 n1 / (2 pi): d/dt of the fine coordinate, d/du = -2 d/dt
   uy *= a.dsy;
   float dWx, dWy;
   const float Wv = hann_wg(a.window_kind, xj, yj, cx, cy, R, pr, dWx, dWy);
@@ -1202,8 +1237,8 @@ enufft_status adjoint_common(enufft_plan_t p, const char *fn, const void *x, con
     a.decon_x = (const float *)p->d_adj1_decon_x;
     a.decon_y = (const float *)p->d_adj1_decon_y;
     a.es = p->adj1_es;
-    a.dsx = (float)(p->n1 / (2.0 * M_PI));
-    a.dsy = (float)(p->n2 / (2.0 * M_PI));
+    a.dsx = (float)(-2.0 * p->n1 / (2.0 * M_PI));   // dt/dx times du/dt of the tap polynomials
+    a.dsy = (float)(-2.0 * p->n2 / (2.0 * M_PI));
     a.bands = 1;
     a.band_rows = p->n2;
     e = launch_adj1(a, p->adj1_W, p->adj1_blocks, p->adj1_threads, p->adj1_lds, p->stream);

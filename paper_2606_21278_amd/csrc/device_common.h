@@ -87,7 +87,7 @@ struct AdjArgs {
   T beta;
   T s1_hi, s1_lo, s2_hi, s2_lo;
   EsPoly es;                   // as in FwdArgs (the single-grid adjoint: its own kernel's taps)
-  T dsx, dsy;                  // single-grid adjoint: n1 / (2 pi), n2 / (2 pi)
+  T dsx, dsy;                  // single-grid adjoint: -2 n1 / (2 pi), -2 n2 / (2 pi)
   int vec4;                    // x, y, h, w are 16-byte aligned: load runs of 4 points
   int bands, band_rows;        // row bands per cell and rows per band
   double *rec_part;            // reconstruction mode: per item (sum (t - h_rec)^2, sum t^2, sum w t^2)
@@ -169,12 +169,13 @@ __device__ __forceinline__ FineCoord<T> fine_coord(T x, T s_hi, T s_lo, T halfw)
 // Radial Hann window W = (1 + cos(pi r / R)) / 2 for r < R, else 0, and its
 // gradient -(pi^2 / (2 R^2)) sinc(pi r / R) (x - cx, y - cy).  kind 0 is no
 // window.  pr = pi / R is precomputed per cell.  FP32 uses the hardware
-// sqrt / reciprocal / sin / cos (errors ~1e-6 absolute on W, far inside the
-// FP32 tolerance); FP64 uses the accurate library functions.
+// sqrt / reciprocal / sin / cos instructions (errors ~1e-6 absolute on W, far
+// inside the FP32 tolerance; the correctly rounded square root costs about ten
+// more instructions per point); FP64 uses the accurate library functions.
 __device__ __forceinline__ float hann_w(int kind, float x, float y, float cx, float cy, float R, float pr) {
   if (kind == 0) return 1.0f;
   const float dx = x - cx, dy = y - cy;
-  const float r = __builtin_sqrtf(dx * dx + dy * dy);
+  const float r = __builtin_amdgcn_sqrtf(dx * dx + dy * dy);
   if (!(r < R)) return 0.0f;
   return 0.5f + 0.5f * __cosf(pr * r);
 }
@@ -190,7 +191,7 @@ __device__ __forceinline__ float hann_wg(int kind, float x, float y, float cx, f
   gx = 0.0f; gy = 0.0f;
   if (kind == 0) return 1.0f;
   const float dx = x - cx, dy = y - cy;
-  const float r = __builtin_sqrtf(dx * dx + dy * dy);
+  const float r = __builtin_amdgcn_sqrtf(dx * dx + dy * dy);
   if (!(r < R)) return 0.0f;
   const float u = pr * r;
   const float s = __sinf(u), c = __cosf(u);
