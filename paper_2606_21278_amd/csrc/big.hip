@@ -145,8 +145,8 @@ struct BigSortArgs {
   int *unit_base;           // [ntiles + 1] first work unit of each tile; [ntiles] = units in all
   int *inv;                 // [n] sorted position of each input point
   T *xs, *ys, *hs, *ws;     // [n] points in tile order
-  int *chunk_fl;            // [nchunks][2] first tile, last tile (-1: tiles descend inside the chunk)
-  int *presorted;           // set when the input is already in tile order (NULL: always scatter)
+  int *chunk_fl;            // [nchunks][4] first key, last key, tiles descend inside, keys descend inside
+  int *presorted;           // [0]: input in tile order, [1]: also by fine cell inside each tile (NULL: always scatter)
 };
 
 template <typename T>
@@ -154,6 +154,17 @@ __device__ __forceinline__ int big_tile(const BigSortArgs<T> &a, T x, T y) {
   const int ix = big_origin<T>(x, a.s1h, a.s1l, a.W, a.n1);
   const int iy = big_origin<T>(y, a.s2h, a.s2l, a.W, a.n2);
   return (iy / BIG_TS) * a.ntx + ix / BIG_TS;
+}
+
+// Tile and fine cell of the footprint origin as one key: the tile times
+// BIG_TS^2 plus the cell's row-major index inside the tile (tiles start at
+// multiples of BIG_TS, so the in-tile index is the origin modulo BIG_TS).
+constexpr int BIG_TS2 = BIG_TS * BIG_TS;
+template <typename T>
+__device__ __forceinline__ int big_key(const BigSortArgs<T> &a, T x, T y) {
+  const int ix = big_origin<T>(x, a.s1h, a.s1l, a.W, a.n1);
+  const int iy = big_origin<T>(y, a.s2h, a.s2l, a.W, a.n2);
+  return ((iy / BIG_TS) * a.ntx + ix / BIG_TS) * BIG_TS2 + (iy % BIG_TS) * BIG_TS + ix % BIG_TS;
 }
 
 __device__ __forceinline__ int big_wave_incl_scan(int v) {
@@ -195,34 +206,42 @@ __device__ int big_block_scan(const int *cnt, O *out, int n, int *wsum) {
   return total;
 }
 
-// Tile histogram of each chunk, written in full, and whether the chunk's tiles
-// never descend (its first and last tile, or -1 for the last when they do): the
-// tile scan concludes from these whether the whole input is in tile order.
+// Tile histogram of each chunk, written in full, and the chunk's order: its
+// first and last key (tile and fine cell, big_key) and whether tiles, or keys,
+// descend inside it.  The tile scan concludes from these whether the whole input
+// is in tile order, and whether it is also in fine-cell order inside each tile.
 template <typename T>
 __global__ __launch_bounds__(BIG_SORT_THREADS) void big_count_kernel(BigSortArgs<T> a) {
-  extern __shared__ int hist[];            // [ntiles], then the chunk's tiles [BIG_SORT_CHUNK]
-  int *tiles = hist + a.ntiles;
-  __shared__ int s_desc;
+  extern __shared__ int hist[];            // [ntiles], then the chunk's keys [BIG_SORT_CHUNK]
+  int *keys = hist + a.ntiles;
+  __shared__ int s_desc[2];
   for (int i = threadIdx.x; i < a.ntiles; i += blockDim.x) hist[i] = 0;
-  if (threadIdx.x == 0) s_desc = 0;
+  if (threadIdx.x < 2) s_desc[threadIdx.x] = 0;
   __syncthreads();
   const int64_t s = (int64_t)blockIdx.x * BIG_SORT_CHUNK, e = min(a.n, s + BIG_SORT_CHUNK);
   const int cnt = (int)(e - s);
   for (int64_t j = s + threadIdx.x; j < e; j += blockDim.x) {
-    const int t = big_tile<T>(a, a.x[j], a.y[j]);
-    tiles[j - s] = t;
-    atomicAdd(&hist[t], 1);
+    const int k = big_key<T>(a, a.x[j], a.y[j]);
+    keys[j - s] = k;
+    atomicAdd(&hist[k / BIG_TS2], 1);
   }
   __syncthreads();
-  int desc = 0;
-  for (int i = threadIdx.x; i + 1 < cnt; i += blockDim.x) desc |= tiles[i] > tiles[i + 1];
-  if (desc) s_desc = 1;
+  int tdesc = 0, kdesc = 0;
+  for (int i = threadIdx.x; i + 1 < cnt; i += blockDim.x) {
+    tdesc |= keys[i] / BIG_TS2 > keys[i + 1] / BIG_TS2;
+    kdesc |= keys[i] > keys[i + 1];
+  }
+  if (tdesc) s_desc[0] = 1;
+  if (kdesc) s_desc[1] = 1;
   int *row = a.chunk_hist + (int64_t)blockIdx.x * a.ntiles;
   for (int i = threadIdx.x; i < a.ntiles; i += blockDim.x) row[i] = hist[i];
   __syncthreads();
   if (threadIdx.x == 0) {
-    a.chunk_fl[2 * blockIdx.x] = tiles[0];
-    a.chunk_fl[2 * blockIdx.x + 1] = s_desc ? -1 : tiles[cnt - 1];
+    int *fl = a.chunk_fl + 4 * (int64_t)blockIdx.x;
+    fl[0] = keys[0];
+    fl[1] = keys[cnt - 1];
+    fl[2] = s_desc[0];
+    fl[3] = s_desc[1];
   }
 }
 
@@ -245,15 +264,22 @@ __global__ __launch_bounds__(1024) void big_tile_scan_kernel(int *group_sum, int
                                                              int nchunks, int *presorted) {
   extern __shared__ int tot[];   // [ntiles]
   __shared__ int wsum[16];
-  // the input is in tile order when no chunk descends inside and each chunk's
-  // last tile is at most the next chunk's first
-  int bad = 0;
+  // the input is in tile order when no chunk's tiles descend inside and each
+  // chunk's last tile is at most the next chunk's first; in key order (tile,
+  // then fine cell) likewise with the keys
+  int tbad = 0, kbad = 0;
   for (int b = threadIdx.x; b < nchunks; b += blockDim.x) {
-    const int last = chunk_fl[2 * b + 1];
-    bad |= last < 0 || (b + 1 < nchunks && last > chunk_fl[2 * (b + 1)]);
+    const int *fl = chunk_fl + 4 * (int64_t)b;
+    const bool more = b + 1 < nchunks;
+    tbad |= fl[2] || (more && fl[1] / BIG_TS2 > fl[4] / BIG_TS2);
+    kbad |= fl[3] || (more && fl[1] > fl[4]);
   }
-  bad = __syncthreads_or(bad);
-  if (threadIdx.x == 0 && presorted) *presorted = bad ? 0 : 1;
+  tbad = __syncthreads_or(tbad);
+  kbad = __syncthreads_or(kbad);
+  if (threadIdx.x == 0 && presorted) {
+    presorted[0] = tbad ? 0 : 1;
+    presorted[1] = (tbad || kbad) ? 0 : 1;
+  }
   for (int t = threadIdx.x; t < ntiles; t += blockDim.x) {
     int run = 0;
     for (int g = 0; g < ngroups; ++g) {
@@ -449,7 +475,11 @@ __global__ __launch_bounds__(BIG_SPREAD_THREADS) void big_spread_kernel(BigTileA
   const double *wn = a.windows + 3 * a.cell;
   const T cx = T(wn[0]), cy = T(wn[1]), R = T(wn[2]);
   const T pr = R > T(0) ? T(M_PI) / R : T(0);
-  const bool pre = *a.presorted;
+  const bool pre = a.presorted[0];
+  // points in fine-cell order inside each tile go to big_spread_run_kernel
+  if constexpr (sizeof(T) == 4 && POLY) {
+    if (a.presorted[1]) return;
+  }
   const T *X = pre ? a.xi : a.xs, *Y = pre ? a.yi : a.ys, *Hh = pre ? a.hi : a.hs, *Wq = pre ? a.wi : a.ws;
   big_units<T>(a, &s_unit, [&](int t, int64_t lo, int64_t hi, int u) {
     for (int i = threadIdx.x; i < S * S; i += blockDim.x) sub[i] = 0.0;
@@ -473,6 +503,103 @@ __global__ __launch_bounds__(BIG_SPREAD_THREADS) void big_spread_kernel(BigTileA
         for (int dx = 0; dx < W; ++dx)
           __hip_atomic_fetch_add(row + dx, vy * (double)kx[dx], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
       }
+    }
+    __syncthreads();
+    double *dst = a.partial + (int64_t)u * (S * S);
+    for (int i = threadIdx.x; i < S * S; i += blockDim.x) dst[i] = sub[i];
+    __syncthreads();
+  });
+}
+
+// FP32 spreading of points that arrive in fine-cell order inside each tile (the
+// order enufft_sort_points leaves): runs of points with one footprint origin
+// add their W x W contributions in FP32 registers, and each run goes to the
+// FP64 sub-grid once, W^2 adds for the run instead of W^2 per point.  Each unit
+// is staged through LDS in pieces of BIG_RUN_P points per thread (coalesced
+// loads); thread t walks its own BIG_RUN_P consecutive points of the piece, the
+// lanes of a wave a few segments apart so their runs seldom share a cell.  A
+// run is flushed when the origin changes and at the end of the segment.
+constexpr int BIG_RUN_P = 8;
+constexpr int BIG_RUN_NP = BIG_RUN_P * BIG_SPREAD_THREADS;
+
+template <int W>
+__device__ __forceinline__ void big_run_flush(double *sub, int key, float (&acc)[W][W]) {
+  constexpr int S = BIG_TS + W + 1;
+  double *base = sub + key;
+#pragma unroll
+  for (int dy = 0; dy < W; ++dy)
+#pragma unroll
+    for (int dx = 0; dx < W; ++dx) {
+      __hip_atomic_fetch_add(base + dy * S + dx, (double)acc[dy][dx], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      acc[dy][dx] = 0.0f;
+    }
+}
+
+template <int W>
+__global__ __launch_bounds__(BIG_SPREAD_THREADS) void big_spread_run_kernel(BigTileArgs<float> a) {
+  constexpr int S = BIG_TS + W + 1;   // as big_spread_kernel
+  constexpr int NW = BIG_SPREAD_THREADS / 64;
+  // staged segment s starts at s * PP + s / NW (one spare slot per segment and
+  // per NW segments, so the lanes of a wave, NW segments apart, read distinct banks)
+  constexpr int PP = BIG_RUN_P + 1;
+  __shared__ double sub[S * S];
+  __shared__ float4 piece[BIG_SPREAD_THREADS * PP + BIG_SPREAD_THREADS / NW];
+  __shared__ int s_unit;
+  if (!a.presorted[1]) return;        // not in cell order: big_spread_kernel spreads this cell
+  const Geom &g = a.g;
+  const float halfw = float(W) / 2.0f;
+  const double *wn = a.windows + 3 * a.cell;
+  const float cx = float(wn[0]), cy = float(wn[1]), R = float(wn[2]);
+  const float pr = R > 0.0f ? float(M_PI) / R : 0.0f;
+  // cell order implies tile order: the input arrays are the tile-sorted points
+  const float *X = a.xi, *Y = a.yi, *Hh = a.hi, *Wq = a.wi;
+  const int seg = (threadIdx.x & 63) * NW + (threadIdx.x >> 6);   // this thread's segment of a piece
+  big_units<float>(a, &s_unit, [&](int t, int64_t lo, int64_t hi, int u) {
+    for (int i = threadIdx.x; i < S * S; i += blockDim.x) sub[i] = 0.0;
+    const int tx0 = (t % a.ntx) * BIG_TS, ty0 = (t / a.ntx) * BIG_TS;
+    for (int64_t p0 = lo; p0 < hi; p0 += BIG_RUN_NP) {
+      const int np = (int)min<int64_t>(BIG_RUN_NP, hi - p0);
+      __syncthreads();   // the previous piece is consumed (and the sub-grid zeroed)
+      for (int q = threadIdx.x; q < np; q += BIG_SPREAD_THREADS) {
+        float4 v;
+        v.x = X[p0 + q];
+        v.y = Y[p0 + q];
+        v.z = Hh[p0 + q];
+        v.w = Wq[p0 + q];
+        const int sq = q / BIG_RUN_P;
+        piece[sq * PP + sq / NW + q % BIG_RUN_P] = v;
+      }
+      __syncthreads();
+      const int q0 = seg * BIG_RUN_P, q1 = min(np, q0 + BIG_RUN_P);
+      float acc[W][W];
+#pragma unroll
+      for (int dy = 0; dy < W; ++dy)
+#pragma unroll
+        for (int dx = 0; dx < W; ++dx) acc[dy][dx] = 0.0f;
+      int cur = -1;   // sub-grid offset of the run's origin; -1: no run yet
+      for (int q = q0; q < q1; ++q) {
+        const float4 v = piece[seg * PP + seg / NW + (q - q0)];
+        const float cj = v.w * v.z * hann_w(a.window_kind, v.x, v.y, cx, cy, R, pr);
+        const FineCoord<float> fx = fine_coord<float>(v.x, a.s1h, a.s1l, halfw);
+        const FineCoord<float> fy = fine_coord<float>(v.y, a.s2h, a.s2l, halfw);
+        const int lx = big_local(fx.i0 & (g.n1 - 1), tx0, g.n1);
+        const int ly = big_local(fy.i0 & (g.n2 - 1), ty0, g.n2);
+        const int key = ly * S + lx;
+        if (key != cur) {
+          if (cur >= 0) big_run_flush<W>(sub, cur, acc);
+          cur = key;
+        }
+        float kx[W], ky[W];
+        big_taps<float, W, true>(fx, a.beta, a.es, kx);
+        big_taps<float, W, true>(fy, a.beta, a.es, ky);
+#pragma unroll
+        for (int dy = 0; dy < W; ++dy) {
+          const float vy = cj * ky[dy];
+#pragma unroll
+          for (int dx = 0; dx < W; ++dx) acc[dy][dx] = fmaf(vy, kx[dx], acc[dy][dx]);
+        }
+      }
+      if (cur >= 0) big_run_flush<W>(sub, cur, acc);
     }
     __syncthreads();
     double *dst = a.partial + (int64_t)u * (S * S);
@@ -1104,6 +1231,36 @@ __global__ __launch_bounds__(256) void big_unpermute_kernel(const typename vec4<
   }
 }
 
+// Second pass of the one-time point sort (enufft_sort_points): inside each
+// tile, by the fine cell of the footprint origin (big_key), one workgroup per
+// tile: the tile's cell histogram in LDS, its scan, then every point moved into
+// its cell's range, with its input index when pin is given.  The order inside a
+// cell is not fixed (LDS atomics rank the points).
+template <typename T>
+__global__ __launch_bounds__(1024) void big_cell_sort_kernel(BigSortArgs<T> a, const T *xt, const T *yt, const T *ht,
+                                                             const T *wt, const int32_t *pin, T *xo, T *yo, T *ho,
+                                                             T *wo, int32_t *pout) {
+  __shared__ int cur[BIG_TS2];
+  __shared__ int wsum[16];
+  const int64_t o0 = a.offsets[blockIdx.x], o1 = a.offsets[blockIdx.x + 1];
+  if (o1 <= o0) return;   // the whole workgroup: an empty tile
+  for (int i = threadIdx.x; i < BIG_TS2; i += blockDim.x) cur[i] = 0;
+  __syncthreads();
+  for (int64_t k = o0 + threadIdx.x; k < o1; k += blockDim.x) atomicAdd(&cur[big_key<T>(a, xt[k], yt[k]) % BIG_TS2], 1);
+  __syncthreads();
+  big_block_scan<1024, int>(cur, cur, BIG_TS2, wsum);
+  for (int64_t k = o0 + threadIdx.x; k < o1; k += blockDim.x) {
+    const T xk = xt[k], yk = yt[k];
+    const int64_t pos = o0 + atomicAdd(&cur[big_key<T>(a, xk, yk) % BIG_TS2], 1);
+    if (pos >= o1) continue;   // only if the two passes disagreed on a key; never out of the tile's range
+    xo[pos] = xk;
+    yo[pos] = yk;
+    if (ho) ho[pos] = ht[k];
+    if (wo) wo[pos] = wt[k];
+    if (pout) pout[pos] = pin[k];
+  }
+}
+
 // perm[inv[j]] = base + j: the input index of each sorted position.
 __global__ __launch_bounds__(256) void big_perm_kernel(const int *inv, int64_t n, int32_t base, int32_t *perm) {
   for (int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x; j < n; j += (int64_t)gridDim.x * 256) {
@@ -1255,6 +1412,17 @@ struct GatherW {
   }
 };
 
+// Launch of the run kernel for FP32 plans with the kernel polynomial.
+hipError_t spread_runs(int W, const BigTileArgs<float> &a, int blocks, hipStream_t s) {
+  switch (W) {
+    case 4: hipLaunchKernelGGL((big_spread_run_kernel<4>), dim3(blocks), dim3(BIG_SPREAD_THREADS), 0, s, a); break;
+    case 6: hipLaunchKernelGGL((big_spread_run_kernel<6>), dim3(blocks), dim3(BIG_SPREAD_THREADS), 0, s, a); break;
+    case 8: hipLaunchKernelGGL((big_spread_run_kernel<8>), dim3(blocks), dim3(BIG_SPREAD_THREADS), 0, s, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 // Width dispatch; the polynomial taps exist for FP32 plans with W <= ES_MAXW.
 template <typename T, template <typename, int, bool> class Fn>
 hipError_t by_width(int W, const BigTileArgs<T> &a, int blocks, hipStream_t s) {
@@ -1318,6 +1486,11 @@ enufft_status type1_t(enufft_plan_t p, const T *x, const T *y, const T *h, const
         a.work_counter = p->big_work;
         a.done_counter = p->big_work + 1;
         e = by_width<T, SpreadW>(p->W, a, tile_blocks(p, n), p->stream);
+        // cells whose points are in fine-cell order: the run kernel (the kernel
+        // above returned at once for them; the flag is known on the device only)
+        if constexpr (sizeof(T) == 4) {
+          if (e == hipSuccess && a.es.on) e = spread_runs(p->W, a, tile_blocks(p, n), p->stream);
+        }
       }
       if (e == hipSuccess) {
         hipLaunchKernelGGL(big_assemble_kernel, dim3((unsigned)((n12 + 255) / 256)), dim3(256), 0, p->stream,
@@ -1433,7 +1606,7 @@ enufft_status big_prepare(enufft_plan_t p) {
       {(void **)&p->big_offsets, (size_t)(ntiles + 1) * sizeof(int64_t), "tile offsets"},
       {(void **)&p->big_unit_base, (size_t)(ntiles + 1) * sizeof(int), "tile unit offsets"},
       {(void **)&p->big_inv, (size_t)q1 * sizeof(int), "inverse permutation"},
-      {(void **)&p->big_chunk_fl, (size_t)(nchunks * 2) * sizeof(int), "chunk tile bounds"},
+      {(void **)&p->big_chunk_fl, (size_t)(nchunks * 4) * sizeof(int), "chunk key bounds"},
       {(void **)&p->big_flags, 4 * sizeof(int), "input order flag"},
       {(void **)&p->big_partial, (size_t)(p->big_units_max * S * S) * sizeof(double), "unit sub-grids"},
       {&p->big_gout, (size_t)q1 * 4 * el, "sorted-order gradients"},
@@ -1471,20 +1644,25 @@ namespace {
 template <typename T>
 enufft_status sort_points_t(enufft_plan_t p, const T *x, const T *y, const T *h, const T *w, T *xs, T *ys, T *hs,
                             T *ws, int32_t *perm) {
+  static_assert(BIG_TS2 == 1024, "big_cell_sort_kernel runs one thread per cell of a tile");
   for (int64_t c = 0; c < p->n_cells; ++c) {
     const int64_t a0 = p->offsets[c], n = p->offsets[c + 1] - a0;
     if (n == 0) continue;
-    // the scatter writes straight into the caller's arrays (the plan's buffers
-    // stand in for outputs not asked for); always scatter, sorted input or not
+    // by tile into the plan's buffers (always scatter, sorted input or not),
+    // then by fine cell inside each tile into the caller's arrays
     BigSortArgs<T> a = sort_args<T>(p, c, x, y, h, w ? w : x);
     a.presorted = nullptr;
-    a.xs = xs + a0; a.ys = ys + a0;
-    a.hs = hs ? hs + a0 : (T *)p->big_hs;
-    a.ws = ws ? ws + a0 : (T *)p->big_ws;
     hipError_t e = sort_launch<T>(p, a);
+    int32_t *ptile = perm ? (int32_t *)p->big_gout : nullptr;   // input index of each tile-order position
     if (e == hipSuccess && perm) {
       hipLaunchKernelGGL(big_perm_kernel, dim3((unsigned)std::min<int64_t>(8192, (n + 255) / 256)), dim3(256), 0,
-                         p->stream, (const int *)p->big_inv, n, (int32_t)a0, perm + a0);
+                         p->stream, (const int *)p->big_inv, n, (int32_t)a0, ptile);
+      e = hipGetLastError();
+    }
+    if (e == hipSuccess) {
+      hipLaunchKernelGGL((big_cell_sort_kernel<T>), dim3((unsigned)a.ntiles), dim3(1024), 0, p->stream, a,
+                         (const T *)a.xs, (const T *)a.ys, (const T *)a.hs, (const T *)a.ws, (const int32_t *)ptile,
+                         xs + a0, ys + a0, hs ? hs + a0 : nullptr, ws ? ws + a0 : nullptr, perm ? perm + a0 : nullptr);
       e = hipGetLastError();
     }
     if (e != hipSuccess) return big_fail(p, e, "large-cell point sort");

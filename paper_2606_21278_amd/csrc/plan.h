@@ -103,8 +103,8 @@ struct enufft_plan_s {
   int64_t *big_offsets = nullptr;            // [tiles + 1] tile ranges of the sorted order
   int *big_unit_base = nullptr;              // [tiles + 1] first work unit of each tile
   int *big_inv = nullptr;                    // [largest cell] sorted position of each input point
-  int *big_chunk_fl = nullptr;               // [chunks][2] first and last tile of each sort chunk
-  int *big_flags = nullptr;                  // [0]: the current cell's input is already in tile order
+  int *big_chunk_fl = nullptr;               // [chunks][4] first and last key, descent flags of each sort chunk
+  int *big_flags = nullptr;                  // [0]: the current cell's input is in tile order, [1]: and by cell
   void *big_xs = nullptr, *big_ys = nullptr, *big_hs = nullptr, *big_ws = nullptr;
   double *big_partial = nullptr;             // [units][S x S] FP64 sub-grids of the spreading units
   int64_t big_units_max = 0;

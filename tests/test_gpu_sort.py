@@ -114,9 +114,10 @@ def test_sort_edge_cases():
 
 @pytest.mark.parametrize("prec", ["f32", "f64"])
 def test_large_cell_sorted_input(prec):
-    """Large cells: sorted by tile, the input lets type-1 and the adjoint skip their
-    scatter (each call's counting pass finds the order) with the same results; one pair of
-    far-apart samples swapped makes the order fail the check and the full sort runs."""
+    """Large cells: sorted by tile (and by fine cell inside each tile), the input lets
+    type-1 and the adjoint skip their scatter (each call's counting pass finds the order)
+    with the same results; one pair of far-apart samples swapped makes the order fail the
+    check and the full sort runs."""
     b = synth.config4(Q=30000, precision=prec, n_modes=(128, 96))
     if prec == "f64":
         b.eps = 1e-10
@@ -147,3 +148,47 @@ def test_large_cell_sorted_input(prec):
         back = torch.empty_like(s)
         back[p] = s
         assert rel_l2(back.cpu().numpy(), a.cpu().numpy()) <= lim
+
+
+def _big_keys(x, y, info):
+    """Tile-then-cell key of each sample's footprint origin (FP64 on the host)."""
+    n1, n2 = info["grid"][0], info["grid"][1]
+    W = info["kernel_width"]
+    ix = (np.ceil(x.astype(np.float64) * n1 / (2 * np.pi) - W / 2).astype(np.int64)) & (n1 - 1)
+    iy = (np.ceil(y.astype(np.float64) * n2 / (2 * np.pi) - W / 2).astype(np.int64)) & (n2 - 1)
+    ntx = n1 // 32
+    return ((iy // 32) * ntx + ix // 32) * 1024 + (iy % 32) * 32 + ix % 32
+
+
+@pytest.mark.parametrize("eps", [1e-3, 1e-5, 1e-6])
+def test_large_cell_runs_fp32(eps):
+    """FP32 large cells in the order enufft_sort_points leaves (by tile, then by fine cell
+    inside each tile): runs of samples with one footprint origin are summed in registers
+    before they reach the FP64 sub-grid (W = 4, 6, 8).  Dense clusters (several samples per
+    fine cell) give long runs.  Against the oracle's direct sum, and against the same
+    samples unsorted (point-by-point spreading: sums in another order)."""
+    b = synth.config4(Q=200000, precision="f32", n_modes=(128, 96))
+    b.eps = eps
+    gb = gpu_batch(b)
+    plan = make_plan(gb)
+    info = plan.info()
+    xs, ys, hs, ws, perm = plan.sort_points(gb.x, gb.y, gb.h, gb.w)
+    f0 = plan.type1(gb.x, gb.y, gb.h, gb.w)
+    f1 = plan.type1(xs, ys, hs, ws)
+    torch.cuda.synchronize()
+    keys = _big_keys(xs.cpu().numpy(), ys.cpu().numpy(), info)
+    # in key order, but for origins that the FP32 device coordinate and the FP64 host
+    # one put on either side of a cell edge
+    desc = int(np.sum(np.diff(keys) < 0))
+    runs = np.diff(np.flatnonzero(np.diff(keys) != 0))
+    print("W %d: %d key descents, mean run %.2f samples, longest %d" % (info["kernel_width"], desc, runs.mean(),
+          runs.max()), flush=True)
+    assert desc <= max(4, gb.n_points // 10000)
+    assert runs.mean() > 2
+    assert np.array_equal(np.sort(perm.cpu().numpy()), np.arange(gb.n_points))
+    ref = oracle_f(b)
+    tol = max(5.0 * eps, TOL["f32"])
+    e1, e01 = rel_l2(f1.cpu().numpy(), ref), rel_l2(f1.cpu().numpy(), f0.cpu().numpy())
+    print("rel-l2 against the oracle %.2e, against point-by-point %.2e" % (e1, e01), flush=True)
+    assert e1 <= tol
+    assert e01 <= 2e-6
