@@ -516,9 +516,10 @@ __global__ __launch_bounds__(BIG_SPREAD_THREADS) void big_spread_kernel(BigTileA
 // add their W x W contributions in FP32 registers, and each run goes to the
 // FP64 sub-grid once, W^2 adds for the run instead of W^2 per point.  Each unit
 // is staged through LDS in pieces of BIG_RUN_P points per thread (coalesced
-// loads); thread t walks its own BIG_RUN_P consecutive points of the piece, the
-// lanes of a wave a few segments apart so their runs seldom share a cell.  A
-// run is flushed when the origin changes and at the end of the segment.
+// loads); thread t walks its own BIG_RUN_P consecutive points of each piece, the
+// lanes of a wave a few segments apart.  A run is flushed when the origin
+// changes and at the end of the segment, where lanes whose runs share an origin
+// are summed across the wave first (big_run_flush_wave).
 constexpr int BIG_RUN_P = 8;
 constexpr int BIG_RUN_NP = BIG_RUN_P * BIG_SPREAD_THREADS;
 
@@ -533,6 +534,54 @@ __device__ __forceinline__ void big_run_flush(double *sub, int key, float (&acc)
       __hip_atomic_fetch_add(base + dy * S + dx, (double)acc[dy][dx], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
       acc[dy][dx] = 0.0f;
     }
+}
+
+// Sum of v over the 64 lanes of the wave, in lane 63 (row shifts inside each row
+// of 16 lanes, then the row broadcasts); every lane must be active.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ float big_dpp_add(float v) {
+  const int t = __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, ROW_MASK, 0xf, false);
+  return v + __builtin_bit_cast(float, t);
+}
+__device__ __forceinline__ float big_wave_total(float v) {
+  v = big_dpp_add<0x111, 0xf>(v);   // row_shr:1
+  v = big_dpp_add<0x112, 0xf>(v);   // row_shr:2
+  v = big_dpp_add<0x114, 0xf>(v);   // row_shr:4
+  v = big_dpp_add<0x118, 0xf>(v);   // row_shr:8
+  v = big_dpp_add<0x142, 0xa>(v);   // row_bcast:15 into rows 1 and 3
+  v = big_dpp_add<0x143, 0xc>(v);   // row_bcast:31 into rows 2 and 3
+  return v;
+}
+
+// End-of-segment flush, called by every lane of the wave: lanes whose runs share
+// an origin with many others (a dense fine cell can hold every lane's run) are
+// first summed across the wave, one group of equal origins at a time, and lane 63
+// adds each sum once; the rest add their own values.  Without this, 64 lanes
+// adding to one address are served one after another.
+template <int W>
+__device__ __forceinline__ void big_run_flush_wave(double *sub, int &cur, float (&acc)[W][W]) {
+  constexpr int S = BIG_TS + W + 1;
+  const int lane = threadIdx.x & 63;
+  for (int grp = 0; grp < 4; ++grp) {
+    const uint64_t pend = __ballot(cur >= 0);
+    if (pend == 0) return;
+    const int lead = __ffsll((unsigned long long)pend) - 1;
+    const int k = __builtin_amdgcn_readlane(cur, lead);
+    const bool mine = cur == k;
+    if (__popcll(__ballot(mine)) < 8) break;   // a small group: its own adds are cheap
+#pragma unroll
+    for (int dy = 0; dy < W; ++dy)
+#pragma unroll
+      for (int dx = 0; dx < W; ++dx) {
+        const float tot = big_wave_total(mine ? acc[dy][dx] : 0.0f);
+        if (lane == 63)
+          __hip_atomic_fetch_add(sub + k + dy * S + dx, (double)tot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (mine) acc[dy][dx] = 0.0f;
+      }
+    if (mine) cur = -1;
+  }
+  if (cur >= 0) big_run_flush<W>(sub, cur, acc);
+  cur = -1;
 }
 
 template <int W>
@@ -599,7 +648,9 @@ __global__ __launch_bounds__(BIG_SPREAD_THREADS) void big_spread_run_kernel(BigT
           for (int dx = 0; dx < W; ++dx) acc[dy][dx] = fmaf(vy, kx[dx], acc[dy][dx]);
         }
       }
-      if (cur >= 0) big_run_flush<W>(sub, cur, acc);
+      // (carrying runs over to the next piece was slower: the lanes whose origin
+      // then changed at the piece's first point all flushed at once, unsummed)
+      big_run_flush_wave<W>(sub, cur, acc);
     }
     __syncthreads();
     double *dst = a.partial + (int64_t)u * (S * S);
