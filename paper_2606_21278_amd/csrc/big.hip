@@ -1283,29 +1283,109 @@ __global__ __launch_bounds__(256) void big_unpermute_kernel(const typename vec4<
 }
 
 // Second pass of the one-time point sort (enufft_sort_points): inside each
-// tile, by the fine cell of the footprint origin (big_key), one workgroup per
-// tile: the tile's cell histogram in LDS, its scan, then every point moved into
-// its cell's range, with its input index when pin is given.  The order inside a
-// cell is not fixed (LDS atomics rank the points).
+// tile, by the fine cell of the footprint origin (big_key).  The work units of
+// the tile order (pieces of at most BIG_UNIT_CHUNK points, one tile each) share
+// the tiles' points out, so a crowded tile is spread over many workgroups:
+//   1. per unit, its cell histogram (LDS) written to uh[unit][cell];
+//   2. per tile, the cells' starts (a scan over the cells of the units' totals)
+//      and each unit's start in every cell, in place in uh;
+//   3. per unit, every point moved to its cell's next slot, with its input index
+//      when pin is given.
+// The order inside a cell is not fixed (LDS atomics rank the points).  Step 3's
+// stores land one point at a time across the tile's range (about 9.6 ms for the
+// 1e8 clustered points of the 512^2-mode cell, a one-time cost); staging each
+// unit in cell order through LDS first, as the tile scatter does, would make them
+// contiguous.
+constexpr int BIG_CS_THREADS = 1024;
+constexpr int BIG_CS_PER = BIG_UNIT_CHUNK / BIG_CS_THREADS;   // points per thread and unit
+
+// The sorted range [k0, k1) of unit u and its tile; false past the last unit.
 template <typename T>
-__global__ __launch_bounds__(1024) void big_cell_sort_kernel(BigSortArgs<T> a, const T *xt, const T *yt, const T *ht,
-                                                             const T *wt, const int32_t *pin, T *xo, T *yo, T *ho,
-                                                             T *wo, int32_t *pout) {
-  __shared__ int cur[BIG_TS2];
+__device__ __forceinline__ bool big_unit_range(const BigSortArgs<T> &a, int u, int &t, int64_t &k0, int64_t &k1) {
+  if (u >= a.unit_base[a.ntiles]) return false;
+  int lo = 0, hi = a.ntiles - 1;   // the largest t with unit_base[t] <= u
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (a.unit_base[mid] <= u) lo = mid;
+    else hi = mid - 1;
+  }
+  t = lo;
+  const int64_t t0 = a.offsets[t], t1 = a.offsets[t + 1];
+  const int64_t c = t0 / BIG_UNIT_CHUNK + (u - a.unit_base[t]);
+  k0 = max(t0, c * BIG_UNIT_CHUNK);
+  k1 = min(t1, (c + 1) * BIG_UNIT_CHUNK);
+  return k0 < k1;
+}
+
+template <typename T>
+__global__ __launch_bounds__(BIG_CS_THREADS) void big_cell_count_kernel(BigSortArgs<T> a, const T *xt, const T *yt,
+                                                                        int *uh) {
+  __shared__ int cnt[BIG_TS2];
+  int t;
+  int64_t k0, k1;
+  if (!big_unit_range<T>(a, blockIdx.x, t, k0, k1)) return;   // the whole workgroup
+  for (int i = threadIdx.x; i < BIG_TS2; i += BIG_CS_THREADS) cnt[i] = 0;
+  __syncthreads();
+  int key[BIG_CS_PER];
+#pragma unroll
+  for (int j = 0; j < BIG_CS_PER; ++j) {   // every load issued before the first add
+    const int64_t k = k0 + threadIdx.x + (int64_t)j * BIG_CS_THREADS;
+    key[j] = k < k1 ? big_key<T>(a, xt[k], yt[k]) % BIG_TS2 : -1;
+  }
+#pragma unroll
+  for (int j = 0; j < BIG_CS_PER; ++j)
+    if (key[j] >= 0) atomicAdd(&cnt[key[j]], 1);
+  __syncthreads();
+  for (int i = threadIdx.x; i < BIG_TS2; i += BIG_CS_THREADS) uh[(int64_t)blockIdx.x * BIG_TS2 + i] = cnt[i];
+}
+
+__global__ __launch_bounds__(BIG_CS_THREADS) void big_cell_scan_kernel(const int64_t *offsets, const int *unit_base,
+                                                                       int *uh) {
+  __shared__ int tot[BIG_TS2];
   __shared__ int wsum[16];
-  const int64_t o0 = a.offsets[blockIdx.x], o1 = a.offsets[blockIdx.x + 1];
-  if (o1 <= o0) return;   // the whole workgroup: an empty tile
-  for (int i = threadIdx.x; i < BIG_TS2; i += blockDim.x) cur[i] = 0;
+  const int t = blockIdx.x, c = threadIdx.x;   // one thread per cell of tile t
+  const int u0 = unit_base[t], u1 = unit_base[t + 1];
+  int n = 0;
+  for (int u = u0; u < u1; ++u) n += uh[(int64_t)u * BIG_TS2 + c];
+  tot[c] = n;
   __syncthreads();
-  for (int64_t k = o0 + threadIdx.x; k < o1; k += blockDim.x) atomicAdd(&cur[big_key<T>(a, xt[k], yt[k]) % BIG_TS2], 1);
+  big_block_scan<BIG_CS_THREADS, int>(tot, tot, BIG_TS2, wsum);
+  int run = (int)offsets[t] + tot[c];
+  for (int u = u0; u < u1; ++u) {
+    int *p = uh + (int64_t)u * BIG_TS2 + c;
+    const int v = *p;
+    *p = run;
+    run += v;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(BIG_CS_THREADS) void big_cell_scatter_kernel(BigSortArgs<T> a, const T *xt, const T *yt,
+                                                                          const T *ht, const T *wt,
+                                                                          const int32_t *pin, const int *uh, T *xo,
+                                                                          T *yo, T *ho, T *wo, int32_t *pout) {
+  __shared__ int cur[BIG_TS2];
+  int t;
+  int64_t k0, k1;
+  if (!big_unit_range<T>(a, blockIdx.x, t, k0, k1)) return;   // the whole workgroup
+  for (int i = threadIdx.x; i < BIG_TS2; i += BIG_CS_THREADS) cur[i] = uh[(int64_t)blockIdx.x * BIG_TS2 + i];
   __syncthreads();
-  big_block_scan<1024, int>(cur, cur, BIG_TS2, wsum);
-  for (int64_t k = o0 + threadIdx.x; k < o1; k += blockDim.x) {
-    const T xk = xt[k], yk = yt[k];
-    const int64_t pos = o0 + atomicAdd(&cur[big_key<T>(a, xk, yk) % BIG_TS2], 1);
-    if (pos >= o1) continue;   // only if the two passes disagreed on a key; never out of the tile's range
-    xo[pos] = xk;
-    yo[pos] = yk;
+  const int64_t e0 = a.offsets[t], e1 = a.offsets[t + 1];
+  T xv[BIG_CS_PER], yv[BIG_CS_PER];
+#pragma unroll
+  for (int j = 0; j < BIG_CS_PER; ++j) {
+    const int64_t k = min(k0 + threadIdx.x + (int64_t)j * BIG_CS_THREADS, k1 - 1);
+    xv[j] = xt[k];
+    yv[j] = yt[k];
+  }
+#pragma unroll
+  for (int j = 0; j < BIG_CS_PER; ++j) {
+    const int64_t k = k0 + threadIdx.x + (int64_t)j * BIG_CS_THREADS;
+    if (k >= k1) continue;
+    const int64_t pos = atomicAdd(&cur[big_key<T>(a, xv[j], yv[j]) % BIG_TS2], 1);
+    if (pos < e0 || pos >= e1) continue;   // only if the passes disagreed on a key; never out of the tile's range
+    xo[pos] = xv[j];
+    yo[pos] = yv[j];
     if (ho) ho[pos] = ht[k];
     if (wo) wo[pos] = wt[k];
     if (pout) pout[pos] = pin[k];
@@ -1695,7 +1775,15 @@ namespace {
 template <typename T>
 enufft_status sort_points_t(enufft_plan_t p, const T *x, const T *y, const T *h, const T *w, T *xs, T *ys, T *hs,
                             T *ws, int32_t *perm) {
-  static_assert(BIG_TS2 == 1024, "big_cell_sort_kernel runs one thread per cell of a tile");
+  static_assert(BIG_TS2 == BIG_CS_THREADS, "the cell scan runs one thread per cell of a tile");
+  static_assert(BIG_CS_PER * BIG_CS_THREADS == BIG_UNIT_CHUNK, "a unit is at most one pass of the workgroup");
+  // the units' cell histograms and starts borrow the spreading sub-grids
+  int *uh = reinterpret_cast<int *>(p->big_partial);
+  if ((size_t)(BIG_TS + p->W + 1) * (BIG_TS + p->W + 1) * sizeof(double) < BIG_TS2 * sizeof(int)) {
+    p->last_error = "enufft_sort_points: unit histograms do not fit the sub-grid buffer";
+    return ENUFFT_EUNSUPPORTED;
+  }
+  const unsigned ublocks = (unsigned)std::max<int64_t>(1, p->big_units_max);
   for (int64_t c = 0; c < p->n_cells; ++c) {
     const int64_t a0 = p->offsets[c], n = p->offsets[c + 1] - a0;
     if (n == 0) continue;
@@ -1711,9 +1799,20 @@ enufft_status sort_points_t(enufft_plan_t p, const T *x, const T *y, const T *h,
       e = hipGetLastError();
     }
     if (e == hipSuccess) {
-      hipLaunchKernelGGL((big_cell_sort_kernel<T>), dim3((unsigned)a.ntiles), dim3(1024), 0, p->stream, a,
+      hipLaunchKernelGGL((big_cell_count_kernel<T>), dim3(ublocks), dim3(BIG_CS_THREADS), 0, p->stream, a,
+                         (const T *)a.xs, (const T *)a.ys, uh);
+      e = hipGetLastError();
+    }
+    if (e == hipSuccess) {
+      hipLaunchKernelGGL(big_cell_scan_kernel, dim3((unsigned)a.ntiles), dim3(BIG_CS_THREADS), 0, p->stream,
+                         (const int64_t *)a.offsets, (const int *)a.unit_base, uh);
+      e = hipGetLastError();
+    }
+    if (e == hipSuccess) {
+      hipLaunchKernelGGL((big_cell_scatter_kernel<T>), dim3(ublocks), dim3(BIG_CS_THREADS), 0, p->stream, a,
                          (const T *)a.xs, (const T *)a.ys, (const T *)a.hs, (const T *)a.ws, (const int32_t *)ptile,
-                         xs + a0, ys + a0, hs ? hs + a0 : nullptr, ws ? ws + a0 : nullptr, perm ? perm + a0 : nullptr);
+                         (const int *)uh, xs + a0, ys + a0, hs ? hs + a0 : nullptr, ws ? ws + a0 : nullptr,
+                         perm ? perm + a0 : nullptr);
       e = hipGetLastError();
     }
     if (e != hipSuccess) return big_fail(p, e, "large-cell point sort");
