@@ -370,13 +370,13 @@ enufft_status enufft_cell_geometry(enufft_plan_t p, const double *tri, const voi
  *   perm            device, n_points int32, or NULL: perm[i] is the input index of the
  *                   sample at sorted position i (a permutation inside each cell).
  * The order of samples that share a fine cell is not specified.  Large-cell plans sort by
- * the 32 x 32 tile of the footprint origin, the order of their tiled spreading, and by
- * fine cell (row-major) inside each tile: their type-1 and adjoint calls sort every call
- * by tile, and skip the sort's scatter when their counting pass finds the input already
- * in tile order; FP32 plans with the kernel polynomial also find whether it is in cell
- * order, and then sum each run of samples with one footprint origin in registers before
- * it reaches the spreading sub-grid.  Batches of 2^31 points or more return
- * ENUFFT_EUNSUPPORTED. */
+ * the 32 x 32 tile of the footprint origin, the order of their tiled spreading (FP32
+ * plans with the kernel polynomial, widths 4, 6 and 8: and by fine cell, row-major,
+ * inside each tile).  Their type-1 and adjoint calls sort every call by tile, and skip
+ * the sort's scatter when their counting pass finds the input already in tile order; the
+ * FP32 ones also find whether it is in cell order, and then sum each run of samples with
+ * one footprint origin in registers before it reaches the spreading sub-grid.  Batches
+ * of 2^31 points or more return ENUFFT_EUNSUPPORTED. */
 enufft_status enufft_sort_points(enufft_plan_t p, const void *x, const void *y, const void *h, const void *w,
                                  void *xs, void *ys, void *hs, void *ws, int32_t *perm);
 
