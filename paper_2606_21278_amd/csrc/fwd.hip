@@ -575,12 +575,45 @@ __global__ __launch_bounds__(NT, (fwd_min_waves<A, NT>())) void fwd_kernel(FwdAr
       run_fft = s_last != 0;
       if (run_fft) {
         __threadfence();
+        // the chunks' grids summed in chunk order (the same order whichever chunk
+        // finishes last); this chunk's own grid is still in LDS.  Each thread
+        // takes MV cells at a time with two chunks' loads in flight (one load at
+        // a time had cost a memory latency per cell and chunk on the critical
+        // path of every split cell).
+        constexpr int MV = 8;
         const T *p0 = a.partial + (int64_t)it.slot0 * nn;
-        for (int i = threadIdx.x; i < nn; i += NT) {
-          T s = T(0);
-          for (int q = 0; q < it.nchunks; ++q) s += p0[(int64_t)q * nn + i];
-          const int r = i / g.n1, c = i - r * g.n1;
-          G[r * pitch + c] = s;
+        const int own = it.slot - it.slot0;
+        // (each thread reads and then writes only its own cells of G)
+        for (int i0 = threadIdx.x; i0 < nn; i0 += MV * NT) {
+          int li[MV];
+          bool in[MV];
+          T sum[MV];
+#pragma unroll
+          for (int v = 0; v < MV; ++v) {
+            in[v] = i0 + v * NT < nn;
+            const int i = in[v] ? i0 + v * NT : i0;
+            const int r = i / g.n1, c = i - r * g.n1;
+            li[v] = r * pitch + c;
+            sum[v] = T(0);
+          }
+          for (int q = 0; q < it.nchunks; q += 2) {
+            const bool two = q + 1 < it.nchunks;
+            T t0[MV], t1[MV];
+#pragma unroll
+            for (int v = 0; v < MV; ++v) {
+              const int i = in[v] ? i0 + v * NT : i0;
+              t0[v] = q == own ? G[li[v]] : p0[(int64_t)q * nn + i];
+              t1[v] = !two ? T(0) : (q + 1 == own ? G[li[v]] : p0[(int64_t)(q + 1) * nn + i]);
+            }
+#pragma unroll
+            for (int v = 0; v < MV; ++v) {
+              sum[v] += t0[v];
+              if (two) sum[v] += t1[v];
+            }
+          }
+#pragma unroll
+          for (int v = 0; v < MV; ++v)
+            if (in[v]) G[li[v]] = sum[v];
         }
         __syncthreads();
       }
