@@ -426,6 +426,7 @@ struct BigTileArgs {
   double *partial;           // spreading: [units][S * S] FP64 sub-grids
   const typename vec4<T>::type *G4;   // gather: n2 x n1 cells of (u, du/dx, du/dy, 0)
   typename vec4<T>::type *gout;       // gather: [n] (dL/dh, dL/dx, dL/dy, 0) in sorted order
+  T *gh, *gx, *gy;                    // gather, input in tile order: the cell's gradients (each may be NULL)
 };
 
 // Persistent loop over the work units; body(t, lo, hi, u) runs unit u, the
@@ -1240,18 +1241,25 @@ __global__ __launch_bounds__(256) void big_gather_kernel(BigTileArgs<T> a) {
       o.y = wh * (dWx * u + Wv * ux);
       o.z = wh * (dWy * u + Wv * uy);
       o.w = T(0);
-      a.gout[k] = o;   // sorted order, coalesced; the unpermute pass puts it at the input index
+      if (pre) {   // the sorted position is the input position: the gradients go straight out
+        if (a.gh) a.gh[k] = o.x;
+        if (a.gx) a.gx[k] = o.y;
+        if (a.gy) a.gy[k] = o.z;
+      } else {
+        a.gout[k] = o;   // sorted order, coalesced; the unpermute pass puts it at the input index
+      }
     }
     __syncthreads();
   });
 }
 
 // Gradients back to input order: one read of the sorted-order record per point
-// (at its sorted position) and coalesced writes of the three outputs.
+// (at its sorted position) and coalesced writes of the three outputs.  Input
+// already in tile order needs none: the gather wrote the gradients itself.
 template <typename T>
 __global__ __launch_bounds__(256) void big_unpermute_kernel(const typename vec4<T>::type *gout, const int *inv,
                                                             const int *presorted, int64_t n, T *gh, T *gx, T *gy) {
-  const bool pre = *presorted;   // sorted order is the input order
+  if (*presorted) return;   // sorted order is the input order: the gather wrote the gradients
   // U points per thread and round, all loads of a round before its stores (the
   // stores could alias the records as far as the compiler knows, so a store
   // between loads would serialise them)
@@ -1264,7 +1272,7 @@ __global__ __launch_bounds__(256) void big_unpermute_kernel(const typename vec4<
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int64_t j = j0 + u * stride;
-      k[u] = j < n ? (pre ? (int)j : inv[j]) : -1;
+      k[u] = j < n ? inv[j] : -1;
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
@@ -1673,6 +1681,9 @@ enufft_status adjoint_t(enufft_plan_t p, const T *x, const T *y, const T *h, con
       BigTileArgs<T> a = tile_args<T>(p, c, x, y, h, w);
       a.G4 = (const V4 *)p->big_gu;
       a.gout = (V4 *)p->big_gout;
+      a.gh = gh ? gh + a0 : nullptr;
+      a.gx = gx ? gx + a0 : nullptr;
+      a.gy = gy ? gy + a0 : nullptr;
       a.work_counter = p->big_work + 2;
       a.done_counter = p->big_work + 3;
       e = by_width<T, GatherW>(p->W, a, tile_blocks(p, n), p->stream);
