@@ -220,10 +220,34 @@ __global__ __launch_bounds__(BIG_SORT_THREADS) void big_count_kernel(BigSortArgs
   __syncthreads();
   const int64_t s = (int64_t)blockIdx.x * BIG_SORT_CHUNK, e = min(a.n, s + BIG_SORT_CHUNK);
   const int cnt = (int)(e - s);
-  for (int64_t j = s + threadIdx.x; j < e; j += blockDim.x) {
-    const int k = big_key<T>(a, a.x[j], a.y[j]);
-    keys[j - s] = k;
-    atomicAdd(&hist[k / BIG_TS2], 1);
+  // CB points per thread and round, every load of a round issued before the
+  // first is used (one memory latency per round, not per point)
+  constexpr int CB = 8;
+  for (int64_t j0 = s + threadIdx.x; j0 < e; j0 += (int64_t)CB * blockDim.x) {
+    T xv[CB], yv[CB];
+#pragma unroll
+    for (int c = 0; c < CB; ++c) {
+      const int64_t j = min(j0 + (int64_t)c * blockDim.x, e - 1);
+      xv[c] = a.x[j];
+      yv[c] = a.y[j];
+    }
+#pragma unroll
+    for (int c = 0; c < CB; ++c) {
+      const int64_t j = j0 + (int64_t)c * blockDim.x;
+      if (j >= e) break;
+      const int k = big_key<T>(a, xv[c], yv[c]);
+      keys[j - s] = k;
+      // a wave whose points all lie in one tile (input in tile order) adds its
+      // count once: 64 adds to one LDS counter are served one after another
+      const int t = k / BIG_TS2;
+      const int t0 = __builtin_amdgcn_readfirstlane(t);
+      const uint64_t act = __ballot(1), same = __ballot(t == t0);
+      if (same == act) {
+        if ((int)(threadIdx.x & 63) == __ffsll((unsigned long long)act) - 1) atomicAdd(&hist[t0], __popcll(act));
+      } else {
+        atomicAdd(&hist[t], 1);
+      }
+    }
   }
   __syncthreads();
   int tdesc = 0, kdesc = 0;
