@@ -380,6 +380,22 @@ enufft_status enufft_cell_geometry(enufft_plan_t p, const double *tri, const voi
 enufft_status enufft_sort_points(enufft_plan_t p, const void *x, const void *y, const void *h, const void *w,
                                  void *xs, void *ys, void *hs, void *ws, int32_t *perm);
 
+/* Bind sample coordinates to the plan (large-cell plans; Section 2.1.2 Step 1: the tiled
+ * spreading's bins depend on x and y only).  Every type-1 and adjoint call of a large-cell
+ * plan otherwise runs the tile sort's counting pass (and its scatter, or its order check)
+ * on x and y; once x and y are bound, calls given exactly these two device pointers use
+ * the tile ranges, work units and order flags computed here and sort nothing; h and w may
+ * change from call to call.
+ *   x, y   device, n_points reals each (the plan's precision), in tile order, as
+ *          enufft_sort_points leaves them; both NULL unbinds.
+ * The contents of x and y must not change while bound: bind again (or unbind) after
+ * writing them.  Returns ENUFFT_EINVAL (and leaves the plan unbound) when a cell's samples
+ * are not in tile order, or when only one of x, y is NULL.  Binding clears a captured
+ * forward graph (the next enufft_forward_graph call captures again).  Plans whose cells fit
+ * LDS sort nothing per call: the call checks its arguments and keeps nothing.  Allocates
+ * 12 bytes per tile and cell on the first call (freed by enufft_destroy). */
+enufft_status enufft_bind_points(enufft_plan_t p, const void *x, const void *y);
+
 /* Plain per-cell form of type-1 + EMS for comparison: the same kernels,
  * launched once per cell from a host loop on the plan's stream (no batching,
  * no graph).  Arguments as enufft_type1_batched and enufft_ems. */

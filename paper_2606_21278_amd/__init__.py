@@ -78,7 +78,7 @@ EXPORTS = ["enufft_default_opts", "enufft_plan", "enufft_set_stream", "enufft_ty
            "enufft_type1_batched_noalloc", "enufft_ems",
            "enufft_ems_flow",
            "enufft_type1_adjoint", "enufft_retained_power_adjoint", "enufft_reconstruct", "enufft_cell_geometry", "enufft_sort_points",
-           "enufft_percell_loop",
+           "enufft_bind_points", "enufft_percell_loop",
            "enufft_forward_graph", "enufft_set_timing", "enufft_get_timing",
            "enufft_get_info", "enufft_destroy", "enufft_last_error", "enufft_version"]
 
@@ -108,6 +108,7 @@ def load_library(path: str = LIB_PATH):
     L.enufft_reconstruct.argtypes = [vp] * 10
     L.enufft_cell_geometry.argtypes = [vp] * 5 + [ctypes.POINTER(GeometryOptsC)] + [vp] * 7
     L.enufft_sort_points.argtypes = [vp] * 10
+    L.enufft_bind_points.argtypes = [vp] * 3
     L.enufft_percell_loop.argtypes = [vp] * 6 + [ctypes.POINTER(EmsParamsC), vp, vp, vp, vp]
     L.enufft_forward_graph.argtypes = [vp] * 6 + [ctypes.POINTER(EmsParamsC), vp, vp, vp, vp]
     L.enufft_set_timing.argtypes = [vp, i32]
@@ -206,6 +207,7 @@ class Plan:
                                        wins, ctypes.byref(opts), ctypes.c_void_p(s.cuda_stream))
             _check(st, None)
         self._h = h
+        self._bound = None   # (x, y) bound by bind_points, kept referenced
 
     # -- helpers
     def _sync_stream(self):
@@ -347,6 +349,27 @@ class Plan:
         _check(self._lib.enufft_sort_points(self._h, _ptr(x), _ptr(y), _ptr(h), _ptr(w), _ptr(xs), _ptr(ys),
                                             _ptr(hs), _ptr(ws), _ptr(perm)), self._h)
         return xs, ys, hs, ws, perm
+
+    def bind_points(self, x, y):
+        """Bind tile-ordered coordinates (enufft_bind_points): later type-1 and adjoint
+        calls given these same tensors skip the large-cell tile sort.  Their contents must
+        not change while bound.  None, None unbinds.  The tensors are kept referenced while
+        bound, so their memory cannot be reused by others."""
+        if (x is None) != (y is None):
+            raise ValueError("x and y are both given (bind) or both None (unbind)")
+        for v in (x, y):
+            if v is not None and (v.dtype != self.dtype or v.device != self.device or not v.is_contiguous()
+                                  or v.numel() != self.n_points):
+                raise ValueError("x, y must be contiguous %s of length %d on %s"
+                                 % (self.dtype, self.n_points, self.device))
+        self._sync_stream()
+        self._bound = None
+        _check(self._lib.enufft_bind_points(self._h, _ptr(x), _ptr(y)), self._h)
+        self._bound = (x, y) if x is not None else None
+
+    def unbind_points(self):
+        """Drop a binding made by bind_points."""
+        self.bind_points(None, None)
 
     def cell_geometry(self, tri, x, y, h, frame="edge", mask="triangle", weights="uniform", raster=64, eta=1.0,
                       floor_frac=0.5, deplane=True, need_inside=True, need_info=True, need_counts=False):

@@ -1526,15 +1526,32 @@ hipError_t sort_cell(enufft_plan_t p, int64_t c, const T *x, const T *y, const T
   return sort_launch<T>(p, sort_args<T>(p, c, x, y, h, w));
 }
 
+// The tile ranges, unit offsets and order flags a call uses for cell c: those
+// that enufft_bind_points stored when x and y are the bound arrays (the call
+// then sorts nothing), else the plan's, which the call's own sort fills.
+struct CellMeta {
+  int64_t *offsets;
+  int *unit_base;
+  int *flags;
+  bool bound;
+};
+CellMeta cell_meta(enufft_plan_t p, int64_t c, const void *x, const void *y) {
+  const int64_t nt1 = (int64_t)p->big_ntx * p->big_nty + 1;
+  if (p->bound_x && x == p->bound_x && y == p->bound_y)
+    return CellMeta{p->bound_offsets + c * nt1, p->bound_unit_base + c * nt1, p->bound_flags + 4 * c, true};
+  return CellMeta{p->big_offsets, p->big_unit_base, p->big_flags, false};
+}
+
 template <typename T>
-BigTileArgs<T> tile_args(enufft_plan_t p, int64_t c, const T *x, const T *y, const T *h, const T *w) {
+BigTileArgs<T> tile_args(enufft_plan_t p, int64_t c, const T *x, const T *y, const T *h, const T *w,
+                         const CellMeta &m) {
   BigTileArgs<T> a{};
   a.xs = (const T *)p->big_xs; a.ys = (const T *)p->big_ys; a.hs = (const T *)p->big_hs; a.ws = (const T *)p->big_ws;
   const int64_t a0 = p->offsets[c];
   a.xi = x + a0; a.yi = y + a0; a.hi = h + a0; a.wi = w + a0;
-  a.presorted = p->big_flags;
-  a.offsets = p->big_offsets;
-  a.unit_base = p->big_unit_base;
+  a.presorted = m.flags;
+  a.offsets = m.offsets;
+  a.unit_base = m.unit_base;
   a.ntiles = p->big_ntx * p->big_nty;
   a.ntx = p->big_ntx;
   a.n = p->offsets[c + 1] - p->offsets[c];
@@ -1642,9 +1659,10 @@ enufft_status type1_t(enufft_plan_t p, const T *x, const T *y, const T *h, const
     if (n == 0) {
       e = fill<double>(p->big_grid, n12, 0.0, p->stream);
     } else {
-      e = sort_cell<T>(p, c, x, y, h, w);
+      const CellMeta m = cell_meta(p, c, x, y);
+      if (!m.bound) e = sort_cell<T>(p, c, x, y, h, w);
       if (e == hipSuccess) {
-        BigTileArgs<T> a = tile_args<T>(p, c, x, y, h, w);
+        BigTileArgs<T> a = tile_args<T>(p, c, x, y, h, w, m);
         a.partial = p->big_partial;
         a.work_counter = p->big_work;
         a.done_counter = p->big_work + 1;
@@ -1657,7 +1675,7 @@ enufft_status type1_t(enufft_plan_t p, const T *x, const T *y, const T *h, const
       }
       if (e == hipSuccess) {
         hipLaunchKernelGGL(big_assemble_kernel, dim3((unsigned)((n12 + 255) / 256)), dim3(256), 0, p->stream,
-                           (const double *)p->big_partial, (const int *)p->big_unit_base, g, p->big_ntx, p->big_nty,
+                           (const double *)p->big_partial, (const int *)m.unit_base, g, p->big_ntx, p->big_nty,
                            BIG_TS + p->W + 1, p->big_grid);
         e = hipGetLastError();
       }
@@ -1688,7 +1706,8 @@ enufft_status adjoint_t(enufft_plan_t p, const T *x, const T *y, const T *h, con
   for (int64_t c = 0; c < p->n_cells; ++c) {
     const int64_t a0 = p->offsets[c], n = p->offsets[c + 1] - a0;
     if (n == 0) continue;
-    hipError_t e = sort_cell<T>(p, c, x, y, h, w);
+    const CellMeta m = cell_meta(p, c, x, y);
+    hipError_t e = m.bound ? hipSuccess : sort_cell<T>(p, c, x, y, h, w);
     if (e == hipSuccess) {
       hipLaunchKernelGGL((big_adj_cols_kernel<T>), dim3(g.K1 + 1), dim3(stock_threads(g.n2)), 4 * (size_t)g.n2 * el,
                          p->stream, fin + c * M * 2, keep ? keep + c * M : nullptr, lam, c, g, (const T *)p->d_tw2,
@@ -1702,7 +1721,7 @@ enufft_status adjoint_t(enufft_plan_t p, const T *x, const T *y, const T *h, con
       e = hipGetLastError();
     }
     if (e == hipSuccess) {
-      BigTileArgs<T> a = tile_args<T>(p, c, x, y, h, w);
+      BigTileArgs<T> a = tile_args<T>(p, c, x, y, h, w, m);
       a.G4 = (const V4 *)p->big_gu;
       a.gout = (V4 *)p->big_gout;
       a.gh = gh ? gh + a0 : nullptr;
@@ -1715,7 +1734,7 @@ enufft_status adjoint_t(enufft_plan_t p, const T *x, const T *y, const T *h, con
     if (e == hipSuccess) {
       const int blocks = (int)std::min<int64_t>(8192, (n + 255) / 256);
       hipLaunchKernelGGL((big_unpermute_kernel<T>), dim3(blocks), dim3(256), 0, p->stream, (const V4 *)p->big_gout,
-                         (const int *)p->big_inv, (const int *)p->big_flags, n, gh ? gh + a0 : nullptr, gx ? gx + a0 : nullptr,
+                         (const int *)p->big_inv, (const int *)m.flags, n, gh ? gh + a0 : nullptr, gx ? gx + a0 : nullptr,
                          gy ? gy + a0 : nullptr);
       e = hipGetLastError();
     }
@@ -1882,6 +1901,82 @@ enufft_status big_sort_points(enufft_plan_t p, const void *x, const void *y, con
                                  (double *)xs, (double *)ys, (double *)hs, (double *)ws, perm);
   return sort_points_t<float>(p, (const float *)x, (const float *)y, (const float *)h, (const float *)w, (float *)xs,
                               (float *)ys, (float *)hs, (float *)ws, perm);
+}
+
+namespace {
+// The counting pass, group sums and tile scan of cell c (no scatter): tile
+// ranges, unit offsets and order flags into m.
+template <typename T>
+hipError_t bind_cell(enufft_plan_t p, int64_t c, const T *x, const T *y, const CellMeta &m) {
+  BigSortArgs<T> a = sort_args<T>(p, c, x, y, nullptr, x);
+  a.offsets = m.offsets;
+  a.unit_base = m.unit_base;
+  a.presorted = m.flags;
+  const dim3 tg((a.ntiles + 255) / 256, a.ngroups);
+  hipLaunchKernelGGL((big_count_kernel<T>), dim3(a.nchunks), dim3(BIG_SORT_THREADS), count_lds(a.ntiles),
+                     p->stream, a);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(big_group_sum_kernel, tg, dim3(256), 0, p->stream, (const int *)a.chunk_hist, a.nchunks,
+                       a.ntiles, a.group_sum);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(big_tile_scan_kernel, dim3(1), dim3(1024), (size_t)a.ntiles * sizeof(int), p->stream,
+                       a.group_sum, a.ngroups, a.ntiles, a.offsets, a.unit_base, (const int *)a.chunk_fl, a.nchunks,
+                       a.presorted);
+    e = hipGetLastError();
+  }
+  return e;
+}
+}  // namespace
+
+enufft_status big_bind_points(enufft_plan_t p, const void *x, const void *y) {
+  p->bound_x = p->bound_y = nullptr;   // unbound while (re)binding, and for good if it fails
+  p->graph_key.clear();                // a captured forward graph holds the sort as it was: capture again
+  if (!x) return ENUFFT_OK;
+  const int64_t nt1 = (int64_t)p->big_ntx * p->big_nty + 1;
+  if (p->bound_cap < p->n_cells) {
+    const size_t bytes[3] = {(size_t)(p->n_cells * nt1) * sizeof(int64_t), (size_t)(p->n_cells * nt1) * sizeof(int),
+                             (size_t)(p->n_cells * 4) * sizeof(int)};
+    void **ptrs[3] = {(void **)&p->bound_offsets, (void **)&p->bound_unit_base, (void **)&p->bound_flags};
+    for (int i = 0; i < 3; ++i) {
+      void *q = nullptr;
+      const hipError_t e = hipMalloc(&q, bytes[i]);
+      if (e != hipSuccess) {
+        p->last_error = std::string("enufft_bind_points: hipMalloc: ") + hipGetErrorString(e);
+        return ENUFFT_ENOMEM;
+      }
+      p->allocations.push_back(q);   // freed with the plan (a smaller earlier set stays until then)
+      p->workspace_bytes += (int64_t)bytes[i];
+      *ptrs[i] = q;
+    }
+    p->bound_cap = p->n_cells;
+  }
+  std::vector<int> flags((size_t)p->n_cells * 4, 1);
+  hipError_t e = hipSuccess;
+  for (int64_t c = 0; c < p->n_cells && e == hipSuccess; ++c) {
+    if (p->offsets[c + 1] == p->offsets[c]) {   // empty: no spreading, nothing to bind
+      e = hipMemcpyAsync(p->bound_flags + 4 * c, flags.data(), 4 * sizeof(int), hipMemcpyHostToDevice, p->stream);
+      continue;
+    }
+    const CellMeta m{p->bound_offsets + c * nt1, p->bound_unit_base + c * nt1, p->bound_flags + 4 * c, true};
+    e = p->prec == ENUFFT_F64 ? bind_cell<double>(p, c, (const double *)x, (const double *)y, m)
+                              : bind_cell<float>(p, c, (const float *)x, (const float *)y, m);
+  }
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(flags.data(), p->bound_flags, flags.size() * sizeof(int), hipMemcpyDeviceToHost, p->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+  if (e != hipSuccess) return big_fail(p, e, "enufft_bind_points");
+  for (int64_t c = 0; c < p->n_cells; ++c)
+    if (!flags[(size_t)4 * c]) {
+      p->last_error = "enufft_bind_points: the samples of cell " + std::to_string(c) +
+                      " are not in tile order (sort them once with enufft_sort_points)";
+      return ENUFFT_EINVAL;
+    }
+  p->bound_x = x;
+  p->bound_y = y;
+  return ENUFFT_OK;
 }
 
 enufft_status big_type1(enufft_plan_t p, const void *x, const void *y, const void *h, const void *w, void *f,

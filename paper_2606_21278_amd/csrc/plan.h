@@ -105,6 +105,13 @@ struct enufft_plan_s {
   int *big_inv = nullptr;                    // [largest cell] sorted position of each input point
   int *big_chunk_fl = nullptr;               // [chunks][4] first and last key, descent flags of each sort chunk
   int *big_flags = nullptr;                  // [0]: the current cell's input is in tile order, [1]: and by cell
+  // enufft_bind_points: coordinate arrays bound in tile order (large cells) and,
+  // per cell, their tile ranges, unit offsets and order flags
+  const void *bound_x = nullptr, *bound_y = nullptr;
+  int64_t *bound_offsets = nullptr;          // [cells][tiles + 1]
+  int *bound_unit_base = nullptr;            // [cells][tiles + 1]
+  int *bound_flags = nullptr;                // [cells][4]
+  int64_t bound_cap = 0;                     // cells the bound arrays hold
   void *big_xs = nullptr, *big_ys = nullptr, *big_hs = nullptr, *big_ws = nullptr;
   double *big_partial = nullptr;             // [units][S x S] FP64 sub-grids of the spreading units
   int64_t big_units_max = 0;
@@ -155,6 +162,7 @@ enufft_status big_type1(enufft_plan_t p, const void *x, const void *y, const voi
                         int64_t c0, int64_t c1);
 enufft_status big_adjoint(enufft_plan_t p, const void *x, const void *y, const void *h, const void *w,
                           const void *fin, const uint8_t *keep, const double *lam, void *gh, void *gx, void *gy);
+enufft_status big_bind_points(enufft_plan_t p, const void *x, const void *y);
 enufft_status big_sort_points(enufft_plan_t p, const void *x, const void *y, const void *h, const void *w, void *xs,
                               void *ys, void *hs, void *ws, int32_t *perm);
 enufft_status big_ems(enufft_plan_t p, const void *f, const enufft_ems_params *prm, const double *mode_weight,

@@ -150,3 +150,16 @@ extern "C" enufft_status enufft_sort_points(enufft_plan_t p, const void *x, cons
   }
   return ENUFFT_OK;
 }
+
+extern "C" enufft_status enufft_bind_points(enufft_plan_t p, const void *x, const void *y) {
+  using namespace enufft;
+  enufft_status st = check_plan(p, "enufft_bind_points");
+  if (st != ENUFFT_OK) return st;
+  if ((x == nullptr) != (y == nullptr)) {
+    p->last_error = "enufft_bind_points: x and y are both given (bind) or both NULL (unbind)";
+    return ENUFFT_EINVAL;
+  }
+  // cells that fit LDS sort nothing per call: there is nothing to keep
+  if (!p->big || p->n_points == 0) return ENUFFT_OK;
+  return big_bind_points(p, x, y);
+}

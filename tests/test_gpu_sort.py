@@ -192,3 +192,41 @@ def test_large_cell_runs_fp32(eps):
     print("rel-l2 against the oracle %.2e, against point-by-point %.2e" % (e1, e01), flush=True)
     assert e1 <= tol
     assert e01 <= 2e-6
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_large_cell_bound_points(prec):
+    """enufft_bind_points: tile-ordered coordinates bound once; calls given exactly those
+    tensors skip the tile sort and give the results of the unbound calls, with h changed
+    between calls; unsorted coordinates are refused (the plan stays unbound); one of the
+    two bound tensors alone is not the binding; unbinding restores the sorting calls."""
+    b = synth.config4(Q=200000, precision=prec, n_modes=(128, 96))
+    if prec == "f64":
+        b.eps = 1e-10
+    gb = gpu_batch(b)
+    plan = make_plan(gb)
+    xs, ys, hs, ws, _ = plan.sort_points(gb.x, gb.y, gb.h, gb.w, need_perm=False)
+    f0 = plan.type1(xs, ys, hs, ws)
+    keep = torch.ones(f0.shape, dtype=torch.uint8, device="cuda:0")
+    f0h = plan.type1(xs, ys, 2 * hs, ws)
+    g0 = plan.retained_power_adjoint(xs, ys, hs, ws, f0, keep)
+    with pytest.raises(enf.EnufftError) as e:
+        plan.bind_points(gb.x, gb.y)   # as generated: not in tile order
+    assert e.value.status == enf.EINVAL
+    plan.bind_points(xs, ys)
+    f1 = plan.type1(xs, ys, hs, ws)
+    f1h = plan.type1(xs, ys, 2 * hs, ws)
+    g1 = plan.retained_power_adjoint(xs, ys, hs, ws, f0, keep)
+    ys2 = ys.clone()
+    f2 = plan.type1(xs, ys2, hs, ws)   # y is another tensor: sorted as usual
+    plan.unbind_points()
+    f3 = plan.type1(xs, ys, hs, ws)
+    torch.cuda.synchronize()
+    lim = 1e-6 if prec == "f32" else 1e-13
+    for f, ref in ((f1, f0), (f1h, f0h), (f2, f0), (f3, f0)):
+        assert rel_l2(f.cpu().numpy(), ref.cpu().numpy()) <= lim
+    for a, c in zip(g1, g0):
+        assert rel_l2(a.cpu().numpy(), c.cpu().numpy()) <= lim
+    assert rel_l2(f0.cpu().numpy(), oracle_f(b)) <= TOL[prec]
+    with pytest.raises(ValueError):
+        plan.bind_points(xs, None)
