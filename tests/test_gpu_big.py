@@ -244,7 +244,11 @@ def test_full_c4_sampled(prec):
                                          rng.choice(np.arange(lo2 + 1, lo2 + N2 - 1), nr - 2, replace=False)])))]
     for name, (kxl, kyl) in zip(("central", "random rows x columns"), blocks):
         print("oracle: direct sums on %s, %d x %d modes" % (name, len(kyl), len(kxl)), flush=True)
-        ref = oracle.type1_axes(x, y, c, kxl, kyl)
+        parts = []
+        for r0 in range(0, len(kyl), 8):   # a few rows at a time, each reported when done
+            parts.append(oracle.type1_axes(x, y, c, kxl, kyl[r0:r0 + 8]))
+            print("  rows %d..%d of %d done" % (r0, min(len(kyl), r0 + 8) - 1, len(kyl)), flush=True)
+        ref = np.concatenate(parts, axis=0)
         got = fg[np.ix_(kyl - lo2, kxl - lo1)]
         err = rel_l2(got, ref)
         print("%s rel-l2 %.3e" % (name, err), flush=True)
