@@ -1322,12 +1322,8 @@ __global__ __launch_bounds__(256) void big_unpermute_kernel(const typename vec4<
 //   2. per tile, the cells' starts (a scan over the cells of the units' totals)
 //      and each unit's start in every cell, in place in uh;
 //   3. per unit, every point moved to its cell's next slot, with its input index
-//      when pin is given.
-// The order inside a cell is not fixed (LDS atomics rank the points).  Step 3's
-// stores land one point at a time across the tile's range (about 9.6 ms for the
-// 1e8 clustered points of the 512^2-mode cell, a one-time cost); staging each
-// unit in cell order through LDS first, as the tile scatter does, would make them
-// contiguous.
+//      when pin is given, through LDS in cell order (below).
+// The order inside a cell is not fixed (LDS atomics rank the points).
 constexpr int BIG_CS_THREADS = 1024;
 constexpr int BIG_CS_PER = BIG_UNIT_CHUNK / BIG_CS_THREADS;   // points per thread and unit
 
@@ -1391,36 +1387,76 @@ __global__ __launch_bounds__(BIG_CS_THREADS) void big_cell_scan_kernel(const int
   }
 }
 
+// Step 3, staged: the unit in sub-chunks of SUB points, each loaded once
+// (coalesced), ranked inside its cells (LDS counts, their scan), placed in LDS in
+// cell order, and written out with consecutive threads on consecutive slots of
+// each cell's range, so a cell's points leave as contiguous stores.
 template <typename T>
 __global__ __launch_bounds__(BIG_CS_THREADS) void big_cell_scatter_kernel(BigSortArgs<T> a, const T *xt, const T *yt,
                                                                           const T *ht, const T *wt,
                                                                           const int32_t *pin, const int *uh, T *xo,
                                                                           T *yo, T *ho, T *wo, int32_t *pout) {
-  __shared__ int cur[BIG_TS2];
+  constexpr int SUB = sizeof(T) == 4 ? 2048 : 1024;
+  constexpr int PT = SUB / BIG_CS_THREADS;
+  static_assert(BIG_TS2 == BIG_CS_THREADS && PT >= 1, "one thread per cell of a tile");
+  using V4 = typename vec4<T>::type;
+  __shared__ int cur[BIG_TS2];   // this unit's next global slot in each cell
+  __shared__ int lh[BIG_TS2];    // the sub-chunk's count per cell, then its start in the staged order
+  __shared__ int wsum[16];
+  __shared__ V4 st[SUB];         // the sub-chunk in cell order
+  __shared__ int sk[SUB], sp[SUB];
   int t;
   int64_t k0, k1;
   if (!big_unit_range<T>(a, blockIdx.x, t, k0, k1)) return;   // the whole workgroup
-  for (int i = threadIdx.x; i < BIG_TS2; i += BIG_CS_THREADS) cur[i] = uh[(int64_t)blockIdx.x * BIG_TS2 + i];
-  __syncthreads();
+  const int c = threadIdx.x;   // the cell this thread keeps the counts of
+  cur[c] = uh[(int64_t)blockIdx.x * BIG_TS2 + c];
   const int64_t e0 = a.offsets[t], e1 = a.offsets[t + 1];
-  T xv[BIG_CS_PER], yv[BIG_CS_PER];
+  for (int64_t p0 = k0; p0 < k1; p0 += SUB) {
+    const int m = (int)min<int64_t>(SUB, k1 - p0);
+    lh[c] = 0;
+    __syncthreads();
+    V4 v[PT];
+    int key[PT], rk[PT], pi[PT];
 #pragma unroll
-  for (int j = 0; j < BIG_CS_PER; ++j) {
-    const int64_t k = min(k0 + threadIdx.x + (int64_t)j * BIG_CS_THREADS, k1 - 1);
-    xv[j] = xt[k];
-    yv[j] = yt[k];
-  }
+    for (int j = 0; j < PT; ++j) {   // every load issued before the first is used
+      const int q = min(c + j * BIG_CS_THREADS, m - 1);
+      v[j].x = xt[p0 + q];
+      v[j].y = yt[p0 + q];
+      v[j].z = ht[p0 + q];
+      v[j].w = wt[p0 + q];
+      pi[j] = pin ? pin[p0 + q] : 0;
+    }
 #pragma unroll
-  for (int j = 0; j < BIG_CS_PER; ++j) {
-    const int64_t k = k0 + threadIdx.x + (int64_t)j * BIG_CS_THREADS;
-    if (k >= k1) continue;
-    const int64_t pos = atomicAdd(&cur[big_key<T>(a, xv[j], yv[j]) % BIG_TS2], 1);
-    if (pos < e0 || pos >= e1) continue;   // only if the passes disagreed on a key; never out of the tile's range
-    xo[pos] = xv[j];
-    yo[pos] = yv[j];
-    if (ho) ho[pos] = ht[k];
-    if (wo) wo[pos] = wt[k];
-    if (pout) pout[pos] = pin[k];
+    for (int j = 0; j < PT; ++j) {
+      const bool on = c + j * BIG_CS_THREADS < m;
+      key[j] = big_key<T>(a, v[j].x, v[j].y) % BIG_TS2;
+      rk[j] = on ? atomicAdd(&lh[key[j]], 1) : 0;
+    }
+    __syncthreads();
+    const int mine = lh[c];
+    big_block_scan<BIG_CS_THREADS, int>(lh, lh, BIG_TS2, wsum);
+#pragma unroll
+    for (int j = 0; j < PT; ++j) {
+      if (c + j * BIG_CS_THREADS >= m) continue;
+      const int slot = lh[key[j]] + rk[j];   // < m: the rank is below the cell's count
+      st[slot] = v[j];
+      sk[slot] = key[j];
+      sp[slot] = pi[j];
+    }
+    __syncthreads();
+    for (int i = c; i < m; i += BIG_CS_THREADS) {
+      const int ki = sk[i];
+      const int64_t pos = (int64_t)cur[ki] + (i - lh[ki]);
+      if (pos < e0 || pos >= e1) continue;   // only if the passes disagreed on a key; never out of the tile's range
+      const V4 w4 = st[i];
+      xo[pos] = w4.x;
+      yo[pos] = w4.y;
+      if (ho) ho[pos] = w4.z;
+      if (wo) wo[pos] = w4.w;
+      if (pout) pout[pos] = sp[i];
+    }
+    __syncthreads();
+    cur[c] += mine;
   }
 }
 
