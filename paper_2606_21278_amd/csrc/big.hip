@@ -915,14 +915,43 @@ __device__ V big_block_excl_scan(V v, V *wred) {
   return base + inc - v;
 }
 
+// Term j of eq. (s_delta): the exponential of the relative gap between sorted
+// energies j and j + 1 (1 for two zeros, 0 before a zero).
+__device__ __forceinline__ double big_sdelta_term(double ea, double eb, double delta) {
+  if (eb == 0.0 && ea == 0.0) return 1.0;
+  if (eb == 0.0) return 0.0;
+  return exp(-(ea / eb - 1.0) / delta);
+}
+
+// The sum of eq. (s_delta)'s terms over the first J_max - 1 gaps, in parts: block b
+// sums the terms of its range of sorted positions into tpart[b] (all CUs share
+// the exponentials; one workgroup had spent most of the scores pass on them).
+constexpr int BIG_TERM_BLOCKS = 256;
+__global__ __launch_bounds__(256) void big_ems_terms_kernel(const double *S, int J, enufft_ems_params prm,
+                                                            double *tpart) {
+  __shared__ double wred[4];
+  const int Jmax = J < prm.k_max ? J : prm.k_max;
+  const int n = max(0, Jmax - 1);
+  const int chunk = (n + BIG_TERM_BLOCKS - 1) / BIG_TERM_BLOCKS;
+  const int lo = min(n, (int)blockIdx.x * chunk), hi = min(n, lo + chunk);
+  double sd = 0.0;
+  for (int j = lo + threadIdx.x; j < hi; j += blockDim.x) sd += big_sdelta_term(S[j], S[j + 1], prm.delta);
+  sd = big_block_sum(sd, wred);
+  if (threadIdx.x == 0) tpart[blockIdx.x] = sd;
+}
+
 // Scores over the sorted energies (one workgroup of 1024 threads, each owning
-// a contiguous run of sorted positions): eqs. (n_eff), (s_delta), (c_score),
-// (alpha_c), (f_cum) and (k_elastic), as in the per-cell kernel.
+// a contiguous run of sorted positions, read eight at a time with the loads of
+// a batch issued together): eqs. (n_eff), (c_score), (alpha_c), (f_cum) and
+// (k_elastic), as in the per-cell kernel, with eq. (s_delta) from the parts.
+constexpr int BIG_SCORE_BATCH = 8;
 __global__ __launch_bounds__(1024) void big_ems_scores_kernel(const double *S, const double *partial, int nparts,
-                                                              int J, enufft_ems_params prm, BigCut *cut) {
+                                                              const double *tpart, int J, enufft_ems_params prm,
+                                                              BigCut *cut) {
   __shared__ double wred[16];
   __shared__ int wredi[16];
   __shared__ int s_kc;
+  constexpr int B = BIG_SCORE_BATCH;
   const int t = threadIdx.x;
   if (t == 0) s_kc = INT_MAX;
   double pa = 0.0, pb = 0.0;
@@ -935,31 +964,39 @@ __global__ __launch_bounds__(1024) void big_ems_scores_kernel(const double *S, c
   const int Jmax = J < prm.k_max ? J : prm.k_max;
   const double neff = T2 > 0.0 ? T1 * T1 / T2 : 0.0;
   const double nclip = neff < (double)Jmax ? neff : (double)Jmax;
-  const int per = (J + 1023) / 1024;
-  const int j0 = min(J, t * per), j1 = min(J, j0 + per);
-  double sd = 0.0;
-  for (int j = j0; j < j1 && j < Jmax - 1; ++j) {
-    const double ea = S[j], eb = S[j + 1];
-    double term;
-    if (eb == 0.0 && ea == 0.0) term = 1.0;
-    else if (eb == 0.0) term = 0.0;
-    else term = exp(-(ea / eb - 1.0) / prm.delta);
-    sd += term;
-  }
-  const double sdsum = big_block_sum(sd, wred);
+  const double sdsum = big_block_sum(t < BIG_TERM_BLOCKS ? tpart[t] : 0.0, wred);
   const double sdel = Jmax < 2 ? 1.0 : sdsum / (double)(Jmax - 1);
   const double Cs = (Jmax > 0 ? prm.w1 * nclip / (double)Jmax : 0.0) + prm.w2 * sdel;
   const double alphaC = prm.alpha_min + (prm.alpha_max - prm.alpha_min) * Cs;
+  const int per = (J + 1023) / 1024;
+  const int j0 = min(J, t * per), j1 = min(J, j0 + per);
+  auto batch = [&](int jb, double (&v)[B]) {
+#pragma unroll
+    for (int q = 0; q < B; ++q) v[q] = S[min(jb + q, j1 - 1)];   // j1 > jb >= j0 here
+  };
   // running sum: per-thread totals, an exclusive scan in thread order, then the threshold
   double loc = 0.0;
-  for (int j = j0; j < j1; ++j) loc += S[j];
+  for (int jb = j0; jb < j1; jb += B) {
+    double v[B];
+    batch(jb, v);
+#pragma unroll
+    for (int q = 0; q < B; ++q)
+      if (jb + q < j1) loc += v[q];
+  }
   double run = big_block_excl_scan(loc, wred);
   if (T1 > 0.0) {
-    for (int j = j0; j < j1; ++j) {
-      run += S[j];
-      if (run / T1 >= alphaC) {
-        atomicMin(&s_kc, j + 1);
-        break;
+    bool found = false;
+    for (int jb = j0; jb < j1 && !found; jb += B) {
+      double v[B];
+      batch(jb, v);
+#pragma unroll
+      for (int q = 0; q < B; ++q) {
+        if (found || jb + q >= j1) continue;
+        run += v[q];
+        if (run / T1 >= alphaC) {
+          atomicMin(&s_kc, jb + q + 1);
+          found = true;
+        }
       }
     }
   }
@@ -975,11 +1012,17 @@ __global__ __launch_bounds__(1024) void big_ems_scores_kernel(const double *S, c
   const double eth = kstar > 0 ? S[kstar - 1] : 0.0;
   double part = 0.0;
   int cgt = 0, ceq = 0;
-  for (int j = j0; j < j1; ++j) {
-    const double v = S[j];
-    if (j < kstar) part += v;
-    cgt += v > eth;
-    ceq += v == eth;
+  for (int jb = j0; jb < j1; jb += B) {
+    double v[B];
+    batch(jb, v);
+#pragma unroll
+    for (int q = 0; q < B; ++q) {
+      const int j = jb + q;
+      if (j >= j1) continue;
+      if (j < kstar) part += v[q];
+      cgt += v[q] > eth;
+      ceq += v[q] == eth;
+    }
   }
   const double th = big_block_sum(part, wred);
   const int ngt = big_block_sum(cgt, wredi);
@@ -2080,9 +2123,16 @@ enufft_status big_ems(enufft_plan_t p, const void *f, const enufft_ems_params *p
         e = hipGetLastError();
       }
     }
+    // the parts of eq. (s_delta) go where the tie flags go later (Jpad >= 8,192 bytes there)
+    double *tpart = reinterpret_cast<double *>(tie);
+    if (e == hipSuccess) {
+      hipLaunchKernelGGL(big_ems_terms_kernel, dim3(BIG_TERM_BLOCKS), dim3(256), 0, p->stream, (const double *)S, J,
+                         *prm, tpart);
+      e = hipGetLastError();
+    }
     if (e == hipSuccess) {
       hipLaunchKernelGGL(big_ems_scores_kernel, dim3(1), dim3(1024), 0, p->stream, (const double *)S,
-                         (const double *)partial, nb, J, *prm, cut);
+                         (const double *)partial, nb, (const double *)tpart, J, *prm, cut);
       e = hipGetLastError();
     }
     if (e == hipSuccess) {
