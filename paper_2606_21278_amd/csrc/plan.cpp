@@ -344,10 +344,15 @@ void dev_release(enufft_plan_t p, void **ptr, size_t bytes) {
   p->workspace_bytes -= (int64_t)(bytes == 0 ? 16 : bytes);
 }
 
-// Forward work list.  Target chunk size T keeps roughly two items per resident
-// workgroup so the largest cells do not leave CUs idle; cells above T are cut
-// into near-equal chunks whose partial grids are merged.  The batched list is
-// ordered by decreasing size (longest first), the per-cell list by cell.
+// Forward work lists.  Batched: target chunk size T keeps roughly two items per
+// resident workgroup so the largest cells do not leave CUs idle; cells above T
+// are cut into near-equal chunks whose partial grids are merged; ordered by
+// decreasing size (longest first).  Per-cell loop: one launch per cell, the
+// cell cut into chunks of at least kPercellChunkMin points so that a cell's
+// launch occupies up to every resident workgroup (below that size a chunk's
+// fixed costs, zeroing, folding and writing a whole grid, outweigh its points).
+constexpr int64_t kPercellChunkMin = 4096;
+
 void build_fwd_schedule(enufft_plan_t p, int slots) {
   const int64_t Q = p->n_points;
   const int64_t per = (int64_t)p->fwd_items_per_slot * std::max(1, slots);
@@ -355,30 +360,42 @@ void build_fwd_schedule(enufft_plan_t p, int slots) {
   p->fwd_items.clear();
   p->fwd_items_cell.clear();
   p->fwd_cell_first.assign(p->n_cells + 1, 0);
-  int64_t slot = 0, nsplit = 0;
+  int64_t slot = 0, nsplit = 0, pc_slots = 1;
   for (int64_t c = 0; c < p->n_cells; ++c) {
     const int64_t a = p->offsets[c], b = p->offsets[c + 1];
     const int64_t q = b - a;
+    // batched schedule: chunks of about T points, every split cell its own partial slots
     const int64_t nch = std::max<int64_t>(1, (q + T - 1) / T);
-    p->fwd_cell_first[c] = (int64_t)p->fwd_items_cell.size();
     if (nch == 1) {
-      p->fwd_items_cell.push_back(FwdItem{a, b, (int32_t)c, 1, -1, -1});
+      p->fwd_items.push_back(FwdItem{a, b, (int32_t)c, 1, -1, -1});
     } else {
       ++nsplit;
       for (int64_t i = 0; i < nch; ++i) {
         const int64_t s = a + q * i / nch, e = a + q * (i + 1) / nch;
-        p->fwd_items_cell.push_back(FwdItem{s, e, (int32_t)c, (int32_t)nch, (int32_t)(slot + i), (int32_t)slot});
+        p->fwd_items.push_back(FwdItem{s, e, (int32_t)c, (int32_t)nch, (int32_t)(slot + i), (int32_t)slot});
       }
       slot += nch;
     }
+    // per-cell loop: a launch holds one cell, so the cell alone is split over the
+    // resident workgroups (chunks of at least kPercellChunkMin points); launches
+    // follow one another on the stream, so every cell reuses partial slots 0..n-1
+    const int64_t tc = std::max<int64_t>(kPercellChunkMin, (q + slots - 1) / std::max(1, slots));
+    const int64_t ncc = std::max<int64_t>(1, (q + tc - 1) / tc);
+    p->fwd_cell_first[c] = (int64_t)p->fwd_items_cell.size();
+    for (int64_t i = 0; i < ncc; ++i) {
+      const int64_t s = a + q * i / ncc, e = a + q * (i + 1) / ncc;
+      p->fwd_items_cell.push_back(ncc == 1 ? FwdItem{s, e, (int32_t)c, 1, -1, -1}
+                                           : FwdItem{s, e, (int32_t)c, (int32_t)ncc, (int32_t)i, 0});
+    }
+    pc_slots = std::max(pc_slots, ncc);
   }
   p->fwd_cell_first[p->n_cells] = (int64_t)p->fwd_items_cell.size();
-  p->fwd_items = p->fwd_items_cell;
   std::stable_sort(p->fwd_items.begin(), p->fwd_items.end(), [](const FwdItem &x, const FwdItem &y) {
     return (x.end - x.begin) > (y.end - y.begin);
   });
   p->n_slots = slot;
   p->n_split = nsplit;
+  p->n_partial = std::max(slot, pc_slots);
 }
 
 // Forward workgroup size (256, 512 or 1024 threads): LDS footprint and the
@@ -407,7 +424,7 @@ enufft_status set_fwd_threads(enufft_plan_t p, int threads, size_t lds_limit) {
 enufft_status install_fwd_schedule(enufft_plan_t p) {
   dev_release(p, &p->d_fwd_items, std::max<size_t>(1, p->fwd_items.size()) * sizeof(FwdItem));
   dev_release(p, &p->d_fwd_items_cell, std::max<size_t>(1, p->fwd_items_cell.size()) * sizeof(FwdItem));
-  dev_release(p, &p->d_partial, std::max<int64_t>(1, p->n_slots) * (size_t)p->n1 * p->n2 * p->elem);
+  dev_release(p, &p->d_partial, std::max<int64_t>(1, p->n_partial) * (size_t)p->n1 * p->n2 * p->elem);
   build_fwd_schedule(p, p->fwd_slots);
   p->fwd_blocks = (int)std::min<int64_t>((int64_t)p->fwd_slots, std::max<int64_t>(1, (int64_t)p->fwd_items.size()));
   enufft_status st = dev_alloc(p, &p->d_fwd_items, std::max<size_t>(1, p->fwd_items.size()) * sizeof(FwdItem),
@@ -416,7 +433,7 @@ enufft_status install_fwd_schedule(enufft_plan_t p) {
     st = dev_alloc(p, &p->d_fwd_items_cell, std::max<size_t>(1, p->fwd_items_cell.size()) * sizeof(FwdItem),
                    "forward items by cell");
   if (st == ENUFFT_OK)
-    st = dev_alloc(p, &p->d_partial, std::max<int64_t>(1, p->n_slots) * (size_t)p->n1 * p->n2 * p->elem,
+    st = dev_alloc(p, &p->d_partial, std::max<int64_t>(1, p->n_partial) * (size_t)p->n1 * p->n2 * p->elem,
                    "partial grids");
   if (st != ENUFFT_OK) return st;
   hipError_t e = hipSuccess;

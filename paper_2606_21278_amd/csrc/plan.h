@@ -51,9 +51,10 @@ struct enufft_plan_s {
 
   // forward schedule
   std::vector<enufft::FwdItem> fwd_items;        // descending size (batched launch)
-  std::vector<enufft::FwdItem> fwd_items_cell;   // grouped by cell (per-cell loop)
+  std::vector<enufft::FwdItem> fwd_items_cell;   // per-cell loop: each cell split over the resident workgroups
   std::vector<int64_t> fwd_cell_first;           // per cell: first index in fwd_items_cell (+ n_cells sentinel)
-  int64_t n_slots = 0, n_split = 0;
+  int64_t n_slots = 0, n_split = 0;              // batched schedule: partial slots, split cells
+  int64_t n_partial = 0;                         // partial grids held: max(batched slots, per-cell chunks)
   int fwd_threads = 512, fwd_blocks = 0, fwd_slots = 0;
   size_t fwd_lds = 0;
 

@@ -165,8 +165,14 @@ def test_unaligned_point_arrays():
     assert per_cell_rel_l2(f_un, ref).max() <= TOL["f32"]
 
 
-def test_percell_loop_matches_batched():
-    b = synth.config1(count_scale=0.004, n_cells=40)
+@pytest.mark.parametrize("count_scale,n_cells", [(0.004, 40), (0.6, 10)])
+def test_percell_loop_matches_batched(count_scale, n_cells):
+    """The per-cell loop (one launch per cell) gives the batched launch's coefficients.
+    At the larger scale most cells hold more than 8,192 points, so each is cut into
+    chunks over several workgroups whose partial grids one of them sums."""
+    b = synth.config1(count_scale=count_scale, n_cells=n_cells)
+    if count_scale > 0.1:
+        assert int(np.diff(np.asarray(b.cell_offsets)).max()) > 8192
     gb = gpu_batch(b)
     plan = make_plan(gb)
     f = plan.type1(gb.x, gb.y, gb.h, gb.w)
