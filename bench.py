@@ -638,8 +638,9 @@ def main():
         b1.record(s_)
         torch.cuda.synchronize()
         bms = b0.elapsed_time(b1)
-        # algorithmic bytes: x, y read twice (count, scatter), h, w read once; the
-        # permutation and the four sorted arrays written
+        # algorithmic bytes of the counting sort: x, y read twice (count, rank), h, w
+        # read once; the permutation and the four sorted arrays written (the gather
+        # pass also reads the permutation back and x, y a third time)
         bb = 44.0 * batch.n_points
         sort_rec = {"ms": bms, "bytes": bb, "achieved_GBps": bb / (bms * 1e-3) / 1e9,
                     "note": "per-cell counting sort by fine cell (enufft_sort_points), once, before timing; "

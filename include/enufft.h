@@ -369,6 +369,9 @@ enufft_status enufft_cell_geometry(enufft_plan_t p, const double *tri, const voi
  *                   alias the inputs.
  *   perm            device, n_points int32, or NULL: perm[i] is the input index of the
  *                   sample at sorted position i (a permutation inside each cell).
+ * Workspace: on its first call the plan allocates 16 bytes per point (32 in FP64) for
+ * interleaved copies of the samples, and with perm NULL 4 bytes per point for its own
+ * permutation; both are kept for later calls and freed by enufft_destroy.
  * The order of samples that share a fine cell is not specified.  Large-cell plans sort by
  * the 32 x 32 tile of the footprint origin, the order of their tiled spreading (FP32
  * plans with the kernel polynomial, widths 4, 6 and 8: and by fine cell, row-major,

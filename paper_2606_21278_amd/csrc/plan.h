@@ -78,6 +78,8 @@ struct enufft_plan_s {
   void *d_cell_items = nullptr;      // int32 item indices grouped by cell (ascending)
   void *d_cell_item_off = nullptr;   // int64 [n_cells + 1] offsets into d_cell_items
   void *d_cell_off = nullptr;        // int64 [n_cells + 1] the plan's cell offsets
+  int32_t *d_sort_perm = nullptr;    // [n_points] enufft_sort_points' permutation when the caller asks for none
+  void *d_sort_rec = nullptr;        // [n_points] enufft_sort_points' interleaved (x, y, h, w) records
   int adj_bands = 1, adj_band_rows = 0;
   int adj_threads = 512, adj_blocks = 0;
   size_t adj_lds = 0;
