@@ -145,7 +145,8 @@ typedef struct {
     int32_t fwd_threads, fwd_blocks;   /* forward launch shape */
     int32_t adj_threads, adj_blocks;
     int64_t workspace_bytes;
-    double kernel_poly_err;  /* FP32: max |polynomial - psi| of the kernel fit, 0 if the exact kernel is used */
+    double kernel_poly_err;  /* max |polynomial - psi| of the kernel fit (FP32 plans, FP64 large-cell plans),
+                                0 if the exact kernel is used */
     int32_t tuned;           /* 1 if the autotuner set the launch shape */
     int32_t tune_cache_hit;  /* 1 if that choice came from the on-disk cache */
     int64_t fwd_chunk_min;   /* smallest forward work item (points) */

@@ -30,6 +30,7 @@
 #include <climits>
 #include <cmath>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "device_common.h"
@@ -77,13 +78,93 @@ __device__ __forceinline__ int big_local(int i0, int t0, int n) {
   return l < BIG_TS + 1 ? l : BIG_TS + 1;
 }
 
+// FP64 per-tap polynomials (EsPoly64): u = 2 v - 1 with v = i0 - t + W/2 clamped
+// to [0, 1]; tap d < W/2 is P_d(u), its mirror W - 1 - d is P_d(-u) (psi is even).
+__device__ __forceinline__ double tap_u64(const FineCoord<double> &c, double halfw) {
+  const double v = ((double(c.i0) - c.hi) - c.lo) + halfw;
+  return 2.0 * fmin(fmax(v, 0.0), 1.0) - 1.0;
+}
+
+// The coefficients of mirror pair d, read where they are used: the offset is
+// opaque to the compiler, so the loads are not hoisted out of the caller's point
+// loop (all W/2 pairs at once would need more scalar registers than there are,
+// and the spills cost a lane move per use).
+__device__ __forceinline__ const double *poly64_pair(const EsPoly64 &cf, int d) {
+  int z = 0;
+  asm volatile("" : "+s"(z));
+  return cf.c + d * (ES64_DEG + 1) + z;
+}
+
+// Mirror pair d at u: P_d(+-u) = E(u^2) +- u O(u^2).
+__device__ __forceinline__ void poly64_pair_eval(const double *cd, double u, double s, double &t0, double &t1) {
+  double e = cd[ES64_DEG - 1], o = cd[ES64_DEG];
+#pragma unroll
+  for (int k = ES64_DEG - 3; k >= 0; k -= 2) {
+    e = fma(e, s, cd[k]);
+    o = fma(o, s, cd[k + 1]);
+  }
+  t0 = fma(u, o, e);
+  t1 = fma(-u, o, e);
+}
+
+// All W taps along both axes, pair by pair (one pair's coefficients live at a time).
+template <int W>
+__device__ __forceinline__ void es_taps_poly64_xy(double ux, double uy, const EsPoly64 &cf, double (&kx)[W],
+                                                  double (&ky)[W]) {
+  static_assert(W % 2 == 0 && ES64_DEG % 2 == 1 && W <= ES64_MAXW, "mirror pairs of an odd-degree fit");
+  const double sx = ux * ux, sy = uy * uy;
+#pragma unroll
+  for (int d = 0; d < W / 2; ++d) {
+    const double *cd = poly64_pair(cf, d);
+    poly64_pair_eval(cd, ux, sx, kx[d], kx[W - 1 - d]);
+    poly64_pair_eval(cd, uy, sy, ky[d], ky[W - 1 - d]);
+  }
+}
+
+// The x taps alone.
+template <int W>
+__device__ __forceinline__ void es_taps_poly64(double u, const EsPoly64 &cf, double (&out)[W]) {
+  static_assert(W % 2 == 0 && ES64_DEG % 2 == 1 && W <= ES64_MAXW, "mirror pairs of an odd-degree fit");
+  const double s = u * u;
+#pragma unroll
+  for (int d = 0; d < W / 2; ++d) poly64_pair_eval(poly64_pair(cf, d), u, s, out[d], out[W - 1 - d]);
+}
+
+// One tap, dd in [0, W): Horner on its pair's coefficients at +-u (dd uniform
+// across the wave, so the coefficient loads stay scalar).
+template <int W>
+__device__ __forceinline__ double es_tap_poly64(double u, const EsPoly64 &cf, int dd) {
+  const bool m = dd >= W / 2;
+  const double *cd = cf.c + (m ? W - 1 - dd : dd) * (ES64_DEG + 1);
+  const double x = m ? -u : u;
+  double acc = cd[ES64_DEG];
+#pragma unroll
+  for (int k = ES64_DEG - 1; k >= 0; --k) acc = fma(acc, x, cd[k]);
+  return acc;
+}
+
+// Kernel-argument form of EsPoly64 per precision (FP32 kernels carry only the flag).
+struct NoPoly64 {
+  int on;
+};
+template <typename T>
+using Poly64Of = typename std::conditional<sizeof(T) == 8, EsPoly64, NoPoly64>::type;
+
 // The W kernel values of one point along one axis: the plan's per-tap
-// polynomials (FP32, W <= ES_MAXW) when POLY, else psi itself.
+// polynomials (FP32, W <= ES_MAXW) when POLY; for FP64 plans their FP64 ones
+// when the plan carries them; else psi itself.
 template <typename T, int W, bool POLY>
-__device__ __forceinline__ void big_taps(const FineCoord<T> &c, T beta, const EsPoly &cf, T (&out)[W]) {
+__device__ __forceinline__ void big_taps(const FineCoord<T> &c, T beta, const EsPoly &cf, const Poly64Of<T> &c64,
+                                         T (&out)[W]) {
   if constexpr (POLY) {
     es_taps_poly<W>(c, float(W) * 0.5f, cf, out);
   } else {
+    if constexpr (sizeof(T) == 8 && W % 2 == 0 && W <= ES64_MAXW) {
+      if (c64.on) {
+        es_taps_poly64<W>(tap_u64(c, double(W) * 0.5), c64, out);
+        return;
+      }
+    }
     const T zsc = T(2) / T(W);
 #pragma unroll
     for (int d = 0; d < W; ++d) out[d] = ker_eval(c.offset(d) * zsc, beta);
@@ -447,6 +528,7 @@ struct BigTileArgs {
   Geom g;
   T s1h, s1l, s2h, s2l, beta;
   EsPoly es;
+  Poly64Of<T> es64;
   double *partial;           // spreading: [units][S * S] FP64 sub-grids
   const typename vec4<T>::type *G4;   // gather: n2 x n1 cells of (u, du/dx, du/dy, 0)
   typename vec4<T>::type *gout;       // gather: [n] (dL/dh, dL/dx, dL/dy, 0) in sorted order
@@ -518,8 +600,17 @@ __global__ __launch_bounds__(BIG_SPREAD_THREADS) void big_spread_kernel(BigTileA
       const int lx = big_local(fx.i0 & (g.n1 - 1), tx0, g.n1);
       const int ly = big_local(fy.i0 & (g.n2 - 1), ty0, g.n2);
       T kx[W], ky[W];
-      big_taps<T, W, POLY>(fx, a.beta, a.es, kx);
-      big_taps<T, W, POLY>(fy, a.beta, a.es, ky);
+      bool both = false;
+      if constexpr (sizeof(T) == 8 && !POLY && W % 2 == 0 && W <= ES64_MAXW) {
+        if (a.es64.on) {
+          es_taps_poly64_xy<W>(tap_u64(fx, double(W) * 0.5), tap_u64(fy, double(W) * 0.5), a.es64, kx, ky);
+          both = true;
+        }
+      }
+      if (!both) {
+        big_taps<T, W, POLY>(fx, a.beta, a.es, a.es64, kx);
+        big_taps<T, W, POLY>(fy, a.beta, a.es, a.es64, ky);
+      }
 #pragma unroll
       for (int dy = 0; dy < W; ++dy) {
         const double vy = (double)(cj * ky[dy]);
@@ -664,8 +755,8 @@ __global__ __launch_bounds__(BIG_SPREAD_THREADS) void big_spread_run_kernel(BigT
           cur = key;
         }
         float kx[W], ky[W];
-        big_taps<float, W, true>(fx, a.beta, a.es, kx);
-        big_taps<float, W, true>(fy, a.beta, a.es, ky);
+        big_taps<float, W, true>(fx, a.beta, a.es, a.es64, kx);
+        big_taps<float, W, true>(fy, a.beta, a.es, a.es64, ky);
 #pragma unroll
         for (int dy = 0; dy < W; ++dy) {
           const float vy = cj * ky[dy];
@@ -1268,7 +1359,7 @@ __global__ __launch_bounds__(256) void big_gather_kernel(BigTileArgs<T> a) {
       const int lx = big_local(fx.i0 & (g.n1 - 1), tx0, g.n1);
       const int ly = big_local(fy.i0 & (g.n2 - 1), ty0, g.n2);
       T kx[W];
-      big_taps<T, W, POLY>(fx, a.beta, a.es, kx);
+      big_taps<T, W, POLY>(fx, a.beta, a.es, a.es64, kx);
       T u = 0, ux = 0, uy = 0;
       auto row = [&](int dy, T kyv) {
         const int rb = (ly + dy) * S + lx;
@@ -1287,7 +1378,7 @@ __global__ __launch_bounds__(256) void big_gather_kernel(BigTileArgs<T> a) {
       // one row at a time keeps the loads of W rows from being hoisted together
       if constexpr (POLY) {
         T ky[W];
-        big_taps<T, W, POLY>(fy, a.beta, a.es, ky);
+        big_taps<T, W, POLY>(fy, a.beta, a.es, a.es64, ky);
 #pragma unroll 1
         for (int dy = 0; dy < W; ++dy) {
           T kyv = ky[0];
@@ -1296,9 +1387,20 @@ __global__ __launch_bounds__(256) void big_gather_kernel(BigTileArgs<T> a) {
           row(dy, kyv);
         }
       } else {
-        const T zsc = T(2) / T(W);
+        bool done = false;
+        if constexpr (sizeof(T) == 8 && W % 2 == 0 && W <= ES64_MAXW) {
+          if (a.es64.on) {
+            const double uy64 = tap_u64(fy, double(W) * 0.5);
 #pragma unroll 1
-        for (int dy = 0; dy < W; ++dy) row(dy, ker_eval(fy.offset(dy) * zsc, a.beta));
+            for (int dy = 0; dy < W; ++dy) row(dy, es_tap_poly64<W>(uy64, a.es64, dy));
+            done = true;
+          }
+        }
+        if (!done) {
+          const T zsc = T(2) / T(W);
+#pragma unroll 1
+          for (int dy = 0; dy < W; ++dy) row(dy, ker_eval(fy.offset(dy) * zsc, a.beta));
+        }
       }
       T dWx, dWy;
       const T Wv = hann_wg(a.window_kind, xj, yj, cx, cy, R, pr, dWx, dWy);
@@ -1642,6 +1744,8 @@ BigTileArgs<T> tile_args(enufft_plan_t p, int64_t c, const T *x, const T *y, con
   split_scale<T>(p->n2, &a.s2h, &a.s2l);
   a.beta = (T)p->beta;
   a.es = p->es;
+  if constexpr (sizeof(T) == 8) a.es64 = p->es64;
+  else a.es64.on = 0;
   return a;
 }
 

@@ -35,6 +35,18 @@ struct EsPoly {
   float c[(ES_MAXW / 2) * (ES_DEG + 1)];   // taps 0 .. W/2 - 1, tap-major, ascending powers of u = 2 v - 1
 };
 
+// The same per-tap form in FP64 for the large-cell kernels of FP64 plans: degree
+// 13 reproduces the taps of the widths those plans use (W = 10 .. 16, eps 1e-9 ..
+// 1e-14) to about 5e-13 at W = 12 (the outer tap's square-root branch point at the
+// edge of the support limits the fit, not the degree).  Also by value in the
+// kernel arguments: its loads are scalar, the same address for every lane.
+constexpr int ES64_DEG = 13;
+constexpr int ES64_MAXW = 16;
+struct EsPoly64 {
+  int on;
+  double c[(ES64_MAXW / 2) * (ES64_DEG + 1)];   // as EsPoly
+};
+
 // Fine-grid and mode-box geometry.
 struct Geom {
   int n1, n2;       // fine grid (powers of two: 16..128 in LDS, 64..4096 for large cells)

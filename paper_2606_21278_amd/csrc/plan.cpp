@@ -587,6 +587,21 @@ enufft_status enufft_plan(enufft_plan_t *out, int64_t n_cells, const int64_t *ce
     }
   }
 
+  // FP64 large-cell plans: the same per-tap form in FP64 (even widths), kept when its fit
+  // is at least ten times below the requested accuracy
+  if (p->prec == ENUFFT_F64 && big && W % 2 == 0 && W <= enufft::ES64_MAXW) {
+    const char *ev = std::getenv("ENUFFT_POLY64");
+    if (!(ev && std::atoi(ev) == 0)) {
+      std::vector<double> cf;
+      const double err = fit_es_poly(W, beta, enufft::ES64_DEG, cf);
+      if (err <= 0.1 * opts->eps) {
+        p->es_poly_err = err;
+        p->es64.on = 1;
+        for (size_t i = 0; i < (size_t)(W / 2) * (enufft::ES64_DEG + 1); ++i) p->es64.c[i] = cf[i];
+      }
+    }
+  }
+
   // Single-grid adjoint: FP32 plans whose kernel takes the polynomial path use one LDS
   // grid per cell with value and derivative taps of a kernel two cells wider (the
   // derivative of the interpolant converges more slowly than the interpolant itself).

@@ -93,6 +93,7 @@ struct enufft_plan_s {
   void *d_decon_x = nullptr, *d_decon_y = nullptr, *d_tw1 = nullptr, *d_tw2 = nullptr;
   void *d_decon_x1 = nullptr;      // 1 / p_x(|k|) without the plan's scale (reconstruction)
   enufft::EsPoly es{};             // FP32 plans: kernel polynomial coefficients (es.on = 0: exact)
+  enufft::EsPoly64 es64{};         // FP64 large-cell plans: the same in FP64 (es64.on = 0: exact)
   double es_poly_err = 0.0;        // max |poly - psi| over the fit interval
   enufft::UnitTable units[2][2];
   int64_t workspace_bytes = 0;

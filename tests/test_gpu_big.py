@@ -157,6 +157,49 @@ def test_big_adjoint_matches_oracle_vjp(prec):
     assert max(errs) <= TOL[prec]
 
 
+def test_big_fp64_polynomial_taps():
+    """FP64 large-cell plans evaluate the kernel as per-tap FP64 polynomials (degree 13,
+    mirror pairs) when the fit is ten times below eps; ENUFFT_POLY64=0 keeps the exact
+    kernel.  Both plans' type-1 and adjoint are within the FP64 tolerance of the oracle,
+    and the two differ by no more than the fit allows."""
+    import os
+    b = synth.config4(Q=20000, precision="f64", n_modes=(128, 96))
+    inp = oracle.batch_inputs(b)
+    ref = oracle_f(b)
+    g = np.ascontiguousarray(2.0 * ref)
+    rh, rx, ry = oracle.type1_vjp(inp["offsets"], inp["x"], inp["y"], inp["h"], inp["w"], inp["windows"],
+                                  inp["n_modes"], g)
+    gb = gpu_batch(b)
+    out = {}
+    for name, env in (("poly", None), ("exact", "0")):
+        old = os.environ.pop("ENUFFT_POLY64", None)
+        if env is not None:
+            os.environ["ENUFFT_POLY64"] = env
+        try:
+            plan = make_plan(gb)
+        finally:
+            os.environ.pop("ENUFFT_POLY64", None)
+            if old is not None:
+                os.environ["ENUFFT_POLY64"] = old
+        info = plan.info()
+        f = plan.type1(gb.x, gb.y, gb.h, gb.w).cpu().numpy()
+        adj = plan.adjoint(gb.x, gb.y, gb.h, gb.w, torch.from_numpy(g).to("cuda:0", plan.cdtype))
+        torch.cuda.synchronize()
+        adj = [a.cpu().numpy() for a in adj]
+        e_f = rel_l2(f, ref)
+        e_a = max(rel_l2(a, r) for a, r in zip(adj, (rh, rx, ry)))
+        print(name, "W", info["kernel_width"], "fit %.2e" % info["kernel_poly_err"],
+              "type-1 rel-l2 %.3e adjoint %.3e" % (e_f, e_a), flush=True)
+        assert info["kernel_width"] == 12
+        assert (info["kernel_poly_err"] > 0) == (name == "poly")
+        assert info["kernel_poly_err"] <= 0.1 * b.eps
+        assert e_f <= TOL["f64"] and e_a <= TOL["f64"]
+        out[name] = (f, adj)
+    assert rel_l2(out["poly"][0], out["exact"][0]) <= 1e-11
+    for a, e in zip(out["poly"][1], out["exact"][1]):
+        assert rel_l2(a, e) <= 1e-11
+
+
 def test_big_retained_power_pipeline_fp32():
     """type-1, EMS and the retained-power adjoint on the GPU, checked against the
     oracle's vjp with the GPU's own cotangent 2 f keep."""
