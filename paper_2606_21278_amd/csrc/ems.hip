@@ -331,10 +331,12 @@ __device__ __forceinline__ V block_exclusive_scan(V v, V *red, int wave, int lan
 // the sort carries values only; which of several units tied at the cut energy
 // are kept is settled afterwards by ascending id (a prefix count of the ties).
 template <typename T, int R, int NW>
-__global__ __launch_bounds__(64 * NW) void ems_kernel(EmsArgs a) {
+__global__ __launch_bounds__(64 * NW, 5) void ems_kernel(EmsArgs a) {
   constexpr int NT = 64 * NW, JW = 64 * R, JP = JW * NW;
   __shared__ double sorted[JP];
-  __shared__ uint8_t tie_kept[JP];
+  // the tie flags reuse the sorted values' storage: they are written only after
+  // every read of the sorted values (see the tie ranking below)
+  uint8_t *tie_kept = reinterpret_cast<uint8_t *>(sorted);
   __shared__ double redd[NW];
   __shared__ int redi[NW];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, t = threadIdx.x;
@@ -500,6 +502,7 @@ __global__ __launch_bounds__(64 * NW) void ems_kernel(EmsArgs a) {
   // rank the tied units by id.  Otherwise every unit at the cut is kept.
   const bool split_ties = kstar > 0 && neq > need;
   if (split_ties) {   // the same in every thread
+    __syncthreads();   // every thread has read the sorted values (tie_kept overwrites them)
     int ties = 0;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
