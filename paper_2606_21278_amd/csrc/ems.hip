@@ -533,7 +533,7 @@ __global__ __launch_bounds__(64 * NW, 5) void ems_kernel(EmsArgs a) {
   // commutes).
   double pw = 0.0;
   uint8_t *kout = a.keep ? a.keep + cell * a.M : nullptr;   // flow mode may skip the masks
-  constexpr int UK = 4;
+  constexpr int UK = 2;
   const int N1 = a.N1, hm1 = 2 * (a.N1 >> 1), hm2 = 2 * (a.N2 >> 1);
   const float inv_n1 = 1.0f / (float)N1;
   for (int m0 = t; m0 < a.M; m0 += UK * NT) {
