@@ -213,6 +213,41 @@ def test_ems_on_identical_coefficients(prm):
     assert np.allclose(st, ok_st, rtol=1e-11, atol=0)
 
 
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+@pytest.mark.parametrize("n_modes", [(64, 64), (64, 32), (16, 16)])
+def test_ems_ties_at_the_cut(n_modes, prec):
+    """In-register EMS (up to 4,096 units per cell): many units share each energy level,
+    so the cut splits a run of equal energies and the kept ones are the tied units of
+    lowest id, as in the oracle.  Coefficients are small integers times a power of i,
+    so every energy is an exact integer on both sides.  The mode boxes and unit rules give
+    one to four waves per cell (single modes: 4,096, 2,048 and 256 units; +-k pairs:
+    2,111, 1,071 and 143)."""
+    N1, N2 = n_modes
+    rng = np.random.default_rng(11 + N1 + N2)
+    phase = np.array([1, 1j, -1, -1j])[rng.integers(0, 4, size=(3, N2, N1))]
+    f = (rng.integers(1, 4, size=(3, N2, N1)) * phase).astype(np.complex128)
+    f[2] = np.abs(f[2])
+    plan = _ems_plan_for(f, prec)
+    fg = torch.from_numpy(f.astype(np.complex64 if prec == "f32" else np.complex128)).to("cuda:0")
+    for prm in (oracle.EmsParams(use_pairs=0, exclude_dc=0, alpha_min=0.5, alpha_max=0.5),
+                oracle.EmsParams(alpha_min=0.3, alpha_max=0.3),
+                oracle.EmsParams(k_min=1, k_max=40, alpha_min=0.9, alpha_max=0.9)):
+        keep, ks, st = plan.ems(fg, enf.EmsParams(**prm.__dict__))
+        ok_keep, ok_ks, ok_st = oracle.ems_batched(f, prm)
+        assert np.array_equal(ks.cpu().numpy(), ok_ks)
+        assert np.array_equal(keep.cpu().numpy(), ok_keep)
+        assert np.allclose(st.cpu().numpy(), ok_st, rtol=1e-11, atol=0)
+        if prm.use_pairs == 0:
+            # the case under test: in some cell the units at the cut energy outnumber
+            # the places left for them, so the tie ranking decides
+            split = 0
+            for c in range(f.shape[0]):
+                e = np.sort((np.abs(f[c]) ** 2).ravel())[::-1]
+                k = int(ok_ks[c])
+                split += int(0 < k < e.size and e[k] == e[k - 1])
+            assert split > 0
+
+
 @pytest.mark.parametrize("use_pairs", [1, 0])
 def test_ems_weighted_on_identical_coefficients(use_pairs):
     """Eq. (weighted_e): per-mode weights (asymmetric between k and -k, a tenth of them
