@@ -1326,9 +1326,13 @@ __global__ __launch_bounds__(512) void big_adj_rows_kernel(const T *cb, const T 
 
 // Gather (the type-2 interpolation back to the points) from the three grids,
 // each tile run staging its sub-grid of u, du/dx and du/dy in LDS.
+// FP32 stages (u, du/dx, du/dy, 0) as one 16-byte vector per cell (one read per
+// tap); FP64 as three planes of doubles: 24 instead of 32 bytes per cell, so three
+// 256-thread workgroups share a CU instead of two at W = 12.
 template <typename T, int W>
 constexpr size_t big_gather_lds() {
-  return (size_t)(BIG_TS + W + 1) * (BIG_TS + W + 1) * sizeof(typename vec4<T>::type);
+  constexpr size_t n = (size_t)(BIG_TS + W + 1) * (BIG_TS + W + 1);
+  return sizeof(T) == 8 ? 3 * n * sizeof(double) : n * sizeof(typename vec4<T>::type);
 }
 
 template <typename T, int W, bool POLY>
@@ -1336,7 +1340,9 @@ __global__ __launch_bounds__(256) void big_gather_kernel(BigTileArgs<T> a) {
   constexpr int S = BIG_TS + W + 1;
   using V4 = typename vec4<T>::type;
   extern __shared__ __align__(32) unsigned char sm_raw[];
-  V4 *sg = reinterpret_cast<V4 *>(sm_raw);   // [S * S] staged (u, du/dx, du/dy, 0)
+  V4 *sg = reinterpret_cast<V4 *>(sm_raw);   // FP32: [S * S] staged (u, du/dx, du/dy, 0)
+  T *su = reinterpret_cast<T *>(sm_raw);     // FP64: [S * S] u, then du/dx, then du/dy
+  T *sx = su + S * S, *sy = sx + S * S;
   __shared__ int s_unit;
   const Geom &g = a.g;
   const T halfw = T(W) / T(2);
@@ -1349,7 +1355,14 @@ __global__ __launch_bounds__(256) void big_gather_kernel(BigTileArgs<T> a) {
     const int tx0 = (t % a.ntx) * BIG_TS, ty0 = (t / a.ntx) * BIG_TS;
     for (int i = threadIdx.x; i < S * S; i += blockDim.x) {
       const int r = i / S, q = i - r * S;
-      sg[i] = a.G4[(int64_t)((ty0 - 1 + r) & (g.n2 - 1)) * g.n1 + ((tx0 - 1 + q) & (g.n1 - 1))];
+      const V4 v = a.G4[(int64_t)((ty0 - 1 + r) & (g.n2 - 1)) * g.n1 + ((tx0 - 1 + q) & (g.n1 - 1))];
+      if constexpr (sizeof(T) == 8) {
+        su[i] = v.x;
+        sx[i] = v.y;
+        sy[i] = v.z;
+      } else {
+        sg[i] = v;
+      }
     }
     __syncthreads();
     for (int64_t k = lo + threadIdx.x; k < hi; k += blockDim.x) {
@@ -1366,10 +1379,16 @@ __global__ __launch_bounds__(256) void big_gather_kernel(BigTileArgs<T> a) {
         T au = 0, ax = 0, ay = 0;
 #pragma unroll
         for (int dx = 0; dx < W; ++dx) {
-          const V4 v = sg[rb + dx];
-          au += kx[dx] * v.x;
-          ax += kx[dx] * v.y;
-          ay += kx[dx] * v.z;
+          if constexpr (sizeof(T) == 8) {
+            au += kx[dx] * su[rb + dx];
+            ax += kx[dx] * sx[rb + dx];
+            ay += kx[dx] * sy[rb + dx];
+          } else {
+            const V4 v = sg[rb + dx];
+            au += kx[dx] * v.x;
+            ax += kx[dx] * v.y;
+            ay += kx[dx] * v.z;
+          }
         }
         u += kyv * au;
         ux += kyv * ax;
