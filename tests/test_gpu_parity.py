@@ -163,6 +163,14 @@ def test_unaligned_point_arrays():
     ref = oracle_f(b.to(dtype=torch.float32))
     assert per_cell_rel_l2(f_al, ref).max() <= TOL["f32"]
     assert per_cell_rel_l2(f_un, ref).max() <= TOL["f32"]
+    # an output block that is only 8-byte aligned: the same values
+    flat = torch.zeros(1 + f_al.size, dtype=torch.complex64, device="cuda:0")
+    out = flat[1:].view(f_al.shape)
+    assert out.data_ptr() % 16 != 0
+    plan.type1(gb.x, gb.y, gb.h, gb.w, out=out)
+    torch.cuda.synchronize()
+    assert rel_l2(out.cpu().numpy(), f_al) <= 1e-6
+    assert flat[0].item() == 0
 
 
 @pytest.mark.parametrize("count_scale,n_cells", [(0.004, 40), (0.6, 10)])
