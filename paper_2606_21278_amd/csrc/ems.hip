@@ -320,6 +320,13 @@ __device__ __forceinline__ V block_exclusive_scan(V v, V *red, int wave, int lan
   }
 }
 
+// five waves per SIMD (96 VGPRs) for up to three waves per cell; the four-wave
+// form's sort does not fit that and keeps four
+template <int NW>
+constexpr int ems_min_waves() {
+  return NW <= 3 ? 5 : 4;
+}
+
 // One workgroup of NW waves per cell; thread t holds sort positions
 // t R .. t R + R - 1.  Each wave sorts its 64 R energies in registers, the
 // sorted runs are merged pairwise through LDS (merge path: every thread finds
@@ -331,7 +338,7 @@ __device__ __forceinline__ V block_exclusive_scan(V v, V *red, int wave, int lan
 // the sort carries values only; which of several units tied at the cut energy
 // are kept is settled afterwards by ascending id (a prefix count of the ties).
 template <typename T, int R, int NW>
-__global__ __launch_bounds__(64 * NW, 5) void ems_kernel(EmsArgs a) {
+__global__ __launch_bounds__(64 * NW, (ems_min_waves<NW>())) void ems_kernel(EmsArgs a) {
   constexpr int NT = 64 * NW, JW = 64 * R, JP = JW * NW;
   __shared__ double sorted[JP];
   // the tie flags reuse the sorted values' storage: they are written only after
