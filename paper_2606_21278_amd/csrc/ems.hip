@@ -11,6 +11,7 @@
 #include <algorithm>
 #include <climits>
 #include <cmath>
+#include <cstdlib>
 #include <string>
 #include <vector>
 
@@ -321,10 +322,11 @@ __device__ __forceinline__ V block_exclusive_scan(V v, V *red, int wave, int lan
 }
 
 // five waves per SIMD (96 VGPRs) for up to three waves per cell; the four-wave
-// form's sort does not fit that and keeps four
+// form's sort does not fit that and keeps four; the wide forms (below) need one
+// workgroup per CU
 template <int NW>
 constexpr int ems_min_waves() {
-  return NW <= 3 ? 5 : 4;
+  return NW <= 3 ? 5 : NW == 4 ? 4 : (NW + 3) / 4;
 }
 
 // One workgroup of NW waves per cell; thread t holds sort positions
@@ -681,9 +683,31 @@ enufft_status ems_validate(enufft_plan_t p, const void *f, const enufft_ems_para
 
 // Sort size per cell: the smallest 64 R NW >= J (R a power of two up to 16,
 // then 1 to 4 waves of 1,024).
+// Whether a launch of `blocks` cells leaves the CUs mostly idle with the narrow
+// forms (fewer than eight of their waves per CU): then the wide forms.
+// ENUFFT_EMS_WIDE=0 or 1 forces the choice.
+bool ems_wide(const enufft_plan_t p, int J, int64_t blocks) {
+  if (const char *ev = std::getenv("ENUFFT_EMS_WIDE")) return std::atoi(ev) != 0;
+  const int64_t waves = blocks * ((J + 1023) / 1024);
+  return waves < (int64_t)p->n_cu * 8;
+}
+
 template <typename T>
-hipError_t launch_ems_t(const EmsArgs &a, int J, int blocks, hipStream_t s) {
+hipError_t launch_ems_t(const EmsArgs &a, int J, int blocks, hipStream_t s, bool wide) {
   const dim3 g(blocks);
+  if (wide && J > 256) {
+    // few cells: each cell's latency is the launch's, so more waves per cell, four
+    // values per lane (a shorter register sort, more merge rounds through LDS)
+    if (J <= 512) hipLaunchKernelGGL((ems_kernel<T, 4, 2>), g, dim3(128), 0, s, a);
+    else if (J <= 768) hipLaunchKernelGGL((ems_kernel<T, 4, 3>), g, dim3(192), 0, s, a);
+    else if (J <= 1024) hipLaunchKernelGGL((ems_kernel<T, 4, 4>), g, dim3(256), 0, s, a);
+    else if (J <= 1536) hipLaunchKernelGGL((ems_kernel<T, 4, 6>), g, dim3(384), 0, s, a);
+    else if (J <= 2048) hipLaunchKernelGGL((ems_kernel<T, 4, 8>), g, dim3(512), 0, s, a);
+    else if (J <= 3072) hipLaunchKernelGGL((ems_kernel<T, 4, 12>), g, dim3(768), 0, s, a);
+    else if (J <= 4096) hipLaunchKernelGGL((ems_kernel<T, 4, 16>), g, dim3(1024), 0, s, a);
+    else return hipErrorInvalidValue;
+    return hipGetLastError();
+  }
   if (J <= 64) hipLaunchKernelGGL((ems_kernel<T, 1, 1>), g, dim3(64), 0, s, a);
   else if (J <= 128) hipLaunchKernelGGL((ems_kernel<T, 2, 1>), g, dim3(64), 0, s, a);
   else if (J <= 256) hipLaunchKernelGGL((ems_kernel<T, 4, 1>), g, dim3(64), 0, s, a);
@@ -716,8 +740,9 @@ enufft_status ems_launch(enufft_plan_t p, const void *f, const enufft_ems_params
   a.alpha_min = prm->alpha_min; a.alpha_max = prm->alpha_max; a.delta = prm->delta;
   a.w1 = prm->w1; a.w2 = prm->w2;
   const int blocks = (int)cell_count;
-  hipError_t e = p->prec == ENUFFT_F64 ? launch_ems_t<double>(a, ut->J, blocks, p->stream)
-                                       : launch_ems_t<float>(a, ut->J, blocks, p->stream);
+  const bool wide = ems_wide(p, ut->J, blocks);
+  hipError_t e = p->prec == ENUFFT_F64 ? launch_ems_t<double>(a, ut->J, blocks, p->stream, wide)
+                                       : launch_ems_t<float>(a, ut->J, blocks, p->stream, wide);
   if (e != hipSuccess) {
     p->last_error = std::string("EMS launch: ") + hipGetErrorString(e);
     p->faulted = true;
@@ -788,8 +813,9 @@ extern "C" enufft_status enufft_ems_flow(enufft_plan_t p, const void *f, const e
   st = enufft::record_start(p, 1, &ev);
   if (st != ENUFFT_OK) return st;
   const int blocks = (int)a.cell_end;
-  hipError_t e = p->prec == ENUFFT_F64 ? enufft::launch_ems_t<double>(a, ut->J, blocks, p->stream)
-                                       : enufft::launch_ems_t<float>(a, ut->J, blocks, p->stream);
+  const bool wide = enufft::ems_wide(p, ut->J, blocks);
+  hipError_t e = p->prec == ENUFFT_F64 ? enufft::launch_ems_t<double>(a, ut->J, blocks, p->stream, wide)
+                                       : enufft::launch_ems_t<float>(a, ut->J, blocks, p->stream, wide);
   if (e != hipSuccess) {
     p->last_error = std::string("enufft_ems_flow launch: ") + hipGetErrorString(e);
     p->faulted = true;

@@ -5,6 +5,7 @@ FP64 path; EMS kept sets identical on tie-free cells; adjoint gradients <= 5e-5
 (FP32) and <= 1e-10 (FP64) relative l2 over all points."""
 import ctypes
 import math
+import os
 
 import numpy as np
 import pytest
@@ -194,6 +195,23 @@ def test_percell_loop_matches_batched(count_scale, n_cells):
 
 # ------------------------------------------------------------------------- EMS
 
+class _ems_form:
+    """Force the narrow ("0") or wide ("1") in-register EMS form (ENUFFT_EMS_WIDE)."""
+
+    def __init__(self, wide):
+        self.wide = wide
+
+    def __enter__(self):
+        self.old = os.environ.get("ENUFFT_EMS_WIDE")
+        os.environ["ENUFFT_EMS_WIDE"] = self.wide
+
+    def __exit__(self, *exc):
+        if self.old is None:
+            os.environ.pop("ENUFFT_EMS_WIDE", None)
+        else:
+            os.environ["ENUFFT_EMS_WIDE"] = self.old
+
+
 def _ems_plan_for(f_ref, prec):
     n, N2, N1 = f_ref.shape
     off = np.arange(n + 1, dtype=np.int64)
@@ -207,23 +225,27 @@ def _ems_plan_for(f_ref, prec):
                                  oracle.EmsParams(k_min=3, k_max=40, alpha_min=0.5, alpha_max=0.99, delta=0.05,
                                                   w1=0.3, w2=0.7),
                                  oracle.EmsParams(use_pairs=0, exclude_dc=0, alpha_min=0.9, alpha_max=0.9)])
-def test_ems_on_identical_coefficients(prm):
-    """Given the same FP64 coefficients, the GPU selection equals the oracle's exactly."""
+@pytest.mark.parametrize("wide", ["0", "1"])
+def test_ems_on_identical_coefficients(prm, wide):
+    """Given the same FP64 coefficients, the GPU selection equals the oracle's exactly,
+    in the narrow (sixteen values per lane) and the wide (four per lane) form."""
     b = synth.config1(count_scale=0.003, n_cells=24, precision="f64")
     ref = oracle_f(b)
     plan = _ems_plan_for(ref, "f64")
     f = torch.from_numpy(ref).to("cuda:0")
-    keep, ks, st = plan.ems(f, enf.EmsParams(**prm.__dict__))
-    keep, ks, st = keep.cpu().numpy(), ks.cpu().numpy(), st.cpu().numpy()
+    with _ems_form(wide):
+        keep, ks, st = plan.ems(f, enf.EmsParams(**prm.__dict__))
+        keep, ks, st = keep.cpu().numpy(), ks.cpu().numpy(), st.cpu().numpy()
     ok_keep, ok_ks, ok_st = oracle.ems_batched(ref, prm)
     assert np.array_equal(ks, ok_ks)
     assert np.array_equal(keep, ok_keep)
     assert np.allclose(st, ok_st, rtol=1e-11, atol=0)
 
 
+@pytest.mark.parametrize("wide", ["0", "1"])
 @pytest.mark.parametrize("prec", ["f32", "f64"])
 @pytest.mark.parametrize("n_modes", [(64, 64), (64, 32), (16, 16)])
-def test_ems_ties_at_the_cut(n_modes, prec):
+def test_ems_ties_at_the_cut(n_modes, prec, wide):
     """In-register EMS (up to 4,096 units per cell): many units share each energy level,
     so the cut splits a run of equal energies and the kept ones are the tied units of
     lowest id, as in the oracle.  Coefficients are small integers times a power of i,
@@ -240,7 +262,9 @@ def test_ems_ties_at_the_cut(n_modes, prec):
     for prm in (oracle.EmsParams(use_pairs=0, exclude_dc=0, alpha_min=0.5, alpha_max=0.5),
                 oracle.EmsParams(alpha_min=0.3, alpha_max=0.3),
                 oracle.EmsParams(k_min=1, k_max=40, alpha_min=0.9, alpha_max=0.9)):
-        keep, ks, st = plan.ems(fg, enf.EmsParams(**prm.__dict__))
+        with _ems_form(wide):
+            keep, ks, st = plan.ems(fg, enf.EmsParams(**prm.__dict__))
+            torch.cuda.synchronize()
         ok_keep, ok_ks, ok_st = oracle.ems_batched(f, prm)
         assert np.array_equal(ks.cpu().numpy(), ok_ks)
         assert np.array_equal(keep.cpu().numpy(), ok_keep)
