@@ -4,6 +4,8 @@ per timestep on fixed coefficients) against the FP64 oracle, through the C ABI.
 
 Given the same coefficients and flow records, the selection must be identical (K*,
 kept sets) and the FP64 statistics equal to rounding."""
+import os
+
 import numpy as np
 import pytest
 import torch
@@ -40,17 +42,28 @@ PARAMS = [oracle.EmsParams(),
           oracle.EmsParams(k_min=2, k_max=60, alpha_min=0.3, alpha_max=0.95, delta=0.05, use_pairs=0)]
 
 
+@pytest.mark.parametrize("wide", ["0", "1"])
 @pytest.mark.parametrize("prm", PARAMS)
-def test_ems_flow_matches_oracle_fp64(prm):
+def test_ems_flow_matches_oracle_fp64(prm, wide):
+    """Both in-register forms (ENUFFT_EMS_WIDE: three waves of sixteen values per lane,
+    or up to sixteen waves of four) give the oracle's selection."""
     b = synth.config1(count_scale=0.003, n_cells=12, precision="f64")
     ref = oracle_f(b)
     plan = _ems_plan_for(ref, "f64")
     T = 5
     fl = _flows(T, ref.shape[0], 91)
     f = torch.from_numpy(ref).to("cuda:0")
-    keep, ks, st = plan.ems_flow(f, fl, enf.EmsParams(**prm.__dict__))
-    _, ks2, st2 = plan.ems_flow(f, fl, enf.EmsParams(**prm.__dict__), need_keep=False)
-    torch.cuda.synchronize()
+    old = os.environ.get("ENUFFT_EMS_WIDE")
+    os.environ["ENUFFT_EMS_WIDE"] = wide
+    try:
+        keep, ks, st = plan.ems_flow(f, fl, enf.EmsParams(**prm.__dict__))
+        _, ks2, st2 = plan.ems_flow(f, fl, enf.EmsParams(**prm.__dict__), need_keep=False)
+        torch.cuda.synchronize()
+    finally:
+        if old is None:
+            os.environ.pop("ENUFFT_EMS_WIDE", None)
+        else:
+            os.environ["ENUFFT_EMS_WIDE"] = old
     ok_keep, ok_ks, ok_st = oracle.ems_flow(ref, fl, prm)
     ks, keep, st = ks.cpu().numpy(), keep.cpu().numpy(), st.cpu().numpy()
     print("K* per step (cell 0):", ks[:, 0], ok_ks[:, 0], flush=True)
